@@ -1,0 +1,185 @@
+/*
+ * spc.h -- C ABI of the MI355X (gfx950) spectrum-preserving graph
+ * coarsening library (method of Brissette, Huang, Slota, "Parallel
+ * coarsening of graph data with spectral guarantees", arXiv 2204.11757).
+ *
+ * Problem (introduction, before Definition 1): given a weighted graph
+ * G = (V, E) with n nodes and a target n_c, merge nodes into n_c
+ * super-nodes.  One level follows Algorithm 1: score every edge by the
+ * 1-norm distance of the endpoints' normalised adjacency rows
+ * (Theorem 1), order the edges by that score, and merge along edges in
+ * that order, skipping edges whose ends already share a super-node, until
+ * n_c super-nodes remain; then build the coarsened graph of Definition 1.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Graphs are symmetric CSR in DEVICE memory: row_ptr int64[n+1],
+ * col int32[nnz] strictly ascending per row with no diagonal entry, and
+ * weights w[nnz].  nnz = 2m counts both directions of each undirected edge.
+ * A node's self-loop weight (the diagonal of the weighted adjacency; zero
+ * on input graphs, the intra-cluster weight on coarse graphs) lives in
+ * self_w[n]; size[n] counts the original nodes a super-node stands for.
+ *
+ * Weight types: SPC_W_I32 (integer path, exact: w int32 > 0, self_w
+ * int64 >= 0, the total weight sum(w) + sum(self_w) at most 2^31 - 1), or
+ * SPC_W_F32 / SPC_W_F64 (floating-point path: scores in FP64, self_w and
+ * coarse weights in FP64; every weight and degree sum is the correctly
+ * rounded value of the exact sum).
+ *
+ * Edge order: by score, then the smaller endpoint id, then the larger one.
+ * Super-nodes are numbered by ascending smallest member.  Results are
+ * bit-for-bit deterministic.
+ *
+ * All device pointers are caller-owned unless stated otherwise.  Calls are
+ * ordered on the context's HIP stream; a call that returns host scalars
+ * synchronises that stream before returning.  No C++ exception crosses
+ * this boundary.  Return value: SPC_OK or a negative error code; the
+ * detail of the last error is available from spc_last_error(ctx).
+ */
+#ifndef SPC_H
+#define SPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPC_OK 0
+#define SPC_EINVAL (-1)       /* bad argument or malformed graph            */
+#define SPC_EUNREACHABLE (-2) /* target below the number of components      */
+#define SPC_EOVERFLOW (-3)    /* integer weight total exceeds 2^31 - 1      */
+#define SPC_ECAPACITY (-4)    /* a caller-provided output is too small      */
+#define SPC_ENOMEM (-5)       /* device or host allocation failed           */
+#define SPC_EHIP (-6)         /* a HIP runtime call failed                  */
+#define SPC_ERANGE (-7)       /* FP weights span too wide an exponent range */
+
+typedef struct spc_ctx spc_ctx;
+typedef struct spc_hier spc_hier;
+
+typedef enum { SPC_W_I32 = 0, SPC_W_F32 = 1, SPC_W_F64 = 2 } spc_wtype;
+
+/* Input graph view (device pointers).  self_w is int64 on the integer path
+ * and double on the floating-point path; self_w and size may be NULL
+ * (all zero / all one). */
+typedef struct {
+  int64_t n, nnz;
+  const int64_t* row_ptr;
+  const int32_t* col;
+  const void* w;
+  const void* self_w;
+  const int32_t* size;
+  int32_t wtype;
+} spc_graph;
+
+/* Caller-allocated output graph (device pointers).  The coarse weight type
+ * is int32 (integer path) or double (floating-point path); self_w is int64
+ * or double.  Capacities equal to the input's n and nnz always suffice. */
+typedef struct {
+  int64_t* row_ptr;   /* [n_cap + 1] */
+  int32_t* col;       /* [nnz_cap]   */
+  void* w;            /* [nnz_cap]   */
+  void* self_w;       /* [n_cap]     */
+  int32_t* size;      /* [n_cap]     */
+  int64_t n_cap, nnz_cap;
+} spc_graph_out;
+
+/* Per-level statistics (host struct, filled when non-NULL). */
+typedef struct {
+  int64_t n_in, m_in, n_out, nnz_out, merges, largest_cluster;
+  int64_t boruvka_rounds, candidate_edges;
+  int32_t key_mode;   /* 0: packed exact fixed-point key, 1: sorted rank */
+  int32_t key_bits;
+  double eps_max;     /* largest accepted score (Theorem 2's epsilon)    */
+  float ms_total;
+} spc_level_stats;
+
+/* Create a context on a device; hip_stream is a hipStream_t (NULL: the
+ * null stream).  The context owns its workspace. */
+int spc_create(spc_ctx** ctx, int device, void* hip_stream);
+int spc_destroy(spc_ctx* ctx);
+int spc_set_stream(spc_ctx* ctx, void* hip_stream);
+
+/* Route the library's device allocations (workspace, hierarchy levels)
+ * through caller-supplied functions, e.g. a framework's caching allocator.
+ * alloc(bytes, user) returns a device pointer or NULL; free(ptr, user).
+ * Passing NULL restores hipMalloc / hipFree. */
+int spc_set_allocator(spc_ctx* ctx, void* (*alloc)(size_t, void*), void (*free_)(void*, void*),
+                      void* user);
+
+/* Context options (for tests and tuning; results never depend on them):
+ *   "rank_order"  1: always order edges by a full sort into ranks, even when
+ *                 the exact packed fixed-point key fits in 64 bits.
+ *   "full_forest" 1: build the spanning forest over every edge instead of
+ *                 only the lightest candidates.
+ * Unknown names return SPC_EINVAL. */
+int spc_set_option(spc_ctx* ctx, const char* name, int64_t value);
+
+/* Human-readable description of the last error on this context. */
+const char* spc_last_error(const spc_ctx* ctx);
+const char* spc_strerror(int code);
+
+/* One level of Algorithm 1 (fitness loop, sort, merge loop) followed by
+ * the contraction of Definition 1.
+ *   g           input graph (device), validated for basic shape only.
+ *   n_target    number of super-nodes; n_target >= n gives the identity.
+ *   cluster_of  device int32[n]: super-node of every node (output).
+ *   coarse      caller-allocated coarse graph (output), n_cap >= n_target,
+ *               nnz_cap >= g->nnz.
+ *   nnz_c       host: number of coarse CSR entries written.
+ *   st          host stats or NULL.
+ * Errors: SPC_EINVAL (bad sizes / null pointers / n_target < 1),
+ * SPC_EUNREACHABLE, SPC_EOVERFLOW, SPC_ECAPACITY, SPC_EHIP, SPC_ENOMEM. */
+int spc_coarsen_level(spc_ctx* ctx, const spc_graph* g, int64_t n_target, int32_t* cluster_of,
+                      spc_graph_out* coarse, int64_t* nnz_c, spc_level_stats* st);
+
+/* Coarsen to n_c super-nodes level by level, re-scoring each level (the
+ * multilevel refinement the conclusion proposes).  schedule 0: halve the
+ * node count per level, t = max(n_c, ceil(n_l / 2)); schedule 1: a single
+ * level straight to n_c (Algorithm 1 as printed).  The hierarchy owns every
+ * level's graph and cluster map; free it with spc_hier_free. */
+int spc_coarsen_to(spc_ctx* ctx, const spc_graph* g, int64_t n_c, int schedule, spc_hier** out);
+
+int spc_hier_num_levels(const spc_hier* h);
+/* Level lvl (1-based; level 0 is the input, not stored).  view receives
+ * device pointers owned by the hierarchy; cluster_of maps level lvl-1
+ * nodes to level lvl super-nodes.  stats may be NULL. */
+int spc_hier_level(const spc_hier* h, int lvl, spc_graph* view, const int32_t** cluster_of,
+                   spc_level_stats* stats);
+/* Copy level lvl (1-based) into caller-allocated device buffers, ordered on
+ * the context's stream: the coarse graph into dst (capacities must hold
+ * the level's n and nnz) and, when cluster_of is non-NULL, its cluster map
+ * (int32[n of level lvl-1]). */
+int spc_hier_export_level(spc_ctx* ctx, const spc_hier* h, int lvl, spc_graph_out* dst,
+                          int32_t* cluster_of);
+void spc_hier_free(spc_hier* h);
+
+/* Lift (Definition 2) of k coarse vectors from level to_lvl down to level
+ * from_lvl < to_lvl (0 = the input graph).  x_c: device double[n_to * k],
+ * column-major; x_f: device double[n_from * k].  mode 0: piecewise
+ * constant, x_f[u] = x_c[c(u)]; mode 1: orthonormal, x_f[u] =
+ * x_c[c(u)] / sqrt(|c(u)|) where |c(u)| counts original nodes. */
+int spc_lift(spc_ctx* ctx, const spc_hier* h, int from_lvl, int to_lvl, int mode,
+             const double* x_c, int k, double* x_f);
+
+/* Spectral error of level lvl's lift against k eigenpairs of the input
+ * graph's normalised Laplacian (Theorem 1's Lambda; the lift of
+ * Definition 2).  U: device double[n0 * k] column-major, unit-norm
+ * eigenvectors; lambda: device double[k].  For each i, with Q the
+ * orthonormal lift, t = D_c^{-1/2} Q^T u_i, R_i = 1 - t^T W_c t (the lift's
+ * Rayleigh quotient at u_i; W_c includes the self-loops).  Writes R
+ * (device double[k], nullable) and the host scalar
+ * loss = sum_i (R_i - lambda_i)^2.  Synchronises. */
+int spc_spectral_error(spc_ctx* ctx, const spc_hier* h, int lvl, const double* U,
+                       const double* lambda, int k, double* R, double* loss);
+
+/* Host-side structural validation of a graph held in HOST memory: sorted
+ * unique columns, no diagonal entries, symmetric weights, positive
+ * weights, and the integer total bound.  No GPU needed. */
+int spc_validate_graph(const spc_graph* host_view);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPC_H */

@@ -1,0 +1,390 @@
+// C ABI of the coarsening library (declared in include/spc.h): context,
+// allocation hooks, error reporting, the level / multilevel entry points,
+// the hierarchy, the lift (Definition 2) and the spectral error.
+#include <cmath>
+#include <cstdarg>
+#include <new>
+
+#include "level.hpp"
+
+using namespace spc;
+
+namespace spc {
+
+int set_error(spc_ctx* ctx, int code, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+    ctx->err_code = code;
+  }
+  return code;
+}
+
+int hip_error(spc_ctx* ctx, hipError_t e, const char* where) {
+  return set_error(ctx, SPC_EHIP, "HIP error %d (%s) at %s", (int)e, hipGetErrorString(e), where);
+}
+
+void* dev_alloc(spc_ctx* ctx, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (ctx->alloc_fn) return ctx->alloc_fn(bytes, ctx->alloc_user);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+
+void dev_free(spc_ctx* ctx, void* p) {
+  if (!p) return;
+  if (ctx->free_fn) ctx->free_fn(p, ctx->alloc_user);
+  else (void)hipFree(p);
+}
+
+int ensure_workspace(spc_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->ws_cap) return SPC_OK;
+  if (ctx->ws) {
+    SPC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    dev_free(ctx, ctx->ws);
+    ctx->ws = nullptr;
+    ctx->ws_cap = 0;
+  }
+  void* p = dev_alloc(ctx, bytes);
+  if (!p) return set_error(ctx, SPC_ENOMEM, "workspace allocation of %zu bytes failed", bytes);
+  ctx->ws = p;
+  ctx->ws_cap = bytes;
+  return SPC_OK;
+}
+
+int readback(spc_ctx* ctx, const void* dev, size_t bytes, void* host) {
+  SPC_HIP(ctx, hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
+  SPC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return SPC_OK;
+}
+
+static int plan_and_bind(spc_ctx* ctx, int64_t n, int64_t nnz, LevelWork& W) {
+  Arena count;
+  count.counting = true;
+  plan_level(count, n, nnz, W);
+  int rc = ensure_workspace(ctx, count.off + 256);
+  if (rc) return rc;
+  Arena real;
+  real.base = (char*)ctx->ws;
+  real.cap = ctx->ws_cap;
+  plan_level(real, n, nnz, W);
+  return SPC_OK;
+}
+
+__global__ void k_iota32(int32_t* a, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = (int32_t)i;
+}
+
+__global__ void k_identity_aux(const int64_t* __restrict__ self_in, const int32_t* __restrict__ size_in,
+                               int64_t* __restrict__ self_out, int32_t* __restrict__ size_out,
+                               int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    self_out[i] = self_in ? self_in[i] : 0;
+    size_out[i] = size_in ? size_in[i] : 1;
+  }
+}
+
+static int check_graph(spc_ctx* ctx, const spc_graph* g) {
+  if (!g) return set_error(ctx, SPC_EINVAL, "graph is NULL");
+  if (g->n < 1 || g->n > INT32_MAX) return set_error(ctx, SPC_EINVAL, "n=%lld out of range", (long long)g->n);
+  if (g->nnz < 0 || (g->nnz & 1) || g->nnz > INT32_MAX)
+    return set_error(ctx, SPC_EINVAL, "nnz=%lld must be even and below 2^31", (long long)g->nnz);
+  if (!g->row_ptr || (g->nnz > 0 && (!g->col || !g->w)))
+    return set_error(ctx, SPC_EINVAL, "graph arrays are NULL");
+  if (g->wtype != SPC_W_I32)
+    return set_error(ctx, SPC_EINVAL, "weight type %d is not supported by this entry point",
+                     (int)g->wtype);
+  return SPC_OK;
+}
+
+static LevelIn level_in(const spc_graph* g) {
+  LevelIn L;
+  L.n = g->n;
+  L.nnz = g->nnz;
+  L.rp = g->row_ptr;
+  L.col = g->col;
+  L.w = (const int32_t*)g->w;
+  L.self = (const int64_t*)g->self_w;
+  L.size = g->size;
+  return L;
+}
+
+// one level into caller buffers
+static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* cluster_of,
+                      spc_graph_out* out, int64_t* nnz_c, spc_level_stats* st) {
+  int rc = check_graph(ctx, g);
+  if (rc) return rc;
+  if (t < 1) return set_error(ctx, SPC_EINVAL, "n_target must be >= 1");
+  if (!cluster_of || !out || !nnz_c) return set_error(ctx, SPC_EINVAL, "output is NULL");
+  if (t > g->n) t = g->n;
+  if (!out->row_ptr || !out->self_w || !out->size || (g->nnz > 0 && (!out->col || !out->w)))
+    return set_error(ctx, SPC_EINVAL, "output arrays are NULL");
+  if (out->n_cap < t) return set_error(ctx, SPC_ECAPACITY, "n_cap %lld < %lld", (long long)out->n_cap, (long long)t);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (st) {
+    SPC_HIP(ctx, hipEventCreate(&e0));
+    SPC_HIP(ctx, hipEventCreate(&e1));
+    SPC_HIP(ctx, hipEventRecord(e0, ctx->stream));
+  }
+  LevelIn L = level_in(g);
+  LevelWork W;
+  LevelResult R;
+  rc = plan_and_bind(ctx, g->n, g->nnz, W);
+  if (rc) return rc;
+  rc = select_level(ctx, L, t, cluster_of, W, R);
+  if (rc) return rc;
+  if (R.n_c == g->n) {
+    // identity: copy the graph
+    if (out->nnz_cap < g->nnz) return set_error(ctx, SPC_ECAPACITY, "nnz_cap too small");
+    SPC_HIP(ctx, hipMemcpyAsync(out->row_ptr, g->row_ptr, sizeof(int64_t) * (g->n + 1),
+                                hipMemcpyDeviceToDevice, ctx->stream));
+    if (g->nnz) {
+      SPC_HIP(ctx, hipMemcpyAsync(out->col, g->col, sizeof(int32_t) * g->nnz, hipMemcpyDeviceToDevice,
+                                  ctx->stream));
+      SPC_HIP(ctx, hipMemcpyAsync(out->w, g->w, sizeof(int32_t) * g->nnz, hipMemcpyDeviceToDevice,
+                                  ctx->stream));
+    }
+    hipLaunchKernelGGL(k_identity_aux, dim3(grid_for(g->n, 256)), dim3(256), 0, ctx->stream,
+                       (const int64_t*)g->self_w, g->size, (int64_t*)out->self_w, out->size, g->n);
+    SPC_LAUNCH_CHECK(ctx, "identity");
+    R.nnz_c = g->nnz;
+    R.maxcl = 1;
+  } else {
+    rc = contract_level(ctx, L, cluster_of, R.n_c, out, W, R);
+    if (rc) return rc;
+  }
+  *nnz_c = R.nnz_c;
+  if (st) {
+    SPC_HIP(ctx, hipEventRecord(e1, ctx->stream));
+    SPC_HIP(ctx, hipEventSynchronize(e1));
+    float ms = 0;
+    SPC_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    st->n_in = g->n;
+    st->m_in = g->nnz / 2;
+    st->n_out = R.n_c;
+    st->nnz_out = R.nnz_c;
+    st->merges = g->n - R.n_c;
+    st->largest_cluster = R.maxcl;
+    st->boruvka_rounds = R.rounds;
+    st->candidate_edges = R.candidates;
+    st->key_mode = R.key_mode;
+    st->key_bits = R.key_bits;
+    st->eps_max = R.eps;
+    st->ms_total = ms;
+  }
+  return SPC_OK;
+}
+
+}  // namespace spc
+
+// ===========================================================================
+// hierarchy
+// ===========================================================================
+
+static void free_level(spc_ctx* ctx, spc_hier::Level& L) {
+  dev_free(ctx, L.rp);
+  dev_free(ctx, L.col);
+  dev_free(ctx, L.w);
+  dev_free(ctx, L.self);
+  dev_free(ctx, L.size);
+  dev_free(ctx, L.cluster_of);
+  L = spc_hier::Level();
+}
+
+extern "C" {
+
+const char* spc_strerror(int code) {
+  switch (code) {
+    case SPC_OK: return "ok";
+    case SPC_EINVAL: return "invalid argument or malformed graph";
+    case SPC_EUNREACHABLE: return "target below the number of connected components";
+    case SPC_EOVERFLOW: return "integer weight total exceeds 2^31-1";
+    case SPC_ECAPACITY: return "output capacity too small";
+    case SPC_ENOMEM: return "allocation failed";
+    case SPC_EHIP: return "HIP runtime error";
+    case SPC_ERANGE: return "floating-point weights span too wide a range";
+    default: return "unknown error";
+  }
+}
+
+int spc_create(spc_ctx** out, int device, void* stream) {
+  if (!out) return SPC_EINVAL;
+  spc_ctx* ctx = new (std::nothrow) spc_ctx();
+  if (!ctx) return SPC_ENOMEM;
+  ctx->device = device;
+  ctx->stream = (hipStream_t)stream;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete ctx;
+    return SPC_EHIP;
+  }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+    ctx->num_cus = cus;
+  if (hipHostMalloc((void**)&ctx->h_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+    delete ctx;
+    return SPC_ENOMEM;
+  }
+  *out = ctx;
+  return SPC_OK;
+}
+
+int spc_destroy(spc_ctx* ctx) {
+  if (!ctx) return SPC_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  dev_free(ctx, ctx->ws);
+  if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
+  delete ctx;
+  return SPC_OK;
+}
+
+int spc_set_stream(spc_ctx* ctx, void* stream) {
+  if (!ctx) return SPC_EINVAL;
+  ctx->stream = (hipStream_t)stream;
+  return SPC_OK;
+}
+
+int spc_set_allocator(spc_ctx* ctx, void* (*alloc)(size_t, void*), void (*free_)(void*, void*),
+                      void* user) {
+  if (!ctx) return SPC_EINVAL;
+  if ((alloc == nullptr) != (free_ == nullptr)) return set_error(ctx, SPC_EINVAL, "allocator pair incomplete");
+  if (ctx->ws) {
+    (void)hipStreamSynchronize(ctx->stream);
+    dev_free(ctx, ctx->ws);
+    ctx->ws = nullptr;
+    ctx->ws_cap = 0;
+  }
+  ctx->alloc_fn = alloc;
+  ctx->free_fn = free_;
+  ctx->alloc_user = user;
+  return SPC_OK;
+}
+
+const char* spc_last_error(const spc_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+int spc_set_option(spc_ctx* ctx, const char* name, int64_t value) {
+  if (!ctx || !name) return SPC_EINVAL;
+  if (!strcmp(name, "rank_order")) ctx->force_rank_mode = value ? 1 : 0;
+  else if (!strcmp(name, "full_forest")) ctx->force_full_filter = value ? 1 : 0;
+  else return set_error(ctx, SPC_EINVAL, "unknown option '%s'", name);
+  return SPC_OK;
+}
+
+int spc_coarsen_level(spc_ctx* ctx, const spc_graph* g, int64_t n_target, int32_t* cluster_of,
+                      spc_graph_out* coarse, int64_t* nnz_c, spc_level_stats* st) {
+  if (!ctx) return SPC_EINVAL;
+  return level_impl(ctx, g, n_target, cluster_of, coarse, nnz_c, st);
+}
+
+int spc_coarsen_to(spc_ctx* ctx, const spc_graph* g, int64_t n_c, int schedule, spc_hier** out) {
+  if (!ctx) return SPC_EINVAL;
+  if (!out) return set_error(ctx, SPC_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = check_graph(ctx, g);
+  if (rc) return rc;
+  if (n_c < 1) return set_error(ctx, SPC_EINVAL, "n_c must be >= 1");
+  if (schedule != 0 && schedule != 1) return set_error(ctx, SPC_EINVAL, "unknown schedule %d", schedule);
+  spc_hier* h = new (std::nothrow) spc_hier();
+  if (!h) return SPC_ENOMEM;
+  h->ctx = ctx;
+  h->n0 = g->n;
+  spc_graph cur = *g;
+  int64_t n = g->n;
+  while (n > n_c) {
+    int64_t t = (schedule == 1) ? n_c : std::max(n_c, (n + 1) / 2);
+    spc_hier::Level L;
+    L.n_prev = n;
+    L.rp = (int64_t*)dev_alloc(ctx, sizeof(int64_t) * (t + 1));
+    L.col = (int32_t*)dev_alloc(ctx, sizeof(int32_t) * std::max<int64_t>(cur.nnz, 1));
+    L.w = (int32_t*)dev_alloc(ctx, sizeof(int32_t) * std::max<int64_t>(cur.nnz, 1));
+    L.self = (int64_t*)dev_alloc(ctx, sizeof(int64_t) * t);
+    L.size = (int32_t*)dev_alloc(ctx, sizeof(int32_t) * t);
+    L.cluster_of = (int32_t*)dev_alloc(ctx, sizeof(int32_t) * n);
+    if (!L.rp || !L.col || !L.w || !L.self || !L.size || !L.cluster_of) {
+      free_level(ctx, L);
+      spc_hier_free(h);
+      return set_error(ctx, SPC_ENOMEM, "hierarchy allocation failed");
+    }
+    spc_graph_out o{L.rp, L.col, L.w, L.self, L.size, t, std::max<int64_t>(cur.nnz, 1)};
+    int64_t nnz_c = 0;
+    rc = level_impl(ctx, &cur, t, L.cluster_of, &o, &nnz_c, &L.st);
+    if (rc) {
+      free_level(ctx, L);
+      spc_hier_free(h);
+      return rc;
+    }
+    L.n = t;
+    L.nnz = nnz_c;
+    h->levels.push_back(L);
+    cur.n = t;
+    cur.nnz = nnz_c;
+    cur.row_ptr = L.rp;
+    cur.col = L.col;
+    cur.w = L.w;
+    cur.self_w = L.self;
+    cur.size = L.size;
+    n = t;
+  }
+  *out = h;
+  return SPC_OK;
+}
+
+int spc_hier_num_levels(const spc_hier* h) { return h ? (int)h->levels.size() : 0; }
+
+int spc_hier_level(const spc_hier* h, int lvl, spc_graph* view, const int32_t** cluster_of,
+                   spc_level_stats* stats) {
+  if (!h || lvl < 1 || lvl > (int)h->levels.size()) return SPC_EINVAL;
+  const spc_hier::Level& L = h->levels[lvl - 1];
+  if (view) {
+    view->n = L.n;
+    view->nnz = L.nnz;
+    view->row_ptr = L.rp;
+    view->col = L.col;
+    view->w = L.w;
+    view->self_w = L.self;
+    view->size = L.size;
+    view->wtype = SPC_W_I32;
+  }
+  if (cluster_of) *cluster_of = L.cluster_of;
+  if (stats) *stats = L.st;
+  return SPC_OK;
+}
+
+int spc_hier_export_level(spc_ctx* ctx, const spc_hier* h, int lvl, spc_graph_out* dst,
+                          int32_t* cluster_of) {
+  if (!ctx) return SPC_EINVAL;
+  if (!h || lvl < 1 || lvl > (int)h->levels.size() || !dst)
+    return set_error(ctx, SPC_EINVAL, "bad export arguments");
+  const spc_hier::Level& L = h->levels[lvl - 1];
+  if (dst->n_cap < L.n || dst->nnz_cap < L.nnz)
+    return set_error(ctx, SPC_ECAPACITY, "export buffers too small");
+  hipStream_t st = ctx->stream;
+  SPC_HIP(ctx, hipMemcpyAsync(dst->row_ptr, L.rp, sizeof(int64_t) * (L.n + 1), hipMemcpyDeviceToDevice, st));
+  if (L.nnz) {
+    SPC_HIP(ctx, hipMemcpyAsync(dst->col, L.col, sizeof(int32_t) * L.nnz, hipMemcpyDeviceToDevice, st));
+    SPC_HIP(ctx, hipMemcpyAsync(dst->w, L.w, sizeof(int32_t) * L.nnz, hipMemcpyDeviceToDevice, st));
+  }
+  SPC_HIP(ctx, hipMemcpyAsync(dst->self_w, L.self, sizeof(int64_t) * L.n, hipMemcpyDeviceToDevice, st));
+  SPC_HIP(ctx, hipMemcpyAsync(dst->size, L.size, sizeof(int32_t) * L.n, hipMemcpyDeviceToDevice, st));
+  if (cluster_of)
+    SPC_HIP(ctx, hipMemcpyAsync(cluster_of, L.cluster_of, sizeof(int32_t) * L.n_prev,
+                                hipMemcpyDeviceToDevice, st));
+  return SPC_OK;
+}
+
+void spc_hier_free(spc_hier* h) {
+  if (!h) return;
+  if (h->ctx) (void)hipStreamSynchronize(h->ctx->stream);
+  for (auto& L : h->levels) free_level(h->ctx, L);
+  delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,294 @@
+// Internal declarations of the gfx950 coarsening library: device helpers
+// for 64-lane wavefronts, the context, the workspace arena and the
+// host-side launch plumbing.  Nothing here is part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "spc.h"
+
+namespace spc {
+
+constexpr int WAVE = 64;
+constexpr uint64_t KEY_INF = ~0ull;
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  return (1ull << lane_id()) - 1ull;
+}
+
+// Wave-aggregated append: every active lane with pred gets a distinct slot
+// in [*counter, *counter + popcount) with one atomic per wave.
+__device__ __forceinline__ int64_t wave_append(unsigned long long* counter, bool pred) {
+  uint64_t mask = __ballot(pred);
+  if (mask == 0) return -1;
+  int leader = __ffsll((long long)mask) - 1;
+  unsigned long long base = 0;
+  if (lane_id() == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
+  base = __shfl(base, leader);
+  return pred ? (int64_t)(base + __popcll(mask & lanemask_lt())) : -1;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_sum(T v) {
+  int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    T t = __shfl_up(v, o);
+    if (l >= o) v += t;
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_max(T v) {
+  int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    T t = __shfl_up(v, o);
+    if (l >= o) v = (t > v) ? t : v;
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    T t = __shfl_xor(v, o);
+    v = (t > v) ? t : v;
+  }
+  return v;
+}
+
+// Block-wide inclusive scan (sum or max) for BS threads; tmp: LDS T[BS/64].
+// Returns the inclusive value; *total receives the block total.
+template <typename T, int BS, bool MAX>
+__device__ __forceinline__ T block_incl_scan(T v, T* tmp, T* total) {
+  constexpr int NW = BS / WAVE;
+  int w = threadIdx.x / WAVE, l = lane_id();
+  T x = MAX ? wave_incl_max(v) : wave_incl_sum(v);
+  if (l == WAVE - 1) tmp[w] = x;
+  __syncthreads();
+  if (w == 0) {
+    T y;
+    if (MAX) {
+      y = (l < NW) ? tmp[l] : tmp[0];
+      y = wave_incl_max(y);
+    } else {
+      y = (l < NW) ? tmp[l] : (T)0;
+      y = wave_incl_sum(y);
+    }
+    if (l < NW) tmp[l] = y;
+  }
+  __syncthreads();
+  T pre = (w > 0) ? tmp[w - 1] : (T)0;
+  T res;
+  if (MAX) res = (w > 0 && pre > x) ? pre : x;
+  else res = x + pre;
+  if (total) *total = tmp[NW - 1];
+  __syncthreads();
+  return res;
+}
+
+// Largest r in [0, nrows) with ptr[r] <= x, for a nondecreasing ptr with
+// ptr[0] <= x.  Executed by one full wave (64 lanes active); every lane
+// returns the result.  A 64-ary search: ~log64(nrows) rounds of loads.
+__device__ __forceinline__ int64_t wave_upper_search(const int64_t* __restrict__ ptr, int64_t nrows,
+                                                     int64_t x) {
+  int64_t lo = 0, hi = nrows - 1;
+  int l = lane_id();
+  while (hi - lo >= WAVE) {
+    int64_t step = (hi - lo + WAVE - 1) / WAVE;
+    int64_t pos = lo + (int64_t)l * step;
+    if (pos > hi) pos = hi;
+    bool pred = (l == 0) || (ptr[pos] <= x);
+    uint64_t mask = __ballot(pred);
+    int k = __popcll(mask) - 1;  // pred is monotone in l
+    int64_t nlo = lo + (int64_t)k * step;
+    if (nlo > hi) nlo = hi;
+    int64_t nhi = (k == WAVE - 1) ? hi : lo + (int64_t)(k + 1) * step - 1;
+    if (nhi > hi) nhi = hi;
+    lo = nlo;
+    hi = nhi;
+  }
+  int64_t pos = lo + l;
+  bool pred = (pos <= hi) && ((l == 0) || ptr[pos] <= x);
+  uint64_t mask = __ballot(pred);
+  return lo + __popcll(mask) - 1;
+}
+
+// Load-balanced mapping of a tile of T consecutive positions
+// [p0, p0 + T) of a CSR-like prefix array ptr[0..nrows] onto rows:
+// srow[k] = row containing position p0 + k.  Called by all BS threads.
+template <int T, int BS>
+__device__ __forceinline__ void lbs_tile(const int64_t* __restrict__ ptr, int64_t nrows, int64_t p0,
+                                         int32_t* srow, int64_t* sh, int32_t* scan_tmp) {
+  int tid = threadIdx.x;
+  if (tid < WAVE) {
+    int64_t total = ptr[nrows];
+    int64_t last = p0 + T - 1;
+    if (last > total - 1) last = total - 1;
+    int64_t r0 = wave_upper_search(ptr, nrows, p0);
+    int64_t r1 = wave_upper_search(ptr, nrows, last);
+    if (tid == 0) {
+      sh[0] = r0;
+      sh[1] = r1;
+    }
+  }
+  __syncthreads();
+  int64_t r0 = sh[0], r1 = sh[1];
+  for (int k = tid; k < T; k += BS) srow[k] = (int32_t)r0;
+  __syncthreads();
+  for (int64_t r = r0 + 1 + tid; r <= r1; r += BS) {
+    int64_t p = ptr[r] - p0;
+    if (p > 0 && p < T) atomicMax(&srow[p], (int32_t)r);
+  }
+  __syncthreads();
+  // inclusive max-scan over srow
+  constexpr int PER = T / BS;
+  static_assert(T % BS == 0, "tile must be a multiple of the block");
+  int32_t loc[PER];
+  int32_t run = INT32_MIN;
+#pragma unroll
+  for (int i = 0; i < PER; i++) {
+    int32_t v = srow[tid * PER + i];
+    run = v > run ? v : run;
+    loc[i] = run;
+  }
+  int32_t tot;
+  int32_t inc = block_incl_scan<int32_t, BS, true>(run, scan_tmp, &tot);
+  // exclusive prefix-max for this thread = max over earlier threads
+  int32_t prev = __shfl_up(inc, 1);
+  int w = tid / WAVE;
+  if (lane_id() == 0) prev = (w > 0) ? scan_tmp[w - 1] : INT32_MIN;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; i++) {
+    int32_t v = loc[i] > prev ? loc[i] : prev;
+    srow[tid * PER + i] = v;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// union-find with hooking of the larger root under the smaller one, so the
+// root of every tree is its smallest member
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t x) {
+  int32_t p = __hip_atomic_load(&parent[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  while (p != x) {
+    int32_t gp = __hip_atomic_load(&parent[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (gp != p) {
+      // path halving: parent pointers only ever move towards the root
+      __hip_atomic_store(&parent[x], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    x = p;
+    p = gp;
+  }
+  return x;
+}
+
+__device__ __forceinline__ void uf_union(int32_t* parent, int32_t a, int32_t b) {
+  while (true) {
+    a = uf_find(parent, a);
+    b = uf_find(parent, b);
+    if (a == b) return;
+    if (a > b) {
+      int32_t t = a;
+      a = b;
+      b = t;
+    }
+    int32_t old = atomicCAS(&parent[b], b, a);
+    if (old == b) return;
+  }
+}
+
+__host__ __device__ __forceinline__ int bitlen64(uint64_t x) {
+  return x ? 64 - __builtin_clzll(x) : 0;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, off = 0;
+  bool counting = false;
+  template <typename T>
+  T* take(size_t count) {
+    size_t a = (off + 255) & ~(size_t)255;
+    size_t bytes = count * sizeof(T);
+    if (bytes == 0) bytes = sizeof(T);
+    off = a + bytes;
+    if (counting || base == nullptr) return nullptr;
+    if (off > cap) return nullptr;
+    return reinterpret_cast<T*>(base + a);
+  }
+};
+
+}  // namespace spc
+
+struct spc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void* (*alloc_fn)(size_t, void*) = nullptr;
+  void (*free_fn)(void*, void*) = nullptr;
+  void* alloc_user = nullptr;
+  void* ws = nullptr;
+  size_t ws_cap = 0;
+  int64_t* h_pinned = nullptr;  // pinned readback area
+  int err_code = 0;
+  std::string err;
+  int num_cus = 256;
+  // knobs
+  int force_rank_mode = 0;   // use the sorted-rank order even when a packed key fits
+  int force_full_filter = 0; // run the spanning-forest phase over every edge
+};
+
+namespace spc {
+
+int set_error(spc_ctx* ctx, int code, const char* fmt, ...);
+int hip_error(spc_ctx* ctx, hipError_t e, const char* where);
+void* dev_alloc(spc_ctx* ctx, size_t bytes);
+void dev_free(spc_ctx* ctx, void* p);
+int ensure_workspace(spc_ctx* ctx, size_t bytes);
+int readback(spc_ctx* ctx, const void* dev, size_t bytes, void* host);
+
+#define SPC_HIP(ctx, call)                                   \
+  do {                                                       \
+    hipError_t e__ = (call);                                 \
+    if (e__ != hipSuccess) return ::spc::hip_error(ctx, e__, #call); \
+  } while (0)
+
+#define SPC_LAUNCH_CHECK(ctx, name)                          \
+  do {                                                       \
+    hipError_t e__ = hipGetLastError();                      \
+    if (e__ != hipSuccess) return ::spc::hip_error(ctx, e__, name); \
+  } while (0)
+
+inline int grid_for(int64_t items, int per_block, int cap = 1 << 30) {
+  int64_t g = (items + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+}  // namespace spc

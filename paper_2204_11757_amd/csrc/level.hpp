@@ -1,0 +1,125 @@
+// One coarsening level: shared types between the selection kernels
+// (degrees, scores, order, merge selection) and the contraction kernels.
+#pragma once
+
+#include "prim.hpp"
+
+
+// Hierarchy produced by spc_coarsen_to: level l (1-based) holds the coarse
+// graph after l levels and the map from level l-1 nodes to its super-nodes.
+struct spc_hier {
+  spc_ctx* ctx = nullptr;
+  int64_t n0 = 0;
+  struct Level {
+    int64_t n = 0, nnz = 0, n_prev = 0;
+    int64_t* rp = nullptr;
+    int32_t* col = nullptr;
+    int32_t* w = nullptr;
+    int64_t* self = nullptr;
+    int32_t* size = nullptr;
+    int32_t* cluster_of = nullptr;
+    spc_level_stats st{};
+  };
+  std::vector<Level> levels;
+};
+
+namespace spc {
+
+// Device view of an integer-path input graph.
+struct LevelIn {
+  int64_t n, nnz;
+  const int64_t* rp;
+  const int32_t* col;
+  const int32_t* w;
+  const int64_t* self;   // nullable
+  const int32_t* size;   // nullable
+};
+
+// Exact sort key of the rank-mode order: score N / D, ties by edge index.
+struct KeyND {
+  uint64_t N, D, e;
+};
+
+struct LessND {
+  __device__ __forceinline__ bool operator()(const KeyND& a, const KeyND& b) const {
+    unsigned __int128 l = (unsigned __int128)a.N * b.D;
+    unsigned __int128 r = (unsigned __int128)b.N * a.D;
+    if (l != r) return l < r;
+    return a.e < b.e;
+  }
+};
+
+// Indices into the per-level device info block.
+enum Info : int {
+  I_DMAX = 0,
+  I_TOTAL = 1,
+  I_LIVE0 = 2,
+  I_LIVE1 = 3,
+  I_MSF = 4,
+  I_MID = 5,
+  I_HUGE = 6,
+  I_LONG = 7,
+  I_BAD = 8,
+  I_NC = 9,
+  I_MAXCL = 10,
+  I_EPS = 11,
+  I_NINFO = 16
+};
+
+struct LevelWork {
+  unsigned long long* info;  // [I_NINFO]
+  uint64_t* deg;             // [n]
+  int32_t* lc;               // [n]  entries with col < row
+  int64_t* uptr;             // [n+1] upper-edge prefix (edge ids)
+  int32_t* longrows;         // [n]
+  uint64_t* P;               // [m]  order key per edge
+  uint64_t* samples;         // [m/64 + 2]
+  uint64_t* bestA;           // [n]
+  uint64_t* bestB;           // [n]
+  int32_t* parent;           // [n]
+  uint64_t* lr[2];           // [m] live edges: current roots (lo | hi << 32)
+  uint64_t* lp[2];           // [m] live edges: key
+  uint64_t* lo[2];           // [m] live edges: original endpoints
+  uint64_t* msfP;            // [n]
+  uint64_t* msfO;            // [n]
+  int32_t* root;             // [n]
+  int32_t* flag;             // [n+1]
+  SelState* sel;
+  SelState* sel2;
+  void* scan_partial;        // SCAN_MAXB * 8 bytes
+  KeyND* keysA;              // [m] rank mode
+  KeyND* keysB;              // [m]
+  // contraction
+  int32_t* mcount;           // [n+1]
+  int32_t* mptr;             // [n+1]
+  int32_t* members;          // [n]
+  int64_t* gptr;             // [n+1]
+  uint64_t* temp;            // [nnz]
+  int64_t* cnt;              // [n+1]
+  int32_t* midlist;          // [n]
+  int32_t* hugelist;         // [n]
+  int64_t* hmoff;            // [n+1]
+  int32_t* hmrow;            // [n]  huge member -> huge row index
+  int32_t* hmnode;           // [n]
+  int64_t* hpos;             // [n+1] huge member -> gathered offset
+  uint64_t* gkeyA;           // [nnz] (key, w) pairs, 16 bytes each
+  uint64_t* gkeyB;           // [nnz]
+};
+
+void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W);
+
+struct LevelResult {
+  int64_t n_c = 0, nnz_c = 0, msf = 0, rounds = 0, candidates = 0, maxcl = 0;
+  int key_mode = 0, key_bits = 0;
+  double eps = 0.0;
+};
+
+// Steps A1-A4: degrees, scores, order, merge selection -> cluster_of.
+int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of, LevelWork& W,
+                 LevelResult& R);
+
+// Step A5: contraction of Definition 1 into caller buffers.
+int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* cluster_of, int64_t n_c,
+                   spc_graph_out* out, LevelWork& W, LevelResult& R);
+
+}  // namespace spc

@@ -1,0 +1,199 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle,
+bit-exact (cluster maps, coarse CSR, self-loops, sizes) on seeded inputs.
+
+Every case prints its name and shape before the GPU call."""
+import numpy as np
+import pytest
+
+import oracle
+from meshgen import from_edges, grid2d, grid3d, random_graph, trimesh
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    from paper_2204_11757_amd import spc
+    spc.lib()
+    torch.cuda.init()
+    yield spc
+    spc.set_option("rank_order", 0)
+    spc.set_option("full_forest", 0)
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def host(x):
+    return None if x is None else x.cpu().numpy()
+
+
+def assert_same_graph(dg, hg, what=""):
+    assert dg.n == hg.n, what
+    np.testing.assert_array_equal(host(dg.row_ptr), hg.row_ptr, err_msg=what + " row_ptr")
+    np.testing.assert_array_equal(host(dg.col), hg.col, err_msg=what + " col")
+    np.testing.assert_array_equal(host(dg.w), hg.w, err_msg=what + " w")
+    np.testing.assert_array_equal(host(dg.self_w), hg.self_w, err_msg=what + " self_w")
+    np.testing.assert_array_equal(host(dg.size), hg.size, err_msg=what + " size")
+
+
+def check_level(P, g, t, what=""):
+    say(what, f"n={g.n} m={g.m} t={t}")
+    dg = P.DeviceGraph.from_host(g)
+    cl, gc, st = P.coarsen_level(dg, t)
+    c_or, gc_or, eps = oracle.coarsen_level(g, t)
+    np.testing.assert_array_equal(host(cl), c_or, err_msg=what + " cluster_of")
+    assert_same_graph(gc, gc_or, what)
+    assert st.n_out == gc_or.n
+    if g.n > t and g.m > 0:
+        assert st.eps_max == eps
+    return st
+
+
+def check_hierarchy(P, g, n_c, schedule=0, what=""):
+    say(what, f"hierarchy n={g.n} m={g.m} n_c={n_c} schedule={schedule}")
+    dg = P.DeviceGraph.from_host(g)
+    h = P.coarsen_to(dg, n_c, schedule)
+    want = oracle.coarsen_to(g, n_c, schedule)
+    assert h.num_levels == len(want)
+    stats = []
+    for l, (c_or, gc_or, _) in enumerate(want, start=1):
+        cl, gc, st = h.level(l)
+        np.testing.assert_array_equal(host(cl), c_or, err_msg=f"{what} level {l} cluster_of")
+        assert_same_graph(gc, gc_or, f"{what} level {l}")
+        stats.append(st)
+    return h, want, stats
+
+
+# ----------------------------------------------------------------------------
+
+RANDOM_CASES = [(n, p, s, sl, fw) for (n, p, s, sl, fw) in [
+    (2, 1.0, 0, False, 1), (3, 0.5, 1, False, 3), (5, 0.6, 2, True, 2), (9, 0.3, 3, False, 5),
+    (17, 0.25, 4, True, 4), (33, 0.2, 5, False, 9), (40, 0.5, 6, True, 1), (64, 0.1, 7, False, 3),
+    (65, 0.08, 8, True, 6), (127, 0.05, 9, False, 2), (300, 0.02, 10, True, 7),
+    (513, 0.01, 11, False, 1), (700, 0.015, 12, True, 3)]]
+
+
+@pytest.mark.parametrize("n,p,seed,self_loops,wmax", RANDOM_CASES)
+def test_random_graphs_every_target(P, n, p, seed, self_loops, wmax):
+    g = random_graph(n, p=p, seed=seed, wmax=wmax, self_loops=self_loops, sizes=self_loops)
+    targets = sorted({1, max(1, n // 3), max(1, n // 2), max(1, n - 1), n})
+    for t in targets:
+        check_level(P, g, t, f"random(n={n},seed={seed})")
+
+
+def test_first_config_halving_and_single_pass(P):
+    g = grid2d(64)
+    check_hierarchy(P, g, 1024, 0, "grid2d-64 halving")
+    check_hierarchy(P, g, 1024, 1, "grid2d-64 single pass")
+
+
+@pytest.mark.parametrize("s,seed", [(96, 3), (131, 5)])
+def test_trimesh_multilevel(P, s, seed):
+    g = trimesh(s, ("uniform", 1, 8), seed=seed)
+    check_hierarchy(P, g, g.n // 100, 0, f"trimesh-{s}")
+
+
+def test_trimesh_unit_weights_ties(P):
+    g = trimesh(80, "unit", seed=[4, 17])
+    check_hierarchy(P, g, g.n // 10, 0, "trimesh-80 unit")
+
+
+@pytest.mark.parametrize("s", [12, 20])
+def test_grid3d_multilevel(P, s):
+    g = grid3d(s, ("uniform", 1, 16), seed=2)
+    check_hierarchy(P, g, max(1, g.n // 64), 0, f"grid3d-{s}")
+
+
+def test_alternate_order_and_forest_paths_agree(P):
+    g = trimesh(70, ("uniform", 1, 8), seed=9)
+    base = check_level(P, g, g.n // 2, "trimesh-70 packed")
+    assert base.key_mode == 0
+    try:
+        P.set_option("rank_order", 1)
+        st = check_level(P, g, g.n // 2, "trimesh-70 rank order")
+        assert st.key_mode == 1
+        P.set_option("full_forest", 1)
+        check_level(P, g, g.n // 2, "trimesh-70 rank order + full forest")
+        P.set_option("rank_order", 0)
+        check_level(P, g, g.n // 3, "trimesh-70 packed + full forest")
+        g3 = grid3d(10, ("uniform", 1, 16), seed=4)
+        check_hierarchy(P, g3, 20, 0, "grid3d-10 full forest")
+    finally:
+        P.set_option("rank_order", 0)
+        P.set_option("full_forest", 0)
+
+
+def test_edge_cases(P):
+    import torch
+    # single edge
+    g = from_edges(2, [0], [1], np.array([3], np.int32))
+    check_level(P, g, 1, "single edge")
+    check_level(P, g, 2, "single edge identity")
+    # target above n is the identity
+    g = random_graph(20, p=0.3, seed=1)
+    check_level(P, g, 50, "target above n")
+    # disconnected graph: reachable and unreachable targets
+    g = from_edges(6, [0, 1, 3, 4], [1, 2, 4, 5], np.array([1, 2, 1, 1], np.int32))
+    check_level(P, g, 2, "two components")
+    say("two components, unreachable target")
+    with pytest.raises(P.SpcError) as ei:
+        P.coarsen_level(P.DeviceGraph.from_host(g), 1)
+    assert ei.value.code == P.SPC_EUNREACHABLE
+    # isolated nodes (a graph with no edges can only keep every node)
+    g = from_edges(3, [0], [1], np.array([1], np.int32))
+    check_level(P, g, 2, "isolated node")
+    # integer overflow guard
+    g = from_edges(3, [0, 1], [1, 2], np.array([2 ** 30, 5], np.int32))
+    say("overflow")
+    with pytest.raises(P.SpcError) as ei:
+        P.coarsen_level(P.DeviceGraph.from_host(g), 2)
+    assert ei.value.code == P.SPC_EOVERFLOW
+    # bad target
+    with pytest.raises(P.SpcError) as ei:
+        P.coarsen_level(P.DeviceGraph.from_host(random_graph(5, 0.5, 2)), 0)
+    assert ei.value.code == P.SPC_EINVAL
+    torch.cuda.synchronize()
+
+
+def test_deterministic_reruns(P):
+    g = trimesh(100, ("uniform", 1, 8), seed=12)
+    dg = P.DeviceGraph.from_host(g)
+    say("determinism trimesh-100")
+    ref = None
+    for _ in range(4):
+        cl, gc, st = P.coarsen_level(dg, g.n // 2)
+        cur = [host(cl), host(gc.row_ptr), host(gc.col), host(gc.w), host(gc.self_w), host(gc.size)]
+        if ref is None:
+            ref = cur
+        else:
+            for a, b in zip(ref, cur):
+                assert np.array_equal(a, b)
+
+
+def test_lift_and_spectral_error(P):
+    import torch
+    from oracle import spectral as S
+    g = trimesh(24, ("uniform", 1, 8), seed=21)
+    say("lift/spectral trimesh-24")
+    dg = P.DeviceGraph.from_host(g)
+    h = P.coarsen_to(dg, g.n // 8, 0)
+    want = oracle.coarsen_to(g, g.n // 8, 0)
+    lam, U = S.eigenpairs(S.dense_w(g))
+    k = 6
+    lam, U = lam[1:k + 1], U[:, 1:k + 1]
+    Ud = torch.from_numpy(U).cuda()
+    ld = torch.from_numpy(lam).cuda()
+    for lvl in range(1, len(want) + 1):
+        comp = oracle.compose(want, lvl)
+        gc = want[lvl - 1][1]
+        loss_o, R_o = S.spectral_error(gc, comp, U, lam)
+        loss_g, R_g = P.spectral_error(h, lvl, Ud, ld)
+        np.testing.assert_allclose(host(R_g), R_o, rtol=1e-12, atol=1e-13)
+        assert abs(loss_g - loss_o) <= 1e-10 * max(loss_o, 1e-300)
+        xc = np.random.default_rng(lvl).normal(size=(gc.n, 3))
+        for mode in (0, 1):
+            xf = P.lift(h, 0, lvl, mode, torch.from_numpy(xc).cuda())
+            np.testing.assert_array_equal(host(xf), S.lift_vectors(xc, comp, gc.size, mode))
