@@ -113,8 +113,17 @@ int spc_set_allocator(spc_ctx* ctx, void* (*alloc)(size_t, void*), void (*free_)
  *                 the exact packed fixed-point key fits in 64 bits.
  *   "full_forest" 1: build the spanning forest over every edge instead of
  *                 only the lightest candidates.
+ *   "timing"      1: record a HIP event pair on the context stream around
+ *                 every kernel launch, for spc_timing_report.
  * Unknown names return SPC_EINVAL. */
 int spc_set_option(spc_ctx* ctx, const char* name, int64_t value);
+
+/* Per-kernel timing collected while the "timing" option was on, as text:
+ * one line per kernel, "name launches total_ms work_units\n" (work units:
+ * edges for edge-parallel kernels, nodes for node-parallel ones).  Clears
+ * the collected events; synchronises the stream.  SPC_ECAPACITY if cap is
+ * too small. */
+int spc_timing_report(spc_ctx* ctx, char* buf, size_t cap);
 
 /* Human-readable description of the last error on this context. */
 const char* spc_last_error(const spc_ctx* ctx);

@@ -274,7 +274,44 @@ int spc_set_option(spc_ctx* ctx, const char* name, int64_t value) {
   if (!ctx || !name) return SPC_EINVAL;
   if (!strcmp(name, "rank_order")) ctx->force_rank_mode = value ? 1 : 0;
   else if (!strcmp(name, "full_forest")) ctx->force_full_filter = value ? 1 : 0;
+  else if (!strcmp(name, "timing")) ctx->timing = value ? 1 : 0;
   else return set_error(ctx, SPC_EINVAL, "unknown option '%s'", name);
+  return SPC_OK;
+}
+
+int spc_timing_report(spc_ctx* ctx, char* buf, size_t cap) {
+  if (!ctx || !buf || cap == 0) return SPC_EINVAL;
+  SPC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  struct Agg {
+    std::string name;
+    int64_t count = 0;
+    double ms = 0.0, units = 0.0;
+  };
+  std::vector<Agg> agg;
+  for (auto& m : ctx->marks) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, m.a, m.b) != hipSuccess) ms = 0.f;
+    size_t i = 0;
+    while (i < agg.size() && agg[i].name != m.name) i++;
+    if (i == agg.size()) {
+      agg.push_back(Agg());
+      agg.back().name = m.name;
+    }
+    agg[i].count++;
+    agg[i].ms += ms;
+    agg[i].units += m.units;
+    ctx->ev_pool.push_back(m.a);
+    ctx->ev_pool.push_back(m.b);
+  }
+  ctx->marks.clear();
+  std::string out;
+  char line[256];
+  for (auto& a : agg) {
+    snprintf(line, sizeof(line), "%s %lld %.6f %.0f\n", a.name.c_str(), (long long)a.count, a.ms, a.units);
+    out += line;
+  }
+  if (out.size() + 1 > cap) return set_error(ctx, SPC_ECAPACITY, "timing report needs %zu bytes", out.size() + 1);
+  memcpy(buf, out.c_str(), out.size() + 1);
   return SPC_OK;
 }
 

@@ -261,7 +261,53 @@ struct spc_ctx {
   // knobs
   int force_rank_mode = 0;   // use the sorted-rank order even when a packed key fits
   int force_full_filter = 0; // run the spanning-forest phase over every edge
+  // per-kernel timing: events recorded around launches on the context stream
+  int timing = 0;
+  std::vector<hipEvent_t> ev_pool;
+  struct Mark {
+    const char* name;
+    hipEvent_t a, b;
+    double units;
+  };
+  std::vector<Mark> marks;
 };
+
+namespace spc {
+
+inline hipEvent_t ev_get(spc_ctx* ctx) {
+  if (!ctx->ev_pool.empty()) {
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records an event pair around the launches in its scope when timing is on.
+// `units` is the work the launch covers (edges, nodes, ...) for reports.
+struct TimedScope {
+  spc_ctx* ctx;
+  const char* name;
+  double units;
+  hipEvent_t a = nullptr;
+  TimedScope(spc_ctx* c, const char* nm, double u = 0.0) : ctx(c), name(nm), units(u) {
+    if (ctx->timing) {
+      a = ev_get(ctx);
+      if (a) (void)hipEventRecord(a, ctx->stream);
+    }
+  }
+  ~TimedScope() {
+    if (!a) return;
+    hipEvent_t b = ev_get(ctx);
+    if (!b) return;
+    (void)hipEventRecord(b, ctx->stream);
+    ctx->marks.push_back({name, a, b, units});
+  }
+};
+
+}  // namespace spc
 
 namespace spc {
 

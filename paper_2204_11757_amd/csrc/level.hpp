@@ -63,8 +63,26 @@ enum Info : int {
   I_NC = 9,
   I_MAXCL = 10,
   I_EPS = 11,
+  I_DMAXE = 12,   // largest D = d_u d_v over edges
+  I_VIOL = 13,    // a guarded-key decision was not exact
+  I_BLOCK = 14,   // contraction rows for the block-per-row class
   I_NINFO = 16
 };
+
+// Block-wide reservation of `my` consecutive slots per thread behind a
+// global counter with one atomic per block.  All BS threads must call it.
+// tmp: LDS int[BS/64]; sh_base: LDS scalar.
+template <int BS>
+__device__ __forceinline__ int64_t block_reserve(unsigned long long* counter, int my,
+                                                 unsigned long long* sh_base, int* tmp) {
+  int total;
+  int incl = block_incl_scan<int, BS, false>(my, tmp, &total);
+  if (threadIdx.x == 0) *sh_base = total ? atomicAdd(counter, (unsigned long long)total) : 0ull;
+  __syncthreads();
+  int64_t base = (int64_t)*sh_base + (incl - my);
+  __syncthreads();
+  return base;
+}
 
 struct LevelWork {
   unsigned long long* info;  // [I_NINFO]
@@ -97,6 +115,7 @@ struct LevelWork {
   uint64_t* temp;            // [nnz]
   int64_t* cnt;              // [n+1]
   int32_t* midlist;          // [n]
+  int32_t* blocklist;        // [n]
   int32_t* hugelist;         // [n]
   int64_t* hmoff;            // [n+1]
   int32_t* hmrow;            // [n]  huge member -> huge row index

@@ -3,9 +3,18 @@
 //   A2 the fitness of every edge, || w_u/d_u - w_v/d_v ||_1 (Theorem 1,
 //      Algorithm 1's fitness loop), evaluated exactly as N / D,
 //   A3 a strict total order on edges (score, then smaller endpoint, then
-//      larger endpoint) encoded as one unique 64-bit key per edge,
+//      larger endpoint) encoded as one 64-bit key per edge,
 //   A4 the merge loop of Algorithm 1, computed as the components of the
 //      lightest n - t edges of the minimum spanning forest under that order.
+//
+// The order key.  With e the edge's position in (u, v) order and
+// K = floor(score * 2^c), c = 62 - bits(e), the key is P = (K << bits(e)) | e.
+// Two different scores N1/D1 != N2/D2 differ by at least 1/(D1 D2), so K
+// separates them whenever 2^c >= Dmax^2 ("exact" keys).  Otherwise the keys
+// are "guarded": every decision that could hinge on two edges sharing one
+// K bucket (a component's lightest edge, the rank cutoff) is re-checked
+// with the exact cross-multiplied comparison, and a level whose check fails
+// is redone with keys = ranks from an exact comparison sort.
 #include "level.hpp"
 
 namespace spc {
@@ -46,6 +55,7 @@ void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W) {
   W.temp = A.take<uint64_t>(nnz);
   W.cnt = A.take<int64_t>(n + 1);
   W.midlist = A.take<int32_t>(n);
+  W.blocklist = A.take<int32_t>(n);
   W.hugelist = A.take<int32_t>(n);
   W.hmoff = A.take<int64_t>(n + 1);
   W.hmrow = A.take<int32_t>(n);
@@ -55,24 +65,34 @@ void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W) {
   W.gkeyB = A.take<uint64_t>(2 * nnz);
 }
 
+constexpr int BS = 256;
+
 // ---------------------------------------------------------------------------
-// A1: degrees, upper-entry counts, and per-level initialisation
+// A1: degrees, upper-entry counts, and per-level initialisation.
+// A block covers 4096 consecutive rows, 16 per thread.
 // ---------------------------------------------------------------------------
-constexpr int DEG_BS = 256;
+constexpr int DEG_PER = 16;
+constexpr int DEG_ROWS = BS * DEG_PER;
 constexpr int DEG_SHORT = 64;
 
-__global__ void __launch_bounds__(DEG_BS)
+__global__ void __launch_bounds__(BS)
     k_degree(LevelIn g, uint64_t* __restrict__ deg, int32_t* __restrict__ lc,
              int64_t* __restrict__ ucnt, uint64_t* __restrict__ bestA,
              uint64_t* __restrict__ bestB, int32_t* __restrict__ parent,
              int32_t* __restrict__ longrows, unsigned long long* info) {
-  int64_t u = (int64_t)blockIdx.x * DEG_BS + threadIdx.x;
-  uint64_t d = 0;
-  bool isLong = false;
-  if (u < g.n) {
+  __shared__ int stmp[BS / WAVE];
+  __shared__ unsigned long long sbase;
+  __shared__ uint64_t smx[BS / WAVE], ssm[BS / WAVE];
+  int tid = threadIdx.x;
+  int64_t base = (int64_t)blockIdx.x * DEG_ROWS;
+  uint64_t mx = 0, sm = 0;
+  uint32_t longmask = 0;
+  int nlong = 0;
+  for (int i = 0; i < DEG_PER; i++) {
+    int64_t u = base + i * BS + tid;
+    if (u >= g.n) break;
     int64_t s = g.rp[u], e = g.rp[u + 1];
-    // entries with col < u: binary search in the ascending row
-    int64_t lo = s, hi = e;
+    int64_t lo = s, hi = e;   // entries with col < u
     while (lo < hi) {
       int64_t mid = (lo + hi) >> 1;
       if (g.col[mid] < u) lo = mid + 1;
@@ -81,40 +101,54 @@ __global__ void __launch_bounds__(DEG_BS)
     lc[u] = (int32_t)(lo - s);
     ucnt[u] = e - lo;
     if (e - s <= DEG_SHORT) {
-      d = g.self ? (uint64_t)g.self[u] : 0;
+      uint64_t d = g.self ? (uint64_t)g.self[u] : 0;
       for (int64_t j = s; j < e; j++) d += (uint64_t)g.w[j];
       deg[u] = d;
+      mx = d > mx ? d : mx;
+      sm += d;
     } else {
-      isLong = true;
+      longmask |= 1u << i;
+      nlong++;
     }
     bestA[u] = KEY_INF;
     bestB[u] = KEY_INF;
     parent[u] = (int32_t)u;
   }
-  int64_t slot = wave_append(&info[I_LONG], isLong);
-  if (isLong) longrows[slot] = (int32_t)u;
-  uint64_t mx = wave_max(d);
-  uint64_t sm = wave_sum(d);
+  mx = wave_max(mx);
+  sm = wave_sum(sm);
   if (lane_id() == 0) {
-    if (mx) atomicMax(&info[I_DMAX], (unsigned long long)mx);
-    if (sm) atomicAdd(&info[I_TOTAL], (unsigned long long)sm);
+    smx[tid / WAVE] = mx;
+    ssm[tid / WAVE] = sm;
   }
+  __syncthreads();
+  if (tid == 0) {
+    uint64_t a = 0, b = 0;
+    for (int w = 0; w < BS / WAVE; w++) {
+      a = smx[w] > a ? smx[w] : a;
+      b += ssm[w];
+    }
+    if (a) atomicMax(&info[I_DMAX], (unsigned long long)a);
+    if (b) atomicAdd(&info[I_TOTAL], (unsigned long long)b);
+  }
+  int64_t pos = block_reserve<BS>(&info[I_LONG], nlong, &sbase, stmp);
+  for (int i = 0; i < DEG_PER; i++)
+    if (longmask >> i & 1u) longrows[pos++] = (int32_t)(base + i * BS + tid);
 }
 
-__global__ void __launch_bounds__(DEG_BS)
+__global__ void __launch_bounds__(BS)
     k_degree_long(LevelIn g, const int32_t* __restrict__ longrows, uint64_t* __restrict__ deg,
                   unsigned long long* info) {
-  __shared__ uint64_t tmp[DEG_BS / WAVE];
+  __shared__ uint64_t tmp[BS / WAVE];
   int64_t u = longrows[blockIdx.x];
   int64_t s = g.rp[u], e = g.rp[u + 1];
   uint64_t d = 0;
-  for (int64_t j = s + threadIdx.x; j < e; j += DEG_BS) d += (uint64_t)g.w[j];
+  for (int64_t j = s + threadIdx.x; j < e; j += BS) d += (uint64_t)g.w[j];
   d = wave_sum(d);
   if (lane_id() == 0) tmp[threadIdx.x / WAVE] = d;
   __syncthreads();
   if (threadIdx.x == 0) {
     uint64_t t = g.self ? (uint64_t)g.self[u] : 0;
-    for (int i = 0; i < DEG_BS / WAVE; i++) t += tmp[i];
+    for (int i = 0; i < BS / WAVE; i++) t += tmp[i];
     deg[u] = t;
     atomicMax(&info[I_DMAX], (unsigned long long)t);
     atomicAdd(&info[I_TOTAL], (unsigned long long)t);
@@ -208,9 +242,9 @@ __device__ __forceinline__ void edge_score(const LevelIn& g, const uint64_t* __r
   N = 2 * D - 2 * M;
 }
 
-// floor(N * 2^b / D) for N < 2^63, D < 2^62 and a result below 2^62.
+// floor(N * 2^b / D) for N < 2^63, D < 2^62, b <= 61 (the result is below 2^62).
 __device__ __forceinline__ uint64_t fixed_key(uint64_t N, uint64_t D, int b) {
-  if (b < 63 && (N >> (63 - b)) == 0) {
+  if ((N >> (63 - b)) == 0) {
     uint64_t num = N << b;
     if (num < (1ull << 53) && D < (1ull << 53)) {
       // the correctly rounded quotient is at most one above the floor
@@ -224,136 +258,192 @@ __device__ __forceinline__ uint64_t fixed_key(uint64_t N, uint64_t D, int b) {
   return (uint64_t)(num / D);
 }
 
-// ---------------------------------------------------------------------------
-// A2 + A3 (packed key) and the first spanning-forest round, fused:
-// one thread per edge (u < v), tiles of 256 consecutive edge ids mapped to
-// rows by a load-balanced search over the upper-entry prefix uptr.
-// ---------------------------------------------------------------------------
-constexpr int TILE_E = 256;
+__device__ __forceinline__ bool exact_less(const KeyND& x, const KeyND& y) {
+  return (unsigned __int128)x.N * y.D < (unsigned __int128)y.N * x.D;
+}
 
-struct EdgeTile {
-  int32_t srow[TILE_E];
-  int64_t sh[2];
-  int32_t stmp[TILE_E / WAVE];
-};
+// ---------------------------------------------------------------------------
+// A2 + A3 fused with the first spanning-forest round: one thread per edge
+// (u < v) for 4 edges each; tiles of 1024 consecutive edge ids are mapped
+// to rows by a load-balanced search over the upper-entry prefix uptr.
+// ---------------------------------------------------------------------------
+constexpr int TILE_S = 1024;
 
-template <int MODE>  // 0: packed key, 1: write (N, D, e) for the rank sort
-__global__ void __launch_bounds__(TILE_E)
+template <int MODE>  // 0: 64-bit key (+ optional exact records), 1: exact records only
+__global__ void __launch_bounds__(BS)
     k_score(LevelIn g, const uint64_t* __restrict__ deg, const int32_t* __restrict__ lc,
-            const int64_t* __restrict__ uptr, int64_t m, int b, int ebits,
+            const int64_t* __restrict__ uptr, int64_t m, int c, int ebits,
             uint64_t* __restrict__ P, uint64_t* __restrict__ bestA,
-            uint64_t* __restrict__ samples, KeyND* __restrict__ keys) {
-  __shared__ EdgeTile T;
-  int64_t e0 = (int64_t)blockIdx.x * TILE_E;
-  lbs_tile<TILE_E, TILE_E>(uptr, g.n, e0, T.srow, T.sh, T.stmp);
+            uint64_t* __restrict__ samples, KeyND* __restrict__ keys, int write_keys,
+            unsigned long long* info) {
+  __shared__ int32_t srow[TILE_S];
+  __shared__ int64_t sh[2];
+  __shared__ int32_t stmp[BS / WAVE];
+  __shared__ uint64_t sred[BS / WAVE];
+  int64_t e0 = (int64_t)blockIdx.x * TILE_S;
+  lbs_tile<TILE_S, BS>(uptr, g.n, e0, srow, sh, stmp);
   int tid = threadIdx.x;
-  int64_t e = e0 + tid;
-  if (e >= m) return;
-  int32_t u = T.srow[tid];
-  int64_t j = g.rp[u] + lc[u] + (e - uptr[u]);
-  int32_t v = g.col[j];
-  int32_t wuv = g.w[j];
-  uint64_t N, D;
-  edge_score(g, deg, u, v, wuv, N, D);
-  if (MODE == 0) {
-    uint64_t K = fixed_key(N, D, b);
-    uint64_t key = (K << ebits) | (uint64_t)e;
-    P[e] = key;
-    atomicMin((unsigned long long*)&bestA[u], (unsigned long long)key);
-    atomicMin((unsigned long long*)&bestA[v], (unsigned long long)key);
-    if ((e & 63) == 0) samples[e >> 6] = key;
-  } else {
-    keys[e] = KeyND{N, D, (uint64_t)e};
-  }
-}
-
-// Generic edge pass with the same tile mapping.  F(e, u, v, valid) is called
-// by every thread of the block (valid is false beyond m).
-template <typename F>
-__global__ void __launch_bounds__(TILE_E)
-    k_edge_pass(LevelIn g, const int32_t* __restrict__ lc, const int64_t* __restrict__ uptr,
-                int64_t m, F f) {
-  __shared__ EdgeTile T;
-  int64_t e0 = (int64_t)blockIdx.x * TILE_E;
-  lbs_tile<TILE_E, TILE_E>(uptr, g.n, e0, T.srow, T.sh, T.stmp);
-  int tid = threadIdx.x;
-  int64_t e = e0 + tid;
-  bool valid = e < m;
-  int32_t u = 0, v = 0;
-  if (valid) {
-    u = T.srow[tid];
+  uint64_t dmx = 0;
+  for (int i = 0; i < TILE_S / BS; i++) {
+    int k = tid + i * BS;
+    int64_t e = e0 + k;
+    if (e >= m) break;
+    int32_t u = srow[k];
     int64_t j = g.rp[u] + lc[u] + (e - uptr[u]);
-    v = g.col[j];
+    int32_t v = g.col[j];
+    uint64_t N, D;
+    edge_score(g, deg, u, v, g.w[j], N, D);
+    dmx = D > dmx ? D : dmx;
+    if (MODE == 0) {
+      uint64_t K = fixed_key(N, D, c);
+      uint64_t key = (K << ebits) | (uint64_t)e;
+      P[e] = key;
+      atomicMin((unsigned long long*)&bestA[u], (unsigned long long)key);
+      atomicMin((unsigned long long*)&bestA[v], (unsigned long long)key);
+      if ((e & 63) == 0) samples[e >> 6] = key;
+    }
+    if (MODE == 1 || write_keys) keys[e] = KeyND{N, D, (uint64_t)e};
   }
-  f(e, u, v, valid);
+  dmx = wave_max(dmx);
+  if (lane_id() == 0) sred[tid / WAVE] = dmx;
+  __syncthreads();
+  if (tid == 0) {
+    uint64_t a = 0;
+    for (int w = 0; w < BS / WAVE; w++) a = sred[w] > a ? sred[w] : a;
+    atomicMax(&info[I_DMAXE], (unsigned long long)a);
+  }
 }
 
-// rank mode: P[e] = position of e in the sorted order
+// rank order: P[e] = position of e in the exact sorted order
 __global__ void k_rank_scatter(const KeyND* __restrict__ sorted, int64_t m, uint64_t* __restrict__ P) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r < m) P[sorted[r].e] = (uint64_t)r;
 }
 
-struct BestFn {  // first spanning-forest round over every edge
-  const uint64_t* P;
-  uint64_t* best;
-  __device__ void operator()(int64_t e, int32_t u, int32_t v, bool valid) const {
-    if (!valid) return;
+// ---------------------------------------------------------------------------
+// edge passes over 4096-edge tiles (16 edges per thread)
+// ---------------------------------------------------------------------------
+constexpr int TILE_F = 4096;
+constexpr int F_PER = TILE_F / BS;
+
+// every component's lightest incident edge (first forest round)
+__global__ void __launch_bounds__(BS)
+    k_best_pass(LevelIn g, const int32_t* __restrict__ lc, const int64_t* __restrict__ uptr,
+                int64_t m, const uint64_t* __restrict__ P, uint64_t* best) {
+  __shared__ int32_t srow[TILE_F];
+  __shared__ int64_t sh[2];
+  __shared__ int32_t stmp[BS / WAVE];
+  int64_t e0 = (int64_t)blockIdx.x * TILE_F;
+  lbs_tile<TILE_F, BS>(uptr, g.n, e0, srow, sh, stmp);
+  for (int i = 0; i < F_PER; i++) {
+    int k = threadIdx.x + i * BS;
+    int64_t e = e0 + k;
+    if (e >= m) break;
+    int32_t u = srow[k];
+    int32_t v = g.col[g.rp[u] + lc[u] + (e - uptr[u])];
     uint64_t key = P[e];
     atomicMin((unsigned long long*)&best[u], (unsigned long long)key);
     atomicMin((unsigned long long*)&best[v], (unsigned long long)key);
   }
-};
+}
 
-struct FilterFn {  // edges with key <= threshold form the live list
-  const uint64_t* P;
-  const unsigned long long* thr;
-  uint64_t* lr;
-  uint64_t* lp;
-  uint64_t* lo;
-  unsigned long long* cnt;
-  __device__ void operator()(int64_t e, int32_t u, int32_t v, bool valid) const {
-    uint64_t key = valid ? P[e] : KEY_INF;
-    bool keep = valid && key <= *thr;
-    int64_t s = wave_append(cnt, keep);
-    if (keep) {
-      uint64_t uv = (uint64_t)(uint32_t)u | ((uint64_t)(uint32_t)v << 32);
-      lr[s] = uv;
-      lp[s] = key;
-      lo[s] = uv;
+// edges with lo < key <= hi (lo absent for the first band) form the live list
+__global__ void __launch_bounds__(BS)
+    k_filter(LevelIn g, const int32_t* __restrict__ lc, const int64_t* __restrict__ uptr, int64_t m,
+             const uint64_t* __restrict__ P, const unsigned long long* thr_lo,
+             const unsigned long long* thr_hi, int use_lo, uint64_t* __restrict__ lr,
+             uint64_t* __restrict__ lp, uint64_t* __restrict__ lo_out, unsigned long long* cnt) {
+  __shared__ int32_t srow[TILE_F];
+  __shared__ int64_t sh[2];
+  __shared__ int32_t stmp[BS / WAVE];
+  __shared__ unsigned long long sbase;
+  int64_t e0 = (int64_t)blockIdx.x * TILE_F;
+  lbs_tile<TILE_F, BS>(uptr, g.n, e0, srow, sh, stmp);
+  int tid = threadIdx.x;
+  uint64_t tlo = use_lo ? *thr_lo : 0, thi = *thr_hi;
+  uint32_t keep = 0;
+  int nk = 0;
+  for (int i = 0; i < F_PER; i++) {
+    int64_t e = e0 + tid + i * BS;
+    if (e >= m) break;
+    uint64_t p = P[e];
+    if (p <= thi && (!use_lo || p > tlo)) {
+      keep |= 1u << i;
+      nk++;
     }
   }
-};
+  int64_t pos = block_reserve<BS>(cnt, nk, &sbase, stmp);
+  for (int i = 0; i < F_PER; i++) {
+    if (!(keep >> i & 1u)) continue;
+    int k = tid + i * BS;
+    int64_t e = e0 + k;
+    int32_t u = srow[k];
+    int32_t v = g.col[g.rp[u] + lc[u] + (e - uptr[u])];
+    uint64_t uv = (uint64_t)(uint32_t)u | ((uint64_t)(uint32_t)v << 32);
+    lr[pos] = uv;
+    lp[pos] = P[e];
+    lo_out[pos] = uv;
+    pos++;
+  }
+}
 
 // ---------------------------------------------------------------------------
-// A4: spanning-forest rounds (Boruvka) on the live list.
+// A4: spanning-forest rounds (Boruvka) on the live list, in chunks of 4096
+// items per block iteration.
 // ---------------------------------------------------------------------------
-constexpr int BV_BS = 256;
+constexpr int BV_CHUNK = 4096;
+constexpr int BV_PER = BV_CHUNK / BS;
+
+// Guarded keys: the winner w of a component must not have a same-bucket
+// rival x with an exactly smaller score.
+__device__ __forceinline__ void guard_check(const KeyND* __restrict__ keys, int ebits, uint64_t key,
+                                            uint64_t w, int* viol) {
+  if (w == key || w == KEY_INF || (w >> ebits) != (key >> ebits)) return;
+  uint64_t emask = (1ull << ebits) - 1;
+  if (exact_less(keys[key & emask], keys[w & emask])) *viol = 1;
+}
 
 // Every component adopts its lightest live edge; those edges are joined and
 // recorded as forest edges.
-__global__ void __launch_bounds__(BV_BS)
+__global__ void __launch_bounds__(BS)
     k_bv_merge(const uint64_t* __restrict__ lr, const uint64_t* __restrict__ lp,
                const uint64_t* __restrict__ lo, const unsigned long long* cnt,
                const uint64_t* __restrict__ best, int32_t* parent, uint64_t* __restrict__ msfP,
-               uint64_t* __restrict__ msfO, unsigned long long* msfcnt, int64_t msf_cap) {
+               uint64_t* __restrict__ msfO, unsigned long long* msfcnt, int64_t msf_cap,
+               const KeyND* __restrict__ keys, int ebits, int* viol) {
+  __shared__ int stmp[BS / WAVE];
+  __shared__ unsigned long long sbase;
   int64_t n = (int64_t)*cnt;
-  int64_t stride = (int64_t)gridDim.x * BV_BS;
-  for (int64_t base = (int64_t)blockIdx.x * BV_BS; base < n; base += stride) {
-    int64_t i = base + threadIdx.x;
-    bool chosen = false;
-    uint64_t key = 0, uv = 0;
-    if (i < n) {
-      uv = lr[i];
-      key = lp[i];
+  int tid = threadIdx.x;
+  for (int64_t base = (int64_t)blockIdx.x * BV_CHUNK; base < n; base += (int64_t)gridDim.x * BV_CHUNK) {
+    uint32_t chosen = 0;
+    int nc = 0;
+    for (int i = 0; i < BV_PER; i++) {
+      int64_t idx = base + tid + i * BS;
+      if (idx >= n) break;
+      uint64_t uv = lr[idx];
+      uint64_t key = lp[idx];
       int32_t a = (int32_t)(uint32_t)uv, b = (int32_t)(uv >> 32);
-      chosen = (best[a] == key) || (best[b] == key);
-      if (chosen) uf_union(parent, a, b);
+      uint64_t wa = best[a], wb = best[b];
+      if (keys) {
+        guard_check(keys, ebits, key, wa, viol);
+        guard_check(keys, ebits, key, wb, viol);
+      }
+      if (wa == key || wb == key) {
+        uf_union(parent, a, b);
+        chosen |= 1u << i;
+        nc++;
+      }
     }
-    int64_t s = wave_append(msfcnt, chosen);
-    if (chosen && s < msf_cap) {  // a forest has fewer than n edges
-      msfP[s] = key;
-      msfO[s] = lo[i];
+    int64_t pos = block_reserve<BS>(msfcnt, nc, &sbase, stmp);
+    for (int i = 0; i < BV_PER; i++) {
+      if (!(chosen >> i & 1u)) continue;
+      int64_t idx = base + tid + i * BS;
+      if (pos < msf_cap) {  // a forest has fewer than n edges
+        msfP[pos] = lp[idx];
+        msfO[pos] = lo[idx];
+      }
+      pos++;
     }
   }
 }
@@ -362,38 +452,64 @@ __global__ void __launch_bounds__(BV_BS)
 // their current roots, move to the next list; each component's lightest
 // live edge is found with atomicMin on the key.  The other best array is
 // reset at every root that still has a live edge.
-__global__ void __launch_bounds__(BV_BS)
+__global__ void __launch_bounds__(BS)
     k_bv_candidates(const uint64_t* __restrict__ lr_in, const uint64_t* __restrict__ lp_in,
                     const uint64_t* __restrict__ lo_in, const unsigned long long* cnt_in,
                     uint64_t* __restrict__ lr_out, uint64_t* __restrict__ lp_out,
                     uint64_t* __restrict__ lo_out, unsigned long long* cnt_out, uint64_t* cur,
                     uint64_t* nxt, int32_t* parent) {
+  __shared__ int stmp[BS / WAVE];
+  __shared__ unsigned long long sbase;
   int64_t n = (int64_t)*cnt_in;
-  int64_t stride = (int64_t)gridDim.x * BV_BS;
-  for (int64_t base = (int64_t)blockIdx.x * BV_BS; base < n; base += stride) {
-    int64_t i = base + threadIdx.x;
-    bool keep = false;
-    uint64_t key = 0, ruv = 0;
-    if (i < n) {
-      uint64_t uv = lr_in[i];
-      key = lp_in[i];
+  int tid = threadIdx.x;
+  for (int64_t base = (int64_t)blockIdx.x * BV_CHUNK; base < n; base += (int64_t)gridDim.x * BV_CHUNK) {
+    uint32_t keep = 0;
+    int nk = 0;
+    uint64_t ruv[BV_PER];
+    for (int i = 0; i < BV_PER; i++) {
+      ruv[i] = 0;
+      int64_t idx = base + tid + i * BS;
+      if (idx >= n) break;
+      uint64_t uv = lr_in[idx];
+      uint64_t key = lp_in[idx];
       int32_t a = uf_find(parent, (int32_t)(uint32_t)uv);
       int32_t b = uf_find(parent, (int32_t)(uv >> 32));
       if (a != b) {
-        keep = true;
         atomicMin((unsigned long long*)&cur[a], (unsigned long long)key);
         atomicMin((unsigned long long*)&cur[b], (unsigned long long)key);
         nxt[a] = KEY_INF;
         nxt[b] = KEY_INF;
-        ruv = (uint64_t)(uint32_t)a | ((uint64_t)(uint32_t)b << 32);
+        ruv[i] = (uint64_t)(uint32_t)a | ((uint64_t)(uint32_t)b << 32);
+        keep |= 1u << i;
+        nk++;
       }
     }
-    int64_t s = wave_append(cnt_out, keep);
-    if (keep) {
-      lr_out[s] = ruv;
-      lp_out[s] = key;
-      lo_out[s] = lo_in[i];
+    int64_t pos = block_reserve<BS>(cnt_out, nk, &sbase, stmp);
+    for (int i = 0; i < BV_PER; i++) {
+      if (!(keep >> i & 1u)) continue;
+      int64_t idx = base + tid + i * BS;
+      lr_out[pos] = ruv[i];
+      lp_out[pos] = lp_in[idx];
+      lo_out[pos] = lo_in[idx];
+      pos++;
     }
+  }
+}
+
+// Guarded keys at the cutoff: every forest edge sharing the cutoff's K
+// bucket must have exactly the cutoff's score (then the edge order inside
+// the bucket is the exact one).
+__global__ void k_cutoff_check(const uint64_t* __restrict__ msfP, const unsigned long long* cnt,
+                               const SelState* st, const KeyND* __restrict__ keys, int ebits, int* viol) {
+  int64_t n = (int64_t)*cnt;
+  uint64_t T = st->prefix;
+  uint64_t emask = (1ull << ebits) - 1;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    uint64_t p = msfP[i];
+    if (p == T || (p >> ebits) != (T >> ebits)) continue;
+    KeyND x = keys[p & emask], y = keys[T & emask];
+    if ((unsigned __int128)x.N * y.D != (unsigned __int128)y.N * x.D) *viol = 1;
   }
 }
 
@@ -432,6 +548,30 @@ __global__ void k_relabel(const int32_t* __restrict__ root, const int32_t* __res
                           int32_t* __restrict__ cluster_of, int64_t n) {
   int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (x < n) cluster_of[x] = cid[root[x]];
+}
+
+// Theorem 2's epsilon: the score of the heaviest accepted edge, which is
+// the forest edge whose key equals the cutoff.
+__global__ void k_eps(LevelIn g, const uint64_t* __restrict__ deg, const uint64_t* __restrict__ msfP,
+                      const uint64_t* __restrict__ msfO, const unsigned long long* cnt,
+                      const SelState* st, double* out) {
+  int64_t n = (int64_t)*cnt;
+  uint64_t T = st->prefix;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    if (msfP[i] != T) continue;
+    uint64_t uv = msfO[i];
+    int32_t u = (int32_t)(uint32_t)uv, v = (int32_t)(uv >> 32);
+    int64_t lo = g.rp[u], hi = g.rp[u + 1];
+    while (lo < hi) {
+      int64_t mid = (lo + hi) >> 1;
+      if (g.col[mid] < v) lo = mid + 1;
+      else hi = mid;
+    }
+    uint64_t N, D;
+    edge_score(g, deg, u, v, g.w[lo], N, D);
+    *out = (double)N / (double)D;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -525,53 +665,46 @@ __global__ void k_fill_u64(uint64_t* __restrict__ a, int64_t n, uint64_t v) {
   if (i < n) a[i] = v;
 }
 
-// threshold of the live list: the selected sample key, or "everything"
-__global__ void k_thr_from_sel(const SelState* st, unsigned long long* thr, int all) {
-  *thr = all ? KEY_INF : st->prefix;
+// upper threshold of a band: the selected sample key widened to the end of
+// its K bucket, or "everything"
+__global__ void k_thr_from_sel(const SelState* st, unsigned long long* thr, int all, int ebits) {
+  if (all) *thr = KEY_INF;
+  else *thr = st->prefix | ((1ull << ebits) - 1);
 }
 
-// Theorem 2's epsilon: the score of the heaviest accepted edge, which is
-// the forest edge whose key equals the cutoff.
-__global__ void k_eps(LevelIn g, const uint64_t* __restrict__ deg, const uint64_t* __restrict__ msfP,
-                      const uint64_t* __restrict__ msfO, const unsigned long long* cnt,
-                      const SelState* st, double* out) {
-  int64_t n = (int64_t)*cnt;
-  uint64_t T = st->prefix;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    if (msfP[i] != T) continue;
-    uint64_t uv = msfO[i];
-    int32_t u = (int32_t)(uint32_t)uv, v = (int32_t)(uv >> 32);
-    int64_t lo = g.rp[u], hi = g.rp[u + 1];
-    while (lo < hi) {
-      int64_t mid = (lo + hi) >> 1;
-      if (g.col[mid] < v) lo = mid + 1;
-      else hi = mid;
-    }
-    uint64_t N, D;
-    edge_score(g, deg, u, v, g.w[lo], N, D);
-    *out = (double)N / (double)D;
-  }
-}
-
-static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t& rounds,
-                           int64_t& live0) {
-  unsigned long long* info = W.info;
-  int64_t* hinfo = ctx->h_pinned;
-  // round 1 on the filtered list with bestA from the score pass
-  SPC_HIP(ctx, hipMemcpyAsync(hinfo, info, sizeof(unsigned long long) * I_NINFO,
+static int sync_info(spc_ctx* ctx, const LevelWork& W) {
+  SPC_HIP(ctx, hipMemcpyAsync(ctx->h_pinned, W.info, sizeof(unsigned long long) * I_NINFO,
                               hipMemcpyDeviceToHost, ctx->stream));
   SPC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return SPC_OK;
+}
+
+// Spanning forest of the live list lr[0]/lp[0]/lo[0] (count in info[I_LIVE0])
+// on top of the components already in parent.  With fused_first, bestA
+// already holds every node's lightest incident key (first round done by the
+// key pass); otherwise both best arrays must be all-infinite on entry.
+static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, bool fused_first,
+                           const KeyND* guard_keys, int ebits, int64_t& rounds, int64_t& live0) {
+  unsigned long long* info = W.info;
+  int64_t* hinfo = ctx->h_pinned;
+  int* viol = (int*)&info[I_VIOL];
+  int rc = sync_info(ctx, W);
+  if (rc) return rc;
   int64_t cnt = hinfo[I_LIVE0];
   live0 = cnt;
-  rounds = 1;
-  int maxgrid = ctx->num_cus * 8;
-  hipLaunchKernelGGL(k_bv_merge, dim3(grid_for(cnt, BV_BS, maxgrid)), dim3(BV_BS), 0, ctx->stream,
-                     W.lr[0], W.lp[0], W.lo[0], &info[I_LIVE0], W.bestA, W.parent, W.msfP, W.msfO,
-                     &info[I_MSF], n);
+  int maxgrid = ctx->num_cus * 4;
+  uint64_t* cur = W.bestA;
+  uint64_t* nxt = W.bestB;
   int in = 0;
-  uint64_t* cur = W.bestB;
-  uint64_t* nxt = W.bestA;
+  if (fused_first && cnt > 0) {
+    rounds++;
+    TimedScope ts(ctx, "forest_merge", (double)cnt);
+    hipLaunchKernelGGL(k_bv_merge, dim3(grid_for(cnt, BV_CHUNK, maxgrid)), dim3(BS), 0, ctx->stream,
+                       W.lr[0], W.lp[0], W.lo[0], &info[I_LIVE0], cur, W.parent, W.msfP, W.msfO,
+                       &info[I_MSF], n, guard_keys, ebits, viol);
+    cur = W.bestB;
+    nxt = W.bestA;
+  }
   while (cnt > 0) {
     // every round at least halves the components that still have live
     // edges, so more than 64 rounds means corrupted state
@@ -580,25 +713,165 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t& round
     int ci = in == 0 ? I_LIVE0 : I_LIVE1;
     int co = out == 0 ? I_LIVE0 : I_LIVE1;
     hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, ctx->stream, &info[co], 0ull);
-    hipLaunchKernelGGL(k_bv_candidates, dim3(grid_for(cnt, BV_BS, maxgrid)), dim3(BV_BS), 0,
-                       ctx->stream, W.lr[in], W.lp[in], W.lo[in], &info[ci], W.lr[out], W.lp[out],
-                       W.lo[out], &info[co], cur, nxt, W.parent);
-    SPC_LAUNCH_CHECK(ctx, "boruvka candidates");
+    {
+      TimedScope ts(ctx, "forest_candidates", (double)cnt);
+      hipLaunchKernelGGL(k_bv_candidates, dim3(grid_for(cnt, BV_CHUNK, maxgrid)), dim3(BS), 0,
+                         ctx->stream, W.lr[in], W.lp[in], W.lo[in], &info[ci], W.lr[out], W.lp[out],
+                         W.lo[out], &info[co], cur, nxt, W.parent);
+    }
+    SPC_LAUNCH_CHECK(ctx, "forest candidates");
     SPC_HIP(ctx, hipMemcpyAsync(&hinfo[co], &info[co], sizeof(unsigned long long),
                                 hipMemcpyDeviceToHost, ctx->stream));
     SPC_HIP(ctx, hipStreamSynchronize(ctx->stream));
     cnt = hinfo[co];
     if (cnt == 0) break;
     rounds++;
-    hipLaunchKernelGGL(k_bv_merge, dim3(grid_for(cnt, BV_BS, maxgrid)), dim3(BV_BS), 0,
-                       ctx->stream, W.lr[out], W.lp[out], W.lo[out], &info[co], cur, W.parent,
-                       W.msfP, W.msfO, &info[I_MSF], n);
-    SPC_LAUNCH_CHECK(ctx, "boruvka merge");
+    {
+      TimedScope ts(ctx, "forest_merge", (double)cnt);
+      hipLaunchKernelGGL(k_bv_merge, dim3(grid_for(cnt, BV_CHUNK, maxgrid)), dim3(BS), 0,
+                         ctx->stream, W.lr[out], W.lp[out], W.lo[out], &info[co], cur, W.parent,
+                         W.msfP, W.msfO, &info[I_MSF], n, guard_keys, ebits, viol);
+    }
+    SPC_LAUNCH_CHECK(ctx, "forest merge");
     uint64_t* t = cur;
     cur = nxt;
     nxt = t;
     in = out;
   }
+  // leave the band's final live list where the next band expects none
+  return SPC_OK;
+}
+
+// Key pass, bands of candidate edges, spanning forest, cutoff.  On return
+// sel2->prefix holds the key of the k-th lightest forest edge and
+// info[I_VIOL] says whether a guarded decision failed.
+static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k, int64_t m,
+                            uint64_t dmax, bool rank, LevelWork& W, LevelResult& R, bool& viol_out) {
+  hipStream_t st = ctx->stream;
+  int64_t n = g.n;
+  unsigned long long* info = W.info;
+  int64_t* hinfo = ctx->h_pinned;
+  int ebits = bitlen64((uint64_t)(m - 1));
+  if (ebits < 1) ebits = 1;
+  int c = 62 - ebits;
+  // Dmax <= dmax^2; the key is exact for sure when dmax^4 <= 2^c
+  unsigned __int128 d2 = (unsigned __int128)dmax * dmax;
+  bool surely_exact = d2 * d2 <= ((unsigned __int128)1 << c);
+  int tiles_s = grid_for(m, TILE_S);
+  int tiles_f = grid_for(m, TILE_F);
+  bool guarded = false;
+  if (!rank) {
+    int write_keys = surely_exact ? 0 : 1;
+    TimedScope ts(ctx, "score", (double)m);
+    hipLaunchKernelGGL(k_score<0>, dim3(tiles_s), dim3(BS), 0, st, g, W.deg, W.lc, W.uptr, m, c,
+                       ebits, W.P, W.bestA, W.samples, W.keysA, write_keys, info);
+    SPC_LAUNCH_CHECK(ctx, "score");
+    if (!surely_exact) {
+      int rc = sync_info(ctx, W);
+      if (rc) return rc;
+      uint64_t De = (uint64_t)hinfo[I_DMAXE];
+      unsigned __int128 D2 = (unsigned __int128)De * De;
+      guarded = D2 > ((unsigned __int128)1 << c);
+    }
+    R.key_mode = guarded ? 2 : 0;
+    R.key_bits = 64;
+  } else {
+    {
+      TimedScope ts(ctx, "score_rank", (double)m);
+      hipLaunchKernelGGL(k_score<1>, dim3(tiles_s), dim3(BS), 0, st, g, W.deg, W.lc, W.uptr, m, c,
+                         ebits, (uint64_t*)nullptr, (uint64_t*)nullptr, (uint64_t*)nullptr, W.keysA,
+                         1, info);
+    }
+    SPC_LAUNCH_CHECK(ctx, "score(rank)");
+    KeyND* sorted = nullptr;
+    {
+      TimedScope ts(ctx, "rank_sort", (double)m);
+      int rc = merge_sort<KeyND, LessND>(ctx, W.keysA, W.keysB, m, LessND(), &sorted);
+      if (rc) return rc;
+    }
+    TimedScope ts(ctx, "rank_scatter_best", (double)m);
+    hipLaunchKernelGGL(k_rank_scatter, dim3(grid_for(m, 256)), dim3(256), 0, st, sorted, m, W.P);
+    hipLaunchKernelGGL(k_best_pass, dim3(tiles_f), dim3(BS), 0, st, g, W.lc, W.uptr, m, W.P, W.bestA);
+    SPC_LAUNCH_CHECK(ctx, "rank best");
+    R.key_mode = 1;
+    R.key_bits = bitlen64((uint64_t)(m - 1));
+  }
+  const KeyND* gk = guarded ? W.keysA : nullptr;
+
+  // A4: bands of the lightest edges; each band extends the forest built so far
+  unsigned long long* thr_lo = &info[I_BAD];
+  unsigned long long* thr_hi = &info[I_NC];
+  int64_t target = k + k / 2 + 4096;
+  int64_t done_cand = 0;
+  R.rounds = 0;
+  R.candidates = 0;
+  for (int band = 0;; band++) {
+    bool all = ctx->force_full_filter || target >= m || band >= 2;
+    if (band > 0) {
+      hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestA, n, KEY_INF);
+      hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestB, n, KEY_INF);
+      // the previous band's upper bound is this band's lower bound
+      SPC_HIP(ctx, hipMemcpyAsync(thr_lo, thr_hi, sizeof(unsigned long long), hipMemcpyDeviceToDevice, st));
+    }
+    if (all) {
+      hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits);
+    } else if (!rank) {
+      int64_t ns = (m + 63) / 64;
+      int64_t q = (int64_t)((double)target / 64.0 * 1.05) + 16;
+      if (q >= ns) {
+        all = true;
+        hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits);
+      } else {
+        TimedScope ts(ctx, "select_threshold", (double)ns);
+        int rc = radix_select(ctx, W.samples, nullptr, ns, nullptr, (unsigned long long)q, 64, W.sel);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 0, ebits);
+      }
+    } else {
+      hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, thr_hi, (unsigned long long)(target - 1));
+    }
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, &info[I_LIVE0], 0ull);
+    {
+      TimedScope ts(ctx, "filter", (double)m);
+      hipLaunchKernelGGL(k_filter, dim3(tiles_f), dim3(BS), 0, st, g, W.lc, W.uptr, m, W.P, thr_lo,
+                         thr_hi, band > 0 ? 1 : 0, W.lr[0], W.lp[0], W.lo[0], &info[I_LIVE0]);
+    }
+    SPC_LAUNCH_CHECK(ctx, "filter");
+    int64_t live0 = 0;
+    int rc = spanning_forest(ctx, W, n, band == 0, gk, ebits, R.rounds, live0);
+    if (rc) return rc;
+    rc = sync_info(ctx, W);
+    if (rc) return rc;
+    done_cand += live0;
+    R.candidates = done_cand;
+    R.msf = hinfo[I_MSF];
+    if (R.msf >= k) break;
+    if (all)
+      return set_error(ctx, SPC_EUNREACHABLE,
+                       "only %lld merges possible, %lld requested (more than %lld components)",
+                       (long long)R.msf, (long long)k, (long long)t);
+    // candidates needed grow with the shortfall of forest edges per candidate
+    double need = (double)done_cand * 1.3 * (double)k / (double)(R.msf > 0 ? R.msf : 1);
+    int64_t nt = (int64_t)need + 4096;
+    target = nt > 2 * target ? nt : 2 * target;
+  }
+
+  // cutoff: the k-th lightest forest edge
+  {
+    TimedScope ts(ctx, "select_cutoff", (double)R.msf);
+    int bits = rank ? bitlen64((uint64_t)(m - 1)) : 64;
+    int rc = radix_select(ctx, W.msfP, &info[I_MSF], n, nullptr, (unsigned long long)(k - 1), bits,
+                          W.sel2);
+    if (rc) return rc;
+  }
+  if (guarded) {
+    hipLaunchKernelGGL(k_cutoff_check, dim3(grid_for(R.msf, 256, ctx->num_cus * 4)), dim3(256), 0, st,
+                       W.msfP, &info[I_MSF], W.sel2, W.keysA, ebits, (int*)&info[I_VIOL]);
+    SPC_LAUNCH_CHECK(ctx, "cutoff check");
+  }
+  int rc = sync_info(ctx, W);
+  if (rc) return rc;
+  viol_out = hinfo[I_VIOL] != 0;
   return SPC_OK;
 }
 
@@ -612,20 +885,20 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
   SPC_HIP(ctx, hipMemsetAsync(info, 0, sizeof(unsigned long long) * I_NINFO, st));
 
   // A1
-  hipLaunchKernelGGL(k_degree, dim3(grid_for(n, DEG_BS)), dim3(DEG_BS), 0, st, g, W.deg, W.lc, W.uptr,
-                     W.bestA, W.bestB, W.parent, W.longrows, info);
+  {
+    TimedScope ts(ctx, "degree", (double)n);
+    hipLaunchKernelGGL(k_degree, dim3(grid_for(n, DEG_ROWS)), dim3(BS), 0, st, g, W.deg, W.lc, W.uptr,
+                       W.bestA, W.bestB, W.parent, W.longrows, info);
+  }
   SPC_LAUNCH_CHECK(ctx, "degree");
-  SPC_HIP(ctx, hipMemcpyAsync(hinfo, info, sizeof(unsigned long long) * I_NINFO,
-                              hipMemcpyDeviceToHost, st));
-  SPC_HIP(ctx, hipStreamSynchronize(st));
+  int rc = sync_info(ctx, W);
+  if (rc) return rc;
   int64_t nlong = hinfo[I_LONG];
   if (nlong > 0) {
-    hipLaunchKernelGGL(k_degree_long, dim3((unsigned)nlong), dim3(DEG_BS), 0, st, g, W.longrows,
-                       W.deg, info);
+    hipLaunchKernelGGL(k_degree_long, dim3((unsigned)nlong), dim3(BS), 0, st, g, W.longrows, W.deg, info);
     SPC_LAUNCH_CHECK(ctx, "degree_long");
-    SPC_HIP(ctx, hipMemcpyAsync(hinfo, info, sizeof(unsigned long long) * I_NINFO,
-                                hipMemcpyDeviceToHost, st));
-    SPC_HIP(ctx, hipStreamSynchronize(st));
+    rc = sync_info(ctx, W);
+    if (rc) return rc;
   }
   uint64_t dmax = (uint64_t)hinfo[I_DMAX];
   uint64_t total = (uint64_t)hinfo[I_TOTAL];
@@ -633,7 +906,8 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
     return set_error(ctx, SPC_EOVERFLOW, "total integer weight %llu exceeds 2^31-1",
                      (unsigned long long)total);
   {
-    int rc = exclusive_scan<int64_t>(ctx, W.uptr, W.uptr, n, (int64_t*)W.scan_partial);
+    TimedScope ts(ctx, "scan_upper", (double)n);
+    rc = exclusive_scan<int64_t>(ctx, W.uptr, W.uptr, n, (int64_t*)W.scan_partial);
     if (rc) return rc;
   }
   if (k <= 0 || m == 0) {
@@ -644,110 +918,48 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
     return SPC_OK;
   }
 
-  // A2 + A3
-  int L = bitlen64(dmax > 0 ? dmax - 1 : 0);  // dmax <= 2^L
-  int b = 4 * L;                               // 2^b >= (max D)^2
-  int ebits = bitlen64((uint64_t)(m - 1));
-  if (ebits < 1) ebits = 1;
-  bool packed = (b + 2 + ebits <= 64) && !ctx->force_rank_mode;
-  R.key_mode = packed ? 0 : 1;
-  R.key_bits = packed ? b + 2 + ebits : bitlen64((uint64_t)(m - 1));
-  int eg = grid_for(m, TILE_E);
-  KeyND* sorted = nullptr;
-  if (packed) {
-    hipLaunchKernelGGL(k_score<0>, dim3(eg), dim3(TILE_E), 0, st, g, W.deg, W.lc, W.uptr, m, b,
-                       ebits, W.P, W.bestA, W.samples, (KeyND*)nullptr);
-    SPC_LAUNCH_CHECK(ctx, "score");
-  } else {
-    hipLaunchKernelGGL(k_score<1>, dim3(eg), dim3(TILE_E), 0, st, g, W.deg, W.lc, W.uptr, m, b,
-                       ebits, (uint64_t*)nullptr, (uint64_t*)nullptr, (uint64_t*)nullptr, W.keysA);
-    SPC_LAUNCH_CHECK(ctx, "score(rank)");
-    int rc = merge_sort<KeyND, LessND>(ctx, W.keysA, W.keysB, m, LessND(), &sorted);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_rank_scatter, dim3(grid_for(m, 256)), dim3(256), 0, st, sorted, m, W.P);
-    hipLaunchKernelGGL((k_edge_pass<BestFn>), dim3(eg), dim3(TILE_E), 0, st, g, W.lc, W.uptr, m,
-                       BestFn{W.P, W.bestA});
-    SPC_LAUNCH_CHECK(ctx, "rank best");
-  }
-
-  // A4: live list of the lightest edges, spanning forest, cutoff, components
-  unsigned long long* thr = &info[I_BAD];  // reuse a slot for the live threshold
-  int64_t target = k + k / 2 + 4096;
-  bool all = ctx->force_full_filter || target >= m;
-  for (int attempt = 0; attempt < 2; attempt++) {
-    if (attempt == 1) {
-      // not enough forest edges below the threshold: redo over every edge
-      all = true;
+  // A2-A4; a guarded key that fails its exactness check falls back to ranks
+  bool rank = ctx->force_rank_mode != 0;
+  for (int pass = 0; pass < 2; pass++) {
+    if (pass == 1) {
+      rank = true;
+      SPC_HIP(ctx, hipMemsetAsync(&info[I_MSF], 0, sizeof(unsigned long long), st));
+      SPC_HIP(ctx, hipMemsetAsync(&info[I_VIOL], 0, sizeof(unsigned long long), st));
       hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256)), dim3(256), 0, st, W.parent, n);
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestA, n, KEY_INF);
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestB, n, KEY_INF);
-      hipLaunchKernelGGL((k_edge_pass<BestFn>), dim3(eg), dim3(TILE_E), 0, st, g, W.lc, W.uptr, m,
-                         BestFn{W.P, W.bestA});
-      hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, &info[I_MSF], 0ull);
     }
-    if (all) {
-      hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr, 1);
-    } else if (packed) {
-      int64_t ns = (m + 63) / 64;
-      int64_t q = (int64_t)((double)target / 64.0 * 1.05) + 16;
-      if (q >= ns) {
-        hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr, 1);
-      } else {
-        int rc = radix_select(ctx, W.samples, nullptr, ns, nullptr, (unsigned long long)q,
-                              b + 2 + ebits, W.sel);
-        if (rc) return rc;
-        hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr, 0);
-      }
-    } else {
-      hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, thr, (unsigned long long)(target - 1));
-    }
-    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, &info[I_LIVE0], 0ull);
-    hipLaunchKernelGGL((k_edge_pass<FilterFn>), dim3(eg), dim3(TILE_E), 0, st, g, W.lc, W.uptr, m,
-                       FilterFn{W.P, thr, W.lr[0], W.lp[0], W.lo[0], &info[I_LIVE0]});
-    SPC_LAUNCH_CHECK(ctx, "filter");
-    int64_t rounds = 0, live0 = 0;
-    int rc = spanning_forest(ctx, W, n, rounds, live0);
+    bool viol = false;
+    rc = order_and_select(ctx, g, t, k, m, dmax, rank, W, R, viol);
     if (rc) return rc;
-    SPC_HIP(ctx, hipMemcpyAsync(hinfo, info, sizeof(unsigned long long) * I_NINFO,
-                                hipMemcpyDeviceToHost, st));
-    SPC_HIP(ctx, hipStreamSynchronize(st));
-    R.rounds = rounds;
-    R.candidates = live0;
-    R.msf = hinfo[I_MSF];
-    if (R.msf >= k) break;
-    if (all) return set_error(ctx, SPC_EUNREACHABLE,
-                              "only %lld merges possible, %lld requested (graph has more than %lld components)",
-                              (long long)R.msf, (long long)k, (long long)t);
+    if (!viol) break;
+    if (rank) return set_error(ctx, SPC_EINVAL, "internal: exact rank order flagged as inexact");
   }
 
-  // cutoff: the k-th lightest forest edge
-  int bits = packed ? (b + 2 + ebits) : bitlen64((uint64_t)(m - 1));
   {
-    int rc = radix_select(ctx, W.msfP, &info[I_MSF], n, nullptr, (unsigned long long)(k - 1), bits,
-                          W.sel2);
-    if (rc) return rc;
+    TimedScope ts(ctx, "components", (double)n);
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256)), dim3(256), 0, st, W.parent, n);
+    hipLaunchKernelGGL(k_cc_union, dim3(grid_for(R.msf, 256, ctx->num_cus * 8)), dim3(256), 0, st,
+                       W.msfP, W.msfO, &info[I_MSF], W.sel2, W.parent);
+    hipLaunchKernelGGL(k_cc_flatten, dim3(grid_for(n, 256)), dim3(256), 0, st, W.parent, W.root,
+                       W.flag, n);
   }
-  hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256)), dim3(256), 0, st, W.parent, n);
-  hipLaunchKernelGGL(k_cc_union, dim3(grid_for(R.msf, 256, ctx->num_cus * 8)), dim3(256), 0, st,
-                     W.msfP, W.msfO, &info[I_MSF], W.sel2, W.parent);
-  hipLaunchKernelGGL(k_cc_flatten, dim3(grid_for(n, 256)), dim3(256), 0, st, W.parent, W.root,
-                     W.flag, n);
   SPC_LAUNCH_CHECK(ctx, "components");
   {
-    int rc = exclusive_scan<int32_t>(ctx, W.flag, W.flag, n, (int32_t*)W.scan_partial);
+    TimedScope ts(ctx, "relabel", (double)n);
+    rc = exclusive_scan<int32_t>(ctx, W.flag, W.flag, n, (int32_t*)W.scan_partial);
     if (rc) return rc;
+    hipLaunchKernelGGL(k_relabel, dim3(grid_for(n, 256)), dim3(256), 0, st, W.root, W.flag,
+                       cluster_of, n);
   }
-  hipLaunchKernelGGL(k_relabel, dim3(grid_for(n, 256)), dim3(256), 0, st, W.root, W.flag,
-                     cluster_of, n);
   double* deps = (double*)&info[I_EPS];
   hipLaunchKernelGGL(k_eps, dim3(grid_for(R.msf, 256, ctx->num_cus * 4)), dim3(256), 0, st, g, W.deg,
                      W.msfP, W.msfO, &info[I_MSF], W.sel2, deps);
   SPC_LAUNCH_CHECK(ctx, "relabel");
   int32_t nc32 = 0;
   SPC_HIP(ctx, hipMemcpyAsync(&nc32, W.flag + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  SPC_HIP(ctx, hipMemcpyAsync(hinfo, info, sizeof(unsigned long long) * I_NINFO,
-                              hipMemcpyDeviceToHost, st));
-  SPC_HIP(ctx, hipStreamSynchronize(st));
+  rc = sync_info(ctx, W);
+  if (rc) return rc;
   double eps;
   memcpy(&eps, &hinfo[I_EPS], sizeof(double));
   R.eps = eps;

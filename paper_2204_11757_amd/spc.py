@@ -29,7 +29,7 @@ EXPORTS = [
     "spc_last_error",
     "spc_strerror", "spc_coarsen_level", "spc_coarsen_to", "spc_hier_num_levels",
     "spc_hier_level", "spc_hier_export_level", "spc_hier_free", "spc_lift",
-    "spc_spectral_error", "spc_validate_graph",
+    "spc_spectral_error", "spc_validate_graph", "spc_timing_report",
 ]
 
 
@@ -90,6 +90,7 @@ def lib():
             "spc_lift": [p, p, i32, i32, i32, p, i32, p],
             "spc_spectral_error": [p, p, i32, p, p, i32, p, C.POINTER(C.c_double)],
             "spc_validate_graph": [C.POINTER(_Graph)],
+            "spc_timing_report": [p, C.c_char_p, C.c_size_t],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -234,6 +235,19 @@ def set_option(name: str, value: int, device=None):
     """Context option (tests / tuning): "rank_order" or "full_forest"."""
     ctx = context(device)
     ctx.check(lib().spc_set_option(ctx.h, name.encode(), int(value)))
+
+
+def timing_report(device=None) -> dict:
+    """Per-kernel timings collected while the "timing" option was on:
+    {name: (launches, total_ms, work_units)}.  Clears the collection."""
+    ctx = context(device)
+    buf = C.create_string_buffer(1 << 16)
+    ctx.check(lib().spc_timing_report(ctx.h, buf, len(buf)))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, cnt, ms, units = line.split()
+        out[name] = (int(cnt), float(ms), float(units))
+    return out
 
 
 def _dev(t: torch.Tensor) -> int:
