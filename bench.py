@@ -98,6 +98,9 @@ def main():
     ap.add_argument("--config", default="grid3d-128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 1 GiB device-to-device tensor copy (reference kernel for "
+                         "scaling hardware byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -111,6 +114,12 @@ def main():
     from paper_2204_11757_amd import spc
     dg = spc.DeviceGraph.from_host(g, "cuda:0")
     torch.cuda.synchronize()
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
         h = spc.coarsen_to(dg, n_c, 0)
@@ -142,7 +151,7 @@ def main():
         st = last.stats(l)
         L = {"level": l, "n": st.n_in, "m": st.m_in, "n_c": st.n_out, "nnz_c": st.nnz_out,
              "self": 1 if l > 1 else 0, "ms": round(st.ms_total, 4),
-             "key_mode": "packed" if st.key_mode == 0 else "rank",
+             "key_mode": {0: "exact-packed", 1: "rank", 2: "guarded-packed"}.get(st.key_mode, "?"),
              "forest_rounds": st.boruvka_rounds, "candidate_edges": st.candidate_edges,
              "largest_cluster": st.largest_cluster}
         L["fine_edges_per_s"] = st.m_in / (st.ms_total * 1e-3) if st.ms_total > 0 else None

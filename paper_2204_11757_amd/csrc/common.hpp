@@ -135,12 +135,31 @@ __device__ __forceinline__ int64_t wave_upper_search(const int64_t* __restrict__
   return lo + __popcll(mask) - 1;
 }
 
+// atomicMax on a value many blocks raise: a block whose candidate does not
+// exceed the value already visible skips the atomic (a stale read only costs
+// an unneeded atomic)
+__device__ __forceinline__ void atomic_max_lazy(unsigned long long* p, unsigned long long v) {
+  if (v > __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(p, v);
+}
+
+// LDS layout of a tile's row map: thread t owns positions [t*PER, t*PER+PER)
+// during the scan; one pad word per PER positions keeps those reads free of
+// bank conflicts.
+template <int T, int BS>
+struct Lbs {
+  static constexpr int PER = T / BS;
+  static constexpr int SIZE = T + BS;
+  __device__ __forceinline__ static int at(int k) { return k + k / PER; }
+};
+
 // Load-balanced mapping of a tile of T consecutive positions
 // [p0, p0 + T) of a CSR-like prefix array ptr[0..nrows] onto rows:
-// srow[k] = row containing position p0 + k.  Called by all BS threads.
+// srow[Lbs<T,BS>::at(k)] = row containing position p0 + k (srow holds
+// Lbs<T,BS>::SIZE words).  Called by all BS threads.
 template <int T, int BS>
 __device__ __forceinline__ void lbs_tile(const int64_t* __restrict__ ptr, int64_t nrows, int64_t p0,
                                          int32_t* srow, int64_t* sh, int32_t* scan_tmp) {
+  using L = Lbs<T, BS>;
   int tid = threadIdx.x;
   if (tid < WAVE) {
     int64_t total = ptr[nrows];
@@ -155,21 +174,21 @@ __device__ __forceinline__ void lbs_tile(const int64_t* __restrict__ ptr, int64_
   }
   __syncthreads();
   int64_t r0 = sh[0], r1 = sh[1];
-  for (int k = tid; k < T; k += BS) srow[k] = (int32_t)r0;
+  for (int k = tid; k < T; k += BS) srow[L::at(k)] = (int32_t)r0;
   __syncthreads();
   for (int64_t r = r0 + 1 + tid; r <= r1; r += BS) {
     int64_t p = ptr[r] - p0;
-    if (p > 0 && p < T) atomicMax(&srow[p], (int32_t)r);
+    if (p > 0 && p < T) atomicMax(&srow[L::at((int)p)], (int32_t)r);
   }
   __syncthreads();
   // inclusive max-scan over srow
-  constexpr int PER = T / BS;
+  constexpr int PER = L::PER;
   static_assert(T % BS == 0, "tile must be a multiple of the block");
   int32_t loc[PER];
   int32_t run = INT32_MIN;
 #pragma unroll
   for (int i = 0; i < PER; i++) {
-    int32_t v = srow[tid * PER + i];
+    int32_t v = srow[L::at(tid * PER + i)];
     run = v > run ? v : run;
     loc[i] = run;
   }
@@ -183,7 +202,7 @@ __device__ __forceinline__ void lbs_tile(const int64_t* __restrict__ ptr, int64_
 #pragma unroll
   for (int i = 0; i < PER; i++) {
     int32_t v = loc[i] > prev ? loc[i] : prev;
-    srow[tid * PER + i] = v;
+    srow[L::at(tid * PER + i)] = v;
   }
   __syncthreads();
 }
@@ -258,6 +277,8 @@ struct spc_ctx {
   int err_code = 0;
   std::string err;
   int num_cus = 256;
+  uint32_t lb_epoch = 0;       // last look-back epoch handed out
+  int64_t lb_words = 0;        // size of the current level's look-back array
   // knobs
   int force_rank_mode = 0;   // use the sorted-rank order even when a packed key fits
   int force_full_filter = 0; // run the spanning-forest phase over every edge

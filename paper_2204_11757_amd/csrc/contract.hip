@@ -18,7 +18,8 @@
 
 namespace spc {
 
-constexpr int SMALL_CAP = 32;
+constexpr int SMALL_CAP = 16;
+constexpr int REG32_CAP = 32;
 constexpr int SMALL_BS = 128;
 constexpr int SMALL_RPT = 4;   // rows per thread
 constexpr int WAVE_CAP = 512;
@@ -42,11 +43,55 @@ __device__ __forceinline__ int run_head_of(uint64_t heads) {
   return 63 - __clzll((long long)upto);
 }
 
-// member counts and gathered-entry counts per super-node; lanes of one
-// wavefront that hit the same super-node add once
-__global__ void k_cluster_count(LevelIn g, const int32_t* __restrict__ c, int32_t* mcount,
-                                unsigned long long* ecnt) {
-  int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Member counting and scattering take one node per thread in blocks of
+// CM_BS.  Consecutive nodes of one super-node form runs; a run inside a
+// wavefront is summed with wavefront operations, and runs that continue
+// across wavefront borders are chained by thread 0 so that a super-node
+// spanning the whole block costs one global atomic (a giant super-node
+// would otherwise serialise one atomic per wavefront on one address).
+constexpr int CM_BS = 1024;
+constexpr int CM_W = CM_BS / WAVE;
+
+struct RunPieces {
+  int32_t fk[CM_W], lk[CM_W];             // keys of each wavefront's first / last run
+  int32_t fc[CM_W], lc[CM_W];             // their lengths in nodes
+  unsigned long long fe[CM_W], le[CM_W];  // their summed values
+  int32_t single[CM_W];                   // the wavefront is one run
+  int32_t fb[CM_W], lb[CM_W];             // slot bases handed back (scatter)
+};
+
+// Border pieces: piece 0 of wavefront w is its first run, piece 1 its last
+// run (present when the wavefront holds more than one run).  A chain is a
+// maximal sequence of pieces with one key that touch across wavefront
+// borders.  Thread q < 2 * CM_W looks at piece (q / 2, q % 2); if that piece
+// starts a chain, it returns true with the chain's key, node count and
+// value sum, and its last piece in (wl, pl).
+__device__ __forceinline__ bool chain_at(const RunPieces& P, int q, int32_t& key, int& cnt,
+                                         unsigned long long& sum, int& wl, int& pl) {
+  int w = q >> 1, p = q & 1;
+  if (p == 1 && P.single[w]) return false;
+  key = p ? P.lk[w] : P.fk[w];
+  if (p == 0 && w > 0 && key == (P.single[w - 1] ? P.fk[w - 1] : P.lk[w - 1])) return false;
+  cnt = p ? P.lc[w] : P.fc[w];
+  sum = p ? P.le[w] : P.fe[w];
+  wl = w;
+  pl = p;
+  // extend while the current piece ends its wavefront and the next
+  // wavefront opens with the same key
+  while ((pl == 1 || P.single[wl]) && wl + 1 < CM_W && P.fk[wl + 1] == key) {
+    wl++;
+    pl = 0;
+    cnt += P.fc[wl];
+    sum += P.fe[wl];
+  }
+  return true;
+}
+
+// member counts and gathered-entry counts per super-node
+__global__ void __launch_bounds__(CM_BS)
+    k_cluster_count(LevelIn g, const int32_t* __restrict__ c, int32_t* mcount, unsigned long long* ecnt) {
+  __shared__ RunPieces P;
+  int64_t x = (int64_t)blockIdx.x * CM_BS + threadIdx.x;
   bool valid = x < g.n;
   int32_t a = valid ? c[x] : -1;
   int64_t len = valid ? g.rp[x + 1] - g.rp[x] : 0;
@@ -56,30 +101,190 @@ __global__ void k_cluster_count(LevelIn g, const int32_t* __restrict__ c, int32_
   wave_runs(a, head, end, heads);
   int64_t inc = wave_incl_sum(len);
   int64_t at_end = __shfl(inc, end - 1);
-  if (head && a >= 0) {
-    atomicAdd(&mcount[a], end - lane_id());
-    atomicAdd(&ecnt[a], (unsigned long long)(at_end - inc + len));
+  int l = lane_id(), w = threadIdx.x / WAVE;
+  if (head) {
+    int cnt = end - l;
+    unsigned long long e = (unsigned long long)(at_end - inc + len);
+    bool first = l == 0, last = end == WAVE;
+    if (first) {
+      P.fk[w] = a;
+      P.fc[w] = cnt;
+      P.fe[w] = e;
+      P.single[w] = last ? 1 : 0;
+    } else if (last) {
+      P.lk[w] = a;
+      P.lc[w] = cnt;
+      P.le[w] = e;
+    } else if (a >= 0) {
+      atomicAdd(&mcount[a], cnt);
+      atomicAdd(&ecnt[a], e);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * CM_W) {
+    int32_t k;
+    int cnt, wl, pl;
+    unsigned long long e;
+    if (chain_at(P, threadIdx.x, k, cnt, e, wl, pl) && k >= 0) {
+      atomicAdd(&mcount[k], cnt);
+      atomicAdd(&ecnt[k], e);
+    }
   }
 }
 
-__global__ void k_member_scatter(const int32_t* __restrict__ c, const int32_t* __restrict__ mptr,
-                                 int32_t* mcount, int32_t* __restrict__ members, int64_t n) {
-  int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// members[mptr[a] + slot] = x; slots are taken from the top of mcount[a]
+// downwards (the order of members inside a super-node is arbitrary)
+__global__ void __launch_bounds__(CM_BS)
+    k_member_scatter(const int32_t* __restrict__ c, const int32_t* __restrict__ mptr, int32_t* mcount,
+                     int32_t* __restrict__ members, int64_t n) {
+  __shared__ RunPieces P;
+  int64_t x = (int64_t)blockIdx.x * CM_BS + threadIdx.x;
   bool valid = x < n;
   int32_t a = valid ? c[x] : -1;
   bool head;
   int end;
   uint64_t heads;
   wave_runs(a, head, end, heads);
-  int old = 0;
-  if (head && a >= 0) old = atomicSub(&mcount[a], end - lane_id());
+  int l = lane_id(), w = threadIdx.x / WAVE;
+  int base = 0;   // on head lanes of inner runs: the run's first slot
+  if (head) {
+    int cnt = end - l;
+    bool first = l == 0, last = end == WAVE;
+    if (first) {
+      P.fk[w] = a;
+      P.fc[w] = cnt;
+      P.fe[w] = 0;
+      P.single[w] = last ? 1 : 0;
+    } else if (last) {
+      P.lk[w] = a;
+      P.lc[w] = cnt;
+      P.le[w] = 0;
+    } else if (a >= 0) {
+      base = atomicSub(&mcount[a], cnt) - cnt;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * CM_W) {
+    int32_t k;
+    int cnt, wl, pl;
+    unsigned long long e;
+    if (chain_at(P, threadIdx.x, k, cnt, e, wl, pl) && k >= 0) {
+      int b = atomicSub(&mcount[k], cnt) - cnt;
+      // consecutive slots to the chain's pieces in block order
+      int v = threadIdx.x >> 1, q = threadIdx.x & 1;
+      while (true) {
+        if (q == 0) {
+          P.fb[v] = b;
+          b += P.fc[v];
+        } else {
+          P.lb[v] = b;
+          b += P.lc[v];
+        }
+        if (v == wl && q == pl) break;
+        v++;
+        q = 0;
+      }
+    }
+  }
+  __syncthreads();
   int h = run_head_of(heads);
-  int oldh = __shfl(old, h);
+  int bh = __shfl(base, h);
   int endh = __shfl(end, h);
   if (valid) {
-    int s = endh - h;
-    members[mptr[a] + oldh - s + (lane_id() - h)] = (int32_t)x;
+    if (h == 0) bh = P.fb[w];
+    else if (endh == WAVE) bh = P.lb[w];
+    members[mptr[a] + bh + (l - h)] = (int32_t)x;
   }
+}
+
+// One coarse row a by one thread: the sorted distinct (column, weight) list
+// is held in registers (every access uses a compile-time index), built by
+// insertion with equal columns merged.  Requires E_a <= CAP.
+template <int CAP>
+__device__ __forceinline__ void contract_row_regs(const LevelIn& g, const int32_t* __restrict__ c,
+                                                  const int32_t* __restrict__ mptr,
+                                                  const int32_t* __restrict__ members,
+                                                  const int64_t* __restrict__ gptr,
+                                                  uint64_t* __restrict__ temp,
+                                                  int64_t* __restrict__ cnt,
+                                                  int64_t* __restrict__ self_out,
+                                                  int32_t* __restrict__ size_out, int32_t a) {
+  int64_t self = 0;
+  int32_t sz = 0;
+  int cntd = 0;
+  int32_t kb[CAP];
+  uint32_t kw[CAP];
+#pragma unroll
+  for (int q = 0; q < CAP; q++) {
+    kb[q] = INT32_MAX;
+    kw[q] = 0;
+  }
+  auto insert = [&](int32_t b, uint32_t wv) {
+    if (b == a) {
+      self += wv;
+      return;
+    }
+    bool found = false;
+    int ins = 0;
+#pragma unroll
+    for (int q = 0; q < CAP; q++) {
+      bool hit = kb[q] == b;
+      kw[q] += hit ? wv : 0u;   // sums stay below 2^31
+      found |= hit;
+      ins += kb[q] < b ? 1 : 0;
+    }
+    if (!found) {
+#pragma unroll
+      for (int q = CAP - 1; q >= 0; q--) {
+        if (q > ins) {
+          kb[q] = kb[q - 1];
+          kw[q] = kw[q - 1];
+        } else if (q == ins) {
+          kb[q] = b;
+          kw[q] = wv;
+        }
+      }
+      cntd++;
+    }
+  };
+  // a row's entries are loaded EB at a time and the next member's row
+  // bounds are fetched ahead, so that load latencies overlap
+  constexpr int EB = 4;
+  int32_t m0 = mptr[a], m1 = mptr[a + 1];
+  int32_t x = m0 < m1 ? members[m0] : -1;
+  int64_t rs = x >= 0 ? g.rp[x] : 0, re = x >= 0 ? g.rp[x + 1] : 0;
+  for (int32_t p = m0; p < m1; p++) {
+    int32_t xn = p + 1 < m1 ? members[p + 1] : -1;
+    sz += g.size ? g.size[x] : 1;
+    if (g.self) self += g.self[x];
+    int64_t rsn = xn >= 0 ? g.rp[xn] : 0, ren = xn >= 0 ? g.rp[xn + 1] : 0;
+#pragma unroll 1
+    for (int64_t j = rs; j < re; j += EB) {
+      int32_t bq[EB];
+      uint32_t wq[EB];
+#pragma unroll
+      for (int q = 0; q < EB; q++) {
+        bool ok = j + q < re;
+        bq[q] = ok ? g.col[j + q] : -1;
+        wq[q] = ok ? (uint32_t)g.w[j + q] : 0u;
+      }
+#pragma unroll
+      for (int q = 0; q < EB; q++) bq[q] = bq[q] >= 0 ? c[bq[q]] : -1;
+#pragma unroll
+      for (int q = 0; q < EB; q++)
+        if (bq[q] >= 0) insert(bq[q], wq[q]);
+    }
+    x = xn;
+    rs = rsn;
+    re = ren;
+  }
+  int64_t o = gptr[a];
+#pragma unroll
+  for (int q = 0; q < CAP; q++)
+    if (q < cntd) temp[o + q] = ((uint64_t)(uint32_t)kb[q] << 32) | kw[q];
+  cnt[a] = cntd;
+  self_out[a] = self;
+  size_out[a] = sz;
 }
 
 // ---- rows with at most SMALL_CAP gathered entries: one thread each --------
@@ -88,16 +293,16 @@ __global__ void __launch_bounds__(SMALL_BS)
                      const int32_t* __restrict__ members, const int64_t* __restrict__ gptr,
                      uint64_t* __restrict__ temp, int64_t* __restrict__ cnt,
                      int64_t* __restrict__ self_out, int32_t* __restrict__ size_out, int64_t n_c,
-                     int32_t* __restrict__ midlist, int32_t* __restrict__ blocklist,
-                     int32_t* __restrict__ hugelist, unsigned long long* info) {
-  __shared__ uint64_t lst[SMALL_CAP * SMALL_BS];
-  __shared__ int stmp[SMALL_BS / WAVE];
-  __shared__ unsigned long long sbase;
+                     int32_t* __restrict__ r32list, int32_t* __restrict__ midlist,
+                     int32_t* __restrict__ blocklist, int32_t* __restrict__ hugelist,
+                     unsigned long long* info, TileScan ts) {
+  __shared__ unsigned long long stmp[SMALL_BS / WAVE];
+  __shared__ int64_t sbase[4];
   __shared__ int32_t smx[SMALL_BS / WAVE];
   int tid = threadIdx.x;
   int64_t base = (int64_t)blockIdx.x * SMALL_BS * SMALL_RPT;
-  uint32_t midm = 0, blkm = 0, hugem = 0;
-  int nmid = 0, nblk = 0, nhuge = 0;
+  uint32_t r32m = 0, midm = 0, blkm = 0, hugem = 0;
+  int nr32 = 0, nmid = 0, nblk = 0, nhuge = 0;
   int32_t mx = 0;
   for (int r = 0; r < SMALL_RPT; r++) {
     int64_t a = base + r * SMALL_BS + tid;
@@ -106,7 +311,10 @@ __global__ void __launch_bounds__(SMALL_BS)
     int32_t msz = mptr[a + 1] - mptr[a];
     mx = msz > mx ? msz : mx;
     if (E > SMALL_CAP) {
-      if (E <= WAVE_CAP) {
+      if (E <= REG32_CAP) {
+        r32m |= 1u << r;
+        nr32++;
+      } else if (E <= WAVE_CAP) {
         midm |= 1u << r;
         nmid++;
       } else if (E <= BLOCK_CAP) {
@@ -120,37 +328,7 @@ __global__ void __launch_bounds__(SMALL_BS)
       }
       continue;
     }
-    int64_t self = 0;
-    int32_t sz = 0;
-    int cntd = 0;
-    int32_t a32 = (int32_t)a;
-    for (int32_t p = mptr[a]; p < mptr[a + 1]; p++) {
-      int32_t x = members[p];
-      sz += g.size ? g.size[x] : 1;
-      if (g.self) self += g.self[x];
-      for (int64_t j = g.rp[x]; j < g.rp[x + 1]; j++) {
-        int32_t b = c[g.col[j]];
-        uint32_t wv = (uint32_t)g.w[j];
-        if (b == a32) {
-          self += wv;
-          continue;
-        }
-        int i = cntd - 1;
-        while (i >= 0 && (int32_t)(lst[i * SMALL_BS + tid] >> 32) > b) i--;
-        if (i >= 0 && (int32_t)(lst[i * SMALL_BS + tid] >> 32) == b) {
-          lst[i * SMALL_BS + tid] += wv;  // sums stay below 2^31: no carry into the column
-        } else {
-          for (int q = cntd; q > i + 1; q--) lst[q * SMALL_BS + tid] = lst[(q - 1) * SMALL_BS + tid];
-          lst[(i + 1) * SMALL_BS + tid] = ((uint64_t)(uint32_t)b << 32) | wv;
-          cntd++;
-        }
-      }
-    }
-    int64_t o = gptr[a];
-    for (int q = 0; q < cntd; q++) temp[o + q] = lst[q * SMALL_BS + tid];
-    cnt[a] = cntd;
-    self_out[a] = self;
-    size_out[a] = sz;
+    contract_row_regs<SMALL_CAP>(g, c, mptr, members, gptr, temp, cnt, self_out, size_out, (int32_t)a);
   }
   mx = wave_max(mx);
   if (lane_id() == 0) smx[tid / WAVE] = mx;
@@ -158,17 +336,52 @@ __global__ void __launch_bounds__(SMALL_BS)
   if (tid == 0) {
     int32_t m2 = 0;
     for (int w = 0; w < SMALL_BS / WAVE; w++) m2 = smx[w] > m2 ? smx[w] : m2;
-    if (m2) atomicMax(&info[I_MAXCL], (unsigned long long)m2);
+    // most blocks see the maximum already published and skip the atomic
+    if ((unsigned long long)m2 >
+        __hip_atomic_load(&info[I_MAXCL], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(&info[I_MAXCL], (unsigned long long)m2);
   }
-  int64_t p1 = block_reserve<SMALL_BS>(&info[I_MID], nmid, &sbase, stmp);
-  int64_t p2 = block_reserve<SMALL_BS>(&info[I_BLOCK], nblk, &sbase, stmp);
-  int64_t p3 = block_reserve<SMALL_BS>(&info[I_HUGE], nhuge, &sbase, stmp);
+  // the four class lists: per-thread counts (at most SMALL_RPT each) packed
+  // in 16-bit fields, one block scan, then one look-back chain per class
+  // run by lanes 0-3
+  unsigned long long mine = (unsigned long long)nr32 | ((unsigned long long)nmid << 16) |
+                            ((unsigned long long)nblk << 32) | ((unsigned long long)nhuge << 48);
+  unsigned long long tot;
+  unsigned long long incl = block_incl_scan<unsigned long long, SMALL_BS, false>(mine, stmp, &tot);
+  unsigned long long excl = incl - mine;
+  if (tid < 4) {
+    int slot = tid == 0 ? I_R32 : tid == 1 ? I_MID : tid == 2 ? I_BLOCK : I_HUGE;
+    uint64_t cnt_c = (tot >> (16 * tid)) & 0xffffull;
+    TileScan t = ts;
+    t.state += (int64_t)tid * gridDim.x;
+    uint64_t ex = lb_exclusive(t, blockIdx.x, cnt_c);
+    sbase[tid] = (int64_t)ex;
+    if (blockIdx.x == gridDim.x - 1) info[slot] = ex + cnt_c;
+  }
+  __syncthreads();
+  int64_t p0 = sbase[0] + (int64_t)(excl & 0xffff);
+  int64_t p1 = sbase[1] + (int64_t)((excl >> 16) & 0xffff);
+  int64_t p2 = sbase[2] + (int64_t)((excl >> 32) & 0xffff);
+  int64_t p3 = sbase[3] + (int64_t)((excl >> 48) & 0xffff);
   for (int r = 0; r < SMALL_RPT; r++) {
     int32_t a = (int32_t)(base + r * SMALL_BS + tid);
+    if (r32m >> r & 1u) r32list[p0++] = a;
     if (midm >> r & 1u) midlist[p1++] = a;
     if (blkm >> r & 1u) blocklist[p2++] = a;
     if (hugem >> r & 1u) hugelist[p3++] = a;
   }
+}
+
+// ---- listed rows with at most REG32_CAP gathered entries: one thread each --
+__global__ void __launch_bounds__(SMALL_BS)
+    k_contract_reg32(LevelIn g, const int32_t* __restrict__ c, const int32_t* __restrict__ mptr,
+                     const int32_t* __restrict__ members, const int64_t* __restrict__ gptr,
+                     const int32_t* __restrict__ rows, int64_t nrows, uint64_t* __restrict__ temp,
+                     int64_t* __restrict__ cnt, int64_t* __restrict__ self_out,
+                     int32_t* __restrict__ size_out) {
+  int64_t i = (int64_t)blockIdx.x * SMALL_BS + threadIdx.x;
+  if (i < nrows)
+    contract_row_regs<REG32_CAP>(g, c, mptr, members, gptr, temp, cnt, self_out, size_out, rows[i]);
 }
 
 // ---- rows with at most CAP gathered entries: one BS-thread block each ----
@@ -280,106 +493,208 @@ __global__ void k_huge_members_count(const int32_t* __restrict__ hugelist, int64
   }
 }
 
-__global__ void k_huge_members_fill(const int32_t* __restrict__ hugelist,
-                                    const int32_t* __restrict__ mptr,
-                                    const int32_t* __restrict__ members,
-                                    const int64_t* __restrict__ hoff, int32_t* __restrict__ hmrow,
-                                    int32_t* __restrict__ hmnode) {
-  int h = blockIdx.x;
-  int32_t a = hugelist[h];
-  int32_t s = mptr[a], e = mptr[a + 1];
-  int64_t o = hoff[h];
-  for (int32_t p = s + threadIdx.x; p < e; p += blockDim.x) {
-    hmrow[o + (p - s)] = h;
-    hmnode[o + (p - s)] = members[p];
+// huge member i (0 <= i < HM, members of huge rows concatenated in list
+// order) -> its huge row h (binary search in hoff[0..H]) and node
+__device__ __forceinline__ int32_t huge_row_of(const int64_t* __restrict__ hoff, int64_t H, int64_t i) {
+  int64_t lo = 0, hi = H - 1;
+  while (lo < hi) {
+    int64_t mid = (lo + hi + 1) >> 1;
+    if (hoff[mid] <= i) lo = mid;
+    else hi = mid - 1;
   }
+  return (int32_t)lo;
 }
 
-// per huge member: count cross entries; add self-loop and intra weight, and
-// sizes, to the super-node with integer atomics (order-independent), once
-// per run of lanes that share a super-node
-__global__ void k_huge_member_pass1(LevelIn g, const int32_t* __restrict__ c,
-                                    const int32_t* __restrict__ hugelist,
-                                    const int32_t* __restrict__ hmrow,
-                                    const int32_t* __restrict__ hmnode, int64_t HM,
-                                    int64_t* __restrict__ hcnt, int64_t* self_out,
-                                    int32_t* size_out) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool valid = i < HM;
-  int32_t h = valid ? hmrow[i] : -1;
-  int64_t self = 0, k = 0;
-  int32_t sz = 0;
-  if (valid) {
-    int32_t x = hmnode[i];
-    int32_t a = hugelist[h];
-    self = g.self ? g.self[x] : 0;
-    sz = g.size ? g.size[x] : 1;
-    for (int64_t j = g.rp[x]; j < g.rp[x + 1]; j++) {
-      if (c[g.col[j]] == a) self += g.w[j];
-      else k++;
+// per huge member: its row length; its self-loop and size go to the
+// super-node with integer atomics (order-independent).  A block covers
+// HMB_T consecutive members, so at most HMB_T rows: lanes of one run add in
+// registers, runs add in LDS, and each row a block touches costs one global
+// atomic per quantity.
+constexpr int HMB_BS = 256;
+constexpr int HMB_T = 1024;
+
+__global__ void __launch_bounds__(HMB_BS)
+    k_huge_members(LevelIn g, const int32_t* __restrict__ hugelist, const int32_t* __restrict__ mptr,
+                   const int32_t* __restrict__ members, const int64_t* __restrict__ hoff, int64_t H,
+                   int64_t HM, int64_t* __restrict__ hlen, int64_t* self_out, int32_t* size_out) {
+  __shared__ unsigned long long sself[HMB_T];
+  __shared__ int32_t ssize[HMB_T];
+  __shared__ int32_t sh0;
+  int tid = threadIdx.x;
+  int64_t i0 = (int64_t)blockIdx.x * HMB_T;
+  for (int k = tid; k < HMB_T; k += HMB_BS) {
+    sself[k] = 0;
+    ssize[k] = 0;
+  }
+  if (tid == 0) sh0 = huge_row_of(hoff, H, i0);
+  __syncthreads();
+  int32_t h0 = sh0;
+#pragma unroll
+  for (int r = 0; r < HMB_T / HMB_BS; r++) {
+    int64_t i = i0 + r * HMB_BS + tid;
+    bool valid = i < HM;
+    int32_t h = -1;
+    int64_t self = 0;
+    int32_t sz = 0;
+    if (valid) {
+      h = huge_row_of(hoff, H, i);
+      int32_t x = members[mptr[hugelist[h]] + (i - hoff[h])];
+      self = g.self ? g.self[x] : 0;
+      sz = g.size ? g.size[x] : 1;
+      hlen[i] = g.rp[x + 1] - g.rp[x];
     }
-    hcnt[i] = k;
+    bool head;
+    int end;
+    uint64_t heads;
+    wave_runs(h, head, end, heads);
+    int64_t si = wave_incl_sum(self);
+    int32_t zi = wave_incl_sum(sz);
+    int64_t se = __shfl(si, end - 1);
+    int32_t ze = __shfl(zi, end - 1);
+    if (head && h >= 0) {
+      atomicAdd(&sself[h - h0], (unsigned long long)(se - si + self));
+      atomicAdd(&ssize[h - h0], ze - zi + sz);
+    }
   }
-  bool head;
-  int end;
-  uint64_t heads;
-  wave_runs(h, head, end, heads);
-  int64_t si = wave_incl_sum(self);
-  int32_t zi = wave_incl_sum(sz);
-  int64_t se = __shfl(si, end - 1);
-  int32_t ze = __shfl(zi, end - 1);
-  if (head && h >= 0) {
-    int32_t a = hugelist[h];
-    atomicAdd((unsigned long long*)&self_out[a], (unsigned long long)(se - si + self));
-    atomicAdd(&size_out[a], ze - zi + sz);
+  __syncthreads();
+  for (int k = tid; k < HMB_T; k += HMB_BS) {
+    if (h0 + k >= H) break;
+    if (hoff[h0 + k] >= i0 + HMB_T) break;   // row starts after this block
+    int32_t a = hugelist[h0 + k];
+    if (sself[k]) atomicAdd((unsigned long long*)&self_out[a], sself[k]);
+    if (ssize[k]) atomicAdd(&size_out[a], ssize[k]);
   }
 }
 
-__global__ void k_huge_member_pass2(LevelIn g, const int32_t* __restrict__ c,
-                                    const int32_t* __restrict__ hugelist,
-                                    const int32_t* __restrict__ hmrow,
-                                    const int32_t* __restrict__ hmnode, int64_t HM,
-                                    const int64_t* __restrict__ hpos, KW* __restrict__ out) {
+// every fine entry of every huge member, in tiles of 4096 mapped to members
+// by a load-balanced search over the member row-length prefix hpre: intra
+// entries add to the self-loop, cross entries are gathered as
+// ((h << 32) | b, w) for the sort
+constexpr int HT = 4096;
+constexpr int HT_BS = 256;
+static_assert(HT <= BLOCK_CAP, "a tile of gathered entries must meet at most two huge rows");
+
+__global__ void __launch_bounds__(HT_BS)
+    k_huge_entries(LevelIn g, const int32_t* __restrict__ c, const int32_t* __restrict__ hugelist,
+                   const int32_t* __restrict__ mptr, const int32_t* __restrict__ members,
+                   const int64_t* __restrict__ hoff, int64_t H, const int64_t* __restrict__ hpre,
+                   int64_t HM, int64_t* self_out, KW* __restrict__ out, unsigned long long* gcnt,
+                   TileScan ts) {
+  __shared__ int32_t srow[Lbs<HT, HT_BS>::SIZE];
+  __shared__ int64_t sh[2];
+  __shared__ int32_t stmp[HT_BS / WAVE];
+  __shared__ unsigned long long sbase;
+  // a huge row has more than HT gathered entries, so a tile meets at most
+  // two rows: h0 and h0 + 1
+  __shared__ unsigned long long sself[2];
+  int64_t q0 = (int64_t)blockIdx.x * HT;
+  int64_t total = hpre[HM];
+  lbs_tile<HT, HT_BS>(hpre, HM, q0, srow, sh, stmp);
+  int tid = threadIdx.x;
+  if (tid < 2) sself[tid] = 0;
+  int32_t h0 = huge_row_of(hoff, H, srow[0]);
+  __syncthreads();
+  uint32_t cross = 0;
+  int ncross = 0;
+  uint64_t keyv[HT / HT_BS];
+  uint32_t wv[HT / HT_BS];
+#pragma unroll
+  for (int r = 0; r < HT / HT_BS; r++) {
+    int k = tid + r * HT_BS;
+    int64_t q = q0 + k;
+    int32_t h = -1;
+    int64_t self = 0;
+    keyv[r] = 0;
+    wv[r] = 0;
+    if (q < total) {
+      int64_t i = srow[Lbs<HT, HT_BS>::at(k)];
+      h = huge_row_of(hoff, H, i);
+      int32_t a = hugelist[h];
+      int32_t x = members[mptr[a] + (i - hoff[h])];
+      int64_t j = g.rp[x] + (q - hpre[i]);
+      int32_t b = c[g.col[j]];
+      uint32_t w = (uint32_t)g.w[j];
+      if (b == a) {
+        self = w;
+      } else {
+        cross |= 1u << r;
+        ncross++;
+        keyv[r] = ((uint64_t)(uint32_t)h << 32) | (uint32_t)b;
+        wv[r] = w;
+      }
+    }
+    bool head;
+    int end;
+    uint64_t heads;
+    wave_runs(h, head, end, heads);
+    int64_t si = wave_incl_sum(self);
+    int64_t se = __shfl(si, end - 1);
+    if (head && h >= 0 && se - si + self)
+      atomicAdd(&sself[h - h0], (unsigned long long)(se - si + self));
+  }
+  __syncthreads();
+  if (tid < 2 && sself[tid]) atomicAdd((unsigned long long*)&self_out[hugelist[h0 + tid]], sself[tid]);
+  int64_t pos = block_reserve_lb<HT_BS>(ts, blockIdx.x, blockIdx.x == gridDim.x - 1, ncross, nullptr,
+                                       gcnt, &sbase, stmp);
+#pragma unroll
+  for (int r = 0; r < HT / HT_BS; r++)
+    if (cross >> r & 1u) out[pos++] = KW{keyv[r], (uint64_t)wv[r]};
+}
+
+__global__ void k_head_flags(const KW* __restrict__ s, int64_t G, int32_t* __restrict__ flag,
+                             uint64_t* __restrict__ wcol) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= HM) return;
-  int32_t x = hmnode[i];
-  int32_t h = hmrow[i];
-  int32_t a = hugelist[h];
-  int64_t o = hpos[i];
-  for (int64_t j = g.rp[x]; j < g.rp[x + 1]; j++) {
-    int32_t b = c[g.col[j]];
-    if (b != a) out[o++] = KW{((uint64_t)(uint32_t)h << 32) | (uint32_t)b, (uint64_t)(uint32_t)g.w[j]};
+  if (i < G) {
+    flag[i] = (i == 0 || s[i].key != s[i - 1].key) ? 1 : 0;
+    wcol[i] = s[i].w;
   }
 }
 
-__global__ void k_head_flags(const KW* __restrict__ s, int64_t G, int32_t* __restrict__ flag) {
+__global__ void k_head_index(const KW* __restrict__ s, int64_t G, const int32_t* __restrict__ pos,
+                             int32_t* __restrict__ hstart) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < G) flag[i] = (i == 0 || s[i].key != s[i - 1].key) ? 1 : 0;
+  if (i < G && (i == 0 || s[i].key != s[i - 1].key)) hstart[pos[i]] = (int32_t)i;
 }
 
+// one (row, column) run per head: its weight sum from the scanned weights;
+// its slot is the head's rank among the heads of its row
 __global__ void k_huge_reduce(const KW* __restrict__ s, int64_t G, const int32_t* __restrict__ pos,
-                              const int32_t* __restrict__ hugelist, const int64_t* __restrict__ hoff,
-                              const int64_t* __restrict__ hpos, const int64_t* __restrict__ gptr,
-                              uint64_t* __restrict__ temp) {
+                              const int32_t* __restrict__ hstart, const uint64_t* __restrict__ wx,
+                              const int32_t* __restrict__ hugelist, const int32_t* __restrict__ rowfirst,
+                              const int64_t* __restrict__ gptr, uint64_t* __restrict__ temp) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= G) return;
   if (!(i == 0 || s[i].key != s[i - 1].key)) return;
+  int32_t r = pos[i];
+  int64_t e = (r + 1 < pos[G]) ? hstart[r + 1] : G;
   uint64_t key = s[i].key;
   int32_t h = (int32_t)(key >> 32);
   uint32_t b = (uint32_t)key;
-  uint64_t sum = 0;
-  for (int64_t q = i; q < G && s[q].key == key; q++) sum += s[q].w;
-  int64_t seg0 = hpos[hoff[h]];
+  uint64_t sum = wx[e] - wx[i];
   int32_t a = hugelist[h];
-  int64_t r = pos[i] - pos[seg0];
-  temp[gptr[a] + r] = ((uint64_t)b << 32) | sum;
+  temp[gptr[a] + (r - rowfirst[h])] = ((uint64_t)b << 32) | sum;
+}
+
+// rowfirst[h] = rank of huge row h's first head, hcount[h] = its heads
+__global__ void k_huge_rowfirst(const KW* __restrict__ s, int64_t G, const int32_t* __restrict__ pos,
+                                int32_t* __restrict__ rowfirst, int32_t* __restrict__ rowlast) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G) return;
+  int32_t h = (int32_t)(s[i].key >> 32);
+  if (i == 0 || (int32_t)(s[i - 1].key >> 32) != h) rowfirst[h] = pos[i];
+  if (i == G - 1 || (int32_t)(s[i + 1].key >> 32) != h) rowlast[h] = pos[i + 1] - 1;
 }
 
 __global__ void k_huge_counts(const int32_t* __restrict__ hugelist, int64_t H,
-                              const int64_t* __restrict__ hoff, const int64_t* __restrict__ hpos,
-                              const int32_t* __restrict__ pos, int64_t* __restrict__ cnt) {
+                              const int32_t* __restrict__ rowfirst, const int32_t* __restrict__ rowlast,
+                              int64_t* __restrict__ cnt) {
   int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (h < H) cnt[hugelist[h]] = pos[hpos[hoff[h + 1]]] - pos[hpos[hoff[h]]];
+  if (h < H) cnt[hugelist[h]] = rowlast[h] < 0 ? 0 : (int64_t)(rowlast[h] - rowfirst[h] + 1);
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
 }
 
 // ---- packing: tiles of output positions mapped to coarse rows -----------
@@ -389,7 +704,7 @@ constexpr int PACK_BS = 256;
 __global__ void __launch_bounds__(PACK_BS)
     k_pack(const int64_t* __restrict__ rpc, int64_t n_c, const int64_t* __restrict__ gptr,
            const uint64_t* __restrict__ temp, int32_t* __restrict__ col_c, int32_t* __restrict__ w_c) {
-  __shared__ int32_t srow[PACK_T];
+  __shared__ int32_t srow[Lbs<PACK_T, PACK_BS>::SIZE];
   __shared__ int64_t sh[2];
   __shared__ int32_t stmp[PACK_BS / WAVE];
   int64_t p0 = (int64_t)blockIdx.x * PACK_T;
@@ -399,7 +714,7 @@ __global__ void __launch_bounds__(PACK_BS)
     int k = threadIdx.x + i * PACK_BS;
     int64_t p = p0 + k;
     if (p >= total) break;
-    int32_t a = srow[k];
+    int32_t a = srow[Lbs<PACK_T, PACK_BS>::at(k)];
     uint64_t v = temp[gptr[a] + (p - rpc[a])];
     col_c[p] = (int32_t)(v >> 32);
     w_c[p] = (int32_t)(uint32_t)v;
@@ -418,31 +733,38 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
     TimedScope ts(ctx, "contract_members", (double)n);
     SPC_HIP(ctx, hipMemsetAsync(W.mcount, 0, sizeof(int32_t) * (n_c + 1), st));
     SPC_HIP(ctx, hipMemsetAsync(W.gptr, 0, sizeof(int64_t) * (n_c + 1), st));
-    hipLaunchKernelGGL(k_cluster_count, dim3(grid_for(n, 256)), dim3(256), 0, st, g, c, W.mcount,
+    hipLaunchKernelGGL(k_cluster_count, dim3(grid_for(n, CM_BS)), dim3(CM_BS), 0, st, g, c, W.mcount,
                        (unsigned long long*)W.gptr);
     SPC_LAUNCH_CHECK(ctx, "cluster_count");
     rc = exclusive_scan<int32_t>(ctx, W.mcount, W.mptr, n_c, (int32_t*)W.scan_partial);
     if (rc) return rc;
     rc = exclusive_scan<int64_t>(ctx, W.gptr, W.gptr, n_c, (int64_t*)W.scan_partial);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_member_scatter, dim3(grid_for(n, 256)), dim3(256), 0, st, c, W.mptr,
+    hipLaunchKernelGGL(k_member_scatter, dim3(grid_for(n, CM_BS)), dim3(CM_BS), 0, st, c, W.mptr,
                        W.mcount, W.members, n);
   }
   SPC_HIP(ctx, hipMemsetAsync(&info[I_MID], 0, sizeof(unsigned long long) * 2, st));
   SPC_HIP(ctx, hipMemsetAsync(&info[I_MAXCL], 0, sizeof(unsigned long long), st));
   SPC_HIP(ctx, hipMemsetAsync(&info[I_BLOCK], 0, sizeof(unsigned long long), st));
+  SPC_HIP(ctx, hipMemsetAsync(&info[I_R32], 0, sizeof(unsigned long long), st));
   {
     TimedScope ts(ctx, "contract_small", (double)g.nnz);
     hipLaunchKernelGGL(k_contract_small, dim3(grid_for(n_c, SMALL_BS * SMALL_RPT)), dim3(SMALL_BS), 0,
                        st, g, c, W.mptr, W.members, W.gptr, W.temp, W.cnt, self_out, out->size, n_c,
-                       W.midlist, W.blocklist, W.hugelist, info);
+                       W.r32list, W.midlist, W.blocklist, W.hugelist, info, next_scan(ctx, W));
   }
   SPC_LAUNCH_CHECK(ctx, "contract_small");
   SPC_HIP(ctx, hipMemcpyAsync(hinfo, info, sizeof(unsigned long long) * I_NINFO,
                               hipMemcpyDeviceToHost, st));
   SPC_HIP(ctx, hipStreamSynchronize(st));
-  int64_t nmid = hinfo[I_MID], nblk = hinfo[I_BLOCK], H = hinfo[I_HUGE];
+  int64_t nr32 = hinfo[I_R32], nmid = hinfo[I_MID], nblk = hinfo[I_BLOCK], H = hinfo[I_HUGE];
   R.maxcl = hinfo[I_MAXCL];
+  if (nr32 > 0) {
+    TimedScope ts(ctx, "contract_reg32", (double)nr32);
+    hipLaunchKernelGGL(k_contract_reg32, dim3(grid_for(nr32, SMALL_BS)), dim3(SMALL_BS), 0, st, g, c,
+                       W.mptr, W.members, W.gptr, W.r32list, nr32, W.temp, W.cnt, self_out, out->size);
+    SPC_LAUNCH_CHECK(ctx, "contract reg32");
+  }
   if (nmid > 0) {
     TimedScope ts(ctx, "contract_wave_rows", (double)nmid);
     hipLaunchKernelGGL((k_contract_row<WAVE, WAVE_CAP>), dim3((unsigned)nmid), dim3(WAVE), 0, st, g, c,
@@ -464,34 +786,53 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
     int64_t HM = 0;
     SPC_HIP(ctx, hipMemcpyAsync(&HM, W.hmoff + H, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     SPC_HIP(ctx, hipStreamSynchronize(st));
-    hipLaunchKernelGGL(k_huge_members_fill, dim3((unsigned)H), dim3(256), 0, st, W.hugelist, W.mptr,
-                       W.members, W.hmoff, W.hmrow, W.hmnode);
-    int64_t* hpos = W.hpos;
-    hipLaunchKernelGGL(k_huge_member_pass1, dim3(grid_for(HM, 256)), dim3(256), 0, st, g, c,
-                       W.hugelist, W.hmrow, W.hmnode, HM, hpos, self_out, out->size);
-    rc = exclusive_scan<int64_t>(ctx, hpos, hpos, HM, (int64_t*)W.scan_partial);
+    int64_t* hpre = W.hpos;   // member row lengths, then their prefix
+    hipLaunchKernelGGL(k_huge_members, dim3(grid_for(HM, HMB_T)), dim3(HMB_BS), 0, st, g, W.hugelist,
+                       W.mptr, W.members, W.hmoff, H, HM, hpre, self_out, out->size);
+    rc = exclusive_scan<int64_t>(ctx, hpre, hpre, HM, (int64_t*)W.scan_partial);
     if (rc) return rc;
-    int64_t G = 0;
-    SPC_HIP(ctx, hipMemcpyAsync(&G, hpos + HM, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    int64_t Etot = 0;
+    SPC_HIP(ctx, hipMemcpyAsync(&Etot, hpre + HM, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SPC_HIP(ctx, hipMemsetAsync(&info[I_LIVE1], 0, sizeof(unsigned long long), st));
     SPC_HIP(ctx, hipStreamSynchronize(st));
     KW* A = (KW*)W.gkeyA;
     KW* B = (KW*)W.gkeyB;
-    hipLaunchKernelGGL(k_huge_member_pass2, dim3(grid_for(HM, 256)), dim3(256), 0, st, g, c,
-                       W.hugelist, W.hmrow, W.hmnode, HM, hpos, A);
-    SPC_LAUNCH_CHECK(ctx, "huge gather");
+    if (Etot > 0) {
+      hipLaunchKernelGGL(k_huge_entries, dim3(grid_for(Etot, HT)), dim3(HT_BS), 0, st, g, c, W.hugelist,
+                         W.mptr, W.members, W.hmoff, H, hpre, HM, self_out, A, &info[I_LIVE1],
+                         next_scan(ctx, W));
+      SPC_LAUNCH_CHECK(ctx, "huge gather");
+    }
+    int64_t G = 0;
+    SPC_HIP(ctx, hipMemcpyAsync(&G, &info[I_LIVE1], sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SPC_HIP(ctx, hipStreamSynchronize(st));
     KW* sorted = A;
     if (G > 0) {
       rc = merge_sort<KW, LessKW>(ctx, A, B, G, LessKW(), &sorted);
       if (rc) return rc;
     }
-    int32_t* pos = (int32_t*)(sorted == A ? B : A);
-    hipLaunchKernelGGL(k_head_flags, dim3(grid_for(G, 256)), dim3(256), 0, st, sorted, G, pos);
-    rc = exclusive_scan<int32_t>(ctx, pos, pos, G, (int32_t*)W.scan_partial);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_huge_reduce, dim3(grid_for(G, 256)), dim3(256), 0, st, sorted, G, pos,
-                       W.hugelist, W.hmoff, hpos, W.gptr, W.temp);
-    hipLaunchKernelGGL(k_huge_counts, dim3(grid_for(H, 256)), dim3(256), 0, st, W.hugelist, H, W.hmoff,
-                       hpos, pos, W.cnt);
+    // scratch in the other buffer: scanned weights, head ranks, head starts
+    char* scratch = (char*)(sorted == A ? B : A);
+    uint64_t* wx = (uint64_t*)scratch;
+    int32_t* pos = (int32_t*)(wx + G + 1);
+    int32_t* hstart = pos + G + 1;
+    int32_t* rowfirst = W.hmrow;
+    int32_t* rowlast = W.hmnode;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(H, 256)), dim3(256), 0, st, rowlast, H, -1);
+    if (G > 0) {
+      hipLaunchKernelGGL(k_head_flags, dim3(grid_for(G, 256)), dim3(256), 0, st, sorted, G, pos, wx);
+      rc = exclusive_scan<int32_t>(ctx, pos, pos, G, (int32_t*)W.scan_partial);
+      if (rc) return rc;
+      rc = exclusive_scan<uint64_t>(ctx, wx, wx, G, (uint64_t*)W.scan_partial);
+      if (rc) return rc;
+      hipLaunchKernelGGL(k_head_index, dim3(grid_for(G, 256)), dim3(256), 0, st, sorted, G, pos, hstart);
+      hipLaunchKernelGGL(k_huge_rowfirst, dim3(grid_for(G, 256)), dim3(256), 0, st, sorted, G, pos,
+                         rowfirst, rowlast);
+      hipLaunchKernelGGL(k_huge_reduce, dim3(grid_for(G, 256)), dim3(256), 0, st, sorted, G, pos,
+                         hstart, wx, W.hugelist, rowfirst, W.gptr, W.temp);
+    }
+    hipLaunchKernelGGL(k_huge_counts, dim3(grid_for(H, 256)), dim3(256), 0, st, W.hugelist, H, rowfirst,
+                       rowlast, W.cnt);
     SPC_LAUNCH_CHECK(ctx, "huge reduce");
   }
   {

@@ -66,7 +66,9 @@ enum Info : int {
   I_DMAXE = 12,   // largest D = d_u d_v over edges
   I_VIOL = 13,    // a guarded-key decision was not exact
   I_BLOCK = 14,   // contraction rows for the block-per-row class
-  I_NINFO = 16
+  I_R32 = 15,     // contraction rows for the 32-entry register class
+  I_LBERR = 16,   // a look-back wait gave up (internal error)
+  I_NINFO = 24
 };
 
 // Block-wide reservation of `my` consecutive slots per thread behind a
@@ -84,13 +86,100 @@ __device__ __forceinline__ int64_t block_reserve(unsigned long long* counter, in
   return base;
 }
 
+// Stream compaction without a hot counter.  A single global counter that
+// every block bumps serialises all blocks of a launch on one address; a
+// decoupled look-back (Merrill and Garland, single-pass prefix scan with
+// decoupled look-back, 2016) lets tile b find the sum of the counts of
+// tiles 0..b-1 from its predecessors' published words instead.
+//
+// A state word is (epoch << 42) | (flag << 40) | value: flag 1 = the tile's
+// own count, 2 = the inclusive prefix through the tile.  Words of an older
+// epoch count as unpublished, so the array is zeroed once per level and
+// every launch takes a fresh epoch.  A tile waits only on lower tiles, which
+// the hardware dispatched before it and which publish before they wait, so
+// every wait ends; a bound on the polling turns a broken invariant into an
+// error flag instead of a hang.
+constexpr uint64_t LB_VMASK = (1ull << 40) - 1;
+constexpr uint32_t LB_MAX_EPOCH = (1u << 22) - 1;
+constexpr uint32_t LB_SPIN_LIMIT = 1u << 20;
+
+struct TileScan {
+  uint64_t* state;            // [tiles] words of this chain
+  uint32_t epoch;             // 1 .. LB_MAX_EPOCH, distinct per launch
+  unsigned long long* err;    // set to 1 when a wait gives up
+};
+
+__device__ __forceinline__ void lb_publish(uint64_t* p, uint32_t epoch, uint64_t flag, uint64_t v) {
+  __hip_atomic_store(p, ((uint64_t)epoch << 42) | (flag << 40) | (v & LB_VMASK), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum of the counts of tiles 0..tile-1 (one thread per chain).
+__device__ __forceinline__ uint64_t lb_exclusive(const TileScan& ts, int64_t tile, uint64_t count) {
+  if (tile == 0) {
+    lb_publish(&ts.state[0], ts.epoch, 2, count);
+    return 0;
+  }
+  lb_publish(&ts.state[tile], ts.epoch, 1, count);
+  uint64_t excl = 0;
+  int64_t p = tile - 1;
+  uint32_t spins = 0;
+  while (true) {
+    uint64_t s = __hip_atomic_load(&ts.state[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((uint32_t)(s >> 42) != ts.epoch) {
+      if (++spins > LB_SPIN_LIMIT) {
+        atomicOr(ts.err, 1ull);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    excl += s & LB_VMASK;
+    if (((s >> 40) & 3) == 2) break;
+    p--;
+  }
+  lb_publish(&ts.state[tile], ts.epoch, 2, excl + count);
+  return excl;
+}
+
+// Block-wide reservation of `my` consecutive slots per thread, positions in
+// tile order.  base_in (nullable) is added to every position: it is read
+// before the tile publishes, so it may be the same counter as total_out,
+// which the last tile sets to base_in + the sum of all counts.  All BS
+// threads must call it.  tmp: LDS int[BS/64]; sh_base: LDS scalar.
+template <int BS>
+__device__ __forceinline__ int64_t block_reserve_lb(const TileScan& ts, int64_t tile, bool last_tile,
+                                                    int my, const unsigned long long* base_in,
+                                                    unsigned long long* total_out,
+                                                    unsigned long long* sh_base, int* tmp) {
+  int total;
+  int incl = block_incl_scan<int, BS, false>(my, tmp, &total);
+  if (threadIdx.x == 0) {
+    uint64_t b0 = 0;
+    if (base_in) {
+      b0 = __hip_atomic_load(base_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();   // the read completes before this tile publishes
+    }
+    uint64_t ex = b0 + lb_exclusive(ts, tile, (uint64_t)total);
+    *sh_base = ex;
+    if (last_tile) *total_out = ex + (uint64_t)total;
+  }
+  __syncthreads();
+  int64_t base = (int64_t)*sh_base + (incl - my);
+  __syncthreads();
+  return base;
+}
+
 struct LevelWork {
   unsigned long long* info;  // [I_NINFO]
+  uint64_t* lbstate;         // look-back words, lb_words(n, nnz)
   uint64_t* deg;             // [n]
+  uint64_t* degpart;         // [n / 4096 + 2] per-block weight sums
   int32_t* lc;               // [n]  entries with col < row
   int64_t* uptr;             // [n+1] upper-edge prefix (edge ids)
   int32_t* longrows;         // [n]
-  uint64_t* P;               // [m]  order key per edge
+  uint64_t* P;               // [m]  order key per edge (sorted-rank order)
+  uint64_t* Pc;              // [nnz] order key per CSR entry (both directions)
   uint64_t* samples;         // [m/64 + 2]
   uint64_t* bestA;           // [n]
   uint64_t* bestB;           // [n]
@@ -114,6 +203,7 @@ struct LevelWork {
   int64_t* gptr;             // [n+1]
   uint64_t* temp;            // [nnz]
   int64_t* cnt;              // [n+1]
+  int32_t* r32list;          // [n]
   int32_t* midlist;          // [n]
   int32_t* blocklist;        // [n]
   int32_t* hugelist;         // [n]
@@ -125,7 +215,20 @@ struct LevelWork {
   uint64_t* gkeyB;           // [nnz]
 };
 
+// look-back words a level needs: the most tiles any compaction launch uses
+inline int64_t lb_words(int64_t n, int64_t nnz) { return nnz / 1024 + 4 * (n / 256) + 4096; }
+
 void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W);
+
+// A fresh look-back chain for one launch, words from `off` of the level's
+// array; the array is zeroed again when the epochs run out.
+inline TileScan next_scan(spc_ctx* ctx, const LevelWork& W, int64_t off = 0) {
+  if (ctx->lb_epoch >= LB_MAX_EPOCH) {
+    (void)hipMemsetAsync(W.lbstate, 0, sizeof(uint64_t) * (size_t)ctx->lb_words, ctx->stream);
+    ctx->lb_epoch = 0;
+  }
+  return TileScan{W.lbstate + off, ++ctx->lb_epoch, &W.info[I_LBERR]};
+}
 
 struct LevelResult {
   int64_t n_c = 0, nnz_c = 0, msf = 0, rounds = 0, candidates = 0, maxcl = 0;

@@ -25,11 +25,14 @@ namespace spc {
 void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W) {
   int64_t m = nnz / 2;
   W.info = A.take<unsigned long long>(I_NINFO);
+  W.lbstate = A.take<uint64_t>(lb_words(n, nnz));
   W.deg = A.take<uint64_t>(n);
+  W.degpart = A.take<uint64_t>(n / 4096 + 2);
   W.lc = A.take<int32_t>(n);
   W.uptr = A.take<int64_t>(n + 1);
   W.longrows = A.take<int32_t>(n);
   W.P = A.take<uint64_t>(m);
+  W.Pc = A.take<uint64_t>(nnz);
   W.samples = A.take<uint64_t>(m / 64 + 2);
   W.bestA = A.take<uint64_t>(n);
   W.bestB = A.take<uint64_t>(n);
@@ -54,6 +57,7 @@ void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W) {
   W.gptr = A.take<int64_t>(n + 1);
   W.temp = A.take<uint64_t>(nnz);
   W.cnt = A.take<int64_t>(n + 1);
+  W.r32list = A.take<int32_t>(n);
   W.midlist = A.take<int32_t>(n);
   W.blocklist = A.take<int32_t>(n);
   W.hugelist = A.take<int32_t>(n);
@@ -61,8 +65,8 @@ void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W) {
   W.hmrow = A.take<int32_t>(n);
   W.hmnode = A.take<int32_t>(n);
   W.hpos = A.take<int64_t>(n + 1);
-  W.gkeyA = A.take<uint64_t>(2 * nnz);
-  W.gkeyB = A.take<uint64_t>(2 * nnz);
+  W.gkeyA = A.take<uint64_t>(2 * nnz + 8);
+  W.gkeyB = A.take<uint64_t>(2 * nnz + 8);
 }
 
 constexpr int BS = 256;
@@ -79,7 +83,7 @@ __global__ void __launch_bounds__(BS)
     k_degree(LevelIn g, uint64_t* __restrict__ deg, int32_t* __restrict__ lc,
              int64_t* __restrict__ ucnt, uint64_t* __restrict__ bestA,
              uint64_t* __restrict__ bestB, int32_t* __restrict__ parent,
-             int32_t* __restrict__ longrows, unsigned long long* info) {
+             int32_t* __restrict__ longrows, uint64_t* __restrict__ part, unsigned long long* info) {
   __shared__ int stmp[BS / WAVE];
   __shared__ unsigned long long sbase;
   __shared__ uint64_t smx[BS / WAVE], ssm[BS / WAVE];
@@ -127,8 +131,8 @@ __global__ void __launch_bounds__(BS)
       a = smx[w] > a ? smx[w] : a;
       b += ssm[w];
     }
-    if (a) atomicMax(&info[I_DMAX], (unsigned long long)a);
-    if (b) atomicAdd(&info[I_TOTAL], (unsigned long long)b);
+    atomic_max_lazy(&info[I_DMAX], (unsigned long long)a);
+    part[blockIdx.x] = b;
   }
   int64_t pos = block_reserve<BS>(&info[I_LONG], nlong, &sbase, stmp);
   for (int i = 0; i < DEG_PER; i++)
@@ -150,8 +154,31 @@ __global__ void __launch_bounds__(BS)
     uint64_t t = g.self ? (uint64_t)g.self[u] : 0;
     for (int i = 0; i < BS / WAVE; i++) t += tmp[i];
     deg[u] = t;
-    atomicMax(&info[I_DMAX], (unsigned long long)t);
+    atomic_max_lazy(&info[I_DMAX], (unsigned long long)t);
     atomicAdd(&info[I_TOTAL], (unsigned long long)t);
+  }
+}
+
+// total weight from the per-block sums (saturating, so that an overflowing
+// input still reads as too large)
+__global__ void __launch_bounds__(1024)
+    k_sum_parts(const uint64_t* __restrict__ part, int64_t np, unsigned long long* total) {
+  __shared__ uint64_t tmp[1024 / WAVE];
+  uint64_t s = 0;
+  for (int64_t i = threadIdx.x; i < np; i += 1024) {
+    uint64_t v = part[i];
+    s = s + v < s ? ~0ull : s + v;
+  }
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    uint64_t v = __shfl_xor(s, o);
+    s = s + v < s ? ~0ull : s + v;
+  }
+  if (lane_id() == 0) tmp[threadIdx.x / WAVE] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t t = 0;
+    for (int w = 0; w < 1024 / WAVE; w++) t = t + tmp[w] < t ? ~0ull : t + tmp[w];
+    atomicAdd(total, (unsigned long long)t);
   }
 }
 
@@ -227,18 +254,61 @@ __device__ __forceinline__ uint64_t common_min_sum(const int32_t* __restrict__ c
   return M;
 }
 
+// position of u in row v (u < v, so it lies among v's lower entries)
+__device__ __forceinline__ int64_t mirror_pos(const LevelIn& g, const int32_t* __restrict__ lc,
+                                              int32_t v, int32_t u) {
+  int64_t lo = g.rp[v], hi = g.rp[v] + lc[v];
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (g.col[mid] < u) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Rows of at most RC entries are read into registers with all loads issued
+// at once (the common-support walk over global memory would chain one
+// dependent load per step); longer rows take the walk.
+constexpr int RC = 8;
+
+// Also returns jm, the CSR position of the mirror entry (v -> u).
 __device__ __forceinline__ void edge_score(const LevelIn& g, const uint64_t* __restrict__ deg,
-                                           int32_t u, int32_t v, int32_t wuv, uint64_t& N,
-                                           uint64_t& D) {
+                                           const int32_t* __restrict__ lc, int32_t u, int32_t v,
+                                           int32_t wuv, uint64_t& N, uint64_t& D, int64_t& jm) {
+  int64_t au = g.rp[u], bu = g.rp[u + 1], av = g.rp[v], bv = g.rp[v + 1];
   uint64_t du = deg[u], dv = deg[v];
+  uint64_t su = g.self ? (uint64_t)g.self[u] : 0, sv = g.self ? (uint64_t)g.self[v] : 0;
+  int64_t lu = bu - au, lv = bv - av;
   D = du * dv;
   uint64_t M = 0;
-  if (g.self) {
-    uint64_t su = (uint64_t)g.self[u], sv = (uint64_t)g.self[v];
-    if (su) M += umin64(su * dv, (uint64_t)wuv * du);   // x = u
-    if (sv) M += umin64((uint64_t)wuv * dv, sv * du);   // x = v
+  if (lu <= RC && lv <= RC) {
+    int32_t cu[RC], cv[RC];
+    uint32_t wu[RC], wv[RC];
+#pragma unroll
+    for (int k = 0; k < RC; k++) {
+      bool pu = k < lu, pv = k < lv;
+      cu[k] = pu ? g.col[au + k] : -1;   // distinct sentinels never match
+      wu[k] = pu ? (uint32_t)g.w[au + k] : 0u;
+      cv[k] = pv ? g.col[av + k] : -2;
+      wv[k] = pv ? (uint32_t)g.w[av + k] : 0u;
+    }
+    int below = 0;
+#pragma unroll
+    for (int k = 0; k < RC; k++) below += (k < lv && cv[k] < u) ? 1 : 0;
+    jm = av + below;
+#pragma unroll
+    for (int i = 0; i < RC; i++) {
+      uint32_t mw = 0;   // weight of cu[i] in row v (0: absent)
+#pragma unroll
+      for (int k = 0; k < RC; k++) mw = (cu[i] == cv[k]) ? wv[k] : mw;
+      if (mw) M += umin64((uint64_t)wu[i] * dv, (uint64_t)mw * du);
+    }
+  } else {
+    M = common_min_sum(g.col, g.w, au, bu, dv, av, bv, du);
+    jm = mirror_pos(g, lc, v, u);
   }
-  M += common_min_sum(g.col, g.w, g.rp[u], g.rp[u + 1], dv, g.rp[v], g.rp[v + 1], du);
+  if (su) M += umin64(su * dv, (uint64_t)wuv * du);   // x = u
+  if (sv) M += umin64((uint64_t)wuv * dv, sv * du);   // x = v
   N = 2 * D - 2 * M;
 }
 
@@ -273,10 +343,9 @@ template <int MODE>  // 0: 64-bit key (+ optional exact records), 1: exact recor
 __global__ void __launch_bounds__(BS)
     k_score(LevelIn g, const uint64_t* __restrict__ deg, const int32_t* __restrict__ lc,
             const int64_t* __restrict__ uptr, int64_t m, int c, int ebits,
-            uint64_t* __restrict__ P, uint64_t* __restrict__ bestA,
-            uint64_t* __restrict__ samples, KeyND* __restrict__ keys, int write_keys,
-            unsigned long long* info) {
-  __shared__ int32_t srow[TILE_S];
+            uint64_t* __restrict__ Pc, uint64_t* __restrict__ samples, KeyND* __restrict__ keys,
+            int write_keys, unsigned long long* info) {
+  __shared__ int32_t srow[Lbs<TILE_S, BS>::SIZE];
   __shared__ int64_t sh[2];
   __shared__ int32_t stmp[BS / WAVE];
   __shared__ uint64_t sred[BS / WAVE];
@@ -284,22 +353,39 @@ __global__ void __launch_bounds__(BS)
   lbs_tile<TILE_S, BS>(uptr, g.n, e0, srow, sh, stmp);
   int tid = threadIdx.x;
   uint64_t dmx = 0;
-  for (int i = 0; i < TILE_S / BS; i++) {
+  constexpr int EPT = TILE_S / BS;
+  // locate all of this thread's edges first so their loads overlap
+  int32_t eu[EPT], ev[EPT], ew[EPT];
+  int64_t ej[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; i++) {
     int k = tid + i * BS;
     int64_t e = e0 + k;
+    eu[i] = e < m ? srow[Lbs<TILE_S, BS>::at(k)] : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; i++) {
+    int64_t e = e0 + tid + i * BS;
+    ej[i] = e < m ? g.rp[eu[i]] + lc[eu[i]] + (e - uptr[eu[i]]) : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; i++) {
+    int64_t e = e0 + tid + i * BS;
+    ev[i] = e < m ? g.col[ej[i]] : 0;
+    ew[i] = e < m ? g.w[ej[i]] : 0;
+  }
+  for (int i = 0; i < EPT; i++) {
+    int64_t e = e0 + tid + i * BS;
     if (e >= m) break;
-    int32_t u = srow[k];
-    int64_t j = g.rp[u] + lc[u] + (e - uptr[u]);
-    int32_t v = g.col[j];
     uint64_t N, D;
-    edge_score(g, deg, u, v, g.w[j], N, D);
+    int64_t jm;
+    edge_score(g, deg, lc, eu[i], ev[i], ew[i], N, D, jm);
     dmx = D > dmx ? D : dmx;
     if (MODE == 0) {
       uint64_t K = fixed_key(N, D, c);
       uint64_t key = (K << ebits) | (uint64_t)e;
-      P[e] = key;
-      atomicMin((unsigned long long*)&bestA[u], (unsigned long long)key);
-      atomicMin((unsigned long long*)&bestA[v], (unsigned long long)key);
+      Pc[ej[i]] = key;   // entry (u -> v)
+      Pc[jm] = key;      // entry (v -> u)
       if ((e & 63) == 0) samples[e >> 6] = key;
     }
     if (MODE == 1 || write_keys) keys[e] = KeyND{N, D, (uint64_t)e};
@@ -310,7 +396,7 @@ __global__ void __launch_bounds__(BS)
   if (tid == 0) {
     uint64_t a = 0;
     for (int w = 0; w < BS / WAVE; w++) a = sred[w] > a ? sred[w] : a;
-    atomicMax(&info[I_DMAXE], (unsigned long long)a);
+    atomic_max_lazy(&info[I_DMAXE], (unsigned long long)a);
   }
 }
 
@@ -326,11 +412,11 @@ __global__ void k_rank_scatter(const KeyND* __restrict__ sorted, int64_t m, uint
 constexpr int TILE_F = 4096;
 constexpr int F_PER = TILE_F / BS;
 
-// every component's lightest incident edge (first forest round)
+// rank order: the rank of edge e into both of its CSR entries
 __global__ void __launch_bounds__(BS)
-    k_best_pass(LevelIn g, const int32_t* __restrict__ lc, const int64_t* __restrict__ uptr,
-                int64_t m, const uint64_t* __restrict__ P, uint64_t* best) {
-  __shared__ int32_t srow[TILE_F];
+    k_rank_mirror(LevelIn g, const int32_t* __restrict__ lc, const int64_t* __restrict__ uptr,
+                  int64_t m, const uint64_t* __restrict__ P, uint64_t* __restrict__ Pc) {
+  __shared__ int32_t srow[Lbs<TILE_F, BS>::SIZE];
   __shared__ int64_t sh[2];
   __shared__ int32_t stmp[BS / WAVE];
   int64_t e0 = (int64_t)blockIdx.x * TILE_F;
@@ -339,49 +425,146 @@ __global__ void __launch_bounds__(BS)
     int k = threadIdx.x + i * BS;
     int64_t e = e0 + k;
     if (e >= m) break;
-    int32_t u = srow[k];
-    int32_t v = g.col[g.rp[u] + lc[u] + (e - uptr[u])];
+    int32_t u = srow[Lbs<TILE_F, BS>::at(k)];
+    int64_t j = g.rp[u] + lc[u] + (e - uptr[u]);
+    int32_t v = g.col[j];
     uint64_t key = P[e];
-    atomicMin((unsigned long long*)&best[u], (unsigned long long)key);
-    atomicMin((unsigned long long*)&best[v], (unsigned long long)key);
+    Pc[j] = key;
+    Pc[mirror_pos(g, lc, v, u)] = key;
   }
 }
 
-// edges with lo < key <= hi (lo absent for the first band) form the live list
+// Row pass over CSR entries, tiles of 2048 entries (8 consecutive entries
+// per thread, keys staged in LDS):
+//  - with do_best, every node's lightest incident key (the first
+//    spanning-forest round), a segmented minimum per row; only row pieces
+//    that straddle a thread's 16 entries combine with atomicMin, so best[]
+//    must hold +inf on entry;
+//  - upper entries (u < v) with lo < key <= hi form the live list (lo is
+//    absent for the first band).
+constexpr int TILE_R = 2048;
+constexpr int R_PER = TILE_R / BS;
+
 __global__ void __launch_bounds__(BS)
-    k_filter(LevelIn g, const int32_t* __restrict__ lc, const int64_t* __restrict__ uptr, int64_t m,
-             const uint64_t* __restrict__ P, const unsigned long long* thr_lo,
-             const unsigned long long* thr_hi, int use_lo, uint64_t* __restrict__ lr,
-             uint64_t* __restrict__ lp, uint64_t* __restrict__ lo_out, unsigned long long* cnt) {
-  __shared__ int32_t srow[TILE_F];
+    k_rowpass(LevelIn g, const int32_t* __restrict__ lc, const uint64_t* __restrict__ Pc,
+              const unsigned long long* thr_lo, const unsigned long long* thr_hi, int use_lo,
+              int do_best, uint64_t* best, uint64_t* __restrict__ lr, uint64_t* __restrict__ lp,
+              uint64_t* __restrict__ lo_out, unsigned long long* cnt, TileScan ts) {
+  using L = Lbs<TILE_R, BS>;
+  static_assert(R_PER == 8, "one 8-byte flag word per thread");
+  __shared__ int32_t srow[L::SIZE];
+  __shared__ uint64_t sp[L::SIZE];   // keys, then per-row minima at each row's first position
+  __shared__ __align__(16) uint8_t sfl[TILE_R];   // bit 0: upper entry, bit 1: row head in tile
   __shared__ int64_t sh[2];
   __shared__ int32_t stmp[BS / WAVE];
   __shared__ unsigned long long sbase;
-  int64_t e0 = (int64_t)blockIdx.x * TILE_F;
-  lbs_tile<TILE_F, BS>(uptr, g.n, e0, srow, sh, stmp);
+  int64_t j0 = (int64_t)blockIdx.x * TILE_R;
+  int64_t nnz = g.nnz;
+  lbs_tile<TILE_R, BS>(g.rp, g.n, j0, srow, sh, stmp);
   int tid = threadIdx.x;
+  // coalesced: key, and from the column the upper / row-head flags
+#pragma unroll
+  for (int i = 0; i < R_PER; i++) {
+    int k = tid + i * BS;
+    int64_t j = j0 + k;
+    uint64_t p = KEY_INF;
+    uint32_t f = 0;
+    if (j < nnz) {
+      p = Pc[j];
+      int32_t u = srow[L::at(k)];
+      f = (g.col[j] > u ? 1u : 0u) | ((k == 0 || srow[L::at(k - 1)] != u) ? 2u : 0u);
+    }
+    sp[L::at(k)] = p;
+    sfl[k] = (uint8_t)f;
+  }
+  __syncthreads();
+  int kb = tid * R_PER;
+  int64_t cb = j0 + kb;                    // this thread's entries [cb, cb + R_PER)
+  uint64_t kp[R_PER];
+  int32_t ku[R_PER];
+  uint8_t fl[R_PER];
+  {
+    uint2 f2 = *(const uint2*)&sfl[kb];
+    uint32_t fw[2] = {f2.x, f2.y};
+#pragma unroll
+    for (int i = 0; i < R_PER; i++) fl[i] = (uint8_t)(fw[i >> 2] >> (8 * (i & 3)));
+  }
+#pragma unroll
+  for (int i = 0; i < R_PER; i++) {
+    kp[i] = sp[L::at(kb + i)];
+    ku[i] = srow[L::at(kb + i)];
+  }
+  __syncthreads();
+  if (do_best) {
+#pragma unroll
+    for (int i = 0; i < R_PER; i++) sp[L::at(kb + i)] = KEY_INF;
+    // a row continued from an earlier thread: its first position in the tile
+    int first_slot = 0;
+    if (cb < nnz && !(fl[0] & 2)) {
+      int64_t rs = g.rp[ku[0]];
+      first_slot = rs > j0 ? (int)(rs - j0) : 0;
+    }
+    __syncthreads();
+    // row pieces of this thread: minimum into the slot at the row's first
+    // position inside the tile
+    int32_t cur = -1;
+    uint64_t run = KEY_INF;
+    int slot = 0;
+#pragma unroll
+    for (int i = 0; i < R_PER; i++) {
+      if (cb + i >= nnz) break;
+      bool head = fl[i] & 2;
+      if (i == 0 || head) {
+        if (cur >= 0) atomicMin((unsigned long long*)&sp[L::at(slot)], (unsigned long long)run);
+        cur = ku[i];
+        run = kp[i];
+        slot = head ? kb + i : first_slot;
+      } else {
+        run = kp[i] < run ? kp[i] : run;
+      }
+    }
+    if (cur >= 0) atomicMin((unsigned long long*)&sp[L::at(slot)], (unsigned long long)run);
+    __syncthreads();
+    // the thread holding a row's first position in the tile publishes it:
+    // a plain store when the whole row lies inside the tile
+    int32_t last_row = srow[L::at(TILE_R - 1)];
+#pragma unroll
+    for (int i = 0; i < R_PER; i++) {
+      int64_t j = cb + i;
+      if (j >= nnz) break;
+      if (!(fl[i] & 2)) continue;
+      int32_t u = ku[i];
+      uint64_t v = sp[L::at(kb + i)];
+      bool starts = kb + i > 0 || g.rp[u] == j0;
+      bool ends = last_row != u && j0 + TILE_R <= nnz;
+      if (starts && ends) best[u] = v;
+      else atomicMin((unsigned long long*)&best[u], (unsigned long long)v);
+    }
+  }
   uint64_t tlo = use_lo ? *thr_lo : 0, thi = *thr_hi;
   uint32_t keep = 0;
   int nk = 0;
-  for (int i = 0; i < F_PER; i++) {
-    int64_t e = e0 + tid + i * BS;
-    if (e >= m) break;
-    uint64_t p = P[e];
-    if (p <= thi && (!use_lo || p > tlo)) {
+#pragma unroll
+  for (int i = 0; i < R_PER; i++) {
+    int64_t j = cb + i;
+    if (j >= nnz) break;
+    uint64_t p = kp[i];
+    if ((fl[i] & 1) && p <= thi && (!use_lo || p > tlo)) {
       keep |= 1u << i;
       nk++;
     }
   }
-  int64_t pos = block_reserve<BS>(cnt, nk, &sbase, stmp);
-  for (int i = 0; i < F_PER; i++) {
+  int64_t pos = block_reserve_lb<BS>(ts, blockIdx.x, blockIdx.x == gridDim.x - 1, nk, nullptr, cnt,
+                                    &sbase, stmp);
+#pragma unroll
+  for (int i = 0; i < R_PER; i++) {
     if (!(keep >> i & 1u)) continue;
-    int k = tid + i * BS;
-    int64_t e = e0 + k;
-    int32_t u = srow[k];
-    int32_t v = g.col[g.rp[u] + lc[u] + (e - uptr[u])];
+    int64_t j = cb + i;
+    int32_t u = ku[i];
+    int32_t v = g.col[j];
     uint64_t uv = (uint64_t)(uint32_t)u | ((uint64_t)(uint32_t)v << 32);
     lr[pos] = uv;
-    lp[pos] = P[e];
+    lp[pos] = kp[i];
     lo_out[pos] = uv;
     pos++;
   }
@@ -410,41 +593,48 @@ __global__ void __launch_bounds__(BS)
                const uint64_t* __restrict__ lo, const unsigned long long* cnt,
                const uint64_t* __restrict__ best, int32_t* parent, uint64_t* __restrict__ msfP,
                uint64_t* __restrict__ msfO, unsigned long long* msfcnt, int64_t msf_cap,
-               const KeyND* __restrict__ keys, int ebits, int* viol) {
+               const KeyND* __restrict__ keys, int ebits, int* viol, TileScan ts) {
   __shared__ int stmp[BS / WAVE];
   __shared__ unsigned long long sbase;
   int64_t n = (int64_t)*cnt;
   int tid = threadIdx.x;
-  for (int64_t base = (int64_t)blockIdx.x * BV_CHUNK; base < n; base += (int64_t)gridDim.x * BV_CHUNK) {
-    uint32_t chosen = 0;
-    int nc = 0;
-    for (int i = 0; i < BV_PER; i++) {
-      int64_t idx = base + tid + i * BS;
-      if (idx >= n) break;
-      uint64_t uv = lr[idx];
-      uint64_t key = lp[idx];
-      int32_t a = (int32_t)(uint32_t)uv, b = (int32_t)(uv >> 32);
-      uint64_t wa = best[a], wb = best[b];
-      if (keys) {
-        guard_check(keys, ebits, key, wa, viol);
-        guard_check(keys, ebits, key, wb, viol);
-      }
-      if (wa == key || wb == key) {
-        uf_union(parent, a, b);
-        chosen |= 1u << i;
-        nc++;
-      }
+  int64_t base = (int64_t)blockIdx.x * BV_CHUNK;
+  if (base >= n) return;
+  uint32_t chosen = 0;
+  int nc = 0;
+  for (int i = 0; i < BV_PER; i++) {
+    int64_t idx = base + tid + i * BS;
+    if (idx >= n) break;
+    uint64_t uv = lr[idx];
+    uint64_t key = lp[idx];
+    int32_t a = (int32_t)(uint32_t)uv, b = (int32_t)(uv >> 32);
+    uint64_t wa = best[a], wb = best[b];
+    if (keys) {
+      guard_check(keys, ebits, key, wa, viol);
+      guard_check(keys, ebits, key, wb, viol);
     }
-    int64_t pos = block_reserve<BS>(msfcnt, nc, &sbase, stmp);
-    for (int i = 0; i < BV_PER; i++) {
-      if (!(chosen >> i & 1u)) continue;
-      int64_t idx = base + tid + i * BS;
-      if (pos < msf_cap) {  // a forest has fewer than n edges
-        msfP[pos] = lp[idx];
-        msfO[pos] = lo[idx];
-      }
-      pos++;
+    bool ca = wa == key, cb = wb == key;
+    if (ca || cb) {
+      // a and b are roots at the start of this round and each root adopts
+      // exactly one edge, so each root's parent is written at most once;
+      // when both adopt this edge the smaller id stays the root
+      int32_t child = (ca && cb) ? (a > b ? a : b) : (ca ? a : b);
+      int32_t to = (ca && cb) ? (a > b ? b : a) : (ca ? b : a);
+      __hip_atomic_store(&parent[child], to, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      chosen |= 1u << i;
+      nc++;
     }
+  }
+  int64_t pos = block_reserve_lb<BS>(ts, blockIdx.x, base + BV_CHUNK >= n, nc, msfcnt, msfcnt,
+                                     &sbase, stmp);
+  for (int i = 0; i < BV_PER; i++) {
+    if (!(chosen >> i & 1u)) continue;
+    int64_t idx = base + tid + i * BS;
+    if (pos < msf_cap) {  // a forest has fewer than n edges
+      msfP[pos] = lp[idx];
+      msfO[pos] = lo[idx];
+    }
+    pos++;
   }
 }
 
@@ -457,42 +647,43 @@ __global__ void __launch_bounds__(BS)
                     const uint64_t* __restrict__ lo_in, const unsigned long long* cnt_in,
                     uint64_t* __restrict__ lr_out, uint64_t* __restrict__ lp_out,
                     uint64_t* __restrict__ lo_out, unsigned long long* cnt_out, uint64_t* cur,
-                    uint64_t* nxt, int32_t* parent) {
+                    uint64_t* nxt, int32_t* parent, TileScan ts) {
   __shared__ int stmp[BS / WAVE];
   __shared__ unsigned long long sbase;
   int64_t n = (int64_t)*cnt_in;
   int tid = threadIdx.x;
-  for (int64_t base = (int64_t)blockIdx.x * BV_CHUNK; base < n; base += (int64_t)gridDim.x * BV_CHUNK) {
-    uint32_t keep = 0;
-    int nk = 0;
-    uint64_t ruv[BV_PER];
-    for (int i = 0; i < BV_PER; i++) {
-      ruv[i] = 0;
-      int64_t idx = base + tid + i * BS;
-      if (idx >= n) break;
-      uint64_t uv = lr_in[idx];
-      uint64_t key = lp_in[idx];
-      int32_t a = uf_find(parent, (int32_t)(uint32_t)uv);
-      int32_t b = uf_find(parent, (int32_t)(uv >> 32));
-      if (a != b) {
-        atomicMin((unsigned long long*)&cur[a], (unsigned long long)key);
-        atomicMin((unsigned long long*)&cur[b], (unsigned long long)key);
-        nxt[a] = KEY_INF;
-        nxt[b] = KEY_INF;
-        ruv[i] = (uint64_t)(uint32_t)a | ((uint64_t)(uint32_t)b << 32);
-        keep |= 1u << i;
-        nk++;
-      }
+  int64_t base = (int64_t)blockIdx.x * BV_CHUNK;
+  if (base >= n) return;
+  uint32_t keep = 0;
+  int nk = 0;
+  uint64_t ruv[BV_PER];
+  for (int i = 0; i < BV_PER; i++) {
+    ruv[i] = 0;
+    int64_t idx = base + tid + i * BS;
+    if (idx >= n) break;
+    uint64_t uv = lr_in[idx];
+    uint64_t key = lp_in[idx];
+    int32_t a = uf_find(parent, (int32_t)(uint32_t)uv);
+    int32_t b = uf_find(parent, (int32_t)(uv >> 32));
+    if (a != b) {
+      atomicMin((unsigned long long*)&cur[a], (unsigned long long)key);
+      atomicMin((unsigned long long*)&cur[b], (unsigned long long)key);
+      nxt[a] = KEY_INF;
+      nxt[b] = KEY_INF;
+      ruv[i] = (uint64_t)(uint32_t)a | ((uint64_t)(uint32_t)b << 32);
+      keep |= 1u << i;
+      nk++;
     }
-    int64_t pos = block_reserve<BS>(cnt_out, nk, &sbase, stmp);
-    for (int i = 0; i < BV_PER; i++) {
-      if (!(keep >> i & 1u)) continue;
-      int64_t idx = base + tid + i * BS;
-      lr_out[pos] = ruv[i];
-      lp_out[pos] = lp_in[idx];
-      lo_out[pos] = lo_in[idx];
-      pos++;
-    }
+  }
+  int64_t pos = block_reserve_lb<BS>(ts, blockIdx.x, base + BV_CHUNK >= n, nk, nullptr, cnt_out,
+                                     &sbase, stmp);
+  for (int i = 0; i < BV_PER; i++) {
+    if (!(keep >> i & 1u)) continue;
+    int64_t idx = base + tid + i * BS;
+    lr_out[pos] = ruv[i];
+    lp_out[pos] = lp_in[idx];
+    lo_out[pos] = lo_in[idx];
+    pos++;
   }
 }
 
@@ -552,7 +743,8 @@ __global__ void k_relabel(const int32_t* __restrict__ root, const int32_t* __res
 
 // Theorem 2's epsilon: the score of the heaviest accepted edge, which is
 // the forest edge whose key equals the cutoff.
-__global__ void k_eps(LevelIn g, const uint64_t* __restrict__ deg, const uint64_t* __restrict__ msfP,
+__global__ void k_eps(LevelIn g, const uint64_t* __restrict__ deg, const int32_t* __restrict__ lc,
+                      const uint64_t* __restrict__ msfP,
                       const uint64_t* __restrict__ msfO, const unsigned long long* cnt,
                       const SelState* st, double* out) {
   int64_t n = (int64_t)*cnt;
@@ -569,7 +761,8 @@ __global__ void k_eps(LevelIn g, const uint64_t* __restrict__ deg, const uint64_
       else hi = mid;
     }
     uint64_t N, D;
-    edge_score(g, deg, u, v, g.w[lo], N, D);
+    int64_t jm;
+    edge_score(g, deg, lc, u, v, g.w[lo], N, D, jm);
     *out = (double)N / (double)D;
   }
 }
@@ -665,11 +858,14 @@ __global__ void k_fill_u64(uint64_t* __restrict__ a, int64_t n, uint64_t v) {
   if (i < n) a[i] = v;
 }
 
-// upper threshold of a band: the selected sample key widened to the end of
-// its K bucket, or "everything"
-__global__ void k_thr_from_sel(const SelState* st, unsigned long long* thr, int all, int ebits) {
+// upper threshold of a band: the selected sample key, or "everything".
+// Guarded keys order edges of one K bucket only approximately, so there the
+// band is widened to the end of the sample's K bucket.
+__global__ void k_thr_from_sel(const SelState* st, unsigned long long* thr, int all, int ebits,
+                               int widen) {
   if (all) *thr = KEY_INF;
-  else *thr = st->prefix | ((1ull << ebits) - 1);
+  else if (widen) *thr = st->prefix | ((1ull << ebits) - 1);
+  else *thr = st->prefix;
 }
 
 static int sync_info(spc_ctx* ctx, const LevelWork& W) {
@@ -692,16 +888,15 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, bool fused_fir
   if (rc) return rc;
   int64_t cnt = hinfo[I_LIVE0];
   live0 = cnt;
-  int maxgrid = ctx->num_cus * 4;
   uint64_t* cur = W.bestA;
   uint64_t* nxt = W.bestB;
   int in = 0;
   if (fused_first && cnt > 0) {
     rounds++;
     TimedScope ts(ctx, "forest_merge", (double)cnt);
-    hipLaunchKernelGGL(k_bv_merge, dim3(grid_for(cnt, BV_CHUNK, maxgrid)), dim3(BS), 0, ctx->stream,
-                       W.lr[0], W.lp[0], W.lo[0], &info[I_LIVE0], cur, W.parent, W.msfP, W.msfO,
-                       &info[I_MSF], n, guard_keys, ebits, viol);
+    hipLaunchKernelGGL(k_bv_merge, dim3(grid_for(cnt, BV_CHUNK)), dim3(BS), 0, ctx->stream, W.lr[0],
+                       W.lp[0], W.lo[0], &info[I_LIVE0], cur, W.parent, W.msfP, W.msfO, &info[I_MSF], n,
+                       guard_keys, ebits, viol, next_scan(ctx, W));
     cur = W.bestB;
     nxt = W.bestA;
   }
@@ -715,9 +910,9 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, bool fused_fir
     hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, ctx->stream, &info[co], 0ull);
     {
       TimedScope ts(ctx, "forest_candidates", (double)cnt);
-      hipLaunchKernelGGL(k_bv_candidates, dim3(grid_for(cnt, BV_CHUNK, maxgrid)), dim3(BS), 0,
-                         ctx->stream, W.lr[in], W.lp[in], W.lo[in], &info[ci], W.lr[out], W.lp[out],
-                         W.lo[out], &info[co], cur, nxt, W.parent);
+      hipLaunchKernelGGL(k_bv_candidates, dim3(grid_for(cnt, BV_CHUNK)), dim3(BS), 0, ctx->stream,
+                         W.lr[in], W.lp[in], W.lo[in], &info[ci], W.lr[out], W.lp[out], W.lo[out],
+                         &info[co], cur, nxt, W.parent, next_scan(ctx, W));
     }
     SPC_LAUNCH_CHECK(ctx, "forest candidates");
     SPC_HIP(ctx, hipMemcpyAsync(&hinfo[co], &info[co], sizeof(unsigned long long),
@@ -728,9 +923,9 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, bool fused_fir
     rounds++;
     {
       TimedScope ts(ctx, "forest_merge", (double)cnt);
-      hipLaunchKernelGGL(k_bv_merge, dim3(grid_for(cnt, BV_CHUNK, maxgrid)), dim3(BS), 0,
-                         ctx->stream, W.lr[out], W.lp[out], W.lo[out], &info[co], cur, W.parent,
-                         W.msfP, W.msfO, &info[I_MSF], n, guard_keys, ebits, viol);
+      hipLaunchKernelGGL(k_bv_merge, dim3(grid_for(cnt, BV_CHUNK)), dim3(BS), 0, ctx->stream,
+                         W.lr[out], W.lp[out], W.lo[out], &info[co], cur, W.parent, W.msfP, W.msfO,
+                         &info[I_MSF], n, guard_keys, ebits, viol, next_scan(ctx, W));
     }
     SPC_LAUNCH_CHECK(ctx, "forest merge");
     uint64_t* t = cur;
@@ -764,7 +959,7 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
     int write_keys = surely_exact ? 0 : 1;
     TimedScope ts(ctx, "score", (double)m);
     hipLaunchKernelGGL(k_score<0>, dim3(tiles_s), dim3(BS), 0, st, g, W.deg, W.lc, W.uptr, m, c,
-                       ebits, W.P, W.bestA, W.samples, W.keysA, write_keys, info);
+                       ebits, W.Pc, W.samples, W.keysA, write_keys, info);
     SPC_LAUNCH_CHECK(ctx, "score");
     if (!surely_exact) {
       int rc = sync_info(ctx, W);
@@ -779,8 +974,7 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
     {
       TimedScope ts(ctx, "score_rank", (double)m);
       hipLaunchKernelGGL(k_score<1>, dim3(tiles_s), dim3(BS), 0, st, g, W.deg, W.lc, W.uptr, m, c,
-                         ebits, (uint64_t*)nullptr, (uint64_t*)nullptr, (uint64_t*)nullptr, W.keysA,
-                         1, info);
+                         ebits, (uint64_t*)nullptr, (uint64_t*)nullptr, W.keysA, 1, info);
     }
     SPC_LAUNCH_CHECK(ctx, "score(rank)");
     KeyND* sorted = nullptr;
@@ -789,10 +983,10 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
       int rc = merge_sort<KeyND, LessND>(ctx, W.keysA, W.keysB, m, LessND(), &sorted);
       if (rc) return rc;
     }
-    TimedScope ts(ctx, "rank_scatter_best", (double)m);
+    TimedScope ts(ctx, "rank_scatter", (double)m);
     hipLaunchKernelGGL(k_rank_scatter, dim3(grid_for(m, 256)), dim3(256), 0, st, sorted, m, W.P);
-    hipLaunchKernelGGL(k_best_pass, dim3(tiles_f), dim3(BS), 0, st, g, W.lc, W.uptr, m, W.P, W.bestA);
-    SPC_LAUNCH_CHECK(ctx, "rank best");
+    hipLaunchKernelGGL(k_rank_mirror, dim3(tiles_f), dim3(BS), 0, st, g, W.lc, W.uptr, m, W.P, W.Pc);
+    SPC_LAUNCH_CHECK(ctx, "rank scatter");
     R.key_mode = 1;
     R.key_bits = bitlen64((uint64_t)(m - 1));
   }
@@ -814,29 +1008,31 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
       SPC_HIP(ctx, hipMemcpyAsync(thr_lo, thr_hi, sizeof(unsigned long long), hipMemcpyDeviceToDevice, st));
     }
     if (all) {
-      hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits);
+      hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits, 0);
     } else if (!rank) {
       int64_t ns = (m + 63) / 64;
       int64_t q = (int64_t)((double)target / 64.0 * 1.05) + 16;
       if (q >= ns) {
         all = true;
-        hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits);
+        hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits, 0);
       } else {
         TimedScope ts(ctx, "select_threshold", (double)ns);
         int rc = radix_select(ctx, W.samples, nullptr, ns, nullptr, (unsigned long long)q, 64, W.sel);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 0, ebits);
+        hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 0, ebits,
+                           guarded ? 1 : 0);
       }
     } else {
       hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, thr_hi, (unsigned long long)(target - 1));
     }
     hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, &info[I_LIVE0], 0ull);
     {
-      TimedScope ts(ctx, "filter", (double)m);
-      hipLaunchKernelGGL(k_filter, dim3(tiles_f), dim3(BS), 0, st, g, W.lc, W.uptr, m, W.P, thr_lo,
-                         thr_hi, band > 0 ? 1 : 0, W.lr[0], W.lp[0], W.lo[0], &info[I_LIVE0]);
+      TimedScope ts(ctx, "rowpass", (double)g.nnz);
+      hipLaunchKernelGGL(k_rowpass, dim3(grid_for(g.nnz, TILE_R)), dim3(BS), 0, st, g, W.lc, W.Pc,
+                         thr_lo, thr_hi, band > 0 ? 1 : 0, band == 0 ? 1 : 0, W.bestA, W.lr[0],
+                         W.lp[0], W.lo[0], &info[I_LIVE0], next_scan(ctx, W));
     }
-    SPC_LAUNCH_CHECK(ctx, "filter");
+    SPC_LAUNCH_CHECK(ctx, "rowpass");
     int64_t live0 = 0;
     int rc = spanning_forest(ctx, W, n, band == 0, gk, ebits, R.rounds, live0);
     if (rc) return rc;
@@ -883,12 +1079,17 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
   unsigned long long* info = W.info;
   int64_t* hinfo = ctx->h_pinned;
   SPC_HIP(ctx, hipMemsetAsync(info, 0, sizeof(unsigned long long) * I_NINFO, st));
+  ctx->lb_words = lb_words(n, g.nnz);
+  ctx->lb_epoch = 0;
+  SPC_HIP(ctx, hipMemsetAsync(W.lbstate, 0, sizeof(uint64_t) * (size_t)ctx->lb_words, st));
 
   // A1
   {
     TimedScope ts(ctx, "degree", (double)n);
-    hipLaunchKernelGGL(k_degree, dim3(grid_for(n, DEG_ROWS)), dim3(BS), 0, st, g, W.deg, W.lc, W.uptr,
-                       W.bestA, W.bestB, W.parent, W.longrows, info);
+    int nb = grid_for(n, DEG_ROWS);
+    hipLaunchKernelGGL(k_degree, dim3(nb), dim3(BS), 0, st, g, W.deg, W.lc, W.uptr, W.bestA, W.bestB,
+                       W.parent, W.longrows, W.degpart, info);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, st, W.degpart, (int64_t)nb, &info[I_TOTAL]);
   }
   SPC_LAUNCH_CHECK(ctx, "degree");
   int rc = sync_info(ctx, W);
@@ -954,7 +1155,7 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
   }
   double* deps = (double*)&info[I_EPS];
   hipLaunchKernelGGL(k_eps, dim3(grid_for(R.msf, 256, ctx->num_cus * 4)), dim3(256), 0, st, g, W.deg,
-                     W.msfP, W.msfO, &info[I_MSF], W.sel2, deps);
+                     W.lc, W.msfP, W.msfO, &info[I_MSF], W.sel2, deps);
   SPC_LAUNCH_CHECK(ctx, "relabel");
   int32_t nc32 = 0;
   SPC_HIP(ctx, hipMemcpyAsync(&nc32, W.flag + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
