@@ -842,7 +842,10 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
   }
   int64_t nnz_c = 0;
   SPC_HIP(ctx, hipMemcpyAsync(&nnz_c, out->row_ptr + n_c, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  SPC_HIP(ctx, hipMemcpyAsync(hinfo, info, sizeof(unsigned long long) * I_NINFO,
+                              hipMemcpyDeviceToHost, st));
   SPC_HIP(ctx, hipStreamSynchronize(st));
+  if (hinfo[I_LBERR]) return set_error(ctx, SPC_EINVAL, "internal: look-back wait gave up");
   if (nnz_c > out->nnz_cap)
     return set_error(ctx, SPC_ECAPACITY, "coarse graph needs %lld entries, capacity %lld",
                      (long long)nnz_c, (long long)out->nnz_cap);

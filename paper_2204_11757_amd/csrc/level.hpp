@@ -68,6 +68,8 @@ enum Info : int {
   I_BLOCK = 14,   // contraction rows for the block-per-row class
   I_R32 = 15,     // contraction rows for the 32-entry register class
   I_LBERR = 16,   // a look-back wait gave up (internal error)
+  I_GUARD = 17,   // packed keys are guarded (not exact for every pair)
+  I_ROUNDS = 18,  // spanning-forest rounds that merged something
   I_NINFO = 24
 };
 

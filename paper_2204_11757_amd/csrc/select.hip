@@ -143,19 +143,23 @@ __global__ void __launch_bounds__(BS)
     k_degree_long(LevelIn g, const int32_t* __restrict__ longrows, uint64_t* __restrict__ deg,
                   unsigned long long* info) {
   __shared__ uint64_t tmp[BS / WAVE];
-  int64_t u = longrows[blockIdx.x];
-  int64_t s = g.rp[u], e = g.rp[u + 1];
-  uint64_t d = 0;
-  for (int64_t j = s + threadIdx.x; j < e; j += BS) d += (uint64_t)g.w[j];
-  d = wave_sum(d);
-  if (lane_id() == 0) tmp[threadIdx.x / WAVE] = d;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint64_t t = g.self ? (uint64_t)g.self[u] : 0;
-    for (int i = 0; i < BS / WAVE; i++) t += tmp[i];
-    deg[u] = t;
-    atomic_max_lazy(&info[I_DMAX], (unsigned long long)t);
-    atomicAdd(&info[I_TOTAL], (unsigned long long)t);
+  int64_t nlong = (int64_t)info[I_LONG];
+  for (int64_t r = blockIdx.x; r < nlong; r += gridDim.x) {
+    int64_t u = longrows[r];
+    int64_t s = g.rp[u], e = g.rp[u + 1];
+    uint64_t d = 0;
+    for (int64_t j = s + threadIdx.x; j < e; j += BS) d += (uint64_t)g.w[j];
+    d = wave_sum(d);
+    if (lane_id() == 0) tmp[threadIdx.x / WAVE] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t t = g.self ? (uint64_t)g.self[u] : 0;
+      for (int i = 0; i < BS / WAVE; i++) t += tmp[i];
+      deg[u] = t;
+      atomic_max_lazy(&info[I_DMAX], (unsigned long long)t);
+      atomicAdd(&info[I_TOTAL], (unsigned long long)t);
+    }
+    __syncthreads();
   }
 }
 
@@ -345,6 +349,12 @@ __global__ void __launch_bounds__(BS)
             const int64_t* __restrict__ uptr, int64_t m, int c, int ebits,
             uint64_t* __restrict__ Pc, uint64_t* __restrict__ samples, KeyND* __restrict__ keys,
             int write_keys, unsigned long long* info) {
+  // write_keys < 0: exact records only when the packed key is not exact
+  // for sure, i.e. when dmax^4 > 2^c
+  if (MODE == 0 && write_keys < 0) {
+    unsigned __int128 d2 = (unsigned __int128)info[I_DMAX] * info[I_DMAX];
+    write_keys = (d2 >> 64) != 0 || d2 * d2 > ((unsigned __int128)1 << c) ? 1 : 0;
+  }
   __shared__ int32_t srow[Lbs<TILE_S, BS>::SIZE];
   __shared__ int64_t sh[2];
   __shared__ int32_t stmp[BS / WAVE];
@@ -593,13 +603,16 @@ __global__ void __launch_bounds__(BS)
                const uint64_t* __restrict__ lo, const unsigned long long* cnt,
                const uint64_t* __restrict__ best, int32_t* parent, uint64_t* __restrict__ msfP,
                uint64_t* __restrict__ msfO, unsigned long long* msfcnt, int64_t msf_cap,
-               const KeyND* __restrict__ keys, int ebits, int* viol, TileScan ts) {
+               const KeyND* __restrict__ keys, const unsigned long long* guard, int ebits, int* viol,
+               TileScan ts, unsigned long long* rounds) {
   __shared__ int stmp[BS / WAVE];
   __shared__ unsigned long long sbase;
   int64_t n = (int64_t)*cnt;
   int tid = threadIdx.x;
   int64_t base = (int64_t)blockIdx.x * BV_CHUNK;
   if (base >= n) return;
+  if (blockIdx.x == 0 && tid == 0) atomicAdd(rounds, 1ull);
+  if (keys && !*guard) keys = nullptr;
   uint32_t chosen = 0;
   int nc = 0;
   for (int i = 0; i < BV_PER; i++) {
@@ -691,7 +704,9 @@ __global__ void __launch_bounds__(BS)
 // bucket must have exactly the cutoff's score (then the edge order inside
 // the bucket is the exact one).
 __global__ void k_cutoff_check(const uint64_t* __restrict__ msfP, const unsigned long long* cnt,
-                               const SelState* st, const KeyND* __restrict__ keys, int ebits, int* viol) {
+                               const SelState* st, const KeyND* __restrict__ keys,
+                               const unsigned long long* guard, int ebits, int* viol) {
+  if (!*guard) return;
   int64_t n = (int64_t)*cnt;
   uint64_t T = st->prefix;
   uint64_t emask = (1ull << ebits) - 1;
@@ -862,9 +877,9 @@ __global__ void k_fill_u64(uint64_t* __restrict__ a, int64_t n, uint64_t v) {
 // Guarded keys order edges of one K bucket only approximately, so there the
 // band is widened to the end of the sample's K bucket.
 __global__ void k_thr_from_sel(const SelState* st, unsigned long long* thr, int all, int ebits,
-                               int widen) {
+                               const unsigned long long* widen) {
   if (all) *thr = KEY_INF;
-  else if (widen) *thr = st->prefix | ((1ull << ebits) - 1);
+  else if (*widen) *thr = st->prefix | ((1ull << ebits) - 1);
   else *thr = st->prefix;
 }
 
@@ -875,73 +890,95 @@ static int sync_info(spc_ctx* ctx, const LevelWork& W) {
   return SPC_OK;
 }
 
+// Whether guarded decisions need checking: the packed key is inexact for
+// some pair of edges only when Dmax^2 > 2^c (Dmax = largest d_u d_v).
+__global__ void k_key_mode(unsigned long long* info, int c) {
+  unsigned __int128 D2 = (unsigned __int128)info[I_DMAXE] * info[I_DMAXE];
+  info[I_GUARD] = ((D2 >> 64) != 0 || D2 > ((unsigned __int128)1 << c)) ? 1ull : 0ull;
+}
+
+static int check_total(spc_ctx* ctx) {
+  uint64_t total = (uint64_t)ctx->h_pinned[I_TOTAL];
+  if (total > 2147483647ull)
+    return set_error(ctx, SPC_EOVERFLOW, "total integer weight %llu exceeds 2^31-1",
+                     (unsigned long long)total);
+  return SPC_OK;
+}
+
 // Spanning forest of the live list lr[0]/lp[0]/lo[0] (count in info[I_LIVE0])
 // on top of the components already in parent.  With fused_first, bestA
 // already holds every node's lightest incident key (first round done by the
 // key pass); otherwise both best arrays must be all-infinite on entry.
+// Rounds are issued two at a time between host synchronisations: a round
+// with no live edges is an empty launch.  On return the host copy of the
+// info block is current.
 static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, bool fused_first,
-                           const KeyND* guard_keys, int ebits, int64_t& rounds, int64_t& live0) {
+                           const KeyND* guard_keys, int ebits, int64_t& live0) {
   unsigned long long* info = W.info;
   int64_t* hinfo = ctx->h_pinned;
   int* viol = (int*)&info[I_VIOL];
+  const unsigned long long* guard = &info[I_GUARD];
   int rc = sync_info(ctx, W);
   if (rc) return rc;
+  rc = check_total(ctx);
+  if (rc) return rc;
+  if (hinfo[I_LBERR]) return set_error(ctx, SPC_EINVAL, "internal: look-back wait gave up");
   int64_t cnt = hinfo[I_LIVE0];
   live0 = cnt;
   uint64_t* cur = W.bestA;
   uint64_t* nxt = W.bestB;
   int in = 0;
   if (fused_first && cnt > 0) {
-    rounds++;
     TimedScope ts(ctx, "forest_merge", (double)cnt);
     hipLaunchKernelGGL(k_bv_merge, dim3(grid_for(cnt, BV_CHUNK)), dim3(BS), 0, ctx->stream, W.lr[0],
                        W.lp[0], W.lo[0], &info[I_LIVE0], cur, W.parent, W.msfP, W.msfO, &info[I_MSF], n,
-                       guard_keys, ebits, viol, next_scan(ctx, W));
+                       guard_keys, guard, ebits, viol, next_scan(ctx, W), &info[I_ROUNDS]);
     cur = W.bestB;
     nxt = W.bestA;
   }
-  while (cnt > 0) {
+  int64_t bound = cnt;   // live edges of the current list, at most
+  for (int batch = 0; bound > 0; batch++) {
     // every round at least halves the components that still have live
-    // edges, so more than 64 rounds means corrupted state
-    if (rounds > 64) return set_error(ctx, SPC_EINVAL, "internal: spanning forest did not converge");
-    int out = in ^ 1;
-    int ci = in == 0 ? I_LIVE0 : I_LIVE1;
-    int co = out == 0 ? I_LIVE0 : I_LIVE1;
-    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, ctx->stream, &info[co], 0ull);
-    {
-      TimedScope ts(ctx, "forest_candidates", (double)cnt);
-      hipLaunchKernelGGL(k_bv_candidates, dim3(grid_for(cnt, BV_CHUNK)), dim3(BS), 0, ctx->stream,
-                         W.lr[in], W.lp[in], W.lo[in], &info[ci], W.lr[out], W.lp[out], W.lo[out],
-                         &info[co], cur, nxt, W.parent, next_scan(ctx, W));
+    // edges, so this many rounds means corrupted state
+    if (batch >= 40) return set_error(ctx, SPC_EINVAL, "internal: spanning forest did not converge");
+    for (int r = 0; r < 2; r++) {
+      int out = in ^ 1;
+      int ci = in == 0 ? I_LIVE0 : I_LIVE1;
+      int co = out == 0 ? I_LIVE0 : I_LIVE1;
+      hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, ctx->stream, &info[co], 0ull);
+      {
+        TimedScope ts(ctx, "forest_candidates", (double)bound);
+        hipLaunchKernelGGL(k_bv_candidates, dim3(grid_for(bound, BV_CHUNK)), dim3(BS), 0, ctx->stream,
+                           W.lr[in], W.lp[in], W.lo[in], &info[ci], W.lr[out], W.lp[out], W.lo[out],
+                           &info[co], cur, nxt, W.parent, next_scan(ctx, W));
+      }
+      {
+        TimedScope ts(ctx, "forest_merge", (double)bound);
+        hipLaunchKernelGGL(k_bv_merge, dim3(grid_for(bound, BV_CHUNK)), dim3(BS), 0, ctx->stream,
+                           W.lr[out], W.lp[out], W.lo[out], &info[co], cur, W.parent, W.msfP, W.msfO,
+                           &info[I_MSF], n, guard_keys, guard, ebits, viol, next_scan(ctx, W),
+                           &info[I_ROUNDS]);
+      }
+      SPC_LAUNCH_CHECK(ctx, "forest round");
+      uint64_t* t = cur;
+      cur = nxt;
+      nxt = t;
+      in = out;
     }
-    SPC_LAUNCH_CHECK(ctx, "forest candidates");
-    SPC_HIP(ctx, hipMemcpyAsync(&hinfo[co], &info[co], sizeof(unsigned long long),
-                                hipMemcpyDeviceToHost, ctx->stream));
-    SPC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    cnt = hinfo[co];
-    if (cnt == 0) break;
-    rounds++;
-    {
-      TimedScope ts(ctx, "forest_merge", (double)cnt);
-      hipLaunchKernelGGL(k_bv_merge, dim3(grid_for(cnt, BV_CHUNK)), dim3(BS), 0, ctx->stream,
-                         W.lr[out], W.lp[out], W.lo[out], &info[co], cur, W.parent, W.msfP, W.msfO,
-                         &info[I_MSF], n, guard_keys, ebits, viol, next_scan(ctx, W));
-    }
-    SPC_LAUNCH_CHECK(ctx, "forest merge");
-    uint64_t* t = cur;
-    cur = nxt;
-    nxt = t;
-    in = out;
+    rc = sync_info(ctx, W);
+    if (rc) return rc;
+    bound = hinfo[in == 0 ? I_LIVE0 : I_LIVE1];
   }
-  // leave the band's final live list where the next band expects none
+  if (hinfo[I_LBERR]) return set_error(ctx, SPC_EINVAL, "internal: look-back wait gave up");
   return SPC_OK;
 }
 
 // Key pass, bands of candidate edges, spanning forest, cutoff.  On return
-// sel2->prefix holds the key of the k-th lightest forest edge and
-// info[I_VIOL] says whether a guarded decision failed.
+// sel2->prefix holds the key of the k-th lightest forest edge; info[I_VIOL]
+// (read at the level's next synchronisation) says whether a guarded
+// decision failed.
 static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k, int64_t m,
-                            uint64_t dmax, bool rank, LevelWork& W, LevelResult& R, bool& viol_out) {
+                            bool rank, LevelWork& W, LevelResult& R) {
   hipStream_t st = ctx->stream;
   int64_t n = g.n;
   unsigned long long* info = W.info;
@@ -949,28 +986,18 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
   int ebits = bitlen64((uint64_t)(m - 1));
   if (ebits < 1) ebits = 1;
   int c = 62 - ebits;
-  // Dmax <= dmax^2; the key is exact for sure when dmax^4 <= 2^c
-  unsigned __int128 d2 = (unsigned __int128)dmax * dmax;
-  bool surely_exact = d2 * d2 <= ((unsigned __int128)1 << c);
   int tiles_s = grid_for(m, TILE_S);
   int tiles_f = grid_for(m, TILE_F);
-  bool guarded = false;
+  const unsigned long long* guard = &info[I_GUARD];
   if (!rank) {
-    int write_keys = surely_exact ? 0 : 1;
     TimedScope ts(ctx, "score", (double)m);
     hipLaunchKernelGGL(k_score<0>, dim3(tiles_s), dim3(BS), 0, st, g, W.deg, W.lc, W.uptr, m, c,
-                       ebits, W.Pc, W.samples, W.keysA, write_keys, info);
+                       ebits, W.Pc, W.samples, W.keysA, -1, info);
+    hipLaunchKernelGGL(k_key_mode, dim3(1), dim3(1), 0, st, info, c);
     SPC_LAUNCH_CHECK(ctx, "score");
-    if (!surely_exact) {
-      int rc = sync_info(ctx, W);
-      if (rc) return rc;
-      uint64_t De = (uint64_t)hinfo[I_DMAXE];
-      unsigned __int128 D2 = (unsigned __int128)De * De;
-      guarded = D2 > ((unsigned __int128)1 << c);
-    }
-    R.key_mode = guarded ? 2 : 0;
     R.key_bits = 64;
   } else {
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, &info[I_GUARD], 0ull);
     {
       TimedScope ts(ctx, "score_rank", (double)m);
       hipLaunchKernelGGL(k_score<1>, dim3(tiles_s), dim3(BS), 0, st, g, W.deg, W.lc, W.uptr, m, c,
@@ -987,17 +1014,16 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
     hipLaunchKernelGGL(k_rank_scatter, dim3(grid_for(m, 256)), dim3(256), 0, st, sorted, m, W.P);
     hipLaunchKernelGGL(k_rank_mirror, dim3(tiles_f), dim3(BS), 0, st, g, W.lc, W.uptr, m, W.P, W.Pc);
     SPC_LAUNCH_CHECK(ctx, "rank scatter");
-    R.key_mode = 1;
     R.key_bits = bitlen64((uint64_t)(m - 1));
   }
-  const KeyND* gk = guarded ? W.keysA : nullptr;
+  // exact records for guarded checks (only consulted when info[I_GUARD] is set)
+  const KeyND* gk = rank ? nullptr : W.keysA;
 
   // A4: bands of the lightest edges; each band extends the forest built so far
   unsigned long long* thr_lo = &info[I_BAD];
   unsigned long long* thr_hi = &info[I_NC];
   int64_t target = k + k / 2 + 4096;
   int64_t done_cand = 0;
-  R.rounds = 0;
   R.candidates = 0;
   for (int band = 0;; band++) {
     bool all = ctx->force_full_filter || target >= m || band >= 2;
@@ -1008,19 +1034,18 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
       SPC_HIP(ctx, hipMemcpyAsync(thr_lo, thr_hi, sizeof(unsigned long long), hipMemcpyDeviceToDevice, st));
     }
     if (all) {
-      hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits, 0);
+      hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits, guard);
     } else if (!rank) {
       int64_t ns = (m + 63) / 64;
       int64_t q = (int64_t)((double)target / 64.0 * 1.05) + 16;
       if (q >= ns) {
         all = true;
-        hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits, 0);
+        hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits, guard);
       } else {
         TimedScope ts(ctx, "select_threshold", (double)ns);
         int rc = radix_select(ctx, W.samples, nullptr, ns, nullptr, (unsigned long long)q, 64, W.sel);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 0, ebits,
-                           guarded ? 1 : 0);
+        hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 0, ebits, guard);
       }
     } else {
       hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, thr_hi, (unsigned long long)(target - 1));
@@ -1034,9 +1059,7 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
     }
     SPC_LAUNCH_CHECK(ctx, "rowpass");
     int64_t live0 = 0;
-    int rc = spanning_forest(ctx, W, n, band == 0, gk, ebits, R.rounds, live0);
-    if (rc) return rc;
-    rc = sync_info(ctx, W);
+    int rc = spanning_forest(ctx, W, n, band == 0, gk, ebits, live0);
     if (rc) return rc;
     done_cand += live0;
     R.candidates = done_cand;
@@ -1060,14 +1083,11 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
                           W.sel2);
     if (rc) return rc;
   }
-  if (guarded) {
+  if (!rank) {
     hipLaunchKernelGGL(k_cutoff_check, dim3(grid_for(R.msf, 256, ctx->num_cus * 4)), dim3(256), 0, st,
-                       W.msfP, &info[I_MSF], W.sel2, W.keysA, ebits, (int*)&info[I_VIOL]);
+                       W.msfP, &info[I_MSF], W.sel2, W.keysA, guard, ebits, (int*)&info[I_VIOL]);
     SPC_LAUNCH_CHECK(ctx, "cutoff check");
   }
-  int rc = sync_info(ctx, W);
-  if (rc) return rc;
-  viol_out = hinfo[I_VIOL] != 0;
   return SPC_OK;
 }
 
@@ -1083,35 +1103,27 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
   ctx->lb_epoch = 0;
   SPC_HIP(ctx, hipMemsetAsync(W.lbstate, 0, sizeof(uint64_t) * (size_t)ctx->lb_words, st));
 
-  // A1
+  // A1 (long rows on a grid-stride launch that reads their count on device)
   {
     TimedScope ts(ctx, "degree", (double)n);
     int nb = grid_for(n, DEG_ROWS);
     hipLaunchKernelGGL(k_degree, dim3(nb), dim3(BS), 0, st, g, W.deg, W.lc, W.uptr, W.bestA, W.bestB,
                        W.parent, W.longrows, W.degpart, info);
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, st, W.degpart, (int64_t)nb, &info[I_TOTAL]);
+    hipLaunchKernelGGL(k_degree_long, dim3(ctx->num_cus), dim3(BS), 0, st, g, W.longrows, W.deg, info);
   }
   SPC_LAUNCH_CHECK(ctx, "degree");
-  int rc = sync_info(ctx, W);
-  if (rc) return rc;
-  int64_t nlong = hinfo[I_LONG];
-  if (nlong > 0) {
-    hipLaunchKernelGGL(k_degree_long, dim3((unsigned)nlong), dim3(BS), 0, st, g, W.longrows, W.deg, info);
-    SPC_LAUNCH_CHECK(ctx, "degree_long");
-    rc = sync_info(ctx, W);
-    if (rc) return rc;
-  }
-  uint64_t dmax = (uint64_t)hinfo[I_DMAX];
-  uint64_t total = (uint64_t)hinfo[I_TOTAL];
-  if (total > 2147483647ull)
-    return set_error(ctx, SPC_EOVERFLOW, "total integer weight %llu exceeds 2^31-1",
-                     (unsigned long long)total);
+  int rc;
   {
     TimedScope ts(ctx, "scan_upper", (double)n);
     rc = exclusive_scan<int64_t>(ctx, W.uptr, W.uptr, n, (int64_t*)W.scan_partial);
     if (rc) return rc;
   }
   if (k <= 0 || m == 0) {
+    rc = sync_info(ctx, W);
+    if (rc) return rc;
+    rc = check_total(ctx);
+    if (rc) return rc;
     if (k > 0) return set_error(ctx, SPC_EUNREACHABLE, "graph has no edges");
     hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256)), dim3(256), 0, st, cluster_of, n);
     R.n_c = n;
@@ -1119,8 +1131,10 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
     return SPC_OK;
   }
 
-  // A2-A4; a guarded key that fails its exactness check falls back to ranks
+  // A2-A4 and the labels; a guarded key that fails its exactness check
+  // falls back to ranks
   bool rank = ctx->force_rank_mode != 0;
+  int32_t nc32 = 0;
   for (int pass = 0; pass < 2; pass++) {
     if (pass == 1) {
       rank = true;
@@ -1130,37 +1144,37 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestA, n, KEY_INF);
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestB, n, KEY_INF);
     }
-    bool viol = false;
-    rc = order_and_select(ctx, g, t, k, m, dmax, rank, W, R, viol);
+    rc = order_and_select(ctx, g, t, k, m, rank, W, R);
     if (rc) return rc;
-    if (!viol) break;
+    {
+      TimedScope ts(ctx, "components", (double)n);
+      hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256)), dim3(256), 0, st, W.parent, n);
+      hipLaunchKernelGGL(k_cc_union, dim3(grid_for(R.msf, 256, ctx->num_cus * 8)), dim3(256), 0, st,
+                         W.msfP, W.msfO, &info[I_MSF], W.sel2, W.parent);
+      hipLaunchKernelGGL(k_cc_flatten, dim3(grid_for(n, 256)), dim3(256), 0, st, W.parent, W.root,
+                         W.flag, n);
+    }
+    SPC_LAUNCH_CHECK(ctx, "components");
+    {
+      TimedScope ts(ctx, "relabel", (double)n);
+      rc = exclusive_scan<int32_t>(ctx, W.flag, W.flag, n, (int32_t*)W.scan_partial);
+      if (rc) return rc;
+      hipLaunchKernelGGL(k_relabel, dim3(grid_for(n, 256)), dim3(256), 0, st, W.root, W.flag,
+                         cluster_of, n);
+    }
+    double* deps = (double*)&info[I_EPS];
+    hipLaunchKernelGGL(k_eps, dim3(grid_for(R.msf, 256, ctx->num_cus * 4)), dim3(256), 0, st, g, W.deg,
+                       W.lc, W.msfP, W.msfO, &info[I_MSF], W.sel2, deps);
+    SPC_LAUNCH_CHECK(ctx, "relabel");
+    SPC_HIP(ctx, hipMemcpyAsync(&nc32, W.flag + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    rc = sync_info(ctx, W);
+    if (rc) return rc;
+    R.key_mode = rank ? 1 : (hinfo[I_GUARD] ? 2 : 0);
+    R.rounds = hinfo[I_ROUNDS];
+    if (hinfo[I_VIOL] == 0) break;
     if (rank) return set_error(ctx, SPC_EINVAL, "internal: exact rank order flagged as inexact");
   }
-
-  {
-    TimedScope ts(ctx, "components", (double)n);
-    hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256)), dim3(256), 0, st, W.parent, n);
-    hipLaunchKernelGGL(k_cc_union, dim3(grid_for(R.msf, 256, ctx->num_cus * 8)), dim3(256), 0, st,
-                       W.msfP, W.msfO, &info[I_MSF], W.sel2, W.parent);
-    hipLaunchKernelGGL(k_cc_flatten, dim3(grid_for(n, 256)), dim3(256), 0, st, W.parent, W.root,
-                       W.flag, n);
-  }
-  SPC_LAUNCH_CHECK(ctx, "components");
-  {
-    TimedScope ts(ctx, "relabel", (double)n);
-    rc = exclusive_scan<int32_t>(ctx, W.flag, W.flag, n, (int32_t*)W.scan_partial);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_relabel, dim3(grid_for(n, 256)), dim3(256), 0, st, W.root, W.flag,
-                       cluster_of, n);
-  }
-  double* deps = (double*)&info[I_EPS];
-  hipLaunchKernelGGL(k_eps, dim3(grid_for(R.msf, 256, ctx->num_cus * 4)), dim3(256), 0, st, g, W.deg,
-                     W.lc, W.msfP, W.msfO, &info[I_MSF], W.sel2, deps);
-  SPC_LAUNCH_CHECK(ctx, "relabel");
-  int32_t nc32 = 0;
-  SPC_HIP(ctx, hipMemcpyAsync(&nc32, W.flag + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  rc = sync_info(ctx, W);
-  if (rc) return rc;
+  if (hinfo[I_LBERR]) return set_error(ctx, SPC_EINVAL, "internal: look-back wait gave up");
   double eps;
   memcpy(&eps, &hinfo[I_EPS], sizeof(double));
   R.eps = eps;
