@@ -47,27 +47,72 @@ def make_config(name):
     raise SystemExit(f"unknown config {name}")
 
 
-# Algorithmic HBM bytes of one launch, from the level's sizes: the data the
-# kernel must move at least once (inputs read once, outputs written once).
+# Algorithmic HBM bytes of a kernel over one level: the data it must move at
+# least once (inputs read once, outputs written once), from the level's sizes
+# and work counters.  Per-launch figures divide by the launches per level.
 def algo_bytes(kernel, L):
     n, m, nnz, n_c, nnz_c, selfb = L["n"], L["m"], 2 * L["m"], L["n_c"], L["nnz_c"], L["self"]
-    if kernel == "score":            # CSR rows once, per-node prefix/degree/bests, key written
-        return 24 * m + 44 * n + 8 * n * selfb
-    if kernel == "degree":           # row_ptr, col + w once, per-node outputs
-        return 8 * nnz + 56 * n + 8 * n * selfb
-    if kernel == "filter":           # keys and per-node prefixes read
-        return 8 * m + 20 * n
-    if kernel == "contract_small":   # member rows, their neighbours' labels, coarse rows written
-        return 12 * nnz + 28 * n + 32 * n_c + 8 * nnz_c + 12 * n * selfb
+    if kernel == "score":
+        # CSR col + w of both rows once (8 B per entry), per-node row_ptr,
+        # degree, lower count, upper prefix (28 B), self-loops at coarse
+        # levels; writes the key of both CSR entries of every edge, one
+        # sample per 64 edges, and the exact records when they are kept
+        if L["key_mode"] == "rank":
+            return None
+        return 8 * nnz + 28 * n + 8 * n * selfb + 16 * m + 8 * ((m + 63) // 64) + 24 * m * L["keys_written"]
+    if kernel == "rowpass":
+        # every band reads each entry's key and column and the row pointers;
+        # the first band writes each node's lightest key; kept edges are
+        # written as three 8-byte words
+        return L["bands"] * (12 * nnz + 8 * (n + 1)) + 8 * n + 24 * L["candidate_edges"]
+    if kernel == "degree":
+        return 8 * nnz + 8 * (n + 1) + 44 * n + 8 * n * selfb
+    if kernel == "forest_candidates":
+        # live list read (24 B) and both root lookups (4 B each), kept edges written
+        return 32 * L["forest_in"] + 24 * L["forest_kept"]
+    if kernel == "forest_merge":
+        # live list and both endpoints' lightest keys read; forest records
+        # (16 B) and parent hooks (4 B) written
+        return 40 * L["merge_in"] + 20 * L["forest_edges"]
     if kernel == "contract_pack":
         return 16 * nnz_c + 16 * n_c
-    if kernel == "contract_members":
-        return 20 * n + 24 * n_c
-    if kernel == "components":
-        return 16 * n
-    if kernel == "relabel":
-        return 16 * n
     return None
+
+
+# kernels timed one launch per scope (the candidates for the roofline line)
+SINGLE_KERNEL_SCOPES = ["score", "rowpass", "degree", "forest_candidates", "forest_merge",
+                        "contract_small", "contract_reg32", "contract_wave_rows",
+                        "contract_block_rows", "contract_pack"]
+KERNEL_SYMBOL = {"score": "k_score<0>", "rowpass": "k_rowpass", "degree": "k_degree",
+                 "forest_candidates": "k_bv_candidates", "forest_merge": "k_bv_merge",
+                 "contract_small": "k_contract_small", "contract_reg32": "k_contract_reg32",
+                 "contract_wave_rows": "k_contract_row<64, 512>",
+                 "contract_block_rows": "k_contract_row<256, 4096>", "contract_pack": "k_pack"}
+# source file of each kernel: a stored counter reading is used only while
+# this file is unchanged
+KERNEL_SOURCE = {"score": "select.hip", "rowpass": "select.hip", "degree": "select.hip",
+                 "forest_candidates": "select.hip", "forest_merge": "select.hip",
+                 "contract_small": "contract.hip", "contract_reg32": "contract.hip",
+                 "contract_wave_rows": "contract.hip", "contract_block_rows": "contract.hip",
+                 "contract_pack": "contract.hip"}
+
+
+def stored_traffic(kernel, config_name):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current source of the kernel and this workload."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(f"{kernel}@{config_name}")
+    if not rec:
+        return None
+    src = os.path.join(ROOT, "paper_2204_11757_amd", "csrc", KERNEL_SOURCE[kernel])
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+            return None
+    return rec["bytes_per_launch"]
 
 
 def method_floor_bytes(L):
@@ -78,16 +123,24 @@ def method_floor_bytes(L):
     return comp + 16 * m
 
 
-def cpu_baseline(g):
+def cpu_baseline(g, n_c):
+    """The oracle on the same step (every level to n_c), repeated until about
+    10 s of host time have passed (at least once), on one host core."""
     import oracle
-    t = (g.n + 1) // 2
-    t0 = time.perf_counter()
-    oracle.coarsen_level(g, t)
-    dt = time.perf_counter() - t0
-    return {"value": g.m / dt, "unit": "fine edges/s", "cores": 1, "kind": "oracle",
-            "seconds": round(dt, 3),
-            "sample": f"one level (the first) of the same mesh: {g.n} nodes, {g.m} edges, "
-                      f"halving to {t}; serial C oracle on one host core"}
+    runs, total_edges, t_all = 0, 0, 0.0
+    while runs == 0 or t_all < 10.0:
+        t0 = time.perf_counter()
+        lv = oracle.coarsen_to(g, n_c, 0)
+        t_all += time.perf_counter() - t0
+        prev = g
+        for _, gc, _ in lv:
+            total_edges += prev.m
+            prev = gc
+        runs += 1
+    return {"value": total_edges / t_all, "unit": "fine edges/s", "cores": 1, "kind": "oracle",
+            "seconds": round(t_all, 3),
+            "sample": f"the whole step ({len(lv)} levels of the same mesh to n_c={n_c}) run {runs} "
+                      f"time(s) by the serial C oracle on one host core"}
 
 
 def main():
@@ -152,8 +205,10 @@ def main():
         L = {"level": l, "n": st.n_in, "m": st.m_in, "n_c": st.n_out, "nnz_c": st.nnz_out,
              "self": 1 if l > 1 else 0, "ms": round(st.ms_total, 4),
              "key_mode": {0: "exact-packed", 1: "rank", 2: "guarded-packed"}.get(st.key_mode, "?"),
+             "keys_written": int(st.keys_written), "bands": int(st.bands),
              "forest_rounds": st.boruvka_rounds, "candidate_edges": st.candidate_edges,
-             "largest_cluster": st.largest_cluster}
+             "forest_in": st.forest_in, "forest_kept": st.forest_kept, "merge_in": st.merge_in,
+             "forest_edges": st.forest_edges, "largest_cluster": st.largest_cluster}
         L["fine_edges_per_s"] = st.m_in / (st.ms_total * 1e-3) if st.ms_total > 0 else None
         L["hbm_floor_frac"] = (method_floor_bytes(L) / (st.ms_total * 1e-3) / (HBM_PEAK_GBS * 1e9)
                                if st.ms_total > 0 else None)
@@ -166,6 +221,8 @@ def main():
     roofline = None
     kernels = None
     if not args.no_roofline:
+        # per-kernel times: the same K steps again with a HIP event pair
+        # recorded on the context stream around every launch
         print("[bench] per-kernel timing pass", file=sys.stderr, flush=True)
         spc.set_option("timing", 1)
         spc.timing_report()   # clear
@@ -176,37 +233,29 @@ def main():
         spc.set_option("timing", 0)
         kernels = {k: {"launches": c, "ms_total": round(t, 4), "ms_avg": round(t / c, 5)}
                    for k, (c, t, u) in sorted(rep.items(), key=lambda kv: -kv[1][1])}
-        dom = None
-        for k, (c, t, u) in sorted(rep.items(), key=lambda kv: -kv[1][1]):
-            dom = k
-            break
-        per_step_bytes = None
-        if dom is not None:
-            b = [algo_bytes(dom, L) for L in levels]
-            if all(x is not None for x in b):
-                per_step_bytes = sum(b)
-        if dom is not None:
-            c, t, u = rep[dom]
+        single = [(k, rep[k]) for k in SINGLE_KERNEL_SCOPES if k in rep]
+        single.sort(key=lambda kv: -kv[1][1])
+        if single:
+            dom, (c, t, u) = single[0]
             avg_ms = t / c
-            if per_step_bytes is not None:
-                launches_per_step = c / args.steps
-                bytes_per_launch = per_step_bytes / launches_per_step
+            per_level = [algo_bytes(dom, L) for L in levels]
+            roofline = {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom], "scope": dom,
+                        "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
+                        "traffic": None, "avg_launch_ms": round(avg_ms, 5),
+                        "launches_per_step": c / args.steps}
+            if all(x is not None for x in per_level):
+                bytes_per_launch = sum(per_level) / (c / args.steps)
                 achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-                roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2),
-                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                            "avg_launch_ms": round(avg_ms, 5),
-                            "algo_bytes_per_launch": int(bytes_per_launch)}
-            else:
-                roofline = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": None, "traffic": None,
-                            "avg_launch_ms": round(avg_ms, 5),
-                            "note": "no algorithmic byte model for this kernel"}
+                roofline.update(achieved=round(achieved, 2), frac=round(achieved / HBM_PEAK_GBS, 4),
+                                algo_bytes_per_launch=int(bytes_per_launch))
+            tr = stored_traffic(dom, args.config)
+            if tr is not None:
+                roofline["traffic"] = int(tr)
 
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, one level)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(g)
+        cpu = cpu_baseline(g, n_c)
 
     out = {
         "metric": METRIC,

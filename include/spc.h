@@ -88,11 +88,19 @@ typedef struct {
 /* Per-level statistics (host struct, filled when non-NULL). */
 typedef struct {
   int64_t n_in, m_in, n_out, nnz_out, merges, largest_cluster;
-  int64_t boruvka_rounds, candidate_edges;
-  int32_t key_mode;   /* 0: packed exact fixed-point key, 1: sorted rank */
+  int64_t boruvka_rounds;   /* spanning-forest rounds that merged something   */
+  int64_t candidate_edges;  /* edges that entered the spanning-forest phase   */
+  int32_t key_mode;   /* 0: exact packed fixed-point key, 1: sorted rank,
+                         2: guarded packed key (checked, exact on success) */
   int32_t key_bits;
   double eps_max;     /* largest accepted score (Theorem 2's epsilon)    */
   float ms_total;
+  int32_t bands;            /* candidate bands (row passes) used             */
+  int64_t forest_in;        /* live edges read by the root-lookup rounds     */
+  int64_t forest_kept;      /* live edges those rounds kept                  */
+  int64_t merge_in;         /* live edges read by the hooking rounds         */
+  int64_t forest_edges;     /* spanning-forest edges found                   */
+  int32_t keys_written;     /* exact per-edge score records were written     */
 } spc_level_stats;
 
 /* Create a context on a device; hip_stream is a hipStream_t (NULL: the

@@ -63,6 +63,36 @@ int readback(spc_ctx* ctx, const void* dev, size_t bytes, void* host) {
   return SPC_OK;
 }
 
+uint32_t scan_state_reserve(spc_ctx* ctx, int64_t words) {
+  words += 1;   // the last word is the error flag
+  if (words > ctx->scan_cap || ctx->scan_epoch >= LB_MAX_EPOCH) {
+    if (words > ctx->scan_cap) {
+      int64_t cap = words > (1 << 16) ? words : (1 << 16);
+      if (ctx->scan_state) {
+        if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+          set_error(ctx, SPC_EHIP, "stream synchronisation failed");
+          return 0;
+        }
+        dev_free(ctx, ctx->scan_state);
+      }
+      ctx->scan_state = (uint64_t*)dev_alloc(ctx, sizeof(uint64_t) * (size_t)cap);
+      if (!ctx->scan_state) {
+        ctx->scan_cap = 0;
+        set_error(ctx, SPC_ENOMEM, "scan state allocation failed");
+        return 0;
+      }
+      ctx->scan_cap = cap;
+    }
+    if (hipMemsetAsync(ctx->scan_state, 0, sizeof(uint64_t) * (size_t)ctx->scan_cap, ctx->stream) !=
+        hipSuccess) {
+      set_error(ctx, SPC_EHIP, "scan state clear failed");
+      return 0;
+    }
+    ctx->scan_epoch = 0;
+  }
+  return ++ctx->scan_epoch;
+}
+
 static int plan_and_bind(spc_ctx* ctx, int64_t n, int64_t nnz, LevelWork& W) {
   Arena count;
   count.counting = true;
@@ -180,6 +210,12 @@ static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* clus
     st->key_bits = R.key_bits;
     st->eps_max = R.eps;
     st->ms_total = ms;
+    st->bands = R.bands;
+    st->forest_in = R.forest_in;
+    st->forest_kept = R.forest_kept;
+    st->merge_in = R.merge_in;
+    st->forest_edges = R.msf;
+    st->keys_written = R.keys_written;
   }
   return SPC_OK;
 }
@@ -241,6 +277,7 @@ int spc_destroy(spc_ctx* ctx) {
   if (!ctx) return SPC_OK;
   (void)hipStreamSynchronize(ctx->stream);
   dev_free(ctx, ctx->ws);
+  dev_free(ctx, ctx->scan_state);
   if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
   delete ctx;
   return SPC_OK;
@@ -256,11 +293,14 @@ int spc_set_allocator(spc_ctx* ctx, void* (*alloc)(size_t, void*), void (*free_)
                       void* user) {
   if (!ctx) return SPC_EINVAL;
   if ((alloc == nullptr) != (free_ == nullptr)) return set_error(ctx, SPC_EINVAL, "allocator pair incomplete");
-  if (ctx->ws) {
+  if (ctx->ws || ctx->scan_state) {
     (void)hipStreamSynchronize(ctx->stream);
     dev_free(ctx, ctx->ws);
+    dev_free(ctx, ctx->scan_state);
     ctx->ws = nullptr;
     ctx->ws_cap = 0;
+    ctx->scan_state = nullptr;
+    ctx->scan_cap = 0;
   }
   ctx->alloc_fn = alloc;
   ctx->free_fn = free_;
@@ -275,6 +315,7 @@ int spc_set_option(spc_ctx* ctx, const char* name, int64_t value) {
   if (!strcmp(name, "rank_order")) ctx->force_rank_mode = value ? 1 : 0;
   else if (!strcmp(name, "full_forest")) ctx->force_full_filter = value ? 1 : 0;
   else if (!strcmp(name, "timing")) ctx->timing = value ? 1 : 0;
+  else if (!strcmp(name, "huge_sort")) ctx->force_huge_sort = value ? 1 : 0;
   else return set_error(ctx, SPC_EINVAL, "unknown option '%s'", name);
   return SPC_OK;
 }

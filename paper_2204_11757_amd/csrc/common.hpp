@@ -277,11 +277,15 @@ struct spc_ctx {
   int err_code = 0;
   std::string err;
   int num_cus = 256;
+  uint64_t* scan_state = nullptr;  // look-back words of the single-pass scan
+  int64_t scan_cap = 0;            // words
+  uint32_t scan_epoch = 0;
   uint32_t lb_epoch = 0;       // last look-back epoch handed out
   int64_t lb_words = 0;        // size of the current level's look-back array
   // knobs
   int force_rank_mode = 0;   // use the sorted-rank order even when a packed key fits
   int force_full_filter = 0; // run the spanning-forest phase over every edge
+  int force_huge_sort = 0;   // contract huge rows by sorting even when dense accumulators fit
   // per-kernel timing: events recorded around launches on the context stream
   int timing = 0;
   std::vector<hipEvent_t> ev_pool;

@@ -349,14 +349,19 @@ __global__ void __launch_bounds__(SMALL_BS)
   unsigned long long tot;
   unsigned long long incl = block_incl_scan<unsigned long long, SMALL_BS, false>(mine, stmp, &tot);
   unsigned long long excl = incl - mine;
-  if (tid < 4) {
-    int slot = tid == 0 ? I_R32 : tid == 1 ? I_MID : tid == 2 ? I_BLOCK : I_HUGE;
-    uint64_t cnt_c = (tot >> (16 * tid)) & 0xffffull;
+  // wavefront w runs the chains of classes w and w + 2
+  static_assert(SMALL_BS == 2 * WAVE, "two wavefronts share the four chains");
+  for (int q = 0; q < 2; q++) {
+    int cls = tid / WAVE + 2 * q;
+    int slot = cls == 0 ? I_R32 : cls == 1 ? I_MID : cls == 2 ? I_BLOCK : I_HUGE;
+    uint64_t cnt_c = (tot >> (16 * cls)) & 0xffffull;
     TileScan t = ts;
-    t.state += (int64_t)tid * gridDim.x;
-    uint64_t ex = lb_exclusive(t, blockIdx.x, cnt_c);
-    sbase[tid] = (int64_t)ex;
-    if (blockIdx.x == gridDim.x - 1) info[slot] = ex + cnt_c;
+    t.state += (int64_t)cls * gridDim.x;
+    uint64_t ex = lb_exclusive_wave(t, blockIdx.x, cnt_c);
+    if (lane_id() == 0) {
+      sbase[cls] = (int64_t)ex;
+      if (blockIdx.x == gridDim.x - 1) info[slot] = ex + cnt_c;
+    }
   }
   __syncthreads();
   int64_t p0 = sbase[0] + (int64_t)(excl & 0xffff);
@@ -516,7 +521,8 @@ constexpr int HMB_T = 1024;
 __global__ void __launch_bounds__(HMB_BS)
     k_huge_members(LevelIn g, const int32_t* __restrict__ hugelist, const int32_t* __restrict__ mptr,
                    const int32_t* __restrict__ members, const int64_t* __restrict__ hoff, int64_t H,
-                   int64_t HM, int64_t* __restrict__ hlen, int64_t* self_out, int32_t* size_out) {
+                   int64_t HM, int64_t* __restrict__ hlen, int32_t* __restrict__ hrow,
+                   int64_t* __restrict__ hrs, int64_t* self_out, int32_t* size_out) {
   __shared__ unsigned long long sself[HMB_T];
   __shared__ int32_t ssize[HMB_T];
   __shared__ int32_t sh0;
@@ -541,7 +547,10 @@ __global__ void __launch_bounds__(HMB_BS)
       int32_t x = members[mptr[hugelist[h]] + (i - hoff[h])];
       self = g.self ? g.self[x] : 0;
       sz = g.size ? g.size[x] : 1;
-      hlen[i] = g.rp[x + 1] - g.rp[x];
+      int64_t rs = g.rp[x];
+      hlen[i] = g.rp[x + 1] - rs;
+      hrow[i] = h;
+      hrs[i] = rs;
     }
     bool head;
     int end;
@@ -576,10 +585,9 @@ static_assert(HT <= BLOCK_CAP, "a tile of gathered entries must meet at most two
 
 __global__ void __launch_bounds__(HT_BS)
     k_huge_entries(LevelIn g, const int32_t* __restrict__ c, const int32_t* __restrict__ hugelist,
-                   const int32_t* __restrict__ mptr, const int32_t* __restrict__ members,
-                   const int64_t* __restrict__ hoff, int64_t H, const int64_t* __restrict__ hpre,
-                   int64_t HM, int64_t* self_out, KW* __restrict__ out, unsigned long long* gcnt,
-                   TileScan ts) {
+                   const int32_t* __restrict__ hrow, const int64_t* __restrict__ hrs,
+                   const int64_t* __restrict__ hpre, int64_t HM, int64_t* self_out,
+                   KW* __restrict__ out, unsigned long long* gcnt, TileScan ts) {
   __shared__ int32_t srow[Lbs<HT, HT_BS>::SIZE];
   __shared__ int64_t sh[2];
   __shared__ int32_t stmp[HT_BS / WAVE];
@@ -592,7 +600,7 @@ __global__ void __launch_bounds__(HT_BS)
   lbs_tile<HT, HT_BS>(hpre, HM, q0, srow, sh, stmp);
   int tid = threadIdx.x;
   if (tid < 2) sself[tid] = 0;
-  int32_t h0 = huge_row_of(hoff, H, srow[0]);
+  int32_t h0 = hrow[srow[0]];
   __syncthreads();
   uint32_t cross = 0;
   int ncross = 0;
@@ -608,10 +616,9 @@ __global__ void __launch_bounds__(HT_BS)
     wv[r] = 0;
     if (q < total) {
       int64_t i = srow[Lbs<HT, HT_BS>::at(k)];
-      h = huge_row_of(hoff, H, i);
+      h = hrow[i];
       int32_t a = hugelist[h];
-      int32_t x = members[mptr[a] + (i - hoff[h])];
-      int64_t j = g.rp[x] + (q - hpre[i]);
+      int64_t j = hrs[i] + (q - hpre[i]);
       int32_t b = c[g.col[j]];
       uint32_t w = (uint32_t)g.w[j];
       if (b == a) {
@@ -639,6 +646,87 @@ __global__ void __launch_bounds__(HT_BS)
 #pragma unroll
   for (int r = 0; r < HT / HT_BS; r++)
     if (cross >> r & 1u) out[pos++] = KW{keyv[r], (uint64_t)wv[r]};
+}
+
+// Dense path for few huge rows: row h's cross weights accumulate in
+// dense[h * ncp + b] (u32; a row's total stays below 2^31), then a compaction
+// in ascending b emits the row.  Same tiling and self-loop handling as
+// k_huge_entries.
+__global__ void __launch_bounds__(HT_BS)
+    k_huge_dense(LevelIn g, const int32_t* __restrict__ c, const int32_t* __restrict__ hugelist,
+                 const int32_t* __restrict__ hrow, const int64_t* __restrict__ hrs,
+                 const int64_t* __restrict__ hpre, int64_t HM, int64_t* self_out,
+                 uint32_t* __restrict__ dense, int64_t ncp) {
+  __shared__ int32_t srow[Lbs<HT, HT_BS>::SIZE];
+  __shared__ int64_t sh[2];
+  __shared__ int32_t stmp[HT_BS / WAVE];
+  __shared__ unsigned long long sself[2];
+  int64_t q0 = (int64_t)blockIdx.x * HT;
+  int64_t total = hpre[HM];
+  lbs_tile<HT, HT_BS>(hpre, HM, q0, srow, sh, stmp);
+  int tid = threadIdx.x;
+  if (tid < 2) sself[tid] = 0;
+  int32_t h0 = hrow[srow[0]];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < HT / HT_BS; r++) {
+    int k = tid + r * HT_BS;
+    int64_t q = q0 + k;
+    int32_t h = -1;
+    int64_t self = 0;
+    if (q < total) {
+      int64_t i = srow[Lbs<HT, HT_BS>::at(k)];
+      h = hrow[i];
+      int32_t a = hugelist[h];
+      int64_t j = hrs[i] + (q - hpre[i]);
+      int32_t b = c[g.col[j]];
+      uint32_t w = (uint32_t)g.w[j];
+      if (b == a) self = w;
+      else atomicAdd(&dense[(int64_t)h * ncp + b], w);
+    }
+    bool head;
+    int end;
+    uint64_t heads;
+    wave_runs(h, head, end, heads);
+    int64_t si = wave_incl_sum(self);
+    int64_t se = __shfl(si, end - 1);
+    if (head && h >= 0 && se - si + self)
+      atomicAdd(&sself[h - h0], (unsigned long long)(se - si + self));
+  }
+  __syncthreads();
+  if (tid < 2 && sself[tid]) atomicAdd((unsigned long long*)&self_out[hugelist[h0 + tid]], sself[tid]);
+}
+
+// Compaction of the dense rows: tile t of row h covers b in
+// [t * DC_T, (t + 1) * DC_T), 8 consecutive b per thread; each row is its
+// own look-back chain, whose last tile writes the row's entry count.
+constexpr int DC_BS = 256;
+constexpr int DC_PER = 8;
+constexpr int DC_T = DC_BS * DC_PER;
+
+__global__ void __launch_bounds__(DC_BS)
+    k_dense_compact(const uint32_t* __restrict__ dense, int64_t ncp, int64_t n_c, int64_t tpr,
+                    const int32_t* __restrict__ hugelist, const int64_t* __restrict__ gptr,
+                    uint64_t* __restrict__ temp, int64_t* cnt, TileScan ts) {
+  __shared__ int stmp[DC_BS / WAVE];
+  __shared__ unsigned long long sbase;
+  int64_t h = blockIdx.x / tpr, t = blockIdx.x % tpr;
+  int32_t a = hugelist[h];
+  int64_t b0 = t * DC_T + (int64_t)threadIdx.x * DC_PER;
+  const uint4* src = (const uint4*)(dense + h * ncp + b0);
+  uint4 v0 = src[0], v1 = src[1];
+  uint32_t v[DC_PER] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+  int my = 0;
+#pragma unroll
+  for (int q = 0; q < DC_PER; q++) my += (v[q] != 0 && b0 + q < n_c) ? 1 : 0;
+  TileScan tr = ts;
+  tr.state += h * tpr;
+  int64_t pos = block_reserve_lb<DC_BS>(tr, t, t == tpr - 1, my, nullptr,
+                                        (unsigned long long*)&cnt[a], &sbase, stmp);
+  uint64_t* o = temp + gptr[a];
+#pragma unroll
+  for (int q = 0; q < DC_PER; q++)
+    if (v[q] != 0 && b0 + q < n_c) o[pos++] = ((uint64_t)(b0 + q) << 32) | v[q];
 }
 
 __global__ void k_head_flags(const KW* __restrict__ s, int64_t G, int32_t* __restrict__ flag,
@@ -788,19 +876,31 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
     SPC_HIP(ctx, hipStreamSynchronize(st));
     int64_t* hpre = W.hpos;   // member row lengths, then their prefix
     hipLaunchKernelGGL(k_huge_members, dim3(grid_for(HM, HMB_T)), dim3(HMB_BS), 0, st, g, W.hugelist,
-                       W.mptr, W.members, W.hmoff, H, HM, hpre, self_out, out->size);
+                       W.mptr, W.members, W.hmoff, H, HM, hpre, W.hmrow, W.hmrs, self_out, out->size);
     rc = exclusive_scan<int64_t>(ctx, hpre, hpre, HM, (int64_t*)W.scan_partial);
     if (rc) return rc;
     int64_t Etot = 0;
     SPC_HIP(ctx, hipMemcpyAsync(&Etot, hpre + HM, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     SPC_HIP(ctx, hipMemsetAsync(&info[I_LIVE1], 0, sizeof(unsigned long long), st));
     SPC_HIP(ctx, hipStreamSynchronize(st));
+    // few huge rows: dense accumulators over the coarse ids (they fit in
+    // the gather buffers when H * ncp <= 2 nnz)
+    int64_t ncp = (n_c + DC_T - 1) / DC_T * DC_T;
+    if (Etot > 0 && !ctx->force_huge_sort && H * ncp <= 2 * g.nnz) {
+      uint32_t* dense = (uint32_t*)W.gkeyA;
+      SPC_HIP(ctx, hipMemsetAsync(dense, 0, sizeof(uint32_t) * (size_t)(H * ncp), st));
+      hipLaunchKernelGGL(k_huge_dense, dim3(grid_for(Etot, HT)), dim3(HT_BS), 0, st, g, c, W.hugelist,
+                         W.hmrow, W.hmrs, hpre, HM, self_out, dense, ncp);
+      int64_t tpr = ncp / DC_T;
+      hipLaunchKernelGGL(k_dense_compact, dim3((unsigned)(H * tpr)), dim3(DC_BS), 0, st, dense, ncp, n_c,
+                         tpr, W.hugelist, W.gptr, W.temp, W.cnt, next_scan(ctx, W));
+      SPC_LAUNCH_CHECK(ctx, "huge dense");
+    } else {
     KW* A = (KW*)W.gkeyA;
     KW* B = (KW*)W.gkeyB;
     if (Etot > 0) {
       hipLaunchKernelGGL(k_huge_entries, dim3(grid_for(Etot, HT)), dim3(HT_BS), 0, st, g, c, W.hugelist,
-                         W.mptr, W.members, W.hmoff, H, hpre, HM, self_out, A, &info[I_LIVE1],
-                         next_scan(ctx, W));
+                         W.hmrow, W.hmrs, hpre, HM, self_out, A, &info[I_LIVE1], next_scan(ctx, W));
       SPC_LAUNCH_CHECK(ctx, "huge gather");
     }
     int64_t G = 0;
@@ -834,6 +934,7 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
     hipLaunchKernelGGL(k_huge_counts, dim3(grid_for(H, 256)), dim3(256), 0, st, W.hugelist, H, rowfirst,
                        rowlast, W.cnt);
     SPC_LAUNCH_CHECK(ctx, "huge reduce");
+    }
   }
   {
     TimedScope ts(ctx, "contract_rowptr", (double)n_c);
@@ -844,8 +945,13 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
   SPC_HIP(ctx, hipMemcpyAsync(&nnz_c, out->row_ptr + n_c, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   SPC_HIP(ctx, hipMemcpyAsync(hinfo, info, sizeof(unsigned long long) * I_NINFO,
                               hipMemcpyDeviceToHost, st));
+  hinfo[I_NINFO] = 0;
+  if (ctx->scan_state)
+    SPC_HIP(ctx, hipMemcpyAsync(&hinfo[I_NINFO], ctx->scan_state + ctx->scan_cap - 1, sizeof(uint64_t),
+                                hipMemcpyDeviceToHost, st));
   SPC_HIP(ctx, hipStreamSynchronize(st));
-  if (hinfo[I_LBERR]) return set_error(ctx, SPC_EINVAL, "internal: look-back wait gave up");
+  if (hinfo[I_LBERR] || hinfo[I_NINFO])
+    return set_error(ctx, SPC_EINVAL, "internal: look-back wait gave up");
   if (nnz_c > out->nnz_cap)
     return set_error(ctx, SPC_ECAPACITY, "coarse graph needs %lld entries, capacity %lld",
                      (long long)nnz_c, (long long)out->nnz_cap);

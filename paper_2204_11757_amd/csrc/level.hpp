@@ -70,6 +70,11 @@ enum Info : int {
   I_LBERR = 16,   // a look-back wait gave up (internal error)
   I_GUARD = 17,   // packed keys are guarded (not exact for every pair)
   I_ROUNDS = 18,  // spanning-forest rounds that merged something
+  I_FIN = 19,     // live edges read by root-lookup rounds
+  I_FKEPT = 20,   // live edges kept by root-lookup rounds
+  I_MIN = 21,     // live edges read by hooking rounds
+  I_KEYS = 22,    // exact per-edge records were written
+  I_MSF0 = 23,    // forest records before the current hooking round
   I_NINFO = 24
 };
 
@@ -82,90 +87,6 @@ __device__ __forceinline__ int64_t block_reserve(unsigned long long* counter, in
   int total;
   int incl = block_incl_scan<int, BS, false>(my, tmp, &total);
   if (threadIdx.x == 0) *sh_base = total ? atomicAdd(counter, (unsigned long long)total) : 0ull;
-  __syncthreads();
-  int64_t base = (int64_t)*sh_base + (incl - my);
-  __syncthreads();
-  return base;
-}
-
-// Stream compaction without a hot counter.  A single global counter that
-// every block bumps serialises all blocks of a launch on one address; a
-// decoupled look-back (Merrill and Garland, single-pass prefix scan with
-// decoupled look-back, 2016) lets tile b find the sum of the counts of
-// tiles 0..b-1 from its predecessors' published words instead.
-//
-// A state word is (epoch << 42) | (flag << 40) | value: flag 1 = the tile's
-// own count, 2 = the inclusive prefix through the tile.  Words of an older
-// epoch count as unpublished, so the array is zeroed once per level and
-// every launch takes a fresh epoch.  A tile waits only on lower tiles, which
-// the hardware dispatched before it and which publish before they wait, so
-// every wait ends; a bound on the polling turns a broken invariant into an
-// error flag instead of a hang.
-constexpr uint64_t LB_VMASK = (1ull << 40) - 1;
-constexpr uint32_t LB_MAX_EPOCH = (1u << 22) - 1;
-constexpr uint32_t LB_SPIN_LIMIT = 1u << 20;
-
-struct TileScan {
-  uint64_t* state;            // [tiles] words of this chain
-  uint32_t epoch;             // 1 .. LB_MAX_EPOCH, distinct per launch
-  unsigned long long* err;    // set to 1 when a wait gives up
-};
-
-__device__ __forceinline__ void lb_publish(uint64_t* p, uint32_t epoch, uint64_t flag, uint64_t v) {
-  __hip_atomic_store(p, ((uint64_t)epoch << 42) | (flag << 40) | (v & LB_VMASK), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Sum of the counts of tiles 0..tile-1 (one thread per chain).
-__device__ __forceinline__ uint64_t lb_exclusive(const TileScan& ts, int64_t tile, uint64_t count) {
-  if (tile == 0) {
-    lb_publish(&ts.state[0], ts.epoch, 2, count);
-    return 0;
-  }
-  lb_publish(&ts.state[tile], ts.epoch, 1, count);
-  uint64_t excl = 0;
-  int64_t p = tile - 1;
-  uint32_t spins = 0;
-  while (true) {
-    uint64_t s = __hip_atomic_load(&ts.state[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((uint32_t)(s >> 42) != ts.epoch) {
-      if (++spins > LB_SPIN_LIMIT) {
-        atomicOr(ts.err, 1ull);
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-      continue;
-    }
-    excl += s & LB_VMASK;
-    if (((s >> 40) & 3) == 2) break;
-    p--;
-  }
-  lb_publish(&ts.state[tile], ts.epoch, 2, excl + count);
-  return excl;
-}
-
-// Block-wide reservation of `my` consecutive slots per thread, positions in
-// tile order.  base_in (nullable) is added to every position: it is read
-// before the tile publishes, so it may be the same counter as total_out,
-// which the last tile sets to base_in + the sum of all counts.  All BS
-// threads must call it.  tmp: LDS int[BS/64]; sh_base: LDS scalar.
-template <int BS>
-__device__ __forceinline__ int64_t block_reserve_lb(const TileScan& ts, int64_t tile, bool last_tile,
-                                                    int my, const unsigned long long* base_in,
-                                                    unsigned long long* total_out,
-                                                    unsigned long long* sh_base, int* tmp) {
-  int total;
-  int incl = block_incl_scan<int, BS, false>(my, tmp, &total);
-  if (threadIdx.x == 0) {
-    uint64_t b0 = 0;
-    if (base_in) {
-      b0 = __hip_atomic_load(base_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __threadfence();   // the read completes before this tile publishes
-    }
-    uint64_t ex = b0 + lb_exclusive(ts, tile, (uint64_t)total);
-    *sh_base = ex;
-    if (last_tile) *total_out = ex + (uint64_t)total;
-  }
   __syncthreads();
   int64_t base = (int64_t)*sh_base + (incl - my);
   __syncthreads();
@@ -191,6 +112,7 @@ struct LevelWork {
   uint64_t* lo[2];           // [m] live edges: original endpoints
   uint64_t* msfP;            // [n]
   uint64_t* msfO;            // [n]
+  int32_t* msfC;             // [n]  root hooked by each forest edge
   int32_t* root;             // [n]
   int32_t* flag;             // [n+1]
   SelState* sel;
@@ -213,6 +135,7 @@ struct LevelWork {
   int32_t* hmrow;            // [n]  huge member -> huge row index
   int32_t* hmnode;           // [n]
   int64_t* hpos;             // [n+1] huge member -> gathered offset
+  int64_t* hmrs;             // [n]  huge member -> its first CSR position
   uint64_t* gkeyA;           // [nnz] (key, w) pairs, 16 bytes each
   uint64_t* gkeyB;           // [nnz]
 };
@@ -234,7 +157,8 @@ inline TileScan next_scan(spc_ctx* ctx, const LevelWork& W, int64_t off = 0) {
 
 struct LevelResult {
   int64_t n_c = 0, nnz_c = 0, msf = 0, rounds = 0, candidates = 0, maxcl = 0;
-  int key_mode = 0, key_bits = 0;
+  int key_mode = 0, key_bits = 0, bands = 0, keys_written = 0;
+  int64_t forest_in = 0, forest_kept = 0, merge_in = 0;
   double eps = 0.0;
 };
 

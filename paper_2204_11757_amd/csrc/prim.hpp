@@ -6,100 +6,206 @@
 
 namespace spc {
 
+// Stream compaction without a hot counter.  A single global counter that
+// every block bumps serialises all blocks of a launch on one address; a
+// decoupled look-back (Merrill and Garland, single-pass prefix scan with
+// decoupled look-back, 2016) lets tile b find the sum of the counts of
+// tiles 0..b-1 from its predecessors' published words instead.
+//
+// A state word is (epoch << 42) | (flag << 40) | value: flag 1 = the tile's
+// own count, 2 = the inclusive prefix through the tile.  Words of an older
+// epoch count as unpublished, so the array is zeroed once per level and
+// every launch takes a fresh epoch.  A tile waits only on lower tiles, which
+// the hardware dispatched before it and which publish before they wait, so
+// every wait ends; a bound on the polling turns a broken invariant into an
+// error flag instead of a hang.
+constexpr uint64_t LB_VMASK = (1ull << 40) - 1;
+constexpr uint32_t LB_MAX_EPOCH = (1u << 22) - 1;
+constexpr uint32_t LB_SPIN_LIMIT = 1u << 20;
+
+struct TileScan {
+  uint64_t* state;            // [tiles] words of this chain
+  uint32_t epoch;             // 1 .. LB_MAX_EPOCH, distinct per launch
+  unsigned long long* err;    // set to 1 when a wait gives up
+};
+
+__device__ __forceinline__ void lb_publish(uint64_t* p, uint32_t epoch, uint64_t flag, uint64_t v) {
+  __hip_atomic_store(p, ((uint64_t)epoch << 42) | (flag << 40) | (v & LB_VMASK), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum of the counts of tiles 0..tile-1, computed by one whole wavefront:
+// each probe reads the words of the 64 preceding tiles at once and stops at
+// the nearest inclusive prefix (positions before tile 0 read as an
+// inclusive prefix of 0).  Every lane returns the sum.
+__device__ __forceinline__ uint64_t lb_exclusive_wave(const TileScan& ts, int64_t tile, uint64_t count) {
+  int lane = lane_id();
+  if (tile == 0) {
+    if (lane == 0) lb_publish(&ts.state[0], ts.epoch, 2, count);
+    return 0;
+  }
+  if (lane == 0) lb_publish(&ts.state[tile], ts.epoch, 1, count);
+  uint64_t excl = 0;
+  int64_t p0 = tile - 1;
+  uint32_t spins = 0;
+  while (true) {
+    int64_t p = p0 - lane;
+    uint64_t s = p >= 0 ? __hip_atomic_load(&ts.state[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                        : (((uint64_t)ts.epoch << 42) | (2ull << 40));
+    bool pub = (uint32_t)(s >> 42) == ts.epoch;
+    bool incl = pub && ((s >> 40) & 3) == 2;
+    uint64_t incl_mask = __ballot(incl);
+    uint64_t unpub_mask = __ballot(!pub);
+    int first = incl_mask ? __ffsll((long long)incl_mask) - 1 : WAVE;
+    uint64_t need = (first >= WAVE - 1) ? ~0ull : ((2ull << first) - 1);
+    if (unpub_mask & need) {
+      if (++spins > LB_SPIN_LIMIT) {
+        if (lane == 0) atomicOr(ts.err, 1ull);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    excl += wave_sum<uint64_t>(lane <= first ? (s & LB_VMASK) : 0ull);
+    if (first < WAVE) break;
+    p0 -= WAVE;
+  }
+  if (lane == 0) lb_publish(&ts.state[tile], ts.epoch, 2, excl + count);
+  return excl;
+}
+
+// Single-thread form for callers that run one chain per lane.
+__device__ __forceinline__ uint64_t lb_exclusive(const TileScan& ts, int64_t tile, uint64_t count) {
+  if (tile == 0) {
+    lb_publish(&ts.state[0], ts.epoch, 2, count);
+    return 0;
+  }
+  lb_publish(&ts.state[tile], ts.epoch, 1, count);
+  uint64_t excl = 0;
+  int64_t p = tile - 1;
+  uint32_t spins = 0;
+  while (true) {
+    uint64_t s = __hip_atomic_load(&ts.state[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((uint32_t)(s >> 42) != ts.epoch) {
+      if (++spins > LB_SPIN_LIMIT) {
+        atomicOr(ts.err, 1ull);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    excl += s & LB_VMASK;
+    if (((s >> 40) & 3) == 2) break;
+    p--;
+  }
+  lb_publish(&ts.state[tile], ts.epoch, 2, excl + count);
+  return excl;
+}
+
+// Block-wide reservation of `my` consecutive slots per thread, positions in
+// tile order.  base_in (nullable) is added to every position: it is read
+// before the tile publishes, so it may be the same counter as total_out,
+// which the last tile sets to base_in + the sum of all counts.  All BS
+// threads must call it.  tmp: LDS int[BS/64]; sh_base: LDS scalar.
+template <int BS>
+__device__ __forceinline__ int64_t block_reserve_lb(const TileScan& ts, int64_t tile, bool last_tile,
+                                                    int my, const unsigned long long* base_in,
+                                                    unsigned long long* total_out,
+                                                    unsigned long long* sh_base, int* tmp) {
+  int total;
+  int incl = block_incl_scan<int, BS, false>(my, tmp, &total);
+  if (threadIdx.x < WAVE) {
+    uint64_t b0 = 0;
+    if (base_in) {
+      b0 = __hip_atomic_load(base_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();   // the read completes before this tile publishes
+    }
+    uint64_t ex = b0 + lb_exclusive_wave(ts, tile, (uint64_t)total);
+    if (threadIdx.x == 0) {
+      *sh_base = ex;
+      if (last_tile) *total_out = ex + (uint64_t)total;
+    }
+  }
+  __syncthreads();
+  int64_t base = (int64_t)*sh_base + (incl - my);
+  __syncthreads();
+  return base;
+}
+
 // ===========================================================================
 // exclusive scan: out[i] = sum in[0..i), out[n] = total (out has n+1 slots).
-// reduce-then-scan over <= SCAN_MAXB contiguous chunks.
+// One pass over tiles of SCAN_TILE items chained by the decoupled look-back
+// of the compaction (level.hpp): sums travel in the 40-bit value field, so
+// the inputs must be non-negative with a total below 2^40 (every scan here
+// counts entries or adds integer weights, all below 2^31); a larger total
+// sets the error flag.
 // ===========================================================================
 constexpr int SCAN_BS = 256;
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = SCAN_BS * SCAN_ITEMS;
-constexpr int SCAN_MAXB = 1024;
+constexpr int SCAN_MAXB = 1024;   // size of the callers' legacy scratch (unused)
 
 template <typename T>
-__global__ void __launch_bounds__(SCAN_BS)
-    k_scan_reduce(const T* __restrict__ in, int64_t n, int64_t chunk, T* __restrict__ partial) {
-  __shared__ T tmp[SCAN_BS / WAVE];
-  int64_t s = (int64_t)blockIdx.x * chunk;
-  int64_t e = s + chunk < n ? s + chunk : n;
-  T acc = 0;
-  for (int64_t i = s + threadIdx.x; i < e; i += SCAN_BS) acc += in[i];
-  acc = wave_sum(acc);
-  if (lane_id() == 0) tmp[threadIdx.x / WAVE] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    T t = 0;
-    for (int w = 0; w < SCAN_BS / WAVE; w++) t += tmp[w];
-    partial[blockIdx.x] = t;
-  }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(1024) k_scan_partials(T* partial, int nb) {
-  __shared__ T tmp[1024 / WAVE];
-  int t = threadIdx.x;
-  T v = t < nb ? partial[t] : (T)0;
-  T tot;
-  T inc = block_incl_scan<T, 1024, false>(v, tmp, &tot);
-  if (t < nb) partial[t] = inc - v;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(SCAN_BS)
-    k_scan_apply(const T* in, T* out, int64_t n, int64_t chunk,
-                 const T* __restrict__ partial, int nb) {
+__global__ void __launch_bounds__(SCAN_BS) k_scan_lb(const T* in, T* out, int64_t n, TileScan ts) {
   __shared__ T buf[SCAN_TILE];
   __shared__ T tmp[SCAN_BS / WAVE];
-  int64_t s = (int64_t)blockIdx.x * chunk;
-  int64_t e = s + chunk < n ? s + chunk : n;
-  T carry = partial[blockIdx.x];
+  __shared__ T sh_excl;
   int tid = threadIdx.x;
-  for (int64_t base = s; base < e; base += SCAN_TILE) {
+  int64_t tile = blockIdx.x;
+  int64_t base = tile * SCAN_TILE;
 #pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; i++) {
-      int64_t g = base + i * SCAN_BS + tid;
-      buf[i * SCAN_BS + tid] = g < e ? in[g] : (T)0;
-    }
-    __syncthreads();
-    T loc[SCAN_ITEMS];
-    T run = 0;
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; i++) {
-      loc[i] = run;
-      run += buf[tid * SCAN_ITEMS + i];
-    }
-    T tot;
-    T inc = block_incl_scan<T, SCAN_BS, false>(run, tmp, &tot);
-    T pre = carry + inc - run;
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; i++) buf[tid * SCAN_ITEMS + i] = pre + loc[i];
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; i++) {
-      int64_t g = base + i * SCAN_BS + tid;
-      if (g < e) out[g] = buf[i * SCAN_BS + tid];
-    }
-    carry += tot;
-    __syncthreads();
+  for (int i = 0; i < SCAN_ITEMS; i++) {
+    int64_t g = base + i * SCAN_BS + tid;
+    buf[i * SCAN_BS + tid] = g < n ? in[g] : (T)0;
   }
-  if (blockIdx.x == nb - 1 && tid == 0) out[n] = carry;
+  __syncthreads();
+  T loc[SCAN_ITEMS];
+  T run = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; i++) {
+    loc[i] = run;
+    run += buf[tid * SCAN_ITEMS + i];
+  }
+  T tot;
+  T inc = block_incl_scan<T, SCAN_BS, false>(run, tmp, &tot);
+  if (tid < WAVE) {
+    uint64_t ex = lb_exclusive_wave(ts, tile, (uint64_t)tot);
+    if (tid == 0) {
+      if ((uint64_t)tot > LB_VMASK || ex + (uint64_t)tot > LB_VMASK) atomicOr(ts.err, 1ull);
+      sh_excl = (T)ex;
+      if (tile == gridDim.x - 1) out[n] = (T)(ex + (uint64_t)tot);
+    }
+  }
+  __syncthreads();
+  T pre = sh_excl + inc - run;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; i++) buf[tid * SCAN_ITEMS + i] = pre + loc[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; i++) {
+    int64_t g = base + i * SCAN_BS + tid;
+    if (g < n) out[g] = buf[i * SCAN_BS + tid];
+  }
 }
 
-// Host wrapper.  partial: device scratch of SCAN_MAXB elements.  in may
-// equal out (the in-place case reads each tile before writing it).
+// Makes room for `words` look-back words in the context (zeroed) and
+// returns a fresh epoch; 0 on allocation failure.
+uint32_t scan_state_reserve(spc_ctx* ctx, int64_t words);
+
+// Host wrapper.  `partial` is unused (kept for callers' scratch layout).
+// in may equal out (each tile reads all of its items before writing).
 template <typename T>
 int exclusive_scan(spc_ctx* ctx, const T* in, T* out, int64_t n, T* partial) {
+  (void)partial;
   if (n <= 0) {
     SPC_HIP(ctx, hipMemsetAsync(out, 0, sizeof(T), ctx->stream));
     return SPC_OK;
   }
   int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
-  int nb = (int)(tiles < SCAN_MAXB ? tiles : SCAN_MAXB);
-  int64_t chunk = ((tiles + nb - 1) / nb) * SCAN_TILE;
-  nb = (int)((n + chunk - 1) / chunk);
-  hipLaunchKernelGGL(k_scan_reduce<T>, dim3(nb), dim3(SCAN_BS), 0, ctx->stream, in, n, chunk, partial);
-  hipLaunchKernelGGL(k_scan_partials<T>, dim3(1), dim3(1024), 0, ctx->stream, partial, nb);
-  hipLaunchKernelGGL(k_scan_apply<T>, dim3(nb), dim3(SCAN_BS), 0, ctx->stream, in, out, n, chunk,
-                     partial, nb);
+  uint32_t epoch = scan_state_reserve(ctx, tiles);
+  if (!epoch) return ctx->err_code ? ctx->err_code : SPC_ENOMEM;
+  TileScan ts{ctx->scan_state, epoch, (unsigned long long*)(ctx->scan_state + ctx->scan_cap - 1)};
+  hipLaunchKernelGGL(k_scan_lb<T>, dim3((unsigned)tiles), dim3(SCAN_BS), 0, ctx->stream, in, out, n, ts);
   SPC_LAUNCH_CHECK(ctx, "exclusive_scan");
   return SPC_OK;
 }
@@ -113,13 +219,14 @@ constexpr int SEL_DIGIT = 11;
 constexpr int SEL_BINS = 1 << SEL_DIGIT;
 
 struct SelState {
-  unsigned long long prefix, mask, k, pad;
+  unsigned long long prefix, mask, k;
+  unsigned int done, pad;   // blocks finished with the current digit
   unsigned int hist[SEL_BINS];
 };
 
 __global__ void k_sel_init(SelState* st, const unsigned long long* k_dev, unsigned long long k_host);
-__global__ void k_sel_hist(const uint64_t* __restrict__ keys, const unsigned long long* cnt_dev,
-                           int64_t cnt_host, SelState* st, int shift, int width);
+__global__ void k_sel_pass(const uint64_t* __restrict__ keys, const unsigned long long* cnt_dev,
+                           int64_t cnt_host, SelState* st, int shift, int width, int fused);
 __global__ void k_sel_pick(SelState* st, int shift, int width);
 
 // After the call st->prefix holds the selected key (device memory).

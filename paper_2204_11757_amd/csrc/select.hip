@@ -44,6 +44,7 @@ void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W) {
   }
   W.msfP = A.take<uint64_t>(n);
   W.msfO = A.take<uint64_t>(n);
+  W.msfC = A.take<int32_t>(n);
   W.root = A.take<int32_t>(n);
   W.flag = A.take<int32_t>(n + 1);
   W.sel = A.take<SelState>(1);
@@ -65,6 +66,7 @@ void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W) {
   W.hmrow = A.take<int32_t>(n);
   W.hmnode = A.take<int32_t>(n);
   W.hpos = A.take<int64_t>(n + 1);
+  W.hmrs = A.take<int64_t>(n);
   W.gkeyA = A.take<uint64_t>(2 * nnz + 8);
   W.gkeyB = A.take<uint64_t>(2 * nnz + 8);
 }
@@ -354,6 +356,7 @@ __global__ void __launch_bounds__(BS)
   if (MODE == 0 && write_keys < 0) {
     unsigned __int128 d2 = (unsigned __int128)info[I_DMAX] * info[I_DMAX];
     write_keys = (d2 >> 64) != 0 || d2 * d2 > ((unsigned __int128)1 << c) ? 1 : 0;
+    if (write_keys && blockIdx.x == 0 && threadIdx.x == 0) info[I_KEYS] = 1;
   }
   __shared__ int32_t srow[Lbs<TILE_S, BS>::SIZE];
   __shared__ int64_t sh[2];
@@ -602,7 +605,8 @@ __global__ void __launch_bounds__(BS)
     k_bv_merge(const uint64_t* __restrict__ lr, const uint64_t* __restrict__ lp,
                const uint64_t* __restrict__ lo, const unsigned long long* cnt,
                const uint64_t* __restrict__ best, int32_t* parent, uint64_t* __restrict__ msfP,
-               uint64_t* __restrict__ msfO, unsigned long long* msfcnt, int64_t msf_cap,
+               uint64_t* __restrict__ msfO, int32_t* __restrict__ msfC, unsigned long long* msfcnt,
+               int64_t msf_cap,
                const KeyND* __restrict__ keys, const unsigned long long* guard, int ebits, int* viol,
                TileScan ts, unsigned long long* rounds) {
   __shared__ int stmp[BS / WAVE];
@@ -611,10 +615,14 @@ __global__ void __launch_bounds__(BS)
   int tid = threadIdx.x;
   int64_t base = (int64_t)blockIdx.x * BV_CHUNK;
   if (base >= n) return;
-  if (blockIdx.x == 0 && tid == 0) atomicAdd(rounds, 1ull);
+  if (blockIdx.x == 0 && tid == 0) {   // rounds points at info[I_ROUNDS]
+    atomicAdd(rounds, 1ull);
+    atomicAdd(rounds + (I_MIN - I_ROUNDS), (unsigned long long)n);
+  }
   if (keys && !*guard) keys = nullptr;
   uint32_t chosen = 0;
   int nc = 0;
+  int32_t hooked[BV_PER];
   for (int i = 0; i < BV_PER; i++) {
     int64_t idx = base + tid + i * BS;
     if (idx >= n) break;
@@ -634,6 +642,7 @@ __global__ void __launch_bounds__(BS)
       int32_t child = (ca && cb) ? (a > b ? a : b) : (ca ? a : b);
       int32_t to = (ca && cb) ? (a > b ? b : a) : (ca ? b : a);
       __hip_atomic_store(&parent[child], to, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      hooked[i] = child;
       chosen |= 1u << i;
       nc++;
     }
@@ -646,8 +655,30 @@ __global__ void __launch_bounds__(BS)
     if (pos < msf_cap) {  // a forest has fewer than n edges
       msfP[pos] = lp[idx];
       msfO[pos] = lo[idx];
+      msfC[pos] = hooked[i];
     }
     pos++;
+  }
+}
+
+// Pointer jumping after a merge round, over the roots that round hooked
+// (forest records [*lo, *hi)): each follows its parent chain to the root,
+// picking up the shortcuts the others write concurrently.  Every other node
+// points at a root of the previous round, so its next lookup takes at most
+// two steps.  Hooking in edge order can chain roots deeply (on a bipartite
+// mesh every score ties and each node hooks to its lowest-numbered
+// neighbour); without this the next round's lookups would walk those chains.
+__global__ void k_shortcut(int32_t* parent, const int32_t* __restrict__ hooked,
+                           const unsigned long long* lo, const unsigned long long* hi) {
+  int64_t i = (int64_t)*lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)*hi) return;
+  int32_t x = hooked[i];
+  int32_t p = __hip_atomic_load(&parent[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  while (true) {
+    int32_t gp = __hip_atomic_load(&parent[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (gp == p) break;
+    p = gp;
+    __hip_atomic_store(&parent[x], p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -660,7 +691,8 @@ __global__ void __launch_bounds__(BS)
                     const uint64_t* __restrict__ lo_in, const unsigned long long* cnt_in,
                     uint64_t* __restrict__ lr_out, uint64_t* __restrict__ lp_out,
                     uint64_t* __restrict__ lo_out, unsigned long long* cnt_out, uint64_t* cur,
-                    uint64_t* nxt, int32_t* parent, TileScan ts) {
+                    uint64_t* nxt, int32_t* parent, TileScan ts, unsigned long long* stats,
+                    const unsigned long long* msf_now, unsigned long long* msf_mark) {
   __shared__ int stmp[BS / WAVE];
   __shared__ unsigned long long sbase;
   int64_t n = (int64_t)*cnt_in;
@@ -688,8 +720,13 @@ __global__ void __launch_bounds__(BS)
       nk++;
     }
   }
-  int64_t pos = block_reserve_lb<BS>(ts, blockIdx.x, base + BV_CHUNK >= n, nk, nullptr, cnt_out,
-                                     &sbase, stmp);
+  bool last = base + BV_CHUNK >= n;
+  int64_t pos = block_reserve_lb<BS>(ts, blockIdx.x, last, nk, nullptr, cnt_out, &sbase, stmp);
+  if (last && tid == 0) {
+    atomicAdd(&stats[0], (unsigned long long)n);   // info[I_FIN]
+    atomicAdd(&stats[1], *cnt_out);                // info[I_FKEPT]
+    *msf_mark = *msf_now;                          // forest records before the next merge
+  }
   for (int i = 0; i < BV_PER; i++) {
     if (!(keep >> i & 1u)) continue;
     int64_t idx = base + tid + i * BS;
@@ -791,72 +828,101 @@ __global__ void k_sel_init(SelState* st, const unsigned long long* k_dev, unsign
     st->prefix = 0;
     st->mask = 0;
     st->k = k_dev ? *k_dev : k_host;
+    st->done = 0;
   }
   for (int b = t; b < SEL_BINS; b += blockDim.x) st->hist[b] = 0;
 }
 
-__global__ void __launch_bounds__(256)
-    k_sel_hist(const uint64_t* __restrict__ keys, const unsigned long long* cnt_dev, int64_t cnt_host,
-               SelState* st, int shift, int width) {
-  __shared__ unsigned int h[SEL_BINS];
+// One digit: every block adds its histogram of the keys that match the
+// prefix so far into st->hist; then one block picks the bucket holding the
+// k-th key, narrows the prefix and clears the histogram.  Small grids pick
+// in the last block to finish (counted with an atomic after a fence); large
+// grids pick in a separate one-block launch, since a counter every block
+// bumps would serialise them.
+constexpr int SEL_BS = 256;
+constexpr int SEL_FUSE_MAX = 64;
+
+__device__ __forceinline__ void sel_pick_block(SelState* st, uint64_t prefix, uint64_t mask, int shift,
+                                               int width) {
+  __shared__ unsigned long long tmp[SEL_BS / WAVE];
+  int t = threadIdx.x;
   int nb = 1 << width;
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) h[b] = 0;
+  // thread t owns bins [8t, 8t + 8)
+  constexpr int PER = SEL_BINS / SEL_BS;
+  unsigned int c[PER];
+  unsigned long long mine = 0;
+#pragma unroll
+  for (int q = 0; q < PER; q++) {
+    int b = PER * t + q;
+    c[q] = b < nb ? __hip_atomic_load(&st->hist[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+    mine += c[q];
+  }
+  unsigned long long tot;
+  unsigned long long before = block_incl_scan<unsigned long long, SEL_BS, false>(mine, tmp, &tot) - mine;
+  unsigned long long k = st->k;
+  __syncthreads();
+  if (k >= before && k < before + mine) {
+    unsigned long long acc = before;
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+      if (k >= acc && k < acc + c[q]) {
+        st->k = k - acc;
+        st->prefix = prefix | ((unsigned long long)(PER * t + q) << shift);
+        st->mask = mask | ((unsigned long long)(nb - 1) << shift);
+      }
+      acc += c[q];
+    }
+  }
+  for (int b = t; b < SEL_BINS; b += SEL_BS) st->hist[b] = 0;
+  if (t == 0) st->done = 0;
+}
+
+__global__ void __launch_bounds__(SEL_BS)
+    k_sel_pass(const uint64_t* __restrict__ keys, const unsigned long long* cnt_dev, int64_t cnt_host,
+               SelState* st, int shift, int width, int fused) {
+  __shared__ unsigned int h[SEL_BINS];
+  __shared__ int last;
+  int t = threadIdx.x;
+  int nb = 1 << width;
+  for (int b = t; b < nb; b += SEL_BS) h[b] = 0;
   __syncthreads();
   int64_t n = cnt_dev ? (int64_t)*cnt_dev : cnt_host;
   uint64_t prefix = st->prefix, mask = st->mask;
   uint64_t dm = (uint64_t)(nb - 1);
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+  int64_t stride = (int64_t)gridDim.x * SEL_BS;
+  for (int64_t i = (int64_t)blockIdx.x * SEL_BS + t; i < n; i += stride) {
     uint64_t k = keys[i];
     if ((k & mask) == prefix) atomicAdd(&h[(k >> shift) & dm], 1u);
   }
   __syncthreads();
-  for (int b = threadIdx.x; b < nb; b += blockDim.x)
+  for (int b = t; b < nb; b += SEL_BS)
     if (h[b]) atomicAdd(&st->hist[b], h[b]);
+  if (!fused) return;
+  __threadfence();
+  __syncthreads();
+  if (t == 0) last = atomicAdd(&st->done, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  sel_pick_block(st, prefix, mask, shift, width);
 }
 
-__global__ void __launch_bounds__(1024) k_sel_pick(SelState* st, int shift, int width) {
-  __shared__ unsigned long long tmp[1024 / WAVE];
-  int t = threadIdx.x;
-  int nb = 1 << width;
-  // thread t owns bins 2t and 2t+1
-  unsigned long long c0 = (2 * t < nb) ? st->hist[2 * t] : 0;
-  unsigned long long c1 = (2 * t + 1 < nb) ? st->hist[2 * t + 1] : 0;
-  unsigned long long tot;
-  unsigned long long inc = block_incl_scan<unsigned long long, 1024, false>(c0 + c1, tmp, &tot);
-  unsigned long long before = inc - c0 - c1;
-  unsigned long long k = st->k;
-  __syncthreads();
-  int bucket = -1;
-  unsigned long long sub = 0;
-  if (k >= before && k < before + c0) {
-    bucket = 2 * t;
-    sub = before;
-  } else if (k >= before + c0 && k < before + c0 + c1) {
-    bucket = 2 * t + 1;
-    sub = before + c0;
-  }
-  __syncthreads();
-  if (bucket >= 0) {
-    st->k = k - sub;
-    st->prefix |= (unsigned long long)bucket << shift;
-    st->mask |= (unsigned long long)(nb - 1) << shift;
-  }
-  __syncthreads();
-  for (int b = t; b < SEL_BINS; b += blockDim.x) st->hist[b] = 0;
+__global__ void __launch_bounds__(SEL_BS) k_sel_pick(SelState* st, int shift, int width) {
+  sel_pick_block(st, st->prefix, st->mask, shift, width);
 }
 
 int radix_select(spc_ctx* ctx, const uint64_t* keys, const unsigned long long* cnt_dev,
                  int64_t cnt_bound, const unsigned long long* k_dev, unsigned long long k_host,
                  int bits, SelState* st) {
   hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, ctx->stream, st, k_dev, k_host);
-  int grid = grid_for(cnt_bound, 256 * 16, 4096);
+  int grid = grid_for(cnt_bound, SEL_BS * 16, 4096);
+  int fused = grid <= SEL_FUSE_MAX ? 1 : 0;
   for (int hi = bits; hi > 0;) {
     int lo = hi - SEL_DIGIT > 0 ? hi - SEL_DIGIT : 0;
     int width = hi - lo;
-    hipLaunchKernelGGL(k_sel_hist, dim3(grid), dim3(256), 0, ctx->stream, keys, cnt_dev, cnt_bound,
-                       st, lo, width);
-    hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(1024), 0, ctx->stream, st, lo, width);
+    hipLaunchKernelGGL(k_sel_pass, dim3(grid), dim3(SEL_BS), 0, ctx->stream, keys, cnt_dev, cnt_bound,
+                       st, lo, width, fused);
+    if (!fused) hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(SEL_BS), 0, ctx->stream, st, lo, width);
     hi = lo;
   }
   SPC_LAUNCH_CHECK(ctx, "radix_select");
@@ -931,8 +997,15 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, bool fused_fir
   if (fused_first && cnt > 0) {
     TimedScope ts(ctx, "forest_merge", (double)cnt);
     hipLaunchKernelGGL(k_bv_merge, dim3(grid_for(cnt, BV_CHUNK)), dim3(BS), 0, ctx->stream, W.lr[0],
-                       W.lp[0], W.lo[0], &info[I_LIVE0], cur, W.parent, W.msfP, W.msfO, &info[I_MSF], n,
-                       guard_keys, guard, ebits, viol, next_scan(ctx, W), &info[I_ROUNDS]);
+                       W.lp[0], W.lo[0], &info[I_LIVE0], cur, W.parent, W.msfP, W.msfO, W.msfC,
+                       &info[I_MSF], n, guard_keys, guard, ebits, viol, next_scan(ctx, W),
+                       &info[I_ROUNDS]);
+  }
+  if (fused_first && cnt > 0) {
+    // the band's first records start where the previous band's ended
+    TimedScope ts(ctx, "forest_shortcut", (double)cnt);
+    hipLaunchKernelGGL(k_shortcut, dim3(grid_for(cnt, 256)), dim3(256), 0, ctx->stream, W.parent, W.msfC,
+                       &info[I_MSF0], &info[I_MSF]);
     cur = W.bestB;
     nxt = W.bestA;
   }
@@ -950,14 +1023,20 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, bool fused_fir
         TimedScope ts(ctx, "forest_candidates", (double)bound);
         hipLaunchKernelGGL(k_bv_candidates, dim3(grid_for(bound, BV_CHUNK)), dim3(BS), 0, ctx->stream,
                            W.lr[in], W.lp[in], W.lo[in], &info[ci], W.lr[out], W.lp[out], W.lo[out],
-                           &info[co], cur, nxt, W.parent, next_scan(ctx, W));
+                           &info[co], cur, nxt, W.parent, next_scan(ctx, W), &info[I_FIN],
+                           &info[I_MSF], &info[I_MSF0]);
       }
       {
         TimedScope ts(ctx, "forest_merge", (double)bound);
         hipLaunchKernelGGL(k_bv_merge, dim3(grid_for(bound, BV_CHUNK)), dim3(BS), 0, ctx->stream,
                            W.lr[out], W.lp[out], W.lo[out], &info[co], cur, W.parent, W.msfP, W.msfO,
-                           &info[I_MSF], n, guard_keys, guard, ebits, viol, next_scan(ctx, W),
+                           W.msfC, &info[I_MSF], n, guard_keys, guard, ebits, viol, next_scan(ctx, W),
                            &info[I_ROUNDS]);
+      }
+      {
+        TimedScope ts(ctx, "forest_shortcut", (double)bound);
+        hipLaunchKernelGGL(k_shortcut, dim3(grid_for(bound, 256)), dim3(256), 0, ctx->stream, W.parent,
+                           W.msfC, &info[I_MSF0], &info[I_MSF]);
       }
       SPC_LAUNCH_CHECK(ctx, "forest round");
       uint64_t* t = cur;
@@ -993,6 +1072,8 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
     TimedScope ts(ctx, "score", (double)m);
     hipLaunchKernelGGL(k_score<0>, dim3(tiles_s), dim3(BS), 0, st, g, W.deg, W.lc, W.uptr, m, c,
                        ebits, W.Pc, W.samples, W.keysA, -1, info);
+  }
+  if (!rank) {
     hipLaunchKernelGGL(k_key_mode, dim3(1), dim3(1), 0, st, info, c);
     SPC_LAUNCH_CHECK(ctx, "score");
     R.key_bits = 64;
@@ -1063,6 +1144,7 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
     if (rc) return rc;
     done_cand += live0;
     R.candidates = done_cand;
+    R.bands = band + 1;
     R.msf = hinfo[I_MSF];
     if (R.msf >= k) break;
     if (all)
@@ -1104,11 +1186,14 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
   SPC_HIP(ctx, hipMemsetAsync(W.lbstate, 0, sizeof(uint64_t) * (size_t)ctx->lb_words, st));
 
   // A1 (long rows on a grid-stride launch that reads their count on device)
+  int nb = grid_for(n, DEG_ROWS);
   {
     TimedScope ts(ctx, "degree", (double)n);
-    int nb = grid_for(n, DEG_ROWS);
     hipLaunchKernelGGL(k_degree, dim3(nb), dim3(BS), 0, st, g, W.deg, W.lc, W.uptr, W.bestA, W.bestB,
                        W.parent, W.longrows, W.degpart, info);
+  }
+  {
+    TimedScope ts(ctx, "degree_aux", (double)n);
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, st, W.degpart, (int64_t)nb, &info[I_TOTAL]);
     hipLaunchKernelGGL(k_degree_long, dim3(ctx->num_cus), dim3(BS), 0, st, g, W.longrows, W.deg, info);
   }
@@ -1139,6 +1224,8 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
     if (pass == 1) {
       rank = true;
       SPC_HIP(ctx, hipMemsetAsync(&info[I_MSF], 0, sizeof(unsigned long long), st));
+      SPC_HIP(ctx, hipMemsetAsync(&info[I_ROUNDS], 0, sizeof(unsigned long long) * (I_MSF0 - I_ROUNDS + 1),
+                                  st));
       SPC_HIP(ctx, hipMemsetAsync(&info[I_VIOL], 0, sizeof(unsigned long long), st));
       hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256)), dim3(256), 0, st, W.parent, n);
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestA, n, KEY_INF);
@@ -1171,6 +1258,10 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
     if (rc) return rc;
     R.key_mode = rank ? 1 : (hinfo[I_GUARD] ? 2 : 0);
     R.rounds = hinfo[I_ROUNDS];
+    R.forest_in = hinfo[I_FIN];
+    R.forest_kept = hinfo[I_FKEPT];
+    R.merge_in = hinfo[I_MIN];
+    R.keys_written = (rank || hinfo[I_KEYS]) ? 1 : 0;
     if (hinfo[I_VIOL] == 0) break;
     if (rank) return set_error(ctx, SPC_EINVAL, "internal: exact rank order flagged as inexact");
   }

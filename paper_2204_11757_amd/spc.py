@@ -56,7 +56,9 @@ class LevelStats(C.Structure):
                 ("nnz_out", C.c_int64), ("merges", C.c_int64), ("largest_cluster", C.c_int64),
                 ("boruvka_rounds", C.c_int64), ("candidate_edges", C.c_int64),
                 ("key_mode", C.c_int32), ("key_bits", C.c_int32), ("eps_max", C.c_double),
-                ("ms_total", C.c_float)]
+                ("ms_total", C.c_float), ("bands", C.c_int32), ("forest_in", C.c_int64),
+                ("forest_kept", C.c_int64), ("merge_in", C.c_int64), ("forest_edges", C.c_int64),
+                ("keys_written", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

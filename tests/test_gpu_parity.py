@@ -20,6 +20,7 @@ def P():
     yield spc
     spc.set_option("rank_order", 0)
     spc.set_option("full_forest", 0)
+    spc.set_option("huge_sort", 0)
 
 
 def say(*a):
@@ -124,6 +125,24 @@ def test_alternate_order_and_forest_paths_agree(P):
     finally:
         P.set_option("rank_order", 0)
         P.set_option("full_forest", 0)
+
+
+def test_huge_rows_sort_and_dense_paths(P):
+    # a giant super-node (bipartite grids tie every score) and power-law hubs
+    # give coarse rows above the block capacity; both contraction strategies
+    # for such rows must agree with the oracle
+    from meshgen import powerlaw_graph
+    cases = [(grid2d(64), 1024, "grid2d-64"),
+             (grid3d(20, ("uniform", 1, 16), seed=2), 125, "grid3d-20")]
+    gp = powerlaw_graph(20000, avg_deg=8.0, gamma=2.05, seed=5)
+    cases.append((gp, gp.n // 8, "powerlaw-20000"))
+    try:
+        for flag in (0, 1):
+            P.set_option("huge_sort", flag)
+            for g, n_c, name in cases:
+                check_hierarchy(P, g, n_c, 0, f"{name} huge_sort={flag}")
+    finally:
+        P.set_option("huge_sort", 0)
 
 
 def test_edge_cases(P):
