@@ -90,7 +90,7 @@ KERNEL_SYMBOL = {"score": "k_score<0>", "rowpass": "k_rowpass", "degree": "k_deg
                  "contract_block_rows": "k_contract_row<256, 4096>", "contract_pack": "k_pack"}
 # source file of each kernel: a stored counter reading is used only while
 # this file is unchanged
-KERNEL_SOURCE = {"score": "select.hip", "rowpass": "select.hip", "degree": "select.hip",
+KERNEL_SOURCE = {"score": "score.hip", "rowpass": "select.hip", "degree": "select.hip",
                  "forest_candidates": "select.hip", "forest_merge": "select.hip",
                  "contract_small": "contract.hip", "contract_reg32": "contract.hip",
                  "contract_wave_rows": "contract.hip", "contract_block_rows": "contract.hip",

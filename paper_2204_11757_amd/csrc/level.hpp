@@ -25,6 +25,8 @@ struct spc_hier {
 
 namespace spc {
 
+constexpr int BS = 256;   // block size of the selection kernels
+
 // Device view of an integer-path input graph.
 struct LevelIn {
   int64_t n, nnz;
@@ -39,6 +41,10 @@ struct LevelIn {
 struct KeyND {
   uint64_t N, D, e;
 };
+
+__device__ __forceinline__ bool exact_less(const KeyND& x, const KeyND& y) {
+  return (unsigned __int128)x.N * y.D < (unsigned __int128)y.N * x.D;
+}
 
 struct LessND {
   __device__ __forceinline__ bool operator()(const KeyND& a, const KeyND& b) const {
@@ -58,7 +64,7 @@ enum Info : int {
   I_MSF = 4,
   I_MID = 5,
   I_HUGE = 6,
-  I_LONG = 7,
+  I_SPARE7 = 7,   // unused
   I_BAD = 8,
   I_NC = 9,
   I_MAXCL = 10,
@@ -100,7 +106,6 @@ struct LevelWork {
   uint64_t* degpart;         // [n / 4096 + 2] per-block weight sums
   int32_t* lc;               // [n]  entries with col < row
   int64_t* uptr;             // [n+1] upper-edge prefix (edge ids)
-  int32_t* longrows;         // [n]
   uint64_t* P;               // [m]  order key per edge (sorted-rank order)
   uint64_t* Pc;              // [nnz] order key per CSR entry (both directions)
   uint64_t* samples;         // [m/64 + 2]
@@ -161,6 +166,17 @@ struct LevelResult {
   int64_t forest_in = 0, forest_kept = 0, merge_in = 0;
   double eps = 0.0;
 };
+
+// A2 and A3 launches (score.hip).  mode 0: packed keys into Pc and the
+// samples (exact records too when the key is not surely exact); mode 1:
+// exact records only, for the sorted-rank order.
+void launch_score(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t m, int c, int ebits,
+                  int mode);
+// rank order: P from the sorted exact records, mirrored into Pc
+void launch_rank_scatter(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t m,
+                         const KeyND* sorted);
+// info[I_EPS] = exact score of the forest edge whose key equals sel2's cutoff
+void launch_eps(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t msf_bound);
 
 // Steps A1-A4: degrees, scores, order, merge selection -> cluster_of.
 int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of, LevelWork& W,

@@ -1,0 +1,313 @@
+// A2 and A3 of a coarsening level: the exact score of every edge and its
+// order key, the sorted-rank scatter of the fallback order, and Theorem 2's
+// epsilon of the accepted merges.
+#include "level.hpp"
+
+namespace spc {
+
+// ---------------------------------------------------------------------------
+// A2: exact fitness N / D of one edge (u, v) with weight wuv.
+// D = d_u d_v and N = 2 D - 2 sum_{x in S(u) cap S(v)} min(a_ux d_v, a_vx d_u),
+// where S(x) is the support of row x including its diagonal.  The common
+// support is the intersection of the two CSR rows plus the diagonal
+// positions x = u (if self_w[u] > 0) and x = v (if self_w[v] > 0).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
+
+__device__ __forceinline__ uint64_t common_min_sum(const int32_t* __restrict__ col,
+                                                   const int32_t* __restrict__ w, int64_t as,
+                                                   int64_t ae, uint64_t fa, int64_t bs, int64_t be,
+                                                   uint64_t fb) {
+  // sum over x in both rows of min(w_a[x] * fa, w_b[x] * fb); rows ascending.
+  uint64_t M = 0;
+  int64_t la = ae - as, lb = be - bs;
+  if (la > 4 * lb && la > 32) {
+    // walk the short row b, galloping search in the long row a
+    int64_t lo = as;
+    for (int64_t j = bs; j < be && lo < ae; j++) {
+      int32_t x = col[j];
+      int64_t hi = ae;
+      while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (col[mid] < x) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo < ae && col[lo] == x) {
+        M += umin64((uint64_t)w[lo] * fa, (uint64_t)w[j] * fb);
+        lo++;
+      }
+    }
+    return M;
+  }
+  if (lb > 4 * la && lb > 32) {
+    int64_t lo = bs;
+    for (int64_t i = as; i < ae && lo < be; i++) {
+      int32_t x = col[i];
+      int64_t hi = be;
+      while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (col[mid] < x) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo < be && col[lo] == x) {
+        M += umin64((uint64_t)w[i] * fa, (uint64_t)w[lo] * fb);
+        lo++;
+      }
+    }
+    return M;
+  }
+  int64_t i = as, j = bs;
+  if (i < ae && j < be) {
+    int32_t x = col[i], y = col[j];
+    while (true) {
+      if (x < y) {
+        if (++i >= ae) break;
+        x = col[i];
+      } else if (x > y) {
+        if (++j >= be) break;
+        y = col[j];
+      } else {
+        M += umin64((uint64_t)w[i] * fa, (uint64_t)w[j] * fb);
+        if (++i >= ae || ++j >= be) break;
+        x = col[i];
+        y = col[j];
+      }
+    }
+  }
+  return M;
+}
+
+// position of u in row v (u < v, so it lies among v's lower entries)
+__device__ __forceinline__ int64_t mirror_pos(const LevelIn& g, const int32_t* __restrict__ lc,
+                                              int32_t v, int32_t u) {
+  int64_t lo = g.rp[v], hi = g.rp[v] + lc[v];
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (g.col[mid] < u) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Rows of at most RC entries are read into registers with all loads issued
+// at once (the common-support walk over global memory would chain one
+// dependent load per step); longer rows take the walk.
+constexpr int RC = 8;
+
+// Also returns jm, the CSR position of the mirror entry (v -> u).
+__device__ __forceinline__ void edge_score(const LevelIn& g, const uint64_t* __restrict__ deg,
+                                           const int32_t* __restrict__ lc, int32_t u, int32_t v,
+                                           int32_t wuv, uint64_t& N, uint64_t& D, int64_t& jm) {
+  int64_t au = g.rp[u], bu = g.rp[u + 1], av = g.rp[v], bv = g.rp[v + 1];
+  uint64_t du = deg[u], dv = deg[v];
+  uint64_t su = g.self ? (uint64_t)g.self[u] : 0, sv = g.self ? (uint64_t)g.self[v] : 0;
+  int64_t lu = bu - au, lv = bv - av;
+  D = du * dv;
+  uint64_t M = 0;
+  if (lu <= RC && lv <= RC) {
+    int32_t cu[RC], cv[RC];
+    uint32_t wu[RC], wv[RC];
+#pragma unroll
+    for (int k = 0; k < RC; k++) {
+      bool pu = k < lu, pv = k < lv;
+      cu[k] = pu ? g.col[au + k] : -1;   // distinct sentinels never match
+      wu[k] = pu ? (uint32_t)g.w[au + k] : 0u;
+      cv[k] = pv ? g.col[av + k] : -2;
+      wv[k] = pv ? (uint32_t)g.w[av + k] : 0u;
+    }
+    int below = 0;
+#pragma unroll
+    for (int k = 0; k < RC; k++) below += (k < lv && cv[k] < u) ? 1 : 0;
+    jm = av + below;
+#pragma unroll
+    for (int i = 0; i < RC; i++) {
+      uint32_t mw = 0;   // weight of cu[i] in row v (0: absent)
+#pragma unroll
+      for (int k = 0; k < RC; k++) mw = (cu[i] == cv[k]) ? wv[k] : mw;
+      if (mw) M += umin64((uint64_t)wu[i] * dv, (uint64_t)mw * du);
+    }
+  } else {
+    M = common_min_sum(g.col, g.w, au, bu, dv, av, bv, du);
+    jm = mirror_pos(g, lc, v, u);
+  }
+  if (su) M += umin64(su * dv, (uint64_t)wuv * du);   // x = u
+  if (sv) M += umin64((uint64_t)wuv * dv, sv * du);   // x = v
+  N = 2 * D - 2 * M;
+}
+
+// floor(N * 2^b / D) for N < 2^63, D < 2^62, b <= 61 (the result is below 2^62).
+__device__ __forceinline__ uint64_t fixed_key(uint64_t N, uint64_t D, int b) {
+  if ((N >> (63 - b)) == 0) {
+    uint64_t num = N << b;
+    if (num < (1ull << 53) && D < (1ull << 53)) {
+      // the correctly rounded quotient is at most one above the floor
+      uint64_t q = (uint64_t)((double)num / (double)D);
+      if (q * D > num) q--;
+      return q;
+    }
+    return num / D;
+  }
+  unsigned __int128 num = (unsigned __int128)N << b;
+  return (uint64_t)(num / D);
+}
+
+// ---------------------------------------------------------------------------
+// A2 + A3 fused with the first spanning-forest round: one thread per edge
+// (u < v) for 4 edges each; tiles of 1024 consecutive edge ids are mapped
+// to rows by a load-balanced search over the upper-entry prefix uptr.
+// ---------------------------------------------------------------------------
+constexpr int TILE_S = 1024;
+
+template <int MODE>  // 0: 64-bit key (+ optional exact records), 1: exact records only
+__global__ void __launch_bounds__(BS)
+    k_score(LevelIn g, const uint64_t* __restrict__ deg, const int32_t* __restrict__ lc,
+            const int64_t* __restrict__ uptr, int64_t m, int c, int ebits,
+            uint64_t* __restrict__ Pc, uint64_t* __restrict__ samples, KeyND* __restrict__ keys,
+            int write_keys, unsigned long long* info) {
+  // write_keys < 0: exact records only when the packed key is not exact
+  // for sure, i.e. when dmax^4 > 2^c
+  if (MODE == 0 && write_keys < 0) {
+    unsigned __int128 d2 = (unsigned __int128)info[I_DMAX] * info[I_DMAX];
+    write_keys = (d2 >> 64) != 0 || d2 * d2 > ((unsigned __int128)1 << c) ? 1 : 0;
+    if (write_keys && blockIdx.x == 0 && threadIdx.x == 0) info[I_KEYS] = 1;
+  }
+  __shared__ int32_t srow[Lbs<TILE_S, BS>::SIZE];
+  __shared__ int64_t sh[2];
+  __shared__ int32_t stmp[BS / WAVE];
+  __shared__ uint64_t sred[BS / WAVE];
+  int64_t e0 = (int64_t)blockIdx.x * TILE_S;
+  lbs_tile<TILE_S, BS>(uptr, g.n, e0, srow, sh, stmp);
+  int tid = threadIdx.x;
+  uint64_t dmx = 0;
+  constexpr int EPT = TILE_S / BS;
+  // locate all of this thread's edges first so their loads overlap
+  int32_t eu[EPT], ev[EPT], ew[EPT];
+  int64_t ej[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; i++) {
+    int k = tid + i * BS;
+    int64_t e = e0 + k;
+    eu[i] = e < m ? srow[Lbs<TILE_S, BS>::at(k)] : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; i++) {
+    int64_t e = e0 + tid + i * BS;
+    ej[i] = e < m ? g.rp[eu[i]] + lc[eu[i]] + (e - uptr[eu[i]]) : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; i++) {
+    int64_t e = e0 + tid + i * BS;
+    ev[i] = e < m ? g.col[ej[i]] : 0;
+    ew[i] = e < m ? g.w[ej[i]] : 0;
+  }
+  for (int i = 0; i < EPT; i++) {
+    int64_t e = e0 + tid + i * BS;
+    if (e >= m) break;
+    uint64_t N, D;
+    int64_t jm;
+    edge_score(g, deg, lc, eu[i], ev[i], ew[i], N, D, jm);
+    dmx = D > dmx ? D : dmx;
+    if (MODE == 0) {
+      uint64_t K = fixed_key(N, D, c);
+      uint64_t key = (K << ebits) | (uint64_t)e;
+      Pc[ej[i]] = key;   // entry (u -> v)
+      Pc[jm] = key;      // entry (v -> u)
+      if ((e & 63) == 0) samples[e >> 6] = key;
+    }
+    if (MODE == 1 || write_keys) keys[e] = KeyND{N, D, (uint64_t)e};
+  }
+  dmx = wave_max(dmx);
+  if (lane_id() == 0) sred[tid / WAVE] = dmx;
+  __syncthreads();
+  if (tid == 0) {
+    uint64_t a = 0;
+    for (int w = 0; w < BS / WAVE; w++) a = sred[w] > a ? sred[w] : a;
+    atomic_max_lazy(&info[I_DMAXE], (unsigned long long)a);
+  }
+}
+
+// rank order: P[e] = position of e in the exact sorted order
+__global__ void k_rank_scatter(const KeyND* __restrict__ sorted, int64_t m, uint64_t* __restrict__ P) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < m) P[sorted[r].e] = (uint64_t)r;
+}
+
+// ---------------------------------------------------------------------------
+// edge passes over 4096-edge tiles (16 edges per thread)
+// ---------------------------------------------------------------------------
+constexpr int TILE_F = 4096;
+constexpr int F_PER = TILE_F / BS;
+
+// rank order: the rank of edge e into both of its CSR entries
+__global__ void __launch_bounds__(BS)
+    k_rank_mirror(LevelIn g, const int32_t* __restrict__ lc, const int64_t* __restrict__ uptr,
+                  int64_t m, const uint64_t* __restrict__ P, uint64_t* __restrict__ Pc) {
+  __shared__ int32_t srow[Lbs<TILE_F, BS>::SIZE];
+  __shared__ int64_t sh[2];
+  __shared__ int32_t stmp[BS / WAVE];
+  int64_t e0 = (int64_t)blockIdx.x * TILE_F;
+  lbs_tile<TILE_F, BS>(uptr, g.n, e0, srow, sh, stmp);
+  for (int i = 0; i < F_PER; i++) {
+    int k = threadIdx.x + i * BS;
+    int64_t e = e0 + k;
+    if (e >= m) break;
+    int32_t u = srow[Lbs<TILE_F, BS>::at(k)];
+    int64_t j = g.rp[u] + lc[u] + (e - uptr[u]);
+    int32_t v = g.col[j];
+    uint64_t key = P[e];
+    Pc[j] = key;
+    Pc[mirror_pos(g, lc, v, u)] = key;
+  }
+}
+
+// Theorem 2's epsilon: the score of the heaviest accepted edge, which is
+// the forest edge whose key equals the cutoff.
+__global__ void k_eps(LevelIn g, const uint64_t* __restrict__ deg, const int32_t* __restrict__ lc,
+                      const uint64_t* __restrict__ msfP,
+                      const uint64_t* __restrict__ msfO, const unsigned long long* cnt,
+                      const SelState* st, double* out) {
+  int64_t n = (int64_t)*cnt;
+  uint64_t T = st->prefix;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    if (msfP[i] != T) continue;
+    uint64_t uv = msfO[i];
+    int32_t u = (int32_t)(uint32_t)uv, v = (int32_t)(uv >> 32);
+    int64_t lo = g.rp[u], hi = g.rp[u + 1];
+    while (lo < hi) {
+      int64_t mid = (lo + hi) >> 1;
+      if (g.col[mid] < v) lo = mid + 1;
+      else hi = mid;
+    }
+    uint64_t N, D;
+    int64_t jm;
+    edge_score(g, deg, lc, u, v, g.w[lo], N, D, jm);
+    *out = (double)N / (double)D;
+  }
+}
+
+void launch_score(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t m, int c, int ebits,
+                  int mode) {
+  int tiles = grid_for(m, TILE_S);
+  if (mode == 0)
+    hipLaunchKernelGGL(k_score<0>, dim3(tiles), dim3(BS), 0, ctx->stream, g, W.deg, W.lc, W.uptr, m, c,
+                       ebits, W.Pc, W.samples, W.keysA, -1, W.info);
+  else
+    hipLaunchKernelGGL(k_score<1>, dim3(tiles), dim3(BS), 0, ctx->stream, g, W.deg, W.lc, W.uptr, m, c,
+                       ebits, (uint64_t*)nullptr, (uint64_t*)nullptr, W.keysA, 1, W.info);
+}
+
+void launch_rank_scatter(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t m,
+                         const KeyND* sorted) {
+  hipLaunchKernelGGL(k_rank_scatter, dim3(grid_for(m, 256)), dim3(256), 0, ctx->stream, sorted, m, W.P);
+  hipLaunchKernelGGL(k_rank_mirror, dim3(grid_for(m, TILE_F)), dim3(BS), 0, ctx->stream, g, W.lc, W.uptr,
+                     m, W.P, W.Pc);
+}
+
+void launch_eps(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t msf_bound) {
+  double* deps = (double*)&W.info[I_EPS];
+  hipLaunchKernelGGL(k_eps, dim3(grid_for(msf_bound, 256, ctx->num_cus * 4)), dim3(256), 0, ctx->stream, g,
+                     W.deg, W.lc, W.msfP, W.msfO, &W.info[I_MSF], W.sel2, deps);
+}
+
+}  // namespace spc
