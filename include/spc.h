@@ -191,6 +191,48 @@ int spc_lift(spc_ctx* ctx, const spc_hier* h, int from_lvl, int to_lvl, int mode
 int spc_spectral_error(spc_ctx* ctx, const spc_hier* h, int lvl, const double* U,
                        const double* lambda, int k, double* R, double* loss);
 
+/* Composed cluster map of level lvl: cmap[x] (device int32[n0]) is the
+ * level-lvl super-node holding input node x (lvl = 0: the identity). */
+int spc_hier_cluster_map(spc_ctx* ctx, const spc_hier* h, int lvl, int32_t* cmap);
+
+/* Spectral error (as spc_spectral_error) of an explicit coarse graph, e.g.
+ * one whose FP64 weights are being refined after coarsening.  coarse:
+ * device graph with SPC_W_I32 or SPC_W_F64 weights, its size[] the number
+ * of input nodes per super-node; cmap: device int32[n0], input node ->
+ * super-node of coarse.  Writes R (nullable) and the host loss.
+ * Synchronises. */
+int spc_spectral_error_graph(spc_ctx* ctx, const spc_graph* coarse, const int32_t* cmap, int64_t n0,
+                             const double* U, const double* lambda, int k, double* R, double* loss);
+
+/* Gradient of that loss with respect to the coarse weights.  The weight of
+ * an undirected coarse edge {a, b} is one parameter held at both CSR
+ * entries (a, b) and (b, a); d_wc[j] (device double[nnz]) receives
+ * d loss / d w_ab at both of them, so a step that updates both entries
+ * alike keeps the graph symmetric.  d_selfc (device double[n_c]) receives
+ * d loss / d self_w[a].  With z = W_c t:
+ *   d(t^T W_c t)/d w_ab   = 2 t_a t_b - t_a z_a / d_a - t_b z_b / d_b,
+ *   d(t^T W_c t)/d self_a = t_a^2 - t_a z_a / d_a,
+ * and d loss / d(t_i^T W_c t_i) = -2 (R_i - lambda_i).  Stream-ordered. */
+int spc_spectral_error_backward(spc_ctx* ctx, const spc_graph* coarse, const int32_t* cmap, int64_t n0,
+                                const double* U, const double* lambda, int k, double* d_wc,
+                                double* d_selfc);
+
+/* Entry map of a contraction (Definition 1): for every fine CSR entry j of
+ * `fine` (device int32[nnz]), the position of its coarse entry
+ * (c(x), c(y)) in `coarse`, or -1 - c(x) when c(x) = c(y) (the entry adds
+ * to that super-node's self-loop).  Stream-ordered. */
+int spc_entry_map(spc_ctx* ctx, const spc_graph* fine, const int32_t* cluster_of,
+                  const spc_graph* coarse, int32_t* entry_map);
+
+/* Adjoint of the contraction of Definition 1 (coarse weights are sums of
+ * fine weights, so their adjoint is a gather): d_wf[j] = d_wc[map[j]] or
+ * d_selfc[-1 - map[j]]; when d_selff is non-NULL, d_selff[x] =
+ * d_selfc[cluster_of[x]] (fine self-loops add to their super-node's).
+ * All device double arrays.  Stream-ordered. */
+int spc_contract_backward(spc_ctx* ctx, const int32_t* entry_map, const int32_t* cluster_of,
+                          int64_t nnz_f, int64_t n_f, const double* d_wc, const double* d_selfc,
+                          double* d_wf, double* d_selff);
+
 /* Host-side structural validation of a graph held in HOST memory: sorted
  * unique columns, no diagonal entries, symmetric weights, positive
  * weights, and the integer total bound.  No GPU needed. */

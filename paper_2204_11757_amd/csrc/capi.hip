@@ -93,16 +93,16 @@ uint32_t scan_state_reserve(spc_ctx* ctx, int64_t words) {
   return ++ctx->scan_epoch;
 }
 
-static int plan_and_bind(spc_ctx* ctx, int64_t n, int64_t nnz, LevelWork& W) {
+static int plan_and_bind(spc_ctx* ctx, int64_t n, int64_t nnz, LevelWork& W, bool fp) {
   Arena count;
   count.counting = true;
-  plan_level(count, n, nnz, W);
+  plan_level(count, n, nnz, W, fp);
   int rc = ensure_workspace(ctx, count.off + 256);
   if (rc) return rc;
   Arena real;
   real.base = (char*)ctx->ws;
   real.cap = ctx->ws_cap;
-  plan_level(real, n, nnz, W);
+  plan_level(real, n, nnz, W, fp);
   return SPC_OK;
 }
 
@@ -128,10 +128,34 @@ static int check_graph(spc_ctx* ctx, const spc_graph* g) {
     return set_error(ctx, SPC_EINVAL, "nnz=%lld must be even and below 2^31", (long long)g->nnz);
   if (!g->row_ptr || (g->nnz > 0 && (!g->col || !g->w)))
     return set_error(ctx, SPC_EINVAL, "graph arrays are NULL");
-  if (g->wtype != SPC_W_I32)
-    return set_error(ctx, SPC_EINVAL, "weight type %d is not supported by this entry point",
-                     (int)g->wtype);
+  if (g->wtype != SPC_W_I32 && g->wtype != SPC_W_F32 && g->wtype != SPC_W_F64)
+    return set_error(ctx, SPC_EINVAL, "unknown weight type %d", (int)g->wtype);
   return SPC_OK;
+}
+
+static LevelInF level_in_f(const spc_graph* g) {
+  LevelInF L;
+  L.n = g->n;
+  L.nnz = g->nnz;
+  L.rp = g->row_ptr;
+  L.col = g->col;
+  L.w = g->w;
+  L.w32 = g->wtype == SPC_W_F32 ? 1 : 0;
+  L.self = (const double*)g->self_w;
+  L.size = g->size;
+  return L;
+}
+
+// identity level of a floating-point graph: weights widened to FP64
+__global__ void k_identity_fp(const void* __restrict__ w, int w32, int64_t nnz, const double* __restrict__ self_in,
+                              const int32_t* __restrict__ size_in, int64_t n, double* __restrict__ w_out,
+                              double* __restrict__ self_out, int32_t* __restrict__ size_out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nnz) w_out[i] = w32 ? (double)((const float*)w)[i] : ((const double*)w)[i];
+  if (i < n) {
+    self_out[i] = self_in ? self_in[i] : 0.0;
+    size_out[i] = size_in ? size_in[i] : 1;
+  }
 }
 
 static LevelIn level_in(const spc_graph* g) {
@@ -163,14 +187,36 @@ static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* clus
     SPC_HIP(ctx, hipEventCreate(&e1));
     SPC_HIP(ctx, hipEventRecord(e0, ctx->stream));
   }
+  bool fp = g->wtype != SPC_W_I32;
   LevelIn L = level_in(g);
+  LevelInF LF = level_in_f(g);
+  if (fp) {
+    L.w = nullptr;      // the structure only: every weight read goes through LF
+    L.self = nullptr;
+  }
   LevelWork W;
   LevelResult R;
-  rc = plan_and_bind(ctx, g->n, g->nnz, W);
+  rc = plan_and_bind(ctx, g->n, g->nnz, W, fp);
   if (rc) return rc;
-  rc = select_level(ctx, L, t, cluster_of, W, R);
+  rc = select_level(ctx, L, t, cluster_of, W, R, fp ? &LF : nullptr);
   if (rc) return rc;
-  if (R.n_c == g->n) {
+  if (fp && R.n_c == g->n) {
+    if (out->nnz_cap < g->nnz) return set_error(ctx, SPC_ECAPACITY, "nnz_cap too small");
+    SPC_HIP(ctx, hipMemcpyAsync(out->row_ptr, g->row_ptr, sizeof(int64_t) * (g->n + 1),
+                                hipMemcpyDeviceToDevice, ctx->stream));
+    if (g->nnz)
+      SPC_HIP(ctx, hipMemcpyAsync(out->col, g->col, sizeof(int32_t) * g->nnz, hipMemcpyDeviceToDevice,
+                                  ctx->stream));
+    hipLaunchKernelGGL(k_identity_fp, dim3(grid_for(std::max(g->n, g->nnz), 256)), dim3(256), 0, ctx->stream,
+                       g->w, LF.w32, g->nnz, LF.self, g->size, g->n, (double*)out->w, (double*)out->self_w,
+                       out->size);
+    SPC_LAUNCH_CHECK(ctx, "identity");
+    R.nnz_c = g->nnz;
+    R.maxcl = 1;
+  } else if (fp) {
+    rc = contract_level_fp(ctx, LF, cluster_of, R.n_c, out, W, R);
+    if (rc) return rc;
+  } else if (R.n_c == g->n) {
     // identity: copy the graph
     if (out->nnz_cap < g->nnz) return set_error(ctx, SPC_ECAPACITY, "nnz_cap too small");
     SPC_HIP(ctx, hipMemcpyAsync(out->row_ptr, g->row_ptr, sizeof(int64_t) * (g->n + 1),
@@ -376,14 +422,17 @@ int spc_coarsen_to(spc_ctx* ctx, const spc_graph* g, int64_t n_c, int schedule, 
   h->n0 = g->n;
   spc_graph cur = *g;
   int64_t n = g->n;
+  bool fp = g->wtype != SPC_W_I32;
+  size_t wsz = fp ? sizeof(double) : sizeof(int32_t);
   while (n > n_c) {
     int64_t t = (schedule == 1) ? n_c : std::max(n_c, (n + 1) / 2);
     spc_hier::Level L;
     L.n_prev = n;
+    L.wtype = fp ? SPC_W_F64 : SPC_W_I32;
     L.rp = (int64_t*)dev_alloc(ctx, sizeof(int64_t) * (t + 1));
     L.col = (int32_t*)dev_alloc(ctx, sizeof(int32_t) * std::max<int64_t>(cur.nnz, 1));
-    L.w = (int32_t*)dev_alloc(ctx, sizeof(int32_t) * std::max<int64_t>(cur.nnz, 1));
-    L.self = (int64_t*)dev_alloc(ctx, sizeof(int64_t) * t);
+    L.w = dev_alloc(ctx, wsz * std::max<int64_t>(cur.nnz, 1));
+    L.self = dev_alloc(ctx, sizeof(int64_t) * t);
     L.size = (int32_t*)dev_alloc(ctx, sizeof(int32_t) * t);
     L.cluster_of = (int32_t*)dev_alloc(ctx, sizeof(int32_t) * n);
     if (!L.rp || !L.col || !L.w || !L.self || !L.size || !L.cluster_of) {
@@ -409,6 +458,7 @@ int spc_coarsen_to(spc_ctx* ctx, const spc_graph* g, int64_t n_c, int schedule, 
     cur.w = L.w;
     cur.self_w = L.self;
     cur.size = L.size;
+    cur.wtype = L.wtype;
     n = t;
   }
   *out = h;
@@ -429,7 +479,7 @@ int spc_hier_level(const spc_hier* h, int lvl, spc_graph* view, const int32_t** 
     view->w = L.w;
     view->self_w = L.self;
     view->size = L.size;
-    view->wtype = SPC_W_I32;
+    view->wtype = L.wtype;
   }
   if (cluster_of) *cluster_of = L.cluster_of;
   if (stats) *stats = L.st;
@@ -448,7 +498,8 @@ int spc_hier_export_level(spc_ctx* ctx, const spc_hier* h, int lvl, spc_graph_ou
   SPC_HIP(ctx, hipMemcpyAsync(dst->row_ptr, L.rp, sizeof(int64_t) * (L.n + 1), hipMemcpyDeviceToDevice, st));
   if (L.nnz) {
     SPC_HIP(ctx, hipMemcpyAsync(dst->col, L.col, sizeof(int32_t) * L.nnz, hipMemcpyDeviceToDevice, st));
-    SPC_HIP(ctx, hipMemcpyAsync(dst->w, L.w, sizeof(int32_t) * L.nnz, hipMemcpyDeviceToDevice, st));
+    size_t wsz = L.wtype == SPC_W_I32 ? sizeof(int32_t) : sizeof(double);
+    SPC_HIP(ctx, hipMemcpyAsync(dst->w, L.w, wsz * L.nnz, hipMemcpyDeviceToDevice, st));
   }
   SPC_HIP(ctx, hipMemcpyAsync(dst->self_w, L.self, sizeof(int64_t) * L.n, hipMemcpyDeviceToDevice, st));
   SPC_HIP(ctx, hipMemcpyAsync(dst->size, L.size, sizeof(int32_t) * L.n, hipMemcpyDeviceToDevice, st));

@@ -14,10 +14,11 @@ struct spc_hier {
     int64_t n = 0, nnz = 0, n_prev = 0;
     int64_t* rp = nullptr;
     int32_t* col = nullptr;
-    int32_t* w = nullptr;
-    int64_t* self = nullptr;
+    void* w = nullptr;        // int32 (integer path) or double (floating-point path)
+    void* self = nullptr;     // int64 or double
     int32_t* size = nullptr;
     int32_t* cluster_of = nullptr;
+    spc_wtype wtype = SPC_W_I32;
     spc_level_stats st{};
   };
   std::vector<Level> levels;
@@ -35,6 +36,30 @@ struct LevelIn {
   const int32_t* w;
   const int64_t* self;   // nullable
   const int32_t* size;   // nullable
+};
+
+// Device view of a floating-point input graph: FP32 weights (an input
+// level) or FP64 weights (coarse levels), FP64 self-loops.
+struct LevelInF {
+  int64_t n, nnz;
+  const int64_t* rp;
+  const int32_t* col;
+  const void* w;
+  int w32;               // 1: w is float[nnz], 0: double[nnz]
+  const double* self;    // nullable
+  const int32_t* size;   // nullable
+};
+
+// Sort record of the floating-point order: FP64 score, ties by edge index.
+struct KeyFD {
+  double s;
+  uint64_t e;
+};
+
+struct LessFD {
+  __device__ __forceinline__ bool operator()(const KeyFD& a, const KeyFD& b) const {
+    return a.s < b.s || (a.s == b.s && a.e < b.e);
+  }
 };
 
 // Exact sort key of the rank-mode order: score N / D, ties by edge index.
@@ -81,7 +106,10 @@ enum Info : int {
   I_MIN = 21,     // live edges read by hooking rounds
   I_KEYS = 22,    // exact per-edge records were written
   I_MSF0 = 23,    // forest records before the current hooking round
-  I_NINFO = 24
+  I_FP_LMIN = 24, // floating-point path: smallest weight ulp exponent + FP_EBIAS
+  I_FP_HMAX = 25, // floating-point path: largest weight exponent + FP_EBIAS
+  I_FP_BAD = 26,  // floating-point path: a weight is not finite / not positive
+  I_NINFO = 32
 };
 
 // Block-wide reservation of `my` consecutive slots per thread behind a
@@ -143,12 +171,28 @@ struct LevelWork {
   int64_t* hmrs;             // [n]  huge member -> its first CSR position
   uint64_t* gkeyA;           // [nnz] (key, w) pairs, 16 bytes each
   uint64_t* gkeyB;           // [nnz]
+  // floating-point path only (null on the integer path)
+  int32_t* ones;             // [nnz]  unit weights for the structure pass
+  int32_t* wtmp;             // [nnz]  structure pass's integer coarse weights
+  int64_t* selftmp;          // [n]
+  uint64_t* acc;             // [FP_LIMBS * nnz] coarse entry sums, 32-bit limbs
+  uint64_t* selfacc;         // [FP_LIMBS * n]
+  int32_t* emap;             // [nnz]  fine entry -> coarse entry (>= 0) or -1 - self node
+  KeyFD* fd_sorted;          // sorted FP order records (points into keysA or keysB)
 };
+
+constexpr int FP_LIMBS = 6;     // 192-bit fixed point in 32-bit limbs
+constexpr int FP_EBIAS = 4096;  // bias of the exponents kept in the info block
+// FP sums: every weight of a level is an integer multiple of 2^L (L the
+// smallest ulp exponent among them) and below 2^(H+1) (H the largest
+// exponent); a sum of at most 2^31 of them in units of 2^L stays below
+// 2^(H - L + 32), inside the 192-bit fixed point when H - L <= 159.
+constexpr int FP_MAX_SPAN = 192 - 33;
 
 // look-back words a level needs: the most tiles any compaction launch uses
 inline int64_t lb_words(int64_t n, int64_t nnz) { return nnz / 1024 + 4 * (n / 256) + 4096; }
 
-void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W);
+void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W, bool fp = false);
 
 // A fresh look-back chain for one launch, words from `off` of the level's
 // array; the array is zeroed again when the epochs run out.
@@ -175,12 +219,29 @@ void launch_score(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t m,
 // rank order: P from the sorted exact records, mirrored into Pc
 void launch_rank_scatter(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t m,
                          const KeyND* sorted);
+// Pc from P (an edge's rank into both of its CSR entries)
+void launch_rank_mirror(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t m);
 // info[I_EPS] = exact score of the forest edge whose key equals sel2's cutoff
 void launch_eps(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t msf_bound);
 
-// Steps A1-A4: degrees, scores, order, merge selection -> cluster_of.
+// Floating-point path pieces (fp.hip).
+// A1: validates the weights, records their exponent range, computes the
+// degrees as correctly rounded exact sums (into W.deg as doubles) and the
+// per-level initialisation of the integer path's k_degree.
+void launch_fp_degree(spc_ctx* ctx, const LevelInF& g, LevelWork& W);
+// A2 + A3: FP64 scores in the common-support form, sorted with ties by edge
+// id, ranks scattered into P and Pc.
+int fp_rank_keys(spc_ctx* ctx, const LevelInF& g, LevelWork& W, int64_t m);
+// info[I_EPS] = score of the cutoff rank
+void launch_eps_fp(spc_ctx* ctx, LevelWork& W);
+// A5 with correctly rounded exact FP64 sums; also fills W.emap.
+int contract_level_fp(spc_ctx* ctx, const LevelInF& g, const int32_t* cluster_of, int64_t n_c,
+                      spc_graph_out* out, LevelWork& W, LevelResult& R);
+
+// Steps A1-A4: degrees, scores, order, merge selection -> cluster_of.  With
+// gf the weights are floating point (g then carries the structure only).
 int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of, LevelWork& W,
-                 LevelResult& R);
+                 LevelResult& R, const LevelInF* gf = nullptr);
 
 // Step A5: contraction of Definition 1 into caller buffers.
 int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* cluster_of, int64_t n_c,

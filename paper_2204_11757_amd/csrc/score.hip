@@ -297,11 +297,15 @@ void launch_score(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t m,
                        ebits, (uint64_t*)nullptr, (uint64_t*)nullptr, W.keysA, 1, W.info);
 }
 
+void launch_rank_mirror(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t m) {
+  hipLaunchKernelGGL(k_rank_mirror, dim3(grid_for(m, TILE_F)), dim3(BS), 0, ctx->stream, g, W.lc, W.uptr,
+                     m, W.P, W.Pc);
+}
+
 void launch_rank_scatter(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t m,
                          const KeyND* sorted) {
   hipLaunchKernelGGL(k_rank_scatter, dim3(grid_for(m, 256)), dim3(256), 0, ctx->stream, sorted, m, W.P);
-  hipLaunchKernelGGL(k_rank_mirror, dim3(grid_for(m, TILE_F)), dim3(BS), 0, ctx->stream, g, W.lc, W.uptr,
-                     m, W.P, W.Pc);
+  launch_rank_mirror(ctx, g, W, m);
 }
 
 void launch_eps(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t msf_bound) {

@@ -23,7 +23,7 @@ namespace spc {
 // ---------------------------------------------------------------------------
 // workspace plan
 // ---------------------------------------------------------------------------
-void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W) {
+void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W, bool fp) {
   int64_t m = nnz / 2;
   W.info = A.take<unsigned long long>(I_NINFO);
   W.lbstate = A.take<uint64_t>(lb_words(n, nnz));
@@ -69,6 +69,19 @@ void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W) {
   W.hmrs = A.take<int64_t>(n);
   W.gkeyA = A.take<uint64_t>(2 * nnz + 8);
   W.gkeyB = A.take<uint64_t>(2 * nnz + 8);
+  if (fp) {
+    W.ones = A.take<int32_t>(nnz);
+    W.wtmp = A.take<int32_t>(nnz);
+    W.selftmp = A.take<int64_t>(n);
+    W.acc = A.take<uint64_t>((int64_t)FP_LIMBS * nnz);
+    W.selfacc = A.take<uint64_t>((int64_t)FP_LIMBS * n);
+    W.emap = A.take<int32_t>(nnz);
+  } else {
+    W.ones = W.wtmp = W.emap = nullptr;
+    W.selftmp = nullptr;
+    W.acc = W.selfacc = nullptr;
+  }
+  W.fd_sorted = nullptr;
 }
 
 // ---------------------------------------------------------------------------
@@ -674,11 +687,20 @@ __global__ void k_key_mode(unsigned long long* info, int c) {
   info[I_GUARD] = ((D2 >> 64) != 0 || D2 > ((unsigned __int128)1 << c)) ? 1ull : 0ull;
 }
 
+// checks of the level's input that the device reports (integer weight
+// total; floating-point weights finite, positive and within the exact range)
 static int check_total(spc_ctx* ctx) {
   uint64_t total = (uint64_t)ctx->h_pinned[I_TOTAL];
   if (total > 2147483647ull)
     return set_error(ctx, SPC_EOVERFLOW, "total integer weight %llu exceeds 2^31-1",
                      (unsigned long long)total);
+  uint64_t bad = (uint64_t)ctx->h_pinned[I_FP_BAD];
+  if (bad & 1)
+    return set_error(ctx, SPC_EINVAL, "floating-point weights must be finite and positive "
+                                      "(self-loops finite and non-negative)");
+  if (bad & 2)
+    return set_error(ctx, SPC_ERANGE, "floating-point weights span more than %d binades: their sums "
+                                      "cannot be held exactly", FP_MAX_SPAN);
   return SPC_OK;
 }
 
@@ -769,7 +791,7 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, bool fused_fir
 // (read at the level's next synchronisation) says whether a guarded
 // decision failed.
 static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k, int64_t m,
-                            bool rank, LevelWork& W, LevelResult& R) {
+                            bool rank, LevelWork& W, LevelResult& R, const LevelInF* gf) {
   hipStream_t st = ctx->stream;
   int64_t n = g.n;
   unsigned long long* info = W.info;
@@ -786,6 +808,11 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
     hipLaunchKernelGGL(k_key_mode, dim3(1), dim3(1), 0, st, info, c);
     SPC_LAUNCH_CHECK(ctx, "score");
     R.key_bits = 64;
+  } else if (gf) {
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, &info[I_GUARD], 0ull);
+    int rc = fp_rank_keys(ctx, *gf, W, m);
+    if (rc) return rc;
+    R.key_bits = bitlen64((uint64_t)(m - 1));
   } else {
     hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, &info[I_GUARD], 0ull);
     {
@@ -881,7 +908,7 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
 }
 
 int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of, LevelWork& W,
-                 LevelResult& R) {
+                 LevelResult& R, const LevelInF* gf) {
   hipStream_t st = ctx->stream;
   int64_t n = g.n, m = g.nnz / 2;
   int64_t k = n - t;  // merges
@@ -894,12 +921,15 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
 
   // A1
   int nb = grid_for(n, DEG_ROWS);
-  {
-    TimedScope ts(ctx, "degree", (double)n);
-    hipLaunchKernelGGL(k_degree, dim3(nb), dim3(BS), 0, st, g, W.deg, W.lc, W.uptr, W.bestA, W.bestB,
-                       W.parent, W.degpart, info);
-  }
-  {
+  if (gf) {
+    TimedScope ts(ctx, "degree_fp", (double)n);
+    launch_fp_degree(ctx, *gf, W);
+  } else {
+    {
+      TimedScope ts(ctx, "degree", (double)n);
+      hipLaunchKernelGGL(k_degree, dim3(nb), dim3(BS), 0, st, g, W.deg, W.lc, W.uptr, W.bestA, W.bestB,
+                         W.parent, W.degpart, info);
+    }
     TimedScope ts(ctx, "degree_total", (double)nb);
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, st, W.degpart, (int64_t)nb, &info[I_TOTAL]);
   }
@@ -924,7 +954,7 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
 
   // A2-A4 and the labels; a guarded key that fails its exactness check
   // falls back to ranks
-  bool rank = ctx->force_rank_mode != 0;
+  bool rank = ctx->force_rank_mode != 0 || gf != nullptr;
   int32_t nc32 = 0;
   for (int pass = 0; pass < 2; pass++) {
     if (pass == 1) {
@@ -937,7 +967,7 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestA, n, KEY_INF);
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestB, n, KEY_INF);
     }
-    rc = order_and_select(ctx, g, t, k, m, rank, W, R);
+    rc = order_and_select(ctx, g, t, k, m, rank, W, R, gf);
     if (rc) return rc;
     {
       TimedScope ts(ctx, "components", (double)n);
@@ -955,12 +985,13 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
       hipLaunchKernelGGL(k_relabel, dim3(grid_for(n, 256)), dim3(256), 0, st, W.root, W.flag,
                          cluster_of, n);
     }
-    launch_eps(ctx, g, W, R.msf);
+    if (gf) launch_eps_fp(ctx, W);
+    else launch_eps(ctx, g, W, R.msf);
     SPC_LAUNCH_CHECK(ctx, "relabel");
     SPC_HIP(ctx, hipMemcpyAsync(&nc32, W.flag + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     rc = sync_info(ctx, W);
     if (rc) return rc;
-    R.key_mode = rank ? 1 : (hinfo[I_GUARD] ? 2 : 0);
+    R.key_mode = gf ? 3 : rank ? 1 : (hinfo[I_GUARD] ? 2 : 0);
     R.rounds = hinfo[I_ROUNDS];
     R.forest_in = hinfo[I_FIN];
     R.forest_kept = hinfo[I_FKEPT];

@@ -57,49 +57,69 @@ __global__ void k_count_clusters(const int32_t* __restrict__ cmap, int64_t n, in
   if (u < n) atomicAdd(&cnt[cmap[u]], 1);
 }
 
-// y = Q^T u_i (members summed in ascending fine id), t = D_c^{-1/2} y
+// Weights of a coarse graph as FP64: int32 or double entries, int64 or
+// double self-loops (integer levels convert exactly).
+struct CoarseView {
+  int64_t nc, nnz;
+  const int64_t* rp;
+  const int32_t* col;
+  const void* w;
+  const void* self;   // nullable
+  const int32_t* size;
+  int fp;             // 1: double weights and self-loops
+};
+
+__device__ __forceinline__ double cv_w(const CoarseView& g, int64_t j) {
+  return g.fp ? ((const double*)g.w)[j] : (double)((const int32_t*)g.w)[j];
+}
+__device__ __forceinline__ double cv_self(const CoarseView& g, int64_t a) {
+  if (!g.self) return 0.0;
+  return g.fp ? ((const double*)g.self)[a] : (double)((const int64_t*)g.self)[a];
+}
+
+// y = Q^T u_i (members summed in ascending fine id), d = W_c row sums with
+// the diagonal, t = D_c^{-1/2} y
 __global__ void k_restrict_scale(const uint64_t* __restrict__ sorted, const int32_t* __restrict__ mptr,
-                                 const double* __restrict__ U, int64_t n0, int k,
-                                 const int64_t* __restrict__ rp, const int32_t* __restrict__ w,
-                                 const int64_t* __restrict__ self, const int32_t* __restrict__ size,
-                                 int64_t nc, double* __restrict__ t) {
+                                 const double* __restrict__ U, int64_t n0, int k, CoarseView g,
+                                 double* __restrict__ t, double* __restrict__ dc) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nc * k) return;
-  int64_t a = idx % nc;
-  int i = (int)(idx / nc);
+  if (idx >= g.nc * k) return;
+  int64_t a = idx % g.nc;
+  int i = (int)(idx / g.nc);
   double y = 0.0;
   for (int32_t p = mptr[a]; p < mptr[a + 1]; p++) {
     int64_t u = (int64_t)(sorted[p] & 0xffffffffull);
     y += U[u + n0 * i];
   }
-  y = y / sqrt((double)(size ? size[a] : 1));
-  int64_t d = self ? self[a] : 0;
-  for (int64_t j = rp[a]; j < rp[a + 1]; j++) d += w[j];
-  t[a + nc * i] = y / sqrt((double)d);
+  y = y / sqrt((double)(g.size ? g.size[a] : 1));
+  double d = cv_self(g, a);
+  for (int64_t j = g.rp[a]; j < g.rp[a + 1]; j++) d += cv_w(g, j);
+  t[a + g.nc * i] = y / sqrt(d);
+  if (i == 0) dc[a] = d;
 }
 
-// prod = t * (W_c t), W_c with its diagonal, summed in ascending column
-__global__ void k_quad(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-                       const int32_t* __restrict__ w, const int64_t* __restrict__ self, int64_t nc,
-                       int k, const double* __restrict__ t, double* __restrict__ prod) {
+// z = W_c t (W_c with its diagonal, summed in ascending column), prod = t z
+__global__ void k_quad(CoarseView g, int k, const double* __restrict__ t, double* __restrict__ z,
+                       double* __restrict__ prod) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nc * k) return;
-  int64_t a = idx % nc;
-  int i = (int)(idx / nc);
-  const double* ti = t + nc * i;
-  double s = self ? (double)self[a] : 0.0;
-  double z = 0.0;
+  if (idx >= g.nc * k) return;
+  int64_t a = idx % g.nc;
+  int i = (int)(idx / g.nc);
+  const double* ti = t + g.nc * i;
+  double s = cv_self(g, a);
+  double acc = 0.0;
   bool placed = (s == 0.0);
-  for (int64_t j = rp[a]; j < rp[a + 1]; j++) {
-    int32_t b = col[j];
+  for (int64_t j = g.rp[a]; j < g.rp[a + 1]; j++) {
+    int32_t b = g.col[j];
     if (!placed && b > a) {
-      z += s * ti[a];
+      acc += s * ti[a];
       placed = true;
     }
-    z += (double)w[j] * ti[b];
+    acc += cv_w(g, j) * ti[b];
   }
-  if (!placed) z += s * ti[a];
-  prod[idx] = ti[a] * z;
+  if (!placed) acc += s * ti[a];
+  z[idx] = acc;
+  prod[idx] = ti[a] * acc;
 }
 
 // f_i = sum_a prod[a, i]: one block per i, fixed reduction shape
@@ -118,6 +138,50 @@ __global__ void __launch_bounds__(256) k_colsum(const double* __restrict__ prod,
   if (threadIdx.x == 0) R[i] = 1.0 - tmp[0];
 }
 
+// Gradient of loss = sum_i (R_i - lambda_i)^2, R_i = 1 - t_i^T W_c t_i,
+// t_i = D_c^{-1/2} y_i, with respect to the undirected weight w_ab = w_ba
+// (written at both of its CSR entries) and to the self-loop weights:
+//   d(t^T W t)/d w_ab   = 2 t_a t_b - t_a z_a / d_a - t_b z_b / d_b
+//   d(t^T W t)/d self_a = t_a^2 - t_a z_a / d_a          (z = W t)
+__global__ void k_spectral_grad(CoarseView g, int k, const double* __restrict__ t, const double* __restrict__ z,
+                                const double* __restrict__ dc, const double* __restrict__ coef,
+                                double* __restrict__ d_w, double* __restrict__ d_self) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < g.nnz) {
+    // the row of entry idx: binary search in rp
+    int64_t lo = 0, hi = g.nc - 1;
+    while (lo < hi) {
+      int64_t mid = (lo + hi + 1) >> 1;
+      if (g.rp[mid] <= idx) lo = mid;
+      else hi = mid - 1;
+    }
+    int64_t a = lo, b = g.col[idx];
+    double s = 0.0;
+    for (int i = 0; i < k; i++) {
+      const double* ti = t + g.nc * i;
+      const double* zi = z + g.nc * i;
+      double f = 2.0 * ti[a] * ti[b] - ti[a] * zi[a] / dc[a] - ti[b] * zi[b] / dc[b];
+      s += coef[i] * f;
+    }
+    d_w[idx] = s;
+  } else if (idx < g.nnz + g.nc) {
+    int64_t a = idx - g.nnz;
+    double s = 0.0;
+    for (int i = 0; i < k; i++) {
+      const double* ti = t + g.nc * i;
+      const double* zi = z + g.nc * i;
+      s += coef[i] * (ti[a] * ti[a] - ti[a] * zi[a] / dc[a]);
+    }
+    d_self[a] = s;
+  }
+}
+
+__global__ void k_loss_coef(const double* __restrict__ R, const double* __restrict__ lam, int k,
+                            double* __restrict__ coef) {
+  int i = threadIdx.x;
+  if (i < k) coef[i] = -2.0 * (R[i] - lam[i]);   // d loss / d f_i, f_i = t_i^T W t_i
+}
+
 int compose_map(spc_ctx* ctx, const spc_hier* h, int from_lvl, int to_lvl, int32_t* out, int64_t n_from) {
   MapChain ch;
   ch.count = 0;
@@ -128,6 +192,150 @@ int compose_map(spc_ctx* ctx, const spc_hier* h, int from_lvl, int to_lvl, int32
   hipLaunchKernelGGL(k_compose, dim3(grid_for(n_from, 256)), dim3(256), 0, ctx->stream, ch, n_from, out);
   SPC_LAUNCH_CHECK(ctx, "compose");
   return SPC_OK;
+}
+
+// Forward (and, when d_w is non-NULL, backward) of the spectral error of a
+// coarse graph whose super-nodes are given by cmap (fine id -> coarse id,
+// n0 entries; cmap may live in the workspace when own_cmap is false).
+int spectral_impl(spc_ctx* ctx, const CoarseView& g, const int32_t* cmap_in, const spc_hier* h, int lvl,
+                  int64_t n0, const double* U, const double* lambda, int k, double* R, double* loss,
+                  double* d_w, double* d_self) {
+  int64_t nc = g.nc;
+  Arena A;
+  A.counting = true;
+  for (int pass = 0; pass < 2; pass++) {
+    A.off = 0;
+    if (pass == 1) {
+      int rc = ensure_workspace(ctx, A.cap + 256);
+      if (rc) return rc;
+      A.counting = false;
+      A.base = (char*)ctx->ws;
+      A.cap = ctx->ws_cap;
+    }
+    int32_t* cmap = A.take<int32_t>(n0);
+    uint64_t* ka = A.take<uint64_t>(n0);
+    uint64_t* kb = A.take<uint64_t>(n0);
+    int32_t* mptr = A.take<int32_t>(nc + 1);
+    double* t = A.take<double>(nc * k);
+    double* z = A.take<double>(nc * k);
+    double* prod = A.take<double>(nc * k);
+    double* dc = A.take<double>(nc);
+    double* Rd = A.take<double>(k);
+    double* coef = A.take<double>(k);
+    if (pass == 0) {
+      A.cap = A.off;
+      continue;
+    }
+    hipStream_t st = ctx->stream;
+    int rc;
+    if (cmap_in) {
+      SPC_HIP(ctx, hipMemcpyAsync(cmap, cmap_in, sizeof(int32_t) * n0, hipMemcpyDeviceToDevice, st));
+    } else {
+      rc = compose_map(ctx, h, 0, lvl, cmap, n0);
+      if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_pair_keys, dim3(grid_for(n0, 256)), dim3(256), 0, st, cmap, n0, ka);
+    uint64_t* sorted = nullptr;
+    rc = merge_sort<uint64_t, LessU64>(ctx, ka, kb, n0, LessU64(), &sorted);
+    if (rc) return rc;
+    SPC_HIP(ctx, hipMemsetAsync(mptr, 0, sizeof(int32_t) * (nc + 1), st));
+    hipLaunchKernelGGL(k_count_clusters, dim3(grid_for(n0, 256)), dim3(256), 0, st, cmap, n0, mptr);
+    rc = exclusive_scan<int32_t>(ctx, mptr, mptr, nc, nullptr);
+    if (rc) return rc;
+    int64_t nk = nc * k;
+    double* Rout = R ? R : Rd;
+    hipLaunchKernelGGL(k_restrict_scale, dim3(grid_for(nk, 256)), dim3(256), 0, st, sorted, mptr, U, n0, k,
+                       g, t, dc);
+    hipLaunchKernelGGL(k_quad, dim3(grid_for(nk, 256)), dim3(256), 0, st, g, k, t, z, prod);
+    hipLaunchKernelGGL(k_colsum, dim3(k), dim3(256), 0, st, prod, nc, Rout);
+    if (d_w) {
+      hipLaunchKernelGGL(k_loss_coef, dim3(1), dim3(256), 0, st, Rout, lambda, k, coef);
+      hipLaunchKernelGGL(k_spectral_grad, dim3(grid_for(g.nnz + nc, 256)), dim3(256), 0, st, g, k, t, z, dc,
+                         coef, d_w, d_self);
+    }
+    SPC_LAUNCH_CHECK(ctx, "spectral_error");
+    if (loss) {
+      std::vector<double> hR(k), hl(k);
+      SPC_HIP(ctx, hipMemcpyAsync(hR.data(), Rout, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+      SPC_HIP(ctx, hipMemcpyAsync(hl.data(), lambda, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+      SPC_HIP(ctx, hipStreamSynchronize(st));
+      double s = 0.0;
+      for (int i = 0; i < k; i++) s += (hR[i] - hl[i]) * (hR[i] - hl[i]);
+      *loss = s;
+    }
+  }
+  return SPC_OK;
+}
+
+CoarseView view_of_level(const spc_hier::Level& L) {
+  CoarseView g;
+  g.nc = L.n;
+  g.nnz = L.nnz;
+  g.rp = L.rp;
+  g.col = L.col;
+  g.w = L.w;
+  g.self = L.self;
+  g.size = L.size;
+  g.fp = L.wtype != SPC_W_I32;
+  return g;
+}
+
+int view_of_graph(spc_ctx* ctx, const spc_graph* c, CoarseView& g) {
+  if (!c || c->n < 1 || c->nnz < 0 || !c->row_ptr || (c->nnz > 0 && (!c->col || !c->w)))
+    return set_error(ctx, SPC_EINVAL, "bad coarse graph");
+  if (c->wtype != SPC_W_I32 && c->wtype != SPC_W_F64)
+    return set_error(ctx, SPC_EINVAL, "coarse weights must be int32 or float64");
+  g.nc = c->n;
+  g.nnz = c->nnz;
+  g.rp = c->row_ptr;
+  g.col = c->col;
+  g.w = c->w;
+  g.self = c->self_w;
+  g.size = c->size;
+  g.fp = c->wtype == SPC_W_F64;
+  return SPC_OK;
+}
+
+// fine entry -> its coarse entry (>= 0) or -1 - super-node for an
+// intra-super-node entry
+__global__ void k_entry_map(const int64_t* __restrict__ rp, const int32_t* __restrict__ col, int64_t n,
+                            int64_t nnz, const int32_t* __restrict__ c, const int64_t* __restrict__ rpc,
+                            const int32_t* __restrict__ colc, int32_t* __restrict__ emap) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nnz) return;
+  int64_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int64_t mid = (lo + hi + 1) >> 1;
+    if (rp[mid] <= j) lo = mid;
+    else hi = mid - 1;
+  }
+  int32_t a = c[lo], b = c[col[j]];
+  if (a == b) {
+    emap[j] = -1 - a;
+    return;
+  }
+  int64_t l = rpc[a], h = rpc[a + 1];
+  while (l < h) {
+    int64_t mid = (l + h) >> 1;
+    if (colc[mid] < b) l = mid + 1;
+    else h = mid;
+  }
+  emap[j] = (int32_t)l;
+}
+
+// adjoint of the contraction (a gather): fine entries take their coarse
+// entry's gradient, intra-super-node entries and fine self-loops take the
+// super-node's self-loop gradient
+__global__ void k_contract_backward(const int32_t* __restrict__ emap, int64_t nnz_f, const int32_t* __restrict__ c,
+                                    int64_t n_f, const double* __restrict__ d_wc, const double* __restrict__ d_selfc,
+                                    double* __restrict__ d_wf, double* __restrict__ d_selff) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nnz_f) {
+    int32_t e = emap[i];
+    d_wf[i] = e >= 0 ? d_wc[e] : d_selfc[-1 - e];
+  } else if (i < nnz_f + n_f && d_selff) {
+    d_selff[i - nnz_f] = d_selfc[c[i - nnz_f]];
+  }
 }
 
 }  // namespace
@@ -163,57 +371,62 @@ int spc_spectral_error(spc_ctx* ctx, const spc_hier* h, int lvl, const double* U
   if (!h || lvl < 0 || lvl > (int)h->levels.size() || k < 1 || !U || !lambda || !loss)
     return set_error(ctx, SPC_EINVAL, "bad spectral_error arguments");
   if (lvl == 0) return set_error(ctx, SPC_EINVAL, "level 0 is the input graph; pass lvl >= 1");
-  const auto& L = h->levels[lvl - 1];
-  int64_t n0 = h->n0, nc = L.n;
-  Arena A;
-  A.counting = true;
-  for (int pass = 0; pass < 2; pass++) {
-    A.off = 0;
-    if (pass == 1) {
-      int rc = ensure_workspace(ctx, A.cap + 256);
-      if (rc) return rc;
-      A.counting = false;
-      A.base = (char*)ctx->ws;
-      A.cap = ctx->ws_cap;
-    }
-    int32_t* cmap = A.take<int32_t>(n0);
-    uint64_t* ka = A.take<uint64_t>(n0);
-    uint64_t* kb = A.take<uint64_t>(n0);
-    int32_t* mptr = A.take<int32_t>(nc + 1);
-    int32_t* partial = A.take<int32_t>(SCAN_MAXB);
-    double* t = A.take<double>(nc * k);
-    double* prod = A.take<double>(nc * k);
-    double* Rd = A.take<double>(k);
-    if (pass == 0) {
-      A.cap = A.off;
-      continue;
-    }
-    hipStream_t st = ctx->stream;
-    int rc = compose_map(ctx, h, 0, lvl, cmap, n0);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_pair_keys, dim3(grid_for(n0, 256)), dim3(256), 0, st, cmap, n0, ka);
-    uint64_t* sorted = nullptr;
-    rc = merge_sort<uint64_t, LessU64>(ctx, ka, kb, n0, LessU64(), &sorted);
-    if (rc) return rc;
-    SPC_HIP(ctx, hipMemsetAsync(mptr, 0, sizeof(int32_t) * (nc + 1), st));
-    hipLaunchKernelGGL(k_count_clusters, dim3(grid_for(n0, 256)), dim3(256), 0, st, cmap, n0, mptr);
-    rc = exclusive_scan<int32_t>(ctx, mptr, mptr, nc, partial);
-    if (rc) return rc;
-    int64_t nk = nc * k;
-    hipLaunchKernelGGL(k_restrict_scale, dim3(grid_for(nk, 256)), dim3(256), 0, st, sorted, mptr, U, n0,
-                       k, L.rp, L.w, L.self, L.size, nc, t);
-    hipLaunchKernelGGL(k_quad, dim3(grid_for(nk, 256)), dim3(256), 0, st, L.rp, L.col, L.w, L.self, nc,
-                       k, t, prod);
-    hipLaunchKernelGGL(k_colsum, dim3(k), dim3(256), 0, st, prod, nc, R ? R : Rd);
-    SPC_LAUNCH_CHECK(ctx, "spectral_error");
-    std::vector<double> hR(k), hl(k);
-    SPC_HIP(ctx, hipMemcpyAsync(hR.data(), R ? R : Rd, sizeof(double) * k, hipMemcpyDeviceToHost, st));
-    SPC_HIP(ctx, hipMemcpyAsync(hl.data(), lambda, sizeof(double) * k, hipMemcpyDeviceToHost, st));
-    SPC_HIP(ctx, hipStreamSynchronize(st));
-    double s = 0.0;
-    for (int i = 0; i < k; i++) s += (hR[i] - hl[i]) * (hR[i] - hl[i]);
-    *loss = s;
-  }
+  return spectral_impl(ctx, view_of_level(h->levels[lvl - 1]), nullptr, h, lvl, h->n0, U, lambda, k, R, loss,
+                       nullptr, nullptr);
+}
+
+int spc_hier_cluster_map(spc_ctx* ctx, const spc_hier* h, int lvl, int32_t* cmap) {
+  if (!ctx) return SPC_EINVAL;
+  if (!h || lvl < 0 || lvl > (int)h->levels.size() || !cmap)
+    return set_error(ctx, SPC_EINVAL, "bad cluster map arguments");
+  return compose_map(ctx, h, 0, lvl, cmap, h->n0);
+}
+
+int spc_spectral_error_graph(spc_ctx* ctx, const spc_graph* coarse, const int32_t* cmap, int64_t n0,
+                             const double* U, const double* lambda, int k, double* R, double* loss) {
+  if (!ctx) return SPC_EINVAL;
+  if (!cmap || n0 < 1 || k < 1 || !U || !lambda || !loss)
+    return set_error(ctx, SPC_EINVAL, "bad spectral_error arguments");
+  CoarseView g;
+  int rc = view_of_graph(ctx, coarse, g);
+  if (rc) return rc;
+  return spectral_impl(ctx, g, cmap, nullptr, 0, n0, U, lambda, k, R, loss, nullptr, nullptr);
+}
+
+int spc_spectral_error_backward(spc_ctx* ctx, const spc_graph* coarse, const int32_t* cmap, int64_t n0,
+                                const double* U, const double* lambda, int k, double* d_wc, double* d_selfc) {
+  if (!ctx) return SPC_EINVAL;
+  if (!cmap || n0 < 1 || k < 1 || !U || !lambda || !d_wc || !d_selfc)
+    return set_error(ctx, SPC_EINVAL, "bad spectral_error_backward arguments");
+  CoarseView g;
+  int rc = view_of_graph(ctx, coarse, g);
+  if (rc) return rc;
+  return spectral_impl(ctx, g, cmap, nullptr, 0, n0, U, lambda, k, nullptr, nullptr, d_wc, d_selfc);
+}
+
+int spc_entry_map(spc_ctx* ctx, const spc_graph* fine, const int32_t* cluster_of, const spc_graph* coarse,
+                  int32_t* entry_map) {
+  if (!ctx) return SPC_EINVAL;
+  if (!fine || !coarse || !cluster_of || !entry_map || fine->n < 1 || fine->nnz < 0 || !fine->row_ptr ||
+      !coarse->row_ptr || (fine->nnz > 0 && !fine->col) || (coarse->nnz > 0 && !coarse->col))
+    return set_error(ctx, SPC_EINVAL, "bad entry_map arguments");
+  if (fine->nnz == 0) return SPC_OK;
+  hipLaunchKernelGGL(k_entry_map, dim3(grid_for(fine->nnz, 256)), dim3(256), 0, ctx->stream, fine->row_ptr,
+                     fine->col, fine->n, fine->nnz, cluster_of, coarse->row_ptr, coarse->col, entry_map);
+  SPC_LAUNCH_CHECK(ctx, "entry_map");
+  return SPC_OK;
+}
+
+int spc_contract_backward(spc_ctx* ctx, const int32_t* entry_map, const int32_t* cluster_of, int64_t nnz_f,
+                          int64_t n_f, const double* d_wc, const double* d_selfc, double* d_wf, double* d_selff) {
+  if (!ctx) return SPC_EINVAL;
+  if (nnz_f < 0 || n_f < 1 || (nnz_f > 0 && (!entry_map || !d_wf)) || !d_selfc || (d_selff && !cluster_of))
+    return set_error(ctx, SPC_EINVAL, "bad contract_backward arguments");
+  int64_t tot = nnz_f + (d_selff ? n_f : 0);
+  if (tot == 0) return SPC_OK;
+  hipLaunchKernelGGL(k_contract_backward, dim3(grid_for(tot, 256)), dim3(256), 0, ctx->stream, entry_map, nnz_f,
+                     cluster_of, n_f, d_wc, d_selfc, d_wf, d_selff);
+  SPC_LAUNCH_CHECK(ctx, "contract_backward");
   return SPC_OK;
 }
 

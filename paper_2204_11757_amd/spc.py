@@ -29,7 +29,9 @@ EXPORTS = [
     "spc_last_error",
     "spc_strerror", "spc_coarsen_level", "spc_coarsen_to", "spc_hier_num_levels",
     "spc_hier_level", "spc_hier_export_level", "spc_hier_free", "spc_lift",
-    "spc_spectral_error", "spc_validate_graph", "spc_timing_report",
+    "spc_spectral_error", "spc_validate_graph", "spc_timing_report", "spc_hier_cluster_map",
+    "spc_spectral_error_graph", "spc_spectral_error_backward", "spc_entry_map",
+    "spc_contract_backward",
 ]
 
 
@@ -93,6 +95,12 @@ def lib():
             "spc_spectral_error": [p, p, i32, p, p, i32, p, C.POINTER(C.c_double)],
             "spc_validate_graph": [C.POINTER(_Graph)],
             "spc_timing_report": [p, C.c_char_p, C.c_size_t],
+            "spc_hier_cluster_map": [p, p, i32, p],
+            "spc_spectral_error_graph": [p, C.POINTER(_Graph), p, i64, p, p, i32, p,
+                                         C.POINTER(C.c_double)],
+            "spc_spectral_error_backward": [p, C.POINTER(_Graph), p, i64, p, p, i32, p, p],
+            "spc_entry_map": [p, C.POINTER(_Graph), p, C.POINTER(_Graph), p],
+            "spc_contract_backward": [p, p, p, i64, i64, p, p, p, p],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -306,7 +314,7 @@ class Hierarchy:
         view = _Graph()
         self.ctx.check(lib().spc_hier_level(self.h, lvl, C.byref(view), None, C.byref(st)))
         dev = torch.device("cuda", self.ctx.device)
-        out = _empty_out(view.n, view.nnz, dev)
+        out = _empty_out(view.n, view.nnz, dev, fp=view.wtype != SPC_W_I32)
         n_prev = self.n0 if lvl == 1 else self.stats(lvl - 1).n_out
         cl = torch.empty(n_prev, dtype=torch.int32, device=dev)
         oc = _out_c(out, view.n, max(view.nnz, 1))
@@ -364,6 +372,102 @@ def spectral_error(h: Hierarchy, lvl: int, U: torch.Tensor, lam: torch.Tensor):
     ctx.check(lib().spc_spectral_error(ctx.h, h.h, lvl, Uc.data_ptr(), lamd.data_ptr(), k,
                                        R.data_ptr(), C.byref(loss)))
     return loss.value, R
+
+
+def cluster_map(h: Hierarchy, lvl: int) -> torch.Tensor:
+    """Input node -> level-lvl super-node (int32[n0])."""
+    ctx = context(h.ctx.device)
+    out = torch.empty(h.n0, dtype=torch.int32, device=torch.device("cuda", h.ctx.device))
+    ctx.check(lib().spc_hier_cluster_map(ctx.h, h.h, lvl, out.data_ptr()))
+    return out
+
+
+def _colmajor(U: torch.Tensor) -> torch.Tensor:
+    return U.to(torch.float64).t().contiguous()
+
+
+def spectral_error_graph(coarse: DeviceGraph, cmap: torch.Tensor, U: torch.Tensor, lam: torch.Tensor):
+    """(loss, R) of an explicit coarse graph (int32 or float64 weights) whose
+    super-nodes are cmap (input node -> super-node)."""
+    ctx = context(_dev(coarse.row_ptr))
+    Uc = _colmajor(U)
+    k = Uc.shape[0]
+    lamd = lam.to(torch.float64).contiguous()
+    R = torch.empty(k, dtype=torch.float64, device=U.device)
+    loss = C.c_double()
+    gc = coarse._c()
+    ctx.check(lib().spc_spectral_error_graph(ctx.h, C.byref(gc), cmap.data_ptr(), int(cmap.numel()),
+                                             Uc.data_ptr(), lamd.data_ptr(), k, R.data_ptr(),
+                                             C.byref(loss)))
+    return loss.value, R
+
+
+def spectral_error_backward(coarse: DeviceGraph, cmap: torch.Tensor, U: torch.Tensor, lam: torch.Tensor):
+    """(d loss / d w_c at every CSR entry, d loss / d self_c)."""
+    ctx = context(_dev(coarse.row_ptr))
+    Uc = _colmajor(U)
+    k = Uc.shape[0]
+    lamd = lam.to(torch.float64).contiguous()
+    dev = coarse.row_ptr.device
+    dw = torch.empty(max(coarse.nnz, 1), dtype=torch.float64, device=dev)
+    ds = torch.empty(coarse.n, dtype=torch.float64, device=dev)
+    gc = coarse._c()
+    ctx.check(lib().spc_spectral_error_backward(ctx.h, C.byref(gc), cmap.data_ptr(), int(cmap.numel()),
+                                                Uc.data_ptr(), lamd.data_ptr(), k, dw.data_ptr(),
+                                                ds.data_ptr()))
+    return dw[: coarse.nnz], ds
+
+
+def entry_map(fine: DeviceGraph, cluster_of: torch.Tensor, coarse: DeviceGraph) -> torch.Tensor:
+    """Fine CSR entry -> coarse entry position, or -1 - super-node."""
+    ctx = context(_dev(fine.row_ptr))
+    out = torch.empty(max(fine.nnz, 1), dtype=torch.int32, device=fine.row_ptr.device)
+    gf, gc = fine._c(), coarse._c()
+    ctx.check(lib().spc_entry_map(ctx.h, C.byref(gf), cluster_of.data_ptr(), C.byref(gc), out.data_ptr()))
+    return out[: fine.nnz]
+
+
+def contract_backward(emap: torch.Tensor, cluster_of: torch.Tensor, d_wc: torch.Tensor,
+                      d_selfc: torch.Tensor, n_f: int, want_self: bool = True):
+    """Adjoint of the contraction: (d_wf, d_selff or None)."""
+    ctx = context(_dev(d_selfc))
+    nnz_f = int(emap.numel())
+    dev = d_selfc.device
+    dwf = torch.empty(max(nnz_f, 1), dtype=torch.float64, device=dev)
+    dsf = torch.empty(n_f, dtype=torch.float64, device=dev) if want_self else None
+    d_wc = d_wc.to(torch.float64).contiguous()
+    d_selfc = d_selfc.to(torch.float64).contiguous()
+    ctx.check(lib().spc_contract_backward(ctx.h, emap.data_ptr() if nnz_f else None, cluster_of.data_ptr(),
+                                          nnz_f, int(n_f), d_wc.data_ptr(), d_selfc.data_ptr(),
+                                          dwf.data_ptr(), dsf.data_ptr() if dsf is not None else None))
+    return dwf[:nnz_f], dsf
+
+
+class SpectralError(torch.autograd.Function):
+    """loss(w_c, self_c) = sum_i (R_i - lambda_i)^2 of a coarse graph whose
+    FP64 weights w_c (one value per CSR entry, symmetric) and self-loops
+    self_c are the differentiable inputs; the structure, cmap, U and lambda
+    are fixed.  Forward and backward run in the library's kernels."""
+
+    @staticmethod
+    def forward(ctx_, w_c, self_c, structure: DeviceGraph, cmap, U, lam):
+        g = DeviceGraph(n=structure.n, row_ptr=structure.row_ptr, col=structure.col,
+                        w=w_c.detach().to(torch.float64).contiguous(),
+                        self_w=self_c.detach().to(torch.float64).contiguous(), size=structure.size)
+        loss, _ = spectral_error_graph(g, cmap, U, lam)
+        ctx_.save_for_backward(w_c.detach(), self_c.detach())
+        ctx_.g = g
+        ctx_.cmap, ctx_.U, ctx_.lam = cmap, U, lam
+        return torch.tensor(loss, dtype=torch.float64, device=w_c.device)
+
+    @staticmethod
+    def backward(ctx_, grad):
+        dw, ds = spectral_error_backward(ctx_.g, ctx_.cmap, ctx_.U, ctx_.lam)
+        return grad * dw, grad * ds, None, None, None, None
+
+
+def spectral_error_loss(w_c, self_c, structure: DeviceGraph, cmap, U, lam):
+    return SpectralError.apply(w_c, self_c, structure, cmap, U, lam)
 
 
 def validate_graph(g) -> int:
