@@ -158,6 +158,24 @@ int spc_coarsen_level(spc_ctx* ctx, const spc_graph* g, int64_t n_target, int32_
  * level's graph and cluster map; free it with spc_hier_free. */
 int spc_coarsen_to(spc_ctx* ctx, const spc_graph* g, int64_t n_c, int schedule, spc_hier** out);
 
+/* Batched coarsening: G independent graphs packed block-diagonally in one
+ * graph g (graph i owns nodes [graph_off[i], graph_off[i+1]) and only edges
+ * among them; host int64[G+1]), each coarsened to its own n_c[i] (host
+ * int64[G]) with the level schedule of spc_coarsen_to applied per graph.
+ * Every graph's result equals what spc_coarsen_to gives for it alone (the
+ * merge loop of Algorithm 1 runs per graph; the graphs only share the
+ * launches).  Level l of the returned hierarchy is the packed union of the
+ * graphs' level-l graphs (a graph already at its target is carried over
+ * unchanged); spc_hier_graph_offsets gives each level's node offsets.
+ * Integer weights only (SPC_W_I32).  SPC_EUNREACHABLE if some graph has
+ * more connected components than its target. */
+int spc_coarsen_batched(spc_ctx* ctx, int32_t G, const spc_graph* g, const int64_t* graph_off,
+                        const int64_t* n_c, int schedule, spc_hier** out);
+/* Node offsets (host int64[G+1], cap >= G+1) of a batched hierarchy's
+ * graphs at level lvl (0 = the input).  SPC_EINVAL for a hierarchy that
+ * does not come from spc_coarsen_batched. */
+int spc_hier_graph_offsets(const spc_hier* h, int lvl, int64_t* off, int64_t cap);
+
 int spc_hier_num_levels(const spc_hier* h);
 /* Level lvl (1-based; level 0 is the input, not stored).  view receives
  * device pointers owned by the hierarchy; cluster_of maps level lvl-1

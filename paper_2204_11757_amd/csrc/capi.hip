@@ -172,7 +172,8 @@ static LevelIn level_in(const spc_graph* g) {
 
 // one level into caller buffers
 static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* cluster_of,
-                      spc_graph_out* out, int64_t* nnz_c, spc_level_stats* st) {
+                      spc_graph_out* out, int64_t* nnz_c, spc_level_stats* st,
+                      const Segments* seg = nullptr) {
   int rc = check_graph(ctx, g);
   if (rc) return rc;
   if (t < 1) return set_error(ctx, SPC_EINVAL, "n_target must be >= 1");
@@ -198,7 +199,7 @@ static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* clus
   LevelResult R;
   rc = plan_and_bind(ctx, g->n, g->nnz, W, fp);
   if (rc) return rc;
-  rc = select_level(ctx, L, t, cluster_of, W, R, fp ? &LF : nullptr);
+  rc = select_level(ctx, L, t, cluster_of, W, R, fp ? &LF : nullptr, seg);
   if (rc) return rc;
   if (fp && R.n_c == g->n) {
     if (out->nnz_cap < g->nnz) return set_error(ctx, SPC_ECAPACITY, "nnz_cap too small");
@@ -462,6 +463,110 @@ int spc_coarsen_to(spc_ctx* ctx, const spc_graph* g, int64_t n_c, int schedule, 
     n = t;
   }
   *out = h;
+  return SPC_OK;
+}
+
+int spc_coarsen_batched(spc_ctx* ctx, int32_t G, const spc_graph* g, const int64_t* graph_off,
+                        const int64_t* n_c, int schedule, spc_hier** out) {
+  if (!ctx) return SPC_EINVAL;
+  if (!out) return set_error(ctx, SPC_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = check_graph(ctx, g);
+  if (rc) return rc;
+  if (g->wtype != SPC_W_I32) return set_error(ctx, SPC_EINVAL, "batched coarsening takes int32 weights");
+  if (G < 1 || !graph_off || !n_c) return set_error(ctx, SPC_EINVAL, "bad batch description");
+  if (schedule != 0 && schedule != 1) return set_error(ctx, SPC_EINVAL, "unknown schedule %d", schedule);
+  if (graph_off[0] != 0 || graph_off[G] != g->n)
+    return set_error(ctx, SPC_EINVAL, "graph offsets must run from 0 to n");
+  std::vector<int64_t> ng(G), nc(G), off(graph_off, graph_off + G + 1);
+  for (int32_t i = 0; i < G; i++) {
+    ng[i] = off[i + 1] - off[i];
+    if (ng[i] < 1) return set_error(ctx, SPC_EINVAL, "graph %d of the batch is empty", (int)i);
+    if (n_c[i] < 1) return set_error(ctx, SPC_EINVAL, "n_c of graph %d must be >= 1", (int)i);
+    nc[i] = std::min(n_c[i], ng[i]);
+  }
+  int64_t* d_off = (int64_t*)dev_alloc(ctx, sizeof(int64_t) * (G + 1));
+  int64_t* d_k = (int64_t*)dev_alloc(ctx, sizeof(int64_t) * G);
+  spc_hier* h = new (std::nothrow) spc_hier();
+  if (!h || !d_off || !d_k) {
+    dev_free(ctx, d_off);
+    dev_free(ctx, d_k);
+    delete h;
+    return set_error(ctx, SPC_ENOMEM, "batch allocation failed");
+  }
+  auto fail = [&](int code) {
+    dev_free(ctx, d_off);
+    dev_free(ctx, d_k);
+    spc_hier_free(h);
+    return code;
+  };
+  h->ctx = ctx;
+  h->n0 = g->n;
+  h->goff.push_back(off);
+  spc_graph cur = *g;
+  while (true) {
+    std::vector<int64_t> tg(G), kk(G), noff(G + 1);
+    int64_t T = 0;
+    bool more = false;
+    for (int32_t i = 0; i < G; i++) {
+      tg[i] = ng[i] <= nc[i] ? ng[i] : (schedule == 1 ? nc[i] : std::max(nc[i], (ng[i] + 1) / 2));
+      kk[i] = ng[i] - tg[i];
+      more |= kk[i] > 0;
+      noff[i] = T;
+      T += tg[i];
+    }
+    noff[G] = T;
+    if (!more) break;
+    SPC_HIP(ctx, hipMemcpyAsync(d_off, off.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, ctx->stream));
+    SPC_HIP(ctx, hipMemcpyAsync(d_k, kk.data(), sizeof(int64_t) * G, hipMemcpyHostToDevice, ctx->stream));
+    Segments seg{G, d_off, d_k};
+    spc_hier::Level L;
+    L.n_prev = cur.n;
+    L.wtype = SPC_W_I32;
+    L.rp = (int64_t*)dev_alloc(ctx, sizeof(int64_t) * (T + 1));
+    L.col = (int32_t*)dev_alloc(ctx, sizeof(int32_t) * std::max<int64_t>(cur.nnz, 1));
+    L.w = dev_alloc(ctx, sizeof(int32_t) * std::max<int64_t>(cur.nnz, 1));
+    L.self = dev_alloc(ctx, sizeof(int64_t) * T);
+    L.size = (int32_t*)dev_alloc(ctx, sizeof(int32_t) * T);
+    L.cluster_of = (int32_t*)dev_alloc(ctx, sizeof(int32_t) * cur.n);
+    if (!L.rp || !L.col || !L.w || !L.self || !L.size || !L.cluster_of) {
+      free_level(ctx, L);
+      set_error(ctx, SPC_ENOMEM, "hierarchy allocation failed");
+      return fail(SPC_ENOMEM);
+    }
+    spc_graph_out o{L.rp, L.col, L.w, L.self, L.size, T, std::max<int64_t>(cur.nnz, 1)};
+    int64_t nnz_c = 0;
+    rc = level_impl(ctx, &cur, T, L.cluster_of, &o, &nnz_c, &L.st, &seg);
+    if (rc) {
+      free_level(ctx, L);
+      return fail(rc);
+    }
+    L.n = T;
+    L.nnz = nnz_c;
+    h->levels.push_back(L);
+    h->goff.push_back(noff);
+    cur.n = T;
+    cur.nnz = nnz_c;
+    cur.row_ptr = L.rp;
+    cur.col = L.col;
+    cur.w = L.w;
+    cur.self_w = L.self;
+    cur.size = L.size;
+    off = noff;
+    ng = tg;
+  }
+  dev_free(ctx, d_off);
+  dev_free(ctx, d_k);
+  *out = h;
+  return SPC_OK;
+}
+
+int spc_hier_graph_offsets(const spc_hier* h, int lvl, int64_t* off, int64_t cap) {
+  if (!h || lvl < 0 || lvl > (int)h->levels.size() || !off) return SPC_EINVAL;
+  if (h->goff.empty()) return SPC_EINVAL;
+  const auto& o = h->goff[lvl];
+  if ((int64_t)o.size() > cap) return SPC_ECAPACITY;
+  for (size_t i = 0; i < o.size(); i++) off[i] = o[i];
   return SPC_OK;
 }
 

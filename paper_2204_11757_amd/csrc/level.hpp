@@ -10,6 +10,9 @@
 struct spc_hier {
   spc_ctx* ctx = nullptr;
   int64_t n0 = 0;
+  // batched hierarchies: node offsets of the batch's graphs at every level
+  // (entry 0: the input); empty for a single graph
+  std::vector<std::vector<int64_t>> goff;
   struct Level {
     int64_t n = 0, nnz = 0, n_prev = 0;
     int64_t* rp = nullptr;
@@ -62,6 +65,15 @@ struct LessFD {
   }
 };
 
+// A batch of independent graphs coarsened as one block-diagonal graph:
+// graph i owns nodes [off[i], off[i+1]) and needs k[i] merges this level.
+// Device arrays.
+struct Segments {
+  int64_t G;
+  const int64_t* off;   // [G + 1]
+  const int64_t* k;     // [G]
+};
+
 // Exact sort key of the rank-mode order: score N / D, ties by edge index.
 struct KeyND {
   uint64_t N, D, e;
@@ -109,6 +121,7 @@ enum Info : int {
   I_FP_LMIN = 24, // floating-point path: smallest weight ulp exponent + FP_EBIAS
   I_FP_HMAX = 25, // floating-point path: largest weight exponent + FP_EBIAS
   I_FP_BAD = 26,  // floating-point path: a weight is not finite / not positive
+  I_SEG_SHORT = 27, // batch: a graph has fewer forest edges than merges needed
   I_NINFO = 32
 };
 
@@ -238,10 +251,18 @@ void launch_eps_fp(spc_ctx* ctx, LevelWork& W);
 int contract_level_fp(spc_ctx* ctx, const LevelInF& g, const int32_t* cluster_of, int64_t n_c,
                       spc_graph_out* out, LevelWork& W, LevelResult& R);
 
+// Batched merge cutoff (batch.hip): forest edges sorted by (graph, key);
+// each graph's first k[i] are joined in `parent` (which must hold the
+// identity); info[I_EPS] receives the largest accepted score, info[I_VIOL]
+// a failed guarded decision, info[I_SEG_SHORT] a graph short of edges.
+int seg_cutoff_union(spc_ctx* ctx, const LevelIn& g, LevelWork& W, const LevelResult& R,
+                     const Segments& seg, int ebits, bool rank);
+
 // Steps A1-A4: degrees, scores, order, merge selection -> cluster_of.  With
-// gf the weights are floating point (g then carries the structure only).
+// gf the weights are floating point (g then carries the structure only);
+// with seg the input is a batch and every graph has its own target.
 int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of, LevelWork& W,
-                 LevelResult& R, const LevelInF* gf = nullptr);
+                 LevelResult& R, const LevelInF* gf = nullptr, const Segments* seg = nullptr);
 
 // Step A5: contraction of Definition 1 into caller buffers.
 int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* cluster_of, int64_t n_c,

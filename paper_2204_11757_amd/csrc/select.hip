@@ -791,7 +791,8 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, bool fused_fir
 // (read at the level's next synchronisation) says whether a guarded
 // decision failed.
 static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k, int64_t m,
-                            bool rank, LevelWork& W, LevelResult& R, const LevelInF* gf) {
+                            bool rank, LevelWork& W, LevelResult& R, const LevelInF* gf,
+                            const Segments* seg) {
   hipStream_t st = ctx->stream;
   int64_t n = g.n;
   unsigned long long* info = W.info;
@@ -841,7 +842,9 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
   int64_t done_cand = 0;
   R.candidates = 0;
   for (int band = 0;; band++) {
-    bool all = ctx->force_full_filter || target >= m || band >= 2;
+    // a batch builds the whole forest in one band (each graph needs its own
+    // count of forest edges)
+    bool all = ctx->force_full_filter || target >= m || band >= 2 || seg != nullptr;
     if (band > 0) {
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestA, n, KEY_INF);
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestB, n, KEY_INF);
@@ -880,7 +883,7 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
     R.candidates = done_cand;
     R.bands = band + 1;
     R.msf = hinfo[I_MSF];
-    if (R.msf >= k) break;
+    if (seg || R.msf >= k) break;
     if (all)
       return set_error(ctx, SPC_EUNREACHABLE,
                        "only %lld merges possible, %lld requested (more than %lld components)",
@@ -891,6 +894,7 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
     target = nt > 2 * target ? nt : 2 * target;
   }
 
+  if (seg) return SPC_OK;   // each graph's cutoff: seg_cutoff_union in select_level
   // cutoff: the k-th lightest forest edge
   {
     TimedScope ts(ctx, "select_cutoff", (double)R.msf);
@@ -908,7 +912,9 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
 }
 
 int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of, LevelWork& W,
-                 LevelResult& R, const LevelInF* gf) {
+                 LevelResult& R, const LevelInF* gf, const Segments* seg) {
+  if (seg && gf)
+    return set_error(ctx, SPC_EINVAL, "batched coarsening takes integer weights");
   hipStream_t st = ctx->stream;
   int64_t n = g.n, m = g.nnz / 2;
   int64_t k = n - t;  // merges
@@ -967,13 +973,19 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestA, n, KEY_INF);
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestB, n, KEY_INF);
     }
-    rc = order_and_select(ctx, g, t, k, m, rank, W, R, gf);
+    rc = order_and_select(ctx, g, t, k, m, rank, W, R, gf, seg);
     if (rc) return rc;
     {
       TimedScope ts(ctx, "components", (double)n);
       hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256)), dim3(256), 0, st, W.parent, n);
-      hipLaunchKernelGGL(k_cc_union, dim3(grid_for(R.msf, 256, ctx->num_cus * 8)), dim3(256), 0, st,
-                         W.msfP, W.msfO, &info[I_MSF], W.sel2, W.parent);
+      if (seg) {
+        int ebits = bitlen64((uint64_t)(m - 1));
+        rc = seg_cutoff_union(ctx, g, W, R, *seg, ebits < 1 ? 1 : ebits, rank);
+        if (rc) return rc;
+      } else {
+        hipLaunchKernelGGL(k_cc_union, dim3(grid_for(R.msf, 256, ctx->num_cus * 8)), dim3(256), 0, st,
+                           W.msfP, W.msfO, &info[I_MSF], W.sel2, W.parent);
+      }
       hipLaunchKernelGGL(k_cc_flatten, dim3(grid_for(n, 256)), dim3(256), 0, st, W.parent, W.root,
                          W.flag, n);
     }
@@ -986,7 +998,7 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
                          cluster_of, n);
     }
     if (gf) launch_eps_fp(ctx, W);
-    else launch_eps(ctx, g, W, R.msf);
+    else if (!seg) launch_eps(ctx, g, W, R.msf);
     SPC_LAUNCH_CHECK(ctx, "relabel");
     SPC_HIP(ctx, hipMemcpyAsync(&nc32, W.flag + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     rc = sync_info(ctx, W);
@@ -1001,6 +1013,8 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
     if (rank) return set_error(ctx, SPC_EINVAL, "internal: exact rank order flagged as inexact");
   }
   if (hinfo[I_LBERR]) return set_error(ctx, SPC_EINVAL, "internal: look-back wait gave up");
+  if (seg && hinfo[I_SEG_SHORT])
+    return set_error(ctx, SPC_EUNREACHABLE, "a graph of the batch has more components than its target");
   double eps;
   memcpy(&eps, &hinfo[I_EPS], sizeof(double));
   R.eps = eps;

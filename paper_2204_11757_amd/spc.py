@@ -31,7 +31,7 @@ EXPORTS = [
     "spc_hier_level", "spc_hier_export_level", "spc_hier_free", "spc_lift",
     "spc_spectral_error", "spc_validate_graph", "spc_timing_report", "spc_hier_cluster_map",
     "spc_spectral_error_graph", "spc_spectral_error_backward", "spc_entry_map",
-    "spc_contract_backward",
+    "spc_contract_backward", "spc_coarsen_batched", "spc_hier_graph_offsets",
 ]
 
 
@@ -101,6 +101,8 @@ def lib():
             "spc_spectral_error_backward": [p, C.POINTER(_Graph), p, i64, p, p, i32, p, p],
             "spc_entry_map": [p, C.POINTER(_Graph), p, C.POINTER(_Graph), p],
             "spc_contract_backward": [p, p, p, i64, i64, p, p, p, p],
+            "spc_coarsen_batched": [p, i32, C.POINTER(_Graph), p, p, i32, C.POINTER(C.c_void_p)],
+            "spc_hier_graph_offsets": [p, i32, p, i64],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -346,6 +348,59 @@ def coarsen_to(g: DeviceGraph, n_c: int, schedule: int = 0) -> Hierarchy:
     return Hierarchy(ctx, h, g.n)
 
 
+def pack_graphs(graphs):
+    """Host block-diagonal union of host graphs (node ids shifted) and the
+    node offsets (int64[G+1])."""
+    from meshgen import Graph
+    offs = np.zeros(len(graphs) + 1, dtype=np.int64)
+    for i, g in enumerate(graphs):
+        offs[i + 1] = offs[i] + g.n
+    eoffs = np.zeros(len(graphs) + 1, dtype=np.int64)
+    for i, g in enumerate(graphs):
+        eoffs[i + 1] = eoffs[i] + g.nnz
+    rp = np.empty(offs[-1] + 1, dtype=np.int64)
+    col = np.empty(eoffs[-1], dtype=np.int32)
+    w = np.empty(eoffs[-1], dtype=graphs[0].w.dtype)
+    for i, g in enumerate(graphs):
+        rp[offs[i]: offs[i + 1]] = g.row_ptr[:-1] + eoffs[i]
+        col[eoffs[i]: eoffs[i + 1]] = g.col + offs[i]
+        w[eoffs[i]: eoffs[i + 1]] = g.w
+    rp[-1] = eoffs[-1]
+    has_self = any(g.self_w is not None for g in graphs)
+    has_size = any(g.size is not None for g in graphs)
+    sw = np.concatenate([g.self_w_or_zero() for g in graphs]) if has_self else None
+    sz = np.concatenate([g.size_or_one() for g in graphs]) if has_size else None
+    return Graph(n=int(offs[-1]), row_ptr=rp, col=col, w=w, self_w=sw, size=sz), offs
+
+
+class BatchHierarchy(Hierarchy):
+    """Hierarchy of a batch: level l is the packed union of the graphs'
+    level-l graphs."""
+
+    def __init__(self, ctx, handle, n0, G):
+        super().__init__(ctx, handle, n0)
+        self.G = G
+
+    def offsets(self, lvl: int) -> np.ndarray:
+        out = np.zeros(self.G + 1, dtype=np.int64)
+        self.ctx.check(lib().spc_hier_graph_offsets(self.h, lvl, out.ctypes.data, self.G + 1))
+        return out
+
+
+def coarsen_batched(g: DeviceGraph, graph_off, n_c, schedule: int = 0) -> BatchHierarchy:
+    """Coarsen a packed batch (graph i owns nodes graph_off[i]..graph_off[i+1])
+    graph by graph to n_c[i], in shared launches."""
+    ctx = context(_dev(g.row_ptr))
+    off = np.ascontiguousarray(graph_off, dtype=np.int64)
+    nc = np.ascontiguousarray(n_c, dtype=np.int64)
+    G = off.shape[0] - 1
+    h = C.c_void_p()
+    gc = g._c()
+    ctx.check(lib().spc_coarsen_batched(ctx.h, G, C.byref(gc), off.ctypes.data, nc.ctypes.data,
+                                        int(schedule), C.byref(h)))
+    return BatchHierarchy(ctx, h, g.n, G)
+
+
 def lift(h: Hierarchy, from_lvl: int, to_lvl: int, mode: int, x_c: torch.Tensor) -> torch.Tensor:
     """Lift coarse vectors (n_to x k, float64) from level to_lvl to level from_lvl."""
     ctx = context(h.ctx.device)
@@ -447,7 +502,12 @@ class SpectralError(torch.autograd.Function):
     """loss(w_c, self_c) = sum_i (R_i - lambda_i)^2 of a coarse graph whose
     FP64 weights w_c (one value per CSR entry, symmetric) and self-loops
     self_c are the differentiable inputs; the structure, cmap, U and lambda
-    are fixed.  Forward and backward run in the library's kernels."""
+    are fixed.  Forward and backward run in the library's kernels.
+
+    An undirected weight w_ab is held at two entries; each entry receives
+    half of d loss / d w_ab, so the gradient is exact for every change that
+    keeps the graph symmetric (a parameter shared by both entries gets the
+    full derivative)."""
 
     @staticmethod
     def forward(ctx_, w_c, self_c, structure: DeviceGraph, cmap, U, lam):
@@ -463,7 +523,7 @@ class SpectralError(torch.autograd.Function):
     @staticmethod
     def backward(ctx_, grad):
         dw, ds = spectral_error_backward(ctx_.g, ctx_.cmap, ctx_.U, ctx_.lam)
-        return grad * dw, grad * ds, None, None, None, None
+        return grad * (0.5 * dw), grad * ds, None, None, None, None
 
 
 def spectral_error_loss(w_c, self_c, structure: DeviceGraph, cmap, U, lam):
