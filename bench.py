@@ -44,6 +44,16 @@ def make_config(name):
     if name == "grid2d-64":
         g = grid2d(64)
         return g, 1024, "2D 5-point grid 64x64, unit weights, halving to 1,024"
+    if name.startswith("batch-"):
+        from meshgen import batch_trimeshes
+        from paper_2204_11757_amd.spc import pack_graphs
+        count = int(name.split("-")[1])
+        graphs = batch_trimeshes(count, seed=4)
+        union, offs = pack_graphs(graphs)
+        union.meta = {"graphs": graphs, "offsets": offs, "n_c": [max(1, x.n // 10) for x in graphs]}
+        return union, None, (f"{count} jittered triangle meshes, sides uniform in [16,256] (seed 4), unit "
+                             f"weights, {union.n:,} nodes and {union.m:,} edges in total, each graph "
+                             f"halving to n/10")
     raise SystemExit(f"unknown config {name}")
 
 
@@ -143,6 +153,24 @@ def cpu_baseline(g, n_c):
                       f"time(s) by the serial C oracle on one host core"}
 
 
+def cpu_baseline_batch(graphs, n_c, seconds=10.0):
+    """The oracle on the batch's graphs in order, one coarsening each, until
+    about `seconds` of host time have passed, on one host core."""
+    import oracle
+    done, t_all = 0, 0.0
+    for x, c in zip(graphs, n_c):
+        t0 = time.perf_counter()
+        oracle.coarsen_to(x, c, 0)
+        t_all += time.perf_counter() - t0
+        done += 1
+        if t_all >= seconds:
+            break
+    return {"value": done / t_all, "unit": "graphs/s", "cores": 1, "kind": "oracle",
+            "seconds": round(t_all, 3),
+            "sample": f"the first {done} graphs of the batch, each coarsened to n/10 by the serial C "
+                      f"oracle on one host core"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,9 +202,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    batch = g.meta.get("graphs") is not None if isinstance(g.meta, dict) else False
+
     def step():
-        h = spc.coarsen_to(dg, n_c, 0)
-        return h
+        if batch:
+            return spc.coarsen_batched(dg, g.meta["offsets"], g.meta["n_c"], 0)
+        return spc.coarsen_to(dg, n_c, 0)
 
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     h = None
@@ -252,15 +283,36 @@ def main():
             if tr is not None:
                 roofline["traffic"] = int(tr)
 
+    per_graph = None
+    if batch:
+        # the same graphs coarsened by one coarsen_to call each (inputs resident)
+        G = len(g.meta["graphs"])
+        print(f"[bench] per-graph calls ({G} graphs)", file=sys.stderr, flush=True)
+        dgs = [spc.DeviceGraph.from_host(x, "cuda:0") for x in g.meta["graphs"]]
+        for x, c in zip(dgs[:8], g.meta["n_c"][:8]):
+            spc.coarsen_to(x, c, 0).free()
+        torch.cuda.synchronize()
+        t0.record()
+        for x, c in zip(dgs, g.meta["n_c"]):
+            spc.coarsen_to(x, c, 0).free()
+        t1.record()
+        torch.cuda.synchronize()
+        ms_pg = t0.elapsed_time(t1)
+        per_graph = {"graphs_per_s": G / (ms_pg * 1e-3), "ms_all_graphs": round(ms_pg, 3),
+                     "batched_speedup": (G / (ms * 1e-3)) / (G / (ms_pg * 1e-3))}
+        del dgs
+
     cpu = None
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle, one level)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(g, n_c)
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline_batch(g.meta["graphs"], g.meta["n_c"]) if batch else cpu_baseline(g, n_c)
 
+    if batch:
+        value = len(g.meta["graphs"]) / (ms * 1e-3)
     out = {
         "metric": METRIC,
         "value": value,
-        "unit": "fine edges/s",
+        "unit": "graphs/s" if batch else "fine edges/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -271,7 +323,10 @@ def main():
         "dtype": "int64",
         "data": "synthetic",
         "config": {"workload": desc, "name": args.config, "nodes": g.n, "edges": g.m,
-                   "n_c": n_c, "levels": len(levels), "schedule": "halving"},
+                   "n_c": n_c if not batch else "n/10 per graph", "levels": len(levels),
+                   "schedule": "halving"},
+        "fine_edges_per_s": total_edges / (ms * 1e-3),
+        "per_graph": per_graph,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "levels": levels,

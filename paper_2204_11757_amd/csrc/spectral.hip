@@ -77,8 +77,27 @@ __device__ __forceinline__ double cv_self(const CoarseView& g, int64_t a) {
   return g.fp ? ((const double*)g.self)[a] : (double)((const int64_t*)g.self)[a];
 }
 
+// Sums over a super-node's members and over a coarse row run in a fixed
+// order, so results are reproducible: one thread walks a short list in
+// order; a list longer than LONG_LIST is summed by one block with a fixed
+// shape (strided partial sums, then a tree), in a separate launch.
+constexpr int LONG_LIST = 2048;
+constexpr int SP_BS = 256;
+
+__device__ __forceinline__ double block_sum_fixed(double v, double* tmp) {
+  tmp[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = SP_BS / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) tmp[threadIdx.x] += tmp[threadIdx.x + o];
+    __syncthreads();
+  }
+  double r = tmp[0];
+  __syncthreads();
+  return r;
+}
+
 // y = Q^T u_i (members summed in ascending fine id), d = W_c row sums with
-// the diagonal, t = D_c^{-1/2} y
+// the diagonal, t = D_c^{-1/2} y; short lists here, long ones in k_restrict_long
 __global__ void k_restrict_scale(const uint64_t* __restrict__ sorted, const int32_t* __restrict__ mptr,
                                  const double* __restrict__ U, int64_t n0, int k, CoarseView g,
                                  double* __restrict__ t, double* __restrict__ dc) {
@@ -86,6 +105,7 @@ __global__ void k_restrict_scale(const uint64_t* __restrict__ sorted, const int3
   if (idx >= g.nc * k) return;
   int64_t a = idx % g.nc;
   int i = (int)(idx / g.nc);
+  if (mptr[a + 1] - mptr[a] > LONG_LIST || g.rp[a + 1] - g.rp[a] > LONG_LIST) return;
   double y = 0.0;
   for (int32_t p = mptr[a]; p < mptr[a + 1]; p++) {
     int64_t u = (int64_t)(sorted[p] & 0xffffffffull);
@@ -98,13 +118,38 @@ __global__ void k_restrict_scale(const uint64_t* __restrict__ sorted, const int3
   if (i == 0) dc[a] = d;
 }
 
-// z = W_c t (W_c with its diagonal, summed in ascending column), prod = t z
+// one block per super-node with a long member list or a long row
+__global__ void __launch_bounds__(SP_BS)
+    k_restrict_long(const uint64_t* __restrict__ sorted, const int32_t* __restrict__ mptr,
+                    const double* __restrict__ U, int64_t n0, int k, CoarseView g, double* __restrict__ t,
+                    double* __restrict__ dc) {
+  __shared__ double tmp[SP_BS];
+  int64_t a = blockIdx.x;
+  int32_t m0 = mptr[a], m1 = mptr[a + 1];
+  int64_t r0 = g.rp[a], r1 = g.rp[a + 1];
+  if (m1 - m0 <= LONG_LIST && r1 - r0 <= LONG_LIST) return;
+  double part = 0.0;
+  for (int64_t j = r0 + threadIdx.x; j < r1; j += SP_BS) part += cv_w(g, j);
+  double d = cv_self(g, a) + block_sum_fixed(part, tmp);
+  for (int i = 0; i < k; i++) {
+    part = 0.0;
+    for (int32_t p = m0 + threadIdx.x; p < m1; p += SP_BS)
+      part += U[(int64_t)(sorted[p] & 0xffffffffull) + n0 * i];
+    double y = block_sum_fixed(part, tmp) / sqrt((double)(g.size ? g.size[a] : 1));
+    if (threadIdx.x == 0) t[a + g.nc * i] = y / sqrt(d);
+  }
+  if (threadIdx.x == 0) dc[a] = d;
+}
+
+// z = W_c t (W_c with its diagonal, summed in ascending column), prod = t z;
+// short rows here, long ones in k_quad_long
 __global__ void k_quad(CoarseView g, int k, const double* __restrict__ t, double* __restrict__ z,
                        double* __restrict__ prod) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= g.nc * k) return;
   int64_t a = idx % g.nc;
   int i = (int)(idx / g.nc);
+  if (g.rp[a + 1] - g.rp[a] > LONG_LIST) return;
   const double* ti = t + g.nc * i;
   double s = cv_self(g, a);
   double acc = 0.0;
@@ -120,6 +165,25 @@ __global__ void k_quad(CoarseView g, int k, const double* __restrict__ t, double
   if (!placed) acc += s * ti[a];
   z[idx] = acc;
   prod[idx] = ti[a] * acc;
+}
+
+__global__ void __launch_bounds__(SP_BS)
+    k_quad_long(CoarseView g, int k, const double* __restrict__ t, double* __restrict__ z,
+                double* __restrict__ prod) {
+  __shared__ double tmp[SP_BS];
+  int64_t a = blockIdx.x;
+  int64_t r0 = g.rp[a], r1 = g.rp[a + 1];
+  if (r1 - r0 <= LONG_LIST) return;
+  for (int i = 0; i < k; i++) {
+    const double* ti = t + g.nc * i;
+    double part = 0.0;
+    for (int64_t j = r0 + threadIdx.x; j < r1; j += SP_BS) part += cv_w(g, j) * ti[g.col[j]];
+    double acc = block_sum_fixed(part, tmp) + cv_self(g, a) * ti[a];
+    if (threadIdx.x == 0) {
+      z[a + g.nc * i] = acc;
+      prod[a + g.nc * i] = ti[a] * acc;
+    }
+  }
 }
 
 // f_i = sum_a prod[a, i]: one block per i, fixed reduction shape
@@ -246,7 +310,10 @@ int spectral_impl(spc_ctx* ctx, const CoarseView& g, const int32_t* cmap_in, con
     double* Rout = R ? R : Rd;
     hipLaunchKernelGGL(k_restrict_scale, dim3(grid_for(nk, 256)), dim3(256), 0, st, sorted, mptr, U, n0, k,
                        g, t, dc);
+    hipLaunchKernelGGL(k_restrict_long, dim3((unsigned)nc), dim3(SP_BS), 0, st, sorted, mptr, U, n0, k, g, t,
+                       dc);
     hipLaunchKernelGGL(k_quad, dim3(grid_for(nk, 256)), dim3(256), 0, st, g, k, t, z, prod);
+    hipLaunchKernelGGL(k_quad_long, dim3((unsigned)nc), dim3(SP_BS), 0, st, g, k, t, z, prod);
     hipLaunchKernelGGL(k_colsum, dim3(k), dim3(256), 0, st, prod, nc, Rout);
     if (d_w) {
       hipLaunchKernelGGL(k_loss_coef, dim3(1), dim3(256), 0, st, Rout, lambda, k, coef);

@@ -55,7 +55,7 @@ def reweight(g: spc.DeviceGraph, cmap: torch.Tensor, U: torch.Tensor, lam: torch
         w, s = weights()
         loss = spc.spectral_error_loss(w, s, g, cmap, U, lam)
         loss.backward()
-        hist.append(float(loss))
+        hist.append(float(loss.detach()))
         opt.step()
     with torch.no_grad():
         w, s = weights()

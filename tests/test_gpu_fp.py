@@ -263,3 +263,39 @@ def test_reweight_lowers_the_spectral_error(P):
     gh = Graph(n=out.n, row_ptr=rp, col=col, w=w, self_w=host(out.self_w), size=host(out.size))
     loss_or, _ = osp.spectral_error(gh, cmap_or, U, lam)
     assert hist[-1] == pytest.approx(loss_or, rel=1e-10)
+
+
+def test_spectral_error_long_member_lists_and_rows(P):
+    # a power-law hub gives a coarse row longer than one thread walks; the
+    # first level of a bipartite grid gives a super-node with thousands of
+    # members: both take the block-reduction kernels
+    import torch
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    from meshgen import powerlaw_graph
+    for g, t, name in [(powerlaw_graph(20000, avg_deg=8.0, gamma=2.05, seed=5), 10000, "powerlaw-20000"),
+                       (grid3d(24, "lognormal", seed=5), 24 ** 3 // 2, "grid3d-24 lognormal")]:
+        say("spectral long lists", name)
+        Wd = osp.sparse_w(g)
+        d = np.asarray(Wd.sum(axis=1)).ravel()
+        s = 1.0 / np.sqrt(d)
+        L = (sp.identity(g.n) - sp.diags(s) @ Wd @ sp.diags(s)).tocsr()
+        lam, U = sla.eigsh(L, k=5, which="SA", tol=1e-12)
+        o = np.argsort(lam)
+        lam, U = lam[o][1:], np.ascontiguousarray(U[:, o][:, 1:])
+        dg = P.DeviceGraph.from_host(g)
+        cl, gc, st = P.coarsen_level(dg, t)
+        c_or, gc_or, _ = oracle.coarsen_level(g, t)
+        Ut, lt = torch.from_numpy(U).cuda(), torch.from_numpy(lam).cuda()
+        loss, R = P.spectral_error_graph(gc, cl, Ut, lt)
+        loss_or, R_or = osp.spectral_error(gc_or, c_or, U, lam)
+        assert loss == pytest.approx(loss_or, rel=1e-10)
+        np.testing.assert_allclose(host(R), R_or, rtol=1e-11, atol=1e-12)
+        dw, ds = P.spectral_error_backward(gc, cl, Ut, lt)
+        gw_or, gs_or = osp.spectral_error_grad(gc_or, c_or, U, lam)
+        scale = max(np.abs(gw_or).max(), np.abs(gs_or).max())
+        np.testing.assert_allclose(host(dw), gw_or, rtol=1e-9, atol=1e-11 * scale)
+        np.testing.assert_allclose(host(ds), gs_or, rtol=1e-9, atol=1e-11 * scale)
+        rp = host(gc.row_ptr)
+        members = np.bincount(c_or)
+        assert members.max() > 2048 or np.diff(rp).max() > 2048
