@@ -518,16 +518,25 @@ __device__ __forceinline__ int32_t huge_row_of(const int64_t* __restrict__ hoff,
 constexpr int HMB_BS = 256;
 constexpr int HMB_T = 1024;
 
+// The member count HM = hoff[H] is read on the device; the launch covers a
+// bound (>= HM) and positions HM..bound-1 get zero row lengths, so a scan
+// over the bound gives the member row prefix with its total at hlen[bound].
 __global__ void __launch_bounds__(HMB_BS)
     k_huge_members(LevelIn g, const int32_t* __restrict__ hugelist, const int32_t* __restrict__ mptr,
                    const int32_t* __restrict__ members, const int64_t* __restrict__ hoff, int64_t H,
-                   int64_t HM, int64_t* __restrict__ hlen, int32_t* __restrict__ hrow,
+                   int64_t bound, int64_t* __restrict__ hlen, int32_t* __restrict__ hrow,
                    int64_t* __restrict__ hrs, int64_t* self_out, int32_t* size_out) {
   __shared__ unsigned long long sself[HMB_T];
   __shared__ int32_t ssize[HMB_T];
   __shared__ int32_t sh0;
   int tid = threadIdx.x;
   int64_t i0 = (int64_t)blockIdx.x * HMB_T;
+  int64_t HM = hoff[H];
+  if (i0 >= HM) {
+    for (int k = tid; k < HMB_T; k += HMB_BS)
+      if (i0 + k < bound) hlen[i0 + k] = 0;
+    return;
+  }
   for (int k = tid; k < HMB_T; k += HMB_BS) {
     sself[k] = 0;
     ssize[k] = 0;
@@ -539,6 +548,7 @@ __global__ void __launch_bounds__(HMB_BS)
   for (int r = 0; r < HMB_T / HMB_BS; r++) {
     int64_t i = i0 + r * HMB_BS + tid;
     bool valid = i < HM;
+    if (!valid && i < bound) hlen[i] = 0;
     int32_t h = -1;
     int64_t self = 0;
     int32_t sz = 0;
@@ -586,7 +596,7 @@ static_assert(HT <= BLOCK_CAP, "a tile of gathered entries must meet at most two
 __global__ void __launch_bounds__(HT_BS)
     k_huge_entries(LevelIn g, const int32_t* __restrict__ c, const int32_t* __restrict__ hugelist,
                    const int32_t* __restrict__ hrow, const int64_t* __restrict__ hrs,
-                   const int64_t* __restrict__ hpre, int64_t HM, int64_t* self_out,
+                   const int64_t* __restrict__ hpre, int64_t bound, int64_t* self_out,
                    KW* __restrict__ out, unsigned long long* gcnt, TileScan ts) {
   __shared__ int32_t srow[Lbs<HT, HT_BS>::SIZE];
   __shared__ int64_t sh[2];
@@ -596,9 +606,13 @@ __global__ void __launch_bounds__(HT_BS)
   // two rows: h0 and h0 + 1
   __shared__ unsigned long long sself[2];
   int64_t q0 = (int64_t)blockIdx.x * HT;
-  int64_t total = hpre[HM];
-  lbs_tile<HT, HT_BS>(hpre, HM, q0, srow, sh, stmp);
+  int64_t total = hpre[bound];
   int tid = threadIdx.x;
+  if (q0 >= total) {   // past the gathered entries: an empty tile of the chain
+    block_reserve_lb<HT_BS>(ts, blockIdx.x, blockIdx.x == gridDim.x - 1, 0, nullptr, gcnt, &sbase, stmp);
+    return;
+  }
+  lbs_tile<HT, HT_BS>(hpre, bound, q0, srow, sh, stmp);
   if (tid < 2) sself[tid] = 0;
   int32_t h0 = hrow[srow[0]];
   __syncthreads();
@@ -655,15 +669,16 @@ __global__ void __launch_bounds__(HT_BS)
 __global__ void __launch_bounds__(HT_BS)
     k_huge_dense(LevelIn g, const int32_t* __restrict__ c, const int32_t* __restrict__ hugelist,
                  const int32_t* __restrict__ hrow, const int64_t* __restrict__ hrs,
-                 const int64_t* __restrict__ hpre, int64_t HM, int64_t* self_out,
+                 const int64_t* __restrict__ hpre, int64_t bound, int64_t* self_out,
                  uint32_t* __restrict__ dense, int64_t ncp) {
   __shared__ int32_t srow[Lbs<HT, HT_BS>::SIZE];
   __shared__ int64_t sh[2];
   __shared__ int32_t stmp[HT_BS / WAVE];
   __shared__ unsigned long long sself[2];
   int64_t q0 = (int64_t)blockIdx.x * HT;
-  int64_t total = hpre[HM];
-  lbs_tile<HT, HT_BS>(hpre, HM, q0, srow, sh, stmp);
+  int64_t total = hpre[bound];
+  if (q0 >= total) return;
+  lbs_tile<HT, HT_BS>(hpre, bound, q0, srow, sh, stmp);
   int tid = threadIdx.x;
   if (tid < 2) sself[tid] = 0;
   int32_t h0 = hrow[srow[0]];
@@ -871,36 +886,33 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
                        W.mptr, W.hmoff);
     rc = exclusive_scan<int64_t>(ctx, W.hmoff, W.hmoff, H, (int64_t*)W.scan_partial);
     if (rc) return rc;
-    int64_t HM = 0;
-    SPC_HIP(ctx, hipMemcpyAsync(&HM, W.hmoff + H, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    SPC_HIP(ctx, hipStreamSynchronize(st));
+    // member and entry totals stay on the device: launches cover bounds
+    // (n members, nnz entries) and read the totals there
     int64_t* hpre = W.hpos;   // member row lengths, then their prefix
-    hipLaunchKernelGGL(k_huge_members, dim3(grid_for(HM, HMB_T)), dim3(HMB_BS), 0, st, g, W.hugelist,
-                       W.mptr, W.members, W.hmoff, H, HM, hpre, W.hmrow, W.hmrs, self_out, out->size);
-    rc = exclusive_scan<int64_t>(ctx, hpre, hpre, HM, (int64_t*)W.scan_partial);
+    hipLaunchKernelGGL(k_huge_members, dim3(grid_for(n, HMB_T)), dim3(HMB_BS), 0, st, g, W.hugelist, W.mptr,
+                       W.members, W.hmoff, H, n, hpre, W.hmrow, W.hmrs, self_out, out->size);
+    rc = exclusive_scan<int64_t>(ctx, hpre, hpre, n, (int64_t*)W.scan_partial);
     if (rc) return rc;
-    int64_t Etot = 0;
-    SPC_HIP(ctx, hipMemcpyAsync(&Etot, hpre + HM, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    SPC_HIP(ctx, hipMemsetAsync(&info[I_LIVE1], 0, sizeof(unsigned long long), st));
-    SPC_HIP(ctx, hipStreamSynchronize(st));
     // few huge rows: dense accumulators over the coarse ids (they fit in
     // the gather buffers when H * ncp <= 2 nnz)
     int64_t ncp = (n_c + DC_T - 1) / DC_T * DC_T;
-    if (Etot > 0 && !ctx->force_huge_sort && H * ncp <= 2 * g.nnz) {
+    if (!ctx->force_huge_sort && H * ncp <= 2 * g.nnz) {
       uint32_t* dense = (uint32_t*)W.gkeyA;
       SPC_HIP(ctx, hipMemsetAsync(dense, 0, sizeof(uint32_t) * (size_t)(H * ncp), st));
-      hipLaunchKernelGGL(k_huge_dense, dim3(grid_for(Etot, HT)), dim3(HT_BS), 0, st, g, c, W.hugelist,
-                         W.hmrow, W.hmrs, hpre, HM, self_out, dense, ncp);
+      if (g.nnz > 0)
+        hipLaunchKernelGGL(k_huge_dense, dim3(grid_for(g.nnz, HT)), dim3(HT_BS), 0, st, g, c, W.hugelist,
+                           W.hmrow, W.hmrs, hpre, n, self_out, dense, ncp);
       int64_t tpr = ncp / DC_T;
       hipLaunchKernelGGL(k_dense_compact, dim3((unsigned)(H * tpr)), dim3(DC_BS), 0, st, dense, ncp, n_c,
                          tpr, W.hugelist, W.gptr, W.temp, W.cnt, next_scan(ctx, W));
       SPC_LAUNCH_CHECK(ctx, "huge dense");
     } else {
+    SPC_HIP(ctx, hipMemsetAsync(&info[I_LIVE1], 0, sizeof(unsigned long long), st));
     KW* A = (KW*)W.gkeyA;
     KW* B = (KW*)W.gkeyB;
-    if (Etot > 0) {
-      hipLaunchKernelGGL(k_huge_entries, dim3(grid_for(Etot, HT)), dim3(HT_BS), 0, st, g, c, W.hugelist,
-                         W.hmrow, W.hmrs, hpre, HM, self_out, A, &info[I_LIVE1], next_scan(ctx, W));
+    if (g.nnz > 0) {
+      hipLaunchKernelGGL(k_huge_entries, dim3(grid_for(g.nnz, HT)), dim3(HT_BS), 0, st, g, c, W.hugelist,
+                         W.hmrow, W.hmrs, hpre, n, self_out, A, &info[I_LIVE1], next_scan(ctx, W));
       SPC_LAUNCH_CHECK(ctx, "huge gather");
     }
     int64_t G = 0;
