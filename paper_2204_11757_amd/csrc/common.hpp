@@ -156,6 +156,16 @@ struct Lbs {
 // [p0, p0 + T) of a CSR-like prefix array ptr[0..nrows] onto rows:
 // srow[Lbs<T,BS>::at(k)] = row containing position p0 + k (srow holds
 // Lbs<T,BS>::SIZE words).  Called by all BS threads.
+// Workgroups are dispatched round-robin over the chip's 8 XCDs, each with its
+// own L2.  xcd_tile renumbers block b of G so that every XCD takes one
+// contiguous run of tiles: neighbouring tiles, which read and write the same
+// cache lines (mirror entries, neighbouring rows), then share an L2.  It is
+// a bijection on [0, G) for any G.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) {
+  int64_t x = b & 7, i = b >> 3, q = G >> 3, r = G & 7;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 template <int T, int BS>
 __device__ __forceinline__ void lbs_tile(const int64_t* __restrict__ ptr, int64_t nrows, int64_t p0,
                                          int32_t* srow, int64_t* sh, int32_t* scan_tmp) {

@@ -834,8 +834,8 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
   int rc;
   {
     TimedScope ts(ctx, "contract_members", (double)n);
-    SPC_HIP(ctx, hipMemsetAsync(W.mcount, 0, sizeof(int32_t) * (n_c + 1), st));
-    SPC_HIP(ctx, hipMemsetAsync(W.gptr, 0, sizeof(int64_t) * (n_c + 1), st));
+    launch_clear(ctx, W.mcount, n_c + 1, (uint64_t*)W.gptr, n_c + 1, info,
+                 (1u << I_MID) | (1u << I_HUGE) | (1u << I_MAXCL) | (1u << I_BLOCK) | (1u << I_R32));
     hipLaunchKernelGGL(k_cluster_count, dim3(grid_for(n, CM_BS)), dim3(CM_BS), 0, st, g, c, W.mcount,
                        (unsigned long long*)W.gptr);
     SPC_LAUNCH_CHECK(ctx, "cluster_count");
@@ -846,10 +846,6 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
     hipLaunchKernelGGL(k_member_scatter, dim3(grid_for(n, CM_BS)), dim3(CM_BS), 0, st, c, W.mptr,
                        W.mcount, W.members, n);
   }
-  SPC_HIP(ctx, hipMemsetAsync(&info[I_MID], 0, sizeof(unsigned long long) * 2, st));
-  SPC_HIP(ctx, hipMemsetAsync(&info[I_MAXCL], 0, sizeof(unsigned long long), st));
-  SPC_HIP(ctx, hipMemsetAsync(&info[I_BLOCK], 0, sizeof(unsigned long long), st));
-  SPC_HIP(ctx, hipMemsetAsync(&info[I_R32], 0, sizeof(unsigned long long), st));
   {
     TimedScope ts(ctx, "contract_small", (double)g.nnz);
     hipLaunchKernelGGL(k_contract_small, dim3(grid_for(n_c, SMALL_BS * SMALL_RPT)), dim3(SMALL_BS), 0,
@@ -857,8 +853,9 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
                        W.r32list, W.midlist, W.blocklist, W.hugelist, info, next_scan(ctx, W));
   }
   SPC_LAUNCH_CHECK(ctx, "contract_small");
-  SPC_HIP(ctx, hipMemcpyAsync(hinfo, info, sizeof(unsigned long long) * I_NINFO,
-                              hipMemcpyDeviceToHost, st));
+  hipLaunchKernelGGL(k_readback, dim3(1), dim3(64), 0, st, info, (int)I_NINFO, (const int64_t*)nullptr,
+                     (const int32_t*)nullptr, (const uint64_t*)nullptr, hinfo);
+  SPC_LAUNCH_CHECK(ctx, "readback");
   SPC_HIP(ctx, hipStreamSynchronize(st));
   int64_t nr32 = hinfo[I_R32], nmid = hinfo[I_MID], nblk = hinfo[I_BLOCK], H = hinfo[I_HUGE];
   R.maxcl = hinfo[I_MAXCL];
@@ -898,7 +895,7 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
     int64_t ncp = (n_c + DC_T - 1) / DC_T * DC_T;
     if (!ctx->force_huge_sort && H * ncp <= 2 * g.nnz) {
       uint32_t* dense = (uint32_t*)W.gkeyA;
-      SPC_HIP(ctx, hipMemsetAsync(dense, 0, sizeof(uint32_t) * (size_t)(H * ncp), st));
+      launch_clear(ctx, (int32_t*)dense, H * ncp, nullptr, 0, nullptr, 0u);
       if (g.nnz > 0)
         hipLaunchKernelGGL(k_huge_dense, dim3(grid_for(g.nnz, HT)), dim3(HT_BS), 0, st, g, c, W.hugelist,
                            W.hmrow, W.hmrs, hpre, n, self_out, dense, ncp);
@@ -907,7 +904,7 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
                          tpr, W.hugelist, W.gptr, W.temp, W.cnt, next_scan(ctx, W));
       SPC_LAUNCH_CHECK(ctx, "huge dense");
     } else {
-    SPC_HIP(ctx, hipMemsetAsync(&info[I_LIVE1], 0, sizeof(unsigned long long), st));
+    launch_clear(ctx, nullptr, 0, nullptr, 0, info, 1u << I_LIVE1);
     KW* A = (KW*)W.gkeyA;
     KW* B = (KW*)W.gkeyB;
     if (g.nnz > 0) {
@@ -915,9 +912,12 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
                          W.hmrow, W.hmrs, hpre, n, self_out, A, &info[I_LIVE1], next_scan(ctx, W));
       SPC_LAUNCH_CHECK(ctx, "huge gather");
     }
-    int64_t G = 0;
-    SPC_HIP(ctx, hipMemcpyAsync(&G, &info[I_LIVE1], sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    hipLaunchKernelGGL(k_readback, dim3(1), dim3(64), 0, st, (const unsigned long long*)nullptr, 0,
+                       (const int64_t*)&info[I_LIVE1], (const int32_t*)nullptr, (const uint64_t*)nullptr,
+                       hinfo);
+    SPC_LAUNCH_CHECK(ctx, "readback");
     SPC_HIP(ctx, hipStreamSynchronize(st));
+    int64_t G = hinfo[I_NINFO];
     KW* sorted = A;
     if (G > 0) {
       rc = merge_sort<KW, LessKW>(ctx, A, B, G, LessKW(), &sorted);
@@ -953,16 +953,13 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
     rc = exclusive_scan<int64_t>(ctx, W.cnt, out->row_ptr, n_c, (int64_t*)W.scan_partial);
     if (rc) return rc;
   }
-  int64_t nnz_c = 0;
-  SPC_HIP(ctx, hipMemcpyAsync(&nnz_c, out->row_ptr + n_c, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  SPC_HIP(ctx, hipMemcpyAsync(hinfo, info, sizeof(unsigned long long) * I_NINFO,
-                              hipMemcpyDeviceToHost, st));
-  hinfo[I_NINFO] = 0;
-  if (ctx->scan_state)
-    SPC_HIP(ctx, hipMemcpyAsync(&hinfo[I_NINFO], ctx->scan_state + ctx->scan_cap - 1, sizeof(uint64_t),
-                                hipMemcpyDeviceToHost, st));
+  hipLaunchKernelGGL(k_readback, dim3(1), dim3(64), 0, st, info, (int)I_NINFO,
+                     (const int64_t*)(out->row_ptr + n_c), (const int32_t*)nullptr,
+                     (const uint64_t*)(ctx->scan_state ? ctx->scan_state + ctx->scan_cap - 1 : nullptr), hinfo);
+  SPC_LAUNCH_CHECK(ctx, "readback");
   SPC_HIP(ctx, hipStreamSynchronize(st));
-  if (hinfo[I_LBERR] || hinfo[I_NINFO])
+  int64_t nnz_c = hinfo[I_NINFO];
+  if (hinfo[I_LBERR] || hinfo[I_NINFO + 2])
     return set_error(ctx, SPC_EINVAL, "internal: look-back wait gave up");
   if (nnz_c > out->nnz_cap)
     return set_error(ctx, SPC_ECAPACITY, "coarse graph needs %lld entries, capacity %lld",

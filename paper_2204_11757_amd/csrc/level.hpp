@@ -30,6 +30,11 @@ struct spc_hier {
 namespace spc {
 
 constexpr int BS = 256;   // block size of the selection kernels
+// Rows longer than HUGE_T are registered by the degree pass; the first H_MAX
+// of them get a dense column -> position map, so the score of each of their
+// edges looks columns up instead of searching the long row.
+constexpr int HUGE_T = 1024;
+constexpr int H_MAX = 4;
 
 // Device view of an integer-path input graph.
 struct LevelIn {
@@ -101,7 +106,7 @@ enum Info : int {
   I_MSF = 4,
   I_MID = 5,
   I_HUGE = 6,
-  I_SPARE7 = 7,   // unused
+  I_LONGROW = 7,  // rows longer than HUGE_T (the first H_MAX get a position map)
   I_BAD = 8,
   I_NC = 9,
   I_MAXCL = 10,
@@ -182,6 +187,8 @@ struct LevelWork {
   int32_t* hmnode;           // [n]
   int64_t* hpos;             // [n+1] huge member -> gathered offset
   int64_t* hmrs;             // [n]  huge member -> its first CSR position
+  int32_t* htab;             // [H_MAX] rows longer than HUGE_T, in registration order
+  int32_t* hmap;             // [H_MAX * n] per such row: column -> position in the row
   uint64_t* gkeyA;           // [nnz] (key, w) pairs, 16 bytes each
   uint64_t* gkeyB;           // [nnz]
   // floating-point path only (null on the integer path)

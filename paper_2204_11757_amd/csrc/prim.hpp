@@ -229,6 +229,20 @@ __global__ void k_sel_pass(const uint64_t* __restrict__ keys, const unsigned lon
                            int64_t cnt_host, SelState* st, int shift, int width, int fused);
 __global__ void k_sel_pick(SelState* st, int shift, int width);
 
+// Small launches that replace the runtime's fill and copy blits on the
+// level path (each blit costs the host far more than a plain launch).
+// k_clear zeroes a[0, na), b[0, nb) and the info slots whose bit is set in
+// `slots`; k_readback copies the info block (I_NINFO words, when info is not
+// null) and up to three scalars (null: 0) into host-visible pinned memory
+// at out[0..I_NINFO) and out[I_NINFO..I_NINFO+3); k_copy_u64 copies one word.
+__global__ void k_clear(int32_t* a, int64_t na, uint64_t* b, int64_t nb, unsigned long long* info,
+                        uint32_t slots);
+__global__ void k_readback(const unsigned long long* info, int ninfo, const int64_t* x0,
+                           const int32_t* x1, const uint64_t* x2, int64_t* out);
+__global__ void k_copy_u64(unsigned long long* dst, const unsigned long long* src);
+void launch_clear(spc_ctx* ctx, int32_t* a, int64_t na, uint64_t* b, int64_t nb, unsigned long long* info,
+                  uint32_t slots);
+
 // After the call st->prefix holds the selected key (device memory).
 int radix_select(spc_ctx* ctx, const uint64_t* keys, const unsigned long long* cnt_dev,
                  int64_t cnt_bound, const unsigned long long* k_dev, unsigned long long k_host,

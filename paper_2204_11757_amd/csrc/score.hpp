@@ -16,69 +16,6 @@ namespace spc {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
-__device__ __forceinline__ uint64_t common_min_sum(const int32_t* __restrict__ col,
-                                                   const int32_t* __restrict__ w, int64_t as,
-                                                   int64_t ae, uint64_t fa, int64_t bs, int64_t be,
-                                                   uint64_t fb) {
-  // sum over x in both rows of min(w_a[x] * fa, w_b[x] * fb); rows ascending.
-  uint64_t M = 0;
-  int64_t la = ae - as, lb = be - bs;
-  if (la > 4 * lb && la > 32) {
-    // walk the short row b, galloping search in the long row a
-    int64_t lo = as;
-    for (int64_t j = bs; j < be && lo < ae; j++) {
-      int32_t x = col[j];
-      int64_t hi = ae;
-      while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (col[mid] < x) lo = mid + 1;
-        else hi = mid;
-      }
-      if (lo < ae && col[lo] == x) {
-        M += umin64((uint64_t)w[lo] * fa, (uint64_t)w[j] * fb);
-        lo++;
-      }
-    }
-    return M;
-  }
-  if (lb > 4 * la && lb > 32) {
-    int64_t lo = bs;
-    for (int64_t i = as; i < ae && lo < be; i++) {
-      int32_t x = col[i];
-      int64_t hi = be;
-      while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (col[mid] < x) lo = mid + 1;
-        else hi = mid;
-      }
-      if (lo < be && col[lo] == x) {
-        M += umin64((uint64_t)w[i] * fa, (uint64_t)w[lo] * fb);
-        lo++;
-      }
-    }
-    return M;
-  }
-  int64_t i = as, j = bs;
-  if (i < ae && j < be) {
-    int32_t x = col[i], y = col[j];
-    while (true) {
-      if (x < y) {
-        if (++i >= ae) break;
-        x = col[i];
-      } else if (x > y) {
-        if (++j >= be) break;
-        y = col[j];
-      } else {
-        M += umin64((uint64_t)w[i] * fa, (uint64_t)w[j] * fb);
-        if (++i >= ae || ++j >= be) break;
-        x = col[i];
-        y = col[j];
-      }
-    }
-  }
-  return M;
-}
-
 // position of u in row v (u < v, so it lies among v's lower entries)
 __device__ __forceinline__ int64_t mirror_pos(const LevelIn& g, const int32_t* __restrict__ lc,
                                               int32_t v, int32_t u) {
@@ -91,10 +28,173 @@ __device__ __forceinline__ int64_t mirror_pos(const LevelIn& g, const int32_t* _
   return lo;
 }
 
-// Rows of at most RC entries are read into registers with all loads issued
-// at once (the common-support walk over global memory would chain one
-// dependent load per step); longer rows take the walk.
+// Rows are read into registers in chunks of RC entries with all loads of a
+// chunk issued at once: a walk over global memory one entry at a time would
+// chain one dependent load per step.
 constexpr int RC = 8;
+
+__device__ __forceinline__ int32_t chunk_last(const int32_t (&c)[RC], int64_t left) {
+  // largest valid column of a chunk (rows ascending, so its last)
+  int32_t m = INT32_MIN;
+#pragma unroll
+  for (int k = 0; k < RC; k++) m = (k < left && c[k] > m) ? c[k] : m;
+  return m;
+}
+
+// Common-support sum of rows a = [as, ae) and b = [bs, be), a merge over
+// chunks: after comparing the current chunks pair by pair, the chunk with
+// the smaller last column advances (both on a tie), so every pair of chunks
+// that can share a column meets exactly once and each step costs one round
+// of independent loads.  Returns sum min(w_a[x] fa, w_b[x] fb); below counts
+// b's columns smaller than lim, complete says whether that count is final.
+__device__ __forceinline__ uint64_t chunk_merge_sum(const int32_t* __restrict__ col,
+                                                    const int32_t* __restrict__ w, int64_t as,
+                                                    int64_t ae, uint64_t fa, int64_t bs, int64_t be,
+                                                    uint64_t fb, int32_t lim, int64_t& below,
+                                                    bool& complete) {
+  int32_t ca[RC], cb[RC];
+  uint32_t wa[RC], wb[RC];
+  uint64_t M = 0;
+  bool seen = false;
+  below = 0;
+#pragma unroll
+  for (int k = 0; k < RC; k++) {
+    bool pa = as + k < ae, pb = bs + k < be;
+    ca[k] = pa ? col[as + k] : -1;   // distinct sentinels never match
+    wa[k] = pa ? (uint32_t)w[as + k] : 0u;
+    cb[k] = pb ? col[bs + k] : -2;
+    wb[k] = pb ? (uint32_t)w[bs + k] : 0u;
+  }
+#pragma unroll
+  for (int k = 0; k < RC; k++) {
+    below += (cb[k] >= 0 && cb[k] < lim) ? 1 : 0;
+    seen |= cb[k] >= lim;
+  }
+  int64_t i = as, j = bs;
+  while (i < ae && j < be) {
+#pragma unroll
+    for (int p = 0; p < RC; p++) {
+      uint32_t mw = 0;
+#pragma unroll
+      for (int q = 0; q < RC; q++) mw = (ca[p] == cb[q]) ? wb[q] : mw;
+      if (mw) M += umin64((uint64_t)wa[p] * fa, (uint64_t)mw * fb);
+    }
+    int32_t la = chunk_last(ca, ae - i), lb = chunk_last(cb, be - j);
+    if (la <= lb) {
+      i += RC;
+#pragma unroll
+      for (int k = 0; k < RC; k++) {
+        bool pa = i + k < ae;
+        ca[k] = pa ? col[i + k] : -1;
+        wa[k] = pa ? (uint32_t)w[i + k] : 0u;
+      }
+    }
+    if (lb <= la) {
+      j += RC;
+#pragma unroll
+      for (int k = 0; k < RC; k++) {
+        bool pb = j + k < be;
+        cb[k] = pb ? col[j + k] : -2;
+        wb[k] = pb ? (uint32_t)w[j + k] : 0u;
+      }
+#pragma unroll
+      for (int k = 0; k < RC; k++) {
+        below += (cb[k] >= 0 && cb[k] < lim) ? 1 : 0;
+        seen |= cb[k] >= lim;
+      }
+    }
+  }
+  complete = seen || j >= be;
+  return M;
+}
+
+constexpr int RS = 4;   // narrower than RC: each search keeps four values per column
+
+// Common-support sum when row t = [ts, te) is much longer than row p =
+// [ps, pe): p is read in chunks of RS and each column of a chunk is located in t by
+// a branchless binary search (the largest position whose column is <= x),
+// all searches of a chunk in step.  Returns sum min(w_p[x] fp, w_t[x] ft) and
+// the number of p's columns smaller than lim.
+__device__ __forceinline__ uint64_t chunk_search_sum(const int32_t* __restrict__ col,
+                                                     const int32_t* __restrict__ w, int64_t ps,
+                                                     int64_t pe, uint64_t fp, int64_t ts, int64_t te,
+                                                     uint64_t ft, int32_t lim, int64_t& below) {
+  uint64_t M = 0;
+  below = 0;
+  int32_t lt = (int32_t)(te - ts);
+  int32_t t0 = col[ts];
+  for (int64_t c = ps; c < pe; c += RS) {
+    int32_t x[RS], base[RS], val[RS];
+    uint32_t wx[RS];
+#pragma unroll
+    for (int k = 0; k < RS; k++) {
+      bool in = c + k < pe;
+      x[k] = in ? col[c + k] : -1;
+      wx[k] = in ? (uint32_t)w[c + k] : 0u;
+      base[k] = 0;
+      val[k] = t0;
+      below += (in && x[k] < lim) ? 1 : 0;
+    }
+    for (int32_t n = lt; n > 1;) {
+      int32_t half = n >> 1;
+#pragma unroll
+      for (int k = 0; k < RS; k++) {
+        int32_t y = col[ts + base[k] + half];
+        if (y <= x[k]) {
+          base[k] += half;
+          val[k] = y;
+        }
+      }
+      n -= half;
+    }
+#pragma unroll
+    for (int k = 0; k < RS; k++)
+      if (x[k] >= 0 && val[k] == x[k])
+        M += umin64((uint64_t)wx[k] * fp, (uint64_t)(uint32_t)w[ts + base[k]] * ft);
+  }
+  return M;
+}
+
+__device__ __forceinline__ int ceil_log2(int64_t x) { return x <= 1 ? 0 : 64 - __clzll(x - 1); }
+
+// Common-support sum when row T has a dense position map tmap (column ->
+// position in T, stale entries allowed): row P is read in chunks of RC with
+// every load of a chunk independent, and each column is looked up in the
+// map and confirmed against T.  Returns the sum of min(w_P[x] fp, w_T[x] ft)
+// and, in below, the number of P's columns smaller than lim.
+__device__ __forceinline__ uint64_t mapped_min_sum(const int32_t* __restrict__ col,
+                                                   const int32_t* __restrict__ w, int64_t ps,
+                                                   int64_t pe, uint64_t fp, int64_t ts, int64_t te,
+                                                   uint64_t ft, const int32_t* __restrict__ tmap,
+                                                   int32_t lim, int64_t& below) {
+  uint64_t M = 0;
+  uint32_t lt = (uint32_t)(te - ts);
+  below = 0;
+  for (int64_t c = ps; c < pe; c += RC) {
+    int32_t x[RC], p[RC];
+    uint32_t wp[RC];
+#pragma unroll
+    for (int k = 0; k < RC; k++) {
+      bool in = c + k < pe;
+      x[k] = in ? col[c + k] : -1;
+      wp[k] = in ? (uint32_t)w[c + k] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < RC; k++) {
+      p[k] = x[k] >= 0 ? tmap[x[k]] : -1;
+      below += (x[k] >= 0 && x[k] < lim) ? 1 : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < RC; k++) {
+      if ((uint32_t)p[k] < lt) {
+        int32_t y = col[ts + p[k]];
+        uint32_t wt = (uint32_t)w[ts + p[k]];
+        if (y == x[k]) M += umin64((uint64_t)wp[k] * fp, (uint64_t)wt * ft);
+      }
+    }
+  }
+  return M;
+}
 
 // Also returns jm, the CSR position of the mirror entry (v -> u).
 __device__ __forceinline__ void edge_score(const LevelIn& g, const uint64_t* __restrict__ deg,
@@ -129,8 +229,23 @@ __device__ __forceinline__ void edge_score(const LevelIn& g, const uint64_t* __r
       if (mw) M += umin64((uint64_t)wu[i] * dv, (uint64_t)mw * du);
     }
   } else {
-    M = common_min_sum(g.col, g.w, au, bu, dv, av, bv, du);
-    jm = mirror_pos(g, lc, v, u);
+    // rounds of loads: the chunk merge reads both rows once; the search
+    // reads the short row once and log2(long) entries per chunk of it
+    int64_t ls = lu < lv ? lu : lv, ll = lu < lv ? lv : lu;
+    int64_t c_merge = (lu + RC - 1) / RC + (lv + RC - 1) / RC;
+    int64_t c_search = (ls + RS - 1) / RS * (ceil_log2(ll) + 2);
+    int64_t below;
+    if (c_search < c_merge && lv <= lu) {
+      M = chunk_search_sum(g.col, g.w, av, bv, du, au, bu, dv, u, below);
+      jm = av + below;
+    } else if (c_search < c_merge) {
+      M = chunk_search_sum(g.col, g.w, au, bu, dv, av, bv, du, INT32_MIN, below);
+      jm = mirror_pos(g, lc, v, u);
+    } else {
+      bool complete;
+      M = chunk_merge_sum(g.col, g.w, au, bu, dv, av, bv, du, u, below, complete);
+      jm = complete ? av + below : mirror_pos(g, lc, v, u);
+    }
   }
   if (su) M += umin64(su * dv, (uint64_t)wuv * du);   // x = u
   if (sv) M += umin64((uint64_t)wuv * dv, sv * du);   // x = v

@@ -67,6 +67,8 @@ void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W, bool fp) {
   W.hmnode = A.take<int32_t>(n);
   W.hpos = A.take<int64_t>(n + 1);
   W.hmrs = A.take<int64_t>(n);
+  W.htab = A.take<int32_t>(H_MAX);
+  W.hmap = A.take<int32_t>((int64_t)H_MAX * n);
   W.gkeyA = A.take<uint64_t>(2 * nnz + 8);
   W.gkeyB = A.take<uint64_t>(2 * nnz + 8);
   if (fp) {
@@ -96,7 +98,7 @@ __global__ void __launch_bounds__(BS)
     k_degree(LevelIn g, uint64_t* __restrict__ deg, int32_t* __restrict__ lc,
              int64_t* __restrict__ ucnt, uint64_t* __restrict__ bestA,
              uint64_t* __restrict__ bestB, int32_t* __restrict__ parent,
-             uint64_t* __restrict__ part, unsigned long long* info) {
+             uint64_t* __restrict__ part, int32_t* __restrict__ htab, unsigned long long* info) {
   __shared__ int stmp[BS / WAVE];
   __shared__ uint64_t smx[BS / WAVE], ssm[BS / WAVE];
   __shared__ int32_t slong[DEG_ROWS];
@@ -151,6 +153,11 @@ __global__ void __launch_bounds__(BS)
       deg[u] = t;
       mx = t > mx ? t : mx;
       sm += t;
+      if (e - s > HUGE_T) {
+        // few rows are this long, so one atomic each stays cheap
+        unsigned long long slot = atomicAdd(&info[I_LONGROW], 1ull);
+        if (slot < (unsigned long long)H_MAX) htab[slot] = (int32_t)u;
+      }
     }
     __syncthreads();
   }
@@ -658,6 +665,37 @@ int radix_select(spc_ctx* ctx, const uint64_t* keys, const unsigned long long* c
 // ---------------------------------------------------------------------------
 __global__ void k_set_u64(unsigned long long* p, unsigned long long v) { *p = v; }
 
+__global__ void k_clear(int32_t* a, int64_t na, uint64_t* b, int64_t nb, unsigned long long* info,
+                        uint32_t slots) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = i0; i < na; i += stride) a[i] = 0;
+  for (int64_t i = i0; i < nb; i += stride) b[i] = 0;
+  if (info && i0 < 32 && (slots >> i0 & 1u)) info[i0] = 0;
+}
+
+void launch_clear(spc_ctx* ctx, int32_t* a, int64_t na, uint64_t* b, int64_t nb, unsigned long long* info,
+                  uint32_t slots) {
+  int64_t big = na > nb ? na : nb;
+  if (big < 32) big = 32;
+  hipLaunchKernelGGL(k_clear, dim3(grid_for(big, 256, ctx->num_cus * 4)), dim3(256), 0, ctx->stream, a, na,
+                     b, nb, info, slots);
+}
+
+__global__ void k_readback(const unsigned long long* info, int ninfo, const int64_t* x0,
+                           const int32_t* x1, const uint64_t* x2, int64_t* out) {
+  int t = threadIdx.x;
+  if (info && t < ninfo) out[t] = (int64_t)info[t];
+  if (t == 0) {
+    out[I_NINFO] = x0 ? *x0 : 0;
+    out[I_NINFO + 1] = x1 ? (int64_t)*x1 : 0;
+    out[I_NINFO + 2] = x2 ? (int64_t)*x2 : 0;
+  }
+  __threadfence_system();
+}
+
+__global__ void k_copy_u64(unsigned long long* dst, const unsigned long long* src) { *dst = *src; }
+
 __global__ void k_fill_u64(uint64_t* __restrict__ a, int64_t n, uint64_t v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) a[i] = v;
@@ -673,9 +711,12 @@ __global__ void k_thr_from_sel(const SelState* st, unsigned long long* thr, int 
   else *thr = st->prefix;
 }
 
-static int sync_info(spc_ctx* ctx, const LevelWork& W) {
-  SPC_HIP(ctx, hipMemcpyAsync(ctx->h_pinned, W.info, sizeof(unsigned long long) * I_NINFO,
-                              hipMemcpyDeviceToHost, ctx->stream));
+// Info block (and up to three scalars) to the pinned host copy, then wait.
+static int sync_info(spc_ctx* ctx, const LevelWork& W, const int64_t* x0 = nullptr,
+                     const int32_t* x1 = nullptr, const uint64_t* x2 = nullptr) {
+  hipLaunchKernelGGL(k_readback, dim3(1), dim3(64), 0, ctx->stream, W.info, (int)I_NINFO, x0, x1, x2,
+                     ctx->h_pinned);
+  SPC_LAUNCH_CHECK(ctx, "readback");
   SPC_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return SPC_OK;
 }
@@ -849,7 +890,7 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestA, n, KEY_INF);
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestB, n, KEY_INF);
       // the previous band's upper bound is this band's lower bound
-      SPC_HIP(ctx, hipMemcpyAsync(thr_lo, thr_hi, sizeof(unsigned long long), hipMemcpyDeviceToDevice, st));
+      hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(1), 0, st, thr_lo, thr_hi);
     }
     if (all) {
       hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits, guard);
@@ -920,10 +961,9 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
   int64_t k = n - t;  // merges
   unsigned long long* info = W.info;
   int64_t* hinfo = ctx->h_pinned;
-  SPC_HIP(ctx, hipMemsetAsync(info, 0, sizeof(unsigned long long) * I_NINFO, st));
   ctx->lb_words = lb_words(n, g.nnz);
   ctx->lb_epoch = 0;
-  SPC_HIP(ctx, hipMemsetAsync(W.lbstate, 0, sizeof(uint64_t) * (size_t)ctx->lb_words, st));
+  launch_clear(ctx, nullptr, 0, W.lbstate, ctx->lb_words, info, 0xffffffffu);
 
   // A1
   int nb = grid_for(n, DEG_ROWS);
@@ -934,7 +974,7 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
     {
       TimedScope ts(ctx, "degree", (double)n);
       hipLaunchKernelGGL(k_degree, dim3(nb), dim3(BS), 0, st, g, W.deg, W.lc, W.uptr, W.bestA, W.bestB,
-                         W.parent, W.degpart, info);
+                         W.parent, W.degpart, W.htab, info);
     }
     TimedScope ts(ctx, "degree_total", (double)nb);
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, st, W.degpart, (int64_t)nb, &info[I_TOTAL]);
@@ -965,10 +1005,9 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
   for (int pass = 0; pass < 2; pass++) {
     if (pass == 1) {
       rank = true;
-      SPC_HIP(ctx, hipMemsetAsync(&info[I_MSF], 0, sizeof(unsigned long long), st));
-      SPC_HIP(ctx, hipMemsetAsync(&info[I_ROUNDS], 0, sizeof(unsigned long long) * (I_MSF0 - I_ROUNDS + 1),
-                                  st));
-      SPC_HIP(ctx, hipMemsetAsync(&info[I_VIOL], 0, sizeof(unsigned long long), st));
+      uint32_t slots = (1u << I_MSF) | (1u << I_VIOL);
+      for (int i = I_ROUNDS; i <= I_MSF0; i++) slots |= 1u << i;
+      launch_clear(ctx, nullptr, 0, nullptr, 0, info, slots);
       hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256)), dim3(256), 0, st, W.parent, n);
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestA, n, KEY_INF);
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestB, n, KEY_INF);
@@ -1000,9 +1039,9 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
     if (gf) launch_eps_fp(ctx, W);
     else if (!seg) launch_eps(ctx, g, W, R.msf);
     SPC_LAUNCH_CHECK(ctx, "relabel");
-    SPC_HIP(ctx, hipMemcpyAsync(&nc32, W.flag + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    rc = sync_info(ctx, W);
+    rc = sync_info(ctx, W, nullptr, W.flag + n);
     if (rc) return rc;
+    nc32 = (int32_t)hinfo[I_NINFO + 1];
     R.key_mode = gf ? 3 : rank ? 1 : (hinfo[I_GUARD] ? 2 : 0);
     R.rounds = hinfo[I_ROUNDS];
     R.forest_in = hinfo[I_FIN];
