@@ -171,9 +171,12 @@ static LevelIn level_in(const spc_graph* g) {
 }
 
 // one level into caller buffers
+// With ev non-null the level's start and end events are recorded there and
+// not waited for (st->ms_total is filled in later); otherwise the call waits
+// for the level's end to time it.
 static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* cluster_of,
                       spc_graph_out* out, int64_t* nnz_c, spc_level_stats* st,
-                      const Segments* seg = nullptr) {
+                      const Segments* seg = nullptr, hipEvent_t* ev = nullptr) {
   int rc = check_graph(ctx, g);
   if (rc) return rc;
   if (t < 1) return set_error(ctx, SPC_EINVAL, "n_target must be >= 1");
@@ -240,11 +243,16 @@ static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* clus
   *nnz_c = R.nnz_c;
   if (st) {
     SPC_HIP(ctx, hipEventRecord(e1, ctx->stream));
-    SPC_HIP(ctx, hipEventSynchronize(e1));
     float ms = 0;
-    SPC_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (ev) {
+      ev[0] = e0;
+      ev[1] = e1;
+    } else {
+      SPC_HIP(ctx, hipEventSynchronize(e1));
+      SPC_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+    }
     st->n_in = g->n;
     st->m_in = g->nnz / 2;
     st->n_out = R.n_c;
@@ -274,13 +282,48 @@ static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* clus
 // ===========================================================================
 
 static void free_level(spc_ctx* ctx, spc_hier::Level& L) {
-  dev_free(ctx, L.rp);
-  dev_free(ctx, L.col);
-  dev_free(ctx, L.w);
-  dev_free(ctx, L.self);
-  dev_free(ctx, L.size);
-  dev_free(ctx, L.cluster_of);
+  dev_free(ctx, L.block);
+  for (hipEvent_t& e : L.ev)
+    if (e) (void)hipEventDestroy(e);
   L = spc_hier::Level();
+}
+
+// One allocation per level (each allocation may be a call into the host
+// program's allocator), carved into the level's arrays at 256-byte offsets.
+static bool alloc_level(spc_ctx* ctx, spc_hier::Level& L, int64_t t, int64_t nnz_cap, int64_t n_prev,
+                        size_t wsz) {
+  size_t sz[6] = {sizeof(int64_t) * (size_t)(t + 1), sizeof(int32_t) * (size_t)nnz_cap, wsz * (size_t)nnz_cap,
+                  sizeof(int64_t) * (size_t)t, sizeof(int32_t) * (size_t)t, sizeof(int32_t) * (size_t)n_prev};
+  size_t off[6], tot = 0;
+  for (int i = 0; i < 6; i++) {
+    off[i] = tot;
+    tot += (sz[i] + 255) & ~(size_t)255;
+  }
+  L.block = dev_alloc(ctx, tot);
+  if (!L.block) return false;
+  char* b = (char*)L.block;
+  L.rp = (int64_t*)(b + off[0]);
+  L.col = (int32_t*)(b + off[1]);
+  L.w = b + off[2];
+  L.self = b + off[3];
+  L.size = (int32_t*)(b + off[4]);
+  L.cluster_of = (int32_t*)(b + off[5]);
+  return true;
+}
+
+// Per-level times recorded without waiting: read after the last level.
+static int finish_timing(spc_ctx* ctx, spc_hier* h) {
+  for (auto& L : h->levels) {
+    if (!L.ev[0]) continue;
+    SPC_HIP(ctx, hipEventSynchronize(L.ev[1]));
+    float ms = 0;
+    SPC_HIP(ctx, hipEventElapsedTime(&ms, L.ev[0], L.ev[1]));
+    L.st.ms_total = ms;
+    (void)hipEventDestroy(L.ev[0]);
+    (void)hipEventDestroy(L.ev[1]);
+    L.ev[0] = L.ev[1] = nullptr;
+  }
+  return SPC_OK;
 }
 
 extern "C" {
@@ -430,20 +473,13 @@ int spc_coarsen_to(spc_ctx* ctx, const spc_graph* g, int64_t n_c, int schedule, 
     spc_hier::Level L;
     L.n_prev = n;
     L.wtype = fp ? SPC_W_F64 : SPC_W_I32;
-    L.rp = (int64_t*)dev_alloc(ctx, sizeof(int64_t) * (t + 1));
-    L.col = (int32_t*)dev_alloc(ctx, sizeof(int32_t) * std::max<int64_t>(cur.nnz, 1));
-    L.w = dev_alloc(ctx, wsz * std::max<int64_t>(cur.nnz, 1));
-    L.self = dev_alloc(ctx, sizeof(int64_t) * t);
-    L.size = (int32_t*)dev_alloc(ctx, sizeof(int32_t) * t);
-    L.cluster_of = (int32_t*)dev_alloc(ctx, sizeof(int32_t) * n);
-    if (!L.rp || !L.col || !L.w || !L.self || !L.size || !L.cluster_of) {
-      free_level(ctx, L);
+    if (!alloc_level(ctx, L, t, std::max<int64_t>(cur.nnz, 1), n, wsz)) {
       spc_hier_free(h);
       return set_error(ctx, SPC_ENOMEM, "hierarchy allocation failed");
     }
     spc_graph_out o{L.rp, L.col, L.w, L.self, L.size, t, std::max<int64_t>(cur.nnz, 1)};
     int64_t nnz_c = 0;
-    rc = level_impl(ctx, &cur, t, L.cluster_of, &o, &nnz_c, &L.st);
+    rc = level_impl(ctx, &cur, t, L.cluster_of, &o, &nnz_c, &L.st, nullptr, L.ev);
     if (rc) {
       free_level(ctx, L);
       spc_hier_free(h);
@@ -461,6 +497,11 @@ int spc_coarsen_to(spc_ctx* ctx, const spc_graph* g, int64_t n_c, int schedule, 
     cur.size = L.size;
     cur.wtype = L.wtype;
     n = t;
+  }
+  rc = finish_timing(ctx, h);
+  if (rc) {
+    spc_hier_free(h);
+    return rc;
   }
   *out = h;
   return SPC_OK;
@@ -523,20 +564,13 @@ int spc_coarsen_batched(spc_ctx* ctx, int32_t G, const spc_graph* g, const int64
     spc_hier::Level L;
     L.n_prev = cur.n;
     L.wtype = SPC_W_I32;
-    L.rp = (int64_t*)dev_alloc(ctx, sizeof(int64_t) * (T + 1));
-    L.col = (int32_t*)dev_alloc(ctx, sizeof(int32_t) * std::max<int64_t>(cur.nnz, 1));
-    L.w = dev_alloc(ctx, sizeof(int32_t) * std::max<int64_t>(cur.nnz, 1));
-    L.self = dev_alloc(ctx, sizeof(int64_t) * T);
-    L.size = (int32_t*)dev_alloc(ctx, sizeof(int32_t) * T);
-    L.cluster_of = (int32_t*)dev_alloc(ctx, sizeof(int32_t) * cur.n);
-    if (!L.rp || !L.col || !L.w || !L.self || !L.size || !L.cluster_of) {
-      free_level(ctx, L);
+    if (!alloc_level(ctx, L, T, std::max<int64_t>(cur.nnz, 1), cur.n, sizeof(int32_t))) {
       set_error(ctx, SPC_ENOMEM, "hierarchy allocation failed");
       return fail(SPC_ENOMEM);
     }
     spc_graph_out o{L.rp, L.col, L.w, L.self, L.size, T, std::max<int64_t>(cur.nnz, 1)};
     int64_t nnz_c = 0;
-    rc = level_impl(ctx, &cur, T, L.cluster_of, &o, &nnz_c, &L.st, &seg);
+    rc = level_impl(ctx, &cur, T, L.cluster_of, &o, &nnz_c, &L.st, &seg, L.ev);
     if (rc) {
       free_level(ctx, L);
       return fail(rc);
@@ -555,6 +589,8 @@ int spc_coarsen_batched(spc_ctx* ctx, int32_t G, const spc_graph* g, const int64
     off = noff;
     ng = tg;
   }
+  rc = finish_timing(ctx, h);
+  if (rc) return fail(rc);
   dev_free(ctx, d_off);
   dev_free(ctx, d_k);
   *out = h;

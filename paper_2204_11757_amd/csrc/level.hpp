@@ -23,6 +23,8 @@ struct spc_hier {
     int32_t* cluster_of = nullptr;
     spc_wtype wtype = SPC_W_I32;
     spc_level_stats st{};
+    void* block = nullptr;    // the one allocation the arrays above live in
+    hipEvent_t ev[2] = {nullptr, nullptr};   // level timing, read once the hierarchy is built
   };
   std::vector<Level> levels;
 };
@@ -127,6 +129,7 @@ enum Info : int {
   I_FP_HMAX = 25, // floating-point path: largest weight exponent + FP_EBIAS
   I_FP_BAD = 26,  // floating-point path: a weight is not finite / not positive
   I_SEG_SHORT = 27, // batch: a graph has fewer forest edges than merges needed
+  I_CAND = 28,    // live edges the band's row pass produced (a copy of I_LIVE0)
   I_NINFO = 32
 };
 

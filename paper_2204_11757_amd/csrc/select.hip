@@ -750,32 +750,30 @@ static int check_total(spc_ctx* ctx) {
 // already holds every node's lightest incident key (first round done by the
 // key pass); otherwise both best arrays must be all-infinite on entry.
 // Rounds are issued two at a time between host synchronisations: a round
-// with no live edges is an empty launch.  On return the host copy of the
-// info block is current.
-static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, bool fused_first,
+// with no live edges is an empty launch.  The first batch runs before any
+// count is known on the host, with grids for the list's capacity m (blocks
+// past the device-side count return at once).  On return the host copy of
+// the info block is current.
+static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, bool fused_first,
                            const KeyND* guard_keys, int ebits, int64_t& live0) {
   unsigned long long* info = W.info;
   int64_t* hinfo = ctx->h_pinned;
   int* viol = (int*)&info[I_VIOL];
   const unsigned long long* guard = &info[I_GUARD];
-  int rc = sync_info(ctx, W);
-  if (rc) return rc;
-  rc = check_total(ctx);
-  if (rc) return rc;
-  if (hinfo[I_LBERR]) return set_error(ctx, SPC_EINVAL, "internal: look-back wait gave up");
-  int64_t cnt = hinfo[I_LIVE0];
-  live0 = cnt;
+  int rc;
+  hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(1), 0, ctx->stream, &info[I_CAND], &info[I_LIVE0]);
+  int64_t cnt = m;
   uint64_t* cur = W.bestA;
   uint64_t* nxt = W.bestB;
   int in = 0;
-  if (fused_first && cnt > 0) {
+  if (fused_first) {
     TimedScope ts(ctx, "forest_merge", (double)cnt);
     hipLaunchKernelGGL(k_bv_merge, dim3(grid_for(cnt, BV_CHUNK)), dim3(BS), 0, ctx->stream, W.lr[0],
                        W.lp[0], W.lo[0], &info[I_LIVE0], cur, W.parent, W.msfP, W.msfO, W.msfC,
                        &info[I_MSF], n, guard_keys, guard, ebits, viol, next_scan(ctx, W),
                        &info[I_ROUNDS]);
   }
-  if (fused_first && cnt > 0) {
+  if (fused_first) {
     // the band's first records start where the previous band's ended
     TimedScope ts(ctx, "forest_shortcut", (double)cnt);
     hipLaunchKernelGGL(k_shortcut, dim3(grid_for(cnt, 256, 2 * ctx->num_cus)), dim3(256), 0, ctx->stream,
@@ -821,9 +819,14 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, bool fused_fir
     }
     rc = sync_info(ctx, W);
     if (rc) return rc;
+    if (batch == 0) {
+      rc = check_total(ctx);
+      if (rc) return rc;
+      live0 = hinfo[I_CAND];
+    }
+    if (hinfo[I_LBERR]) return set_error(ctx, SPC_EINVAL, "internal: look-back wait gave up");
     bound = hinfo[in == 0 ? I_LIVE0 : I_LIVE1];
   }
-  if (hinfo[I_LBERR]) return set_error(ctx, SPC_EINVAL, "internal: look-back wait gave up");
   return SPC_OK;
 }
 
@@ -918,7 +921,7 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
     }
     SPC_LAUNCH_CHECK(ctx, "rowpass");
     int64_t live0 = 0;
-    int rc = spanning_forest(ctx, W, n, band == 0, gk, ebits, live0);
+    int rc = spanning_forest(ctx, W, n, m, band == 0, gk, ebits, live0);
     if (rc) return rc;
     done_cand += live0;
     R.candidates = done_cand;
