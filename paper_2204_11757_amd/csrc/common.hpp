@@ -78,6 +78,16 @@ __device__ __forceinline__ T wave_max(T v) {
   return v;
 }
 
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    T t = __shfl_xor(v, o);
+    v = (t < v) ? t : v;
+  }
+  return v;
+}
+
 // Block-wide inclusive scan (sum or max) for BS threads; tmp: LDS T[BS/64].
 // Returns the inclusive value; *total receives the block total.
 template <typename T, int BS, bool MAX>
@@ -140,6 +150,10 @@ __device__ __forceinline__ int64_t wave_upper_search(const int64_t* __restrict__
 // an unneeded atomic)
 __device__ __forceinline__ void atomic_max_lazy(unsigned long long* p, unsigned long long v) {
   if (v > __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(p, v);
+}
+
+__device__ __forceinline__ void atomic_min_lazy(unsigned long long* p, unsigned long long v) {
+  if (v < __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(p, v);
 }
 
 // LDS layout of a tile's row map: thread t owns positions [t*PER, t*PER+PER)

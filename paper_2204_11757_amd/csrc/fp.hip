@@ -144,10 +144,6 @@ __device__ __forceinline__ int fp_level_L(const unsigned long long* info) {
   return (int)((int64_t)info[I_FP_LMIN] - FP_EBIAS);
 }
 
-__device__ __forceinline__ void atomic_min_lazy(unsigned long long* p, unsigned long long v) {
-  if (v < __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(p, v);
-}
-
 // ---------------------------------------------------------------------------
 // validation and exponent range of a level's weights
 // ---------------------------------------------------------------------------

@@ -211,23 +211,48 @@ int exclusive_scan(spc_ctx* ctx, const T* in, T* out, int64_t n, T* partial) {
 }
 
 // ===========================================================================
-// radix select: the k-th smallest (0-based) of cnt 64-bit keys, using
-// 11-bit digits from the most significant of `bits` bits down.  Runs fully
-// on the device; cnt may be read from device memory.
+// radix select: the k-th smallest (0-based) of cnt 64-bit keys below 2^bits,
+// in one launch of at most min(SEL_MAXB, CUs) blocks that meet at grid
+// barriers (one block per CU at most is needed, so all are resident).  Each
+// pass histograms one 11-bit digit of the keys that match the digits chosen
+// so far; every block stores its histogram and its 32 group sums (64 bins
+// each), meets the others at one barrier, then finds the group holding the
+// k-th key from the stored group sums and the bin inside it from that
+// group's stored bins, so all blocks pick the same bucket without atomics
+// across the chip.  Each pass also finds the smallest and largest matching
+// key: when every matching key lands in one bucket, the bits those two share
+// are decided at once (a run of equal scores costs one pass, not one per
+// digit).  Once at most SEL_SMALL keys match, each block copies its
+// matches to an offset known from the stored histograms and one block
+// finishes in LDS.  cnt and k may be read from device memory; the result is
+// left in st->prefix.
 // ===========================================================================
 constexpr int SEL_DIGIT = 11;
 constexpr int SEL_BINS = 1 << SEL_DIGIT;
+constexpr int SEL_GBINS = 64;                     // bins per group
+constexpr int SEL_NGRP = SEL_BINS / SEL_GBINS;    // 32 groups
+constexpr int SEL_SMALL = 4096;
+constexpr int SEL_MAXB = 128;    // blocks of one select
+constexpr int SEL_FLAG = 8;      // flag stride (one 64-byte line per block)
 
 struct SelState {
-  unsigned long long prefix, mask, k;
-  unsigned int done, pad;   // blocks finished with the current digit
-  unsigned int hist[SEL_BINS];
+  unsigned long long prefix, mask;
+  unsigned long long pad[2];
+  unsigned long long flag[SEL_MAXB * SEL_FLAG];      // per-block barrier arrivals
+  unsigned long long bmn[2][SEL_MAXB], bmx[2][SEL_MAXB];   // extreme matching keys per block
+  unsigned int gsum[2][SEL_NGRP][SEL_MAXB];          // per-block group sums, pass p in [p % 2]
+  unsigned int bhist[2][SEL_BINS][SEL_MAXB];         // per-block histograms by bin
+  uint64_t buf[SEL_SMALL];                           // gathered keys
 };
 
-__global__ void k_sel_init(SelState* st, const unsigned long long* k_dev, unsigned long long k_host);
-__global__ void k_sel_pass(const uint64_t* __restrict__ keys, const unsigned long long* cnt_dev,
-                           int64_t cnt_host, SelState* st, int shift, int width, int fused);
-__global__ void k_sel_pick(SelState* st, int shift, int width);
+__global__ void k_sel_init(SelState* st);
+
+// After the call st->prefix holds the selected key (device memory); a grid
+// barrier that waited too long, or k >= cnt, sets *err (the result is then
+// undefined).
+int radix_select(spc_ctx* ctx, const uint64_t* keys, const unsigned long long* cnt_dev,
+                 int64_t cnt_bound, const unsigned long long* k_dev, unsigned long long k_host,
+                 int bits, SelState* st, unsigned long long* err);
 
 // Small launches that replace the runtime's fill and copy blits on the
 // level path (each blit costs the host far more than a plain launch).
@@ -243,10 +268,6 @@ __global__ void k_copy_u64(unsigned long long* dst, const unsigned long long* sr
 void launch_clear(spc_ctx* ctx, int32_t* a, int64_t na, uint64_t* b, int64_t nb, unsigned long long* info,
                   uint32_t slots);
 
-// After the call st->prefix holds the selected key (device memory).
-int radix_select(spc_ctx* ctx, const uint64_t* keys, const unsigned long long* cnt_dev,
-                 int64_t cnt_bound, const unsigned long long* k_dev, unsigned long long k_host,
-                 int bits, SelState* st);
 
 // ===========================================================================
 // merge sort of n elements of type E under a strict order `less` (a

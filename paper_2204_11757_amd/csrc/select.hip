@@ -553,109 +553,419 @@ __global__ void k_relabel(const int32_t* __restrict__ root, const int32_t* __res
 // ---------------------------------------------------------------------------
 // radix select (declared in prim.hpp)
 // ---------------------------------------------------------------------------
-__global__ void k_sel_init(SelState* st, const unsigned long long* k_dev, unsigned long long k_host) {
+__global__ void k_sel_init(SelState* st) {
   int t = threadIdx.x;
   if (t == 0) {
     st->prefix = 0;
     st->mask = 0;
-    st->k = k_dev ? *k_dev : k_host;
-    st->done = 0;
   }
-  for (int b = t; b < SEL_BINS; b += blockDim.x) st->hist[b] = 0;
+  for (int b = t; b < SEL_MAXB; b += blockDim.x) st->flag[b * SEL_FLAG] = 0;
 }
 
-// One digit: every block adds its histogram of the keys that match the
-// prefix so far into st->hist; then one block picks the bucket holding the
-// k-th key, narrows the prefix and clears the histogram.  Small grids pick
-// in the last block to finish (counted with an atomic after a fence); large
-// grids pick in a separate one-block launch, since a counter every block
-// bumps would serialise them.
 constexpr int SEL_BS = 256;
-constexpr int SEL_FUSE_MAX = 64;
+constexpr int SEL_UNROLL = 16;
+constexpr long SEL_SPIN = 1l << 24;          // barrier polls before giving up (about a second)
 
-__device__ __forceinline__ void sel_pick_block(SelState* st, uint64_t prefix, uint64_t mask, int shift,
-                                               int width) {
-  __shared__ unsigned long long tmp[SEL_BS / WAVE];
-  int t = threadIdx.x;
-  int nb = 1 << width;
-  // thread t owns bins [8t, 8t + 8)
-  constexpr int PER = SEL_BINS / SEL_BS;
-  unsigned int c[PER];
-  unsigned long long mine = 0;
-#pragma unroll
-  for (int q = 0; q < PER; q++) {
-    int b = PER * t + q;
-    c[q] = b < nb ? __hip_atomic_load(&st->hist[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
-    mine += c[q];
-  }
-  unsigned long long tot;
-  unsigned long long before = block_incl_scan<unsigned long long, SEL_BS, false>(mine, tmp, &tot) - mine;
-  unsigned long long k = st->k;
+// Grid barrier: each block publishes its arrival epoch in its own flag line
+// (after a release fence) and waits, one thread per block, until every flag
+// has reached the epoch.  Flags start at zero (k_sel_init) and barrier i of
+// a launch publishes epoch i + 1, so a flag only ever moves forward.  Plain
+// stores and no read-modify-write: atomics on one address serialise across
+// the chip.  The wait is bounded; a timeout sets *err.
+__device__ void sel_barrier(SelState* st, unsigned long long epoch, unsigned long long* err) {
   __syncthreads();
-  if (k >= before && k < before + mine) {
-    unsigned long long acc = before;
-#pragma unroll
-    for (int q = 0; q < PER; q++) {
-      if (k >= acc && k < acc + c[q]) {
-        st->k = k - acc;
-        st->prefix = prefix | ((unsigned long long)(PER * t + q) << shift);
-        st->mask = mask | ((unsigned long long)(nb - 1) << shift);
+  int t = threadIdx.x;
+  if (t == 0) {
+    __threadfence();
+    __hip_atomic_store(&st->flag[blockIdx.x * SEL_FLAG], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (t < (int)gridDim.x) {
+    long spins = 0;
+    while (__hip_atomic_load(&st->flag[t * SEL_FLAG], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+      if (++spins > SEL_SPIN) {
+        __hip_atomic_store(err, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
       }
-      acc += c[q];
     }
   }
-  for (int b = t; b < SEL_BINS; b += SEL_BS) st->hist[b] = 0;
-  if (t == 0) st->done = 0;
+  __syncthreads();
+  if (t == 0) __threadfence();   // acquire: later plain loads see the other blocks' stores
+  __syncthreads();
+}
+
+// LDS histogram increment of bin `bin` for the lanes with `m` set: when all
+// such lanes of the wave share one bin (skewed digits, ties), one lane adds
+// their count, so equal keys do not serialise on one LDS address.
+__device__ __forceinline__ void hist_add(unsigned int* h, bool m, uint32_t bin) {
+  unsigned long long act = __ballot(m);
+  if (!act) return;
+  int leader = __ffsll((long long)act) - 1;
+  uint32_t lb = (uint32_t)__shfl((int)bin, leader);
+  unsigned long long same = __ballot(m && bin == lb);
+  if (same == act) {
+    if (lane_id() == leader) atomicAdd(&h[lb], (unsigned int)__popcll(act));
+  } else if (m) {
+    atomicAdd(&h[bin], 1u);
+  }
+}
+
+// Slot in an LDS list for the lanes with `m` set: one LDS atomic per wave.
+__device__ __forceinline__ unsigned int wave_reserve(unsigned int* counter, bool m) {
+  unsigned long long act = __ballot(m);
+  if (!act) return 0;
+  int leader = __ffsll((long long)act) - 1;
+  unsigned int base = 0;
+  if (lane_id() == leader) base = atomicAdd(counter, (unsigned int)__popcll(act));
+  base = (unsigned int)__shfl((int)base, leader);
+  unsigned long long below = act & ((1ull << lane_id()) - 1);
+  return base + (unsigned int)__popcll(below);
+}
+
+// Block-wide smallest and largest of the values the threads hold.
+__device__ __forceinline__ void block_minmax(uint64_t& mn, uint64_t& mx, unsigned long long* red) {
+  mn = wave_min(mn);
+  mx = wave_max(mx);
+  int w = threadIdx.x / WAVE;
+  if (lane_id() == 0) {
+    red[w] = mn;
+    red[SEL_BS / WAVE + w] = mx;
+  }
+  __syncthreads();
+  mn = ~0ull;
+  mx = 0;
+  for (int i = 0; i < SEL_BS / WAVE; i++) {
+    mn = red[i] < mn ? red[i] : mn;
+    mx = red[SEL_BS / WAVE + i] > mx ? red[SEL_BS / WAVE + i] : mx;
+  }
+  __syncthreads();
+}
+
+// The k-th smallest of the c <= SEL_SMALL keys in s (LDS), by one block with
+// 8-bit digits below the highest bit in which the keys differ.
+__device__ uint64_t lds_select(const uint64_t* s, int c, unsigned long long k, unsigned int* h,
+                               unsigned long long* tmp, unsigned long long* red, unsigned long long* spick,
+                               unsigned long long* err) {
+  int t = threadIdx.x;
+  if (k >= (unsigned long long)c) {
+    if (t == 0) __hip_atomic_store(err, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return ~0ull;
+  }
+  uint64_t mn = ~0ull, mx = 0;
+  for (int i = t; i < c; i += SEL_BS) {
+    mn = s[i] < mn ? s[i] : mn;
+    mx = s[i] > mx ? s[i] : mx;
+  }
+  block_minmax(mn, mx, red);
+  uint64_t x = mn ^ mx;
+  if (x == 0) return mn;
+  int hi = 64 - __clzll((long long)x);
+  uint64_t mask = hi == 64 ? 0ull : ~((1ull << hi) - 1);
+  uint64_t prefix = mn & mask;
+  while (hi > 0) {
+    int lo = hi - 8 > 0 ? hi - 8 : 0;
+    int nb = 1 << (hi - lo);
+    uint64_t dm = (uint64_t)(nb - 1);
+    h[t] = 0;
+    __syncthreads();
+    for (int i0 = 0; i0 < c; i0 += SEL_BS) {
+      int i = i0 + t;
+      uint64_t x = i < c ? s[i] : 0;
+      hist_add(h, i < c && (x & mask) == prefix, (uint32_t)((x >> lo) & dm));
+    }
+    __syncthreads();
+    unsigned long long cnt = t < nb ? h[t] : 0;
+    unsigned long long tot;
+    unsigned long long before = block_incl_scan<unsigned long long, SEL_BS, false>(cnt, tmp, &tot) - cnt;
+    if (k >= before && k < before + cnt) {
+      spick[0] = (unsigned long long)t;
+      spick[1] = before;
+      spick[2] = cnt;
+    }
+    __syncthreads();
+    prefix |= spick[0] << lo;
+    mask |= dm << lo;
+    k -= spick[1];
+    hi = lo;
+    bool one = spick[2] == 1;
+    __syncthreads();
+    if (one && hi > 0) {
+      // a single key is left in the bucket: find it
+      for (int i = t; i < c; i += SEL_BS)
+        if ((s[i] & mask) == prefix) spick[0] = s[i];
+      __syncthreads();
+      uint64_t r = spick[0];
+      __syncthreads();
+      return r;
+    }
+  }
+  return prefix;
+}
+
+// Sum of row[0..G) (G <= SEL_MAXB, 16-byte aligned rows) for `lanes`
+// threads sharing the row: thread `sub` takes every lanes-th vector.  All
+// of a thread's loads are issued before any is used (after a barrier they
+// all go to memory).
+template <int LANES>
+__device__ __forceinline__ unsigned int row_part_sum(const unsigned int* row, int G, int sub) {
+  constexpr int NV = SEL_MAXB / 4 / LANES;
+  const uint4* r4 = (const uint4*)row;
+  uint4 v[NV];
+#pragma unroll
+  for (int q = 0; q < NV; q++) {
+    int j = 4 * (sub + q * LANES);
+    v[q] = j < G ? r4[sub + q * LANES] : make_uint4(0, 0, 0, 0);
+  }
+  unsigned int s = 0;
+#pragma unroll
+  for (int q = 0; q < NV; q++) {
+    int j = 4 * (sub + q * LANES);
+    s += (j < G ? v[q].x : 0u) + (j + 1 < G ? v[q].y : 0u) + (j + 2 < G ? v[q].z : 0u) +
+         (j + 3 < G ? v[q].w : 0u);
+  }
+  return s;
 }
 
 __global__ void __launch_bounds__(SEL_BS)
-    k_sel_pass(const uint64_t* __restrict__ keys, const unsigned long long* cnt_dev, int64_t cnt_host,
-               SelState* st, int shift, int width, int fused) {
+    k_select(const uint64_t* __restrict__ keys, const unsigned long long* cnt_dev, int64_t cnt_host,
+             const unsigned long long* k_dev, unsigned long long k_host, int bits, SelState* st,
+             unsigned long long* err) {
+  static_assert(SEL_NGRP * 8 == SEL_BS && SEL_GBINS * 4 == SEL_BS, "pick layout");
   __shared__ unsigned int h[SEL_BINS];
-  __shared__ int last;
+  __shared__ uint64_t sbuf[SEL_SMALL];
+  __shared__ unsigned long long tmp[SEL_BS / WAVE];
+  __shared__ unsigned long long red[2 * (SEL_BS / WAVE)];
+  __shared__ unsigned long long spick[3];
+  __shared__ unsigned int sgrp[2];
+  __shared__ unsigned int slocal;
   int t = threadIdx.x;
-  int nb = 1 << width;
-  for (int b = t; b < nb; b += SEL_BS) h[b] = 0;
-  __syncthreads();
+  int G = gridDim.x, B = blockIdx.x;
   int64_t n = cnt_dev ? (int64_t)*cnt_dev : cnt_host;
-  uint64_t prefix = st->prefix, mask = st->mask;
-  uint64_t dm = (uint64_t)(nb - 1);
-  int64_t stride = (int64_t)gridDim.x * SEL_BS;
-  for (int64_t i = (int64_t)blockIdx.x * SEL_BS + t; i < n; i += stride) {
-    uint64_t k = keys[i];
-    if ((k & mask) == prefix) atomicAdd(&h[(k >> shift) & dm], 1u);
+  unsigned long long k = k_dev ? *k_dev : k_host;
+  int64_t stride = (int64_t)G * SEL_BS;
+  unsigned long long epoch = 0;   // barrier i publishes i + 1
+  uint64_t prefix = 0, mask = 0;
+  int hi = bits;
+  int64_t cb = n;   // keys matching (prefix, mask)
+  unsigned long long bstar = 0;   // bucket chosen by the last pass
+  int p = 0;
+  if (G > 1) {
+    for (; p == 0 || (cb > SEL_SMALL && hi > 0); p++) {
+      int lo = hi - SEL_DIGIT > 0 ? hi - SEL_DIGIT : 0;
+      int nb = 1 << (hi - lo);
+      uint64_t dm = (uint64_t)(nb - 1);
+      for (int b = t; b < SEL_BINS; b += SEL_BS) h[b] = 0;
+      __syncthreads();
+      uint64_t mn = ~0ull, mx = 0;
+      for (int64_t i0 = (int64_t)B * SEL_BS + t; i0 < n; i0 += stride * SEL_UNROLL) {
+        uint64_t kk[SEL_UNROLL];
+#pragma unroll
+        for (int u = 0; u < SEL_UNROLL; u++) {
+          int64_t i = i0 + u * stride;
+          kk[u] = i < n ? keys[i] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < SEL_UNROLL; u++) {
+          bool m = i0 + u * stride < n && (kk[u] & mask) == prefix;
+          hist_add(h, m, (uint32_t)((kk[u] >> lo) & dm));
+          if (m) {
+            mn = kk[u] < mn ? kk[u] : mn;
+            mx = kk[u] > mx ? kk[u] : mx;
+          }
+        }
+      }
+      __syncthreads();
+      unsigned int (*bh)[SEL_MAXB] = st->bhist[p & 1];
+      unsigned int (*gs)[SEL_MAXB] = st->gsum[p & 1];
+      for (int b = t; b < SEL_BINS; b += SEL_BS) bh[b][B] = h[b];
+      {
+        // group sums: 8 threads per group of 64 bins
+        int g = t / 8, sub = t % 8;
+        unsigned int s = 0;
+        for (int q = 0; q < SEL_GBINS / 8; q++) s += h[g * SEL_GBINS + sub + 8 * q];
+        s += __shfl_xor((int)s, 1);
+        s += __shfl_xor((int)s, 2);
+        s += __shfl_xor((int)s, 4);
+        if (sub == 0) gs[g][B] = s;
+      }
+      block_minmax(mn, mx, red);
+      if (t == 0) {
+        st->bmn[p & 1][B] = mn;
+        st->bmx[p & 1][B] = mx;
+      }
+      sel_barrier(st, ++epoch, err);
+      mn = ~0ull;
+      mx = 0;
+      for (int j = t; j < G; j += SEL_BS) {
+        uint64_t a = st->bmn[p & 1][j], c = st->bmx[p & 1][j];
+        mn = a < mn ? a : mn;
+        mx = c > mx ? c : mx;
+      }
+      block_minmax(mn, mx, red);
+      // the group holding the k-th key: 8 threads per group's row
+      unsigned long long gc;
+      {
+        int g = t / 8, sub = t % 8;
+        unsigned int s = row_part_sum<8>(gs[g], G, sub);
+        s += __shfl_xor((int)s, 1);
+        s += __shfl_xor((int)s, 2);
+        s += __shfl_xor((int)s, 4);
+        gc = sub == 0 ? s : 0;
+      }
+      unsigned long long total;
+      unsigned long long before = block_incl_scan<unsigned long long, SEL_BS, false>(gc, tmp, &total) - gc;
+      if (t == 0) spick[0] = ~0ull;
+      __syncthreads();
+      if (gc && k >= before && k < before + gc) {
+        sgrp[0] = (unsigned int)(t / 8);
+        spick[1] = before;
+        spick[0] = 0;
+      }
+      __syncthreads();
+      if (spick[0] == ~0ull) {   // k >= the number of keys (uniform over the grid)
+        if (B == 0 && t == 0) {
+          __hip_atomic_store(err, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          st->prefix = ~0ull;
+        }
+        return;
+      }
+      unsigned int gstar = sgrp[0];
+      unsigned long long kg = k - spick[1];
+      __syncthreads();
+      // the bin inside that group: 4 threads per bin's row
+      unsigned long long bc;
+      {
+        int bi = t / 4, sub = t % 4;
+        unsigned int s = row_part_sum<4>(bh[gstar * SEL_GBINS + bi], G, sub);
+        s += __shfl_xor((int)s, 1);
+        s += __shfl_xor((int)s, 2);
+        bc = sub == 0 ? s : 0;
+      }
+      before = block_incl_scan<unsigned long long, SEL_BS, false>(bc, tmp, &total) - bc;
+      if (bc && kg >= before && kg < before + bc) {
+        spick[0] = (unsigned long long)(gstar * SEL_GBINS + t / 4);
+        spick[1] = before + (k - kg);
+        spick[2] = bc;
+      }
+      __syncthreads();
+      bstar = spick[0];
+      prefix |= bstar << lo;
+      mask |= dm << lo;
+      k -= spick[1];
+      bool all_one = (int64_t)spick[2] == cb;
+      cb = (int64_t)spick[2];
+      hi = lo;
+      __syncthreads();
+      if (all_one) {
+        // one bucket holds every matching key: the bits the extreme ones share
+        // are decided
+        uint64_t x = mn ^ mx;
+        if (x == 0) {
+          prefix = mn;
+          mask = ~0ull;
+          hi = 0;
+        } else {
+          int d = 63 - __clzll((long long)x);   // highest differing bit
+          if (d + 1 < hi) {
+            uint64_t low = (2ull << d) - 1;     // d < hi <= 63 here
+            prefix = mn & ~low;
+            mask = ~low;
+            hi = d + 1;
+          }
+        }
+      }
+    }
+  }
+  if (hi == 0 || cb == 0) {
+    if (B == 0 && t == 0) {
+      st->prefix = prefix;
+      st->mask = mask;
+    }
+    return;
+  }
+  // at most SEL_SMALL keys match: gather them
+  if (t == 0) slocal = 0;
+  __syncthreads();
+  if (G == 1) {
+    // every key matches: copy them in order
+    constexpr int PER = SEL_SMALL / SEL_BS;
+    uint64_t v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+      int i = t + q * SEL_BS;
+      v[q] = i < n ? keys[i] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+      int i = t + q * SEL_BS;
+      if (i < n) sbuf[i] = v[q];
+    }
+    __syncthreads();
+    uint64_t r = lds_select(sbuf, (int)n, k, h, tmp, red, spick, err);
+    if (t == 0) {
+      st->prefix = r;
+      st->mask = ~0ull;
+    }
+    return;
+  }
+  // this block's offset: the chosen bucket's counts of the blocks before it
+  unsigned int (*bh)[SEL_MAXB] = st->bhist[(p - 1) & 1];
+  unsigned long long part = t < B ? bh[bstar][t] : 0;   // B < SEL_MAXB <= SEL_BS
+  unsigned long long off;
+  (void)block_incl_scan<unsigned long long, SEL_BS, false>(part, tmp, &off);
+  for (int64_t i0 = (int64_t)B * SEL_BS; i0 < n; i0 += stride * SEL_UNROLL) {
+    uint64_t kk[SEL_UNROLL];
+#pragma unroll
+    for (int u = 0; u < SEL_UNROLL; u++) {
+      int64_t i = i0 + u * stride + t;
+      kk[u] = i < n ? keys[i] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < SEL_UNROLL; u++) {
+      bool m = i0 + u * stride + t < n && (kk[u] & mask) == prefix;
+      unsigned int q = wave_reserve(&slocal, m);
+      if (m && q < (unsigned)SEL_SMALL) sbuf[q] = kk[u];
+    }
   }
   __syncthreads();
-  for (int b = t; b < nb; b += SEL_BS)
-    if (h[b]) atomicAdd(&st->hist[b], h[b]);
-  if (!fused) return;
-  __threadfence();
+  unsigned int cnt = slocal < (unsigned)SEL_SMALL ? slocal : (unsigned)SEL_SMALL;
+  for (unsigned int i = t; i < cnt; i += SEL_BS)
+    if (off + i < (unsigned long long)SEL_SMALL) st->buf[off + i] = sbuf[i];
+  sel_barrier(st, ++epoch, err);
+  if (B != 0) return;
+  cnt = (unsigned int)cb;
+  {
+    constexpr int PER = SEL_SMALL / SEL_BS;
+    uint64_t v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+      unsigned int i = t + q * SEL_BS;
+      v[q] = i < cnt ? st->buf[i] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+      unsigned int i = t + q * SEL_BS;
+      if (i < cnt) sbuf[i] = v[q];
+    }
+  }
   __syncthreads();
-  if (t == 0) last = atomicAdd(&st->done, 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  sel_pick_block(st, prefix, mask, shift, width);
-}
-
-__global__ void __launch_bounds__(SEL_BS) k_sel_pick(SelState* st, int shift, int width) {
-  sel_pick_block(st, st->prefix, st->mask, shift, width);
+  uint64_t r = lds_select(sbuf, (int)cnt, k, h, tmp, red, spick, err);
+  if (t == 0) {
+    st->prefix = r;
+    st->mask = ~0ull;
+  }
 }
 
 int radix_select(spc_ctx* ctx, const uint64_t* keys, const unsigned long long* cnt_dev,
                  int64_t cnt_bound, const unsigned long long* k_dev, unsigned long long k_host,
-                 int bits, SelState* st) {
-  hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, ctx->stream, st, k_dev, k_host);
-  int grid = grid_for(cnt_bound, SEL_BS * 16, 4096);
-  int fused = grid <= SEL_FUSE_MAX ? 1 : 0;
-  for (int hi = bits; hi > 0;) {
-    int lo = hi - SEL_DIGIT > 0 ? hi - SEL_DIGIT : 0;
-    int width = hi - lo;
-    hipLaunchKernelGGL(k_sel_pass, dim3(grid), dim3(SEL_BS), 0, ctx->stream, keys, cnt_dev, cnt_bound,
-                       st, lo, width, fused);
-    if (!fused) hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(SEL_BS), 0, ctx->stream, st, lo, width);
-    hi = lo;
-  }
+                 int bits, SelState* st, unsigned long long* err) {
+  hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(SEL_MAXB), 0, ctx->stream, st);
+  // 32 keys per thread and pass up to SEL_MAXB blocks (a barrier's cost
+  // grows with the blocks that meet at it)
+  int maxb = ctx->num_cus < SEL_MAXB ? ctx->num_cus : SEL_MAXB;
+  int grid = cnt_bound <= SEL_SMALL ? 1 : grid_for(cnt_bound, SEL_BS * 32, maxb);
+  if (grid < 2 && cnt_bound > SEL_SMALL) grid = 2;
+  hipLaunchKernelGGL(k_select, dim3(grid), dim3(SEL_BS), 0, ctx->stream, keys, cnt_dev, cnt_bound, k_dev,
+                     k_host, bits, st, err);
   SPC_LAUNCH_CHECK(ctx, "radix_select");
   return SPC_OK;
 }
@@ -905,7 +1215,8 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
         hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits, guard);
       } else {
         TimedScope ts(ctx, "select_threshold", (double)ns);
-        int rc = radix_select(ctx, W.samples, nullptr, ns, nullptr, (unsigned long long)q, 64, W.sel);
+        int rc = radix_select(ctx, W.samples, nullptr, ns, nullptr, (unsigned long long)q, 64, W.sel,
+                              &info[I_LBERR]);
         if (rc) return rc;
         hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 0, ebits, guard);
       }
@@ -944,7 +1255,7 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
     TimedScope ts(ctx, "select_cutoff", (double)R.msf);
     int bits = rank ? bitlen64((uint64_t)(m - 1)) : 64;
     int rc = radix_select(ctx, W.msfP, &info[I_MSF], n, nullptr, (unsigned long long)(k - 1), bits,
-                          W.sel2);
+                          W.sel2, &info[I_LBERR]);
     if (rc) return rc;
   }
   if (!rank) {
