@@ -171,6 +171,7 @@ struct LevelWork {
   int32_t* flag;             // [n+1]
   SelState* sel;
   SelState* sel2;
+  uint64_t* selflag;         // [SEL_MAXB * SEL_FLAG] radix-select barrier flags
   void* scan_partial;        // SCAN_MAXB * 8 bytes
   KeyND* keysA;              // [m] rank mode
   KeyND* keysB;              // [m]

@@ -238,35 +238,34 @@ constexpr int SEL_FLAG = 8;      // flag stride (one 64-byte line per block)
 struct SelState {
   unsigned long long prefix, mask;
   unsigned long long pad[2];
-  unsigned long long flag[SEL_MAXB * SEL_FLAG];      // per-block barrier arrivals
   unsigned long long bmn[2][SEL_MAXB], bmx[2][SEL_MAXB];   // extreme matching keys per block
   unsigned int gsum[2][SEL_NGRP][SEL_MAXB];          // per-block group sums, pass p in [p % 2]
   unsigned int bhist[2][SEL_BINS][SEL_MAXB];         // per-block histograms by bin
   uint64_t buf[SEL_SMALL];                           // gathered keys
 };
 
-__global__ void k_sel_init(SelState* st);
-
 // After the call st->prefix holds the selected key (device memory); a grid
 // barrier that waited too long, or k >= cnt, sets *err (the result is then
-// undefined).
+// undefined).  flags: SEL_MAXB * SEL_FLAG words, zeroed when ctx->sel_epoch
+// was last reset to 0; every select of that period uses epochs above the
+// previous one's.
 int radix_select(spc_ctx* ctx, const uint64_t* keys, const unsigned long long* cnt_dev,
                  int64_t cnt_bound, const unsigned long long* k_dev, unsigned long long k_host,
-                 int bits, SelState* st, unsigned long long* err);
+                 int bits, SelState* st, unsigned long long* flags, unsigned long long* err);
 
 // Small launches that replace the runtime's fill and copy blits on the
 // level path (each blit costs the host far more than a plain launch).
-// k_clear zeroes a[0, na), b[0, nb) and the info slots whose bit is set in
+// k_clear zeroes a[0, na), b[0, nb), c[0, nc) and the info slots whose bit is set in
 // `slots`; k_readback copies the info block (I_NINFO words, when info is not
 // null) and up to three scalars (null: 0) into host-visible pinned memory
 // at out[0..I_NINFO) and out[I_NINFO..I_NINFO+3); k_copy_u64 copies one word.
-__global__ void k_clear(int32_t* a, int64_t na, uint64_t* b, int64_t nb, unsigned long long* info,
-                        uint32_t slots);
+__global__ void k_clear(int32_t* a, int64_t na, uint64_t* b, int64_t nb, uint64_t* c, int64_t nc,
+                        unsigned long long* info, uint32_t slots);
 __global__ void k_readback(const unsigned long long* info, int ninfo, const int64_t* x0,
                            const int32_t* x1, const uint64_t* x2, int64_t* out);
 __global__ void k_copy_u64(unsigned long long* dst, const unsigned long long* src);
 void launch_clear(spc_ctx* ctx, int32_t* a, int64_t na, uint64_t* b, int64_t nb, unsigned long long* info,
-                  uint32_t slots);
+                  uint32_t slots, uint64_t* c = nullptr, int64_t nc = 0);
 
 
 // ===========================================================================

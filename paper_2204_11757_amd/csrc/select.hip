@@ -49,6 +49,7 @@ void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W, bool fp) {
   W.flag = A.take<int32_t>(n + 1);
   W.sel = A.take<SelState>(1);
   W.sel2 = A.take<SelState>(1);
+  W.selflag = A.take<uint64_t>(SEL_MAXB * SEL_FLAG);
   W.scan_partial = A.take<int64_t>(SCAN_MAXB);
   W.keysA = A.take<KeyND>(m);
   W.keysB = A.take<KeyND>(m);
@@ -455,7 +456,13 @@ __global__ void __launch_bounds__(BS)
   int64_t n = (int64_t)*cnt_in;
   int tid = threadIdx.x;
   int64_t base = (int64_t)blockIdx.x * BV_CHUNK;
-  if (base >= n) return;
+  if (base >= n) {
+    if (n == 0 && blockIdx.x == 0 && tid == 0) {   // no tile runs: the empty list's count
+      *cnt_out = 0;
+      *msf_mark = *msf_now;
+    }
+    return;
+  }
   uint32_t keep = 0;
   int nk = 0;
   uint64_t ruv[BV_PER];
@@ -553,35 +560,27 @@ __global__ void k_relabel(const int32_t* __restrict__ root, const int32_t* __res
 // ---------------------------------------------------------------------------
 // radix select (declared in prim.hpp)
 // ---------------------------------------------------------------------------
-__global__ void k_sel_init(SelState* st) {
-  int t = threadIdx.x;
-  if (t == 0) {
-    st->prefix = 0;
-    st->mask = 0;
-  }
-  for (int b = t; b < SEL_MAXB; b += blockDim.x) st->flag[b * SEL_FLAG] = 0;
-}
-
 constexpr int SEL_BS = 256;
 constexpr int SEL_UNROLL = 16;
 constexpr long SEL_SPIN = 1l << 24;          // barrier polls before giving up (about a second)
 
 // Grid barrier: each block publishes its arrival epoch in its own flag line
 // (after a release fence) and waits, one thread per block, until every flag
-// has reached the epoch.  Flags start at zero (k_sel_init) and barrier i of
-// a launch publishes epoch i + 1, so a flag only ever moves forward.  Plain
+// has reached the epoch.  Flags start at zero (cleared with the level's
+// info block) and every barrier of the level publishes a larger epoch than
+// the one before, so a flag only ever moves forward.  Plain
 // stores and no read-modify-write: atomics on one address serialise across
 // the chip.  The wait is bounded; a timeout sets *err.
-__device__ void sel_barrier(SelState* st, unsigned long long epoch, unsigned long long* err) {
+__device__ void sel_barrier(unsigned long long* flags, unsigned long long epoch, unsigned long long* err) {
   __syncthreads();
   int t = threadIdx.x;
   if (t == 0) {
     __threadfence();
-    __hip_atomic_store(&st->flag[blockIdx.x * SEL_FLAG], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&flags[blockIdx.x * SEL_FLAG], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   if (t < (int)gridDim.x) {
     long spins = 0;
-    while (__hip_atomic_load(&st->flag[t * SEL_FLAG], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+    while (__hip_atomic_load(&flags[t * SEL_FLAG], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
       if (++spins > SEL_SPIN) {
         __hip_atomic_store(err, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
@@ -728,7 +727,7 @@ __device__ __forceinline__ unsigned int row_part_sum(const unsigned int* row, in
 __global__ void __launch_bounds__(SEL_BS)
     k_select(const uint64_t* __restrict__ keys, const unsigned long long* cnt_dev, int64_t cnt_host,
              const unsigned long long* k_dev, unsigned long long k_host, int bits, SelState* st,
-             unsigned long long* err) {
+             unsigned long long* flags, unsigned long long epoch0, unsigned long long* err) {
   static_assert(SEL_NGRP * 8 == SEL_BS && SEL_GBINS * 4 == SEL_BS, "pick layout");
   __shared__ unsigned int h[SEL_BINS];
   __shared__ uint64_t sbuf[SEL_SMALL];
@@ -742,7 +741,7 @@ __global__ void __launch_bounds__(SEL_BS)
   int64_t n = cnt_dev ? (int64_t)*cnt_dev : cnt_host;
   unsigned long long k = k_dev ? *k_dev : k_host;
   int64_t stride = (int64_t)G * SEL_BS;
-  unsigned long long epoch = 0;   // barrier i publishes i + 1
+  unsigned long long epoch = epoch0;   // barrier i publishes epoch0 + i + 1
   uint64_t prefix = 0, mask = 0;
   int hi = bits;
   int64_t cb = n;   // keys matching (prefix, mask)
@@ -792,7 +791,7 @@ __global__ void __launch_bounds__(SEL_BS)
         st->bmn[p & 1][B] = mn;
         st->bmx[p & 1][B] = mx;
       }
-      sel_barrier(st, ++epoch, err);
+      sel_barrier(flags, ++epoch, err);
       mn = ~0ull;
       mx = 0;
       for (int j = t; j < G; j += SEL_BS) {
@@ -930,7 +929,7 @@ __global__ void __launch_bounds__(SEL_BS)
   unsigned int cnt = slocal < (unsigned)SEL_SMALL ? slocal : (unsigned)SEL_SMALL;
   for (unsigned int i = t; i < cnt; i += SEL_BS)
     if (off + i < (unsigned long long)SEL_SMALL) st->buf[off + i] = sbuf[i];
-  sel_barrier(st, ++epoch, err);
+  sel_barrier(flags, ++epoch, err);
   if (B != 0) return;
   cnt = (unsigned int)cb;
   {
@@ -957,15 +956,16 @@ __global__ void __launch_bounds__(SEL_BS)
 
 int radix_select(spc_ctx* ctx, const uint64_t* keys, const unsigned long long* cnt_dev,
                  int64_t cnt_bound, const unsigned long long* k_dev, unsigned long long k_host,
-                 int bits, SelState* st, unsigned long long* err) {
-  hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(SEL_MAXB), 0, ctx->stream, st);
+                 int bits, SelState* st, unsigned long long* flags, unsigned long long* err) {
+  unsigned long long epoch0 = ctx->sel_epoch;
+  ctx->sel_epoch += 64;   // a select meets at most 2 + 64 / SEL_DIGIT times
   // 32 keys per thread and pass up to SEL_MAXB blocks (a barrier's cost
   // grows with the blocks that meet at it)
   int maxb = ctx->num_cus < SEL_MAXB ? ctx->num_cus : SEL_MAXB;
   int grid = cnt_bound <= SEL_SMALL ? 1 : grid_for(cnt_bound, SEL_BS * 32, maxb);
   if (grid < 2 && cnt_bound > SEL_SMALL) grid = 2;
   hipLaunchKernelGGL(k_select, dim3(grid), dim3(SEL_BS), 0, ctx->stream, keys, cnt_dev, cnt_bound, k_dev,
-                     k_host, bits, st, err);
+                     k_host, bits, st, flags, epoch0, err);
   SPC_LAUNCH_CHECK(ctx, "radix_select");
   return SPC_OK;
 }
@@ -975,21 +975,23 @@ int radix_select(spc_ctx* ctx, const uint64_t* keys, const unsigned long long* c
 // ---------------------------------------------------------------------------
 __global__ void k_set_u64(unsigned long long* p, unsigned long long v) { *p = v; }
 
-__global__ void k_clear(int32_t* a, int64_t na, uint64_t* b, int64_t nb, unsigned long long* info,
-                        uint32_t slots) {
+__global__ void k_clear(int32_t* a, int64_t na, uint64_t* b, int64_t nb, uint64_t* c, int64_t nc,
+                        unsigned long long* info, uint32_t slots) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t i = i0; i < na; i += stride) a[i] = 0;
   for (int64_t i = i0; i < nb; i += stride) b[i] = 0;
+  for (int64_t i = i0; i < nc; i += stride) c[i] = 0;
   if (info && i0 < 32 && (slots >> i0 & 1u)) info[i0] = 0;
 }
 
 void launch_clear(spc_ctx* ctx, int32_t* a, int64_t na, uint64_t* b, int64_t nb, unsigned long long* info,
-                  uint32_t slots) {
+                  uint32_t slots, uint64_t* c, int64_t nc) {
   int64_t big = na > nb ? na : nb;
+  if (nc > big) big = nc;
   if (big < 32) big = 32;
   hipLaunchKernelGGL(k_clear, dim3(grid_for(big, 256, ctx->num_cus * 4)), dim3(256), 0, ctx->stream, a, na,
-                     b, nb, info, slots);
+                     b, nb, c, nc, info, slots);
 }
 
 __global__ void k_readback(const unsigned long long* info, int ninfo, const int64_t* x0,
@@ -1101,7 +1103,6 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, boo
       int out = in ^ 1;
       int ci = in == 0 ? I_LIVE0 : I_LIVE1;
       int co = out == 0 ? I_LIVE0 : I_LIVE1;
-      hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, ctx->stream, &info[co], 0ull);
       {
         TimedScope ts(ctx, "forest_candidates", (double)bound);
         hipLaunchKernelGGL(k_bv_candidates, dim3(grid_for(bound, BV_CHUNK)), dim3(BS), 0, ctx->stream,
@@ -1216,14 +1217,13 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
       } else {
         TimedScope ts(ctx, "select_threshold", (double)ns);
         int rc = radix_select(ctx, W.samples, nullptr, ns, nullptr, (unsigned long long)q, 64, W.sel,
-                              &info[I_LBERR]);
+                              (unsigned long long*)W.selflag, &info[I_LBERR]);
         if (rc) return rc;
         hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 0, ebits, guard);
       }
     } else {
       hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, thr_hi, (unsigned long long)(target - 1));
     }
-    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, &info[I_LIVE0], 0ull);
     {
       TimedScope ts(ctx, "rowpass", (double)g.nnz);
       hipLaunchKernelGGL(k_rowpass, dim3(grid_for(g.nnz, TILE_R)), dim3(BS), 0, st, g, W.lc, W.Pc,
@@ -1255,7 +1255,7 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
     TimedScope ts(ctx, "select_cutoff", (double)R.msf);
     int bits = rank ? bitlen64((uint64_t)(m - 1)) : 64;
     int rc = radix_select(ctx, W.msfP, &info[I_MSF], n, nullptr, (unsigned long long)(k - 1), bits,
-                          W.sel2, &info[I_LBERR]);
+                          W.sel2, (unsigned long long*)W.selflag, &info[I_LBERR]);
     if (rc) return rc;
   }
   if (!rank) {
@@ -1277,7 +1277,9 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
   int64_t* hinfo = ctx->h_pinned;
   ctx->lb_words = lb_words(n, g.nnz);
   ctx->lb_epoch = 0;
-  launch_clear(ctx, nullptr, 0, W.lbstate, ctx->lb_words, info, 0xffffffffu);
+  ctx->sel_epoch = 0;
+  launch_clear(ctx, nullptr, 0, W.lbstate, ctx->lb_words, info, 0xffffffffu, W.selflag,
+               (int64_t)SEL_MAXB * SEL_FLAG);
 
   // A1
   int nb = grid_for(n, DEG_ROWS);
