@@ -340,11 +340,14 @@ __global__ void __launch_bounds__(BS)
 }
 
 // ---------------------------------------------------------------------------
-// A4: spanning-forest rounds (Boruvka) on the live list, in chunks of 4096
-// items per block iteration.
+// A4: spanning-forest rounds (Boruvka) on the live list, one chunk of items
+// per block: 4096 for the hooking pass, 1024 for the root lookups (an item's
+// lookups are chains of dependent loads, so fewer per thread).
 // ---------------------------------------------------------------------------
 constexpr int BV_CHUNK = 4096;
 constexpr int BV_PER = BV_CHUNK / BS;
+constexpr int BC_CHUNK = 1024;
+constexpr int BC_PER = BC_CHUNK / BS;
 
 // Guarded keys: the winner w of a component must not have a same-bucket
 // rival x with an exactly smaller score.
@@ -455,7 +458,7 @@ __global__ void __launch_bounds__(BS)
   __shared__ unsigned long long sbase;
   int64_t n = (int64_t)*cnt_in;
   int tid = threadIdx.x;
-  int64_t base = (int64_t)blockIdx.x * BV_CHUNK;
+  int64_t base = (int64_t)blockIdx.x * BC_CHUNK;
   if (base >= n) {
     if (n == 0 && blockIdx.x == 0 && tid == 0) {   // no tile runs: the empty list's count
       *cnt_out = 0;
@@ -465,8 +468,8 @@ __global__ void __launch_bounds__(BS)
   }
   uint32_t keep = 0;
   int nk = 0;
-  uint64_t ruv[BV_PER];
-  for (int i = 0; i < BV_PER; i++) {
+  uint64_t ruv[BC_PER];
+  for (int i = 0; i < BC_PER; i++) {
     ruv[i] = 0;
     int64_t idx = base + tid + i * BS;
     if (idx >= n) break;
@@ -484,14 +487,14 @@ __global__ void __launch_bounds__(BS)
       nk++;
     }
   }
-  bool last = base + BV_CHUNK >= n;
+  bool last = base + BC_CHUNK >= n;
   int64_t pos = block_reserve_lb<BS>(ts, blockIdx.x, last, nk, nullptr, cnt_out, &sbase, stmp);
   if (last && tid == 0) {
     atomicAdd(&stats[0], (unsigned long long)n);   // info[I_FIN]
     atomicAdd(&stats[1], *cnt_out);                // info[I_FKEPT]
     *msf_mark = *msf_now;                          // forest records before the next merge
   }
-  for (int i = 0; i < BV_PER; i++) {
+  for (int i = 0; i < BC_PER; i++) {
     if (!(keep >> i & 1u)) continue;
     int64_t idx = base + tid + i * BS;
     lr_out[pos] = ruv[i];
@@ -1088,7 +1091,7 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, boo
   if (fused_first) {
     // the band's first records start where the previous band's ended
     TimedScope ts(ctx, "forest_shortcut", (double)cnt);
-    hipLaunchKernelGGL(k_shortcut, dim3(grid_for(cnt, 256, 2 * ctx->num_cus)), dim3(256), 0, ctx->stream,
+    hipLaunchKernelGGL(k_shortcut, dim3(grid_for(cnt, 256, 16 * ctx->num_cus)), dim3(256), 0, ctx->stream,
                        W.parent, W.msfC,
                        &info[I_MSF0], &info[I_MSF]);
     cur = W.bestB;
@@ -1105,7 +1108,7 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, boo
       int co = out == 0 ? I_LIVE0 : I_LIVE1;
       {
         TimedScope ts(ctx, "forest_candidates", (double)bound);
-        hipLaunchKernelGGL(k_bv_candidates, dim3(grid_for(bound, BV_CHUNK)), dim3(BS), 0, ctx->stream,
+        hipLaunchKernelGGL(k_bv_candidates, dim3(grid_for(bound, BC_CHUNK)), dim3(BS), 0, ctx->stream,
                            W.lr[in], W.lp[in], W.lo[in], &info[ci], W.lr[out], W.lp[out], W.lo[out],
                            &info[co], cur, nxt, W.parent, next_scan(ctx, W), &info[I_FIN],
                            &info[I_MSF], &info[I_MSF0]);
@@ -1119,7 +1122,7 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, boo
       }
       {
         TimedScope ts(ctx, "forest_shortcut", (double)bound);
-        hipLaunchKernelGGL(k_shortcut, dim3(grid_for(bound, 256, 2 * ctx->num_cus)), dim3(256), 0,
+        hipLaunchKernelGGL(k_shortcut, dim3(grid_for(bound, 256, 16 * ctx->num_cus)), dim3(256), 0,
                            ctx->stream, W.parent, W.msfC, &info[I_MSF0], &info[I_MSF]);
       }
       SPC_LAUNCH_CHECK(ctx, "forest round");
