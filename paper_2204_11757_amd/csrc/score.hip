@@ -250,23 +250,35 @@ __global__ void __launch_bounds__(BS)
 void launch_score(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t m, int c, int ebits,
                   int mode) {
   int tiles = grid_for(m, TILE_S);
-  if (g.nnz > HUGE_T)
+  bool maps = g.nnz > HUGE_T;
+  if (maps) {
+    TimedScope ts(ctx, "score_long_rows", (double)H_MAX);
     hipLaunchKernelGGL(k_huge_map, dim3(H_MAX * HM_BLOCKS), dim3(BS), 0, ctx->stream, g, W.htab, W.info,
                        W.hmap);
-  bool maps = g.nnz > HUGE_T;
+  }
   if (mode == 0) {
-    hipLaunchKernelGGL(k_score<0>, dim3(tiles), dim3(BS), 0, ctx->stream, g, W.deg, W.lc, W.uptr, m, c,
-                       ebits, W.Pc, W.samples, W.keysA, -1, W.info, W.htab);
-    if (maps)
+    {
+      TimedScope ts(ctx, "score", (double)m);
+      hipLaunchKernelGGL(k_score<0>, dim3(tiles), dim3(BS), 0, ctx->stream, g, W.deg, W.lc, W.uptr, m, c,
+                         ebits, W.Pc, W.samples, W.keysA, -1, W.info, W.htab);
+    }
+    if (maps) {
+      TimedScope ts(ctx, "score_long_rows", (double)H_MAX);
       hipLaunchKernelGGL(k_score_mapped<0>, dim3(H_MAX * HS_BLOCKS), dim3(BS), 0, ctx->stream, g, W.deg,
                          W.lc, W.uptr, c, ebits, W.Pc, W.samples, W.keysA, -1, W.info, W.htab, W.hmap);
+    }
   } else {
-    hipLaunchKernelGGL(k_score<1>, dim3(tiles), dim3(BS), 0, ctx->stream, g, W.deg, W.lc, W.uptr, m, c,
-                       ebits, (uint64_t*)nullptr, (uint64_t*)nullptr, W.keysA, 1, W.info, W.htab);
-    if (maps)
+    {
+      TimedScope ts(ctx, "score_rank", (double)m);
+      hipLaunchKernelGGL(k_score<1>, dim3(tiles), dim3(BS), 0, ctx->stream, g, W.deg, W.lc, W.uptr, m, c,
+                         ebits, (uint64_t*)nullptr, (uint64_t*)nullptr, W.keysA, 1, W.info, W.htab);
+    }
+    if (maps) {
+      TimedScope ts(ctx, "score_long_rows", (double)H_MAX);
       hipLaunchKernelGGL(k_score_mapped<1>, dim3(H_MAX * HS_BLOCKS), dim3(BS), 0, ctx->stream, g, W.deg,
                          W.lc, W.uptr, c, ebits, (uint64_t*)nullptr, (uint64_t*)nullptr, W.keysA, 1, W.info,
                          W.htab, W.hmap);
+    }
   }
 }
 

@@ -1160,8 +1160,7 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
   int c = 62 - ebits;
   const unsigned long long* guard = &info[I_GUARD];
   if (!rank) {
-    TimedScope ts(ctx, "score", (double)m);
-    launch_score(ctx, g, W, m, c, ebits, 0);
+    launch_score(ctx, g, W, m, c, ebits, 0);   // timed inside, one scope per kernel
   }
   if (!rank) {
     hipLaunchKernelGGL(k_key_mode, dim3(1), dim3(1), 0, st, info, c);
@@ -1175,7 +1174,6 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
   } else {
     hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, &info[I_GUARD], 0ull);
     {
-      TimedScope ts(ctx, "score_rank", (double)m);
       launch_score(ctx, g, W, m, c, ebits, 1);
     }
     SPC_LAUNCH_CHECK(ctx, "score(rank)");
