@@ -17,8 +17,7 @@
  * adjacency, nonzero on coarse graphs) and an optional per-node size (the
  * number of original nodes a super-node stands for).
  *
- * Readings of the paper that this file fixes (each is listed with its
- * reason in the design notes):
+ * Readings of the paper that this file fixes:
  *  - w_x is node x's full weighted adjacency row, diagonal included, and
  *    d_x is its row sum (Theorem 1 and the notation following it).
  *  - The coarsened graph keeps the intra-cluster weight as a self-loop
