@@ -178,6 +178,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="grid3d-128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-graph", action="store_true",
+                    help="batch configs: skip the one-call-per-graph comparison (for profiling)")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device tensor copy (reference kernel for "
@@ -284,7 +286,7 @@ def main():
                 roofline["traffic"] = int(tr)
 
     per_graph = None
-    if batch:
+    if batch and not args.no_per_graph:
         # the same graphs coarsened by one coarsen_to call each (inputs resident)
         G = len(g.meta["graphs"])
         print(f"[bench] per-graph calls ({G} graphs)", file=sys.stderr, flush=True)

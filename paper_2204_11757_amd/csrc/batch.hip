@@ -2,52 +2,28 @@
 // graph, each to its own target.  Algorithm 1's merge loop runs per graph;
 // since the graphs share no edge, the union's minimum spanning forest is the
 // union of the graphs' forests, and graph i's merges are the components of
-// its k[i] lightest forest edges.  The kernels below pick those per graph:
-// forest edges are sorted by (graph, key) and the first k[i] of each graph's
-// run are joined.  Edge ids, and so the tie-break, keep each graph's own
-// (u, v) order because graph i's node ids are a contiguous, increasing range.
+// its k[i] lightest forest edges.  Every forest edge hooked exactly one
+// component root, so keying the forest by hooked node puts graph i's forest
+// edges in its own node range: one block per graph selects its k[i]-th key
+// there and joins the edges up to it.  Edge ids, and so the tie-break, keep
+// each graph's own (u, v) order because graph i's node ids are a contiguous,
+// increasing range.
+#include "radix.hpp"
 #include "score.hpp"
 
 namespace spc {
 
-struct KeyGK {
-  uint64_t g, key, i;
-};
-
-struct LessGK {
-  __device__ __forceinline__ bool operator()(const KeyGK& a, const KeyGK& b) const {
-    return a.g < b.g || (a.g == b.g && a.key < b.key);
+// fkey[x] = key of the forest edge that hooked node x, fidx[x] = its record
+__global__ void k_forest_by_node(const uint64_t* __restrict__ msfP, const int32_t* __restrict__ msfC,
+                                 const unsigned long long* cnt, uint64_t* __restrict__ fkey,
+                                 uint64_t* __restrict__ fidx) {
+  int64_t n = (int64_t)*cnt;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    int32_t x = msfC[i];
+    fkey[x] = msfP[i];
+    fidx[x] = (uint64_t)i;
   }
-};
-
-// graph of node x: the last i with off[i] <= x
-__device__ __forceinline__ int64_t graph_of(const int64_t* __restrict__ off, int64_t G, int64_t x) {
-  int64_t lo = 0, hi = G - 1;
-  while (lo < hi) {
-    int64_t mid = (lo + hi + 1) >> 1;
-    if (off[mid] <= x) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
-// first position p in s[0..n) with s[p].g >= gid
-__device__ __forceinline__ int64_t seg_lower(const KeyGK* __restrict__ s, int64_t n, uint64_t gid) {
-  int64_t lo = 0, hi = n;
-  while (lo < hi) {
-    int64_t mid = (lo + hi) >> 1;
-    if (s[mid].g < gid) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
-
-__global__ void k_seg_records(const uint64_t* __restrict__ msfP, const uint64_t* __restrict__ msfO, int64_t n,
-                              const int64_t* __restrict__ off, int64_t G, KeyGK* __restrict__ out) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int64_t u = (int64_t)(uint32_t)msfO[i];
-  out[i] = KeyGK{(uint64_t)graph_of(off, G, u), msfP[i], (uint64_t)i};
 }
 
 __device__ __forceinline__ void atomic_max_double(unsigned long long* p, double v) {
@@ -55,79 +31,179 @@ __device__ __forceinline__ void atomic_max_double(unsigned long long* p, double 
   atomicMax(p, (unsigned long long)__double_as_longlong(v));
 }
 
-// Joins each graph's first k lightest forest edges; the last accepted edge of
-// each graph contributes its exact score to epsilon; with guarded keys, a
-// forest edge of the cutoff's K bucket whose exact score differs from the
-// cutoff's flags the level (the packed order inside that bucket may then be
-// inexact).
-__global__ void k_seg_accept(const KeyGK* __restrict__ s, int64_t n, const int64_t* __restrict__ kseg,
-                             const uint64_t* __restrict__ msfO, int32_t* parent, LevelIn g,
-                             const uint64_t* __restrict__ deg, const int32_t* __restrict__ lc,
-                             const KeyND* __restrict__ exact, int ebits, unsigned long long* info) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  uint64_t gid = s[p].g;
-  int64_t start = seg_lower(s, n, gid);
-  int64_t k = kseg[gid];
-  int64_t r = p - start;
-  if (k <= 0) return;
-  int64_t c = start + k - 1;              // the graph's cutoff position
-  uint64_t uv = msfO[s[p].i];
-  int32_t u = (int32_t)(uint32_t)uv, v = (int32_t)(uv >> 32);
-  if (r < k) uf_union(parent, u, v);
-  if (r == k - 1) {
-    int64_t lo = g.rp[u], hi = g.rp[u + 1];
-    while (lo < hi) {
-      int64_t mid = (lo + hi) >> 1;
-      if (g.col[mid] < v) lo = mid + 1;
-      else hi = mid;
+// One block per graph: the (k-1)-th smallest forest key of the graph's node
+// range (radix passes over the range with an LDS histogram, the extreme-key
+// skip, and an LDS finish once at most SEL_SMALL keys remain), then the union
+// of every forest edge up to it.  The cutoff edge's exact score goes into
+// epsilon; with guarded keys, a forest edge of the cutoff's K bucket whose
+// exact score differs from the cutoff's flags the level.  A graph with fewer
+// than k forest edges sets info[I_SEG_SHORT].
+__global__ void __launch_bounds__(SEL_BS)
+    k_seg_select(const uint64_t* __restrict__ fkey, const uint64_t* __restrict__ fidx,
+                 const int64_t* __restrict__ off, const int64_t* __restrict__ kseg,
+                 const uint64_t* __restrict__ msfO, int32_t* parent, LevelIn g,
+                 const uint64_t* __restrict__ deg, const int32_t* __restrict__ lc,
+                 const KeyND* __restrict__ exact, int ebits, unsigned long long* info) {
+  __shared__ unsigned int h[SEL_BINS];
+  __shared__ uint64_t sbuf[SEL_SMALL];
+  __shared__ unsigned long long tmp[SEL_BS / WAVE];
+  __shared__ unsigned long long red[2 * (SEL_BS / WAVE)];
+  __shared__ unsigned long long spick[3];
+  __shared__ unsigned int slocal;
+  int t = threadIdx.x;
+  int64_t gid = blockIdx.x;
+  int64_t lo = off[gid], hi_n = off[gid + 1];
+  int64_t kk = kseg[gid];
+  if (kk <= 0) return;   // no merges in this graph
+  unsigned long long k = (unsigned long long)(kk - 1);
+  uint64_t prefix = 0, mask = 0;
+  int hi = 64;
+  int64_t cb = -1;   // keys matching (prefix, mask); unknown before the first pass
+  bool first = true;
+  while (hi > 0 && (cb < 0 || cb > SEL_SMALL)) {
+    int lo_b = hi - SEL_DIGIT > 0 ? hi - SEL_DIGIT : 0;
+    int nb = 1 << (hi - lo_b);
+    uint64_t dm = (uint64_t)(nb - 1);
+    for (int b = t; b < SEL_BINS; b += SEL_BS) h[b] = 0;
+    __syncthreads();
+    uint64_t mn = ~0ull, mx = 0;
+    for (int64_t i0 = lo; i0 < hi_n; i0 += SEL_BS * SEL_UNROLL) {
+      uint64_t x[SEL_UNROLL];
+#pragma unroll
+      for (int u = 0; u < SEL_UNROLL; u++) {
+        int64_t i = i0 + u * SEL_BS + t;
+        x[u] = i < hi_n ? fkey[i] : KEY_INF;
+      }
+#pragma unroll
+      for (int u = 0; u < SEL_UNROLL; u++) {
+        bool m = x[u] != KEY_INF && (x[u] & mask) == prefix;
+        hist_add(h, m, (uint32_t)((x[u] >> lo_b) & dm));
+        if (m) {
+          mn = x[u] < mn ? x[u] : mn;
+          mx = x[u] > mx ? x[u] : mx;
+        }
+      }
     }
-    uint64_t N, D;
-    int64_t jm;
-    edge_score(g, deg, lc, u, v, g.w[lo], N, D, jm);
-    atomic_max_double(&info[I_EPS], (double)N / (double)D);
-  }
-  if (exact && info[I_GUARD] && c < n && s[c].g == gid && p != c) {
-    uint64_t kp = s[p].key, kc = s[c].key;
-    if ((kp >> ebits) == (kc >> ebits)) {
-      uint64_t emask = (1ull << ebits) - 1;
-      KeyND x = exact[kp & emask], y = exact[kc & emask];
-      if ((unsigned __int128)x.N * y.D != (unsigned __int128)y.N * x.D) atomicOr(&info[I_VIOL], 1ull);
+    __syncthreads();
+    block_minmax(mn, mx, red);
+    unsigned long long cnt = 0;
+    for (int q = 0; q < SEL_BINS / SEL_BS; q++) {
+      int b = SEL_BINS / SEL_BS * t + q;
+      cnt += b < nb ? h[b] : 0u;
+    }
+    unsigned long long total;
+    unsigned long long before = block_incl_scan<unsigned long long, SEL_BS, false>(cnt, tmp, &total) - cnt;
+    if (first && total <= k) {
+      // fewer forest edges than merges: the target is out of reach
+      if (t == 0) atomicOr(&info[I_SEG_SHORT], 1ull);
+      return;
+    }
+    if (k >= before && k < before + cnt) {
+      unsigned long long acc = before;
+      for (int q = 0; q < SEL_BINS / SEL_BS; q++) {
+        int b = SEL_BINS / SEL_BS * t + q;
+        unsigned long long c = b < nb ? h[b] : 0u;
+        if (k >= acc && k < acc + c) {
+          spick[0] = (unsigned long long)b;
+          spick[1] = acc;
+          spick[2] = c;
+        }
+        acc += c;
+      }
+    }
+    __syncthreads();
+    bool all_one = (unsigned long long)spick[2] == total;
+    prefix |= spick[0] << lo_b;
+    mask |= dm << lo_b;
+    k -= spick[1];
+    cb = (int64_t)spick[2];
+    hi = lo_b;
+    first = false;
+    __syncthreads();
+    if (all_one) {
+      // every matching key is in this bucket: the bits the extreme ones share
+      uint64_t xx = mn ^ mx;
+      if (xx == 0) {
+        prefix = mn;
+        mask = ~0ull;
+        hi = 0;
+      } else {
+        int d = 63 - __clzll((long long)xx);
+        if (d + 1 < hi) {
+          uint64_t low = (2ull << d) - 1;
+          prefix = mn & ~low;
+          mask = ~low;
+          hi = d + 1;
+        }
+      }
     }
   }
-}
-
-// a graph whose forest has fewer than k edges cannot reach its target
-__global__ void k_seg_reach(const KeyGK* __restrict__ s, int64_t n, const int64_t* __restrict__ kseg, int64_t G,
-                            unsigned long long* info) {
-  int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= G) return;
-  int64_t cnt = seg_lower(s, n, (uint64_t)gid + 1) - seg_lower(s, n, (uint64_t)gid);
-  if (cnt < kseg[gid]) atomicOr(&info[I_SEG_SHORT], 1ull);
+  uint64_t cut;
+  if (hi == 0) {
+    cut = prefix;
+  } else {
+    // at most SEL_SMALL keys match: gather them and finish in LDS
+    if (t == 0) slocal = 0;
+    __syncthreads();
+    for (int64_t i0 = lo; i0 < hi_n; i0 += SEL_BS) {
+      int64_t i = i0 + t;
+      uint64_t x = i < hi_n ? fkey[i] : KEY_INF;
+      bool m = x != KEY_INF && (x & mask) == prefix;
+      unsigned int q = wave_reserve(&slocal, m);
+      if (m && q < (unsigned)SEL_SMALL) sbuf[q] = x;
+    }
+    __syncthreads();
+    unsigned int c = slocal < (unsigned)SEL_SMALL ? slocal : (unsigned)SEL_SMALL;
+    cut = lds_select(sbuf, (int)c, k, h, tmp, red, spick, &info[I_LBERR]);
+  }
+  // join the forest edges up to the cutoff; the cutoff edge gives epsilon
+  bool guarded = exact && info[I_GUARD];
+  uint64_t emask = (1ull << ebits) - 1;
+  for (int64_t x0 = lo; x0 < hi_n; x0 += SEL_BS) {
+    int64_t x = x0 + t;
+    if (x >= hi_n) break;
+    uint64_t key = fkey[x];
+    if (key == KEY_INF) continue;
+    if (key <= cut) {
+      uint64_t uv = msfO[fidx[x]];
+      int32_t u = (int32_t)(uint32_t)uv, v = (int32_t)(uv >> 32);
+      uf_union(parent, u, v);
+      if (key == cut) {
+        int64_t a = g.rp[u], b = g.rp[u + 1];
+        while (a < b) {
+          int64_t mid = (a + b) >> 1;
+          if (g.col[mid] < v) a = mid + 1;
+          else b = mid;
+        }
+        uint64_t N, D;
+        int64_t jm;
+        edge_score(g, deg, lc, u, v, g.w[a], N, D, jm);
+        atomic_max_double(&info[I_EPS], (double)N / (double)D);
+      }
+    }
+    if (guarded && key != cut && (key >> ebits) == (cut >> ebits)) {
+      KeyND p = exact[key & emask], q = exact[cut & emask];
+      if ((unsigned __int128)p.N * q.D != (unsigned __int128)q.N * p.D) atomicOr(&info[I_VIOL], 1ull);
+    }
+  }
 }
 
 int seg_cutoff_union(spc_ctx* ctx, const LevelIn& g, LevelWork& W, const LevelResult& R, const Segments& seg,
                      int ebits, bool rank) {
   hipStream_t st = ctx->stream;
-  int64_t n = R.msf;
-  // the gather buffers of the contraction are free during selection and
-  // hold 16 nnz + 64 bytes >= 24 bytes per forest edge; keysA keeps the
-  // exact score records for the guarded checks
-  KeyGK* A = (KeyGK*)W.gkeyA;
-  KeyGK* B = (KeyGK*)W.gkeyB;
-  KeyGK* sorted = A;
-  if (n > 0) {
-    hipLaunchKernelGGL(k_seg_records, dim3(grid_for(n, 256)), dim3(256), 0, st, W.msfP, W.msfO, n, seg.off,
-                       seg.G, A);
-    int rc = merge_sort<KeyGK, LessGK>(ctx, A, B, n, LessGK(), &sorted);
-    if (rc) return rc;
-    // packed keys: exact records (keysA) for the guarded check, consulted
-    // only when the level's keys are guarded (info[I_GUARD])
-    const KeyND* exact = rank ? nullptr : W.keysA;
-    hipLaunchKernelGGL(k_seg_accept, dim3(grid_for(n, 256)), dim3(256), 0, st, sorted, n, seg.k, W.msfO,
-                       W.parent, g, W.deg, W.lc, exact, ebits, W.info);
-  }
-  hipLaunchKernelGGL(k_seg_reach, dim3(grid_for(seg.G, 256)), dim3(256), 0, st, sorted, n, seg.k, seg.G, W.info);
+  int64_t n = g.n;
+  // the lightest-key arrays of the forest rounds are free now
+  uint64_t* fkey = W.bestA;
+  uint64_t* fidx = W.bestB;
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, fkey, n, KEY_INF);
+  if (R.msf > 0)
+    hipLaunchKernelGGL(k_forest_by_node, dim3(grid_for(R.msf, 256, ctx->num_cus * 16)), dim3(256), 0, st,
+                       W.msfP, W.msfC, &W.info[I_MSF], fkey, fidx);
+  // packed keys: exact records (keysA) for the guarded check, consulted
+  // only when the level's keys are guarded (info[I_GUARD])
+  const KeyND* exact = rank ? nullptr : W.keysA;
+  hipLaunchKernelGGL(k_seg_select, dim3((unsigned)seg.G), dim3(SEL_BS), 0, st, fkey, fidx, seg.off, seg.k,
+                     W.msfO, W.parent, g, W.deg, W.lc, exact, ebits, W.info);
   SPC_LAUNCH_CHECK(ctx, "batched cutoff");
   return SPC_OK;
 }

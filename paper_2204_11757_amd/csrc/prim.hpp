@@ -264,6 +264,7 @@ __global__ void k_clear(int32_t* a, int64_t na, uint64_t* b, int64_t nb, uint64_
 __global__ void k_readback(const unsigned long long* info, int ninfo, const int64_t* x0,
                            const int32_t* x1, const uint64_t* x2, int64_t* out);
 __global__ void k_copy_u64(unsigned long long* dst, const unsigned long long* src);
+__global__ void k_fill_u64(uint64_t* __restrict__ a, int64_t n, uint64_t v);
 void launch_clear(spc_ctx* ctx, int32_t* a, int64_t na, uint64_t* b, int64_t nb, unsigned long long* info,
                   uint32_t slots, uint64_t* c = nullptr, int64_t nc = 0);
 
