@@ -237,7 +237,7 @@ static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* clus
     R.nnz_c = g->nnz;
     R.maxcl = 1;
   } else {
-    rc = contract_level(ctx, L, cluster_of, R.n_c, out, W, R);
+    rc = contract_level(ctx, L, cluster_of, R.n_c, out, W, R, seg);
     if (rc) return rc;
   }
   *nnz_c = R.nnz_c;
@@ -528,16 +528,19 @@ int spc_coarsen_batched(spc_ctx* ctx, int32_t G, const spc_graph* g, const int64
   }
   int64_t* d_off = (int64_t*)dev_alloc(ctx, sizeof(int64_t) * (G + 1));
   int64_t* d_k = (int64_t*)dev_alloc(ctx, sizeof(int64_t) * G);
+  int64_t* d_coff = (int64_t*)dev_alloc(ctx, sizeof(int64_t) * (G + 1));
   spc_hier* h = new (std::nothrow) spc_hier();
-  if (!h || !d_off || !d_k) {
+  if (!h || !d_off || !d_k || !d_coff) {
     dev_free(ctx, d_off);
     dev_free(ctx, d_k);
+    dev_free(ctx, d_coff);
     delete h;
     return set_error(ctx, SPC_ENOMEM, "batch allocation failed");
   }
   auto fail = [&](int code) {
     dev_free(ctx, d_off);
     dev_free(ctx, d_k);
+    dev_free(ctx, d_coff);
     spc_hier_free(h);
     return code;
   };
@@ -560,7 +563,9 @@ int spc_coarsen_batched(spc_ctx* ctx, int32_t G, const spc_graph* g, const int64
     if (!more) break;
     SPC_HIP(ctx, hipMemcpyAsync(d_off, off.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, ctx->stream));
     SPC_HIP(ctx, hipMemcpyAsync(d_k, kk.data(), sizeof(int64_t) * G, hipMemcpyHostToDevice, ctx->stream));
-    Segments seg{G, d_off, d_k};
+    SPC_HIP(ctx, hipMemcpyAsync(d_coff, noff.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice,
+                                ctx->stream));
+    Segments seg{G, d_off, d_k, d_coff, *std::max_element(tg.begin(), tg.end())};
     spc_hier::Level L;
     L.n_prev = cur.n;
     L.wtype = SPC_W_I32;
@@ -593,6 +598,7 @@ int spc_coarsen_batched(spc_ctx* ctx, int32_t G, const spc_graph* g, const int64
   if (rc) return fail(rc);
   dev_free(ctx, d_off);
   dev_free(ctx, d_k);
+  dev_free(ctx, d_coff);
   *out = h;
   return SPC_OK;
 }

@@ -663,14 +663,17 @@ __global__ void __launch_bounds__(HT_BS)
 }
 
 // Dense path for few huge rows: row h's cross weights accumulate in
-// dense[h * ncp + b] (u32; a row's total stays below 2^31), then a compaction
-// in ascending b emits the row.  Same tiling and self-loop handling as
-// k_huge_entries.
+// dense[h * ncp + (b - base[h])] (u32; a row's total stays below 2^31), then
+// a compaction in ascending b emits the row.  base is null (0) for one graph;
+// in a batch it is the first coarse node of the row's graph, whose coarse
+// range (at most ncp wide) holds every column of the row.  Same tiling and
+// self-loop handling as k_huge_entries.
 __global__ void __launch_bounds__(HT_BS)
     k_huge_dense(LevelIn g, const int32_t* __restrict__ c, const int32_t* __restrict__ hugelist,
                  const int32_t* __restrict__ hrow, const int64_t* __restrict__ hrs,
                  const int64_t* __restrict__ hpre, int64_t bound, int64_t* self_out,
-                 uint32_t* __restrict__ dense, int64_t ncp) {
+                 uint32_t* __restrict__ dense, int64_t ncp, const int32_t* __restrict__ base,
+                 unsigned long long* bad) {
   __shared__ int32_t srow[Lbs<HT, HT_BS>::SIZE];
   __shared__ int64_t sh[2];
   __shared__ int32_t stmp[HT_BS / WAVE];
@@ -696,8 +699,10 @@ __global__ void __launch_bounds__(HT_BS)
       int64_t j = hrs[i] + (q - hpre[i]);
       int32_t b = c[g.col[j]];
       uint32_t w = (uint32_t)g.w[j];
+      int64_t rel = (int64_t)b - (base ? base[h] : 0);
       if (b == a) self = w;
-      else atomicAdd(&dense[(int64_t)h * ncp + b], w);
+      else if ((uint64_t)rel < (uint64_t)ncp) atomicAdd(&dense[(int64_t)h * ncp + rel], w);
+      else *bad = 1;
     }
     bool head;
     int end;
@@ -722,11 +727,14 @@ constexpr int DC_T = DC_BS * DC_PER;
 __global__ void __launch_bounds__(DC_BS)
     k_dense_compact(const uint32_t* __restrict__ dense, int64_t ncp, int64_t n_c, int64_t tpr,
                     const int32_t* __restrict__ hugelist, const int64_t* __restrict__ gptr,
-                    uint64_t* __restrict__ temp, int64_t* cnt, TileScan ts) {
+                    uint64_t* __restrict__ temp, int64_t* cnt, TileScan ts,
+                    const int32_t* __restrict__ base) {
   __shared__ int stmp[DC_BS / WAVE];
   __shared__ unsigned long long sbase;
   int64_t h = blockIdx.x / tpr, t = blockIdx.x % tpr;
   int32_t a = hugelist[h];
+  int64_t cb = base ? base[h] : 0;   // column of the window's first slot
+  n_c -= cb;                          // slots past the last coarse node stay unused
   int64_t b0 = t * DC_T + (int64_t)threadIdx.x * DC_PER;
   const uint4* src = (const uint4*)(dense + h * ncp + b0);
   uint4 v0 = src[0], v1 = src[1];
@@ -741,7 +749,21 @@ __global__ void __launch_bounds__(DC_BS)
   uint64_t* o = temp + gptr[a];
 #pragma unroll
   for (int q = 0; q < DC_PER; q++)
-    if (v[q] != 0 && b0 + q < n_c) o[pos++] = ((uint64_t)(b0 + q) << 32) | v[q];
+    if (v[q] != 0 && b0 + q < n_c) o[pos++] = ((uint64_t)(cb + b0 + q) << 32) | v[q];
+}
+
+// first coarse node of the graph holding huge row h (batches)
+__global__ void k_huge_base(const int32_t* __restrict__ hugelist, int64_t H, const int64_t* __restrict__ coff,
+                            int64_t G, int32_t* __restrict__ base) {
+  int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= H) return;
+  int64_t a = hugelist[h], lo = 0, hi = G - 1;
+  while (lo < hi) {   // the last graph whose range starts at or before a
+    int64_t mid = (lo + hi + 1) >> 1;
+    if (coff[mid] <= a) lo = mid;
+    else hi = mid - 1;
+  }
+  base[h] = (int32_t)coff[lo];
 }
 
 __global__ void k_head_flags(const KW* __restrict__ s, int64_t G, int32_t* __restrict__ flag,
@@ -825,7 +847,7 @@ __global__ void __launch_bounds__(PACK_BS)
 }
 
 int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c,
-                   spc_graph_out* out, LevelWork& W, LevelResult& R) {
+                   spc_graph_out* out, LevelWork& W, LevelResult& R, const Segments* seg) {
   hipStream_t st = ctx->stream;
   int64_t n = g.n;
   int64_t* hinfo = ctx->h_pinned;
@@ -892,16 +914,25 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
     if (rc) return rc;
     // few huge rows: dense accumulators over the coarse ids (they fit in
     // the gather buffers when H * ncp <= 2 nnz)
-    int64_t ncp = (n_c + DC_T - 1) / DC_T * DC_T;
+    // (in a batch, per huge row only the coarse range of its own graph)
+    int64_t win = seg ? seg->wmax : n_c;
+    int64_t ncp = (win + DC_T - 1) / DC_T * DC_T;
     if (!ctx->force_huge_sort && H * ncp <= 2 * g.nnz) {
       uint32_t* dense = (uint32_t*)W.gkeyA;
+      int32_t* base = nullptr;
+      if (seg) {
+        base = W.hmnode;   // free on this path
+        hipLaunchKernelGGL(k_huge_base, dim3(grid_for(H, 256)), dim3(256), 0, st, W.hugelist, H, seg->coff,
+                           seg->G, base);
+      }
       launch_clear(ctx, (int32_t*)dense, H * ncp, nullptr, 0, nullptr, 0u);
       if (g.nnz > 0)
         hipLaunchKernelGGL(k_huge_dense, dim3(grid_for(g.nnz, HT)), dim3(HT_BS), 0, st, g, c, W.hugelist,
-                           W.hmrow, W.hmrs, hpre, n, self_out, dense, ncp);
+                           W.hmrow, W.hmrs, hpre, n, self_out, dense, ncp, (const int32_t*)base,
+                           &info[I_DENSE]);
       int64_t tpr = ncp / DC_T;
       hipLaunchKernelGGL(k_dense_compact, dim3((unsigned)(H * tpr)), dim3(DC_BS), 0, st, dense, ncp, n_c,
-                         tpr, W.hugelist, W.gptr, W.temp, W.cnt, next_scan(ctx, W));
+                         tpr, W.hugelist, W.gptr, W.temp, W.cnt, next_scan(ctx, W), (const int32_t*)base);
       SPC_LAUNCH_CHECK(ctx, "huge dense");
     } else {
     launch_clear(ctx, nullptr, 0, nullptr, 0, info, 1u << I_LIVE1);
@@ -959,6 +990,7 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
   SPC_LAUNCH_CHECK(ctx, "readback");
   SPC_HIP(ctx, hipStreamSynchronize(st));
   int64_t nnz_c = hinfo[I_NINFO];
+  if (hinfo[I_DENSE]) return set_error(ctx, SPC_EINVAL, "internal: a huge row left its graph's coarse range");
   if (hinfo[I_LBERR] || hinfo[I_NINFO + 2])
     return set_error(ctx, SPC_EINVAL, "internal: look-back wait gave up");
   if (nnz_c > out->nnz_cap)

@@ -77,8 +77,10 @@ struct LessFD {
 // Device arrays.
 struct Segments {
   int64_t G;
-  const int64_t* off;   // [G + 1]
-  const int64_t* k;     // [G]
+  const int64_t* off;   // [G + 1] node ranges of the graphs
+  const int64_t* k;     // [G] merges per graph
+  const int64_t* coff;  // [G + 1] the graphs' coarse node ranges after the level
+  int64_t wmax;         // largest coarse range
 };
 
 // Exact sort key of the rank-mode order: score N / D, ties by edge index.
@@ -130,6 +132,7 @@ enum Info : int {
   I_FP_BAD = 26,  // floating-point path: a weight is not finite / not positive
   I_SEG_SHORT = 27, // batch: a graph has fewer forest edges than merges needed
   I_CAND = 28,    // live edges the band's row pass produced (a copy of I_LIVE0)
+  I_DENSE = 29,   // a dense row accumulator index fell outside its window (internal error)
   I_NINFO = 32
 };
 
@@ -277,6 +280,6 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
 
 // Step A5: contraction of Definition 1 into caller buffers.
 int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* cluster_of, int64_t n_c,
-                   spc_graph_out* out, LevelWork& W, LevelResult& R);
+                   spc_graph_out* out, LevelWork& W, LevelResult& R, const Segments* seg = nullptr);
 
 }  // namespace spc
