@@ -24,12 +24,16 @@ namespace spc {
 // ---------------------------------------------------------------------------
 // workspace plan
 // ---------------------------------------------------------------------------
+constexpr int DEG_PER = 4;
+constexpr int DEG_ROWS = BS * DEG_PER;
+constexpr int DEG_SHORT = 64;
+
 void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W, bool fp) {
   int64_t m = nnz / 2;
   W.info = A.take<unsigned long long>(I_NINFO);
   W.lbstate = A.take<uint64_t>(lb_words(n, nnz));
   W.deg = A.take<uint64_t>(n);
-  W.degpart = A.take<uint64_t>(n / 4096 + 2);
+  W.degpart = A.take<uint64_t>(n / DEG_ROWS + 2);
   W.lc = A.take<int32_t>(n);
   W.uptr = A.take<int64_t>(n + 1);
   W.P = A.take<uint64_t>(m);
@@ -90,11 +94,8 @@ void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W, bool fp) {
 
 // ---------------------------------------------------------------------------
 // A1: degrees, upper-entry counts, and per-level initialisation.
-// A block covers 4096 consecutive rows, 16 per thread.
+// A block covers 1024 consecutive rows, 4 per thread.
 // ---------------------------------------------------------------------------
-constexpr int DEG_PER = 16;
-constexpr int DEG_ROWS = BS * DEG_PER;
-constexpr int DEG_SHORT = 64;
 
 __global__ void __launch_bounds__(BS)
     k_degree(LevelIn g, uint64_t* __restrict__ deg, int32_t* __restrict__ lc,
@@ -113,21 +114,40 @@ __global__ void __launch_bounds__(BS)
     int64_t u = base + i * BS + tid;
     if (u >= g.n) break;
     int64_t s = g.rp[u], e = g.rp[u + 1];
-    int64_t lo = s, hi = e;   // entries with col < u
-    while (lo < hi) {
-      int64_t mid = (lo + hi) >> 1;
-      if (g.col[mid] < u) lo = mid + 1;
-      else hi = mid;
-    }
-    lc[u] = (int32_t)(lo - s);
-    ucnt[u] = e - lo;
     if (e - s <= DEG_SHORT) {
+      // weights summed and lower entries counted in one sweep, the loads of
+      // each chunk of 8 entries issued together
       uint64_t d = g.self ? (uint64_t)g.self[u] : 0;
-      for (int64_t j = s; j < e; j++) d += (uint64_t)g.w[j];
+      int32_t below = 0;
+      for (int64_t j0 = s; j0 < e; j0 += 8) {
+        int32_t cc[8];
+        uint32_t ww[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+          bool in = j0 + q < e;
+          cc[q] = in ? g.col[j0 + q] : INT32_MAX;
+          ww[q] = in ? (uint32_t)g.w[j0 + q] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+          d += ww[q];
+          below += cc[q] < u ? 1 : 0;
+        }
+      }
+      lc[u] = below;
+      ucnt[u] = (e - s) - below;
       deg[u] = d;
       mx = d > mx ? d : mx;
       sm += d;
     } else {
+      int64_t lo = s, hi = e;   // entries with col < u
+      while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (g.col[mid] < u) lo = mid + 1;
+        else hi = mid;
+      }
+      lc[u] = (int32_t)(lo - s);
+      ucnt[u] = e - lo;
       longmask |= 1u << i;
       nlong++;
     }
