@@ -33,7 +33,7 @@ __device__ __forceinline__ void atomic_max_double(unsigned long long* p, double 
 
 // One block per graph: the (k-1)-th smallest forest key of the graph's node
 // range (radix passes over the range with an LDS histogram, the extreme-key
-// skip, and an LDS finish once at most SEL_SMALL keys remain), then the union
+// skip, and an LDS finish once at most SEG_SMALL keys remain), then the union
 // of every forest edge up to it.  The cutoff edge's exact score goes into
 // epsilon; with guarded keys, a forest edge of the cutoff's K bucket whose
 // exact score differs from the cutoff's flags the level.  A graph with fewer
@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(SEL_BS)
                  const uint64_t* __restrict__ deg, const int32_t* __restrict__ lc,
                  const KeyND* __restrict__ exact, int ebits, unsigned long long* info) {
   __shared__ unsigned int h[SEL_BINS];
-  __shared__ uint64_t sbuf[SEL_SMALL];
+  __shared__ uint64_t sbuf[SEG_SMALL];
   __shared__ unsigned long long tmp[SEL_BS / WAVE];
   __shared__ unsigned long long red[2 * (SEL_BS / WAVE)];
   __shared__ unsigned long long spick[3];
@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(SEL_BS)
   int hi = 64;
   int64_t cb = -1;   // keys matching (prefix, mask); unknown before the first pass
   bool first = true;
-  while (hi > 0 && (cb < 0 || cb > SEL_SMALL)) {
+  while (hi > 0 && (cb < 0 || cb > SEG_SMALL)) {
     int lo_b = hi - SEL_DIGIT > 0 ? hi - SEL_DIGIT : 0;
     int nb = 1 << (hi - lo_b);
     uint64_t dm = (uint64_t)(nb - 1);
@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(SEL_BS)
   if (hi == 0) {
     cut = prefix;
   } else {
-    // at most SEL_SMALL keys match: gather them and finish in LDS
+    // at most SEG_SMALL keys match: gather them and finish in LDS
     if (t == 0) slocal = 0;
     __syncthreads();
     for (int64_t i0 = lo; i0 < hi_n; i0 += SEL_BS) {
@@ -150,10 +150,10 @@ __global__ void __launch_bounds__(SEL_BS)
       uint64_t x = i < hi_n ? fkey[i] : KEY_INF;
       bool m = x != KEY_INF && (x & mask) == prefix;
       unsigned int q = wave_reserve(&slocal, m);
-      if (m && q < (unsigned)SEL_SMALL) sbuf[q] = x;
+      if (m && q < (unsigned)SEG_SMALL) sbuf[q] = x;
     }
     __syncthreads();
-    unsigned int c = slocal < (unsigned)SEL_SMALL ? slocal : (unsigned)SEL_SMALL;
+    unsigned int c = slocal < (unsigned)SEG_SMALL ? slocal : (unsigned)SEG_SMALL;
     cut = lds_select(sbuf, (int)c, k, h, tmp, red, spick, &info[I_LBERR]);
   }
   // join the forest edges up to the cutoff; the cutoff edge gives epsilon

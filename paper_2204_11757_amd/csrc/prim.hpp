@@ -231,7 +231,8 @@ constexpr int SEL_DIGIT = 11;
 constexpr int SEL_BINS = 1 << SEL_DIGIT;
 constexpr int SEL_GBINS = 64;                     // bins per group
 constexpr int SEL_NGRP = SEL_BINS / SEL_GBINS;    // 32 groups
-constexpr int SEL_SMALL = 4096;
+constexpr int SEL_SMALL = 16384;   // keys one block finishes in LDS (128 KB)
+constexpr int SEG_SMALL = 4096;    // the same for the per-graph selects of batches
 constexpr int SEL_MAXB = 128;    // blocks of one select
 constexpr int SEL_FLAG = 8;      // flag stride (one 64-byte line per block)
 
@@ -239,8 +240,8 @@ struct SelState {
   unsigned long long prefix, mask;
   unsigned long long pad[2];
   unsigned long long bmn[2][SEL_MAXB], bmx[2][SEL_MAXB];   // extreme matching keys per block
-  unsigned int gsum[2][SEL_NGRP][SEL_MAXB];          // per-block group sums, pass p in [p % 2]
-  unsigned int bhist[2][SEL_BINS][SEL_MAXB];         // per-block histograms by bin
+  unsigned int gsum[2][SEL_MAXB][SEL_NGRP];          // per-block group sums, pass p in [p % 2]
+  unsigned int bhist[2][SEL_MAXB][SEL_BINS];         // per-block histograms
   uint64_t buf[SEL_SMALL];                           // gathered keys
 };
 

@@ -59,55 +59,79 @@ __device__ __forceinline__ void block_minmax(uint64_t& mn, uint64_t& mx, unsigne
   __syncthreads();
 }
 
-// The k-th smallest of the c <= SEL_SMALL keys in s (LDS), by one block with
-// 8-bit digits below the highest bit in which the keys differ.
+// The k-th smallest of the c keys in s (LDS), by one block.
+// Each round first finds the smallest and largest key still in play and
+// decides the bits they share (so a run of equal scores costs nothing),
+// then histograms the next 11 bits (8 bins per thread) and keeps the
+// bucket of the k-th key.  h needs SEL_BS * 8 counters.
 __device__ __forceinline__ uint64_t lds_select(const uint64_t* s, int c, unsigned long long k, unsigned int* h,
-                               unsigned long long* tmp, unsigned long long* red, unsigned long long* spick,
-                               unsigned long long* err) {
+                                               unsigned long long* tmp, unsigned long long* red,
+                                               unsigned long long* spick, unsigned long long* err) {
+  constexpr int PER = 8;
+  constexpr int DIG = 11;
   int t = threadIdx.x;
   if (k >= (unsigned long long)c) {
     if (t == 0) __hip_atomic_store(err, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return ~0ull;
   }
-  uint64_t mn = ~0ull, mx = 0;
-  for (int i = t; i < c; i += SEL_BS) {
-    mn = s[i] < mn ? s[i] : mn;
-    mx = s[i] > mx ? s[i] : mx;
-  }
-  block_minmax(mn, mx, red);
-  uint64_t x = mn ^ mx;
-  if (x == 0) return mn;
-  int hi = 64 - __clzll((long long)x);
-  uint64_t mask = hi == 64 ? 0ull : ~((1ull << hi) - 1);
-  uint64_t prefix = mn & mask;
-  while (hi > 0) {
-    int lo = hi - 8 > 0 ? hi - 8 : 0;
+  uint64_t prefix = 0, mask = 0;
+  int hi = 64;
+  while (true) {
+    uint64_t mn = ~0ull, mx = 0;
+    for (int i = t; i < c; i += SEL_BS) {
+      uint64_t x = s[i];
+      if ((x & mask) == prefix) {
+        mn = x < mn ? x : mn;
+        mx = x > mx ? x : mx;
+      }
+    }
+    block_minmax(mn, mx, red);
+    uint64_t x = mn ^ mx;
+    if (x == 0) return mn;   // every key in play is equal
+    int d = 63 - __clzll((long long)x);   // highest differing bit, below hi
+    uint64_t low = d == 63 ? ~0ull : (2ull << d) - 1;
+    prefix = mn & ~low;
+    mask = ~low;
+    hi = d + 1;
+    int lo = hi - DIG > 0 ? hi - DIG : 0;
     int nb = 1 << (hi - lo);
     uint64_t dm = (uint64_t)(nb - 1);
-    h[t] = 0;
+    for (int q = 0; q < PER; q++) h[PER * t + q] = 0;
     __syncthreads();
     for (int i0 = 0; i0 < c; i0 += SEL_BS) {
       int i = i0 + t;
-      uint64_t x = i < c ? s[i] : 0;
-      hist_add(h, i < c && (x & mask) == prefix, (uint32_t)((x >> lo) & dm));
+      uint64_t y = i < c ? s[i] : 0;
+      hist_add(h, i < c && (y & mask) == prefix, (uint32_t)((y >> lo) & dm));
     }
     __syncthreads();
-    unsigned long long cnt = t < nb ? h[t] : 0;
+    unsigned int cq[PER];
+    unsigned long long cnt = 0;
+    for (int q = 0; q < PER; q++) {
+      int b = PER * t + q;
+      cq[q] = b < nb ? h[b] : 0u;
+      cnt += cq[q];
+    }
     unsigned long long tot;
     unsigned long long before = block_incl_scan<unsigned long long, SEL_BS, false>(cnt, tmp, &tot) - cnt;
     if (k >= before && k < before + cnt) {
-      spick[0] = (unsigned long long)t;
-      spick[1] = before;
-      spick[2] = cnt;
+      unsigned long long acc = before;
+      for (int q = 0; q < PER; q++) {
+        if (k >= acc && k < acc + cq[q]) {
+          spick[0] = (unsigned long long)(PER * t + q);
+          spick[1] = acc;
+          spick[2] = cq[q];
+        }
+        acc += cq[q];
+      }
     }
     __syncthreads();
     prefix |= spick[0] << lo;
     mask |= dm << lo;
     k -= spick[1];
-    hi = lo;
     bool one = spick[2] == 1;
     __syncthreads();
-    if (one && hi > 0) {
+    if (lo == 0) return prefix;
+    if (one) {
       // a single key is left in the bucket: find it
       for (int i = t; i < c; i += SEL_BS)
         if ((s[i] & mask) == prefix) spick[0] = s[i];
@@ -117,7 +141,6 @@ __device__ __forceinline__ uint64_t lds_select(const uint64_t* s, int c, unsigne
       return r;
     }
   }
-  return prefix;
 }
 
 }  // namespace spc

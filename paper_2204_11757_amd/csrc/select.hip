@@ -612,27 +612,23 @@ __device__ void sel_barrier(unsigned long long* flags, unsigned long long epoch,
   __syncthreads();
 }
 
-// Sum of row[0..G) (G <= SEL_MAXB, 16-byte aligned rows) for `lanes`
-// threads sharing the row: thread `sub` takes every lanes-th vector.  All
-// of a thread's loads are issued before any is used (after a barrier they
-// all go to memory).
+// Sum over blocks j = sub, sub + LANES, ... < G of a[j * stride + col]: the
+// column of one bin (or group) in the per-block histograms, for LANES
+// threads sharing it.  All of a thread's loads are issued before any is
+// used (after a barrier they all go to memory).
 template <int LANES>
-__device__ __forceinline__ unsigned int row_part_sum(const unsigned int* row, int G, int sub) {
-  constexpr int NV = SEL_MAXB / 4 / LANES;
-  const uint4* r4 = (const uint4*)row;
-  uint4 v[NV];
+__device__ __forceinline__ unsigned int col_part_sum(const unsigned int* a, int stride, int col, int G,
+                                                     int sub) {
+  constexpr int NV = SEL_MAXB / LANES;
+  unsigned int v[NV];
 #pragma unroll
   for (int q = 0; q < NV; q++) {
-    int j = 4 * (sub + q * LANES);
-    v[q] = j < G ? r4[sub + q * LANES] : make_uint4(0, 0, 0, 0);
+    int j = sub + q * LANES;
+    v[q] = j < G ? a[(int64_t)j * stride + col] : 0u;
   }
   unsigned int s = 0;
 #pragma unroll
-  for (int q = 0; q < NV; q++) {
-    int j = 4 * (sub + q * LANES);
-    s += (j < G ? v[q].x : 0u) + (j + 1 < G ? v[q].y : 0u) + (j + 2 < G ? v[q].z : 0u) +
-         (j + 3 < G ? v[q].w : 0u);
-  }
+  for (int q = 0; q < NV; q++) s += v[q];
   return s;
 }
 
@@ -685,9 +681,9 @@ __global__ void __launch_bounds__(SEL_BS)
         }
       }
       __syncthreads();
-      unsigned int (*bh)[SEL_MAXB] = st->bhist[p & 1];
-      unsigned int (*gs)[SEL_MAXB] = st->gsum[p & 1];
-      for (int b = t; b < SEL_BINS; b += SEL_BS) bh[b][B] = h[b];
+      unsigned int (*bh)[SEL_BINS] = st->bhist[p & 1];
+      unsigned int (*gs)[SEL_NGRP] = st->gsum[p & 1];
+      for (int b = t; b < SEL_BINS; b += SEL_BS) bh[B][b] = h[b];   // one contiguous row per block
       {
         // group sums: 8 threads per group of 64 bins
         int g = t / 8, sub = t % 8;
@@ -696,7 +692,7 @@ __global__ void __launch_bounds__(SEL_BS)
         s += __shfl_xor((int)s, 1);
         s += __shfl_xor((int)s, 2);
         s += __shfl_xor((int)s, 4);
-        if (sub == 0) gs[g][B] = s;
+        if (sub == 0) gs[B][g] = s;
       }
       block_minmax(mn, mx, red);
       if (t == 0) {
@@ -716,7 +712,7 @@ __global__ void __launch_bounds__(SEL_BS)
       unsigned long long gc;
       {
         int g = t / 8, sub = t % 8;
-        unsigned int s = row_part_sum<8>(gs[g], G, sub);
+        unsigned int s = col_part_sum<8>(&gs[0][0], SEL_NGRP, g, G, sub);
         s += __shfl_xor((int)s, 1);
         s += __shfl_xor((int)s, 2);
         s += __shfl_xor((int)s, 4);
@@ -746,7 +742,7 @@ __global__ void __launch_bounds__(SEL_BS)
       unsigned long long bc;
       {
         int bi = t / 4, sub = t % 4;
-        unsigned int s = row_part_sum<4>(bh[gstar * SEL_GBINS + bi], G, sub);
+        unsigned int s = col_part_sum<4>(&bh[0][0], SEL_BINS, gstar * SEL_GBINS + bi, G, sub);
         s += __shfl_xor((int)s, 1);
         s += __shfl_xor((int)s, 2);
         bc = sub == 0 ? s : 0;
@@ -798,17 +794,19 @@ __global__ void __launch_bounds__(SEL_BS)
   __syncthreads();
   if (G == 1) {
     // every key matches: copy them in order
-    constexpr int PER = SEL_SMALL / SEL_BS;
-    uint64_t v[PER];
+    constexpr int PER = 16;
+    for (int c0 = 0; c0 < n; c0 += PER * SEL_BS) {
+      uint64_t v[PER];
 #pragma unroll
-    for (int q = 0; q < PER; q++) {
-      int i = t + q * SEL_BS;
-      v[q] = i < n ? keys[i] : 0;
-    }
+      for (int q = 0; q < PER; q++) {
+        int i = c0 + t + q * SEL_BS;
+        v[q] = i < n ? keys[i] : 0;
+      }
 #pragma unroll
-    for (int q = 0; q < PER; q++) {
-      int i = t + q * SEL_BS;
-      if (i < n) sbuf[i] = v[q];
+      for (int q = 0; q < PER; q++) {
+        int i = c0 + t + q * SEL_BS;
+        if (i < n) sbuf[i] = v[q];
+      }
     }
     __syncthreads();
     uint64_t r = lds_select(sbuf, (int)n, k, h, tmp, red, spick, err);
@@ -819,8 +817,8 @@ __global__ void __launch_bounds__(SEL_BS)
     return;
   }
   // this block's offset: the chosen bucket's counts of the blocks before it
-  unsigned int (*bh)[SEL_MAXB] = st->bhist[(p - 1) & 1];
-  unsigned long long part = t < B ? bh[bstar][t] : 0;   // B < SEL_MAXB <= SEL_BS
+  unsigned int (*bh)[SEL_BINS] = st->bhist[(p - 1) & 1];
+  unsigned long long part = t < B ? bh[t][bstar] : 0;   // B < SEL_MAXB <= SEL_BS
   unsigned long long off;
   (void)block_incl_scan<unsigned long long, SEL_BS, false>(part, tmp, &off);
   for (int64_t i0 = (int64_t)B * SEL_BS; i0 < n; i0 += stride * SEL_UNROLL) {
@@ -845,17 +843,19 @@ __global__ void __launch_bounds__(SEL_BS)
   if (B != 0) return;
   cnt = (unsigned int)cb;
   {
-    constexpr int PER = SEL_SMALL / SEL_BS;
-    uint64_t v[PER];
+    constexpr int PER = 16;
+    for (unsigned int c0 = 0; c0 < cnt; c0 += PER * SEL_BS) {
+      uint64_t v[PER];
 #pragma unroll
-    for (int q = 0; q < PER; q++) {
-      unsigned int i = t + q * SEL_BS;
-      v[q] = i < cnt ? st->buf[i] : 0;
-    }
+      for (int q = 0; q < PER; q++) {
+        unsigned int i = c0 + t + q * SEL_BS;
+        v[q] = i < cnt ? st->buf[i] : 0;
+      }
 #pragma unroll
-    for (int q = 0; q < PER; q++) {
-      unsigned int i = t + q * SEL_BS;
-      if (i < cnt) sbuf[i] = v[q];
+      for (int q = 0; q < PER; q++) {
+        unsigned int i = c0 + t + q * SEL_BS;
+        if (i < cnt) sbuf[i] = v[q];
+      }
     }
   }
   __syncthreads();
