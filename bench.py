@@ -73,8 +73,8 @@ def algo_bytes(kernel, L):
     if kernel == "rowpass":
         # every band reads each entry's key and column and the row pointers;
         # the first band writes each node's lightest key; kept edges are
-        # written as three 8-byte words
-        return L["bands"] * (12 * nnz + 8 * (n + 1)) + 8 * n + 24 * L["candidate_edges"]
+        # written as two 8-byte words (endpoints, key)
+        return L["bands"] * (12 * nnz + 8 * (n + 1)) + 8 * n + 16 * L["candidate_edges"]
     if kernel == "degree":
         return 8 * nnz + 8 * (n + 1) + 44 * n + 8 * n * selfb
     if kernel == "forest_candidates":

@@ -231,7 +231,8 @@ __global__ void __launch_bounds__(1024)
 //    that straddle a thread's 16 entries combine with atomicMin, so best[]
 //    must hold +inf on entry;
 //  - upper entries (u < v) with lo < key <= hi form the live list (lo is
-//    absent for the first band).
+//    absent for the first band); its roots are still the original endpoints,
+//    so the list's endpoint array is not written (readers take lr for it).
 constexpr int TILE_R = 2048;
 constexpr int R_PER = TILE_R / BS;
 
@@ -239,7 +240,7 @@ __global__ void __launch_bounds__(BS)
     k_rowpass(LevelIn g, const int32_t* __restrict__ lc, const uint64_t* __restrict__ Pc,
               const unsigned long long* thr_lo, const unsigned long long* thr_hi, int use_lo,
               int do_best, uint64_t* best, uint64_t* __restrict__ lr, uint64_t* __restrict__ lp,
-              uint64_t* __restrict__ lo_out, unsigned long long* cnt, TileScan ts) {
+              unsigned long long* cnt, TileScan ts) {
   using L = Lbs<TILE_R, BS>;
   static_assert(R_PER == 8, "one 8-byte flag word per thread");
   __shared__ int32_t srow[L::SIZE];
@@ -250,6 +251,7 @@ __global__ void __launch_bounds__(BS)
   __shared__ unsigned long long sbase;
   int64_t j0 = (int64_t)blockIdx.x * TILE_R;
   int64_t nnz = g.nnz;
+  uint64_t tlo = use_lo ? *thr_lo : 0, thi = *thr_hi;   // issued early, used at the end
   lbs_tile<TILE_R, BS>(g.rp, g.n, j0, srow, sh, stmp);
   int tid = threadIdx.x;
   // coalesced: key, and from the column the upper / row-head flags
@@ -331,7 +333,6 @@ __global__ void __launch_bounds__(BS)
       else atomicMin((unsigned long long*)&best[u], (unsigned long long)v);
     }
   }
-  uint64_t tlo = use_lo ? *thr_lo : 0, thi = *thr_hi;
   uint32_t keep = 0;
   int nk = 0;
 #pragma unroll
@@ -355,7 +356,6 @@ __global__ void __launch_bounds__(BS)
     uint64_t uv = (uint64_t)(uint32_t)u | ((uint64_t)(uint32_t)v << 32);
     lr[pos] = uv;
     lp[pos] = kp[i];
-    lo_out[pos] = uv;
     pos++;
   }
 }
@@ -993,7 +993,7 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, boo
   if (fused_first) {
     TimedScope ts(ctx, "forest_merge", (double)cnt);
     hipLaunchKernelGGL(k_bv_merge, dim3(grid_for(cnt, BV_CHUNK)), dim3(BS), 0, ctx->stream, W.lr[0],
-                       W.lp[0], W.lo[0], &info[I_LIVE0], cur, W.parent, W.msfP, W.msfO, W.msfC,
+                       W.lp[0], W.lr[0], &info[I_LIVE0], cur, W.parent, W.msfP, W.msfO, W.msfC,
                        &info[I_MSF], n, guard_keys, guard, ebits, viol, next_scan(ctx, W),
                        &info[I_ROUNDS]);
   }
@@ -1007,6 +1007,7 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, boo
     nxt = W.bestA;
   }
   int64_t bound = cnt;   // live edges of the current list, at most
+  bool lo0_is_lr = true;  // list 0 comes from the row pass: its endpoints are its roots
   for (int batch = 0; bound > 0; batch++) {
     // every round at least halves the components that still have live
     // edges, so this many rounds means corrupted state
@@ -1018,10 +1019,11 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, boo
       {
         TimedScope ts(ctx, "forest_candidates", (double)bound);
         hipLaunchKernelGGL(k_bv_candidates, dim3(grid_for(bound, BC_CHUNK)), dim3(BS), 0, ctx->stream,
-                           W.lr[in], W.lp[in], W.lo[in], &info[ci], W.lr[out], W.lp[out], W.lo[out],
-                           &info[co], cur, nxt, W.parent, next_scan(ctx, W), &info[I_FIN],
-                           &info[I_MSF], &info[I_MSF0]);
+                           W.lr[in], W.lp[in], (in == 0 && lo0_is_lr) ? W.lr[0] : W.lo[in], &info[ci],
+                           W.lr[out], W.lp[out], W.lo[out], &info[co], cur, nxt, W.parent,
+                           next_scan(ctx, W), &info[I_FIN], &info[I_MSF], &info[I_MSF0]);
       }
+      if (out == 0) lo0_is_lr = false;
       {
         TimedScope ts(ctx, "forest_merge", (double)bound);
         hipLaunchKernelGGL(k_bv_merge, dim3(grid_for(bound, BV_CHUNK)), dim3(BS), 0, ctx->stream,
@@ -1138,7 +1140,7 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
       TimedScope ts(ctx, "rowpass", (double)g.nnz);
       hipLaunchKernelGGL(k_rowpass, dim3(grid_for(g.nnz, TILE_R)), dim3(BS), 0, st, g, W.lc, W.Pc,
                          thr_lo, thr_hi, band > 0 ? 1 : 0, band == 0 ? 1 : 0, W.bestA, W.lr[0],
-                         W.lp[0], W.lo[0], &info[I_LIVE0], next_scan(ctx, W));
+                         W.lp[0], &info[I_LIVE0], next_scan(ctx, W));
     }
     SPC_LAUNCH_CHECK(ctx, "rowpass");
     int64_t live0 = 0;
