@@ -184,17 +184,17 @@ template <int T, int BS>
 __device__ __forceinline__ void lbs_tile(const int64_t* __restrict__ ptr, int64_t nrows, int64_t p0,
                                          int32_t* srow, int64_t* sh, int32_t* scan_tmp) {
   using L = Lbs<T, BS>;
+  static_assert(BS >= 2 * WAVE, "the tile's first and last rows are searched by two wavefronts");
   int tid = threadIdx.x;
   if (tid < WAVE) {
+    int64_t r0 = wave_upper_search(ptr, nrows, p0);
+    if (tid == 0) sh[0] = r0;
+  } else if (tid < 2 * WAVE) {
     int64_t total = ptr[nrows];
     int64_t last = p0 + T - 1;
     if (last > total - 1) last = total - 1;
-    int64_t r0 = wave_upper_search(ptr, nrows, p0);
     int64_t r1 = wave_upper_search(ptr, nrows, last);
-    if (tid == 0) {
-      sh[0] = r0;
-      sh[1] = r1;
-    }
+    if (tid == WAVE) sh[1] = r1;
   }
   __syncthreads();
   int64_t r0 = sh[0], r1 = sh[1];
