@@ -1012,7 +1012,11 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, boo
     // every round at least halves the components that still have live
     // edges, so this many rounds means corrupted state
     if (batch >= 40) return set_error(ctx, SPC_EINVAL, "internal: spanning forest did not converge");
-    for (int r = 0; r < 2; r++) {
+    // the first batch issues as many rounds as the previous level needed
+    // (each round past convergence is three empty launches, each batch a
+    // host wait); later batches two
+    int rounds = batch == 0 ? ctx->forest_batch : 2;
+    for (int r = 0; r < rounds; r++) {
       int out = in ^ 1;
       int ci = in == 0 ? I_LIVE0 : I_LIVE1;
       int co = out == 0 ? I_LIVE0 : I_LIVE1;
@@ -1272,6 +1276,12 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
     nc32 = (int32_t)hinfo[I_NINFO + 1];
     R.key_mode = gf ? 3 : rank ? 1 : (hinfo[I_GUARD] ? 2 : 0);
     R.rounds = hinfo[I_ROUNDS];
+    {
+      // rounds after the fused first one, plus the lookup that finds the
+      // list empty
+      int64_t need = R.rounds - (R.bands == 1 ? 1 : 0) + 1;
+      ctx->forest_batch = need < 1 ? 1 : need > 6 ? 6 : (int)need;
+    }
     R.forest_in = hinfo[I_FIN];
     R.forest_kept = hinfo[I_FKEPT];
     R.merge_in = hinfo[I_MIN];
