@@ -43,7 +43,8 @@ __global__ void __launch_bounds__(SEL_BS)
                  const int64_t* __restrict__ off, const int64_t* __restrict__ kseg,
                  const uint64_t* __restrict__ msfO, int32_t* parent, LevelIn g,
                  const uint64_t* __restrict__ deg, const int32_t* __restrict__ lc,
-                 const KeyND* __restrict__ exact, int ebits, unsigned long long* info) {
+                 const KeyND* __restrict__ exact, const uint64_t* __restrict__ kexact, int ebits,
+                 unsigned long long* info) {
   __shared__ unsigned int h[SEL_BINS];
   __shared__ uint64_t sbuf[SEG_SMALL];
   __shared__ unsigned long long tmp[SEL_BS / WAVE];
@@ -181,7 +182,8 @@ __global__ void __launch_bounds__(SEL_BS)
         atomic_max_double(&info[I_EPS], (double)N / (double)D);
       }
     }
-    if (guarded && key != cut && (key >> ebits) == (cut >> ebits)) {
+    if (guarded && key != cut && (key >> ebits) == (cut >> ebits) &&
+        !(key_exact(kexact, key & emask) && key_exact(kexact, cut & emask))) {
       KeyND p = exact[key & emask], q = exact[cut & emask];
       if ((unsigned __int128)p.N * q.D != (unsigned __int128)q.N * p.D) atomicOr(&info[I_VIOL], 1ull);
     }
@@ -203,7 +205,7 @@ int seg_cutoff_union(spc_ctx* ctx, const LevelIn& g, LevelWork& W, const LevelRe
   // only when the level's keys are guarded (info[I_GUARD])
   const KeyND* exact = rank ? nullptr : W.keysA;
   hipLaunchKernelGGL(k_seg_select, dim3((unsigned)seg.G), dim3(SEL_BS), 0, st, fkey, fidx, seg.off, seg.k,
-                     W.msfO, W.parent, g, W.deg, W.lc, exact, ebits, W.info);
+                     W.msfO, W.parent, g, W.deg, W.lc, exact, W.kexact, ebits, W.info);
   SPC_LAUNCH_CHECK(ctx, "batched cutoff");
   return SPC_OK;
 }

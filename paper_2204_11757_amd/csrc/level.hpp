@@ -88,6 +88,12 @@ struct KeyND {
   uint64_t N, D, e;
 };
 
+// bit e of the exactness map (set by the score pass for edges whose packed
+// key was computed without remainder)
+__device__ __forceinline__ bool key_exact(const uint64_t* __restrict__ kexact, uint64_t e) {
+  return (kexact[e >> 6] >> (e & 63)) & 1ull;
+}
+
 __device__ __forceinline__ bool exact_less(const KeyND& x, const KeyND& y) {
   return (unsigned __int128)x.N * y.D < (unsigned __int128)y.N * x.D;
 }
@@ -161,6 +167,7 @@ struct LevelWork {
   uint64_t* P;               // [m]  order key per edge (sorted-rank order)
   uint64_t* Pc;              // [nnz] order key per CSR entry (both directions)
   uint64_t* samples;         // [m/64 + 2]
+  uint64_t* kexact;          // [m/64 + 2] bit e: edge e's packed key has no remainder
   uint64_t* bestA;           // [n]
   uint64_t* bestB;           // [n]
   int32_t* parent;           // [n]

@@ -7,11 +7,11 @@ namespace spc {
 
 
 // ---------------------------------------------------------------------------
-// A2 + A3 fused with the first spanning-forest round: one thread per edge
-// (u < v) for 4 edges each; tiles of 1024 consecutive edge ids are mapped
-// to rows by a load-balanced search over the upper-entry prefix uptr.
+// A2 + A3: 3 edges (u < v) per thread; tiles of TILE_S consecutive edge ids
+// are mapped to rows by a load-balanced search over the upper-entry prefix
+// uptr.
 // ---------------------------------------------------------------------------
-constexpr int TILE_S = 1024;
+constexpr int TILE_S = 768;   // 3 edges per thread: the register budget of 5 waves per SIMD
 
 // five waves per SIMD: the register budget that keeps the long-row paths
 // free of spills
@@ -20,7 +20,8 @@ __global__ void __launch_bounds__(BS, 5)
     k_score(LevelIn g, const uint64_t* __restrict__ deg, const int32_t* __restrict__ lc,
             const int64_t* __restrict__ uptr, int64_t m, int c, int ebits,
             uint64_t* __restrict__ Pc, uint64_t* __restrict__ samples, KeyND* __restrict__ keys,
-            int write_keys, unsigned long long* info, const int32_t* __restrict__ htab) {
+            int write_keys, unsigned long long* info, const int32_t* __restrict__ htab,
+            uint64_t* __restrict__ kexact) {
   // write_keys < 0: exact records only when the packed key is not exact
   // for sure, i.e. when dmax^4 > 2^c
   if (MODE == 0 && write_keys < 0) {
@@ -65,23 +66,31 @@ __global__ void __launch_bounds__(BS, 5)
   }
   for (int i = 0; i < EPT; i++) {
     int64_t e = e0 + tid + i * BS;
-    if (e >= m) break;
-    uint64_t N, D;
-    int64_t jm;
+    bool ex = false;
     bool mapped = false;
 #pragma unroll
     for (int s = 0; s < H_MAX; s++) mapped |= hrow[s] == eu[i] || hrow[s] == ev[i];
-    if (mapped) continue;   // scored by k_score_mapped
-    edge_score(g, deg, lc, eu[i], ev[i], ew[i], N, D, jm);
-    dmx = D > dmx ? D : dmx;
-    if (MODE == 0) {
-      uint64_t K = fixed_key(N, D, c);
-      uint64_t key = (K << ebits) | (uint64_t)e;
-      Pc[ej[i]] = key;   // entry (u -> v)
-      Pc[jm] = key;      // entry (v -> u)
-      if ((e & 63) == 0) samples[e >> 6] = key;
+    // edges of a mapped row are scored by k_score_mapped (their bit stays clear)
+    if (e < m && !mapped) {
+      uint64_t N, D;
+      int64_t jm;
+      edge_score(g, deg, lc, eu[i], ev[i], ew[i], N, D, jm);
+      dmx = D > dmx ? D : dmx;
+      if (MODE == 0) {
+        uint64_t K = fixed_key(N, D, c, ex);
+        uint64_t key = (K << ebits) | (uint64_t)e;
+        Pc[ej[i]] = key;   // entry (u -> v)
+        Pc[jm] = key;      // entry (v -> u)
+        if ((e & 63) == 0) samples[e >> 6] = key;
+      }
+      if (MODE == 1 || write_keys) keys[e] = KeyND{N, D, (uint64_t)e};
     }
-    if (MODE == 1 || write_keys) keys[e] = KeyND{N, D, (uint64_t)e};
+    if (MODE == 0) {
+      // the exactness map: a wavefront's 64 consecutive edges make one word
+      uint64_t bits = __ballot(ex);
+      int64_t ew0 = e0 + (tid & ~(WAVE - 1)) + i * BS;
+      if (lane_id() == 0 && ew0 < m) kexact[ew0 >> 6] = bits;
+    }
   }
   dmx = wave_max(dmx);
   if (lane_id() == 0) sred[tid / WAVE] = dmx;
@@ -260,7 +269,7 @@ void launch_score(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t m,
     {
       TimedScope ts(ctx, "score", (double)m);
       hipLaunchKernelGGL(k_score<0>, dim3(tiles), dim3(BS), 0, ctx->stream, g, W.deg, W.lc, W.uptr, m, c,
-                         ebits, W.Pc, W.samples, W.keysA, -1, W.info, W.htab);
+                         ebits, W.Pc, W.samples, W.keysA, -1, W.info, W.htab, W.kexact);
     }
     if (maps) {
       TimedScope ts(ctx, "score_long_rows", (double)H_MAX);
@@ -271,7 +280,8 @@ void launch_score(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t m,
     {
       TimedScope ts(ctx, "score_rank", (double)m);
       hipLaunchKernelGGL(k_score<1>, dim3(tiles), dim3(BS), 0, ctx->stream, g, W.deg, W.lc, W.uptr, m, c,
-                         ebits, (uint64_t*)nullptr, (uint64_t*)nullptr, W.keysA, 1, W.info, W.htab);
+                         ebits, (uint64_t*)nullptr, (uint64_t*)nullptr, W.keysA, 1, W.info, W.htab,
+                         (uint64_t*)nullptr);
     }
     if (maps) {
       TimedScope ts(ctx, "score_long_rows", (double)H_MAX);

@@ -252,20 +252,33 @@ __device__ __forceinline__ void edge_score(const LevelIn& g, const uint64_t* __r
   N = 2 * D - 2 * M;
 }
 
-// floor(N * 2^b / D) for N < 2^63, D < 2^62, b <= 61 (the result is below 2^62).
-__device__ __forceinline__ uint64_t fixed_key(uint64_t N, uint64_t D, int b) {
+// floor(N * 2^b / D) for N < 2^63, D < 2^62, b <= 61 (the result is below 2^62);
+// exact says whether the division left no remainder (then two edges with the
+// same K have exactly the same score).
+__device__ __forceinline__ uint64_t fixed_key(uint64_t N, uint64_t D, int b, bool& exact) {
   if ((N >> (63 - b)) == 0) {
     uint64_t num = N << b;
+    uint64_t q;
     if (num < (1ull << 53) && D < (1ull << 53)) {
       // the correctly rounded quotient is at most one above the floor
-      uint64_t q = (uint64_t)((double)num / (double)D);
+      q = (uint64_t)((double)num / (double)D);
       if (q * D > num) q--;
-      return q;
+    } else {
+      q = num / D;
     }
-    return num / D;
+    exact = q * D == num;
+    return q;
   }
   unsigned __int128 num = (unsigned __int128)N << b;
-  return (uint64_t)(num / D);
+  uint64_t q = (uint64_t)(num / D);
+  exact = (unsigned __int128)q * D == num;
+  return q;
 }
+
+__device__ __forceinline__ uint64_t fixed_key(uint64_t N, uint64_t D, int b) {
+  bool exact;
+  return fixed_key(N, D, b, exact);
+}
+
 
 }  // namespace spc

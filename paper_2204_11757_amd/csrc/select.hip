@@ -39,6 +39,7 @@ void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W, bool fp) {
   W.P = A.take<uint64_t>(m);
   W.Pc = A.take<uint64_t>(nnz);
   W.samples = A.take<uint64_t>(m / 64 + 2);
+  W.kexact = A.take<uint64_t>(m / 64 + 2);
   W.bestA = A.take<uint64_t>(n);
   W.bestB = A.take<uint64_t>(n);
   W.parent = A.take<int32_t>(n);
@@ -372,11 +373,15 @@ constexpr int BC_PER = BC_CHUNK / BS;
 
 // Guarded keys: the winner w of a component must not have a same-bucket
 // rival x with an exactly smaller score.
-__device__ __forceinline__ void guard_check(const KeyND* __restrict__ keys, int ebits, uint64_t key,
-                                            uint64_t w, int* viol) {
+// Two keys of one bucket whose K were both computed without remainder have
+// equal scores, so their packed order (by edge id) is the exact one.
+__device__ __forceinline__ void guard_check(const KeyND* __restrict__ keys, const uint64_t* __restrict__ kexact,
+                                            int ebits, uint64_t key, uint64_t w, int* viol) {
   if (w == key || w == KEY_INF || (w >> ebits) != (key >> ebits)) return;
   uint64_t emask = (1ull << ebits) - 1;
-  if (exact_less(keys[key & emask], keys[w & emask])) *viol = 1;
+  uint64_t ek = key & emask, ew = w & emask;
+  if (key_exact(kexact, ek) && key_exact(kexact, ew)) return;
+  if (exact_less(keys[ek], keys[ew])) *viol = 1;
 }
 
 // Every component adopts its lightest live edge; those edges are joined and
@@ -387,8 +392,9 @@ __global__ void __launch_bounds__(BS)
                const uint64_t* __restrict__ best, int32_t* parent, uint64_t* __restrict__ msfP,
                uint64_t* __restrict__ msfO, int32_t* __restrict__ msfC, unsigned long long* msfcnt,
                int64_t msf_cap,
-               const KeyND* __restrict__ keys, const unsigned long long* guard, int ebits, int* viol,
-               TileScan ts, unsigned long long* rounds) {
+               const KeyND* __restrict__ keys, const uint64_t* __restrict__ kexact,
+               const unsigned long long* guard, int ebits, int* viol, TileScan ts,
+               unsigned long long* rounds) {
   __shared__ int stmp[BS / WAVE];
   __shared__ unsigned long long sbase;
   int64_t n = (int64_t)*cnt;
@@ -411,8 +417,8 @@ __global__ void __launch_bounds__(BS)
     int32_t a = (int32_t)(uint32_t)uv, b = (int32_t)(uv >> 32);
     uint64_t wa = best[a], wb = best[b];
     if (keys) {
-      guard_check(keys, ebits, key, wa, viol);
-      guard_check(keys, ebits, key, wb, viol);
+      guard_check(keys, kexact, ebits, key, wa, viol);
+      guard_check(keys, kexact, ebits, key, wb, viol);
     }
     bool ca = wa == key, cb = wb == key;
     if (ca || cb) {
@@ -530,7 +536,8 @@ __global__ void __launch_bounds__(BS)
 // the bucket is the exact one).
 __global__ void k_cutoff_check(const uint64_t* __restrict__ msfP, const unsigned long long* cnt,
                                const SelState* st, const KeyND* __restrict__ keys,
-                               const unsigned long long* guard, int ebits, int* viol) {
+                               const uint64_t* __restrict__ kexact, const unsigned long long* guard,
+                               int ebits, int* viol) {
   if (!*guard) return;
   int64_t n = (int64_t)*cnt;
   uint64_t T = st->prefix;
@@ -539,6 +546,7 @@ __global__ void k_cutoff_check(const uint64_t* __restrict__ msfP, const unsigned
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     uint64_t p = msfP[i];
     if (p == T || (p >> ebits) != (T >> ebits)) continue;
+    if (key_exact(kexact, p & emask) && key_exact(kexact, T & emask)) continue;   // equal scores
     KeyND x = keys[p & emask], y = keys[T & emask];
     if ((unsigned __int128)x.N * y.D != (unsigned __int128)y.N * x.D) *viol = 1;
   }
@@ -994,7 +1002,7 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, boo
     TimedScope ts(ctx, "forest_merge", (double)cnt);
     hipLaunchKernelGGL(k_bv_merge, dim3(grid_for(cnt, BV_CHUNK)), dim3(BS), 0, ctx->stream, W.lr[0],
                        W.lp[0], W.lr[0], &info[I_LIVE0], cur, W.parent, W.msfP, W.msfO, W.msfC,
-                       &info[I_MSF], n, guard_keys, guard, ebits, viol, next_scan(ctx, W),
+                       &info[I_MSF], n, guard_keys, W.kexact, guard, ebits, viol, next_scan(ctx, W),
                        &info[I_ROUNDS]);
   }
   if (fused_first) {
@@ -1032,7 +1040,7 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, boo
         TimedScope ts(ctx, "forest_merge", (double)bound);
         hipLaunchKernelGGL(k_bv_merge, dim3(grid_for(bound, BV_CHUNK)), dim3(BS), 0, ctx->stream,
                            W.lr[out], W.lp[out], W.lo[out], &info[co], cur, W.parent, W.msfP, W.msfO,
-                           W.msfC, &info[I_MSF], n, guard_keys, guard, ebits, viol, next_scan(ctx, W),
+                           W.msfC, &info[I_MSF], n, guard_keys, W.kexact, guard, ebits, viol, next_scan(ctx, W),
                            &info[I_ROUNDS]);
       }
       {
@@ -1176,7 +1184,7 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
   }
   if (!rank) {
     hipLaunchKernelGGL(k_cutoff_check, dim3(grid_for(R.msf, 256, ctx->num_cus * 4)), dim3(256), 0, st,
-                       W.msfP, &info[I_MSF], W.sel2, W.keysA, guard, ebits, (int*)&info[I_VIOL]);
+                       W.msfP, &info[I_MSF], W.sel2, W.keysA, W.kexact, guard, ebits, (int*)&info[I_VIOL]);
     SPC_LAUNCH_CHECK(ctx, "cutoff check");
   }
   return SPC_OK;
