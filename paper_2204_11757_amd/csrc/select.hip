@@ -936,11 +936,20 @@ __global__ void k_fill_u64(uint64_t* __restrict__ a, int64_t n, uint64_t v) {
 // upper threshold of a band: the selected sample key, or "everything".
 // Guarded keys order edges of one K bucket only approximately, so there the
 // band is widened to the end of the sample's K bucket.
+// Samples are the keys of edges 0, 64, 128, ...; when the q-th smallest is
+// edge 64q itself, the band is (most likely) one tied K bucket read in edge
+// order, i.e. a run of consecutive rows, whose forest has about one edge per
+// row rather than per candidate.  Such a band is extended to edge e_tie
+// (chosen by the caller to cover k rows); only the band's size changes.
 __global__ void k_thr_from_sel(const SelState* st, unsigned long long* thr, int all, int ebits,
-                               const unsigned long long* widen) {
+                               const unsigned long long* widen, unsigned long long q,
+                               unsigned long long e_tie) {
+  uint64_t emask = (1ull << ebits) - 1;
+  uint64_t p = st->prefix;
   if (all) *thr = KEY_INF;
-  else if (*widen) *thr = st->prefix | ((1ull << ebits) - 1);
-  else *thr = st->prefix;
+  else if (*widen) *thr = p | emask;
+  else if ((p & emask) == 64 * q && e_tie > (p & emask)) *thr = (p & ~emask) | (e_tie & emask);
+  else *thr = p;
 }
 
 // Info block (and up to three scalars) to the pinned host copy, then wait.
@@ -1131,19 +1140,28 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
       hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(1), 0, st, thr_lo, thr_hi);
     }
     if (all) {
-      hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits, guard);
+      hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits, guard, 0ull,
+                         0ull);
     } else if (!rank) {
       int64_t ns = (m + 63) / 64;
       int64_t q = (int64_t)((double)target / 64.0 * 1.05) + 16;
       if (q >= ns) {
         all = true;
-        hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits, guard);
+        hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits, guard, 0ull,
+                         0ull);
       } else {
         TimedScope ts(ctx, "select_threshold", (double)ns);
         int rc = radix_select(ctx, W.samples, nullptr, ns, nullptr, (unsigned long long)q, 64, W.sel,
                               (unsigned long long*)W.selflag, &info[I_LBERR]);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 0, ebits, guard);
+        // a tied band of consecutive rows needs about k rows: k m / n edges
+        uint64_t e_tie = 0;
+        if (band == 0) {
+          double rows = 1.1 * (double)k * (double)m / (double)n + 4096.0;
+          e_tie = rows >= (double)(m - 1) ? (uint64_t)(m - 1) : (uint64_t)rows;
+        }
+        hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 0, ebits, guard,
+                           (unsigned long long)q, (unsigned long long)e_tie);
       }
     } else {
       hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, thr_hi, (unsigned long long)(target - 1));
