@@ -121,6 +121,11 @@ int spc_set_allocator(spc_ctx* ctx, void* (*alloc)(size_t, void*), void (*free_)
  *                 the exact packed fixed-point key fits in 64 bits.
  *   "full_forest" 1: build the spanning forest over every edge instead of
  *                 only the lightest candidates.
+ *   "huge_sort"   1: contract coarse rows above the block capacity by a
+ *                 sort even when dense accumulators would fit.
+ *   "redo_rank"   1: treat every packed-key level as if one of its guarded
+ *                 decisions had failed, so that it is redone with rank keys
+ *                 (the fallback path).
  *   "timing"      1: record a HIP event pair on the context stream around
  *                 every kernel launch, for spc_timing_report.
  * Unknown names return SPC_EINVAL. */

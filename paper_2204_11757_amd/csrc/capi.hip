@@ -202,7 +202,11 @@ static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* clus
   LevelResult R;
   rc = plan_and_bind(ctx, g->n, g->nnz, W, fp);
   if (rc) return rc;
-  rc = select_level(ctx, L, t, cluster_of, W, R, fp ? &LF : nullptr, seg);
+  // the integer path checks the selection at the contraction's first
+  // synchronisation (one wait per level fewer); a batch waits, since a graph
+  // short of forest edges leaves more super-nodes than the target
+  bool defer = !fp && !seg && t < g->n;
+  rc = select_level(ctx, L, t, cluster_of, W, R, fp ? &LF : nullptr, seg, defer);
   if (rc) return rc;
   if (fp && R.n_c == g->n) {
     if (out->nnz_cap < g->nnz) return set_error(ctx, SPC_ECAPACITY, "nnz_cap too small");
@@ -238,6 +242,13 @@ static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* clus
     R.maxcl = 1;
   } else {
     rc = contract_level(ctx, L, cluster_of, R.n_c, out, W, R, seg);
+    if (rc == SPC_REDO_RANK) {
+      // a guarded key decision failed: the level again with rank keys
+      R = LevelResult();
+      rc = select_level(ctx, L, t, cluster_of, W, R, nullptr, seg, false, true);
+      if (rc) return rc;
+      rc = contract_level(ctx, L, cluster_of, R.n_c, out, W, R, seg);
+    }
     if (rc) return rc;
   }
   *nnz_c = R.nnz_c;
@@ -406,6 +417,7 @@ int spc_set_option(spc_ctx* ctx, const char* name, int64_t value) {
   else if (!strcmp(name, "full_forest")) ctx->force_full_filter = value ? 1 : 0;
   else if (!strcmp(name, "timing")) ctx->timing = value ? 1 : 0;
   else if (!strcmp(name, "huge_sort")) ctx->force_huge_sort = value ? 1 : 0;
+  else if (!strcmp(name, "redo_rank")) ctx->force_redo_rank = value ? 1 : 0;
   else return set_error(ctx, SPC_EINVAL, "unknown option '%s'", name);
   return SPC_OK;
 }

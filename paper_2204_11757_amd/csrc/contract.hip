@@ -875,10 +875,16 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
                        W.r32list, W.midlist, W.blocklist, W.hugelist, info, next_scan(ctx, W));
   }
   SPC_LAUNCH_CHECK(ctx, "contract_small");
+  // with a deferred selection, this read also carries its super-node count
   hipLaunchKernelGGL(k_readback, dim3(1), dim3(64), 0, st, info, (int)I_NINFO, (const int64_t*)nullptr,
-                     (const int32_t*)nullptr, (const uint64_t*)nullptr, hinfo);
+                     R.pending ? (const int32_t*)(W.flag + n) : (const int32_t*)nullptr,
+                     (const uint64_t*)nullptr, hinfo);
   SPC_LAUNCH_CHECK(ctx, "readback");
   SPC_HIP(ctx, hipStreamSynchronize(st));
+  if (R.pending) {
+    rc = finish_select(ctx, R, n_c, R.pending_rank, false, seg);
+    if (rc) return rc;
+  }
   int64_t nr32 = hinfo[I_R32], nmid = hinfo[I_MID], nblk = hinfo[I_BLOCK], H = hinfo[I_HUGE];
   R.maxcl = hinfo[I_MAXCL];
   if (nr32 > 0) {

@@ -243,7 +243,14 @@ struct LevelResult {
   int key_mode = 0, key_bits = 0, bands = 0, keys_written = 0;
   int64_t forest_in = 0, forest_kept = 0, merge_in = 0;
   double eps = 0.0;
+  // the selection's checks wait for the contraction's first synchronisation
+  // (n_c is the target until then); rank: the labels came from rank keys
+  bool pending = false, pending_rank = false;
 };
+
+// internal return code (never reaches the caller): a guarded key decision
+// failed after a deferred check, the level is redone with rank keys
+constexpr int SPC_REDO_RANK = 1;
 
 // A2 and A3 launches (score.hip).  mode 0: packed keys into Pc and the
 // samples (exact records too when the key is not surely exact); mode 1:
@@ -282,8 +289,16 @@ int seg_cutoff_union(spc_ctx* ctx, const LevelIn& g, LevelWork& W, const LevelRe
 // Steps A1-A4: degrees, scores, order, merge selection -> cluster_of.  With
 // gf the weights are floating point (g then carries the structure only);
 // with seg the input is a batch and every graph has its own target.
+// With defer, the host does not wait for the labels: R.pending is set and
+// finish_select runs at the contraction's first synchronisation; with
+// rank_only the level starts in rank-key mode.
 int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of, LevelWork& W,
-                 LevelResult& R, const LevelInF* gf = nullptr, const Segments* seg = nullptr);
+                 LevelResult& R, const LevelInF* gf = nullptr, const Segments* seg = nullptr,
+                 bool defer = false, bool rank_only = false);
+// Checks and results of the selection from the host copy of the info block
+// (super-node count in slot I_NINFO + 1): SPC_OK, an error, or
+// SPC_REDO_RANK when packed keys took an inexact decision.
+int finish_select(spc_ctx* ctx, LevelResult& R, int64_t t, bool rank, bool fp, const Segments* seg);
 
 // Step A5: contraction of Definition 1 into caller buffers.
 int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* cluster_of, int64_t n_c,

@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(BS)
     k_rowpass(LevelIn g, const int32_t* __restrict__ lc, const uint64_t* __restrict__ Pc,
               const unsigned long long* thr_lo, const unsigned long long* thr_hi, int use_lo,
               int do_best, uint64_t* best, uint64_t* __restrict__ lr, uint64_t* __restrict__ lp,
-              unsigned long long* cnt, TileScan ts) {
+              unsigned long long* cnt, unsigned long long* cnt_copy, TileScan ts) {
   using L = Lbs<TILE_R, BS>;
   static_assert(R_PER == 8, "one 8-byte flag word per thread");
   __shared__ int32_t srow[L::SIZE];
@@ -348,6 +348,7 @@ __global__ void __launch_bounds__(BS)
   }
   int64_t pos = block_reserve_lb<BS>(ts, blockIdx.x, blockIdx.x == gridDim.x - 1, nk, nullptr, cnt,
                                     &sbase, stmp);
+  if (tid == 0 && blockIdx.x == gridDim.x - 1) *cnt_copy = *cnt;   // this thread set *cnt
 #pragma unroll
   for (int i = 0; i < R_PER; i++) {
     if (!(keep >> i & 1u)) continue;
@@ -583,10 +584,16 @@ __global__ void k_cc_flatten(int32_t* parent, int32_t* __restrict__ root, int32_
   }
 }
 
+// Labels are clamped to [0, t): they are there by construction, and the
+// clamp keeps a later contraction in bounds should a check (done once the
+// host next reads the info block) fail.
 __global__ void k_relabel(const int32_t* __restrict__ root, const int32_t* __restrict__ cid,
-                          int32_t* __restrict__ cluster_of, int64_t n) {
+                          int32_t* __restrict__ cluster_of, int64_t n, int64_t t) {
   int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x < n) cluster_of[x] = cid[root[x]];
+  if (x < n) {
+    int64_t c = cid[root[x]];
+    cluster_of[x] = (int32_t)(c < 0 ? 0 : c >= t ? t - 1 : c);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -941,13 +948,21 @@ __global__ void k_fill_u64(uint64_t* __restrict__ a, int64_t n, uint64_t v) {
 // order, i.e. a run of consecutive rows, whose forest has about one edge per
 // row rather than per candidate.  Such a band is extended to edge e_tie
 // (chosen by the caller to cover k rows); only the band's size changes.
+// With c > 0 it first decides the level's key mode into info[I_GUARD]
+// (the packed key is inexact for some pair of edges only when
+// Dmax^2 > 2^c, Dmax = largest d_u d_v).
 __global__ void k_thr_from_sel(const SelState* st, unsigned long long* thr, int all, int ebits,
-                               const unsigned long long* widen, unsigned long long q,
+                               unsigned long long* info, int c, unsigned long long q,
                                unsigned long long e_tie) {
   uint64_t emask = (1ull << ebits) - 1;
   uint64_t p = st->prefix;
+  if (c > 0) {
+    unsigned __int128 D2 = (unsigned __int128)info[I_DMAXE] * info[I_DMAXE];
+    info[I_GUARD] = ((D2 >> 64) != 0 || D2 > ((unsigned __int128)1 << c)) ? 1ull : 0ull;
+  }
+  bool widen = info[I_GUARD] != 0;
   if (all) *thr = KEY_INF;
-  else if (*widen) *thr = p | emask;
+  else if (widen) *thr = p | emask;
   else if ((p & emask) == 64 * q && e_tie > (p & emask)) *thr = (p & ~emask) | (e_tie & emask);
   else *thr = p;
 }
@@ -960,13 +975,6 @@ static int sync_info(spc_ctx* ctx, const LevelWork& W, const int64_t* x0 = nullp
   SPC_LAUNCH_CHECK(ctx, "readback");
   SPC_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return SPC_OK;
-}
-
-// Whether guarded decisions need checking: the packed key is inexact for
-// some pair of edges only when Dmax^2 > 2^c (Dmax = largest d_u d_v).
-__global__ void k_key_mode(unsigned long long* info, int c) {
-  unsigned __int128 D2 = (unsigned __int128)info[I_DMAXE] * info[I_DMAXE];
-  info[I_GUARD] = ((D2 >> 64) != 0 || D2 > ((unsigned __int128)1 << c)) ? 1ull : 0ull;
 }
 
 // checks of the level's input that the device reports (integer weight
@@ -1002,7 +1010,6 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, boo
   int* viol = (int*)&info[I_VIOL];
   const unsigned long long* guard = &info[I_GUARD];
   int rc;
-  hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(1), 0, ctx->stream, &info[I_CAND], &info[I_LIVE0]);
   int64_t cnt = m;
   uint64_t* cur = W.bestA;
   uint64_t* nxt = W.bestB;
@@ -1095,8 +1102,7 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
     launch_score(ctx, g, W, m, c, ebits, 0);   // timed inside, one scope per kernel
   }
   if (!rank) {
-    hipLaunchKernelGGL(k_key_mode, dim3(1), dim3(1), 0, st, info, c);
-    SPC_LAUNCH_CHECK(ctx, "score");
+    SPC_LAUNCH_CHECK(ctx, "score");   // the first band's threshold kernel sets the key mode
     R.key_bits = 64;
   } else if (gf) {
     hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, &info[I_GUARD], 0ull);
@@ -1133,6 +1139,7 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
     // a batch builds the whole forest in one band (each graph needs its own
     // count of forest edges)
     bool all = ctx->force_full_filter || target >= m || band >= 2 || seg != nullptr;
+    int kc = (!rank && band == 0) ? c : 0;   // the first threshold kernel also sets the key mode
     if (band > 0) {
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestA, n, KEY_INF);
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestB, n, KEY_INF);
@@ -1140,14 +1147,14 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
       hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(1), 0, st, thr_lo, thr_hi);
     }
     if (all) {
-      hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits, guard, 0ull,
+      hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits, info, kc, 0ull,
                          0ull);
     } else if (!rank) {
       int64_t ns = (m + 63) / 64;
       int64_t q = (int64_t)((double)target / 64.0 * 1.05) + 16;
       if (q >= ns) {
         all = true;
-        hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits, guard, 0ull,
+        hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits, info, kc, 0ull,
                          0ull);
       } else {
         TimedScope ts(ctx, "select_threshold", (double)ns);
@@ -1160,7 +1167,7 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
           double rows = 1.1 * (double)k * (double)m / (double)n + 4096.0;
           e_tie = rows >= (double)(m - 1) ? (uint64_t)(m - 1) : (uint64_t)rows;
         }
-        hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 0, ebits, guard,
+        hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 0, ebits, info, kc,
                            (unsigned long long)q, (unsigned long long)e_tie);
       }
     } else {
@@ -1170,7 +1177,7 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
       TimedScope ts(ctx, "rowpass", (double)g.nnz);
       hipLaunchKernelGGL(k_rowpass, dim3(grid_for(g.nnz, TILE_R)), dim3(BS), 0, st, g, W.lc, W.Pc,
                          thr_lo, thr_hi, band > 0 ? 1 : 0, band == 0 ? 1 : 0, W.bestA, W.lr[0],
-                         W.lp[0], &info[I_LIVE0], next_scan(ctx, W));
+                         W.lp[0], &info[I_LIVE0], &info[I_CAND], next_scan(ctx, W));
     }
     SPC_LAUNCH_CHECK(ctx, "rowpass");
     int64_t live0 = 0;
@@ -1209,7 +1216,7 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
 }
 
 int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of, LevelWork& W,
-                 LevelResult& R, const LevelInF* gf, const Segments* seg) {
+                 LevelResult& R, const LevelInF* gf, const Segments* seg, bool defer, bool rank_only) {
   if (seg && gf)
     return set_error(ctx, SPC_EINVAL, "batched coarsening takes integer weights");
   hipStream_t st = ctx->stream;
@@ -1258,8 +1265,7 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
 
   // A2-A4 and the labels; a guarded key that fails its exactness check
   // falls back to ranks
-  bool rank = ctx->force_rank_mode != 0 || gf != nullptr;
-  int32_t nc32 = 0;
+  bool rank = ctx->force_rank_mode != 0 || gf != nullptr || rank_only;
   for (int pass = 0; pass < 2; pass++) {
     if (pass == 1) {
       rank = true;
@@ -1292,28 +1298,48 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
       rc = exclusive_scan<int32_t>(ctx, W.flag, W.flag, n, (int32_t*)W.scan_partial);
       if (rc) return rc;
       hipLaunchKernelGGL(k_relabel, dim3(grid_for(n, 256)), dim3(256), 0, st, W.root, W.flag,
-                         cluster_of, n);
+                         cluster_of, n, t);
     }
     if (gf) launch_eps_fp(ctx, W);
     else if (!seg) launch_eps(ctx, g, W, R.msf);
+    if (ctx->force_redo_rank && !rank)
+      hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, &info[I_VIOL], 1ull);
     SPC_LAUNCH_CHECK(ctx, "relabel");
+    if (defer) {
+      // labels are in [0, t) whatever the key mode: the cutoff joins exactly
+      // k forest edges (keys are distinct), and k_relabel clamps besides
+      R.pending = true;
+      R.pending_rank = rank;
+      R.n_c = t;
+      return SPC_OK;
+    }
     rc = sync_info(ctx, W, nullptr, W.flag + n);
     if (rc) return rc;
-    nc32 = (int32_t)hinfo[I_NINFO + 1];
-    R.key_mode = gf ? 3 : rank ? 1 : (hinfo[I_GUARD] ? 2 : 0);
-    R.rounds = hinfo[I_ROUNDS];
-    {
-      // rounds after the fused first one, plus the lookup that finds the
-      // list empty
-      int64_t need = R.rounds - (R.bands == 1 ? 1 : 0) + 1;
-      ctx->forest_batch = need < 1 ? 1 : need > 6 ? 6 : (int)need;
-    }
-    R.forest_in = hinfo[I_FIN];
-    R.forest_kept = hinfo[I_FKEPT];
-    R.merge_in = hinfo[I_MIN];
-    R.keys_written = (rank || hinfo[I_KEYS]) ? 1 : 0;
-    if (hinfo[I_VIOL] == 0) break;
+    rc = finish_select(ctx, R, t, rank, gf != nullptr, seg);
+    if (rc != SPC_REDO_RANK) return rc;
+  }
+  return set_error(ctx, SPC_EINVAL, "internal: rank keys redone twice");
+}
+
+int finish_select(spc_ctx* ctx, LevelResult& R, int64_t t, bool rank, bool fp, const Segments* seg) {
+  int64_t* hinfo = ctx->h_pinned;
+  R.pending = false;
+  int64_t nc = (int32_t)hinfo[I_NINFO + 1];
+  R.key_mode = fp ? 3 : rank ? 1 : (hinfo[I_GUARD] ? 2 : 0);
+  R.rounds = hinfo[I_ROUNDS];
+  {
+    // rounds after the fused first one, plus the lookup that finds the
+    // list empty
+    int64_t need = R.rounds - (R.bands == 1 ? 1 : 0) + 1;
+    ctx->forest_batch = need < 1 ? 1 : need > 6 ? 6 : (int)need;
+  }
+  R.forest_in = hinfo[I_FIN];
+  R.forest_kept = hinfo[I_FKEPT];
+  R.merge_in = hinfo[I_MIN];
+  R.keys_written = (rank || hinfo[I_KEYS]) ? 1 : 0;
+  if (hinfo[I_VIOL]) {
     if (rank) return set_error(ctx, SPC_EINVAL, "internal: exact rank order flagged as inexact");
+    return SPC_REDO_RANK;
   }
   if (hinfo[I_LBERR]) return set_error(ctx, SPC_EINVAL, "internal: look-back wait gave up");
   if (seg && hinfo[I_SEG_SHORT])
@@ -1321,7 +1347,7 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
   double eps;
   memcpy(&eps, &hinfo[I_EPS], sizeof(double));
   R.eps = eps;
-  R.n_c = nc32;
+  R.n_c = nc;
   if (R.n_c != t)
     return set_error(ctx, SPC_EINVAL, "internal: %lld super-nodes produced, %lld expected",
                      (long long)R.n_c, (long long)t);

@@ -20,6 +20,7 @@ def P():
     torch.cuda.init()
     yield spc
     spc.set_option("rank_order", 0)
+    spc.set_option("redo_rank", 0)
 
 
 def say(*a):
@@ -94,6 +95,18 @@ def test_batch_rank_order_path(P):
         check_batch(P, graphs, n_c, 0, "rank-order batch")
     finally:
         P.set_option("rank_order", 0)
+
+
+def test_batch_inexact_key_fallback(P):
+    # a batch level flagged inexact is redone with rank keys before its
+    # contraction
+    graphs = batch_trimeshes(8, seed=13, lo=10, hi=30)
+    n_c = [max(1, g.n // 8) for g in graphs]
+    try:
+        P.set_option("redo_rank", 1)
+        check_batch(P, graphs, n_c, 0, "batch redo with rank keys")
+    finally:
+        P.set_option("redo_rank", 0)
 
 
 def test_batch_matches_separate_gpu_calls(P):

@@ -21,6 +21,7 @@ def P():
     spc.set_option("rank_order", 0)
     spc.set_option("full_forest", 0)
     spc.set_option("huge_sort", 0)
+    spc.set_option("redo_rank", 0)
 
 
 def say(*a):
@@ -125,6 +126,23 @@ def test_alternate_order_and_forest_paths_agree(P):
     finally:
         P.set_option("rank_order", 0)
         P.set_option("full_forest", 0)
+
+
+def test_inexact_key_fallback_redoes_the_level(P):
+    # a level whose packed keys took an inexact decision is redone with rank
+    # keys; the integer path notices this only after its contraction ran, so
+    # the labels and the coarse graph are built twice and must still match
+    try:
+        P.set_option("redo_rank", 1)
+        g = trimesh(60, ("uniform", 1, 8), seed=21)
+        st = check_level(P, g, g.n // 2, "trimesh-60 redo with rank keys")
+        assert st.key_mode == 1
+        _, _, stats = check_hierarchy(P, grid3d(12, ("uniform", 1, 16), seed=6), 30, 0, "grid3d-12 redo")
+        assert all(s.key_mode == 1 for s in stats)
+    finally:
+        P.set_option("redo_rank", 0)
+    st = check_level(P, g, g.n // 2, "trimesh-60 packed again")
+    assert st.key_mode == 0
 
 
 def test_huge_rows_sort_and_dense_paths(P):
