@@ -21,7 +21,7 @@ namespace spc {
 constexpr int SMALL_CAP = 16;
 constexpr int REG32_CAP = 32;
 constexpr int SMALL_BS = 128;
-constexpr int SMALL_RPT = 4;   // rows per thread
+constexpr int SMALL_RPT = 4;   // rows per thread, at most (fewer when there are few rows)
 constexpr int WAVE_CAP = 512;
 constexpr int BLOCK_CAP = 4096;
 
@@ -288,6 +288,10 @@ __device__ __forceinline__ void contract_row_regs(const LevelIn& g, const int32_
 }
 
 // ---- rows with at most SMALL_CAP gathered entries: one thread each --------
+// RPT rows per thread: 4 when the rows fill the chip many times over (fewer
+// blocks on the class chains), fewer when there are few, so that the rows'
+// chains of dependent loads run on more threads side by side.
+template <int RPT>
 __global__ void __launch_bounds__(SMALL_BS)
     k_contract_small(LevelIn g, const int32_t* __restrict__ c, const int32_t* __restrict__ mptr,
                      const int32_t* __restrict__ members, const int64_t* __restrict__ gptr,
@@ -300,11 +304,11 @@ __global__ void __launch_bounds__(SMALL_BS)
   __shared__ int64_t sbase[4];
   __shared__ int32_t smx[SMALL_BS / WAVE];
   int tid = threadIdx.x;
-  int64_t base = (int64_t)blockIdx.x * SMALL_BS * SMALL_RPT;
+  int64_t base = (int64_t)blockIdx.x * SMALL_BS * RPT;
   uint32_t r32m = 0, midm = 0, blkm = 0, hugem = 0;
   int nr32 = 0, nmid = 0, nblk = 0, nhuge = 0;
   int32_t mx = 0;
-  for (int r = 0; r < SMALL_RPT; r++) {
+  for (int r = 0; r < RPT; r++) {
     int64_t a = base + r * SMALL_BS + tid;
     if (a >= n_c) break;
     int64_t E = gptr[a + 1] - gptr[a];
@@ -341,7 +345,7 @@ __global__ void __launch_bounds__(SMALL_BS)
         __hip_atomic_load(&info[I_MAXCL], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
       atomicMax(&info[I_MAXCL], (unsigned long long)m2);
   }
-  // the four class lists: per-thread counts (at most SMALL_RPT each) packed
+  // the four class lists: per-thread counts (at most RPT each) packed
   // in 16-bit fields, one block scan, then one look-back chain per class
   // run by lanes 0-3
   unsigned long long mine = (unsigned long long)nr32 | ((unsigned long long)nmid << 16) |
@@ -368,7 +372,7 @@ __global__ void __launch_bounds__(SMALL_BS)
   int64_t p1 = sbase[1] + (int64_t)((excl >> 16) & 0xffff);
   int64_t p2 = sbase[2] + (int64_t)((excl >> 32) & 0xffff);
   int64_t p3 = sbase[3] + (int64_t)((excl >> 48) & 0xffff);
-  for (int r = 0; r < SMALL_RPT; r++) {
+  for (int r = 0; r < RPT; r++) {
     int32_t a = (int32_t)(base + r * SMALL_BS + tid);
     if (r32m >> r & 1u) r32list[p0++] = a;
     if (midm >> r & 1u) midlist[p1++] = a;
@@ -666,34 +670,40 @@ __global__ void __launch_bounds__(HT_BS)
 // dense[h * ncp + (b - base[h])] (u32; a row's total stays below 2^31), then
 // a compaction in ascending b emits the row.  base is null (0) for one graph;
 // in a batch it is the first coarse node of the row's graph, whose coarse
-// range (at most ncp wide) holds every column of the row.  Same tiling and
-// self-loop handling as k_huge_entries.
+// range (at most ncp wide) holds every column of the row.  Same self-loop
+// handling as k_huge_entries, in tiles of HD entries: 4096 on large levels,
+// 1024 (4 per thread) on small ones, where an entry's chain of dependent
+// loads would otherwise repeat 16 times per thread on few blocks.
+constexpr int64_t HD_SMALL_NNZ = 4000000;   // levels up to this many entries use 1024-entry tiles
+
+template <int HD>
 __global__ void __launch_bounds__(HT_BS)
     k_huge_dense(LevelIn g, const int32_t* __restrict__ c, const int32_t* __restrict__ hugelist,
                  const int32_t* __restrict__ hrow, const int64_t* __restrict__ hrs,
                  const int64_t* __restrict__ hpre, int64_t bound, int64_t* self_out,
                  uint32_t* __restrict__ dense, int64_t ncp, const int32_t* __restrict__ base,
                  unsigned long long* bad) {
-  __shared__ int32_t srow[Lbs<HT, HT_BS>::SIZE];
+  __shared__ int32_t srow[Lbs<HD, HT_BS>::SIZE];
   __shared__ int64_t sh[2];
   __shared__ int32_t stmp[HT_BS / WAVE];
+  static_assert(HD <= HT && HD % HT_BS == 0, "a dense tile meets at most two huge rows");
   __shared__ unsigned long long sself[2];
-  int64_t q0 = (int64_t)blockIdx.x * HT;
+  int64_t q0 = (int64_t)blockIdx.x * HD;
   int64_t total = hpre[bound];
   if (q0 >= total) return;
-  lbs_tile<HT, HT_BS>(hpre, bound, q0, srow, sh, stmp);
+  lbs_tile<HD, HT_BS>(hpre, bound, q0, srow, sh, stmp);
   int tid = threadIdx.x;
   if (tid < 2) sself[tid] = 0;
   int32_t h0 = hrow[srow[0]];
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < HT / HT_BS; r++) {
+  for (int r = 0; r < HD / HT_BS; r++) {
     int k = tid + r * HT_BS;
     int64_t q = q0 + k;
     int32_t h = -1;
     int64_t self = 0;
     if (q < total) {
-      int64_t i = srow[Lbs<HT, HT_BS>::at(k)];
+      int64_t i = srow[Lbs<HD, HT_BS>::at(k)];
       h = hrow[i];
       int32_t a = hugelist[h];
       int64_t j = hrs[i] + (q - hpre[i]);
@@ -870,9 +880,21 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
   }
   {
     TimedScope ts(ctx, "contract_small", (double)g.nnz);
-    hipLaunchKernelGGL(k_contract_small, dim3(grid_for(n_c, SMALL_BS * SMALL_RPT)), dim3(SMALL_BS), 0,
-                       st, g, c, W.mptr, W.members, W.gptr, W.temp, W.cnt, self_out, out->size, n_c,
-                       W.r32list, W.midlist, W.blocklist, W.hugelist, info, next_scan(ctx, W));
+    // the fewest rows per thread that keep the grid within 1024 blocks (its
+    // four class chains then fit the look-back words any level reserves)
+    TileScan tsc = next_scan(ctx, W);
+    if (n_c <= 1024 * SMALL_BS)
+      hipLaunchKernelGGL(k_contract_small<1>, dim3(grid_for(n_c, SMALL_BS)), dim3(SMALL_BS), 0, st, g, c,
+                         W.mptr, W.members, W.gptr, W.temp, W.cnt, self_out, out->size, n_c, W.r32list,
+                         W.midlist, W.blocklist, W.hugelist, info, tsc);
+    else if (n_c <= 1024 * SMALL_BS * 2)
+      hipLaunchKernelGGL(k_contract_small<2>, dim3(grid_for(n_c, SMALL_BS * 2)), dim3(SMALL_BS), 0, st, g,
+                         c, W.mptr, W.members, W.gptr, W.temp, W.cnt, self_out, out->size, n_c, W.r32list,
+                         W.midlist, W.blocklist, W.hugelist, info, tsc);
+    else
+      hipLaunchKernelGGL(k_contract_small<SMALL_RPT>, dim3(grid_for(n_c, SMALL_BS * SMALL_RPT)),
+                         dim3(SMALL_BS), 0, st, g, c, W.mptr, W.members, W.gptr, W.temp, W.cnt, self_out,
+                         out->size, n_c, W.r32list, W.midlist, W.blocklist, W.hugelist, info, tsc);
   }
   SPC_LAUNCH_CHECK(ctx, "contract_small");
   // with a deferred selection, this read also carries its super-node count
@@ -932,9 +954,13 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
                            seg->G, base);
       }
       launch_clear(ctx, (int32_t*)dense, H * ncp, nullptr, 0, nullptr, 0u);
-      if (g.nnz > 0)
-        hipLaunchKernelGGL(k_huge_dense, dim3(grid_for(g.nnz, HT)), dim3(HT_BS), 0, st, g, c, W.hugelist,
+      if (g.nnz > HD_SMALL_NNZ)
+        hipLaunchKernelGGL(k_huge_dense<HT>, dim3(grid_for(g.nnz, HT)), dim3(HT_BS), 0, st, g, c, W.hugelist,
                            W.hmrow, W.hmrs, hpre, n, self_out, dense, ncp, (const int32_t*)base,
+                           &info[I_DENSE]);
+      else if (g.nnz > 0)
+        hipLaunchKernelGGL(k_huge_dense<1024>, dim3(grid_for(g.nnz, 1024)), dim3(HT_BS), 0, st, g, c,
+                           W.hugelist, W.hmrow, W.hmrs, hpre, n, self_out, dense, ncp, (const int32_t*)base,
                            &info[I_DENSE]);
       int64_t tpr = ncp / DC_T;
       hipLaunchKernelGGL(k_dense_compact, dim3((unsigned)(H * tpr)), dim3(DC_BS), 0, st, dense, ncp, n_c,

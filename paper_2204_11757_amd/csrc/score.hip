@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(BS)
 // the other endpoint x = col[j].  Row x is read in chunks and looked up in
 // h's map (when x is mapped too and its row is longer, the roles swap; such
 // an edge is scored by the smaller endpoint's row only).
-constexpr int HS_BLOCKS = 64;
+constexpr int HS_BLOCKS = 256;   // about one entry per thread for the rows seen in practice
 
 template <int MODE>
 __global__ void __launch_bounds__(BS)

@@ -106,6 +106,7 @@ __global__ void __launch_bounds__(BS)
   __shared__ int stmp[BS / WAVE];
   __shared__ uint64_t smx[BS / WAVE], ssm[BS / WAVE];
   __shared__ int32_t slong[DEG_ROWS];
+  __shared__ int sdefer;
   int tid = threadIdx.x;
   int64_t base = (int64_t)blockIdx.x * DEG_ROWS;
   uint64_t mx = 0, sm = 0;
@@ -156,7 +157,9 @@ __global__ void __launch_bounds__(BS)
     bestB[u] = KEY_INF;
     parent[u] = (int32_t)u;
   }
-  // rows longer than DEG_SHORT: the whole block sums each of them
+  // rows longer than DEG_SHORT: the whole block sums each of them, except
+  // the first H_MAX rows longer than HUGE_T, which get a position map for
+  // the scores and are summed by k_sum_parts with a block of its own
   int total_long;
   int p = block_incl_scan<int, BS, false>(nlong, stmp, &total_long) - nlong;
   for (int i = 0; i < DEG_PER; i++)
@@ -165,6 +168,18 @@ __global__ void __launch_bounds__(BS)
   for (int r = 0; r < total_long; r++) {
     int64_t u = slong[r];
     int64_t s = g.rp[u], e = g.rp[u + 1];
+    if (e - s > HUGE_T) {
+      if (tid == 0) {
+        // few rows are this long, so one atomic each stays cheap
+        unsigned long long slot = atomicAdd(&info[I_LONGROW], 1ull);
+        sdefer = slot < (unsigned long long)H_MAX ? 1 : 0;
+        if (sdefer) htab[slot] = (int32_t)u;
+      }
+      __syncthreads();
+      int defer = sdefer;
+      __syncthreads();
+      if (defer) continue;
+    }
     uint64_t d = 0;
     for (int64_t j = s + tid; j < e; j += BS) d += (uint64_t)g.w[j];
     d = wave_sum(d);
@@ -176,11 +191,6 @@ __global__ void __launch_bounds__(BS)
       deg[u] = t;
       mx = t > mx ? t : mx;
       sm += t;
-      if (e - s > HUGE_T) {
-        // few rows are this long, so one atomic each stays cheap
-        unsigned long long slot = atomicAdd(&info[I_LONGROW], 1ull);
-        if (slot < (unsigned long long)H_MAX) htab[slot] = (int32_t)u;
-      }
     }
     __syncthreads();
   }
@@ -202,26 +212,59 @@ __global__ void __launch_bounds__(BS)
   }
 }
 
-// total weight from the per-block sums (saturating, so that an overflowing
-// input still reads as too large)
-__global__ void __launch_bounds__(1024)
-    k_sum_parts(const uint64_t* __restrict__ part, int64_t np, unsigned long long* total) {
-  __shared__ uint64_t tmp[1024 / WAVE];
+// Degrees of the mapped long rows (at most H_MAX, registered by k_degree),
+// each summed by the whole block with 8 loads per thread in flight; then the
+// total weight from the per-block sums and those rows (saturating, so that
+// an overflowing input still reads as too large).
+constexpr int SP_BS = 1024;
+constexpr int SP_UNROLL = 8;
+
+__device__ __forceinline__ uint64_t sat_add(uint64_t a, uint64_t b) { return a + b < a ? ~0ull : a + b; }
+
+__global__ void __launch_bounds__(SP_BS)
+    k_sum_parts(const uint64_t* __restrict__ part, int64_t np, LevelIn g, const int32_t* __restrict__ htab,
+                uint64_t* __restrict__ deg, unsigned long long* info) {
+  __shared__ uint64_t tmp[SP_BS / WAVE];
+  int tid = threadIdx.x;
+  unsigned long long nh = info[I_LONGROW];
+  int hc = nh < (unsigned long long)H_MAX ? (int)nh : H_MAX;
+  uint64_t extra = 0, dmx = 0;   // thread 0's
+  for (int r = 0; r < hc; r++) {
+    int32_t u = htab[r];
+    int64_t a = g.rp[u], b = g.rp[u + 1];
+    uint64_t d = 0;
+    for (int64_t j0 = a + tid; j0 < b; j0 += (int64_t)SP_BS * SP_UNROLL) {
+      uint32_t v[SP_UNROLL];
+#pragma unroll
+      for (int q = 0; q < SP_UNROLL; q++) {
+        int64_t j = j0 + (int64_t)q * SP_BS;
+        v[q] = j < b ? (uint32_t)g.w[j] : 0u;
+      }
+#pragma unroll
+      for (int q = 0; q < SP_UNROLL; q++) d += v[q];
+    }
+    d = wave_sum(d);
+    if (lane_id() == 0) tmp[tid / WAVE] = d;
+    __syncthreads();
+    if (tid == 0) {
+      uint64_t t = g.self ? (uint64_t)g.self[u] : 0;
+      for (int w = 0; w < SP_BS / WAVE; w++) t += tmp[w];
+      deg[u] = t;
+      dmx = t > dmx ? t : dmx;
+      extra += t;
+    }
+    __syncthreads();
+  }
   uint64_t s = 0;
-  for (int64_t i = threadIdx.x; i < np; i += 1024) {
-    uint64_t v = part[i];
-    s = s + v < s ? ~0ull : s + v;
-  }
-  for (int o = WAVE / 2; o > 0; o >>= 1) {
-    uint64_t v = __shfl_xor(s, o);
-    s = s + v < s ? ~0ull : s + v;
-  }
-  if (lane_id() == 0) tmp[threadIdx.x / WAVE] = s;
+  for (int64_t i = tid; i < np; i += SP_BS) s = sat_add(s, part[i]);
+  for (int o = WAVE / 2; o > 0; o >>= 1) s = sat_add(s, __shfl_xor(s, o));
+  if (lane_id() == 0) tmp[tid / WAVE] = s;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint64_t t = 0;
-    for (int w = 0; w < 1024 / WAVE; w++) t = t + tmp[w] < t ? ~0ull : t + tmp[w];
-    *total = t;
+  if (tid == 0) {
+    uint64_t t = extra;
+    for (int w = 0; w < SP_BS / WAVE; w++) t = sat_add(t, tmp[w]);
+    info[I_TOTAL] = t;
+    if (hc > 0) atomic_max_lazy(&info[I_DMAX], (unsigned long long)dmx);
   }
 }
 
@@ -363,12 +406,15 @@ __global__ void __launch_bounds__(BS)
 }
 
 // ---------------------------------------------------------------------------
-// A4: spanning-forest rounds (Boruvka) on the live list, one chunk of items
-// per block: 4096 for the hooking pass, 1024 for the root lookups (an item's
-// lookups are chains of dependent loads, so fewer per thread).
+// A4: spanning-forest rounds (Boruvka) on the live list.  A hooking pass
+// takes 4096 items per block (16 per thread) on long lists and 1024 (4 per
+// thread, their loads issued side by side) on short ones, where too few
+// blocks would leave each thread a long chain of dependent loads; the root
+// lookups take 1024 (an item's lookups are chains of dependent loads).
 // ---------------------------------------------------------------------------
-constexpr int BV_CHUNK = 4096;
-constexpr int BV_PER = BV_CHUNK / BS;
+constexpr int BV_LONG = 16;
+constexpr int BV_SHORT = 4;
+constexpr int64_t BV_SHORT_MAX = 1000000;   // lists up to this many items use BV_SHORT
 constexpr int BC_CHUNK = 1024;
 constexpr int BC_PER = BC_CHUNK / BS;
 
@@ -386,7 +432,8 @@ __device__ __forceinline__ void guard_check(const KeyND* __restrict__ keys, cons
 }
 
 // Every component adopts its lightest live edge; those edges are joined and
-// recorded as forest edges.
+// recorded as forest edges.  PER items per thread.
+template <int PER>
 __global__ void __launch_bounds__(BS)
     k_bv_merge(const uint64_t* __restrict__ lr, const uint64_t* __restrict__ lp,
                const uint64_t* __restrict__ lo, const unsigned long long* cnt,
@@ -396,27 +443,55 @@ __global__ void __launch_bounds__(BS)
                const KeyND* __restrict__ keys, const uint64_t* __restrict__ kexact,
                const unsigned long long* guard, int ebits, int* viol, TileScan ts,
                unsigned long long* rounds) {
+  constexpr int CHUNK = PER * BS;
+  constexpr bool SIDE = PER <= BV_SHORT;   // all of a thread's loads of one kind at once
   __shared__ int stmp[BS / WAVE];
   __shared__ unsigned long long sbase;
   int64_t n = (int64_t)*cnt;
   int tid = threadIdx.x;
-  int64_t base = (int64_t)blockIdx.x * BV_CHUNK;
+  int64_t base = (int64_t)blockIdx.x * CHUNK;
   if (base >= n) return;
   if (blockIdx.x == 0 && tid == 0) {   // rounds points at info[I_ROUNDS]
     atomicAdd(rounds, 1ull);
     atomicAdd(rounds + (I_MIN - I_ROUNDS), (unsigned long long)n);
   }
   if (keys && !*guard) keys = nullptr;
+  uint64_t suv[SIDE ? PER : 1], skey[SIDE ? PER : 1], swa[SIDE ? PER : 1], swb[SIDE ? PER : 1];
+  if constexpr (SIDE) {
+#pragma unroll
+    for (int i = 0; i < PER; i++) {
+      int64_t idx = base + tid + i * BS;
+      suv[i] = idx < n ? lr[idx] : 0;
+      skey[i] = idx < n ? lp[idx] : KEY_INF;
+    }
+#pragma unroll
+    for (int i = 0; i < PER; i++) {
+      int64_t idx = base + tid + i * BS;
+      swa[i] = idx < n ? best[(int32_t)(uint32_t)suv[i]] : KEY_INF;
+      swb[i] = idx < n ? best[(int32_t)(suv[i] >> 32)] : KEY_INF;
+    }
+  }
   uint32_t chosen = 0;
   int nc = 0;
-  int32_t hooked[BV_PER];
-  for (int i = 0; i < BV_PER; i++) {
+  int32_t hooked[PER];
+#pragma unroll
+  for (int i = 0; i < PER; i++) {
     int64_t idx = base + tid + i * BS;
+    hooked[i] = 0;
     if (idx >= n) break;
-    uint64_t uv = lr[idx];
-    uint64_t key = lp[idx];
+    uint64_t uv, key, wa, wb;
+    if constexpr (SIDE) {
+      uv = suv[i];
+      key = skey[i];
+      wa = swa[i];
+      wb = swb[i];
+    } else {
+      uv = lr[idx];
+      key = lp[idx];
+      wa = best[(int32_t)(uint32_t)uv];
+      wb = best[(int32_t)(uv >> 32)];
+    }
     int32_t a = (int32_t)(uint32_t)uv, b = (int32_t)(uv >> 32);
-    uint64_t wa = best[a], wb = best[b];
     if (keys) {
       guard_check(keys, kexact, ebits, key, wa, viol);
       guard_check(keys, kexact, ebits, key, wb, viol);
@@ -434,9 +509,9 @@ __global__ void __launch_bounds__(BS)
       nc++;
     }
   }
-  int64_t pos = block_reserve_lb<BS>(ts, blockIdx.x, base + BV_CHUNK >= n, nc, msfcnt, msfcnt,
+  int64_t pos = block_reserve_lb<BS>(ts, blockIdx.x, base + CHUNK >= n, nc, msfcnt, msfcnt,
                                      &sbase, stmp);
-  for (int i = 0; i < BV_PER; i++) {
+  for (int i = 0; i < PER; i++) {
     if (!(chosen >> i & 1u)) continue;
     int64_t idx = base + tid + i * BS;
     if (pos < msf_cap) {  // a forest has fewer than n edges
@@ -446,6 +521,22 @@ __global__ void __launch_bounds__(BS)
     }
     pos++;
   }
+}
+
+static void launch_bv_merge(spc_ctx* ctx, LevelWork& W, int64_t bound, const uint64_t* lr, const uint64_t* lp,
+                            const uint64_t* lo, const unsigned long long* cnt, const uint64_t* best, int64_t n,
+                            const KeyND* guard_keys, int ebits) {
+  unsigned long long* info = W.info;
+  if (bound <= BV_SHORT_MAX)
+    hipLaunchKernelGGL(k_bv_merge<BV_SHORT>, dim3(grid_for(bound, BV_SHORT * BS)), dim3(BS), 0, ctx->stream,
+                       lr, lp, lo, cnt, best, W.parent, W.msfP, W.msfO, W.msfC, &info[I_MSF], n, guard_keys,
+                       W.kexact, &info[I_GUARD], ebits, (int*)&info[I_VIOL], next_scan(ctx, W),
+                       &info[I_ROUNDS]);
+  else
+    hipLaunchKernelGGL(k_bv_merge<BV_LONG>, dim3(grid_for(bound, BV_LONG * BS)), dim3(BS), 0, ctx->stream,
+                       lr, lp, lo, cnt, best, W.parent, W.msfP, W.msfO, W.msfC, &info[I_MSF], n, guard_keys,
+                       W.kexact, &info[I_GUARD], ebits, (int*)&info[I_VIOL], next_scan(ctx, W),
+                       &info[I_ROUNDS]);
 }
 
 // Pointer jumping after a merge round, over the roots that round hooked
@@ -1007,8 +1098,6 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, boo
                            const KeyND* guard_keys, int ebits, int64_t& live0) {
   unsigned long long* info = W.info;
   int64_t* hinfo = ctx->h_pinned;
-  int* viol = (int*)&info[I_VIOL];
-  const unsigned long long* guard = &info[I_GUARD];
   int rc;
   int64_t cnt = m;
   uint64_t* cur = W.bestA;
@@ -1016,10 +1105,7 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, boo
   int in = 0;
   if (fused_first) {
     TimedScope ts(ctx, "forest_merge", (double)cnt);
-    hipLaunchKernelGGL(k_bv_merge, dim3(grid_for(cnt, BV_CHUNK)), dim3(BS), 0, ctx->stream, W.lr[0],
-                       W.lp[0], W.lr[0], &info[I_LIVE0], cur, W.parent, W.msfP, W.msfO, W.msfC,
-                       &info[I_MSF], n, guard_keys, W.kexact, guard, ebits, viol, next_scan(ctx, W),
-                       &info[I_ROUNDS]);
+    launch_bv_merge(ctx, W, cnt, W.lr[0], W.lp[0], W.lr[0], &info[I_LIVE0], cur, n, guard_keys, ebits);
   }
   if (fused_first) {
     // the band's first records start where the previous band's ended
@@ -1054,10 +1140,7 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, boo
       if (out == 0) lo0_is_lr = false;
       {
         TimedScope ts(ctx, "forest_merge", (double)bound);
-        hipLaunchKernelGGL(k_bv_merge, dim3(grid_for(bound, BV_CHUNK)), dim3(BS), 0, ctx->stream,
-                           W.lr[out], W.lp[out], W.lo[out], &info[co], cur, W.parent, W.msfP, W.msfO,
-                           W.msfC, &info[I_MSF], n, guard_keys, W.kexact, guard, ebits, viol, next_scan(ctx, W),
-                           &info[I_ROUNDS]);
+        launch_bv_merge(ctx, W, bound, W.lr[out], W.lp[out], W.lo[out], &info[co], cur, n, guard_keys, ebits);
       }
       {
         TimedScope ts(ctx, "forest_shortcut", (double)bound);
@@ -1242,7 +1325,8 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
                          W.parent, W.degpart, W.htab, info);
     }
     TimedScope ts(ctx, "degree_total", (double)nb);
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, st, W.degpart, (int64_t)nb, &info[I_TOTAL]);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(SP_BS), 0, st, W.degpart, (int64_t)nb, g, W.htab, W.deg,
+                       info);
   }
   SPC_LAUNCH_CHECK(ctx, "degree");
   int rc;
