@@ -47,6 +47,8 @@ __global__ void __launch_bounds__(SEL_BS)
                  unsigned long long* info) {
   __shared__ unsigned int h[SEL_BINS];
   __shared__ uint64_t sbuf[SEG_SMALL];
+  __shared__ uint64_t s2[LDS_SMALL2];
+  __shared__ unsigned int s2cnt;
   __shared__ unsigned long long tmp[SEL_BS / WAVE];
   __shared__ unsigned long long red[2 * (SEL_BS / WAVE)];
   __shared__ unsigned long long spick[3];
@@ -155,7 +157,7 @@ __global__ void __launch_bounds__(SEL_BS)
     }
     __syncthreads();
     unsigned int c = slocal < (unsigned)SEG_SMALL ? slocal : (unsigned)SEG_SMALL;
-    cut = lds_select(sbuf, (int)c, k, h, tmp, red, spick, &info[I_LBERR]);
+    cut = lds_select(sbuf, (int)c, k, h, tmp, red, spick, &info[I_LBERR], s2, &s2cnt);
   }
   // join the forest edges up to the cutoff; the cutoff edge gives epsilon
   bool guarded = exact && info[I_GUARD];

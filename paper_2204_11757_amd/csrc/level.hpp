@@ -166,7 +166,7 @@ struct LevelWork {
   int64_t* uptr;             // [n+1] upper-edge prefix (edge ids)
   uint64_t* P;               // [m]  order key per edge (sorted-rank order)
   uint64_t* Pc;              // [nnz] order key per CSR entry (both directions)
-  uint64_t* samples;         // [m/64 + 2]
+  uint64_t* samples;         // [m/64 + 2], keys of edges 0, s, 2s, ... (s = 2^sample_shift(m))
   uint64_t* kexact;          // [m/64 + 2] bit e: edge e's packed key has no remainder
   uint64_t* bestA;           // [n]
   uint64_t* bestB;           // [n]
@@ -224,6 +224,14 @@ constexpr int FP_EBIAS = 4096;  // bias of the exponents kept in the info block
 constexpr int FP_MAX_SPAN = 192 - 33;
 
 // look-back words a level needs: the most tiles any compaction launch uses
+// Edges between two key samples: 64, or more so that at most about 4096
+// samples (one block's in-LDS selection) pick a band's threshold.
+inline int sample_shift(int64_t m) {
+  int s = 6;
+  while ((m >> s) > 4096) s++;
+  return s;
+}
+
 inline int64_t lb_words(int64_t n, int64_t nnz) { return nnz / 1024 + 4 * (n / 256) + 4096; }
 
 void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W, bool fp = false);

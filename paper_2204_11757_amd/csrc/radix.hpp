@@ -14,17 +14,19 @@ constexpr long SEL_SPIN = 1l << 24;          // barrier polls before giving up (
 
 // LDS histogram increment of bin `bin` for the lanes with `m` set: when all
 // such lanes of the wave share one bin (skewed digits, ties), one lane adds
-// their count, so equal keys do not serialise on one LDS address.
+// their count, so equal keys do not serialise on one LDS address.  Inside
+// the branch the active lanes are exactly those with `m`, so the first one's
+// bin is a scalar read (no cross-lane LDS traffic).
 __device__ __forceinline__ void hist_add(unsigned int* h, bool m, uint32_t bin) {
-  unsigned long long act = __ballot(m);
-  if (!act) return;
-  int leader = __ffsll((long long)act) - 1;
-  uint32_t lb = (uint32_t)__shfl((int)bin, leader);
-  unsigned long long same = __ballot(m && bin == lb);
-  if (same == act) {
-    if (lane_id() == leader) atomicAdd(&h[lb], (unsigned int)__popcll(act));
-  } else if (m) {
-    atomicAdd(&h[bin], 1u);
+  if (m) {
+    uint32_t lb = __builtin_amdgcn_readfirstlane(bin);
+    unsigned long long act = __ballot(1);
+    unsigned long long same = __ballot(bin == lb);
+    if (same == act) {
+      if (lane_id() == __ffsll((long long)act) - 1) atomicAdd(&h[lb], (unsigned int)__popcll(act));
+    } else {
+      atomicAdd(&h[bin], 1u);
+    }
   }
 }
 
@@ -60,48 +62,80 @@ __device__ __forceinline__ void block_minmax(uint64_t& mn, uint64_t& mx, unsigne
 }
 
 // The k-th smallest of the c keys in s (LDS), by one block.
-// Each round first finds the smallest and largest key still in play and
-// decides the bits they share (so a run of equal scores costs nothing),
-// then histograms the next 11 bits (8 bins per thread) and keeps the
-// bucket of the k-th key.  h needs SEL_BS * 8 counters.
+// It first finds the smallest and largest key and decides the bits they
+// share (so a run of equal scores costs nothing); each round then
+// histograms the next 11 bits of the keys still in play (8 bins per thread)
+// and keeps the bucket of the k-th key.  Once that bucket holds at most
+// LDS_SMALL2 keys they are copied to s2 and later rounds read only those;
+// every copy or rescan also finds the bucket's smallest and largest key, so
+// bits they share are skipped again.  h needs SEL_BS * 8 counters, s2
+// LDS_SMALL2 keys.
+constexpr int LDS_SMALL2 = 1024;
+
 __device__ __forceinline__ uint64_t lds_select(const uint64_t* s, int c, unsigned long long k, unsigned int* h,
                                                unsigned long long* tmp, unsigned long long* red,
-                                               unsigned long long* spick, unsigned long long* err) {
+                                               unsigned long long* spick, unsigned long long* err,
+                                               uint64_t* s2, unsigned int* scount) {
   constexpr int PER = 8;
   constexpr int DIG = 11;
+  constexpr int U = 8;   // keys per thread whose LDS loads are issued together
   int t = threadIdx.x;
   if (k >= (unsigned long long)c) {
     if (t == 0) __hip_atomic_store(err, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return ~0ull;
   }
   uint64_t prefix = 0, mask = 0;
-  int hi = 64;
-  while (true) {
-    uint64_t mn = ~0ull, mx = 0;
-    for (int i = t; i < c; i += SEL_BS) {
-      uint64_t x = s[i];
-      if ((x & mask) == prefix) {
-        mn = x < mn ? x : mn;
-        mx = x > mx ? x : mx;
+  const uint64_t* cur = s;
+  int cc = c;
+  // extremes of the keys matching (prefix, mask) in cur
+  auto extremes = [&](uint64_t& mn, uint64_t& mx) {
+    mn = ~0ull;
+    mx = 0;
+    for (int i0 = 0; i0 < cc; i0 += SEL_BS * U) {
+      uint64_t v[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        int i = i0 + u * SEL_BS + t;
+        v[u] = i < cc ? cur[i] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        int i = i0 + u * SEL_BS + t;
+        if (i < cc && (v[u] & mask) == prefix) {
+          mn = v[u] < mn ? v[u] : mn;
+          mx = v[u] > mx ? v[u] : mx;
+        }
       }
     }
     block_minmax(mn, mx, red);
+  };
+  uint64_t mn, mx;
+  extremes(mn, mx);
+  while (true) {
     uint64_t x = mn ^ mx;
     if (x == 0) return mn;   // every key in play is equal
-    int d = 63 - __clzll((long long)x);   // highest differing bit, below hi
+    int d = 63 - __clzll((long long)x);   // highest differing bit
     uint64_t low = d == 63 ? ~0ull : (2ull << d) - 1;
     prefix = mn & ~low;
     mask = ~low;
-    hi = d + 1;
+    int hi = d + 1;
     int lo = hi - DIG > 0 ? hi - DIG : 0;
     int nb = 1 << (hi - lo);
     uint64_t dm = (uint64_t)(nb - 1);
     for (int q = 0; q < PER; q++) h[PER * t + q] = 0;
     __syncthreads();
-    for (int i0 = 0; i0 < c; i0 += SEL_BS) {
-      int i = i0 + t;
-      uint64_t y = i < c ? s[i] : 0;
-      hist_add(h, i < c && (y & mask) == prefix, (uint32_t)((y >> lo) & dm));
+    for (int i0 = 0; i0 < cc; i0 += SEL_BS * U) {
+      uint64_t v[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        int i = i0 + u * SEL_BS + t;
+        v[u] = i < cc ? cur[i] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        int i = i0 + u * SEL_BS + t;
+        hist_add(h, i < cc && (v[u] & mask) == prefix, (uint32_t)((v[u] >> lo) & dm));
+      }
     }
     __syncthreads();
     unsigned int cq[PER];
@@ -128,17 +162,39 @@ __device__ __forceinline__ uint64_t lds_select(const uint64_t* s, int c, unsigne
     prefix |= spick[0] << lo;
     mask |= dm << lo;
     k -= spick[1];
-    bool one = spick[2] == 1;
+    unsigned long long cb = spick[2];
     __syncthreads();
     if (lo == 0) return prefix;
-    if (one) {
-      // a single key is left in the bucket: find it
-      for (int i = t; i < c; i += SEL_BS)
-        if ((s[i] & mask) == prefix) spick[0] = s[i];
+    if (cur == s && cb <= (unsigned long long)LDS_SMALL2) {
+      // copy the bucket's keys (in any order) and take their extremes
+      if (t == 0) *scount = 0;
       __syncthreads();
-      uint64_t r = spick[0];
-      __syncthreads();
-      return r;
+      mn = ~0ull;
+      mx = 0;
+      for (int i0 = 0; i0 < cc; i0 += SEL_BS * U) {
+        uint64_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          int i = i0 + u * SEL_BS + t;
+          v[u] = i < cc ? cur[i] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          int i = i0 + u * SEL_BS + t;
+          bool m = i < cc && (v[u] & mask) == prefix;
+          unsigned int q = wave_reserve(scount, m);
+          if (m) {
+            if (q < (unsigned)LDS_SMALL2) s2[q] = v[u];
+            mn = v[u] < mn ? v[u] : mn;
+            mx = v[u] > mx ? v[u] : mx;
+          }
+        }
+      }
+      block_minmax(mn, mx, red);   // its barriers also publish s2 and *scount
+      cur = s2;
+      cc = (int)cb;
+    } else {
+      extremes(mn, mx);
     }
   }
 }

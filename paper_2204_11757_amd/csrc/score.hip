@@ -21,7 +21,7 @@ __global__ void __launch_bounds__(BS, 5)
             const int64_t* __restrict__ uptr, int64_t m, int c, int ebits,
             uint64_t* __restrict__ Pc, uint64_t* __restrict__ samples, KeyND* __restrict__ keys,
             int write_keys, unsigned long long* info, const int32_t* __restrict__ htab,
-            uint64_t* __restrict__ kexact) {
+            uint64_t* __restrict__ kexact, int sshift) {
   // write_keys < 0: exact records only when the packed key is not exact
   // for sure, i.e. when dmax^4 > 2^c
   if (MODE == 0 && write_keys < 0) {
@@ -81,7 +81,7 @@ __global__ void __launch_bounds__(BS, 5)
         uint64_t key = (K << ebits) | (uint64_t)e;
         Pc[ej[i]] = key;   // entry (u -> v)
         Pc[jm] = key;      // entry (v -> u)
-        if ((e & 63) == 0) samples[e >> 6] = key;
+        if ((e & ((1ll << sshift) - 1)) == 0) samples[e >> sshift] = key;
       }
       if (MODE == 1 || write_keys) keys[e] = KeyND{N, D, (uint64_t)e};
     }
@@ -193,7 +193,7 @@ __global__ void __launch_bounds__(BS)
                    const int64_t* __restrict__ uptr, int c, int ebits, uint64_t* __restrict__ Pc,
                    uint64_t* __restrict__ samples, KeyND* __restrict__ keys, int write_keys,
                    unsigned long long* info, const int32_t* __restrict__ htab,
-                   const int32_t* __restrict__ hmap) {
+                   const int32_t* __restrict__ hmap, int sshift) {
   __shared__ uint64_t sred[BS / WAVE];
   int s = blockIdx.x / HS_BLOCKS;
   unsigned long long nh = info[I_LONGROW];
@@ -242,7 +242,7 @@ __global__ void __launch_bounds__(BS)
       uint64_t key = (fixed_key(N, D, c) << ebits) | (uint64_t)e;
       Pc[j] = key;
       Pc[jm] = key;
-      if ((e & 63) == 0) samples[e >> 6] = key;
+      if ((e & ((1ll << sshift) - 1)) == 0) samples[e >> sshift] = key;
     }
     if (MODE == 1 || write_keys) keys[e] = KeyND{N, D, (uint64_t)e};
   }
@@ -269,25 +269,26 @@ void launch_score(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t m,
     {
       TimedScope ts(ctx, "score", (double)m);
       hipLaunchKernelGGL(k_score<0>, dim3(tiles), dim3(BS), 0, ctx->stream, g, W.deg, W.lc, W.uptr, m, c,
-                         ebits, W.Pc, W.samples, W.keysA, -1, W.info, W.htab, W.kexact);
+                         ebits, W.Pc, W.samples, W.keysA, -1, W.info, W.htab, W.kexact, sample_shift(m));
     }
     if (maps) {
       TimedScope ts(ctx, "score_long_rows", (double)H_MAX);
       hipLaunchKernelGGL(k_score_mapped<0>, dim3(H_MAX * HS_BLOCKS), dim3(BS), 0, ctx->stream, g, W.deg,
-                         W.lc, W.uptr, c, ebits, W.Pc, W.samples, W.keysA, -1, W.info, W.htab, W.hmap);
+                         W.lc, W.uptr, c, ebits, W.Pc, W.samples, W.keysA, -1, W.info, W.htab, W.hmap,
+                         sample_shift(m));
     }
   } else {
     {
       TimedScope ts(ctx, "score_rank", (double)m);
       hipLaunchKernelGGL(k_score<1>, dim3(tiles), dim3(BS), 0, ctx->stream, g, W.deg, W.lc, W.uptr, m, c,
                          ebits, (uint64_t*)nullptr, (uint64_t*)nullptr, W.keysA, 1, W.info, W.htab,
-                         (uint64_t*)nullptr);
+                         (uint64_t*)nullptr, sample_shift(m));
     }
     if (maps) {
       TimedScope ts(ctx, "score_long_rows", (double)H_MAX);
       hipLaunchKernelGGL(k_score_mapped<1>, dim3(H_MAX * HS_BLOCKS), dim3(BS), 0, ctx->stream, g, W.deg,
                          W.lc, W.uptr, c, ebits, (uint64_t*)nullptr, (uint64_t*)nullptr, W.keysA, 1, W.info,
-                         W.htab, W.hmap);
+                         W.htab, W.hmap, sample_shift(m));
     }
   }
 }

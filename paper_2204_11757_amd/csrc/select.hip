@@ -745,6 +745,8 @@ __global__ void __launch_bounds__(SEL_BS)
   static_assert(SEL_NGRP * 8 == SEL_BS && SEL_GBINS * 4 == SEL_BS, "pick layout");
   __shared__ unsigned int h[SEL_BINS];
   __shared__ uint64_t sbuf[SEL_SMALL];
+  __shared__ uint64_t s2[LDS_SMALL2];
+  __shared__ unsigned int s2cnt;
   __shared__ unsigned long long tmp[SEL_BS / WAVE];
   __shared__ unsigned long long red[2 * (SEL_BS / WAVE)];
   __shared__ unsigned long long spick[3];
@@ -915,7 +917,7 @@ __global__ void __launch_bounds__(SEL_BS)
       }
     }
     __syncthreads();
-    uint64_t r = lds_select(sbuf, (int)n, k, h, tmp, red, spick, err);
+    uint64_t r = lds_select(sbuf, (int)n, k, h, tmp, red, spick, err, s2, &s2cnt);
     if (t == 0) {
       st->prefix = r;
       st->mask = ~0ull;
@@ -965,7 +967,7 @@ __global__ void __launch_bounds__(SEL_BS)
     }
   }
   __syncthreads();
-  uint64_t r = lds_select(sbuf, (int)cnt, k, h, tmp, red, spick, err);
+  uint64_t r = lds_select(sbuf, (int)cnt, k, h, tmp, red, spick, err, s2, &s2cnt);
   if (t == 0) {
     st->prefix = r;
     st->mask = ~0ull;
@@ -1034,16 +1036,16 @@ __global__ void k_fill_u64(uint64_t* __restrict__ a, int64_t n, uint64_t v) {
 // upper threshold of a band: the selected sample key, or "everything".
 // Guarded keys order edges of one K bucket only approximately, so there the
 // band is widened to the end of the sample's K bucket.
-// Samples are the keys of edges 0, 64, 128, ...; when the q-th smallest is
-// edge 64q itself, the band is (most likely) one tied K bucket read in edge
-// order, i.e. a run of consecutive rows, whose forest has about one edge per
-// row rather than per candidate.  Such a band is extended to edge e_tie
-// (chosen by the caller to cover k rows); only the band's size changes.
+// Samples are the keys of edges 0, s, 2s, ...; when the q-th smallest is
+// edge eq = q s itself, the band is (most likely) one tied K bucket read in
+// edge order, i.e. a run of consecutive rows, whose forest has about one
+// edge per row rather than per candidate.  Such a band is extended to edge
+// e_tie (chosen by the caller to cover k rows); only the band's size changes.
 // With c > 0 it first decides the level's key mode into info[I_GUARD]
 // (the packed key is inexact for some pair of edges only when
 // Dmax^2 > 2^c, Dmax = largest d_u d_v).
 __global__ void k_thr_from_sel(const SelState* st, unsigned long long* thr, int all, int ebits,
-                               unsigned long long* info, int c, unsigned long long q,
+                               unsigned long long* info, int c, unsigned long long eq,
                                unsigned long long e_tie) {
   uint64_t emask = (1ull << ebits) - 1;
   uint64_t p = st->prefix;
@@ -1054,7 +1056,7 @@ __global__ void k_thr_from_sel(const SelState* st, unsigned long long* thr, int 
   bool widen = info[I_GUARD] != 0;
   if (all) *thr = KEY_INF;
   else if (widen) *thr = p | emask;
-  else if ((p & emask) == 64 * q && e_tie > (p & emask)) *thr = (p & ~emask) | (e_tie & emask);
+  else if ((p & emask) == eq && e_tie > (p & emask)) *thr = (p & ~emask) | (e_tie & emask);
   else *thr = p;
 }
 
@@ -1233,8 +1235,9 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
       hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits, info, kc, 0ull,
                          0ull);
     } else if (!rank) {
-      int64_t ns = (m + 63) / 64;
-      int64_t q = (int64_t)((double)target / 64.0 * 1.05) + 16;
+      int sh = sample_shift(m);
+      int64_t ns = ((m - 1) >> sh) + 1;
+      int64_t q = (int64_t)((double)target / (double)(1ll << sh) * 1.05) + 16;
       if (q >= ns) {
         all = true;
         hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits, info, kc, 0ull,
@@ -1251,7 +1254,7 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
           e_tie = rows >= (double)(m - 1) ? (uint64_t)(m - 1) : (uint64_t)rows;
         }
         hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 0, ebits, info, kc,
-                           (unsigned long long)q, (unsigned long long)e_tie);
+                           (unsigned long long)q << sh, (unsigned long long)e_tie);
       }
     } else {
       hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, thr_hi, (unsigned long long)(target - 1));
