@@ -270,8 +270,11 @@ void launch_rank_scatter(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int
                          const KeyND* sorted);
 // Pc from P (an edge's rank into both of its CSR entries)
 void launch_rank_mirror(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t m);
-// info[I_EPS] = exact score of the forest edge whose key equals sel2's cutoff
-void launch_eps(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t msf_bound);
+// cluster_of[x] = label of x's component root (W.root, labels in W.flag,
+// clamped to [0, t)); with eps, also info[I_EPS] = exact score of the forest
+// edge whose key equals sel2's cutoff.  One launch.
+void launch_relabel_eps(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int32_t* cluster_of, int64_t t,
+                        int64_t msf_bound, bool eps);
 
 // Floating-point path pieces (fp.hip).
 // A1: validates the weights, records their exponent range, computes the

@@ -249,10 +249,13 @@ struct SelState {
 // barrier that waited too long, or k >= cnt, sets *err (the result is then
 // undefined).  flags: SEL_MAXB * SEL_FLAG words, zeroed when ctx->sel_epoch
 // was last reset to 0; every select of that period uses epochs above the
-// previous one's.
+// previous one's.  thr (nullable): also derive a band threshold from the
+// selected key, in the same launch.
+struct ThrSpec;
 int radix_select(spc_ctx* ctx, const uint64_t* keys, const unsigned long long* cnt_dev,
                  int64_t cnt_bound, const unsigned long long* k_dev, unsigned long long k_host,
-                 int bits, SelState* st, unsigned long long* flags, unsigned long long* err);
+                 int bits, SelState* st, unsigned long long* flags, unsigned long long* err,
+                 const ThrSpec* thr = nullptr);
 
 // Small launches that replace the runtime's fill and copy blits on the
 // level path (each blit costs the host far more than a plain launch).

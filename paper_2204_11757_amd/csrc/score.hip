@@ -136,15 +136,25 @@ __global__ void __launch_bounds__(BS)
   }
 }
 
-// Theorem 2's epsilon: the score of the heaviest accepted edge, which is
-// the forest edge whose key equals the cutoff.
-__global__ void k_eps(LevelIn g, const uint64_t* __restrict__ deg, const int32_t* __restrict__ lc,
-                      const uint64_t* __restrict__ msfP,
-                      const uint64_t* __restrict__ msfO, const unsigned long long* cnt,
-                      const SelState* st, double* out) {
+// Labels and Theorem 2's epsilon in one launch.  Labels: every node takes
+// its component root's number, clamped to [0, t) (they are there by
+// construction; the clamp keeps a later contraction in bounds should a check
+// done at the host's next read of the info block fail).  Epsilon (with
+// cnt non-null): the score of the heaviest accepted edge, which is the
+// forest edge whose key equals the cutoff.
+__global__ void k_relabel_eps(LevelIn g, const int32_t* __restrict__ root, const int32_t* __restrict__ cid,
+                              int32_t* __restrict__ cluster_of, int64_t t,
+                              const uint64_t* __restrict__ deg, const int32_t* __restrict__ lc,
+                              const uint64_t* __restrict__ msfP, const uint64_t* __restrict__ msfO,
+                              const unsigned long long* cnt, const SelState* st, double* out) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < g.n; x += stride) {
+    int64_t c = cid[root[x]];
+    cluster_of[x] = (int32_t)(c < 0 ? 0 : c >= t ? t - 1 : c);
+  }
+  if (!cnt) return;
   int64_t n = (int64_t)*cnt;
   uint64_t T = st->prefix;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     if (msfP[i] != T) continue;
     uint64_t uv = msfO[i];
@@ -304,10 +314,13 @@ void launch_rank_scatter(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int
   launch_rank_mirror(ctx, g, W, m);
 }
 
-void launch_eps(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t msf_bound) {
-  double* deps = (double*)&W.info[I_EPS];
-  hipLaunchKernelGGL(k_eps, dim3(grid_for(msf_bound, 256, ctx->num_cus * 4)), dim3(256), 0, ctx->stream, g,
-                     W.deg, W.lc, W.msfP, W.msfO, &W.info[I_MSF], W.sel2, deps);
+void launch_relabel_eps(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int32_t* cluster_of, int64_t t,
+                        int64_t msf_bound, bool eps) {
+  int64_t items = g.n > msf_bound ? g.n : msf_bound;
+  hipLaunchKernelGGL(k_relabel_eps, dim3(grid_for(items, 256)), dim3(256), 0, ctx->stream, g, W.root, W.flag,
+                     cluster_of, t, W.deg, W.lc, W.msfP, W.msfO,
+                     eps ? (const unsigned long long*)&W.info[I_MSF] : (const unsigned long long*)nullptr,
+                     W.sel2, (double*)&W.info[I_EPS]);
 }
 
 }  // namespace spc

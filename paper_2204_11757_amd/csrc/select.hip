@@ -100,10 +100,13 @@ void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W, bool fp) {
 
 __global__ void __launch_bounds__(BS)
     k_degree(LevelIn g, uint64_t* __restrict__ deg, int32_t* __restrict__ lc,
-             int64_t* __restrict__ ucnt, uint64_t* __restrict__ bestA,
+             int64_t* __restrict__ uptr, uint64_t* __restrict__ bestA,
              uint64_t* __restrict__ bestB, int32_t* __restrict__ parent,
-             uint64_t* __restrict__ part, int32_t* __restrict__ htab, unsigned long long* info) {
+             uint64_t* __restrict__ part, int32_t* __restrict__ htab, unsigned long long* info,
+             TileScan ts) {
   __shared__ int stmp[BS / WAVE];
+  __shared__ int64_t stmp64[BS / WAVE];
+  __shared__ int64_t sbase;
   __shared__ uint64_t smx[BS / WAVE], ssm[BS / WAVE];
   __shared__ int32_t slong[DEG_ROWS];
   __shared__ int sdefer;
@@ -112,6 +115,10 @@ __global__ void __launch_bounds__(BS)
   uint64_t mx = 0, sm = 0;
   uint32_t longmask = 0;
   int nlong = 0;
+  int64_t ucnt[DEG_PER];   // upper entries of this thread's rows
+#pragma unroll
+  for (int i = 0; i < DEG_PER; i++) ucnt[i] = 0;
+#pragma unroll
   for (int i = 0; i < DEG_PER; i++) {
     int64_t u = base + i * BS + tid;
     if (u >= g.n) break;
@@ -137,7 +144,7 @@ __global__ void __launch_bounds__(BS)
         }
       }
       lc[u] = below;
-      ucnt[u] = (e - s) - below;
+      ucnt[i] = (e - s) - below;
       deg[u] = d;
       mx = d > mx ? d : mx;
       sm += d;
@@ -149,13 +156,39 @@ __global__ void __launch_bounds__(BS)
         else hi = mid;
       }
       lc[u] = (int32_t)(lo - s);
-      ucnt[u] = e - lo;
+      ucnt[i] = e - lo;
       longmask |= 1u << i;
       nlong++;
     }
     bestA[u] = KEY_INF;
     bestB[u] = KEY_INF;
     parent[u] = (int32_t)u;
+  }
+  // uptr: exclusive prefix of the upper-entry counts in row order (the
+  // edge id of each row's first upper entry), block offsets chained by a
+  // decoupled look-back; the last block also stores uptr[n] = m
+  {
+    int64_t run = 0, pre[DEG_PER];
+#pragma unroll
+    for (int i = 0; i < DEG_PER; i++) {
+      int64_t tot;
+      int64_t inc = block_incl_scan<int64_t, BS, false>(ucnt[i], stmp64, &tot);
+      pre[i] = run + inc - ucnt[i];
+      run += tot;
+    }
+    if (tid < WAVE) {
+      uint64_t ex = lb_exclusive_wave(ts, blockIdx.x, (uint64_t)run);
+      if (tid == 0) {
+        sbase = (int64_t)ex;
+        if (blockIdx.x == gridDim.x - 1) uptr[g.n] = (int64_t)ex + run;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < DEG_PER; i++) {
+      int64_t u = base + i * BS + tid;
+      if (u < g.n) uptr[u] = sbase + pre[i];
+    }
   }
   // rows longer than DEG_SHORT: the whole block sums each of them, except
   // the first H_MAX rows longer than HUGE_T, which get a position map for
@@ -623,19 +656,22 @@ __global__ void __launch_bounds__(BS)
   }
 }
 
-// Guarded keys at the cutoff: every forest edge sharing the cutoff's K
-// bucket must have exactly the cutoff's score (then the edge order inside
-// the bucket is the exact one).
-__global__ void k_cutoff_check(const uint64_t* __restrict__ msfP, const unsigned long long* cnt,
-                               const SelState* st, const KeyND* __restrict__ keys,
-                               const uint64_t* __restrict__ kexact, const unsigned long long* guard,
-                               int ebits, int* viol) {
-  if (!*guard) return;
+// After the cutoff selection: the union-find array is reset to the
+// identity for the components pass, and with guarded keys every forest edge
+// sharing the cutoff's K bucket must have exactly the cutoff's score (then
+// the edge order inside the bucket is the exact one).  keys null: no check.
+__global__ void k_cutoff_prep(const uint64_t* __restrict__ msfP, const unsigned long long* cnt,
+                              const SelState* st, const KeyND* __restrict__ keys,
+                              const uint64_t* __restrict__ kexact, const unsigned long long* guard,
+                              int ebits, int* viol, int32_t* __restrict__ parent, int64_t nn) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t x = i0; x < nn; x += stride) parent[x] = (int32_t)x;
+  if (!keys || !*guard) return;
   int64_t n = (int64_t)*cnt;
   uint64_t T = st->prefix;
   uint64_t emask = (1ull << ebits) - 1;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+  for (int64_t i = i0; i < n; i += stride) {
     uint64_t p = msfP[i];
     if (p == T || (p >> ebits) != (T >> ebits)) continue;
     if (key_exact(kexact, p & emask) && key_exact(kexact, T & emask)) continue;   // equal scores
@@ -665,6 +701,8 @@ __global__ void k_cc_union(const uint64_t* __restrict__ msfP, const uint64_t* __
   }
 }
 
+// Every node's root, and a flag on each root (its number among the roots
+// in id order is the flags' exclusive scan).
 __global__ void k_cc_flatten(int32_t* parent, int32_t* __restrict__ root, int32_t* __restrict__ flag,
                              int64_t n) {
   int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -675,17 +713,6 @@ __global__ void k_cc_flatten(int32_t* parent, int32_t* __restrict__ root, int32_
   }
 }
 
-// Labels are clamped to [0, t): they are there by construction, and the
-// clamp keeps a later contraction in bounds should a check (done once the
-// host next reads the info block) fail.
-__global__ void k_relabel(const int32_t* __restrict__ root, const int32_t* __restrict__ cid,
-                          int32_t* __restrict__ cluster_of, int64_t n, int64_t t) {
-  int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x < n) {
-    int64_t c = cid[root[x]];
-    cluster_of[x] = (int32_t)(c < 0 ? 0 : c >= t ? t - 1 : c);
-  }
-}
 
 // ---------------------------------------------------------------------------
 // radix select (declared in prim.hpp)
@@ -738,10 +765,40 @@ __device__ __forceinline__ unsigned int col_part_sum(const unsigned int* a, int 
   return s;
 }
 
+// A band threshold derived from a selected sample key (thr null: none).
+// With c > 0 the level's key mode goes into info[I_GUARD] first (the packed
+// key is inexact for some pair of edges only when Dmax^2 > 2^c, Dmax =
+// largest d_u d_v).  Guarded keys order edges of one K bucket only
+// approximately, so there the band is widened to the end of the sample's K
+// bucket.  Samples are the keys of edges 0, s, 2s, ...; when the selected
+// one is edge eq = q s itself, the band is (most likely) one tied K bucket
+// read in edge order, i.e. a run of consecutive rows, whose forest has about
+// one edge per row rather than per candidate: such a band is extended to
+// edge e_tie (chosen to cover k rows).  Only the band's size changes.
+struct ThrSpec {
+  unsigned long long* thr;
+  unsigned long long* info;
+  int c, ebits;
+  unsigned long long eq, e_tie;
+};
+
+__device__ __forceinline__ void band_threshold(const ThrSpec& ts, uint64_t p, bool all) {
+  uint64_t emask = (1ull << ts.ebits) - 1;
+  if (ts.c > 0) {
+    unsigned __int128 D2 = (unsigned __int128)ts.info[I_DMAXE] * ts.info[I_DMAXE];
+    ts.info[I_GUARD] = ((D2 >> 64) != 0 || D2 > ((unsigned __int128)1 << ts.c)) ? 1ull : 0ull;
+  }
+  bool widen = ts.info[I_GUARD] != 0;
+  if (all) *ts.thr = KEY_INF;
+  else if (widen) *ts.thr = p | emask;
+  else if ((p & emask) == ts.eq && ts.e_tie > (p & emask)) *ts.thr = (p & ~emask) | (ts.e_tie & emask);
+  else *ts.thr = p;
+}
+
 __global__ void __launch_bounds__(SEL_BS)
     k_select(const uint64_t* __restrict__ keys, const unsigned long long* cnt_dev, int64_t cnt_host,
              const unsigned long long* k_dev, unsigned long long k_host, int bits, SelState* st,
-             unsigned long long* flags, unsigned long long epoch0, unsigned long long* err) {
+             unsigned long long* flags, unsigned long long epoch0, unsigned long long* err, ThrSpec tsp) {
   static_assert(SEL_NGRP * 8 == SEL_BS && SEL_GBINS * 4 == SEL_BS, "pick layout");
   __shared__ unsigned int h[SEL_BINS];
   __shared__ uint64_t sbuf[SEL_SMALL];
@@ -840,6 +897,7 @@ __global__ void __launch_bounds__(SEL_BS)
         if (B == 0 && t == 0) {
           __hip_atomic_store(err, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           st->prefix = ~0ull;
+          if (tsp.thr) band_threshold(tsp, ~0ull, false);
         }
         return;
       }
@@ -894,6 +952,7 @@ __global__ void __launch_bounds__(SEL_BS)
     if (B == 0 && t == 0) {
       st->prefix = prefix;
       st->mask = mask;
+      if (tsp.thr) band_threshold(tsp, prefix, false);
     }
     return;
   }
@@ -901,7 +960,12 @@ __global__ void __launch_bounds__(SEL_BS)
   if (t == 0) slocal = 0;
   __syncthreads();
   if (G == 1) {
-    // every key matches: copy them in order
+    // every key matches: copy them in order (the host sized this launch
+    // for at most SEL_SMALL keys)
+    if (n > SEL_SMALL) {
+      if (t == 0) __hip_atomic_store(err, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      n = SEL_SMALL;
+    }
     constexpr int PER = 16;
     for (int c0 = 0; c0 < n; c0 += PER * SEL_BS) {
       uint64_t v[PER];
@@ -921,6 +985,7 @@ __global__ void __launch_bounds__(SEL_BS)
     if (t == 0) {
       st->prefix = r;
       st->mask = ~0ull;
+      if (tsp.thr) band_threshold(tsp, r, false);
     }
     return;
   }
@@ -971,12 +1036,14 @@ __global__ void __launch_bounds__(SEL_BS)
   if (t == 0) {
     st->prefix = r;
     st->mask = ~0ull;
+    if (tsp.thr) band_threshold(tsp, r, false);
   }
 }
 
 int radix_select(spc_ctx* ctx, const uint64_t* keys, const unsigned long long* cnt_dev,
                  int64_t cnt_bound, const unsigned long long* k_dev, unsigned long long k_host,
-                 int bits, SelState* st, unsigned long long* flags, unsigned long long* err) {
+                 int bits, SelState* st, unsigned long long* flags, unsigned long long* err,
+                 const ThrSpec* thr) {
   unsigned long long epoch0 = ctx->sel_epoch;
   ctx->sel_epoch += 64;   // a select meets at most 2 + 64 / SEL_DIGIT times
   // 32 keys per thread and pass up to SEL_MAXB blocks (a barrier's cost
@@ -985,7 +1052,7 @@ int radix_select(spc_ctx* ctx, const uint64_t* keys, const unsigned long long* c
   int grid = cnt_bound <= SEL_SMALL ? 1 : grid_for(cnt_bound, SEL_BS * 32, maxb);
   if (grid < 2 && cnt_bound > SEL_SMALL) grid = 2;
   hipLaunchKernelGGL(k_select, dim3(grid), dim3(SEL_BS), 0, ctx->stream, keys, cnt_dev, cnt_bound, k_dev,
-                     k_host, bits, st, flags, epoch0, err);
+                     k_host, bits, st, flags, epoch0, err, thr ? *thr : ThrSpec{nullptr, nullptr, 0, 1, 0, 0});
   SPC_LAUNCH_CHECK(ctx, "radix_select");
   return SPC_OK;
 }
@@ -1033,32 +1100,8 @@ __global__ void k_fill_u64(uint64_t* __restrict__ a, int64_t n, uint64_t v) {
   if (i < n) a[i] = v;
 }
 
-// upper threshold of a band: the selected sample key, or "everything".
-// Guarded keys order edges of one K bucket only approximately, so there the
-// band is widened to the end of the sample's K bucket.
-// Samples are the keys of edges 0, s, 2s, ...; when the q-th smallest is
-// edge eq = q s itself, the band is (most likely) one tied K bucket read in
-// edge order, i.e. a run of consecutive rows, whose forest has about one
-// edge per row rather than per candidate.  Such a band is extended to edge
-// e_tie (chosen by the caller to cover k rows); only the band's size changes.
-// With c > 0 it first decides the level's key mode into info[I_GUARD]
-// (the packed key is inexact for some pair of edges only when
-// Dmax^2 > 2^c, Dmax = largest d_u d_v).
-__global__ void k_thr_from_sel(const SelState* st, unsigned long long* thr, int all, int ebits,
-                               unsigned long long* info, int c, unsigned long long eq,
-                               unsigned long long e_tie) {
-  uint64_t emask = (1ull << ebits) - 1;
-  uint64_t p = st->prefix;
-  if (c > 0) {
-    unsigned __int128 D2 = (unsigned __int128)info[I_DMAXE] * info[I_DMAXE];
-    info[I_GUARD] = ((D2 >> 64) != 0 || D2 > ((unsigned __int128)1 << c)) ? 1ull : 0ull;
-  }
-  bool widen = info[I_GUARD] != 0;
-  if (all) *thr = KEY_INF;
-  else if (widen) *thr = p | emask;
-  else if ((p & emask) == eq && e_tie > (p & emask)) *thr = (p & ~emask) | (e_tie & emask);
-  else *thr = p;
-}
+// a band threshold without a selection ("everything")
+__global__ void k_thr_all(ThrSpec ts) { band_threshold(ts, 0, true); }
 
 // Info block (and up to three scalars) to the pinned host copy, then wait.
 static int sync_info(spc_ctx* ctx, const LevelWork& W, const int64_t* x0 = nullptr,
@@ -1232,29 +1275,26 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
       hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(1), 0, st, thr_lo, thr_hi);
     }
     if (all) {
-      hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits, info, kc, 0ull,
-                         0ull);
+      hipLaunchKernelGGL(k_thr_all, dim3(1), dim3(1), 0, st, ThrSpec{thr_hi, info, kc, ebits, 0, 0});
     } else if (!rank) {
       int sh = sample_shift(m);
       int64_t ns = ((m - 1) >> sh) + 1;
       int64_t q = (int64_t)((double)target / (double)(1ll << sh) * 1.05) + 16;
       if (q >= ns) {
         all = true;
-        hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 1, ebits, info, kc, 0ull,
-                         0ull);
+        hipLaunchKernelGGL(k_thr_all, dim3(1), dim3(1), 0, st, ThrSpec{thr_hi, info, kc, ebits, 0, 0});
       } else {
         TimedScope ts(ctx, "select_threshold", (double)ns);
-        int rc = radix_select(ctx, W.samples, nullptr, ns, nullptr, (unsigned long long)q, 64, W.sel,
-                              (unsigned long long*)W.selflag, &info[I_LBERR]);
-        if (rc) return rc;
         // a tied band of consecutive rows needs about k rows: k m / n edges
         uint64_t e_tie = 0;
         if (band == 0) {
           double rows = 1.1 * (double)k * (double)m / (double)n + 4096.0;
           e_tie = rows >= (double)(m - 1) ? (uint64_t)(m - 1) : (uint64_t)rows;
         }
-        hipLaunchKernelGGL(k_thr_from_sel, dim3(1), dim3(1), 0, st, W.sel, thr_hi, 0, ebits, info, kc,
-                           (unsigned long long)q << sh, (unsigned long long)e_tie);
+        ThrSpec tsp{thr_hi, info, kc, ebits, (unsigned long long)q << sh, (unsigned long long)e_tie};
+        int rc = radix_select(ctx, W.samples, nullptr, ns, nullptr, (unsigned long long)q, 64, W.sel,
+                              (unsigned long long*)W.selflag, &info[I_LBERR], &tsp);
+        if (rc) return rc;
       }
     } else {
       hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, thr_hi, (unsigned long long)(target - 1));
@@ -1289,15 +1329,16 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
   {
     TimedScope ts(ctx, "select_cutoff", (double)R.msf);
     int bits = rank ? bitlen64((uint64_t)(m - 1)) : 64;
-    int rc = radix_select(ctx, W.msfP, &info[I_MSF], n, nullptr, (unsigned long long)(k - 1), bits,
+    // sized for the forest's record count, which the host read last
+    int64_t nf = R.msf > 1 ? R.msf : 1;
+    int rc = radix_select(ctx, W.msfP, &info[I_MSF], nf, nullptr, (unsigned long long)(k - 1), bits,
                           W.sel2, (unsigned long long*)W.selflag, &info[I_LBERR]);
     if (rc) return rc;
   }
-  if (!rank) {
-    hipLaunchKernelGGL(k_cutoff_check, dim3(grid_for(R.msf, 256, ctx->num_cus * 4)), dim3(256), 0, st,
-                       W.msfP, &info[I_MSF], W.sel2, W.keysA, W.kexact, guard, ebits, (int*)&info[I_VIOL]);
-    SPC_LAUNCH_CHECK(ctx, "cutoff check");
-  }
+  hipLaunchKernelGGL(k_cutoff_prep, dim3(grid_for(n > R.msf ? n : R.msf, 256)), dim3(256), 0, st, W.msfP,
+                     &info[I_MSF], W.sel2, rank ? (const KeyND*)nullptr : (const KeyND*)W.keysA, W.kexact, guard,
+                     ebits, (int*)&info[I_VIOL], W.parent, n);
+  SPC_LAUNCH_CHECK(ctx, "cutoff check");
   return SPC_OK;
 }
 
@@ -1325,7 +1366,7 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
     {
       TimedScope ts(ctx, "degree", (double)n);
       hipLaunchKernelGGL(k_degree, dim3(nb), dim3(BS), 0, st, g, W.deg, W.lc, W.uptr, W.bestA, W.bestB,
-                         W.parent, W.degpart, W.htab, info);
+                         W.parent, W.degpart, W.htab, info, next_scan(ctx, W));
     }
     TimedScope ts(ctx, "degree_total", (double)nb);
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(SP_BS), 0, st, W.degpart, (int64_t)nb, g, W.htab, W.deg,
@@ -1333,7 +1374,9 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
   }
   SPC_LAUNCH_CHECK(ctx, "degree");
   int rc;
-  {
+  if (gf) {
+    // the floating-point degree pass leaves upper-entry counts (the integer
+    // one stores their prefix itself)
     TimedScope ts(ctx, "scan_upper", (double)n);
     rc = exclusive_scan<int64_t>(ctx, W.uptr, W.uptr, n, (int64_t*)W.scan_partial);
     if (rc) return rc;
@@ -1367,8 +1410,9 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
     if (rc) return rc;
     {
       TimedScope ts(ctx, "components", (double)n);
-      hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256)), dim3(256), 0, st, W.parent, n);
       if (seg) {
+        // (the whole-graph path reset parent in its cutoff check)
+        hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256)), dim3(256), 0, st, W.parent, n);
         int ebits = bitlen64((uint64_t)(m - 1));
         rc = seg_cutoff_union(ctx, g, W, R, *seg, ebits < 1 ? 1 : ebits, rank);
         if (rc) return rc;
@@ -1382,19 +1426,18 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
     SPC_LAUNCH_CHECK(ctx, "components");
     {
       TimedScope ts(ctx, "relabel", (double)n);
+      // labels: the scan leaves the number of roots in flag[n]
       rc = exclusive_scan<int32_t>(ctx, W.flag, W.flag, n, (int32_t*)W.scan_partial);
       if (rc) return rc;
-      hipLaunchKernelGGL(k_relabel, dim3(grid_for(n, 256)), dim3(256), 0, st, W.root, W.flag,
-                         cluster_of, n, t);
+      launch_relabel_eps(ctx, g, W, cluster_of, t, gf || seg ? 0 : R.msf, !gf && !seg);
     }
     if (gf) launch_eps_fp(ctx, W);
-    else if (!seg) launch_eps(ctx, g, W, R.msf);
     if (ctx->force_redo_rank && !rank)
       hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, &info[I_VIOL], 1ull);
     SPC_LAUNCH_CHECK(ctx, "relabel");
     if (defer) {
       // labels are in [0, t) whatever the key mode: the cutoff joins exactly
-      // k forest edges (keys are distinct), and k_relabel clamps besides
+      // k forest edges (keys are distinct), and the labelling clamps besides
       R.pending = true;
       R.pending_rank = rank;
       R.n_c = t;
