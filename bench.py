@@ -60,16 +60,27 @@ def make_config(name):
 # Algorithmic HBM bytes of a kernel over one level: the data it must move at
 # least once (inputs read once, outputs written once), from the level's sizes
 # and work counters.  Per-launch figures divide by the launches per level.
+def sample_count(m):
+    """Key samples of a level with m edges: one per 2^s edges, s >= 6 the
+    smallest with at most 4096 samples (the library's sample_shift)."""
+    s = 6
+    while (m >> s) > 4096:
+        s += 1
+    return ((m - 1) >> s) + 1 if m > 0 else 0
+
+
 def algo_bytes(kernel, L):
     n, m, nnz, n_c, nnz_c, selfb = L["n"], L["m"], 2 * L["m"], L["n_c"], L["nnz_c"], L["self"]
     if kernel == "score":
         # CSR col + w of both rows once (8 B per entry), per-node row_ptr,
         # degree, lower count, upper prefix (28 B), self-loops at coarse
-        # levels; writes the key of both CSR entries of every edge, one
-        # sample per 64 edges, and the exact records when they are kept
+        # levels; writes the key of both CSR entries of every edge, the key
+        # samples, the exactness map (1 bit per edge) and the exact records
+        # when they are kept
         if L["key_mode"] == "rank":
             return None
-        return 8 * nnz + 28 * n + 8 * n * selfb + 16 * m + 8 * ((m + 63) // 64) + 24 * m * L["keys_written"]
+        return (8 * nnz + 28 * n + 8 * n * selfb + 16 * m + 8 * sample_count(m) + m // 8
+                + 24 * m * L["keys_written"])
     if kernel == "rowpass":
         # every band reads each entry's key and column and the row pointers;
         # the first band writes each node's lightest key; kept edges are
