@@ -126,6 +126,9 @@ int spc_set_allocator(spc_ctx* ctx, void* (*alloc)(size_t, void*), void (*free_)
  *   "redo_rank"   1: treat every packed-key level as if one of its guarded
  *                 decisions had failed, so that it is redone with rank keys
  *                 (the fallback path).
+ *   "bad_select_guess" 1: give the merge cutoff's selection key bounds that
+ *                 some forest keys lie outside, so that it starts over (the
+ *                 selection's fallback path).
  *   "timing"      1: record a HIP event pair on the context stream around
  *                 every kernel launch, for spc_timing_report.
  * Unknown names return SPC_EINVAL. */

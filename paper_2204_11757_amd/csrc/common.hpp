@@ -313,6 +313,7 @@ struct spc_ctx {
   int force_full_filter = 0; // run the spanning-forest phase over every edge
   int force_huge_sort = 0;   // contract huge rows by sorting even when dense accumulators fit
   int force_redo_rank = 0;   // flag every packed-key level as inexact (redone with rank keys)
+  int force_bad_guess = 0;   // give the cutoff selection key bounds that some keys lie outside
   // per-kernel timing: events recorded around launches on the context stream
   int timing = 0;
   std::vector<hipEvent_t> ev_pool;

@@ -238,7 +238,7 @@ constexpr int SEL_FLAG = 8;      // flag stride (one 64-byte line per block)
 
 struct SelState {
   unsigned long long prefix, mask;
-  unsigned long long pad[2];
+  unsigned long long ext[2];   // smallest and largest key (written by the one-block path)
   unsigned long long bmn[2][SEL_MAXB], bmx[2][SEL_MAXB];   // extreme matching keys per block
   unsigned int gsum[2][SEL_MAXB][SEL_NGRP];          // per-block group sums, pass p in [p % 2]
   unsigned int bhist[2][SEL_MAXB][SEL_BINS];         // per-block histograms
@@ -250,12 +250,16 @@ struct SelState {
 // undefined).  flags: SEL_MAXB * SEL_FLAG words, zeroed when ctx->sel_epoch
 // was last reset to 0; every select of that period uses epochs above the
 // previous one's.  thr (nullable): also derive a band threshold from the
-// selected key, in the same launch.
+// selected key, in the same launch.  guess_lo / guess_hi (nullable, device
+// words): likely bounds of the keys; the bits they share are taken as
+// decided for the first pass, which counts the keys that share them and
+// starts over without the guess when that is not every key.
 struct ThrSpec;
 int radix_select(spc_ctx* ctx, const uint64_t* keys, const unsigned long long* cnt_dev,
                  int64_t cnt_bound, const unsigned long long* k_dev, unsigned long long k_host,
                  int bits, SelState* st, unsigned long long* flags, unsigned long long* err,
-                 const ThrSpec* thr = nullptr);
+                 const ThrSpec* thr = nullptr, const unsigned long long* guess_lo = nullptr,
+                 const unsigned long long* guess_hi = nullptr);
 
 // Small launches that replace the runtime's fill and copy blits on the
 // level path (each blit costs the host far more than a plain launch).

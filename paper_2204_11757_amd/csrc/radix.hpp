@@ -69,13 +69,15 @@ __device__ __forceinline__ void block_minmax(uint64_t& mn, uint64_t& mx, unsigne
 // LDS_SMALL2 keys they are copied to s2 and later rounds read only those;
 // every copy or rescan also finds the bucket's smallest and largest key, so
 // bits they share are skipped again.  h needs SEL_BS * 8 counters, s2
-// LDS_SMALL2 keys.
+// LDS_SMALL2 keys.  ext (nullable): thread 0 stores the smallest and largest
+// key there.
 constexpr int LDS_SMALL2 = 1024;
 
 __device__ __forceinline__ uint64_t lds_select(const uint64_t* s, int c, unsigned long long k, unsigned int* h,
                                                unsigned long long* tmp, unsigned long long* red,
                                                unsigned long long* spick, unsigned long long* err,
-                                               uint64_t* s2, unsigned int* scount) {
+                                               uint64_t* s2, unsigned int* scount,
+                                               unsigned long long* ext = nullptr) {
   constexpr int PER = 8;
   constexpr int DIG = 11;
   constexpr int U = 8;   // keys per thread whose LDS loads are issued together
@@ -111,6 +113,10 @@ __device__ __forceinline__ uint64_t lds_select(const uint64_t* s, int c, unsigne
   };
   uint64_t mn, mx;
   extremes(mn, mx);
+  if (ext && t == 0) {
+    ext[0] = mn;
+    ext[1] = mx;
+  }
   while (true) {
     uint64_t x = mn ^ mx;
     if (x == 0) return mn;   // every key in play is equal

@@ -798,7 +798,8 @@ __device__ __forceinline__ void band_threshold(const ThrSpec& ts, uint64_t p, bo
 __global__ void __launch_bounds__(SEL_BS)
     k_select(const uint64_t* __restrict__ keys, const unsigned long long* cnt_dev, int64_t cnt_host,
              const unsigned long long* k_dev, unsigned long long k_host, int bits, SelState* st,
-             unsigned long long* flags, unsigned long long epoch0, unsigned long long* err, ThrSpec tsp) {
+             unsigned long long* flags, unsigned long long epoch0, unsigned long long* err, ThrSpec tsp,
+             const unsigned long long* guess_lo, const unsigned long long* guess_hi) {
   static_assert(SEL_NGRP * 8 == SEL_BS && SEL_GBINS * 4 == SEL_BS, "pick layout");
   __shared__ unsigned int h[SEL_BINS];
   __shared__ uint64_t sbuf[SEL_SMALL];
@@ -820,8 +821,23 @@ __global__ void __launch_bounds__(SEL_BS)
   int64_t cb = n;   // keys matching (prefix, mask)
   unsigned long long bstar = 0;   // bucket chosen by the last pass
   int p = 0;
+  bool guessed = false, again = false;
+  if (G > 1 && guess_lo && guess_hi) {
+    uint64_t lo = *guess_lo, hk = *guess_hi;
+    if (lo < hk) {
+      int d = 63 - __clzll((long long)(lo ^ hk));   // highest bit the bounds differ in
+      if (d + 1 < hi) {
+        uint64_t low = (2ull << d) - 1;
+        prefix = lo & ~low;
+        mask = ~low;
+        hi = d + 1;
+        guessed = true;
+      }
+    }
+  }
   if (G > 1) {
-    for (; p == 0 || (cb > SEL_SMALL && hi > 0); p++) {
+    for (; p == 0 || again || (cb > SEL_SMALL && hi > 0); p++) {
+      again = false;
       int lo = hi - SEL_DIGIT > 0 ? hi - SEL_DIGIT : 0;
       int nb = 1 << (hi - lo);
       uint64_t dm = (uint64_t)(nb - 1);
@@ -885,6 +901,21 @@ __global__ void __launch_bounds__(SEL_BS)
       }
       unsigned long long total;
       unsigned long long before = block_incl_scan<unsigned long long, SEL_BS, false>(gc, tmp, &total) - gc;
+      if (guessed) {
+        guessed = false;
+        if (total != (unsigned long long)n) {
+          // some key lies outside the guessed bounds: a pass again over
+          // every key (uniform: every block read the same total), into the
+          // other histogram buffers, which no block still reads
+          prefix = 0;
+          mask = 0;
+          hi = bits;
+          cb = n;
+          again = true;
+          __syncthreads();
+          continue;
+        }
+      }
       if (t == 0) spick[0] = ~0ull;
       __syncthreads();
       if (gc && k >= before && k < before + gc) {
@@ -981,7 +1012,7 @@ __global__ void __launch_bounds__(SEL_BS)
       }
     }
     __syncthreads();
-    uint64_t r = lds_select(sbuf, (int)n, k, h, tmp, red, spick, err, s2, &s2cnt);
+    uint64_t r = lds_select(sbuf, (int)n, k, h, tmp, red, spick, err, s2, &s2cnt, st->ext);
     if (t == 0) {
       st->prefix = r;
       st->mask = ~0ull;
@@ -1043,7 +1074,7 @@ __global__ void __launch_bounds__(SEL_BS)
 int radix_select(spc_ctx* ctx, const uint64_t* keys, const unsigned long long* cnt_dev,
                  int64_t cnt_bound, const unsigned long long* k_dev, unsigned long long k_host,
                  int bits, SelState* st, unsigned long long* flags, unsigned long long* err,
-                 const ThrSpec* thr) {
+                 const ThrSpec* thr, const unsigned long long* guess_lo, const unsigned long long* guess_hi) {
   unsigned long long epoch0 = ctx->sel_epoch;
   ctx->sel_epoch += 64;   // a select meets at most 2 + 64 / SEL_DIGIT times
   // 32 keys per thread and pass up to SEL_MAXB blocks (a barrier's cost
@@ -1052,7 +1083,8 @@ int radix_select(spc_ctx* ctx, const uint64_t* keys, const unsigned long long* c
   int grid = cnt_bound <= SEL_SMALL ? 1 : grid_for(cnt_bound, SEL_BS * 32, maxb);
   if (grid < 2 && cnt_bound > SEL_SMALL) grid = 2;
   hipLaunchKernelGGL(k_select, dim3(grid), dim3(SEL_BS), 0, ctx->stream, keys, cnt_dev, cnt_bound, k_dev,
-                     k_host, bits, st, flags, epoch0, err, thr ? *thr : ThrSpec{nullptr, nullptr, 0, 1, 0, 0});
+                     k_host, bits, st, flags, epoch0, err, thr ? *thr : ThrSpec{nullptr, nullptr, 0, 1, 0, 0},
+                     guess_lo, guess_hi);
   SPC_LAUNCH_CHECK(ctx, "radix_select");
   return SPC_OK;
 }
@@ -1262,6 +1294,7 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
   unsigned long long* thr_hi = &info[I_NC];
   int64_t target = k + k / 2 + 4096;
   int64_t done_cand = 0;
+  bool sampled = false;   // a band threshold came from the key samples
   R.candidates = 0;
   for (int band = 0;; band++) {
     // a batch builds the whole forest in one band (each graph needs its own
@@ -1295,6 +1328,7 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
         int rc = radix_select(ctx, W.samples, nullptr, ns, nullptr, (unsigned long long)q, 64, W.sel,
                               (unsigned long long*)W.selflag, &info[I_LBERR], &tsp);
         if (rc) return rc;
+        sampled = true;
       }
     } else {
       hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, thr_hi, (unsigned long long)(target - 1));
@@ -1331,8 +1365,15 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
     int bits = rank ? bitlen64((uint64_t)(m - 1)) : 64;
     // sized for the forest's record count, which the host read last
     int64_t nf = R.msf > 1 ? R.msf : 1;
+    // forest keys lie at or below the last band's threshold, and most
+    // likely at or above the smallest key sample (checked by the selection)
+    const unsigned long long* glo = sampled && !rank ? &W.sel->ext[0] : nullptr;
+    // (a test option substitutes the band's selected sample, above many
+    // forest keys, so that the selection takes its start-over path)
+    if (glo && ctx->force_bad_guess) glo = &W.sel->prefix;
     int rc = radix_select(ctx, W.msfP, &info[I_MSF], nf, nullptr, (unsigned long long)(k - 1), bits,
-                          W.sel2, (unsigned long long*)W.selflag, &info[I_LBERR]);
+                          W.sel2, (unsigned long long*)W.selflag, &info[I_LBERR], nullptr, glo,
+                          glo ? thr_hi : nullptr);
     if (rc) return rc;
   }
   hipLaunchKernelGGL(k_cutoff_prep, dim3(grid_for(n > R.msf ? n : R.msf, 256)), dim3(256), 0, st, W.msfP,

@@ -22,6 +22,7 @@ def P():
     spc.set_option("full_forest", 0)
     spc.set_option("huge_sort", 0)
     spc.set_option("redo_rank", 0)
+    spc.set_option("bad_select_guess", 0)
 
 
 def say(*a):
@@ -143,6 +144,19 @@ def test_inexact_key_fallback_redoes_the_level(P):
         P.set_option("redo_rank", 0)
     st = check_level(P, g, g.n // 2, "trimesh-60 packed again")
     assert st.key_mode == 0
+
+
+def test_cutoff_selection_start_over(P):
+    # the merge cutoff's selection starts from bounds guessed from the key
+    # samples; keys outside them make it start over, which must not change
+    # anything (forests of more than 16,384 edges take the multi-block path)
+    try:
+        P.set_option("bad_select_guess", 1)
+        g = trimesh(160, ("uniform", 1, 8), seed=23)
+        check_hierarchy(P, g, g.n // 16, 0, "trimesh-160 bad cutoff guess")
+        check_level(P, grid3d(32, ("uniform", 1, 16), seed=8), 8192, "grid3d-32 bad cutoff guess")
+    finally:
+        P.set_option("bad_select_guess", 0)
 
 
 def test_huge_rows_sort_and_dense_paths(P):
