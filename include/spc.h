@@ -129,6 +129,11 @@ int spc_set_allocator(spc_ctx* ctx, void* (*alloc)(size_t, void*), void (*free_)
  *   "bad_select_guess" 1: give the merge cutoff's selection key bounds that
  *                 some forest keys lie outside, so that it starts over (the
  *                 selection's fallback path).
+ *   "contract_wait" how the contraction launches its row-class kernels:
+ *                 0 (default) as the previous level's classes suggest, 1
+ *                 always after reading the class counts on the host, 2
+ *                 always on counts the kernels read from device memory
+ *                 (when the huge rows' accumulators fit).
  *   "timing"      1: record a HIP event pair on the context stream around
  *                 every kernel launch, for spc_timing_report.
  * Unknown names return SPC_EINVAL. */

@@ -419,6 +419,10 @@ int spc_set_option(spc_ctx* ctx, const char* name, int64_t value) {
   else if (!strcmp(name, "huge_sort")) ctx->force_huge_sort = value ? 1 : 0;
   else if (!strcmp(name, "redo_rank")) ctx->force_redo_rank = value ? 1 : 0;
   else if (!strcmp(name, "bad_select_guess")) ctx->force_bad_guess = value ? 1 : 0;
+  else if (!strcmp(name, "contract_wait")) {
+    if (value < 0 || value > 2) return set_error(ctx, SPC_EINVAL, "contract_wait takes 0, 1 or 2");
+    ctx->contract_wait = (int)value;
+  }
   else return set_error(ctx, SPC_EINVAL, "unknown option '%s'", name);
   return SPC_OK;
 }

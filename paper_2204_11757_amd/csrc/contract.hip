@@ -329,6 +329,7 @@ __global__ void __launch_bounds__(SMALL_BS)
         nhuge++;
         self_out[a] = 0;
         size_out[a] = 0;
+        cnt[a] = 0;   // until the huge-row pass writes it
       }
       continue;
     }
@@ -385,11 +386,12 @@ __global__ void __launch_bounds__(SMALL_BS)
 __global__ void __launch_bounds__(SMALL_BS)
     k_contract_reg32(LevelIn g, const int32_t* __restrict__ c, const int32_t* __restrict__ mptr,
                      const int32_t* __restrict__ members, const int64_t* __restrict__ gptr,
-                     const int32_t* __restrict__ rows, int64_t nrows, uint64_t* __restrict__ temp,
-                     int64_t* __restrict__ cnt, int64_t* __restrict__ self_out,
+                     const int32_t* __restrict__ rows, int64_t nrows, const unsigned long long* nrows_dev,
+                     uint64_t* __restrict__ temp, int64_t* __restrict__ cnt, int64_t* __restrict__ self_out,
                      int32_t* __restrict__ size_out) {
-  int64_t i = (int64_t)blockIdx.x * SMALL_BS + threadIdx.x;
-  if (i < nrows)
+  // (with nrows_dev the count is read here and the grid strides over it)
+  int64_t nr = nrows_dev ? (int64_t)*nrows_dev : nrows;
+  for (int64_t i = (int64_t)blockIdx.x * SMALL_BS + threadIdx.x; i < nr; i += (int64_t)gridDim.x * SMALL_BS)
     contract_row_regs<REG32_CAP>(g, c, mptr, members, gptr, temp, cnt, self_out, size_out, rows[i]);
 }
 
@@ -398,8 +400,8 @@ template <int TB, int CAP>
 __global__ void __launch_bounds__(TB)
     k_contract_row(LevelIn g, const int32_t* __restrict__ c, const int32_t* __restrict__ mptr,
                    const int32_t* __restrict__ members, const int64_t* __restrict__ gptr,
-                   const int32_t* __restrict__ rowlist, uint64_t* __restrict__ temp,
-                   int64_t* __restrict__ cnt, int64_t* __restrict__ self_out,
+                   const int32_t* __restrict__ rowlist, const unsigned long long* nrows_dev,
+                   uint64_t* __restrict__ temp, int64_t* __restrict__ cnt, int64_t* __restrict__ self_out,
                    int32_t* __restrict__ size_out) {
   __shared__ uint64_t ent[CAP];
   __shared__ int lcnt;
@@ -407,7 +409,11 @@ __global__ void __launch_bounds__(TB)
   __shared__ int lsize;
   __shared__ int32_t stmp[TB / WAVE];
   int tid = threadIdx.x;
-  int32_t a = rowlist[blockIdx.x];
+  // one row per block, or (nrows_dev: the count is read here) the blocks
+  // stride over the rows
+  int64_t nr = nrows_dev ? (int64_t)*nrows_dev : (int64_t)gridDim.x;
+  for (int64_t r = blockIdx.x; r < nr; r += gridDim.x) {
+  int32_t a = rowlist[r];
   if (tid == 0) {
     lcnt = 0;
     lself = 0;
@@ -483,6 +489,8 @@ __global__ void __launch_bounds__(TB)
     self_out[a] = (int64_t)lself;
     size_out[a] = lsize;
   }
+  __syncthreads();   // the next row reuses the block's LDS
+  }
 }
 
 // ---- rows with more than BLOCK_CAP gathered entries ------------------------
@@ -493,12 +501,26 @@ struct LessKW {
   __device__ __forceinline__ bool operator()(const KW& a, const KW& b) const { return a.key < b.key; }
 };
 
+// hcount[h] = members of huge row h, for h < H.  With H_dev (the count in
+// device memory, launch bound H), rows past that count get 0, and a count
+// above the bound sets *over and leaves every entry 0.
 __global__ void k_huge_members_count(const int32_t* __restrict__ hugelist, int64_t H,
-                                     const int32_t* __restrict__ mptr, int64_t* __restrict__ hcount) {
+                                     const int32_t* __restrict__ mptr, int64_t* __restrict__ hcount,
+                                     const unsigned long long* H_dev, unsigned long long* over) {
   int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (h < H) {
+  int64_t Hn = H;
+  if (H_dev) {
+    Hn = (int64_t)*H_dev;
+    if (Hn > H) {
+      if (h == 0) *over = 1;
+      Hn = 0;
+    }
+  }
+  if (h < Hn) {
     int32_t a = hugelist[h];
     hcount[h] = mptr[a + 1] - mptr[a];
+  } else if (h < H) {
+    hcount[h] = 0;
   }
 }
 
@@ -529,12 +551,19 @@ __global__ void __launch_bounds__(HMB_BS)
     k_huge_members(LevelIn g, const int32_t* __restrict__ hugelist, const int32_t* __restrict__ mptr,
                    const int32_t* __restrict__ members, const int64_t* __restrict__ hoff, int64_t H,
                    int64_t bound, int64_t* __restrict__ hlen, int32_t* __restrict__ hrow,
-                   int64_t* __restrict__ hrs, int64_t* self_out, int32_t* size_out) {
+                   int64_t* __restrict__ hrs, int64_t* self_out, int32_t* size_out,
+                   const unsigned long long* H_dev) {
   __shared__ unsigned long long sself[HMB_T];
   __shared__ int32_t ssize[HMB_T];
   __shared__ int32_t sh0;
   int tid = threadIdx.x;
   int64_t i0 = (int64_t)blockIdx.x * HMB_T;
+  if (H_dev) {
+    // the count in device memory; above the launch bound H nothing is done
+    // (k_huge_members_count flagged it and left hoff all 0)
+    int64_t Hn = (int64_t)*H_dev;
+    H = Hn <= H ? Hn : 0;
+  }
   int64_t HM = hoff[H];
   if (i0 >= HM) {
     for (int k = tid; k < HMB_T; k += HMB_BS)
@@ -738,10 +767,15 @@ __global__ void __launch_bounds__(DC_BS)
     k_dense_compact(const uint32_t* __restrict__ dense, int64_t ncp, int64_t n_c, int64_t tpr,
                     const int32_t* __restrict__ hugelist, const int64_t* __restrict__ gptr,
                     uint64_t* __restrict__ temp, int64_t* cnt, TileScan ts,
-                    const int32_t* __restrict__ base) {
+                    const int32_t* __restrict__ base, const unsigned long long* H_dev, int64_t H) {
   __shared__ int stmp[DC_BS / WAVE];
   __shared__ unsigned long long sbase;
   int64_t h = blockIdx.x / tpr, t = blockIdx.x % tpr;
+  if (H_dev) {
+    // rows past the count in device memory (or all, above the bound H)
+    unsigned long long Hn = *H_dev;
+    if (Hn > (unsigned long long)H || h >= (int64_t)Hn) return;
+  }
   int32_t a = hugelist[h];
   int64_t cb = base ? base[h] : 0;   // column of the window's first slot
   n_c -= cb;                          // slots past the last coarse node stay unused
@@ -856,6 +890,163 @@ __global__ void __launch_bounds__(PACK_BS)
   }
 }
 
+// Rows of the register, wavefront and block classes.  With dev the class
+// counts stay in device memory (the kernels read them; grids cover a bound),
+// otherwise hinfo holds them.
+static int contract_classes(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c, spc_graph_out* out,
+                            LevelWork& W, bool dev) {
+  hipStream_t st = ctx->stream;
+  int64_t* hinfo = ctx->h_pinned;
+  unsigned long long* info = W.info;
+  int64_t* self_out = (int64_t*)out->self_w;
+  int64_t nr32 = dev ? 0 : hinfo[I_R32], nmid = dev ? 0 : hinfo[I_MID], nblk = dev ? 0 : hinfo[I_BLOCK];
+  int64_t cap = (int64_t)ctx->num_cus * 8;
+  if (dev || nr32 > 0) {
+    TimedScope ts(ctx, "contract_reg32", (double)nr32);
+    int64_t gr = dev ? std::min((int64_t)grid_for(n_c, SMALL_BS), cap) : (int64_t)grid_for(nr32, SMALL_BS);
+    hipLaunchKernelGGL(k_contract_reg32, dim3((unsigned)gr), dim3(SMALL_BS), 0, st, g, c, W.mptr, W.members,
+                       W.gptr, W.r32list, nr32, dev ? &info[I_R32] : nullptr, W.temp, W.cnt, self_out, out->size);
+    SPC_LAUNCH_CHECK(ctx, "contract reg32");
+  }
+  if (dev || nmid > 0) {
+    TimedScope ts(ctx, "contract_wave_rows", (double)nmid);
+    int64_t gr = dev ? std::min(n_c, cap * 4) : nmid;
+    hipLaunchKernelGGL((k_contract_row<WAVE, WAVE_CAP>), dim3((unsigned)gr), dim3(WAVE), 0, st, g, c, W.mptr,
+                       W.members, W.gptr, W.midlist, dev ? &info[I_MID] : nullptr, W.temp, W.cnt, self_out,
+                       out->size);
+    SPC_LAUNCH_CHECK(ctx, "contract wave rows");
+  }
+  if (dev || nblk > 0) {
+    TimedScope ts(ctx, "contract_block_rows", (double)nblk);
+    int64_t gr = dev ? std::min(n_c, cap) : nblk;
+    hipLaunchKernelGGL((k_contract_row<256, BLOCK_CAP>), dim3((unsigned)gr), dim3(256), 0, st, g, c, W.mptr,
+                       W.members, W.gptr, W.blocklist, dev ? &info[I_BLOCK] : nullptr, W.temp, W.cnt, self_out,
+                       out->size);
+    SPC_LAUNCH_CHECK(ctx, "contract block rows");
+  }
+  return SPC_OK;
+}
+
+// Rows with more than BLOCK_CAP gathered entries ("huge").  H rows, or with
+// dev at most H (the count in device memory; above H the kernels do nothing
+// and set info[I_HOVER]); dev always takes the dense path, which the caller
+// checked fits for H rows.
+static int contract_huge(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c, spc_graph_out* out,
+                         LevelWork& W, const Segments* seg, int64_t H, bool dev) {
+  hipStream_t st = ctx->stream;
+  int64_t n = g.n;
+  int64_t* hinfo = ctx->h_pinned;
+  unsigned long long* info = W.info;
+  int64_t* self_out = (int64_t*)out->self_w;
+  const unsigned long long* Hd = dev ? &info[I_HUGE] : nullptr;
+  int rc;
+  TimedScope ts(ctx, "contract_huge", (double)H);
+  hipLaunchKernelGGL(k_huge_members_count, dim3(grid_for(H, 256)), dim3(256), 0, st, W.hugelist, H, W.mptr,
+                     W.hmoff, Hd, &info[I_HOVER]);
+  rc = exclusive_scan<int64_t>(ctx, W.hmoff, W.hmoff, H, (int64_t*)W.scan_partial);
+  if (rc) return rc;
+  // member and entry totals stay on the device: launches cover bounds
+  // (n members, nnz entries) and read the totals there
+  int64_t* hpre = W.hpos;   // member row lengths, then their prefix
+  hipLaunchKernelGGL(k_huge_members, dim3(grid_for(n, HMB_T)), dim3(HMB_BS), 0, st, g, W.hugelist, W.mptr,
+                     W.members, W.hmoff, H, n, hpre, W.hmrow, W.hmrs, self_out, out->size, Hd);
+  rc = exclusive_scan<int64_t>(ctx, hpre, hpre, n, (int64_t*)W.scan_partial);
+  if (rc) return rc;
+  // few huge rows: dense accumulators over the coarse ids (they fit in
+  // the gather buffers when H * ncp <= 2 nnz)
+  // (in a batch, per huge row only the coarse range of its own graph)
+  int64_t win = seg ? seg->wmax : n_c;
+  int64_t ncp = (win + DC_T - 1) / DC_T * DC_T;
+  if (dev || (!ctx->force_huge_sort && H * ncp <= 2 * g.nnz)) {
+    uint32_t* dense = (uint32_t*)W.gkeyA;
+    int32_t* base = nullptr;
+    if (seg) {
+      base = W.hmnode;   // free on this path
+      hipLaunchKernelGGL(k_huge_base, dim3(grid_for(H, 256)), dim3(256), 0, st, W.hugelist, H, seg->coff,
+                         seg->G, base);
+    }
+    launch_clear(ctx, (int32_t*)dense, H * ncp, nullptr, 0, nullptr, 0u);
+    if (g.nnz > HD_SMALL_NNZ)
+      hipLaunchKernelGGL(k_huge_dense<HT>, dim3(grid_for(g.nnz, HT)), dim3(HT_BS), 0, st, g, c, W.hugelist,
+                         W.hmrow, W.hmrs, hpre, n, self_out, dense, ncp, (const int32_t*)base,
+                         &info[I_DENSE]);
+    else if (g.nnz > 0)
+      hipLaunchKernelGGL(k_huge_dense<1024>, dim3(grid_for(g.nnz, 1024)), dim3(HT_BS), 0, st, g, c,
+                         W.hugelist, W.hmrow, W.hmrs, hpre, n, self_out, dense, ncp, (const int32_t*)base,
+                         &info[I_DENSE]);
+    int64_t tpr = ncp / DC_T;
+    hipLaunchKernelGGL(k_dense_compact, dim3((unsigned)(H * tpr)), dim3(DC_BS), 0, st, dense, ncp, n_c,
+                       tpr, W.hugelist, W.gptr, W.temp, W.cnt, next_scan(ctx, W), (const int32_t*)base, Hd, H);
+    SPC_LAUNCH_CHECK(ctx, "huge dense");
+    return SPC_OK;
+  }
+  launch_clear(ctx, nullptr, 0, nullptr, 0, info, 1u << I_LIVE1);
+  KW* A = (KW*)W.gkeyA;
+  KW* B = (KW*)W.gkeyB;
+  if (g.nnz > 0) {
+    hipLaunchKernelGGL(k_huge_entries, dim3(grid_for(g.nnz, HT)), dim3(HT_BS), 0, st, g, c, W.hugelist,
+                       W.hmrow, W.hmrs, hpre, n, self_out, A, &info[I_LIVE1], next_scan(ctx, W));
+    SPC_LAUNCH_CHECK(ctx, "huge gather");
+  }
+  hipLaunchKernelGGL(k_readback, dim3(1), dim3(64), 0, st, (const unsigned long long*)nullptr, 0,
+                     (const int64_t*)&info[I_LIVE1], (const int32_t*)nullptr, (const uint64_t*)nullptr,
+                     hinfo);
+  SPC_LAUNCH_CHECK(ctx, "readback");
+  SPC_HIP(ctx, hipStreamSynchronize(st));
+  int64_t G = hinfo[I_NINFO];
+  KW* sorted = A;
+  if (G > 0) {
+    rc = merge_sort<KW, LessKW>(ctx, A, B, G, LessKW(), &sorted);
+    if (rc) return rc;
+  }
+  // scratch in the other buffer: scanned weights, head ranks, head starts
+  char* scratch = (char*)(sorted == A ? B : A);
+  uint64_t* wx = (uint64_t*)scratch;
+  int32_t* pos = (int32_t*)(wx + G + 1);
+  int32_t* hstart = pos + G + 1;
+  int32_t* rowfirst = W.hmrow;
+  int32_t* rowlast = W.hmnode;
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(H, 256)), dim3(256), 0, st, rowlast, H, -1);
+  if (G > 0) {
+    hipLaunchKernelGGL(k_head_flags, dim3(grid_for(G, 256)), dim3(256), 0, st, sorted, G, pos, wx);
+    rc = exclusive_scan<int32_t>(ctx, pos, pos, G, (int32_t*)W.scan_partial);
+    if (rc) return rc;
+    rc = exclusive_scan<uint64_t>(ctx, wx, wx, G, (uint64_t*)W.scan_partial);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_head_index, dim3(grid_for(G, 256)), dim3(256), 0, st, sorted, G, pos, hstart);
+    hipLaunchKernelGGL(k_huge_rowfirst, dim3(grid_for(G, 256)), dim3(256), 0, st, sorted, G, pos,
+                       rowfirst, rowlast);
+    hipLaunchKernelGGL(k_huge_reduce, dim3(grid_for(G, 256)), dim3(256), 0, st, sorted, G, pos,
+                       hstart, wx, W.hugelist, rowfirst, W.gptr, W.temp);
+  }
+  hipLaunchKernelGGL(k_huge_counts, dim3(grid_for(H, 256)), dim3(256), 0, st, W.hugelist, H, rowfirst,
+                     rowlast, W.cnt);
+  SPC_LAUNCH_CHECK(ctx, "huge reduce");
+  return SPC_OK;
+}
+
+// Coarse row pointer from the row counts, then the info block, the entry
+// total and the look-back error flags to the host.
+static int rowptr_and_read(spc_ctx* ctx, const LevelWork& W, spc_graph_out* out, int64_t n_c,
+                           const int32_t* x1) {
+  {
+    TimedScope ts(ctx, "contract_rowptr", (double)n_c);
+    int rc = exclusive_scan<int64_t>(ctx, W.cnt, out->row_ptr, n_c, (int64_t*)W.scan_partial);
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(k_readback, dim3(1), dim3(64), 0, ctx->stream, W.info, (int)I_NINFO,
+                     (const int64_t*)(out->row_ptr + n_c), x1,
+                     (const uint64_t*)(ctx->scan_state ? ctx->scan_state + ctx->scan_cap - 1 : nullptr),
+                     ctx->h_pinned);
+  SPC_LAUNCH_CHECK(ctx, "readback");
+  SPC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return SPC_OK;
+}
+
+// At most this many huge rows take the path without a host wait after the
+// small rows (their dense accumulators are cleared for all of them).
+constexpr int64_t H_DEV = 4;
+
 int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c,
                    spc_graph_out* out, LevelWork& W, LevelResult& R, const Segments* seg) {
   hipStream_t st = ctx->stream;
@@ -867,7 +1058,8 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
   {
     TimedScope ts(ctx, "contract_members", (double)n);
     launch_clear(ctx, W.mcount, n_c + 1, (uint64_t*)W.gptr, n_c + 1, info,
-                 (1u << I_MID) | (1u << I_HUGE) | (1u << I_MAXCL) | (1u << I_BLOCK) | (1u << I_R32));
+                 (1u << I_MID) | (1u << I_HUGE) | (1u << I_MAXCL) | (1u << I_BLOCK) | (1u << I_R32) |
+                     (1u << I_HOVER));
     hipLaunchKernelGGL(k_cluster_count, dim3(grid_for(n, CM_BS)), dim3(CM_BS), 0, st, g, c, W.mcount,
                        (unsigned long long*)W.gptr);
     SPC_LAUNCH_CHECK(ctx, "cluster_count");
@@ -897,130 +1089,60 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
                          out->size, n_c, W.r32list, W.midlist, W.blocklist, W.hugelist, info, tsc);
   }
   SPC_LAUNCH_CHECK(ctx, "contract_small");
-  // with a deferred selection, this read also carries its super-node count
-  hipLaunchKernelGGL(k_readback, dim3(1), dim3(64), 0, st, info, (int)I_NINFO, (const int64_t*)nullptr,
-                     R.pending ? (const int32_t*)(W.flag + n) : (const int32_t*)nullptr,
-                     (const uint64_t*)nullptr, hinfo);
-  SPC_LAUNCH_CHECK(ctx, "readback");
-  SPC_HIP(ctx, hipStreamSynchronize(st));
-  if (R.pending) {
-    rc = finish_select(ctx, R, n_c, R.pending_rank, false, seg);
+  // with a deferred selection, the first read also carries its super-node count
+  const int32_t* x1 = R.pending ? (const int32_t*)(W.flag + n) : (const int32_t*)nullptr;
+  int64_t ncp1 = (n_c + DC_T - 1) / DC_T * DC_T;
+  // without the wait when the last level had a few huge rows and few rows
+  // of the wavefront and block classes (their kernels then stride over
+  // device-held counts on bounded grids, which is slower for many rows)
+  bool dev = !seg && !ctx->force_huge_sort && ctx->contract_wait != 1 && H_DEV * ncp1 <= 2 * g.nnz &&
+             (ctx->contract_wait == 2 || ctx->contract_dev);
+  if (dev) {
+    // the class lists and up to H_DEV huge rows run on counts the device
+    // holds; the one host wait is the coarse row pointer's
+    rc = contract_classes(ctx, g, c, n_c, out, W, true);
     if (rc) return rc;
-  }
-  int64_t nr32 = hinfo[I_R32], nmid = hinfo[I_MID], nblk = hinfo[I_BLOCK], H = hinfo[I_HUGE];
-  R.maxcl = hinfo[I_MAXCL];
-  if (nr32 > 0) {
-    TimedScope ts(ctx, "contract_reg32", (double)nr32);
-    hipLaunchKernelGGL(k_contract_reg32, dim3(grid_for(nr32, SMALL_BS)), dim3(SMALL_BS), 0, st, g, c,
-                       W.mptr, W.members, W.gptr, W.r32list, nr32, W.temp, W.cnt, self_out, out->size);
-    SPC_LAUNCH_CHECK(ctx, "contract reg32");
-  }
-  if (nmid > 0) {
-    TimedScope ts(ctx, "contract_wave_rows", (double)nmid);
-    hipLaunchKernelGGL((k_contract_row<WAVE, WAVE_CAP>), dim3((unsigned)nmid), dim3(WAVE), 0, st, g, c,
-                       W.mptr, W.members, W.gptr, W.midlist, W.temp, W.cnt, self_out, out->size);
-    SPC_LAUNCH_CHECK(ctx, "contract wave rows");
-  }
-  if (nblk > 0) {
-    TimedScope ts(ctx, "contract_block_rows", (double)nblk);
-    hipLaunchKernelGGL((k_contract_row<256, BLOCK_CAP>), dim3((unsigned)nblk), dim3(256), 0, st, g, c,
-                       W.mptr, W.members, W.gptr, W.blocklist, W.temp, W.cnt, self_out, out->size);
-    SPC_LAUNCH_CHECK(ctx, "contract block rows");
-  }
-  if (H > 0) {
-    TimedScope ts(ctx, "contract_huge", (double)H);
-    hipLaunchKernelGGL(k_huge_members_count, dim3(grid_for(H, 256)), dim3(256), 0, st, W.hugelist, H,
-                       W.mptr, W.hmoff);
-    rc = exclusive_scan<int64_t>(ctx, W.hmoff, W.hmoff, H, (int64_t*)W.scan_partial);
+    rc = contract_huge(ctx, g, c, n_c, out, W, seg, H_DEV, true);
     if (rc) return rc;
-    // member and entry totals stay on the device: launches cover bounds
-    // (n members, nnz entries) and read the totals there
-    int64_t* hpre = W.hpos;   // member row lengths, then their prefix
-    hipLaunchKernelGGL(k_huge_members, dim3(grid_for(n, HMB_T)), dim3(HMB_BS), 0, st, g, W.hugelist, W.mptr,
-                       W.members, W.hmoff, H, n, hpre, W.hmrow, W.hmrs, self_out, out->size);
-    rc = exclusive_scan<int64_t>(ctx, hpre, hpre, n, (int64_t*)W.scan_partial);
+    rc = rowptr_and_read(ctx, W, out, n_c, x1);
     if (rc) return rc;
-    // few huge rows: dense accumulators over the coarse ids (they fit in
-    // the gather buffers when H * ncp <= 2 nnz)
-    // (in a batch, per huge row only the coarse range of its own graph)
-    int64_t win = seg ? seg->wmax : n_c;
-    int64_t ncp = (win + DC_T - 1) / DC_T * DC_T;
-    if (!ctx->force_huge_sort && H * ncp <= 2 * g.nnz) {
-      uint32_t* dense = (uint32_t*)W.gkeyA;
-      int32_t* base = nullptr;
-      if (seg) {
-        base = W.hmnode;   // free on this path
-        hipLaunchKernelGGL(k_huge_base, dim3(grid_for(H, 256)), dim3(256), 0, st, W.hugelist, H, seg->coff,
-                           seg->G, base);
-      }
-      launch_clear(ctx, (int32_t*)dense, H * ncp, nullptr, 0, nullptr, 0u);
-      if (g.nnz > HD_SMALL_NNZ)
-        hipLaunchKernelGGL(k_huge_dense<HT>, dim3(grid_for(g.nnz, HT)), dim3(HT_BS), 0, st, g, c, W.hugelist,
-                           W.hmrow, W.hmrs, hpre, n, self_out, dense, ncp, (const int32_t*)base,
-                           &info[I_DENSE]);
-      else if (g.nnz > 0)
-        hipLaunchKernelGGL(k_huge_dense<1024>, dim3(grid_for(g.nnz, 1024)), dim3(HT_BS), 0, st, g, c,
-                           W.hugelist, W.hmrow, W.hmrs, hpre, n, self_out, dense, ncp, (const int32_t*)base,
-                           &info[I_DENSE]);
-      int64_t tpr = ncp / DC_T;
-      hipLaunchKernelGGL(k_dense_compact, dim3((unsigned)(H * tpr)), dim3(DC_BS), 0, st, dense, ncp, n_c,
-                         tpr, W.hugelist, W.gptr, W.temp, W.cnt, next_scan(ctx, W), (const int32_t*)base);
-      SPC_LAUNCH_CHECK(ctx, "huge dense");
-    } else {
-    launch_clear(ctx, nullptr, 0, nullptr, 0, info, 1u << I_LIVE1);
-    KW* A = (KW*)W.gkeyA;
-    KW* B = (KW*)W.gkeyB;
-    if (g.nnz > 0) {
-      hipLaunchKernelGGL(k_huge_entries, dim3(grid_for(g.nnz, HT)), dim3(HT_BS), 0, st, g, c, W.hugelist,
-                         W.hmrow, W.hmrs, hpre, n, self_out, A, &info[I_LIVE1], next_scan(ctx, W));
-      SPC_LAUNCH_CHECK(ctx, "huge gather");
+    if (R.pending) {
+      rc = finish_select(ctx, R, n_c, R.pending_rank, false, seg);
+      if (rc) return rc;
     }
-    hipLaunchKernelGGL(k_readback, dim3(1), dim3(64), 0, st, (const unsigned long long*)nullptr, 0,
-                       (const int64_t*)&info[I_LIVE1], (const int32_t*)nullptr, (const uint64_t*)nullptr,
-                       hinfo);
+    if (hinfo[I_HOVER]) {
+      // more huge rows than H_DEV: they were left alone; the host knows how
+      // many now
+      int64_t H = hinfo[I_HUGE];
+      rc = contract_huge(ctx, g, c, n_c, out, W, seg, H, false);
+      if (rc) return rc;
+      rc = rowptr_and_read(ctx, W, out, n_c, nullptr);
+      if (rc) return rc;
+    }
+  } else {
+    hipLaunchKernelGGL(k_readback, dim3(1), dim3(64), 0, st, info, (int)I_NINFO, (const int64_t*)nullptr, x1,
+                       (const uint64_t*)nullptr, hinfo);
     SPC_LAUNCH_CHECK(ctx, "readback");
     SPC_HIP(ctx, hipStreamSynchronize(st));
-    int64_t G = hinfo[I_NINFO];
-    KW* sorted = A;
-    if (G > 0) {
-      rc = merge_sort<KW, LessKW>(ctx, A, B, G, LessKW(), &sorted);
+    if (R.pending) {
+      rc = finish_select(ctx, R, n_c, R.pending_rank, false, seg);
       if (rc) return rc;
     }
-    // scratch in the other buffer: scanned weights, head ranks, head starts
-    char* scratch = (char*)(sorted == A ? B : A);
-    uint64_t* wx = (uint64_t*)scratch;
-    int32_t* pos = (int32_t*)(wx + G + 1);
-    int32_t* hstart = pos + G + 1;
-    int32_t* rowfirst = W.hmrow;
-    int32_t* rowlast = W.hmnode;
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(H, 256)), dim3(256), 0, st, rowlast, H, -1);
-    if (G > 0) {
-      hipLaunchKernelGGL(k_head_flags, dim3(grid_for(G, 256)), dim3(256), 0, st, sorted, G, pos, wx);
-      rc = exclusive_scan<int32_t>(ctx, pos, pos, G, (int32_t*)W.scan_partial);
+    int64_t H = hinfo[I_HUGE];
+    rc = contract_classes(ctx, g, c, n_c, out, W, false);
+    if (rc) return rc;
+    if (H > 0) {
+      rc = contract_huge(ctx, g, c, n_c, out, W, seg, H, false);
       if (rc) return rc;
-      rc = exclusive_scan<uint64_t>(ctx, wx, wx, G, (uint64_t*)W.scan_partial);
-      if (rc) return rc;
-      hipLaunchKernelGGL(k_head_index, dim3(grid_for(G, 256)), dim3(256), 0, st, sorted, G, pos, hstart);
-      hipLaunchKernelGGL(k_huge_rowfirst, dim3(grid_for(G, 256)), dim3(256), 0, st, sorted, G, pos,
-                         rowfirst, rowlast);
-      hipLaunchKernelGGL(k_huge_reduce, dim3(grid_for(G, 256)), dim3(256), 0, st, sorted, G, pos,
-                         hstart, wx, W.hugelist, rowfirst, W.gptr, W.temp);
     }
-    hipLaunchKernelGGL(k_huge_counts, dim3(grid_for(H, 256)), dim3(256), 0, st, W.hugelist, H, rowfirst,
-                       rowlast, W.cnt);
-    SPC_LAUNCH_CHECK(ctx, "huge reduce");
-    }
-  }
-  {
-    TimedScope ts(ctx, "contract_rowptr", (double)n_c);
-    rc = exclusive_scan<int64_t>(ctx, W.cnt, out->row_ptr, n_c, (int64_t*)W.scan_partial);
+    rc = rowptr_and_read(ctx, W, out, n_c, nullptr);
     if (rc) return rc;
   }
-  hipLaunchKernelGGL(k_readback, dim3(1), dim3(64), 0, st, info, (int)I_NINFO,
-                     (const int64_t*)(out->row_ptr + n_c), (const int32_t*)nullptr,
-                     (const uint64_t*)(ctx->scan_state ? ctx->scan_state + ctx->scan_cap - 1 : nullptr), hinfo);
-  SPC_LAUNCH_CHECK(ctx, "readback");
-  SPC_HIP(ctx, hipStreamSynchronize(st));
+  R.maxcl = hinfo[I_MAXCL];
+  {
+    int64_t H = hinfo[I_HUGE];
+    ctx->contract_dev = H >= 1 && H <= H_DEV && hinfo[I_MID] + hinfo[I_BLOCK] <= 8192 && hinfo[I_R32] <= 65536;
+  }
   int64_t nnz_c = hinfo[I_NINFO];
   if (hinfo[I_DENSE]) return set_error(ctx, SPC_EINVAL, "internal: a huge row left its graph's coarse range");
   if (hinfo[I_LBERR] || hinfo[I_NINFO + 2])

@@ -139,6 +139,7 @@ enum Info : int {
   I_SEG_SHORT = 27, // batch: a graph has fewer forest edges than merges needed
   I_CAND = 28,    // live edges the band's row pass produced (a copy of I_LIVE0)
   I_DENSE = 29,   // a dense row accumulator index fell outside its window (internal error)
+  I_HOVER = 30,   // more huge contraction rows than the path without a host wait takes
   I_NINFO = 32
 };
 

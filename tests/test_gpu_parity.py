@@ -23,6 +23,7 @@ def P():
     spc.set_option("huge_sort", 0)
     spc.set_option("redo_rank", 0)
     spc.set_option("bad_select_guess", 0)
+    spc.set_option("contract_wait", 0)
 
 
 def say(*a):
@@ -157,6 +158,34 @@ def test_cutoff_selection_start_over(P):
         check_level(P, grid3d(32, ("uniform", 1, 16), seed=8), 8192, "grid3d-32 bad cutoff guess")
     finally:
         P.set_option("bad_select_guess", 0)
+
+
+def interleaved_grids(copies, side):
+    """copies disjoint side x side grids with node x of copy i numbered
+    copies * x + i, so that tied merges in edge order reach every copy."""
+    g = grid2d(side)
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    up = g.col > rows
+    u, v, w = rows[up], g.col[up], g.w[up]
+    U = np.concatenate([u * copies + i for i in range(copies)])
+    V = np.concatenate([v * copies + i for i in range(copies)])
+    return from_edges(g.n * copies, U, V, np.concatenate([w] * copies).astype(np.int32))
+
+
+def test_contraction_class_counts_on_device_and_host(P):
+    # the contraction's row classes run on counts the device holds, with up
+    # to four huge rows; six giant super-nodes (one per grid) exceed that and
+    # take the fallback that reads the counts first; the option that always
+    # reads them first, and the adaptive default, must agree as well
+    g = interleaved_grids(6, 64)
+    try:
+        for flag in (2, 1, 0):
+            P.set_option("contract_wait", flag)
+            check_hierarchy(P, g, g.n // 16, 0, f"6 interleaved grid2d-64, contract_wait={flag}")
+            check_hierarchy(P, trimesh(90, ("uniform", 1, 8), seed=31), 800, 0,
+                            f"trimesh-90, contract_wait={flag}")
+    finally:
+        P.set_option("contract_wait", 0)
 
 
 def test_huge_rows_sort_and_dense_paths(P):
