@@ -129,6 +129,11 @@ int spc_set_allocator(spc_ctx* ctx, void* (*alloc)(size_t, void*), void (*free_)
  *   "bad_select_guess" 1: give the merge cutoff's selection key bounds that
  *                 some forest keys lie outside, so that it starts over (the
  *                 selection's fallback path).
+ *   "speculate"   whether the host waits for the first batch of spanning-
+ *                 forest rounds: 0 (default) not when the previous level's
+ *                 forest was complete after it, 1 always, 2 never (and that
+ *                 batch is one round, so a longer forest takes the path that
+ *                 redoes the level waiting).
  *   "contract_wait" how the contraction launches its row-class kernels:
  *                 0 (default) as the previous level's classes suggest, 1
  *                 always after reading the class counts on the host, 2

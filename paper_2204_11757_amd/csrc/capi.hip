@@ -206,7 +206,10 @@ static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* clus
   // synchronisation (one wait per level fewer); a batch waits, since a graph
   // short of forest edges leaves more super-nodes than the target
   bool defer = !fp && !seg && t < g->n;
-  rc = select_level(ctx, L, t, cluster_of, W, R, fp ? &LF : nullptr, seg, defer);
+  // nor for the first forest batch when the last level's forest was complete
+  // after it, in one band
+  bool spec = defer && (ctx->speculate == 2 || (ctx->speculate == 0 && ctx->spec_ok));
+  rc = select_level(ctx, L, t, cluster_of, W, R, fp ? &LF : nullptr, seg, defer, false, spec);
   if (rc) return rc;
   if (fp && R.n_c == g->n) {
     if (out->nnz_cap < g->nnz) return set_error(ctx, SPC_ECAPACITY, "nnz_cap too small");
@@ -242,6 +245,13 @@ static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* clus
     R.maxcl = 1;
   } else {
     rc = contract_level(ctx, L, cluster_of, R.n_c, out, W, R, seg);
+    if (rc == SPC_REDO_SPEC) {
+      // the forest needed more than its first batch: the level again, waiting
+      R = LevelResult();
+      rc = select_level(ctx, L, t, cluster_of, W, R, nullptr, seg, defer, false, false);
+      if (rc) return rc;
+      rc = contract_level(ctx, L, cluster_of, R.n_c, out, W, R, seg);
+    }
     if (rc == SPC_REDO_RANK) {
       // a guarded key decision failed: the level again with rank keys
       R = LevelResult();
@@ -419,7 +429,10 @@ int spc_set_option(spc_ctx* ctx, const char* name, int64_t value) {
   else if (!strcmp(name, "huge_sort")) ctx->force_huge_sort = value ? 1 : 0;
   else if (!strcmp(name, "redo_rank")) ctx->force_redo_rank = value ? 1 : 0;
   else if (!strcmp(name, "bad_select_guess")) ctx->force_bad_guess = value ? 1 : 0;
-  else if (!strcmp(name, "contract_wait")) {
+  else if (!strcmp(name, "speculate")) {
+    if (value < 0 || value > 2) return set_error(ctx, SPC_EINVAL, "speculate takes 0, 1 or 2");
+    ctx->speculate = (int)value;
+  } else if (!strcmp(name, "contract_wait")) {
     if (value < 0 || value > 2) return set_error(ctx, SPC_EINVAL, "contract_wait takes 0, 1 or 2");
     ctx->contract_wait = (int)value;
   }
@@ -466,6 +479,7 @@ int spc_timing_report(spc_ctx* ctx, char* buf, size_t cap) {
 int spc_coarsen_level(spc_ctx* ctx, const spc_graph* g, int64_t n_target, int32_t* cluster_of,
                       spc_graph_out* coarse, int64_t* nnz_c, spc_level_stats* st) {
   if (!ctx) return SPC_EINVAL;
+  ctx->spec_ok = 0;   // a new graph: its first level waits for its forest
   return level_impl(ctx, g, n_target, cluster_of, coarse, nnz_c, st);
 }
 
@@ -473,6 +487,7 @@ int spc_coarsen_to(spc_ctx* ctx, const spc_graph* g, int64_t n_c, int schedule, 
   if (!ctx) return SPC_EINVAL;
   if (!out) return set_error(ctx, SPC_EINVAL, "out is NULL");
   *out = nullptr;
+  ctx->spec_ok = 0;   // a new graph: its first level waits for its forest
   int rc = check_graph(ctx, g);
   if (rc) return rc;
   if (n_c < 1) return set_error(ctx, SPC_EINVAL, "n_c must be >= 1");

@@ -140,6 +140,7 @@ enum Info : int {
   I_CAND = 28,    // live edges the band's row pass produced (a copy of I_LIVE0)
   I_DENSE = 29,   // a dense row accumulator index fell outside its window (internal error)
   I_HOVER = 30,   // more huge contraction rows than the path without a host wait takes
+  I_SPEC = 31,    // live edges left after the first forest batch (checked later when not waited for)
   I_NINFO = 32
 };
 
@@ -255,11 +256,19 @@ struct LevelResult {
   // the selection's checks wait for the contraction's first synchronisation
   // (n_c is the target until then); rank: the labels came from rank keys
   bool pending = false, pending_rank = false;
+  // spec: the host did not wait for the first forest batch (the forest was
+  // assumed complete, with at least k edges); checked with the others
+  bool spec = false;
+  int64_t k = 0;       // merges of the level
+  bool first_batch_complete = false;
 };
 
-// internal return code (never reaches the caller): a guarded key decision
-// failed after a deferred check, the level is redone with rank keys
+// internal return codes (never reach the caller): a guarded key decision
+// failed after a deferred check, the level is redone with rank keys; the
+// forest was not complete after its first batch (or had too few edges)
+// although the host did not wait for it, the level is redone waiting
 constexpr int SPC_REDO_RANK = 1;
+constexpr int SPC_REDO_SPEC = 2;
 
 // A2 and A3 launches (score.hip).  mode 0: packed keys into Pc and the
 // samples (exact records too when the key is not surely exact); mode 1:
@@ -304,12 +313,15 @@ int seg_cutoff_union(spc_ctx* ctx, const LevelIn& g, LevelWork& W, const LevelRe
 // With defer, the host does not wait for the labels: R.pending is set and
 // finish_select runs at the contraction's first synchronisation; with
 // rank_only the level starts in rank-key mode.
+// With speculate (only with defer) the host does not wait for the first
+// forest batch either.
 int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of, LevelWork& W,
                  LevelResult& R, const LevelInF* gf = nullptr, const Segments* seg = nullptr,
-                 bool defer = false, bool rank_only = false);
+                 bool defer = false, bool rank_only = false, bool speculate = false);
 // Checks and results of the selection from the host copy of the info block
 // (super-node count in slot I_NINFO + 1): SPC_OK, an error, or
-// SPC_REDO_RANK when packed keys took an inexact decision.
+// SPC_REDO_RANK when packed keys took an inexact decision, SPC_REDO_SPEC
+// when a forest the host did not wait for turned out incomplete.
 int finish_select(spc_ctx* ctx, LevelResult& R, int64_t t, bool rank, bool fp, const Segments* seg);
 
 // Step A5: contraction of Definition 1 into caller buffers.

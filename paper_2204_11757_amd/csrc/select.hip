@@ -1172,7 +1172,8 @@ static int check_total(spc_ctx* ctx) {
 // past the device-side count return at once).  On return the host copy of
 // the info block is current.
 static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, bool fused_first,
-                           const KeyND* guard_keys, int ebits, int64_t& live0) {
+                           const KeyND* guard_keys, int ebits, int64_t& live0, bool speculate,
+                           bool& first_complete) {
   unsigned long long* info = W.info;
   int64_t* hinfo = ctx->h_pinned;
   int rc;
@@ -1202,7 +1203,7 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, boo
     // the first batch issues as many rounds as the previous level needed
     // (each round past convergence is three empty launches, each batch a
     // host wait); later batches two
-    int rounds = batch == 0 ? ctx->forest_batch : 2;
+    int rounds = batch == 0 ? (speculate && ctx->speculate == 2 ? 1 : ctx->forest_batch) : 2;
     for (int r = 0; r < rounds; r++) {
       int out = in ^ 1;
       int ci = in == 0 ? I_LIVE0 : I_LIVE1;
@@ -1230,6 +1231,13 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, boo
       nxt = t;
       in = out;
     }
+    if (speculate) {
+      // no wait: the live edges left go to info[I_SPEC] for a later check
+      hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(1), 0, ctx->stream, &info[I_SPEC],
+                         &info[in == 0 ? I_LIVE0 : I_LIVE1]);
+      live0 = 0;
+      return SPC_OK;
+    }
     rc = sync_info(ctx, W);
     if (rc) return rc;
     if (batch == 0) {
@@ -1239,6 +1247,7 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, boo
     }
     if (hinfo[I_LBERR]) return set_error(ctx, SPC_EINVAL, "internal: look-back wait gave up");
     bound = hinfo[in == 0 ? I_LIVE0 : I_LIVE1];
+    if (batch == 0) first_complete = bound == 0;
   }
   return SPC_OK;
 }
@@ -1249,7 +1258,7 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, boo
 // decision failed.
 static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k, int64_t m,
                             bool rank, LevelWork& W, LevelResult& R, const LevelInF* gf,
-                            const Segments* seg) {
+                            const Segments* seg, bool speculate) {
   hipStream_t st = ctx->stream;
   int64_t n = g.n;
   unsigned long long* info = W.info;
@@ -1341,11 +1350,21 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
     }
     SPC_LAUNCH_CHECK(ctx, "rowpass");
     int64_t live0 = 0;
-    int rc = spanning_forest(ctx, W, n, m, band == 0, gk, ebits, live0);
+    bool spec = speculate && band == 0 && !seg;
+    bool first_complete = false;
+    int rc = spanning_forest(ctx, W, n, m, band == 0, gk, ebits, live0, spec, first_complete);
     if (rc) return rc;
+    R.bands = band + 1;
+    if (spec) {
+      // assumed complete with at least k edges; counts come with the
+      // level's later read
+      R.spec = true;
+      R.msf = -1;
+      break;
+    }
+    if (band == 0) R.first_batch_complete = first_complete;
     done_cand += live0;
     R.candidates = done_cand;
-    R.bands = band + 1;
     R.msf = hinfo[I_MSF];
     if (seg || R.msf >= k) break;
     if (all)
@@ -1363,8 +1382,8 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
   {
     TimedScope ts(ctx, "select_cutoff", (double)R.msf);
     int bits = rank ? bitlen64((uint64_t)(m - 1)) : 64;
-    // sized for the forest's record count, which the host read last
-    int64_t nf = R.msf > 1 ? R.msf : 1;
+    // sized for the forest's record count when the host read it (else for n)
+    int64_t nf = R.spec ? n : R.msf > 1 ? R.msf : 1;
     // forest keys lie at or below the last band's threshold, and most
     // likely at or above the smallest key sample (checked by the selection)
     const unsigned long long* glo = sampled && !rank ? &W.sel->ext[0] : nullptr;
@@ -1376,7 +1395,7 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
                           glo ? thr_hi : nullptr);
     if (rc) return rc;
   }
-  hipLaunchKernelGGL(k_cutoff_prep, dim3(grid_for(n > R.msf ? n : R.msf, 256)), dim3(256), 0, st, W.msfP,
+  hipLaunchKernelGGL(k_cutoff_prep, dim3(grid_for(n, 256)), dim3(256), 0, st, W.msfP,
                      &info[I_MSF], W.sel2, rank ? (const KeyND*)nullptr : (const KeyND*)W.keysA, W.kexact, guard,
                      ebits, (int*)&info[I_VIOL], W.parent, n);
   SPC_LAUNCH_CHECK(ctx, "cutoff check");
@@ -1384,7 +1403,8 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
 }
 
 int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of, LevelWork& W,
-                 LevelResult& R, const LevelInF* gf, const Segments* seg, bool defer, bool rank_only) {
+                 LevelResult& R, const LevelInF* gf, const Segments* seg, bool defer, bool rank_only,
+                 bool speculate) {
   if (seg && gf)
     return set_error(ctx, SPC_EINVAL, "batched coarsening takes integer weights");
   hipStream_t st = ctx->stream;
@@ -1447,8 +1467,10 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestA, n, KEY_INF);
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestB, n, KEY_INF);
     }
-    rc = order_and_select(ctx, g, t, k, m, rank, W, R, gf, seg);
+    R.k = k;
+    rc = order_and_select(ctx, g, t, k, m, rank, W, R, gf, seg, speculate && defer && pass == 0);
     if (rc) return rc;
+    int64_t msf_bound = R.msf >= 0 ? R.msf : n;
     {
       TimedScope ts(ctx, "components", (double)n);
       if (seg) {
@@ -1458,7 +1480,7 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
         rc = seg_cutoff_union(ctx, g, W, R, *seg, ebits < 1 ? 1 : ebits, rank);
         if (rc) return rc;
       } else {
-        hipLaunchKernelGGL(k_cc_union, dim3(grid_for(R.msf, 256, ctx->num_cus * 8)), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_cc_union, dim3(grid_for(msf_bound, 256, ctx->num_cus * 8)), dim3(256), 0, st,
                            W.msfP, W.msfO, &info[I_MSF], W.sel2, W.parent);
       }
       hipLaunchKernelGGL(k_cc_flatten, dim3(grid_for(n, 256)), dim3(256), 0, st, W.parent, W.root,
@@ -1470,7 +1492,7 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
       // labels: the scan leaves the number of roots in flag[n]
       rc = exclusive_scan<int32_t>(ctx, W.flag, W.flag, n, (int32_t*)W.scan_partial);
       if (rc) return rc;
-      launch_relabel_eps(ctx, g, W, cluster_of, t, gf || seg ? 0 : R.msf, !gf && !seg);
+      launch_relabel_eps(ctx, g, W, cluster_of, t, gf || seg ? 0 : msf_bound, !gf && !seg);
     }
     if (gf) launch_eps_fp(ctx, W);
     if (ctx->force_redo_rank && !rank)
@@ -1495,6 +1517,22 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
 int finish_select(spc_ctx* ctx, LevelResult& R, int64_t t, bool rank, bool fp, const Segments* seg) {
   int64_t* hinfo = ctx->h_pinned;
   R.pending = false;
+  if (R.spec) {
+    // the forest the host did not wait for: complete after its first batch
+    // and with at least k edges?  Otherwise every later step used a wrong
+    // forest, and the level is redone waiting
+    R.spec = false;
+    if (hinfo[I_SPEC] != 0 || hinfo[I_MSF] < R.k) {
+      ctx->spec_ok = 0;
+      return SPC_REDO_SPEC;
+    }
+    int rc = check_total(ctx);
+    if (rc) return rc;
+    R.msf = hinfo[I_MSF];
+    R.candidates = hinfo[I_CAND];
+    R.first_batch_complete = true;
+  }
+  ctx->spec_ok = R.bands == 1 && R.first_batch_complete ? 1 : 0;
   int64_t nc = (int32_t)hinfo[I_NINFO + 1];
   R.key_mode = fp ? 3 : rank ? 1 : (hinfo[I_GUARD] ? 2 : 0);
   R.rounds = hinfo[I_ROUNDS];

@@ -24,6 +24,7 @@ def P():
     spc.set_option("redo_rank", 0)
     spc.set_option("bad_select_guess", 0)
     spc.set_option("contract_wait", 0)
+    spc.set_option("speculate", 0)
 
 
 def say(*a):
@@ -186,6 +187,21 @@ def test_contraction_class_counts_on_device_and_host(P):
                             f"trimesh-90, contract_wait={flag}")
     finally:
         P.set_option("contract_wait", 0)
+
+
+def test_forest_without_waiting_and_its_redo(P):
+    # the host need not wait for the first batch of forest rounds; a forest
+    # that needs more rounds than that batch (or a band short of forest
+    # edges) makes the level start over with the wait, which must change
+    # nothing; never and always-with-one-round must agree with the oracle
+    try:
+        for mode in (2, 1):
+            P.set_option("speculate", mode)
+            check_hierarchy(P, trimesh(90, ("uniform", 1, 8), seed=41), 500, 0, f"trimesh-90 speculate={mode}")
+            check_hierarchy(P, grid3d(16, ("uniform", 1, 16), seed=3), 64, 0, f"grid3d-16 speculate={mode}")
+            check_level(P, random_graph(700, 0.015, seed=12, self_loops=True), 200, f"random-700 speculate={mode}")
+    finally:
+        P.set_option("speculate", 0)
 
 
 def test_huge_rows_sort_and_dense_paths(P):
