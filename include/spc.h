@@ -138,7 +138,8 @@ int spc_set_allocator(spc_ctx* ctx, void* (*alloc)(size_t, void*), void (*free_)
  *                 0 (default) as the previous level's classes suggest, 1
  *                 always after reading the class counts on the host, 2
  *                 always on counts the kernels read from device memory
- *                 (when the huge rows' accumulators fit).
+ *                 (when the huge rows' accumulators fit), 3 as 2 but with
+ *                 no class kernel launched before the counts are read.
  *   "timing"      1: record a HIP event pair on the context stream around
  *                 every kernel launch, for spc_timing_report.
  * Unknown names return SPC_EINVAL. */

@@ -433,7 +433,7 @@ int spc_set_option(spc_ctx* ctx, const char* name, int64_t value) {
     if (value < 0 || value > 2) return set_error(ctx, SPC_EINVAL, "speculate takes 0, 1 or 2");
     ctx->speculate = (int)value;
   } else if (!strcmp(name, "contract_wait")) {
-    if (value < 0 || value > 2) return set_error(ctx, SPC_EINVAL, "contract_wait takes 0, 1 or 2");
+    if (value < 0 || value > 3) return set_error(ctx, SPC_EINVAL, "contract_wait takes 0 to 3");
     ctx->contract_wait = (int)value;
   }
   else return set_error(ctx, SPC_EINVAL, "unknown option '%s'", name);

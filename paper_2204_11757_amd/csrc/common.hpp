@@ -317,6 +317,7 @@ struct spc_ctx {
   int contract_wait = 0;     // 0: as the last level suggests, 1: the host reads the row-class counts
                              // before the class kernels, 2: never (when the huge rows fit)
   int contract_dev = 0;      // the last level's row classes suited the contraction without that wait
+  int contract_classes_seen = 7;  // row classes (1: 32-entry, 2: wavefront, 4: block) the last level had
   int spec_ok = 0;           // the last level's forest was complete after its first batch, in one band
   int speculate = 0;         // 0: as spec_ok says, 1: never, 2: always, with a one-round first batch
   // per-kernel timing: events recorded around launches on the context stream

@@ -315,6 +315,7 @@ __global__ void __launch_bounds__(SMALL_BS)
     int32_t msz = mptr[a + 1] - mptr[a];
     mx = msz > mx ? msz : mx;
     if (E > SMALL_CAP) {
+      cnt[a] = 0;   // until its class's kernel writes it
       if (E <= REG32_CAP) {
         r32m |= 1u << r;
         nr32++;
@@ -329,7 +330,6 @@ __global__ void __launch_bounds__(SMALL_BS)
         nhuge++;
         self_out[a] = 0;
         size_out[a] = 0;
-        cnt[a] = 0;   // until the huge-row pass writes it
       }
       continue;
     }
@@ -893,22 +893,27 @@ __global__ void __launch_bounds__(PACK_BS)
 // Rows of the register, wavefront and block classes.  With dev the class
 // counts stay in device memory (the kernels read them; grids cover a bound),
 // otherwise hinfo holds them.
+// Classes whose bit is clear in `skip` (dev only) are not launched: the
+// caller checks their counts once read.
 static int contract_classes(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c, spc_graph_out* out,
-                            LevelWork& W, bool dev) {
+                            LevelWork& W, bool dev, int launch = 7) {
   hipStream_t st = ctx->stream;
   int64_t* hinfo = ctx->h_pinned;
   unsigned long long* info = W.info;
   int64_t* self_out = (int64_t*)out->self_w;
   int64_t nr32 = dev ? 0 : hinfo[I_R32], nmid = dev ? 0 : hinfo[I_MID], nblk = dev ? 0 : hinfo[I_BLOCK];
   int64_t cap = (int64_t)ctx->num_cus * 8;
-  if (dev || nr32 > 0) {
+  if (!(launch & 1)) nr32 = 0;
+  if (!(launch & 2)) nmid = 0;
+  if (!(launch & 4)) nblk = 0;
+  if ((dev && (launch & 1)) || nr32 > 0) {
     TimedScope ts(ctx, "contract_reg32", (double)nr32);
     int64_t gr = dev ? std::min((int64_t)grid_for(n_c, SMALL_BS), cap) : (int64_t)grid_for(nr32, SMALL_BS);
     hipLaunchKernelGGL(k_contract_reg32, dim3((unsigned)gr), dim3(SMALL_BS), 0, st, g, c, W.mptr, W.members,
                        W.gptr, W.r32list, nr32, dev ? &info[I_R32] : nullptr, W.temp, W.cnt, self_out, out->size);
     SPC_LAUNCH_CHECK(ctx, "contract reg32");
   }
-  if (dev || nmid > 0) {
+  if ((dev && (launch & 2)) || nmid > 0) {
     TimedScope ts(ctx, "contract_wave_rows", (double)nmid);
     int64_t gr = dev ? std::min(n_c, cap * 4) : nmid;
     hipLaunchKernelGGL((k_contract_row<WAVE, WAVE_CAP>), dim3((unsigned)gr), dim3(WAVE), 0, st, g, c, W.mptr,
@@ -916,7 +921,7 @@ static int contract_classes(spc_ctx* ctx, const LevelIn& g, const int32_t* c, in
                        out->size);
     SPC_LAUNCH_CHECK(ctx, "contract wave rows");
   }
-  if (dev || nblk > 0) {
+  if ((dev && (launch & 4)) || nblk > 0) {
     TimedScope ts(ctx, "contract_block_rows", (double)nblk);
     int64_t gr = dev ? std::min(n_c, cap) : nblk;
     hipLaunchKernelGGL((k_contract_row<256, BLOCK_CAP>), dim3((unsigned)gr), dim3(256), 0, st, g, c, W.mptr,
@@ -1057,9 +1062,12 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
   int rc;
   {
     TimedScope ts(ctx, "contract_members", (double)n);
-    launch_clear(ctx, W.mcount, n_c + 1, (uint64_t*)W.gptr, n_c + 1, info,
-                 (1u << I_MID) | (1u << I_HUGE) | (1u << I_MAXCL) | (1u << I_BLOCK) | (1u << I_R32) |
-                     (1u << I_HOVER));
+    // (the merge cutoff's launch zeroed the counts already when it ran; the
+    // class slots are still zero from the level's start then)
+    if (!R.contract_zeroed)
+      launch_clear(ctx, W.mcount, n_c + 1, (uint64_t*)W.gptr, n_c + 1, info,
+                   (1u << I_MID) | (1u << I_HUGE) | (1u << I_MAXCL) | (1u << I_BLOCK) | (1u << I_R32) |
+                       (1u << I_HOVER));
     hipLaunchKernelGGL(k_cluster_count, dim3(grid_for(n, CM_BS)), dim3(CM_BS), 0, st, g, c, W.mcount,
                        (unsigned long long*)W.gptr);
     SPC_LAUNCH_CHECK(ctx, "cluster_count");
@@ -1096,11 +1104,14 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
   // of the wavefront and block classes (their kernels then stride over
   // device-held counts on bounded grids, which is slower for many rows)
   bool dev = !seg && !ctx->force_huge_sort && ctx->contract_wait != 1 && H_DEV * ncp1 <= 2 * g.nnz &&
-             (ctx->contract_wait == 2 || ctx->contract_dev);
+             (ctx->contract_wait >= 2 || ctx->contract_dev);
   if (dev) {
     // the class lists and up to H_DEV huge rows run on counts the device
-    // holds; the one host wait is the coarse row pointer's
-    rc = contract_classes(ctx, g, c, n_c, out, W, true);
+    // holds; the one host wait is the coarse row pointer's.  Classes the
+    // last level did not have are not launched; should this level have
+    // rows of them after all, they run once the counts are read.
+    int launch = ctx->contract_wait == 3 ? 0 : ctx->contract_classes_seen;
+    rc = contract_classes(ctx, g, c, n_c, out, W, true, launch);
     if (rc) return rc;
     rc = contract_huge(ctx, g, c, n_c, out, W, seg, H_DEV, true);
     if (rc) return rc;
@@ -1110,12 +1121,19 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
       rc = finish_select(ctx, R, n_c, R.pending_rank, false, seg);
       if (rc) return rc;
     }
-    if (hinfo[I_HOVER]) {
-      // more huge rows than H_DEV: they were left alone; the host knows how
-      // many now
-      int64_t H = hinfo[I_HUGE];
-      rc = contract_huge(ctx, g, c, n_c, out, W, seg, H, false);
-      if (rc) return rc;
+    int missed = ((hinfo[I_R32] > 0) ? 1 : 0) | ((hinfo[I_MID] > 0) ? 2 : 0) | ((hinfo[I_BLOCK] > 0) ? 4 : 0);
+    missed &= ~launch;
+    if (hinfo[I_HOVER] || missed) {
+      // more huge rows than H_DEV (they were left alone), or rows of a class
+      // not launched: the host knows the counts now
+      if (missed) {
+        rc = contract_classes(ctx, g, c, n_c, out, W, false, missed);
+        if (rc) return rc;
+      }
+      if (hinfo[I_HOVER]) {
+        rc = contract_huge(ctx, g, c, n_c, out, W, seg, hinfo[I_HUGE], false);
+        if (rc) return rc;
+      }
       rc = rowptr_and_read(ctx, W, out, n_c, nullptr);
       if (rc) return rc;
     }
@@ -1142,6 +1160,8 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
   {
     int64_t H = hinfo[I_HUGE];
     ctx->contract_dev = H >= 1 && H <= H_DEV && hinfo[I_MID] + hinfo[I_BLOCK] <= 8192 && hinfo[I_R32] <= 65536;
+    ctx->contract_classes_seen =
+        ((hinfo[I_R32] > 0) ? 1 : 0) | ((hinfo[I_MID] > 0) ? 2 : 0) | ((hinfo[I_BLOCK] > 0) ? 4 : 0);
   }
   int64_t nnz_c = hinfo[I_NINFO];
   if (hinfo[I_DENSE]) return set_error(ctx, SPC_EINVAL, "internal: a huge row left its graph's coarse range");

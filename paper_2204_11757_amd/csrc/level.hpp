@@ -261,6 +261,8 @@ struct LevelResult {
   bool spec = false;
   int64_t k = 0;       // merges of the level
   bool first_batch_complete = false;
+  // the selection zeroed the contraction's member counts and gather prefix
+  bool contract_zeroed = false;
 };
 
 // internal return codes (never reach the caller): a guarded key decision

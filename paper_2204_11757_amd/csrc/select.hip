@@ -605,7 +605,8 @@ __global__ void __launch_bounds__(BS)
                     uint64_t* __restrict__ lr_out, uint64_t* __restrict__ lp_out,
                     uint64_t* __restrict__ lo_out, unsigned long long* cnt_out, uint64_t* cur,
                     uint64_t* nxt, int32_t* parent, TileScan ts, unsigned long long* stats,
-                    const unsigned long long* msf_now, unsigned long long* msf_mark) {
+                    const unsigned long long* msf_now, unsigned long long* msf_mark,
+                    unsigned long long* cnt_copy) {
   __shared__ int stmp[BS / WAVE];
   __shared__ unsigned long long sbase;
   int64_t n = (int64_t)*cnt_in;
@@ -615,6 +616,7 @@ __global__ void __launch_bounds__(BS)
     if (n == 0 && blockIdx.x == 0 && tid == 0) {   // no tile runs: the empty list's count
       *cnt_out = 0;
       *msf_mark = *msf_now;
+      if (cnt_copy) *cnt_copy = 0;
     }
     return;
   }
@@ -645,6 +647,7 @@ __global__ void __launch_bounds__(BS)
     atomicAdd(&stats[0], (unsigned long long)n);   // info[I_FIN]
     atomicAdd(&stats[1], *cnt_out);                // info[I_FKEPT]
     *msf_mark = *msf_now;                          // forest records before the next merge
+    if (cnt_copy) *cnt_copy = *cnt_out;            // (this thread set *cnt_out)
   }
   for (int i = 0; i < BC_PER; i++) {
     if (!(keep >> i & 1u)) continue;
@@ -663,10 +666,16 @@ __global__ void __launch_bounds__(BS)
 __global__ void k_cutoff_prep(const uint64_t* __restrict__ msfP, const unsigned long long* cnt,
                               const SelState* st, const KeyND* __restrict__ keys,
                               const uint64_t* __restrict__ kexact, const unsigned long long* guard,
-                              int ebits, int* viol, int32_t* __restrict__ parent, int64_t nn) {
+                              int ebits, int* viol, int32_t* __restrict__ parent, int64_t nn,
+                              int32_t* __restrict__ zero_a, int64_t* __restrict__ zero_b, int64_t nz) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t x = i0; x < nn; x += stride) parent[x] = (int32_t)x;
+  // (and the contraction's member counts and gather prefix start at zero)
+  for (int64_t x = i0; x < nz; x += stride) {
+    zero_a[x] = 0;
+    zero_b[x] = 0;
+  }
   if (!keys || !*guard) return;
   int64_t n = (int64_t)*cnt;
   uint64_t T = st->prefix;
@@ -1210,10 +1219,14 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, boo
       int co = out == 0 ? I_LIVE0 : I_LIVE1;
       {
         TimedScope ts(ctx, "forest_candidates", (double)bound);
+        // the last round of a batch the host does not wait for also leaves
+        // its live count in info[I_SPEC]
+        bool mark = speculate && batch == 0 && r == rounds - 1;
         hipLaunchKernelGGL(k_bv_candidates, dim3(grid_for(bound, BC_CHUNK)), dim3(BS), 0, ctx->stream,
                            W.lr[in], W.lp[in], (in == 0 && lo0_is_lr) ? W.lr[0] : W.lo[in], &info[ci],
                            W.lr[out], W.lp[out], W.lo[out], &info[co], cur, nxt, W.parent,
-                           next_scan(ctx, W), &info[I_FIN], &info[I_MSF], &info[I_MSF0]);
+                           next_scan(ctx, W), &info[I_FIN], &info[I_MSF], &info[I_MSF0],
+                           mark ? &info[I_SPEC] : (unsigned long long*)nullptr);
       }
       if (out == 0) lo0_is_lr = false;
       {
@@ -1232,9 +1245,7 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, boo
       in = out;
     }
     if (speculate) {
-      // no wait: the live edges left go to info[I_SPEC] for a later check
-      hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(1), 0, ctx->stream, &info[I_SPEC],
-                         &info[in == 0 ? I_LIVE0 : I_LIVE1]);
+      // no wait: the live edges left are in info[I_SPEC] for a later check
       live0 = 0;
       return SPC_OK;
     }
@@ -1397,7 +1408,8 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
   }
   hipLaunchKernelGGL(k_cutoff_prep, dim3(grid_for(n, 256)), dim3(256), 0, st, W.msfP,
                      &info[I_MSF], W.sel2, rank ? (const KeyND*)nullptr : (const KeyND*)W.keysA, W.kexact, guard,
-                     ebits, (int*)&info[I_VIOL], W.parent, n);
+                     ebits, (int*)&info[I_VIOL], W.parent, n, W.mcount, W.gptr, t + 1);
+  R.contract_zeroed = true;
   SPC_LAUNCH_CHECK(ctx, "cutoff check");
   return SPC_OK;
 }

@@ -180,7 +180,7 @@ def test_contraction_class_counts_on_device_and_host(P):
     # reads them first, and the adaptive default, must agree as well
     g = interleaved_grids(6, 64)
     try:
-        for flag in (2, 1, 0):
+        for flag in (2, 3, 1, 0):
             P.set_option("contract_wait", flag)
             check_hierarchy(P, g, g.n // 16, 0, f"6 interleaved grid2d-64, contract_wait={flag}")
             check_hierarchy(P, trimesh(90, ("uniform", 1, 8), seed=31), 800, 0,
