@@ -524,6 +524,30 @@ __global__ void k_huge_members_count(const int32_t* __restrict__ hugelist, int64
   }
 }
 
+// The same for at most 64 rows, by one wavefront, which also takes the
+// exclusive prefix: hoff[h] = members of rows before h, hoff[H] = all.
+__global__ void k_huge_members_prefix(const int32_t* __restrict__ hugelist, int64_t H,
+                                      const int32_t* __restrict__ mptr, int64_t* __restrict__ hoff,
+                                      const unsigned long long* H_dev, unsigned long long* over) {
+  int h = threadIdx.x;
+  int64_t Hn = H;
+  if (H_dev) {
+    Hn = (int64_t)*H_dev;
+    if (Hn > H) {
+      if (h == 0) *over = 1;
+      Hn = 0;
+    }
+  }
+  int64_t v = 0;
+  if (h < Hn) {
+    int32_t a = hugelist[h];
+    v = mptr[a + 1] - mptr[a];
+  }
+  int64_t incl = wave_incl_sum(v);
+  if (h < H) hoff[h] = incl - v;
+  if (h == WAVE - 1) hoff[H] = incl;
+}
+
 // huge member i (0 <= i < HM, members of huge rows concatenated in list
 // order) -> its huge row h (binary search in hoff[0..H]) and node
 __device__ __forceinline__ int32_t huge_row_of(const int64_t* __restrict__ hoff, int64_t H, int64_t i) {
@@ -946,10 +970,15 @@ static int contract_huge(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64
   const unsigned long long* Hd = dev ? &info[I_HUGE] : nullptr;
   int rc;
   TimedScope ts(ctx, "contract_huge", (double)H);
-  hipLaunchKernelGGL(k_huge_members_count, dim3(grid_for(H, 256)), dim3(256), 0, st, W.hugelist, H, W.mptr,
-                     W.hmoff, Hd, &info[I_HOVER]);
-  rc = exclusive_scan<int64_t>(ctx, W.hmoff, W.hmoff, H, (int64_t*)W.scan_partial);
-  if (rc) return rc;
+  if (H <= WAVE) {
+    hipLaunchKernelGGL(k_huge_members_prefix, dim3(1), dim3(WAVE), 0, st, W.hugelist, H, W.mptr, W.hmoff, Hd,
+                       &info[I_HOVER]);
+  } else {
+    hipLaunchKernelGGL(k_huge_members_count, dim3(grid_for(H, 256)), dim3(256), 0, st, W.hugelist, H, W.mptr,
+                       W.hmoff, Hd, &info[I_HOVER]);
+    rc = exclusive_scan<int64_t>(ctx, W.hmoff, W.hmoff, H, (int64_t*)W.scan_partial);
+    if (rc) return rc;
+  }
   // member and entry totals stay on the device: launches cover bounds
   // (n members, nnz entries) and read the totals there
   int64_t* hpre = W.hpos;   // member row lengths, then their prefix

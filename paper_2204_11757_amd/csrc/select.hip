@@ -116,13 +116,19 @@ __global__ void __launch_bounds__(BS)
   uint32_t longmask = 0;
   int nlong = 0;
   int64_t ucnt[DEG_PER];   // upper entries of this thread's rows
+  int64_t rs[DEG_PER], re[DEG_PER];   // their bounds, loaded together
 #pragma unroll
-  for (int i = 0; i < DEG_PER; i++) ucnt[i] = 0;
+  for (int i = 0; i < DEG_PER; i++) {
+    ucnt[i] = 0;
+    int64_t u = base + i * BS + tid;
+    rs[i] = u < g.n ? g.rp[u] : 0;
+    re[i] = u < g.n ? g.rp[u + 1] : 0;
+  }
 #pragma unroll
   for (int i = 0; i < DEG_PER; i++) {
     int64_t u = base + i * BS + tid;
     if (u >= g.n) break;
-    int64_t s = g.rp[u], e = g.rp[u + 1];
+    int64_t s = rs[i], e = re[i];
     if (e - s <= DEG_SHORT) {
       // weights summed and lower entries counted in one sweep, the loads of
       // each chunk of 8 entries issued together
