@@ -574,12 +574,15 @@ constexpr int HMB_T = 1024;
 __global__ void __launch_bounds__(HMB_BS)
     k_huge_members(LevelIn g, const int32_t* __restrict__ hugelist, const int32_t* __restrict__ mptr,
                    const int32_t* __restrict__ members, const int64_t* __restrict__ hoff, int64_t H,
-                   int64_t bound, int64_t* __restrict__ hlen, int32_t* __restrict__ hrow,
+                   int64_t bound, int64_t* __restrict__ hpre, int32_t* __restrict__ hrow,
                    int64_t* __restrict__ hrs, int64_t* self_out, int32_t* size_out,
-                   const unsigned long long* H_dev) {
+                   const unsigned long long* H_dev, TileScan ts) {
+  constexpr int PER = HMB_T / HMB_BS;
   __shared__ unsigned long long sself[HMB_T];
   __shared__ int32_t ssize[HMB_T];
   __shared__ int32_t sh0;
+  __shared__ int64_t stmp64[HMB_BS / WAVE];
+  __shared__ int64_t sbase;
   int tid = threadIdx.x;
   int64_t i0 = (int64_t)blockIdx.x * HMB_T;
   if (H_dev) {
@@ -589,56 +592,79 @@ __global__ void __launch_bounds__(HMB_BS)
     H = Hn <= H ? Hn : 0;
   }
   int64_t HM = hoff[H];
-  if (i0 >= HM) {
-    for (int k = tid; k < HMB_T; k += HMB_BS)
-      if (i0 + k < bound) hlen[i0 + k] = 0;
-    return;
-  }
-  for (int k = tid; k < HMB_T; k += HMB_BS) {
-    sself[k] = 0;
-    ssize[k] = 0;
-  }
-  if (tid == 0) sh0 = huge_row_of(hoff, H, i0);
-  __syncthreads();
-  int32_t h0 = sh0;
+  int64_t len[PER];
 #pragma unroll
-  for (int r = 0; r < HMB_T / HMB_BS; r++) {
-    int64_t i = i0 + r * HMB_BS + tid;
-    bool valid = i < HM;
-    if (!valid && i < bound) hlen[i] = 0;
-    int32_t h = -1;
-    int64_t self = 0;
-    int32_t sz = 0;
-    if (valid) {
-      h = huge_row_of(hoff, H, i);
-      int32_t x = members[mptr[hugelist[h]] + (i - hoff[h])];
-      self = g.self ? g.self[x] : 0;
-      sz = g.size ? g.size[x] : 1;
-      int64_t rs = g.rp[x];
-      hlen[i] = g.rp[x + 1] - rs;
-      hrow[i] = h;
-      hrs[i] = rs;
+  for (int r = 0; r < PER; r++) len[r] = 0;
+  if (i0 < HM) {   // uniform over the block
+    for (int k = tid; k < HMB_T; k += HMB_BS) {
+      sself[k] = 0;
+      ssize[k] = 0;
     }
-    bool head;
-    int end;
-    uint64_t heads;
-    wave_runs(h, head, end, heads);
-    int64_t si = wave_incl_sum(self);
-    int32_t zi = wave_incl_sum(sz);
-    int64_t se = __shfl(si, end - 1);
-    int32_t ze = __shfl(zi, end - 1);
-    if (head && h >= 0) {
-      atomicAdd(&sself[h - h0], (unsigned long long)(se - si + self));
-      atomicAdd(&ssize[h - h0], ze - zi + sz);
+    if (tid == 0) sh0 = huge_row_of(hoff, H, i0);
+    __syncthreads();
+    int32_t h0 = sh0;
+#pragma unroll
+    for (int r = 0; r < PER; r++) {
+      int64_t i = i0 + r * HMB_BS + tid;
+      bool valid = i < HM;
+      int32_t h = -1;
+      int64_t self = 0;
+      int32_t sz = 0;
+      if (valid) {
+        h = huge_row_of(hoff, H, i);
+        int32_t x = members[mptr[hugelist[h]] + (i - hoff[h])];
+        self = g.self ? g.self[x] : 0;
+        sz = g.size ? g.size[x] : 1;
+        int64_t rs = g.rp[x];
+        len[r] = g.rp[x + 1] - rs;
+        hrow[i] = h;
+        hrs[i] = rs;
+      }
+      bool head;
+      int end;
+      uint64_t heads;
+      wave_runs(h, head, end, heads);
+      int64_t si = wave_incl_sum(self);
+      int32_t zi = wave_incl_sum(sz);
+      int64_t se = __shfl(si, end - 1);
+      int32_t ze = __shfl(zi, end - 1);
+      if (head && h >= 0) {
+        atomicAdd(&sself[h - h0], (unsigned long long)(se - si + self));
+        atomicAdd(&ssize[h - h0], ze - zi + sz);
+      }
+    }
+    __syncthreads();
+    for (int k = tid; k < HMB_T; k += HMB_BS) {
+      if (h0 + k >= H) break;
+      if (hoff[h0 + k] >= i0 + HMB_T) break;   // row starts after this block
+      int32_t a = hugelist[h0 + k];
+      if (sself[k]) atomicAdd((unsigned long long*)&self_out[a], sself[k]);
+      if (ssize[k]) atomicAdd(&size_out[a], ssize[k]);
+    }
+  }
+  // hpre: exclusive prefix of the member row lengths in member order (0 past
+  // the huge members), block offsets chained by a decoupled look-back; the
+  // last block stores the total at hpre[bound]
+  int64_t run = 0, pre[PER];
+#pragma unroll
+  for (int r = 0; r < PER; r++) {
+    int64_t tot;
+    int64_t inc = block_incl_scan<int64_t, HMB_BS, false>(len[r], stmp64, &tot);
+    pre[r] = run + inc - len[r];
+    run += tot;
+  }
+  if (tid < WAVE) {
+    uint64_t ex = lb_exclusive_wave(ts, blockIdx.x, (uint64_t)run);
+    if (tid == 0) {
+      sbase = (int64_t)ex;
+      if (blockIdx.x == gridDim.x - 1) hpre[bound] = (int64_t)ex + run;
     }
   }
   __syncthreads();
-  for (int k = tid; k < HMB_T; k += HMB_BS) {
-    if (h0 + k >= H) break;
-    if (hoff[h0 + k] >= i0 + HMB_T) break;   // row starts after this block
-    int32_t a = hugelist[h0 + k];
-    if (sself[k]) atomicAdd((unsigned long long*)&self_out[a], sself[k]);
-    if (ssize[k]) atomicAdd(&size_out[a], ssize[k]);
+#pragma unroll
+  for (int r = 0; r < PER; r++) {
+    int64_t i = i0 + r * HMB_BS + tid;
+    if (i < bound) hpre[i] = sbase + pre[r];
   }
 }
 
@@ -981,11 +1007,9 @@ static int contract_huge(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64
   }
   // member and entry totals stay on the device: launches cover bounds
   // (n members, nnz entries) and read the totals there
-  int64_t* hpre = W.hpos;   // member row lengths, then their prefix
+  int64_t* hpre = W.hpos;   // prefix of the member row lengths
   hipLaunchKernelGGL(k_huge_members, dim3(grid_for(n, HMB_T)), dim3(HMB_BS), 0, st, g, W.hugelist, W.mptr,
-                     W.members, W.hmoff, H, n, hpre, W.hmrow, W.hmrs, self_out, out->size, Hd);
-  rc = exclusive_scan<int64_t>(ctx, hpre, hpre, n, (int64_t*)W.scan_partial);
-  if (rc) return rc;
+                     W.members, W.hmoff, H, n, hpre, W.hmrow, W.hmrs, self_out, out->size, Hd, next_scan(ctx, W));
   // few huge rows: dense accumulators over the coarse ids (they fit in
   // the gather buffers when H * ncp <= 2 nnz)
   // (in a batch, per huge row only the coarse range of its own graph)
@@ -1100,9 +1124,7 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
     hipLaunchKernelGGL(k_cluster_count, dim3(grid_for(n, CM_BS)), dim3(CM_BS), 0, st, g, c, W.mcount,
                        (unsigned long long*)W.gptr);
     SPC_LAUNCH_CHECK(ctx, "cluster_count");
-    rc = exclusive_scan<int32_t>(ctx, W.mcount, W.mptr, n_c, (int32_t*)W.scan_partial);
-    if (rc) return rc;
-    rc = exclusive_scan<int64_t>(ctx, W.gptr, W.gptr, n_c, (int64_t*)W.scan_partial);
+    rc = exclusive_scan2<int32_t, int64_t>(ctx, W.mcount, W.mptr, W.gptr, W.gptr, n_c);
     if (rc) return rc;
     hipLaunchKernelGGL(k_member_scatter, dim3(grid_for(n, CM_BS)), dim3(CM_BS), 0, st, c, W.mptr,
                        W.mcount, W.members, n);

@@ -188,6 +188,78 @@ __global__ void __launch_bounds__(SCAN_BS) k_scan_lb(const T* in, T* out, int64_
   }
 }
 
+// Two exclusive scans of the same length in one launch (each tile scans
+// both arrays; wavefront 0 runs the first chain's look-back, wavefront 1 the
+// second's, side by side).
+template <typename T1, typename T2>
+__global__ void __launch_bounds__(SCAN_BS)
+    k_scan2_lb(const T1* in1, T1* out1, const T2* in2, T2* out2, int64_t n, TileScan ts1, TileScan ts2) {
+  static_assert(SCAN_BS >= 2 * WAVE, "two wavefronts run the chains");
+  __shared__ T1 buf1[SCAN_TILE];
+  __shared__ T2 buf2[SCAN_TILE];
+  __shared__ T1 tmp1[SCAN_BS / WAVE];
+  __shared__ T2 tmp2[SCAN_BS / WAVE];
+  __shared__ T1 sh1;
+  __shared__ T2 sh2;
+  int tid = threadIdx.x;
+  int64_t tile = blockIdx.x;
+  int64_t base = tile * SCAN_TILE;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; i++) {
+    int64_t g = base + i * SCAN_BS + tid;
+    buf1[i * SCAN_BS + tid] = g < n ? in1[g] : (T1)0;
+    buf2[i * SCAN_BS + tid] = g < n ? in2[g] : (T2)0;
+  }
+  __syncthreads();
+  T1 loc1[SCAN_ITEMS];
+  T2 loc2[SCAN_ITEMS];
+  T1 run1 = 0;
+  T2 run2 = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; i++) {
+    loc1[i] = run1;
+    loc2[i] = run2;
+    run1 += buf1[tid * SCAN_ITEMS + i];
+    run2 += buf2[tid * SCAN_ITEMS + i];
+  }
+  T1 tot1;
+  T2 tot2;
+  T1 inc1 = block_incl_scan<T1, SCAN_BS, false>(run1, tmp1, &tot1);
+  T2 inc2 = block_incl_scan<T2, SCAN_BS, false>(run2, tmp2, &tot2);
+  if (tid < WAVE) {
+    uint64_t ex = lb_exclusive_wave(ts1, tile, (uint64_t)tot1);
+    if (tid == 0) {
+      if ((uint64_t)tot1 > LB_VMASK || ex + (uint64_t)tot1 > LB_VMASK) atomicOr(ts1.err, 1ull);
+      sh1 = (T1)ex;
+      if (tile == gridDim.x - 1) out1[n] = (T1)(ex + (uint64_t)tot1);
+    }
+  } else if (tid < 2 * WAVE) {
+    uint64_t ex = lb_exclusive_wave(ts2, tile, (uint64_t)tot2);
+    if (tid == WAVE) {
+      if ((uint64_t)tot2 > LB_VMASK || ex + (uint64_t)tot2 > LB_VMASK) atomicOr(ts2.err, 1ull);
+      sh2 = (T2)ex;
+      if (tile == gridDim.x - 1) out2[n] = (T2)(ex + (uint64_t)tot2);
+    }
+  }
+  __syncthreads();
+  T1 pre1 = sh1 + inc1 - run1;
+  T2 pre2 = sh2 + inc2 - run2;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; i++) {
+    buf1[tid * SCAN_ITEMS + i] = pre1 + loc1[i];
+    buf2[tid * SCAN_ITEMS + i] = pre2 + loc2[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; i++) {
+    int64_t g = base + i * SCAN_BS + tid;
+    if (g < n) {
+      out1[g] = buf1[i * SCAN_BS + tid];
+      out2[g] = buf2[i * SCAN_BS + tid];
+    }
+  }
+}
+
 // Makes room for `words` look-back words in the context (zeroed) and
 // returns a fresh epoch; 0 on allocation failure.
 uint32_t scan_state_reserve(spc_ctx* ctx, int64_t words);
@@ -207,6 +279,25 @@ int exclusive_scan(spc_ctx* ctx, const T* in, T* out, int64_t n, T* partial) {
   TileScan ts{ctx->scan_state, epoch, (unsigned long long*)(ctx->scan_state + ctx->scan_cap - 1)};
   hipLaunchKernelGGL(k_scan_lb<T>, dim3((unsigned)tiles), dim3(SCAN_BS), 0, ctx->stream, in, out, n, ts);
   SPC_LAUNCH_CHECK(ctx, "exclusive_scan");
+  return SPC_OK;
+}
+
+// Both exclusive scans (out[n] = total each) in one launch.
+template <typename T1, typename T2>
+int exclusive_scan2(spc_ctx* ctx, const T1* in1, T1* out1, const T2* in2, T2* out2, int64_t n) {
+  if (n <= 0) {
+    SPC_HIP(ctx, hipMemsetAsync(out1, 0, sizeof(T1), ctx->stream));
+    SPC_HIP(ctx, hipMemsetAsync(out2, 0, sizeof(T2), ctx->stream));
+    return SPC_OK;
+  }
+  int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+  uint32_t epoch = scan_state_reserve(ctx, 2 * tiles);
+  if (!epoch) return ctx->err_code ? ctx->err_code : SPC_ENOMEM;
+  unsigned long long* err = (unsigned long long*)(ctx->scan_state + ctx->scan_cap - 1);
+  TileScan ts1{ctx->scan_state, epoch, err}, ts2{ctx->scan_state + tiles, epoch, err};
+  hipLaunchKernelGGL((k_scan2_lb<T1, T2>), dim3((unsigned)tiles), dim3(SCAN_BS), 0, ctx->stream, in1, out1, in2,
+                     out2, n, ts1, ts2);
+  SPC_LAUNCH_CHECK(ctx, "exclusive_scan2");
   return SPC_OK;
 }
 
