@@ -6,6 +6,98 @@
 namespace spc {
 
 
+// Position maps of the rows registered by the degree pass: for each of the
+// first H_MAX, hmap[s * n + col[j]] = j - rp[row].  Entries of other columns
+// keep stale values, which the lookups confirm against the row itself.
+constexpr int HM_BLOCKS = 32;
+
+__global__ void __launch_bounds__(BS)
+    k_huge_map(LevelIn g, const int32_t* __restrict__ htab, const unsigned long long* info,
+               int32_t* __restrict__ hmap) {
+  int s = blockIdx.x / HM_BLOCKS;
+  unsigned long long nh = info[I_LONGROW];
+  if ((unsigned long long)s >= nh) return;
+  int32_t u = htab[s];
+  int64_t a = g.rp[u], b = g.rp[u + 1];
+  int32_t* map = hmap + (int64_t)s * g.n;
+  for (int64_t j = a + (int64_t)(blockIdx.x % HM_BLOCKS) * BS + threadIdx.x; j < b;
+       j += (int64_t)HM_BLOCKS * BS)
+    map[g.col[j]] = (int32_t)(j - a);
+}
+
+// The edges of the mapped rows: one thread per entry j of a mapped row h,
+// the other endpoint x = col[j].  Row x is read in chunks and looked up in
+// h's map (when x is mapped too and its row is longer, the roles swap; such
+// an edge is scored by the smaller endpoint's row only).
+constexpr int HS_BLOCKS = 256;   // about one entry per thread for the rows seen in practice
+
+template <int MODE>
+__device__ __forceinline__ void score_mapped_block(
+    int bid, LevelIn g, const uint64_t* __restrict__ deg, const int32_t* __restrict__ lc,
+    const int64_t* __restrict__ uptr, int c, int ebits, uint64_t* __restrict__ Pc,
+    uint64_t* __restrict__ samples, KeyND* __restrict__ keys, int write_keys, unsigned long long* info,
+    const int32_t* __restrict__ htab, const int32_t* __restrict__ hmap, int sshift, uint64_t* sred) {
+  int s = bid / HS_BLOCKS;
+  unsigned long long nh = info[I_LONGROW];
+  int hc = nh < (unsigned long long)H_MAX ? (int)nh : H_MAX;
+  if (s >= hc) return;   // uniform over the block
+  if (MODE == 0 && write_keys < 0) {
+    unsigned __int128 d2 = (unsigned __int128)info[I_DMAX] * info[I_DMAX];
+    write_keys = (d2 >> 64) != 0 || d2 * d2 > ((unsigned __int128)1 << c) ? 1 : 0;
+  }
+  int32_t hrow[H_MAX];
+#pragma unroll
+  for (int q = 0; q < H_MAX; q++) hrow[q] = q < hc ? htab[q] : -1;
+  int32_t h = hrow[s];
+  int64_t ah = g.rp[h], bh = g.rp[h + 1];
+  uint64_t dh = deg[h];
+  uint64_t sh_ = g.self ? (uint64_t)g.self[h] : 0;
+  uint64_t dmx = 0;
+  for (int64_t j = ah + (int64_t)(bid % HS_BLOCKS) * BS + threadIdx.x; j < bh;
+       j += (int64_t)HS_BLOCKS * BS) {
+    int32_t x = g.col[j];
+    int32_t wx = g.w[j];
+    int xs = -1;
+#pragma unroll
+    for (int q = 0; q < H_MAX; q++) xs = hrow[q] == x ? q : xs;
+    if (xs >= 0 && x < h) continue;   // the edge belongs to row x's threads
+    int64_t ax = g.rp[x], bx = g.rp[x + 1];
+    uint64_t dx = deg[x];
+    uint64_t sx = g.self ? (uint64_t)g.self[x] : 0;
+    int64_t below;
+    uint64_t M;
+    if (xs >= 0 && bx - ax > bh - ah) {
+      // both rows mapped, x's longer: walk h's row in x's map
+      M = mapped_min_sum(g.col, g.w, ah, bh, dx, ax, bx, dh, hmap + (int64_t)xs * g.n, INT32_MIN, below);
+      below = hmap[(int64_t)xs * g.n + h];
+    } else {
+      M = mapped_min_sum(g.col, g.w, ax, bx, dh, ah, bh, dx, hmap + (int64_t)s * g.n, h, below);
+    }
+    if (sh_) M += umin64(sh_ * dx, (uint64_t)wx * dh);   // column h
+    if (sx) M += umin64((uint64_t)wx * dx, sx * dh);     // column x
+    uint64_t D = dh * dx;
+    uint64_t N = 2 * D - 2 * M;
+    dmx = D > dmx ? D : dmx;
+    int64_t jm = ax + below;   // entry (x -> h)
+    int64_t e = h < x ? uptr[h] + (j - ah - lc[h]) : uptr[x] + (below - lc[x]);
+    if (MODE == 0) {
+      uint64_t key = (fixed_key(N, D, c) << ebits) | (uint64_t)e;
+      Pc[j] = key;
+      Pc[jm] = key;
+      if ((e & ((1ll << sshift) - 1)) == 0) samples[e >> sshift] = key;
+    }
+    if (MODE == 1 || write_keys) keys[e] = KeyND{N, D, (uint64_t)e};
+  }
+  dmx = wave_max(dmx);
+  if (lane_id() == 0) sred[threadIdx.x / WAVE] = dmx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t a = 0;
+    for (int w = 0; w < BS / WAVE; w++) a = sred[w] > a ? sred[w] : a;
+    atomic_max_lazy(&info[I_DMAXE], (unsigned long long)a);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // A2 + A3: 3 edges (u < v) per thread; tiles of TILE_S consecutive edge ids
 // are mapped to rows by a load-balanced search over the upper-entry prefix
@@ -21,7 +113,7 @@ __global__ void __launch_bounds__(BS, 5)
             const int64_t* __restrict__ uptr, int64_t m, int c, int ebits,
             uint64_t* __restrict__ Pc, uint64_t* __restrict__ samples, KeyND* __restrict__ keys,
             int write_keys, unsigned long long* info, const int32_t* __restrict__ htab,
-            uint64_t* __restrict__ kexact, int sshift) {
+            uint64_t* __restrict__ kexact, int sshift, int tiles, const int32_t* __restrict__ hmap) {
   // write_keys < 0: exact records only when the packed key is not exact
   // for sure, i.e. when dmax^4 > 2^c
   if (MODE == 0 && write_keys < 0) {
@@ -33,7 +125,14 @@ __global__ void __launch_bounds__(BS, 5)
   __shared__ int64_t sh[2];
   __shared__ int32_t stmp[BS / WAVE];
   __shared__ uint64_t sred[BS / WAVE];
-  int64_t e0 = xcd_tile(blockIdx.x, gridDim.x) * TILE_S;
+  if ((int)blockIdx.x >= tiles) {
+    // the blocks past the edge tiles score the mapped long rows' edges
+    // (dispatched last, they fill the tail of the launch)
+    score_mapped_block<MODE>((int)blockIdx.x - tiles, g, deg, lc, uptr, c, ebits, Pc, samples, keys,
+                             write_keys, info, htab, hmap, sshift, sred);
+    return;
+  }
+  int64_t e0 = xcd_tile(blockIdx.x, tiles) * TILE_S;
   lbs_tile<TILE_S, BS>(uptr, g.n, e0, srow, sh, stmp);
   int tid = threadIdx.x;
   uint64_t dmx = 0;
@@ -70,7 +169,7 @@ __global__ void __launch_bounds__(BS, 5)
     bool mapped = false;
 #pragma unroll
     for (int s = 0; s < H_MAX; s++) mapped |= hrow[s] == eu[i] || hrow[s] == ev[i];
-    // edges of a mapped row are scored by k_score_mapped (their bit stays clear)
+    // edges of a mapped row are scored by the mapped rows' blocks (their bit stays clear)
     if (e < m && !mapped) {
       uint64_t N, D;
       int64_t jm;
@@ -172,100 +271,6 @@ __global__ void k_relabel_eps(LevelIn g, const int32_t* __restrict__ root, const
   }
 }
 
-// Position maps of the rows registered by the degree pass: for each of the
-// first H_MAX, hmap[s * n + col[j]] = j - rp[row].  Entries of other columns
-// keep stale values, which the lookups confirm against the row itself.
-constexpr int HM_BLOCKS = 32;
-
-__global__ void __launch_bounds__(BS)
-    k_huge_map(LevelIn g, const int32_t* __restrict__ htab, const unsigned long long* info,
-               int32_t* __restrict__ hmap) {
-  int s = blockIdx.x / HM_BLOCKS;
-  unsigned long long nh = info[I_LONGROW];
-  if ((unsigned long long)s >= nh) return;
-  int32_t u = htab[s];
-  int64_t a = g.rp[u], b = g.rp[u + 1];
-  int32_t* map = hmap + (int64_t)s * g.n;
-  for (int64_t j = a + (int64_t)(blockIdx.x % HM_BLOCKS) * BS + threadIdx.x; j < b;
-       j += (int64_t)HM_BLOCKS * BS)
-    map[g.col[j]] = (int32_t)(j - a);
-}
-
-// The edges of the mapped rows: one thread per entry j of a mapped row h,
-// the other endpoint x = col[j].  Row x is read in chunks and looked up in
-// h's map (when x is mapped too and its row is longer, the roles swap; such
-// an edge is scored by the smaller endpoint's row only).
-constexpr int HS_BLOCKS = 256;   // about one entry per thread for the rows seen in practice
-
-template <int MODE>
-__global__ void __launch_bounds__(BS)
-    k_score_mapped(LevelIn g, const uint64_t* __restrict__ deg, const int32_t* __restrict__ lc,
-                   const int64_t* __restrict__ uptr, int c, int ebits, uint64_t* __restrict__ Pc,
-                   uint64_t* __restrict__ samples, KeyND* __restrict__ keys, int write_keys,
-                   unsigned long long* info, const int32_t* __restrict__ htab,
-                   const int32_t* __restrict__ hmap, int sshift) {
-  __shared__ uint64_t sred[BS / WAVE];
-  int s = blockIdx.x / HS_BLOCKS;
-  unsigned long long nh = info[I_LONGROW];
-  int hc = nh < (unsigned long long)H_MAX ? (int)nh : H_MAX;
-  if (s >= hc) return;   // uniform over the block
-  if (MODE == 0 && write_keys < 0) {
-    unsigned __int128 d2 = (unsigned __int128)info[I_DMAX] * info[I_DMAX];
-    write_keys = (d2 >> 64) != 0 || d2 * d2 > ((unsigned __int128)1 << c) ? 1 : 0;
-  }
-  int32_t hrow[H_MAX];
-#pragma unroll
-  for (int q = 0; q < H_MAX; q++) hrow[q] = q < hc ? htab[q] : -1;
-  int32_t h = hrow[s];
-  int64_t ah = g.rp[h], bh = g.rp[h + 1];
-  uint64_t dh = deg[h];
-  uint64_t sh_ = g.self ? (uint64_t)g.self[h] : 0;
-  uint64_t dmx = 0;
-  for (int64_t j = ah + (int64_t)(blockIdx.x % HS_BLOCKS) * BS + threadIdx.x; j < bh;
-       j += (int64_t)HS_BLOCKS * BS) {
-    int32_t x = g.col[j];
-    int32_t wx = g.w[j];
-    int xs = -1;
-#pragma unroll
-    for (int q = 0; q < H_MAX; q++) xs = hrow[q] == x ? q : xs;
-    if (xs >= 0 && x < h) continue;   // the edge belongs to row x's threads
-    int64_t ax = g.rp[x], bx = g.rp[x + 1];
-    uint64_t dx = deg[x];
-    uint64_t sx = g.self ? (uint64_t)g.self[x] : 0;
-    int64_t below;
-    uint64_t M;
-    if (xs >= 0 && bx - ax > bh - ah) {
-      // both rows mapped, x's longer: walk h's row in x's map
-      M = mapped_min_sum(g.col, g.w, ah, bh, dx, ax, bx, dh, hmap + (int64_t)xs * g.n, INT32_MIN, below);
-      below = hmap[(int64_t)xs * g.n + h];
-    } else {
-      M = mapped_min_sum(g.col, g.w, ax, bx, dh, ah, bh, dx, hmap + (int64_t)s * g.n, h, below);
-    }
-    if (sh_) M += umin64(sh_ * dx, (uint64_t)wx * dh);   // column h
-    if (sx) M += umin64((uint64_t)wx * dx, sx * dh);     // column x
-    uint64_t D = dh * dx;
-    uint64_t N = 2 * D - 2 * M;
-    dmx = D > dmx ? D : dmx;
-    int64_t jm = ax + below;   // entry (x -> h)
-    int64_t e = h < x ? uptr[h] + (j - ah - lc[h]) : uptr[x] + (below - lc[x]);
-    if (MODE == 0) {
-      uint64_t key = (fixed_key(N, D, c) << ebits) | (uint64_t)e;
-      Pc[j] = key;
-      Pc[jm] = key;
-      if ((e & ((1ll << sshift) - 1)) == 0) samples[e >> sshift] = key;
-    }
-    if (MODE == 1 || write_keys) keys[e] = KeyND{N, D, (uint64_t)e};
-  }
-  dmx = wave_max(dmx);
-  if (lane_id() == 0) sred[threadIdx.x / WAVE] = dmx;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint64_t a = 0;
-    for (int w = 0; w < BS / WAVE; w++) a = sred[w] > a ? sred[w] : a;
-    atomic_max_lazy(&info[I_DMAXE], (unsigned long long)a);
-  }
-}
-
 void launch_score(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t m, int c, int ebits,
                   int mode) {
   int tiles = grid_for(m, TILE_S);
@@ -275,31 +280,17 @@ void launch_score(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t m,
     hipLaunchKernelGGL(k_huge_map, dim3(H_MAX * HM_BLOCKS), dim3(BS), 0, ctx->stream, g, W.htab, W.info,
                        W.hmap);
   }
+  // one launch: the edge tiles, then (when rows can be long) the mapped rows' blocks
+  int grid = tiles + (maps ? H_MAX * HS_BLOCKS : 0);
   if (mode == 0) {
-    {
-      TimedScope ts(ctx, "score", (double)m);
-      hipLaunchKernelGGL(k_score<0>, dim3(tiles), dim3(BS), 0, ctx->stream, g, W.deg, W.lc, W.uptr, m, c,
-                         ebits, W.Pc, W.samples, W.keysA, -1, W.info, W.htab, W.kexact, sample_shift(m));
-    }
-    if (maps) {
-      TimedScope ts(ctx, "score_long_rows", (double)H_MAX);
-      hipLaunchKernelGGL(k_score_mapped<0>, dim3(H_MAX * HS_BLOCKS), dim3(BS), 0, ctx->stream, g, W.deg,
-                         W.lc, W.uptr, c, ebits, W.Pc, W.samples, W.keysA, -1, W.info, W.htab, W.hmap,
-                         sample_shift(m));
-    }
+    TimedScope ts(ctx, "score", (double)m);
+    hipLaunchKernelGGL(k_score<0>, dim3(grid), dim3(BS), 0, ctx->stream, g, W.deg, W.lc, W.uptr, m, c, ebits,
+                       W.Pc, W.samples, W.keysA, -1, W.info, W.htab, W.kexact, sample_shift(m), tiles, W.hmap);
   } else {
-    {
-      TimedScope ts(ctx, "score_rank", (double)m);
-      hipLaunchKernelGGL(k_score<1>, dim3(tiles), dim3(BS), 0, ctx->stream, g, W.deg, W.lc, W.uptr, m, c,
-                         ebits, (uint64_t*)nullptr, (uint64_t*)nullptr, W.keysA, 1, W.info, W.htab,
-                         (uint64_t*)nullptr, sample_shift(m));
-    }
-    if (maps) {
-      TimedScope ts(ctx, "score_long_rows", (double)H_MAX);
-      hipLaunchKernelGGL(k_score_mapped<1>, dim3(H_MAX * HS_BLOCKS), dim3(BS), 0, ctx->stream, g, W.deg,
-                         W.lc, W.uptr, c, ebits, (uint64_t*)nullptr, (uint64_t*)nullptr, W.keysA, 1, W.info,
-                         W.htab, W.hmap, sample_shift(m));
-    }
+    TimedScope ts(ctx, "score_rank", (double)m);
+    hipLaunchKernelGGL(k_score<1>, dim3(grid), dim3(BS), 0, ctx->stream, g, W.deg, W.lc, W.uptr, m, c, ebits,
+                       (uint64_t*)nullptr, (uint64_t*)nullptr, W.keysA, 1, W.info, W.htab, (uint64_t*)nullptr,
+                       sample_shift(m), tiles, W.hmap);
   }
 }
 
