@@ -576,8 +576,12 @@ __global__ void __launch_bounds__(HMB_BS)
                    const int32_t* __restrict__ members, const int64_t* __restrict__ hoff, int64_t H,
                    int64_t bound, int64_t* __restrict__ hpre, int32_t* __restrict__ hrow,
                    int64_t* __restrict__ hrs, int64_t* self_out, int32_t* size_out,
-                   const unsigned long long* H_dev, TileScan ts) {
+                   const unsigned long long* H_dev, TileScan ts, uint32_t* __restrict__ zero,
+                   int64_t nzero) {
   constexpr int PER = HMB_T / HMB_BS;
+  // (the dense accumulators of the next launch start at zero)
+  for (int64_t i = (int64_t)blockIdx.x * HMB_BS + threadIdx.x; i < nzero; i += (int64_t)gridDim.x * HMB_BS)
+    zero[i] = 0;
   __shared__ unsigned long long sself[HMB_T];
   __shared__ int32_t ssize[HMB_T];
   __shared__ int32_t sh0;
@@ -1007,23 +1011,24 @@ static int contract_huge(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64
   }
   // member and entry totals stay on the device: launches cover bounds
   // (n members, nnz entries) and read the totals there
-  int64_t* hpre = W.hpos;   // prefix of the member row lengths
-  hipLaunchKernelGGL(k_huge_members, dim3(grid_for(n, HMB_T)), dim3(HMB_BS), 0, st, g, W.hugelist, W.mptr,
-                     W.members, W.hmoff, H, n, hpre, W.hmrow, W.hmrs, self_out, out->size, Hd, next_scan(ctx, W));
   // few huge rows: dense accumulators over the coarse ids (they fit in
-  // the gather buffers when H * ncp <= 2 nnz)
+  // the gather buffers when H * ncp <= 2 nnz), zeroed by the members' launch
   // (in a batch, per huge row only the coarse range of its own graph)
   int64_t win = seg ? seg->wmax : n_c;
   int64_t ncp = (win + DC_T - 1) / DC_T * DC_T;
-  if (dev || (!ctx->force_huge_sort && H * ncp <= 2 * g.nnz)) {
-    uint32_t* dense = (uint32_t*)W.gkeyA;
+  bool dense_path = dev || (!ctx->force_huge_sort && H * ncp <= 2 * g.nnz);
+  uint32_t* dense = (uint32_t*)W.gkeyA;
+  int64_t* hpre = W.hpos;   // prefix of the member row lengths
+  hipLaunchKernelGGL(k_huge_members, dim3(grid_for(n, HMB_T)), dim3(HMB_BS), 0, st, g, W.hugelist, W.mptr,
+                     W.members, W.hmoff, H, n, hpre, W.hmrow, W.hmrs, self_out, out->size, Hd, next_scan(ctx, W),
+                     dense, dense_path ? H * ncp : (int64_t)0);
+  if (dense_path) {
     int32_t* base = nullptr;
     if (seg) {
       base = W.hmnode;   // free on this path
       hipLaunchKernelGGL(k_huge_base, dim3(grid_for(H, 256)), dim3(256), 0, st, W.hugelist, H, seg->coff,
                          seg->G, base);
     }
-    launch_clear(ctx, (int32_t*)dense, H * ncp, nullptr, 0, nullptr, 0u);
     if (g.nnz > HD_SMALL_NNZ)
       hipLaunchKernelGGL(k_huge_dense<HT>, dim3(grid_for(g.nnz, HT)), dim3(HT_BS), 0, st, g, c, W.hugelist,
                          W.hmrow, W.hmrs, hpre, n, self_out, dense, ncp, (const int32_t*)base,

@@ -6,24 +6,6 @@
 namespace spc {
 
 
-// Position maps of the rows registered by the degree pass: for each of the
-// first H_MAX, hmap[s * n + col[j]] = j - rp[row].  Entries of other columns
-// keep stale values, which the lookups confirm against the row itself.
-constexpr int HM_BLOCKS = 32;
-
-__global__ void __launch_bounds__(BS)
-    k_huge_map(LevelIn g, const int32_t* __restrict__ htab, const unsigned long long* info,
-               int32_t* __restrict__ hmap) {
-  int s = blockIdx.x / HM_BLOCKS;
-  unsigned long long nh = info[I_LONGROW];
-  if ((unsigned long long)s >= nh) return;
-  int32_t u = htab[s];
-  int64_t a = g.rp[u], b = g.rp[u + 1];
-  int32_t* map = hmap + (int64_t)s * g.n;
-  for (int64_t j = a + (int64_t)(blockIdx.x % HM_BLOCKS) * BS + threadIdx.x; j < b;
-       j += (int64_t)HM_BLOCKS * BS)
-    map[g.col[j]] = (int32_t)(j - a);
-}
 
 // The edges of the mapped rows: one thread per entry j of a mapped row h,
 // the other endpoint x = col[j].  Row x is read in chunks and looked up in
@@ -274,12 +256,7 @@ __global__ void k_relabel_eps(LevelIn g, const int32_t* __restrict__ root, const
 void launch_score(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t m, int c, int ebits,
                   int mode) {
   int tiles = grid_for(m, TILE_S);
-  bool maps = g.nnz > HUGE_T;
-  if (maps) {
-    TimedScope ts(ctx, "score_long_rows", (double)H_MAX);
-    hipLaunchKernelGGL(k_huge_map, dim3(H_MAX * HM_BLOCKS), dim3(BS), 0, ctx->stream, g, W.htab, W.info,
-                       W.hmap);
-  }
+  bool maps = g.nnz > HUGE_T;   // (their position maps come with the degree totals)
   // one launch: the edge tiles, then (when rows can be long) the mapped rows' blocks
   int grid = tiles + (maps ? H_MAX * HS_BLOCKS : 0);
   if (mode == 0) {

@@ -260,11 +260,28 @@ constexpr int SP_UNROLL = 8;
 
 __device__ __forceinline__ uint64_t sat_add(uint64_t a, uint64_t b) { return a + b < a ? ~0ull : a + b; }
 
+// Blocks past the first (when the launch has them) write the mapped rows'
+// position maps instead: for each of the first H_MAX registered rows,
+// hmap[s * n + col[j]] = j - rp[row], SP_MAP blocks per row.  Entries of
+// other columns keep stale values, which the lookups confirm against the row
+// itself.
+constexpr int SP_MAP = 8;
+
 __global__ void __launch_bounds__(SP_BS)
     k_sum_parts(const uint64_t* __restrict__ part, int64_t np, LevelIn g, const int32_t* __restrict__ htab,
-                uint64_t* __restrict__ deg, unsigned long long* info) {
+                uint64_t* __restrict__ deg, unsigned long long* info, int32_t* __restrict__ hmap) {
   __shared__ uint64_t tmp[SP_BS / WAVE];
   int tid = threadIdx.x;
+  if (blockIdx.x > 0) {
+    int sr = (blockIdx.x - 1) / SP_MAP;
+    if ((unsigned long long)sr >= info[I_LONGROW]) return;
+    int32_t u = htab[sr];
+    int64_t a = g.rp[u], b = g.rp[u + 1];
+    int32_t* map = hmap + (int64_t)sr * g.n;
+    for (int64_t j = a + (int64_t)((blockIdx.x - 1) % SP_MAP) * SP_BS + tid; j < b; j += (int64_t)SP_MAP * SP_BS)
+      map[g.col[j]] = (int32_t)(j - a);
+    return;
+  }
   unsigned long long nh = info[I_LONGROW];
   int hc = nh < (unsigned long long)H_MAX ? (int)nh : H_MAX;
   uint64_t extra = 0, dmx = 0;   // thread 0's
@@ -1448,8 +1465,10 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
                          W.parent, W.degpart, W.htab, info, next_scan(ctx, W));
     }
     TimedScope ts(ctx, "degree_total", (double)nb);
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(SP_BS), 0, st, W.degpart, (int64_t)nb, g, W.htab, W.deg,
-                       info);
+    // (with the long rows' position maps for the scores, when rows can be long)
+    int sp_grid = 1 + (g.nnz > HUGE_T ? H_MAX * SP_MAP : 0);
+    hipLaunchKernelGGL(k_sum_parts, dim3(sp_grid), dim3(SP_BS), 0, st, W.degpart, (int64_t)nb, g, W.htab, W.deg,
+                       info, W.hmap);
   }
   SPC_LAUNCH_CHECK(ctx, "degree");
   int rc;
