@@ -207,7 +207,7 @@ int seg_cutoff_union(spc_ctx* ctx, const LevelIn& g, LevelWork& W, const LevelRe
   // only when the level's keys are guarded (info[I_GUARD])
   const KeyND* exact = rank ? nullptr : W.keysA;
   hipLaunchKernelGGL(k_seg_select, dim3((unsigned)seg.G), dim3(SEL_BS), 0, st, fkey, fidx, seg.off, seg.k,
-                     W.msfO, W.parent, g, W.deg, W.lc, exact, W.kexact, ebits, W.info);
+                     W.msfO, W.root, g, W.deg, W.lc, exact, W.kexact, ebits, W.info);
   SPC_LAUNCH_CHECK(ctx, "batched cutoff");
   return SPC_OK;
 }

@@ -235,6 +235,21 @@ __device__ __forceinline__ void lbs_tile(const int64_t* __restrict__ ptr, int64_
 // union-find with hooking of the larger root under the smaller one, so the
 // root of every tree is its smallest member
 // ---------------------------------------------------------------------------
+// The root of x given p, a value of parent[x] already read (parent
+// pointers only ever move towards the root, so any earlier value will do).
+__device__ __forceinline__ int32_t uf_find_from(int32_t* parent, int32_t x, int32_t p) {
+  while (p != x) {
+    int32_t gp = __hip_atomic_load(&parent[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (gp != p) {
+      // path halving: parent pointers only ever move towards the root
+      __hip_atomic_store(&parent[x], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    x = p;
+    p = gp;
+  }
+  return x;
+}
+
 __device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t x) {
   int32_t p = __hip_atomic_load(&parent[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   while (p != x) {

@@ -221,7 +221,7 @@ constexpr int FD_SHORT = 64;
 __global__ void __launch_bounds__(BS)
     k_fp_degree(LevelInF g, double* __restrict__ deg, int32_t* __restrict__ lc, int64_t* __restrict__ ucnt,
                 uint64_t* __restrict__ bestA, uint64_t* __restrict__ bestB, int32_t* __restrict__ parent,
-                const unsigned long long* info) {
+                int32_t* __restrict__ cc, const unsigned long long* info) {
   __shared__ int stmp[BS / WAVE];
   __shared__ int32_t slong[FD_ROWS];
   __shared__ uint64_t schunk[BS / WAVE][FP_LIMBS];
@@ -254,6 +254,7 @@ __global__ void __launch_bounds__(BS)
     bestA[u] = KEY_INF;
     bestB[u] = KEY_INF;
     parent[u] = (int32_t)u;
+    cc[u] = (int32_t)u;
   }
   int total_long;
   int p = block_incl_scan<int, BS, false>(nlong, stmp, &total_long) - nlong;
@@ -495,7 +496,7 @@ void launch_fp_degree(spc_ctx* ctx, const LevelInF& g, LevelWork& W) {
                      W.info);
   hipLaunchKernelGGL(k_fp_span, dim3(1), dim3(1), 0, st, W.info);
   hipLaunchKernelGGL(k_fp_degree, dim3(grid_for(g.n, FD_ROWS)), dim3(BS), 0, st, g, (double*)W.deg, W.lc,
-                     W.uptr, W.bestA, W.bestB, W.parent, W.info);
+                     W.uptr, W.bestA, W.bestB, W.parent, W.root, W.info);
 }
 
 int fp_rank_keys(spc_ctx* ctx, const LevelInF& g, LevelWork& W, int64_t m) {

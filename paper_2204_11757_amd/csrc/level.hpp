@@ -179,7 +179,7 @@ struct LevelWork {
   uint64_t* msfP;            // [n]
   uint64_t* msfO;            // [n]
   int32_t* msfC;             // [n]  root hooked by each forest edge
-  int32_t* root;             // [n]
+  int32_t* root;             // [n] union-find of the merge cutoff's components
   int32_t* flag;             // [n+1]
   SelState* sel;
   SelState* sel2;
@@ -282,7 +282,7 @@ void launch_rank_scatter(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int
                          const KeyND* sorted);
 // Pc from P (an edge's rank into both of its CSR entries)
 void launch_rank_mirror(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t m);
-// cluster_of[x] = label of x's component root (W.root, labels in W.flag,
+// cluster_of[x] = label of x's component root (W.parent, labels in W.flag,
 // clamped to [0, t)); with eps, also info[I_EPS] = exact score of the forest
 // edge whose key equals sel2's cutoff.  One launch.
 void launch_relabel_eps(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int32_t* cluster_of, int64_t t,

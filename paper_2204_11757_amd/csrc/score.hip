@@ -285,7 +285,7 @@ void launch_rank_scatter(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int
 void launch_relabel_eps(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int32_t* cluster_of, int64_t t,
                         int64_t msf_bound, bool eps) {
   int64_t items = g.n > msf_bound ? g.n : msf_bound;
-  hipLaunchKernelGGL(k_relabel_eps, dim3(grid_for(items, 256)), dim3(256), 0, ctx->stream, g, W.root, W.flag,
+  hipLaunchKernelGGL(k_relabel_eps, dim3(grid_for(items, 256)), dim3(256), 0, ctx->stream, g, W.parent, W.flag,
                      cluster_of, t, W.deg, W.lc, W.msfP, W.msfO,
                      eps ? (const unsigned long long*)&W.info[I_MSF] : (const unsigned long long*)nullptr,
                      W.sel2, (double*)&W.info[I_EPS]);

@@ -101,7 +101,7 @@ void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W, bool fp) {
 __global__ void __launch_bounds__(BS)
     k_degree(LevelIn g, uint64_t* __restrict__ deg, int32_t* __restrict__ lc,
              int64_t* __restrict__ uptr, uint64_t* __restrict__ bestA,
-             uint64_t* __restrict__ bestB, int32_t* __restrict__ parent,
+             uint64_t* __restrict__ bestB, int32_t* __restrict__ parent, int32_t* __restrict__ cc,
              uint64_t* __restrict__ part, int32_t* __restrict__ htab, unsigned long long* info,
              TileScan ts) {
   __shared__ int stmp[BS / WAVE];
@@ -168,7 +168,8 @@ __global__ void __launch_bounds__(BS)
     }
     bestA[u] = KEY_INF;
     bestB[u] = KEY_INF;
-    parent[u] = (int32_t)u;
+    parent[u] = (int32_t)u;   // the spanning forest's union-find
+    cc[u] = (int32_t)u;       // the merge cutoff's components
   }
   // uptr: exclusive prefix of the upper-entry counts in row order (the
   // edge id of each row's first upper entry), block offsets chained by a
@@ -470,6 +471,7 @@ __global__ void __launch_bounds__(BS)
 // ---------------------------------------------------------------------------
 constexpr int BV_LONG = 16;
 constexpr int BV_SHORT = 4;
+constexpr int BV_BATCH = 4;   // items whose loads a thread issues together
 constexpr int64_t BV_SHORT_MAX = 1000000;   // lists up to this many items use BV_SHORT
 constexpr int BC_CHUNK = 1024;
 constexpr int BC_PER = BC_CHUNK / BS;
@@ -500,7 +502,11 @@ __global__ void __launch_bounds__(BS)
                const unsigned long long* guard, int ebits, int* viol, TileScan ts,
                unsigned long long* rounds) {
   constexpr int CHUNK = PER * BS;
-  constexpr bool SIDE = PER <= BV_SHORT;   // all of a thread's loads of one kind at once
+  // the items are taken HB at a time, all of a batch's loads of one kind
+  // issued together (a thread's chain of dependent loads is PER / HB
+  // batches long, not PER items)
+  constexpr int HB = PER < BV_BATCH ? PER : BV_BATCH;
+  static_assert(PER % HB == 0, "whole batches");
   __shared__ int stmp[BS / WAVE];
   __shared__ unsigned long long sbase;
   int64_t n = (int64_t)*cnt;
@@ -512,57 +518,48 @@ __global__ void __launch_bounds__(BS)
     atomicAdd(rounds + (I_MIN - I_ROUNDS), (unsigned long long)n);
   }
   if (keys && !*guard) keys = nullptr;
-  uint64_t suv[SIDE ? PER : 1], skey[SIDE ? PER : 1], swa[SIDE ? PER : 1], swb[SIDE ? PER : 1];
-  if constexpr (SIDE) {
-#pragma unroll
-    for (int i = 0; i < PER; i++) {
-      int64_t idx = base + tid + i * BS;
-      suv[i] = idx < n ? lr[idx] : 0;
-      skey[i] = idx < n ? lp[idx] : KEY_INF;
-    }
-#pragma unroll
-    for (int i = 0; i < PER; i++) {
-      int64_t idx = base + tid + i * BS;
-      swa[i] = idx < n ? best[(int32_t)(uint32_t)suv[i]] : KEY_INF;
-      swb[i] = idx < n ? best[(int32_t)(suv[i] >> 32)] : KEY_INF;
-    }
-  }
   uint32_t chosen = 0;
   int nc = 0;
   int32_t hooked[PER];
 #pragma unroll
-  for (int i = 0; i < PER; i++) {
-    int64_t idx = base + tid + i * BS;
-    hooked[i] = 0;
-    if (idx >= n) break;
-    uint64_t uv, key, wa, wb;
-    if constexpr (SIDE) {
-      uv = suv[i];
-      key = skey[i];
-      wa = swa[i];
-      wb = swb[i];
-    } else {
-      uv = lr[idx];
-      key = lp[idx];
-      wa = best[(int32_t)(uint32_t)uv];
-      wb = best[(int32_t)(uv >> 32)];
+  for (int b0 = 0; b0 < PER; b0 += HB) {
+    uint64_t suv[HB], skey[HB], swa[HB], swb[HB];
+#pragma unroll
+    for (int q = 0; q < HB; q++) {
+      int64_t idx = base + tid + (b0 + q) * BS;
+      suv[q] = idx < n ? lr[idx] : 0;
+      skey[q] = idx < n ? lp[idx] : KEY_INF;
     }
-    int32_t a = (int32_t)(uint32_t)uv, b = (int32_t)(uv >> 32);
-    if (keys) {
-      guard_check(keys, kexact, ebits, key, wa, viol);
-      guard_check(keys, kexact, ebits, key, wb, viol);
+#pragma unroll
+    for (int q = 0; q < HB; q++) {
+      int64_t idx = base + tid + (b0 + q) * BS;
+      swa[q] = idx < n ? best[(int32_t)(uint32_t)suv[q]] : KEY_INF;
+      swb[q] = idx < n ? best[(int32_t)(suv[q] >> 32)] : KEY_INF;
     }
-    bool ca = wa == key, cb = wb == key;
-    if (ca || cb) {
-      // a and b are roots at the start of this round and each root adopts
-      // exactly one edge, so each root's parent is written at most once;
-      // when both adopt this edge the smaller id stays the root
-      int32_t child = (ca && cb) ? (a > b ? a : b) : (ca ? a : b);
-      int32_t to = (ca && cb) ? (a > b ? b : a) : (ca ? b : a);
-      __hip_atomic_store(&parent[child], to, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      hooked[i] = child;
-      chosen |= 1u << i;
-      nc++;
+#pragma unroll
+    for (int q = 0; q < HB; q++) {
+      int i = b0 + q;
+      int64_t idx = base + tid + i * BS;
+      hooked[i] = 0;
+      if (idx >= n) continue;
+      uint64_t uv = suv[q], key = skey[q], wa = swa[q], wb = swb[q];
+      int32_t a = (int32_t)(uint32_t)uv, b = (int32_t)(uv >> 32);
+      if (keys) {
+        guard_check(keys, kexact, ebits, key, wa, viol);
+        guard_check(keys, kexact, ebits, key, wb, viol);
+      }
+      bool ca = wa == key, cb = wb == key;
+      if (ca || cb) {
+        // a and b are roots at the start of this round and each root adopts
+        // exactly one edge, so each root's parent is written at most once;
+        // when both adopt this edge the smaller id stays the root
+        int32_t child = (ca && cb) ? (a > b ? a : b) : (ca ? a : b);
+        int32_t to = (ca && cb) ? (a > b ? b : a) : (ca ? b : a);
+        __hip_atomic_store(&parent[child], to, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        hooked[i] = child;
+        chosen |= 1u << i;
+        nc++;
+      }
     }
   }
   int64_t pos = block_reserve_lb<BS>(ts, blockIdx.x, base + CHUNK >= n, nc, msfcnt, msfcnt,
@@ -646,14 +643,29 @@ __global__ void __launch_bounds__(BS)
   uint32_t keep = 0;
   int nk = 0;
   uint64_t ruv[BC_PER];
+  // the items' words, then their endpoints' first parent steps, are each
+  // loaded together; the lookups continue from there
+  uint64_t suv[BC_PER], skey[BC_PER];
+  int32_t pa[BC_PER], pb[BC_PER];
+#pragma unroll
+  for (int i = 0; i < BC_PER; i++) {
+    int64_t idx = base + tid + i * BS;
+    suv[i] = idx < n ? lr_in[idx] : 0;
+    skey[i] = idx < n ? lp_in[idx] : KEY_INF;
+  }
+#pragma unroll
+  for (int i = 0; i < BC_PER; i++) {
+    pa[i] = __hip_atomic_load(&parent[(int32_t)(uint32_t)suv[i]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    pb[i] = __hip_atomic_load(&parent[(int32_t)(suv[i] >> 32)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   for (int i = 0; i < BC_PER; i++) {
     ruv[i] = 0;
     int64_t idx = base + tid + i * BS;
     if (idx >= n) break;
-    uint64_t uv = lr_in[idx];
-    uint64_t key = lp_in[idx];
-    int32_t a = uf_find(parent, (int32_t)(uint32_t)uv);
-    int32_t b = uf_find(parent, (int32_t)(uv >> 32));
+    uint64_t uv = suv[i];
+    uint64_t key = skey[i];
+    int32_t a = uf_find_from(parent, (int32_t)(uint32_t)uv, pa[i]);
+    int32_t b = uf_find_from(parent, (int32_t)(uv >> 32), pb[i]);
     if (a != b) {
       atomicMin((unsigned long long*)&cur[a], (unsigned long long)key);
       atomicMin((unsigned long long*)&cur[b], (unsigned long long)key);
@@ -682,30 +694,34 @@ __global__ void __launch_bounds__(BS)
   }
 }
 
-// After the cutoff selection: the union-find array is reset to the
-// identity for the components pass, and with guarded keys every forest edge
-// sharing the cutoff's K bucket must have exactly the cutoff's score (then
-// the edge order inside the bucket is the exact one).  keys null: no check.
-__global__ void k_cutoff_prep(const uint64_t* __restrict__ msfP, const unsigned long long* cnt,
-                              const SelState* st, const KeyND* __restrict__ keys,
-                              const uint64_t* __restrict__ kexact, const unsigned long long* guard,
-                              int ebits, int* viol, int32_t* __restrict__ parent, int64_t nn,
-                              int32_t* __restrict__ zero_a, int64_t* __restrict__ zero_b, int64_t nz) {
+// After the cutoff selection, one launch: the components of the forest
+// edges up to the cutoff T (union-find in cc, which holds the identity from
+// the degree pass), the contraction's member counts and gather prefix set to
+// zero, and with guarded keys the check that every forest edge sharing T's K
+// bucket has exactly T's score (then the edge order inside the bucket is the
+// exact one; keys null: no check).
+__global__ void k_cutoff_union(const uint64_t* __restrict__ msfP, const uint64_t* __restrict__ msfO,
+                               const unsigned long long* cnt, const SelState* st, const KeyND* __restrict__ keys,
+                               const uint64_t* __restrict__ kexact, const unsigned long long* guard, int ebits,
+                               int* viol, int32_t* cc, int32_t* __restrict__ zero_a,
+                               int64_t* __restrict__ zero_b, int64_t nz) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int64_t x = i0; x < nn; x += stride) parent[x] = (int32_t)x;
-  // (and the contraction's member counts and gather prefix start at zero)
   for (int64_t x = i0; x < nz; x += stride) {
     zero_a[x] = 0;
     zero_b[x] = 0;
   }
-  if (!keys || !*guard) return;
   int64_t n = (int64_t)*cnt;
   uint64_t T = st->prefix;
+  bool check = keys && *guard;
   uint64_t emask = (1ull << ebits) - 1;
   for (int64_t i = i0; i < n; i += stride) {
     uint64_t p = msfP[i];
-    if (p == T || (p >> ebits) != (T >> ebits)) continue;
+    if (p <= T) {
+      uint64_t uv = msfO[i];
+      uf_union(cc, (int32_t)(uint32_t)uv, (int32_t)(uv >> 32));
+    }
+    if (!check || p == T || (p >> ebits) != (T >> ebits)) continue;
     if (key_exact(kexact, p & emask) && key_exact(kexact, T & emask)) continue;   // equal scores
     KeyND x = keys[p & emask], y = keys[T & emask];
     if ((unsigned __int128)x.N * y.D != (unsigned __int128)y.N * x.D) *viol = 1;
@@ -720,26 +736,13 @@ __global__ void k_iota(int32_t* __restrict__ a, int64_t n) {
   if (i < n) a[i] = (int32_t)i;
 }
 
-__global__ void k_cc_union(const uint64_t* __restrict__ msfP, const uint64_t* __restrict__ msfO,
-                           const unsigned long long* cnt, const SelState* thr, int32_t* parent) {
-  int64_t n = (int64_t)*cnt;
-  uint64_t T = thr->prefix;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    if (msfP[i] <= T) {
-      uint64_t uv = msfO[i];
-      uf_union(parent, (int32_t)(uint32_t)uv, (int32_t)(uv >> 32));
-    }
-  }
-}
 
-// Every node's root, and a flag on each root (its number among the roots
-// in id order is the flags' exclusive scan).
-__global__ void k_cc_flatten(int32_t* parent, int32_t* __restrict__ root, int32_t* __restrict__ flag,
-                             int64_t n) {
+// Every node's root in the union-find uf (into root), and a flag on each
+// root (its number among the roots in id order is the flags' exclusive scan).
+__global__ void k_cc_flatten(int32_t* uf, int32_t* __restrict__ root, int32_t* __restrict__ flag, int64_t n) {
   int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (x < n) {
-    int32_t r = uf_find(parent, (int32_t)x);
+    int32_t r = uf_find(uf, (int32_t)x);
     root[x] = r;
     flag[x] = (r == (int32_t)x) ? 1 : 0;
   }
@@ -1429,9 +1432,9 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
                           glo ? thr_hi : nullptr);
     if (rc) return rc;
   }
-  hipLaunchKernelGGL(k_cutoff_prep, dim3(grid_for(n, 256)), dim3(256), 0, st, W.msfP,
-                     &info[I_MSF], W.sel2, rank ? (const KeyND*)nullptr : (const KeyND*)W.keysA, W.kexact, guard,
-                     ebits, (int*)&info[I_VIOL], W.parent, n, W.mcount, W.gptr, t + 1);
+  hipLaunchKernelGGL(k_cutoff_union, dim3(grid_for(n, 256, ctx->num_cus * 8)), dim3(256), 0, st, W.msfP,
+                     W.msfO, &info[I_MSF], W.sel2, rank ? (const KeyND*)nullptr : (const KeyND*)W.keysA, W.kexact,
+                     guard, ebits, (int*)&info[I_VIOL], W.root, W.mcount, W.gptr, t + 1);
   R.contract_zeroed = true;
   SPC_LAUNCH_CHECK(ctx, "cutoff check");
   return SPC_OK;
@@ -1462,7 +1465,7 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
     {
       TimedScope ts(ctx, "degree", (double)n);
       hipLaunchKernelGGL(k_degree, dim3(nb), dim3(BS), 0, st, g, W.deg, W.lc, W.uptr, W.bestA, W.bestB,
-                         W.parent, W.degpart, W.htab, info, next_scan(ctx, W));
+                         W.parent, W.root, W.degpart, W.htab, info, next_scan(ctx, W));
     }
     TimedScope ts(ctx, "degree_total", (double)nb);
     // (with the long rows' position maps for the scores, when rows can be long)
@@ -1501,6 +1504,7 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
       for (int i = I_ROUNDS; i <= I_MSF0; i++) slots |= 1u << i;
       launch_clear(ctx, nullptr, 0, nullptr, 0, info, slots);
       hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256)), dim3(256), 0, st, W.parent, n);
+      hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256)), dim3(256), 0, st, W.root, n);
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestA, n, KEY_INF);
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestB, n, KEY_INF);
     }
@@ -1510,17 +1514,15 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
     int64_t msf_bound = R.msf >= 0 ? R.msf : n;
     {
       TimedScope ts(ctx, "components", (double)n);
+      // (the whole-graph path joined its cutoff's forest edges in the
+      // cutoff's launch; a batch joins each graph's here)
       if (seg) {
-        // (the whole-graph path reset parent in its cutoff check)
-        hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256)), dim3(256), 0, st, W.parent, n);
         int ebits = bitlen64((uint64_t)(m - 1));
         rc = seg_cutoff_union(ctx, g, W, R, *seg, ebits < 1 ? 1 : ebits, rank);
         if (rc) return rc;
-      } else {
-        hipLaunchKernelGGL(k_cc_union, dim3(grid_for(msf_bound, 256, ctx->num_cus * 8)), dim3(256), 0, st,
-                           W.msfP, W.msfO, &info[I_MSF], W.sel2, W.parent);
       }
-      hipLaunchKernelGGL(k_cc_flatten, dim3(grid_for(n, 256)), dim3(256), 0, st, W.parent, W.root,
+      // roots (into parent, free after the forest) and root flags
+      hipLaunchKernelGGL(k_cc_flatten, dim3(grid_for(n, 256)), dim3(256), 0, st, W.root, W.parent,
                          W.flag, n);
     }
     SPC_LAUNCH_CHECK(ctx, "components");
