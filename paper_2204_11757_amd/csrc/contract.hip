@@ -1092,16 +1092,21 @@ static int contract_huge(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64
 // total and the look-back error flags to the host.
 static int rowptr_and_read(spc_ctx* ctx, const LevelWork& W, spc_graph_out* out, int64_t n_c,
                            const int32_t* x1) {
-  {
+  if (n_c > 0) {
+    // the scan's last tile writes the host's copy (one launch fewer)
     TimedScope ts(ctx, "contract_rowptr", (double)n_c);
+    int rc = exclusive_scan<int64_t>(ctx, W.cnt, out->row_ptr, n_c, (int64_t*)W.scan_partial,
+                                     ScanReadback{W.info, (int)I_NINFO, x1, ctx->h_pinned});
+    if (rc) return rc;
+  } else {
     int rc = exclusive_scan<int64_t>(ctx, W.cnt, out->row_ptr, n_c, (int64_t*)W.scan_partial);
     if (rc) return rc;
+    hipLaunchKernelGGL(k_readback, dim3(1), dim3(64), 0, ctx->stream, W.info, (int)I_NINFO,
+                       (const int64_t*)(out->row_ptr + n_c), x1,
+                       (const uint64_t*)(ctx->scan_state ? ctx->scan_state + ctx->scan_cap - 1 : nullptr),
+                       ctx->h_pinned);
+    SPC_LAUNCH_CHECK(ctx, "readback");
   }
-  hipLaunchKernelGGL(k_readback, dim3(1), dim3(64), 0, ctx->stream, W.info, (int)I_NINFO,
-                     (const int64_t*)(out->row_ptr + n_c), x1,
-                     (const uint64_t*)(ctx->scan_state ? ctx->scan_state + ctx->scan_cap - 1 : nullptr),
-                     ctx->h_pinned);
-  SPC_LAUNCH_CHECK(ctx, "readback");
   SPC_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return SPC_OK;
 }

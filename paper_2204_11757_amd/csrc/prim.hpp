@@ -145,8 +145,19 @@ constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = SCAN_BS * SCAN_ITEMS;
 constexpr int SCAN_MAXB = 1024;   // size of the callers' legacy scratch (unused)
 
+// With rb.out set, the last tile also copies to host-visible memory what the
+// host reads after the scan: rb.ninfo words of rb.info, then the total, *rb.x1
+// (or 0) and the chain's error word, at rb.out[0..ninfo+3).
+struct ScanReadback {
+  const unsigned long long* info;
+  int ninfo;
+  const int32_t* x1;
+  int64_t* out;
+};
+
 template <typename T>
-__global__ void __launch_bounds__(SCAN_BS) k_scan_lb(const T* in, T* out, int64_t n, TileScan ts) {
+__global__ void __launch_bounds__(SCAN_BS)
+    k_scan_lb(const T* in, T* out, int64_t n, TileScan ts, ScanReadback rb) {
   __shared__ T buf[SCAN_TILE];
   __shared__ T tmp[SCAN_BS / WAVE];
   __shared__ T sh_excl;
@@ -173,7 +184,17 @@ __global__ void __launch_bounds__(SCAN_BS) k_scan_lb(const T* in, T* out, int64_
     if (tid == 0) {
       if ((uint64_t)tot > LB_VMASK || ex + (uint64_t)tot > LB_VMASK) atomicOr(ts.err, 1ull);
       sh_excl = (T)ex;
-      if (tile == gridDim.x - 1) out[n] = (T)(ex + (uint64_t)tot);
+      if (tile == gridDim.x - 1) {
+        out[n] = (T)(ex + (uint64_t)tot);
+        if (rb.out) {
+          for (int i = 0; i < rb.ninfo; i++) rb.out[i] = (int64_t)rb.info[i];
+          rb.out[rb.ninfo] = (int64_t)(ex + (uint64_t)tot);
+          rb.out[rb.ninfo + 1] = rb.x1 ? (int64_t)*rb.x1 : 0;
+          rb.out[rb.ninfo + 2] =
+              (int64_t)__hip_atomic_load(ts.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __threadfence_system();
+        }
+      }
     }
   }
   __syncthreads();
@@ -267,7 +288,8 @@ uint32_t scan_state_reserve(spc_ctx* ctx, int64_t words);
 // Host wrapper.  `partial` is unused (kept for callers' scratch layout).
 // in may equal out (each tile reads all of its items before writing).
 template <typename T>
-int exclusive_scan(spc_ctx* ctx, const T* in, T* out, int64_t n, T* partial) {
+int exclusive_scan(spc_ctx* ctx, const T* in, T* out, int64_t n, T* partial,
+                   ScanReadback rb = ScanReadback{nullptr, 0, nullptr, nullptr}) {
   (void)partial;
   if (n <= 0) {
     SPC_HIP(ctx, hipMemsetAsync(out, 0, sizeof(T), ctx->stream));
@@ -277,7 +299,7 @@ int exclusive_scan(spc_ctx* ctx, const T* in, T* out, int64_t n, T* partial) {
   uint32_t epoch = scan_state_reserve(ctx, tiles);
   if (!epoch) return ctx->err_code ? ctx->err_code : SPC_ENOMEM;
   TileScan ts{ctx->scan_state, epoch, (unsigned long long*)(ctx->scan_state + ctx->scan_cap - 1)};
-  hipLaunchKernelGGL(k_scan_lb<T>, dim3((unsigned)tiles), dim3(SCAN_BS), 0, ctx->stream, in, out, n, ts);
+  hipLaunchKernelGGL(k_scan_lb<T>, dim3((unsigned)tiles), dim3(SCAN_BS), 0, ctx->stream, in, out, n, ts, rb);
   SPC_LAUNCH_CHECK(ctx, "exclusive_scan");
   return SPC_OK;
 }

@@ -1241,13 +1241,14 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, boo
     int rounds = batch == 0 ? (speculate && ctx->speculate == 2 ? 1 : ctx->forest_batch) : 2;
     for (int r = 0; r < rounds; r++) {
       int out = in ^ 1;
+      bool mark = false;
       int ci = in == 0 ? I_LIVE0 : I_LIVE1;
       int co = out == 0 ? I_LIVE0 : I_LIVE1;
       {
         TimedScope ts(ctx, "forest_candidates", (double)bound);
         // the last round of a batch the host does not wait for also leaves
         // its live count in info[I_SPEC]
-        bool mark = speculate && batch == 0 && r == rounds - 1;
+        mark = speculate && batch == 0 && r == rounds - 1;
         hipLaunchKernelGGL(k_bv_candidates, dim3(grid_for(bound, BC_CHUNK)), dim3(BS), 0, ctx->stream,
                            W.lr[in], W.lp[in], (in == 0 && lo0_is_lr) ? W.lr[0] : W.lo[in], &info[ci],
                            W.lr[out], W.lp[out], W.lo[out], &info[co], cur, nxt, W.parent,
@@ -1255,6 +1256,13 @@ static int spanning_forest(spc_ctx* ctx, LevelWork& W, int64_t n, int64_t m, boo
                            mark ? &info[I_SPEC] : (unsigned long long*)nullptr);
       }
       if (out == 0) lo0_is_lr = false;
+      if (mark) {
+        // not waited for: the forest counts as complete only when this
+        // lookup left no live edge, so its hooking round would be empty
+        SPC_LAUNCH_CHECK(ctx, "forest round");
+        in = out;
+        break;
+      }
       {
         TimedScope ts(ctx, "forest_merge", (double)bound);
         launch_bv_merge(ctx, W, bound, W.lr[out], W.lp[out], W.lo[out], &info[co], cur, n, guard_keys, ebits);
