@@ -352,7 +352,9 @@ constexpr int SEL_FLAG = 8;      // flag stride (one 64-byte line per block)
 struct SelState {
   unsigned long long prefix, mask;
   unsigned long long ext[2];   // smallest and largest key (written by the one-block path)
+  unsigned long long guess[2];  // likely bounds of a later selection's result (band selections)
   unsigned long long bmn[2][SEL_MAXB], bmx[2][SEL_MAXB];   // extreme matching keys per block
+  unsigned long long bbelow[SEL_MAXB];                     // keys below the guessed range, per block
   unsigned int gsum[2][SEL_MAXB][SEL_NGRP];          // per-block group sums, pass p in [p % 2]
   unsigned int bhist[2][SEL_MAXB][SEL_BINS];         // per-block histograms
   uint64_t buf[SEL_SMALL];                           // gathered keys
@@ -364,9 +366,10 @@ struct SelState {
 // was last reset to 0; every select of that period uses epochs above the
 // previous one's.  thr (nullable): also derive a band threshold from the
 // selected key, in the same launch.  guess_lo / guess_hi (nullable, device
-// words): likely bounds of the keys; the bits they share are taken as
-// decided for the first pass, which counts the keys that share them and
-// starts over without the guess when that is not every key.
+// words): likely bounds of the k-th key; the bits they share are taken as
+// decided for the first pass, which also counts the keys below them and
+// starts over without the guess when the k-th key is not among the keys
+// that share those bits.
 struct ThrSpec;
 int radix_select(spc_ctx* ctx, const uint64_t* keys, const unsigned long long* cnt_dev,
                  int64_t cnt_bound, const unsigned long long* k_dev, unsigned long long k_host,

@@ -810,11 +810,19 @@ __device__ __forceinline__ unsigned int col_part_sum(const unsigned int* a, int 
 // read in edge order, i.e. a run of consecutive rows, whose forest has about
 // one edge per row rather than per candidate: such a band is extended to
 // edge e_tie (chosen to cover k rows).  Only the band's size changes.
+// guess (nullable, two words): where the level's cutoff, the k-th lightest
+// forest edge, most likely lies.  Forest keys lie at or below the band's
+// threshold.  When fewer than qlo_max samples (fewer than about 0.9 k edges)
+// lie below the selected sample's K bucket, the cutoff lies in that bucket,
+// ties included; otherwise the guess is the smallest sample up to the
+// threshold.
 struct ThrSpec {
   unsigned long long* thr;
   unsigned long long* info;
   int c, ebits;
   unsigned long long eq, e_tie;
+  unsigned long long* guess;
+  unsigned long long qlo_max;
 };
 
 __device__ __forceinline__ void band_threshold(const ThrSpec& ts, uint64_t p, bool all) {
@@ -879,6 +887,7 @@ __global__ void __launch_bounds__(SEL_BS)
       for (int b = t; b < SEL_BINS; b += SEL_BS) h[b] = 0;
       __syncthreads();
       uint64_t mn = ~0ull, mx = 0;
+      unsigned long long nbelow = 0;   // keys below the guessed range (guessed pass)
       for (int64_t i0 = (int64_t)B * SEL_BS + t; i0 < n; i0 += stride * SEL_UNROLL) {
         uint64_t kk[SEL_UNROLL];
 #pragma unroll
@@ -888,7 +897,9 @@ __global__ void __launch_bounds__(SEL_BS)
         }
 #pragma unroll
         for (int u = 0; u < SEL_UNROLL; u++) {
-          bool m = i0 + u * stride < n && (kk[u] & mask) == prefix;
+          bool in = i0 + u * stride < n;
+          bool m = in && (kk[u] & mask) == prefix;
+          nbelow += in && (kk[u] & mask) < prefix;
           hist_add(h, m, (uint32_t)((kk[u] >> lo) & dm));
           if (m) {
             mn = kk[u] < mn ? kk[u] : mn;
@@ -897,6 +908,11 @@ __global__ void __launch_bounds__(SEL_BS)
         }
       }
       __syncthreads();
+      if (guessed) {
+        unsigned long long bt;
+        (void)block_incl_scan<unsigned long long, SEL_BS, false>(nbelow, tmp, &bt);
+        if (t == 0) st->bbelow[B] = bt;
+      }
       unsigned int (*bh)[SEL_BINS] = st->bhist[p & 1];
       unsigned int (*gs)[SEL_NGRP] = st->gsum[p & 1];
       for (int b = t; b < SEL_BINS; b += SEL_BS) bh[B][b] = h[b];   // one contiguous row per block
@@ -938,10 +954,18 @@ __global__ void __launch_bounds__(SEL_BS)
       unsigned long long before = block_incl_scan<unsigned long long, SEL_BS, false>(gc, tmp, &total) - gc;
       if (guessed) {
         guessed = false;
-        if (total != (unsigned long long)n) {
-          // some key lies outside the guessed bounds: a pass again over
-          // every key (uniform: every block read the same total), into the
-          // other histogram buffers, which no block still reads
+        unsigned long long bs = 0;
+        for (int j = t; j < G; j += SEL_BS) bs += st->bbelow[j];
+        unsigned long long below;
+        (void)block_incl_scan<unsigned long long, SEL_BS, false>(bs, tmp, &below);
+        if (k >= below && k - below < total) {
+          // the k-th key shares the guessed bits: rank it among those keys
+          k -= below;
+          cb = (int64_t)total;
+        } else {
+          // it lies outside the guessed bounds: a pass again over every key
+          // (uniform: every block read the same counts), into the other
+          // histogram buffers, which no block still reads
           prefix = 0;
           mask = 0;
           hi = bits;
@@ -1048,10 +1072,24 @@ __global__ void __launch_bounds__(SEL_BS)
     }
     __syncthreads();
     uint64_t r = lds_select(sbuf, (int)n, k, h, tmp, red, spick, err, s2, &s2cnt, st->ext);
+    uint64_t kb = r & ~((1ull << tsp.ebits) - 1);   // start of the selected key's K bucket
+    unsigned long long nlo = 0;
+    if (tsp.guess) {
+      unsigned long long c = 0;
+      for (int i = t; i < n; i += SEL_BS) c += sbuf[i] < kb;
+      (void)block_incl_scan<unsigned long long, SEL_BS, false>(c, tmp, &nlo);
+    }
     if (t == 0) {
       st->prefix = r;
       st->mask = ~0ull;
-      if (tsp.thr) band_threshold(tsp, r, false);
+      if (tsp.thr) {
+        band_threshold(tsp, r, false);
+        if (tsp.guess) {
+          bool bucket = nlo < tsp.qlo_max;
+          tsp.guess[0] = bucket ? kb : st->ext[0];
+          tsp.guess[1] = bucket ? (r | ((1ull << tsp.ebits) - 1)) : *tsp.thr;
+        }
+      }
     }
     return;
   }
@@ -1118,7 +1156,7 @@ int radix_select(spc_ctx* ctx, const uint64_t* keys, const unsigned long long* c
   int grid = cnt_bound <= SEL_SMALL ? 1 : grid_for(cnt_bound, SEL_BS * 32, maxb);
   if (grid < 2 && cnt_bound > SEL_SMALL) grid = 2;
   hipLaunchKernelGGL(k_select, dim3(grid), dim3(SEL_BS), 0, ctx->stream, keys, cnt_dev, cnt_bound, k_dev,
-                     k_host, bits, st, flags, epoch0, err, thr ? *thr : ThrSpec{nullptr, nullptr, 0, 1, 0, 0},
+                     k_host, bits, st, flags, epoch0, err, thr ? *thr : ThrSpec{nullptr, nullptr, 0, 1, 0, 0, nullptr, 0},
                      guess_lo, guess_hi);
   SPC_LAUNCH_CHECK(ctx, "radix_select");
   return SPC_OK;
@@ -1362,14 +1400,14 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
       hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(1), 0, st, thr_lo, thr_hi);
     }
     if (all) {
-      hipLaunchKernelGGL(k_thr_all, dim3(1), dim3(1), 0, st, ThrSpec{thr_hi, info, kc, ebits, 0, 0});
+      hipLaunchKernelGGL(k_thr_all, dim3(1), dim3(1), 0, st, ThrSpec{thr_hi, info, kc, ebits, 0, 0, nullptr, 0});
     } else if (!rank) {
       int sh = sample_shift(m);
       int64_t ns = ((m - 1) >> sh) + 1;
       int64_t q = (int64_t)((double)target / (double)(1ll << sh) * 1.05) + 16;
       if (q >= ns) {
         all = true;
-        hipLaunchKernelGGL(k_thr_all, dim3(1), dim3(1), 0, st, ThrSpec{thr_hi, info, kc, ebits, 0, 0});
+        hipLaunchKernelGGL(k_thr_all, dim3(1), dim3(1), 0, st, ThrSpec{thr_hi, info, kc, ebits, 0, 0, nullptr, 0});
       } else {
         TimedScope ts(ctx, "select_threshold", (double)ns);
         // a tied band of consecutive rows needs about k rows: k m / n edges
@@ -1378,7 +1416,10 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
           double rows = 1.1 * (double)k * (double)m / (double)n + 4096.0;
           e_tie = rows >= (double)(m - 1) ? (uint64_t)(m - 1) : (uint64_t)rows;
         }
-        ThrSpec tsp{thr_hi, info, kc, ebits, (unsigned long long)q << sh, (unsigned long long)e_tie};
+        // the cutoff is taken to lie in the selected sample's K bucket when
+        // fewer than about 0.9 k edges lie below that bucket
+        ThrSpec tsp{thr_hi, info, kc, ebits, (unsigned long long)q << sh, (unsigned long long)e_tie,
+                    W.sel->guess, (unsigned long long)(0.9 * (double)k) >> sh};
         int rc = radix_select(ctx, W.samples, nullptr, ns, nullptr, (unsigned long long)q, 64, W.sel,
                               (unsigned long long*)W.selflag, &info[I_LBERR], &tsp);
         if (rc) return rc;
@@ -1429,15 +1470,18 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
     int bits = rank ? bitlen64((uint64_t)(m - 1)) : 64;
     // sized for the forest's record count when the host read it (else for n)
     int64_t nf = R.spec ? n : R.msf > 1 ? R.msf : 1;
-    // forest keys lie at or below the last band's threshold, and most
-    // likely at or above the smallest key sample (checked by the selection)
-    const unsigned long long* glo = sampled && !rank ? &W.sel->ext[0] : nullptr;
-    // (a test option substitutes the band's selected sample, above many
-    // forest keys, so that the selection takes its start-over path)
-    if (glo && ctx->force_bad_guess) glo = &W.sel->prefix;
+    // bounds the band's sample selection guessed for the cutoff (checked by
+    // the selection)
+    const unsigned long long* glo = sampled && !rank ? &W.sel->guess[0] : nullptr;
+    if (glo && ctx->force_bad_guess) {
+      // (a test option: bounds above every forest key, so that the
+      // selection takes its start-over path)
+      hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, &W.sel->guess[0], ~0ull - 1);
+      hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, &W.sel->guess[1], ~0ull);
+    }
     int rc = radix_select(ctx, W.msfP, &info[I_MSF], nf, nullptr, (unsigned long long)(k - 1), bits,
                           W.sel2, (unsigned long long*)W.selflag, &info[I_LBERR], nullptr, glo,
-                          glo ? thr_hi : nullptr);
+                          glo ? &W.sel->guess[1] : nullptr);
     if (rc) return rc;
   }
   hipLaunchKernelGGL(k_cutoff_union, dim3(grid_for(n, 256, ctx->num_cus * 8)), dim3(256), 0, st, W.msfP,
