@@ -126,9 +126,9 @@ int spc_set_allocator(spc_ctx* ctx, void* (*alloc)(size_t, void*), void (*free_)
  *   "redo_rank"   1: treat every packed-key level as if one of its guarded
  *                 decisions had failed, so that it is redone with rank keys
  *                 (the fallback path).
- *   "bad_select_guess" 1: give the merge cutoff's selection key bounds that
- *                 some forest keys lie outside, so that it starts over (the
- *                 selection's fallback path).
+ *   "bad_select_guess" 1: give the merge cutoff's selection key bounds above
+ *                 every forest key, so that the cutoff lies below them and the
+ *                 selection starts over (its fallback path).
  *   "speculate"   whether the host waits for the first batch of spanning-
  *                 forest rounds: 0 (default) not when the previous level's
  *                 forest was complete after it, 1 always, 2 never (and that

@@ -150,8 +150,11 @@ def test_inexact_key_fallback_redoes_the_level(P):
 
 def test_cutoff_selection_start_over(P):
     # the merge cutoff's selection starts from bounds guessed from the key
-    # samples; keys outside them make it start over, which must not change
-    # anything (forests of more than 16,384 edges take the multi-block path)
+    # samples (the selected sample's K bucket, or the smallest sample up to
+    # the band threshold); a cutoff outside them makes it start over, which
+    # must not change anything (forests of more than 16,384 edges take the
+    # multi-block path; the tied-bucket guess itself runs on the bench
+    # workload's levels 2-5 in the full-size test)
     try:
         P.set_option("bad_select_guess", 1)
         g = trimesh(160, ("uniform", 1, 8), seed=23)
