@@ -376,7 +376,8 @@ int spc_create(spc_ctx** out, int device, void* stream) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     ctx->num_cus = cus;
-  if (hipHostMalloc((void**)&ctx->h_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+  // coherent: the host polls a word that a running kernel writes
+  if (hipHostMalloc((void**)&ctx->h_pinned, 4096, hipHostMallocCoherent) != hipSuccess) {
     delete ctx;
     return SPC_ENOMEM;
   }

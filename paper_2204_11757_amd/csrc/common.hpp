@@ -312,7 +312,8 @@ struct spc_ctx {
   void* alloc_user = nullptr;
   void* ws = nullptr;
   size_t ws_cap = 0;
-  int64_t* h_pinned = nullptr;  // pinned readback area
+  int64_t* h_pinned = nullptr;  // pinned readback area (host-coherent)
+  int64_t rb_token = 0;         // last token a readback published in h_pinned
   int err_code = 0;
   std::string err;
   int num_cus = 256;

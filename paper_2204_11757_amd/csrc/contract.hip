@@ -1090,14 +1090,34 @@ static int contract_huge(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64
 
 // Coarse row pointer from the row counts, then the info block, the entry
 // total and the look-back error flags to the host.
+// Waits until the readback published `token` in the pinned area: its copy
+// is complete then, and later launches stay ordered on the stream behind the
+// kernel's remaining work.  A stream that ends or fails without the token
+// is synchronised for its status.
+static int wait_token(spc_ctx* ctx, int64_t token) {
+  int64_t* w = ctx->h_pinned + I_NINFO + 3;
+  for (long spins = 1;; spins++) {
+    if (__atomic_load_n(w, __ATOMIC_ACQUIRE) == token) return SPC_OK;
+    if ((spins & 4095) == 0 && hipStreamQuery(ctx->stream) != hipErrorNotReady) {
+      SPC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+      if (__atomic_load_n(w, __ATOMIC_ACQUIRE) == token) return SPC_OK;
+      return set_error(ctx, SPC_EHIP, "the row-pointer scan ended without its readback");
+    }
+  }
+}
+
 static int rowptr_and_read(spc_ctx* ctx, const LevelWork& W, spc_graph_out* out, int64_t n_c,
                            const int32_t* x1) {
   if (n_c > 0) {
-    // the scan's last tile writes the host's copy (one launch fewer)
+    // the scan's last tile writes the host's copy (one launch fewer) and
+    // then a new token, which the host polls
     TimedScope ts(ctx, "contract_rowptr", (double)n_c);
+    int64_t token = ++ctx->rb_token;
     int rc = exclusive_scan<int64_t>(ctx, W.cnt, out->row_ptr, n_c, (int64_t*)W.scan_partial,
-                                     ScanReadback{W.info, (int)I_NINFO, x1, ctx->h_pinned});
+                                     ScanReadback{W.info, (int)I_NINFO, x1, ctx->h_pinned, token});
     if (rc) return rc;
+    SPC_LAUNCH_CHECK(ctx, "row-pointer scan");
+    return wait_token(ctx, token);
   } else {
     int rc = exclusive_scan<int64_t>(ctx, W.cnt, out->row_ptr, n_c, (int64_t*)W.scan_partial);
     if (rc) return rc;

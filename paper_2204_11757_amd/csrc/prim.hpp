@@ -147,12 +147,15 @@ constexpr int SCAN_MAXB = 1024;   // size of the callers' legacy scratch (unused
 
 // With rb.out set, the last tile also copies to host-visible memory what the
 // host reads after the scan: rb.ninfo words of rb.info, then the total, *rb.x1
-// (or 0) and the chain's error word, at rb.out[0..ninfo+3).
+// (or 0) and the chain's error word, at rb.out[0..ninfo+3); then, after a
+// system-scope fence, rb.token (when nonzero) at rb.out[ninfo+3], which the
+// host polls instead of waiting for the stream.
 struct ScanReadback {
   const unsigned long long* info;
   int ninfo;
   const int32_t* x1;
   int64_t* out;
+  int64_t token;
 };
 
 template <typename T>
@@ -193,6 +196,8 @@ __global__ void __launch_bounds__(SCAN_BS)
           rb.out[rb.ninfo + 2] =
               (int64_t)__hip_atomic_load(ts.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           __threadfence_system();
+          if (rb.token)
+            __hip_atomic_store(&rb.out[rb.ninfo + 3], rb.token, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         }
       }
     }
@@ -289,7 +294,7 @@ uint32_t scan_state_reserve(spc_ctx* ctx, int64_t words);
 // in may equal out (each tile reads all of its items before writing).
 template <typename T>
 int exclusive_scan(spc_ctx* ctx, const T* in, T* out, int64_t n, T* partial,
-                   ScanReadback rb = ScanReadback{nullptr, 0, nullptr, nullptr}) {
+                   ScanReadback rb = ScanReadback{nullptr, 0, nullptr, nullptr, 0}) {
   (void)partial;
   if (n <= 0) {
     SPC_HIP(ctx, hipMemsetAsync(out, 0, sizeof(T), ctx->stream));
