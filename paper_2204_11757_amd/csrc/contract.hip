@@ -1051,11 +1051,8 @@ static int contract_huge(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64
                        W.hmrow, W.hmrs, hpre, n, self_out, A, &info[I_LIVE1], next_scan(ctx, W));
     SPC_LAUNCH_CHECK(ctx, "huge gather");
   }
-  hipLaunchKernelGGL(k_readback, dim3(1), dim3(64), 0, st, (const unsigned long long*)nullptr, 0,
-                     (const int64_t*)&info[I_LIVE1], (const int32_t*)nullptr, (const uint64_t*)nullptr,
-                     hinfo);
-  SPC_LAUNCH_CHECK(ctx, "readback");
-  SPC_HIP(ctx, hipStreamSynchronize(st));
+  rc = readback_wait(ctx, nullptr, 0, (const int64_t*)&info[I_LIVE1]);
+  if (rc) return rc;
   int64_t G = hinfo[I_NINFO];
   KW* sorted = A;
   if (G > 0) {
@@ -1090,22 +1087,6 @@ static int contract_huge(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64
 
 // Coarse row pointer from the row counts, then the info block, the entry
 // total and the look-back error flags to the host.
-// Waits until the readback published `token` in the pinned area: its copy
-// is complete then, and later launches stay ordered on the stream behind the
-// kernel's remaining work.  A stream that ends or fails without the token
-// is synchronised for its status.
-static int wait_token(spc_ctx* ctx, int64_t token) {
-  int64_t* w = ctx->h_pinned + I_NINFO + 3;
-  for (long spins = 1;; spins++) {
-    if (__atomic_load_n(w, __ATOMIC_ACQUIRE) == token) return SPC_OK;
-    if ((spins & 4095) == 0 && hipStreamQuery(ctx->stream) != hipErrorNotReady) {
-      SPC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-      if (__atomic_load_n(w, __ATOMIC_ACQUIRE) == token) return SPC_OK;
-      return set_error(ctx, SPC_EHIP, "the row-pointer scan ended without its readback");
-    }
-  }
-}
-
 static int rowptr_and_read(spc_ctx* ctx, const LevelWork& W, spc_graph_out* out, int64_t n_c,
                            const int32_t* x1) {
   if (n_c > 0) {
@@ -1118,17 +1099,11 @@ static int rowptr_and_read(spc_ctx* ctx, const LevelWork& W, spc_graph_out* out,
     if (rc) return rc;
     SPC_LAUNCH_CHECK(ctx, "row-pointer scan");
     return wait_token(ctx, token);
-  } else {
-    int rc = exclusive_scan<int64_t>(ctx, W.cnt, out->row_ptr, n_c, (int64_t*)W.scan_partial);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_readback, dim3(1), dim3(64), 0, ctx->stream, W.info, (int)I_NINFO,
-                       (const int64_t*)(out->row_ptr + n_c), x1,
-                       (const uint64_t*)(ctx->scan_state ? ctx->scan_state + ctx->scan_cap - 1 : nullptr),
-                       ctx->h_pinned);
-    SPC_LAUNCH_CHECK(ctx, "readback");
   }
-  SPC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  return SPC_OK;
+  int rc = exclusive_scan<int64_t>(ctx, W.cnt, out->row_ptr, n_c, (int64_t*)W.scan_partial);
+  if (rc) return rc;
+  return readback_wait(ctx, W.info, (int)I_NINFO, (const int64_t*)(out->row_ptr + n_c), x1,
+                       (const uint64_t*)(ctx->scan_state ? ctx->scan_state + ctx->scan_cap - 1 : nullptr));
 }
 
 // At most this many huge rows take the path without a host wait after the
@@ -1219,10 +1194,8 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
       if (rc) return rc;
     }
   } else {
-    hipLaunchKernelGGL(k_readback, dim3(1), dim3(64), 0, st, info, (int)I_NINFO, (const int64_t*)nullptr, x1,
-                       (const uint64_t*)nullptr, hinfo);
-    SPC_LAUNCH_CHECK(ctx, "readback");
-    SPC_HIP(ctx, hipStreamSynchronize(st));
+    rc = readback_wait(ctx, info, (int)I_NINFO, nullptr, x1);
+    if (rc) return rc;
     if (R.pending) {
       rc = finish_select(ctx, R, n_c, R.pending_rank, false, seg);
       if (rc) return rc;

@@ -1187,7 +1187,7 @@ void launch_clear(spc_ctx* ctx, int32_t* a, int64_t na, uint64_t* b, int64_t nb,
 }
 
 __global__ void k_readback(const unsigned long long* info, int ninfo, const int64_t* x0,
-                           const int32_t* x1, const uint64_t* x2, int64_t* out) {
+                           const int32_t* x1, const uint64_t* x2, int64_t* out, int64_t token) {
   int t = threadIdx.x;
   if (info && t < ninfo) out[t] = (int64_t)info[t];
   if (t == 0) {
@@ -1196,6 +1196,29 @@ __global__ void k_readback(const unsigned long long* info, int ninfo, const int6
     out[I_NINFO + 2] = x2 ? (int64_t)*x2 : 0;
   }
   __threadfence_system();
+  __syncthreads();
+  if (t == 0 && token) __hip_atomic_store(&out[I_NINFO + 3], token, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+int wait_token(spc_ctx* ctx, int64_t token) {
+  int64_t* w = ctx->h_pinned + I_NINFO + 3;
+  for (long spins = 1;; spins++) {
+    if (__atomic_load_n(w, __ATOMIC_ACQUIRE) == token) return SPC_OK;
+    if ((spins & 4095) == 0 && hipStreamQuery(ctx->stream) != hipErrorNotReady) {
+      SPC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+      if (__atomic_load_n(w, __ATOMIC_ACQUIRE) == token) return SPC_OK;
+      return set_error(ctx, SPC_EHIP, "a kernel ended without its readback");
+    }
+  }
+}
+
+int readback_wait(spc_ctx* ctx, const unsigned long long* info, int ninfo, const int64_t* x0, const int32_t* x1,
+                  const uint64_t* x2) {
+  int64_t token = ++ctx->rb_token;
+  hipLaunchKernelGGL(k_readback, dim3(1), dim3(64), 0, ctx->stream, info, ninfo, x0, x1, x2, ctx->h_pinned,
+                     token);
+  SPC_LAUNCH_CHECK(ctx, "readback");
+  return wait_token(ctx, token);
 }
 
 __global__ void k_copy_u64(unsigned long long* dst, const unsigned long long* src) { *dst = *src; }
@@ -1211,11 +1234,7 @@ __global__ void k_thr_all(ThrSpec ts) { band_threshold(ts, 0, true); }
 // Info block (and up to three scalars) to the pinned host copy, then wait.
 static int sync_info(spc_ctx* ctx, const LevelWork& W, const int64_t* x0 = nullptr,
                      const int32_t* x1 = nullptr, const uint64_t* x2 = nullptr) {
-  hipLaunchKernelGGL(k_readback, dim3(1), dim3(64), 0, ctx->stream, W.info, (int)I_NINFO, x0, x1, x2,
-                     ctx->h_pinned);
-  SPC_LAUNCH_CHECK(ctx, "readback");
-  SPC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  return SPC_OK;
+  return readback_wait(ctx, W.info, (int)I_NINFO, x0, x1, x2);
 }
 
 // checks of the level's input that the device reports (integer weight
