@@ -187,8 +187,11 @@ static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* clus
   if (out->n_cap < t) return set_error(ctx, SPC_ECAPACITY, "n_cap %lld < %lld", (long long)out->n_cap, (long long)t);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (st) {
-    SPC_HIP(ctx, hipEventCreate(&e0));
-    SPC_HIP(ctx, hipEventCreate(&e1));
+    // events from the context's pool (creating one is a runtime call the
+    // level boundary need not wait for)
+    e0 = ev_get(ctx);
+    e1 = ev_get(ctx);
+    if (!e0 || !e1) return set_error(ctx, SPC_EHIP, "event creation failed");
     SPC_HIP(ctx, hipEventRecord(e0, ctx->stream));
   }
   bool fp = g->wtype != SPC_W_I32;
@@ -271,8 +274,8 @@ static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* clus
     } else {
       SPC_HIP(ctx, hipEventSynchronize(e1));
       SPC_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
+      ctx->ev_pool.push_back(e0);
+      ctx->ev_pool.push_back(e1);
     }
     st->n_in = g->n;
     st->m_in = g->nnz / 2;
@@ -305,7 +308,7 @@ static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* clus
 static void free_level(spc_ctx* ctx, spc_hier::Level& L) {
   dev_free(ctx, L.block);
   for (hipEvent_t& e : L.ev)
-    if (e) (void)hipEventDestroy(e);
+    if (e) ctx->ev_pool.push_back(e);
   L = spc_hier::Level();
 }
 
@@ -340,8 +343,8 @@ static int finish_timing(spc_ctx* ctx, spc_hier* h) {
     float ms = 0;
     SPC_HIP(ctx, hipEventElapsedTime(&ms, L.ev[0], L.ev[1]));
     L.st.ms_total = ms;
-    (void)hipEventDestroy(L.ev[0]);
-    (void)hipEventDestroy(L.ev[1]);
+    ctx->ev_pool.push_back(L.ev[0]);
+    ctx->ev_pool.push_back(L.ev[1]);
     L.ev[0] = L.ev[1] = nullptr;
   }
   return SPC_OK;
@@ -390,6 +393,7 @@ int spc_destroy(spc_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   dev_free(ctx, ctx->ws);
   dev_free(ctx, ctx->scan_state);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
   delete ctx;
   return SPC_OK;
