@@ -174,7 +174,10 @@ int spc_coarsen_level(spc_ctx* ctx, const spc_graph* g, int64_t n_target, int32_
  * multilevel refinement the conclusion proposes).  schedule 0: halve the
  * node count per level, t = max(n_c, ceil(n_l / 2)); schedule 1: a single
  * level straight to n_c (Algorithm 1 as printed).  The hierarchy owns every
- * level's graph and cluster map; free it with spc_hier_free. */
+ * level's graph and cluster map; free it with spc_hier_free.  The call
+ * returns once the last level's work is queued on the context's stream
+ * (each level waits inside the call for its coarse size): read the arrays
+ * in that stream's order. */
 int spc_coarsen_to(spc_ctx* ctx, const spc_graph* g, int64_t n_c, int schedule, spc_hier** out);
 
 /* Batched coarsening: G independent graphs packed block-diagonally in one
@@ -198,7 +201,9 @@ int spc_hier_graph_offsets(const spc_hier* h, int lvl, int64_t* off, int64_t cap
 int spc_hier_num_levels(const spc_hier* h);
 /* Level lvl (1-based; level 0 is the input, not stored).  view receives
  * device pointers owned by the hierarchy; cluster_of maps level lvl-1
- * nodes to level lvl super-nodes.  stats may be NULL. */
+ * nodes to level lvl super-nodes.  stats may be NULL; the first request
+ * for stats waits until the hierarchy's work has run (its level times are
+ * read then). */
 int spc_hier_level(const spc_hier* h, int lvl, spc_graph* view, const int32_t** cluster_of,
                    spc_level_stats* stats);
 /* Copy level lvl (1-based) into caller-allocated device buffers, ordered on

@@ -347,6 +347,7 @@ static int finish_timing(spc_ctx* ctx, spc_hier* h) {
     ctx->ev_pool.push_back(L.ev[1]);
     L.ev[0] = L.ev[1] = nullptr;
   }
+  h->timing_pending = false;
   return SPC_OK;
 }
 
@@ -535,11 +536,7 @@ int spc_coarsen_to(spc_ctx* ctx, const spc_graph* g, int64_t n_c, int schedule, 
     cur.wtype = L.wtype;
     n = t;
   }
-  rc = finish_timing(ctx, h);
-  if (rc) {
-    spc_hier_free(h);
-    return rc;
-  }
+  h->timing_pending = true;
   *out = h;
   return SPC_OK;
 }
@@ -631,8 +628,7 @@ int spc_coarsen_batched(spc_ctx* ctx, int32_t G, const spc_graph* g, const int64
     off = noff;
     ng = tg;
   }
-  rc = finish_timing(ctx, h);
-  if (rc) return fail(rc);
+  h->timing_pending = true;
   dev_free(ctx, d_off);
   dev_free(ctx, d_k);
   dev_free(ctx, d_coff);
@@ -666,7 +662,13 @@ int spc_hier_level(const spc_hier* h, int lvl, spc_graph* view, const int32_t** 
     view->wtype = L.wtype;
   }
   if (cluster_of) *cluster_of = L.cluster_of;
-  if (stats) *stats = L.st;
+  if (stats) {
+    if (h->timing_pending) {
+      int rc = finish_timing(h->ctx, const_cast<spc_hier*>(h));
+      if (rc) return rc;
+    }
+    *stats = h->levels[lvl - 1].st;
+  }
   return SPC_OK;
 }
 
@@ -695,7 +697,10 @@ int spc_hier_export_level(spc_ctx* ctx, const spc_hier* h, int lvl, spc_graph_ou
 
 void spc_hier_free(spc_hier* h) {
   if (!h) return;
-  if (h->ctx) (void)hipStreamSynchronize(h->ctx->stream);
+  // no wait: blocks go back to the allocator hook (which reuses them in the
+  // context's stream order) or to hipFree (which waits for the device); a
+  // level event still pending returns to the context's pool, where the next
+  // record replaces it
   for (auto& L : h->levels) free_level(h->ctx, L);
   delete h;
 }

@@ -27,6 +27,9 @@ struct spc_hier {
     hipEvent_t ev[2] = {nullptr, nullptr};   // level timing, read once the hierarchy is built
   };
   std::vector<Level> levels;
+  // the levels' timing events are read (a wait for the last level) when
+  // stats are first asked for, so a call returns once its work is queued
+  bool timing_pending = false;
 };
 
 namespace spc {
