@@ -296,3 +296,28 @@ def test_lift_and_spectral_error(P):
         for mode in (0, 1):
             xf = P.lift(h, 0, lvl, mode, torch.from_numpy(xc).cuda())
             np.testing.assert_array_equal(host(xf), S.lift_vectors(xc, comp, gc.size, mode))
+
+
+def test_calls_queued_back_to_back_and_freed_without_waiting(P):
+    # a call returns once its last level is queued and freeing a hierarchy
+    # does not wait: hierarchies freed while later calls run, and blocks
+    # handed out again in stream order, must leave every result intact
+    ga = grid3d(24, ("uniform", 1, 16), seed=31)
+    gb = trimesh(90, ("uniform", 1, 8), seed=32)
+    da, db = P.DeviceGraph.from_host(ga), P.DeviceGraph.from_host(gb)
+    say("back-to-back calls", f"grid3d-24 n={ga.n}, trimesh-90 n={gb.n}")
+    ha = P.coarsen_to(da, ga.n // 16, 0)
+    hb = P.coarsen_to(db, gb.n // 8, 0)
+    ha.free()                                   # hb's work may still be queued
+    ha2 = P.coarsen_to(da, ga.n // 16, 0)       # takes ha's blocks again
+    hb.free()
+    hb2 = P.coarsen_to(db, gb.n // 8, 0)
+    for h, g, n_c, what in ((ha2, ga, ga.n // 16, "grid3d-24"), (hb2, gb, gb.n // 8, "trimesh-90")):
+        want = oracle.coarsen_to(g, n_c, 0)
+        assert h.num_levels == len(want)
+        for l, (c_or, gc_or, _) in enumerate(want, start=1):
+            cl, gc, st = h.level(l)
+            np.testing.assert_array_equal(host(cl), c_or, err_msg=f"{what} level {l} cluster_of")
+            assert_same_graph(gc, gc_or, f"{what} level {l}")
+            assert st.ms_total > 0
+        h.free()
