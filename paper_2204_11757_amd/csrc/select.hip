@@ -350,6 +350,7 @@ __global__ void __launch_bounds__(BS)
   __shared__ int64_t sh[2];
   __shared__ int32_t stmp[BS / WAVE];
   __shared__ unsigned long long sbase;
+  __shared__ int stot;
   int64_t j0 = (int64_t)blockIdx.x * TILE_R;
   int64_t nnz = g.nnz;
   uint64_t tlo = use_lo ? *thr_lo : 0, thi = *thr_hi;   // issued early, used at the end
@@ -449,17 +450,28 @@ __global__ void __launch_bounds__(BS)
   int64_t pos = block_reserve_lb<BS>(ts, blockIdx.x, blockIdx.x == gridDim.x - 1, nk, nullptr, cnt,
                                     &sbase, stmp);
   if (tid == 0 && blockIdx.x == gridDim.x - 1) *cnt_copy = *cnt;   // this thread set *cnt
+  // the block's records are staged in LDS (sp is free now) and written out
+  // one word per lane, so every wave stores whole lines
+  int64_t bbase = (int64_t)sbase;
+  int loc = (int)(pos - bbase);
+  if (tid == BS - 1) stot = loc + nk;
+  int q = loc;
 #pragma unroll
   for (int i = 0; i < R_PER; i++) {
     if (!(keep >> i & 1u)) continue;
-    int64_t j = cb + i;
-    int32_t u = ku[i];
-    int32_t v = g.col[j];
-    uint64_t uv = (uint64_t)(uint32_t)u | ((uint64_t)(uint32_t)v << 32);
-    lr[pos] = uv;
-    lp[pos] = kp[i];
-    pos++;
+    int32_t v = g.col[cb + i];
+    sp[q++] = (uint64_t)(uint32_t)ku[i] | ((uint64_t)(uint32_t)v << 32);
   }
+  __syncthreads();
+  int tot = stot;
+  for (int k = tid; k < tot; k += BS) lr[bbase + k] = sp[k];
+  __syncthreads();
+  q = loc;
+#pragma unroll
+  for (int i = 0; i < R_PER; i++)
+    if (keep >> i & 1u) sp[q++] = kp[i];
+  __syncthreads();
+  for (int k = tid; k < tot; k += BS) lp[bbase + k] = sp[k];
 }
 
 // ---------------------------------------------------------------------------
