@@ -641,6 +641,8 @@ __global__ void __launch_bounds__(BS)
                     unsigned long long* cnt_copy) {
   __shared__ int stmp[BS / WAVE];
   __shared__ unsigned long long sbase;
+  __shared__ uint64_t sst[BC_CHUNK];
+  __shared__ int stot;
   int64_t n = (int64_t)*cnt_in;
   int tid = threadIdx.x;
   int64_t base = (int64_t)blockIdx.x * BC_CHUNK;
@@ -696,14 +698,35 @@ __global__ void __launch_bounds__(BS)
     *msf_mark = *msf_now;                          // forest records before the next merge
     if (cnt_copy) *cnt_copy = *cnt_out;            // (this thread set *cnt_out)
   }
-  for (int i = 0; i < BC_PER; i++) {
-    if (!(keep >> i & 1u)) continue;
-    int64_t idx = base + tid + i * BS;
-    lr_out[pos] = ruv[i];
-    lp_out[pos] = lp_in[idx];
-    lo_out[pos] = lo_in[idx];
-    pos++;
-  }
+  // the block's records are staged in LDS, one array at a time, and written
+  // out one word per lane, so every wave stores whole lines
+  uint64_t ro[BC_PER];
+#pragma unroll
+  for (int i = 0; i < BC_PER; i++) ro[i] = (keep >> i & 1u) ? lo_in[base + tid + i * BS] : 0;
+  int64_t bbase = (int64_t)sbase;
+  int loc = (int)(pos - bbase);
+  if (tid == BS - 1) stot = loc + nk;
+  int q = loc;
+#pragma unroll
+  for (int i = 0; i < BC_PER; i++)
+    if (keep >> i & 1u) sst[q++] = ruv[i];
+  __syncthreads();
+  int tot = stot;
+  for (int k = tid; k < tot; k += BS) lr_out[bbase + k] = sst[k];
+  __syncthreads();
+  q = loc;
+#pragma unroll
+  for (int i = 0; i < BC_PER; i++)
+    if (keep >> i & 1u) sst[q++] = skey[i];
+  __syncthreads();
+  for (int k = tid; k < tot; k += BS) lp_out[bbase + k] = sst[k];
+  __syncthreads();
+  q = loc;
+#pragma unroll
+  for (int i = 0; i < BC_PER; i++)
+    if (keep >> i & 1u) sst[q++] = ro[i];
+  __syncthreads();
+  for (int k = tid; k < tot; k += BS) lo_out[bbase + k] = sst[k];
 }
 
 // After the cutoff selection, one launch: the components of the forest
