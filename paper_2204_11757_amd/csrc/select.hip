@@ -521,6 +521,8 @@ __global__ void __launch_bounds__(BS)
   static_assert(PER % HB == 0, "whole batches");
   __shared__ int stmp[BS / WAVE];
   __shared__ unsigned long long sbase;
+  __shared__ uint64_t sst[CHUNK];
+  __shared__ int stot;
   int64_t n = (int64_t)*cnt;
   int tid = threadIdx.x;
   int64_t base = (int64_t)blockIdx.x * CHUNK;
@@ -576,16 +578,34 @@ __global__ void __launch_bounds__(BS)
   }
   int64_t pos = block_reserve_lb<BS>(ts, blockIdx.x, base + CHUNK >= n, nc, msfcnt, msfcnt,
                                      &sbase, stmp);
-  for (int i = 0; i < PER; i++) {
-    if (!(chosen >> i & 1u)) continue;
-    int64_t idx = base + tid + i * BS;
-    if (pos < msf_cap) {  // a forest has fewer than n edges
-      msfP[pos] = lp[idx];
-      msfO[pos] = lo[idx];
-      msfC[pos] = hooked[i];
-    }
-    pos++;
-  }
+  // the block's records are staged in LDS, one array at a time, and written
+  // out one word per lane (a forest has fewer than n edges: positions at or
+  // beyond msf_cap are dropped)
+  int64_t bbase = (int64_t)sbase;
+  int loc = (int)(pos - bbase);
+  if (tid == BS - 1) stot = loc + nc;
+  int q = loc;
+  for (int i = 0; i < PER; i++)
+    if (chosen >> i & 1u) sst[q++] = lp[base + tid + i * BS];
+  __syncthreads();
+  int tot = stot;
+  for (int k = tid; k < tot; k += BS)
+    if (bbase + k < msf_cap) msfP[bbase + k] = sst[k];
+  __syncthreads();
+  q = loc;
+  for (int i = 0; i < PER; i++)
+    if (chosen >> i & 1u) sst[q++] = lo[base + tid + i * BS];
+  __syncthreads();
+  for (int k = tid; k < tot; k += BS)
+    if (bbase + k < msf_cap) msfO[bbase + k] = sst[k];
+  __syncthreads();
+  int32_t* sc = reinterpret_cast<int32_t*>(sst);
+  q = loc;
+  for (int i = 0; i < PER; i++)
+    if (chosen >> i & 1u) sc[q++] = hooked[i];
+  __syncthreads();
+  for (int k = tid; k < tot; k += BS)
+    if (bbase + k < msf_cap) msfC[bbase + k] = sc[k];
 }
 
 static void launch_bv_merge(spc_ctx* ctx, LevelWork& W, int64_t bound, const uint64_t* lr, const uint64_t* lp,
