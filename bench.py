@@ -57,47 +57,49 @@ def make_config(name):
     raise SystemExit(f"unknown config {name}")
 
 
-# Algorithmic HBM bytes of a kernel over one level: the data it must move at
-# least once (inputs read once, outputs written once), from the level's sizes
-# and work counters.  Per-launch figures divide by the launches per level.
-def sample_count(m):
-    """Key samples of a level with m edges: one per 2^s edges, s >= 6 the
-    smallest with at most 4096 samples (the library's sample_shift)."""
-    s = 6
-    while (m >> s) > 4096:
-        s += 1
-    return ((m - 1) >> s) + 1 if m > 0 else 0
+# Algorithmic HBM bytes over one level, from the level's sizes: what the
+# method must move at least once (inputs read once, outputs written once).
+# Units: n nodes and m undirected edges in, n_c nodes and nnz_c entries out;
+# `self` is 1 on coarse levels, which carry per-node self-loops.
+def csr_read_bytes(L):
+    """The level's CSR read once: row pointers, columns and weights of both
+    directions (4 + 4 bytes per entry), self-loops on coarse levels."""
+    return 8 * (L["n"] + 1) + 16 * L["m"] + 8 * L["n"] * L["self"]
+
+
+def coarse_write_bytes(L):
+    """Labels (4 B per fine node) and the coarse CSR written once: row
+    pointers, columns and weights, self-loops and sizes."""
+    return 4 * L["n"] + 8 * (L["n_c"] + 1) + 8 * L["nnz_c"] + 8 * L["n_c"] + 4 * L["n_c"]
 
 
 def algo_bytes(kernel, L):
-    n, m, nnz, n_c, nnz_c, selfb = L["n"], L["m"], 2 * L["m"], L["n_c"], L["nnz_c"], L["self"]
+    """Per-level algorithmic bytes of a kernel (or a phase) as the method
+    defines its work; None where no unit applies."""
+    m = L["m"]
     if kernel == "score":
-        # CSR col + w of both rows once (8 B per entry), per-node row_ptr,
-        # degree, lower count, upper prefix (28 B), self-loops at coarse
-        # levels; writes the key of both CSR entries of every edge, the key
-        # samples, the exactness map (1 bit per edge) and the exact records
-        # when they are kept
-        if L["key_mode"] == "rank":
-            return None
-        return (8 * nnz + 28 * n + 8 * n * selfb + 16 * m + 8 * sample_count(m) + m // 8
-                + 24 * m * L["keys_written"])
-    if kernel == "rowpass":
-        # every band reads each entry's key and column and the row pointers;
-        # the first band writes each node's lightest key; kept edges are
-        # written as two 8-byte words (endpoints, key)
-        return L["bands"] * (12 * nnz + 8 * (n + 1)) + 8 * n + 16 * L["candidate_edges"]
+        # degrees and scores: the CSR read once, one 8-byte score per edge written
+        return csr_read_bytes(L) + 8 * m
     if kernel == "degree":
-        return 8 * nnz + 8 * (n + 1) + 44 * n + 8 * n * selfb
-    if kernel == "forest_candidates":
-        # live list read (24 B) and both root lookups (4 B each), kept edges written
-        return 32 * L["forest_in"] + 24 * L["forest_kept"]
-    if kernel == "forest_merge":
-        # live list and both endpoints' lightest keys read; forest records
-        # (16 B) and parent hooks (4 B) written
-        return 40 * L["merge_in"] + 20 * L["forest_edges"]
-    if kernel == "contract_pack":
-        return 16 * nnz_c + 16 * n_c
+        return csr_read_bytes(L) + 8 * L["n"]
+    if kernel == "rowpass":
+        # the order: each edge's score read once
+        return 8 * m
+    if kernel == "phase:contract":
+        # Definition 1: the fine CSR and each node's label and size read once,
+        # the coarse CSR written once
+        return csr_read_bytes(L) + 8 * L["n"] + coarse_write_bytes(L) - 4 * L["n"]
     return None
+
+
+# timing scopes per phase of a level
+PHASES = {
+    "score": ["degree", "degree_total", "scan_upper", "score", "score_rank", "rank_sort", "rank_scatter"],
+    "select": ["select_threshold", "rowpass", "forest_candidates", "forest_merge", "forest_shortcut",
+               "select_cutoff", "components", "relabel"],
+    "contract": ["contract_members", "contract_small", "contract_reg32", "contract_wave_rows",
+                 "contract_block_rows", "contract_huge", "contract_rowptr", "contract_pack"],
+}
 
 
 # kernels timed one launch per scope (the candidates for the roofline line)
@@ -137,16 +139,27 @@ def stored_traffic(kernel, config_name):
 
 
 def method_floor_bytes(L):
-    """Compulsory traffic of a level plus one 8-byte key written and read per edge."""
-    n, m, n_c, nnz_c = L["n"], L["m"], L["n_c"], L["nnz_c"]
-    comp = 8 * (n + 1) + 16 * m + (8 * n if L["self"] else 0) + 4 * n
-    comp += 8 * (n_c + 1) + 8 * nnz_c + 8 * n_c + 4 * n_c
-    return comp + 16 * m
+    """Compulsory traffic of a level (the CSR read once, labels and the
+    coarse CSR written once) plus one 8-byte score written and read per edge."""
+    return csr_read_bytes(L) + coarse_write_bytes(L) + 16 * L["m"]
 
 
-def cpu_baseline(g, n_c):
-    """The oracle on the same step (every level to n_c), repeated until about
-    10 s of host time have passed (at least once), on one host core."""
+def cpu_sample(name, g, n_c):
+    """A bounded sample of the workload for the oracle's timing (about 10-30 s
+    of one host core): the whole step when it is that short, else the same
+    generator at a smaller size, every level to the same relative target."""
+    if name == "trimesh-4096":
+        from meshgen import trimesh
+        x = trimesh(1024, ("uniform", 1, 8), seed=3)
+        return x, x.n // 100, ("the whole step on a 1024x1024 triangle mesh of the same generator and "
+                               "weights (1/16 of the nodes; 1,048,576 nodes, 3,141,633 edges), halving "
+                               "levels to n/100")
+    return g, n_c, f"the whole step ({name}, every level to n_c={n_c})"
+
+
+def cpu_baseline(g, n_c, what):
+    """The oracle on one step of `g`, repeated until about 10 s of host time
+    have passed (at least once), on one host core."""
     import oracle
     runs, total_edges, t_all = 0, 0, 0.0
     while runs == 0 or t_all < 10.0:
@@ -160,8 +173,7 @@ def cpu_baseline(g, n_c):
         runs += 1
     return {"value": total_edges / t_all, "unit": "fine edges/s", "cores": 1, "kind": "oracle",
             "seconds": round(t_all, 3),
-            "sample": f"the whole step ({len(lv)} levels of the same mesh to n_c={n_c}) run {runs} "
-                      f"time(s) by the serial C oracle on one host core"}
+            "sample": f"{what}, run {runs} time(s) by the serial C oracle on one host core"}
 
 
 def cpu_baseline_batch(graphs, n_c, seconds=10.0):
@@ -187,7 +199,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="grid3d-128")
+    ap.add_argument("--config", default="trimesh-4096")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-graph", action="store_true",
                     help="batch configs: skip the one-call-per-graph comparison (for profiling)")
@@ -264,6 +276,7 @@ def main():
 
     roofline = None
     kernels = None
+    phases = None
     if not args.no_roofline:
         # per-kernel times: the same K steps again with a HIP event pair
         # recorded on the context stream around every launch
@@ -295,6 +308,16 @@ def main():
             tr = stored_traffic(dom, args.config)
             if tr is not None:
                 roofline["traffic"] = int(tr)
+        # per phase of the step: time (sum of its scopes) and the fraction of
+        # peak its algorithmic bytes reach
+        phases = {}
+        for ph, scopes in PHASES.items():
+            t_ph = sum(rep[k][1] for k in scopes if k in rep) / args.steps
+            b = [algo_bytes("phase:contract", L) if ph == "contract" else
+                 algo_bytes("score", L) if ph == "score" else algo_bytes("rowpass", L) for L in levels]
+            phases[ph] = {"ms_per_step": round(t_ph, 4), "algo_bytes_per_step": int(sum(b)),
+                          "frac_of_peak": (round(sum(b) / (t_ph * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
+                                           if t_ph > 0 else None)}
 
     per_graph = None
     if batch and not args.no_per_graph:
@@ -318,7 +341,10 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline_batch(g.meta["graphs"], g.meta["n_c"]) if batch else cpu_baseline(g, n_c)
+        if batch:
+            cpu = cpu_baseline_batch(g.meta["graphs"], g.meta["n_c"])
+        else:
+            cpu = cpu_baseline(*cpu_sample(args.config, g, n_c))
 
     if batch:
         value = len(g.meta["graphs"]) / (ms * 1e-3)
@@ -342,6 +368,9 @@ def main():
         "per_graph": per_graph,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "step_floor_frac": (sum(method_floor_bytes(L) for L in levels) / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
+                            if levels else None),
+        "phases": phases,
         "levels": levels,
         "kernels": kernels,
     }

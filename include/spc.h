@@ -107,6 +107,10 @@ typedef struct {
  * null stream).  The context owns its workspace. */
 int spc_create(spc_ctx** ctx, int device, void* hip_stream);
 int spc_destroy(spc_ctx* ctx);
+/* Make hip_stream the context's stream.  When it differs from the current
+ * one, the new stream first waits (on the device, no host wait) for what
+ * was queued on the old one, since that work still uses the context's
+ * workspace. */
 int spc_set_stream(spc_ctx* ctx, void* hip_stream);
 
 /* Route the library's device allocations (workspace, hierarchy levels)
@@ -116,7 +120,8 @@ int spc_set_stream(spc_ctx* ctx, void* hip_stream);
 int spc_set_allocator(spc_ctx* ctx, void* (*alloc)(size_t, void*), void (*free_)(void*, void*),
                       void* user);
 
-/* Context options (for tests and tuning; results never depend on them):
+/* Context options (for tests and tuning; results never depend on them, but
+ * "scan_flag" makes one level fail on purpose):
  *   "rank_order"  1: always order edges by a full sort into ranks, even when
  *                 the exact packed fixed-point key fits in 64 bits.
  *   "full_forest" 1: build the spanning forest over every edge instead of
@@ -129,6 +134,10 @@ int spc_set_allocator(spc_ctx* ctx, void* (*alloc)(size_t, void*), void (*free_)
  *   "bad_select_guess" 1: give the merge cutoff's selection key bounds above
  *                 every forest key, so that the cutoff lies below them and the
  *                 selection starts over (its fallback path).
+ *   "scan_flag"   1: the next level (once) finds the error flag of the
+ *                 context's scan chain raised, as after a look-back wait that
+ *                 gave up, and fails with SPC_EINVAL; later levels start with
+ *                 the flag clear.
  *   "speculate"   whether the host waits for the first batch of spanning-
  *                 forest rounds: 0 (default) not when the previous level's
  *                 forest was complete after it, 1 always, 2 never (and that
@@ -215,10 +224,18 @@ int spc_hier_export_level(spc_ctx* ctx, const spc_hier* h, int lvl, spc_graph_ou
 void spc_hier_free(spc_hier* h);
 
 /* Lift (Definition 2) of k coarse vectors from level to_lvl down to level
- * from_lvl < to_lvl (0 = the input graph).  x_c: device double[n_to * k],
- * column-major; x_f: device double[n_from * k].  mode 0: piecewise
- * constant, x_f[u] = x_c[c(u)]; mode 1: orthonormal, x_f[u] =
- * x_c[c(u)] / sqrt(|c(u)|) where |c(u)| counts original nodes. */
+ * from_lvl <= to_lvl (0 = the input graph).  x_c: device double[n_to * k],
+ * column-major; x_f: device double[n_from * k].  c(u) is the level-to_lvl
+ * super-node holding level-from_lvl node u (the cluster maps composed) and
+ * s(.) the number of input nodes a node stands for (its size).
+ * mode 0: piecewise constant, x_f[u] = x_c[c(u)];
+ * mode 1: orthonormal, x_f[u] = x_c[c(u)] / sqrt(s(c(u)) / s(u)): the
+ * coordinates, in level from_lvl's orthonormal basis, of the orthonormal
+ * lift Q = B S^-1/2 (B the input-node membership matrix, S = diag(s)).
+ * From level 0 this is x_c[c(u)] / sqrt(s(c(u))); the columns of the map
+ * are orthonormal, and lifting to_lvl -> from_lvl -> 0 equals lifting
+ * to_lvl -> 0.  Stream-ordered.  SPC_EINVAL unless 0 <= from_lvl <= to_lvl
+ * <= levels. */
 int spc_lift(spc_ctx* ctx, const spc_hier* h, int from_lvl, int to_lvl, int mode,
              const double* x_c, int k, double* x_f);
 

@@ -77,6 +77,29 @@ def lift_vectors(x_c: np.ndarray, cluster_of: np.ndarray, size_c: np.ndarray,
     return out
 
 
+def lift_between(maps, sizes, from_lvl: int, to_lvl: int, x_c: np.ndarray, mode: int = 0) -> np.ndarray:
+    """Lift coarse vectors from level to_lvl to level from_lvl <= to_lvl of a
+    hierarchy (Definition 2 applied between levels).
+
+    maps[l] is the cluster map from level l to level l + 1 (level 0 is the
+    input); sizes[l] the node sizes of level l (input nodes per node; level
+    0 all ones).  c(u) composes the maps from from_lvl to to_lvl.
+    mode 0: x_f[u] = x_c[c(u)];
+    mode 1: x_f[u] = x_c[c(u)] / sqrt(s(c(u)) / s(u)), the coordinates of the
+    orthonormal lift B S^-1/2 in level from_lvl's orthonormal basis."""
+    n_from = np.asarray(sizes[from_lvl]).shape[0]
+    c = np.arange(n_from, dtype=np.int64)
+    for lvl in range(from_lvl, to_lvl):
+        c = np.asarray(maps[lvl], dtype=np.int64)[c]
+    x = np.asarray(x_c, dtype=np.float64)
+    out = x[c]
+    if mode == 1:
+        ratio = np.asarray(sizes[to_lvl], dtype=np.float64)[c] / np.asarray(sizes[from_lvl], dtype=np.float64)
+        s = np.sqrt(ratio)
+        out = out / (s[:, None] if out.ndim == 2 else s)
+    return out
+
+
 def restrict(U: np.ndarray, cluster_of: np.ndarray, size_c: np.ndarray) -> np.ndarray:
     """Transpose of the orthonormal lift: y[a] = sum_{x in a} U[x] / sqrt(|a|)."""
     c = np.asarray(cluster_of, dtype=np.int64)

@@ -266,12 +266,13 @@ static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* clus
   }
   *nnz_c = R.nnz_c;
   if (st) {
-    SPC_HIP(ctx, hipEventRecord(e1, ctx->stream));
     float ms = 0;
     if (ev) {
+      SPC_HIP(ctx, hipEventRecord(e1, ctx->stream));
       ev[0] = e0;
       ev[1] = e1;
     } else {
+      SPC_HIP(ctx, hipEventRecord(e1, ctx->stream));
       SPC_HIP(ctx, hipEventSynchronize(e1));
       SPC_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
       ctx->ev_pool.push_back(e0);
@@ -402,7 +403,18 @@ int spc_destroy(spc_ctx* ctx) {
 
 int spc_set_stream(spc_ctx* ctx, void* stream) {
   if (!ctx) return SPC_EINVAL;
-  ctx->stream = (hipStream_t)stream;
+  hipStream_t s = (hipStream_t)stream;
+  if (s == ctx->stream) return SPC_OK;
+  // Work queued by earlier calls on the old stream still uses the context's
+  // workspace, look-back words and pinned readback area: the new stream
+  // waits for it on the device (no host wait).
+  hipEvent_t e = ev_get(ctx);
+  if (!e) return set_error(ctx, SPC_EHIP, "event creation failed");
+  hipError_t r = hipEventRecord(e, ctx->stream);
+  if (r == hipSuccess) r = hipStreamWaitEvent(s, e, 0);
+  ctx->ev_pool.push_back(e);
+  if (r != hipSuccess) return hip_error(ctx, r, "ordering the new stream after the old one");
+  ctx->stream = s;
   return SPC_OK;
 }
 
@@ -435,6 +447,7 @@ int spc_set_option(spc_ctx* ctx, const char* name, int64_t value) {
   else if (!strcmp(name, "huge_sort")) ctx->force_huge_sort = value ? 1 : 0;
   else if (!strcmp(name, "redo_rank")) ctx->force_redo_rank = value ? 1 : 0;
   else if (!strcmp(name, "bad_select_guess")) ctx->force_bad_guess = value ? 1 : 0;
+  else if (!strcmp(name, "scan_flag")) ctx->force_scan_flag = value ? 1 : 0;
   else if (!strcmp(name, "speculate")) {
     if (value < 0 || value > 2) return set_error(ctx, SPC_EINVAL, "speculate takes 0, 1 or 2");
     ctx->speculate = (int)value;

@@ -384,13 +384,13 @@ int radix_select(spc_ctx* ctx, const uint64_t* keys, const unsigned long long* c
 
 // Small launches that replace the runtime's fill and copy blits on the
 // level path (each blit costs the host far more than a plain launch).
-// k_clear zeroes a[0, na), b[0, nb), c[0, nc) and the info slots whose bit is set in
-// `slots`; k_readback copies the info block (I_NINFO words, when info is not
+// k_clear zeroes a[0, na), b[0, nb), c[0, nc), the info slots whose bit is set in
+// `slots` and *word; k_readback copies the info block (I_NINFO words, when info is not
 // null) and up to three scalars (null: 0) into host-visible pinned memory
 // at out[0..I_NINFO) and out[I_NINFO..I_NINFO+3), then the token (when
 // nonzero) at out[I_NINFO + 3]; k_copy_u64 copies one word.
 __global__ void k_clear(int32_t* a, int64_t na, uint64_t* b, int64_t nb, uint64_t* c, int64_t nc,
-                        unsigned long long* info, uint32_t slots);
+                        unsigned long long* info, uint32_t slots, unsigned long long* word);
 __global__ void k_readback(const unsigned long long* info, int ninfo, const int64_t* x0,
                            const int32_t* x1, const uint64_t* x2, int64_t* out, int64_t token);
 // Host waits.  The pinned copy is host-coherent: a kernel that fills it then
@@ -403,8 +403,9 @@ int readback_wait(spc_ctx* ctx, const unsigned long long* info, int ninfo, const
                   const int32_t* x1 = nullptr, const uint64_t* x2 = nullptr);
 __global__ void k_copy_u64(unsigned long long* dst, const unsigned long long* src);
 __global__ void k_fill_u64(uint64_t* __restrict__ a, int64_t n, uint64_t v);
+// `word` (nullable) is one more word to zero (the scan chain's error flag).
 void launch_clear(spc_ctx* ctx, int32_t* a, int64_t na, uint64_t* b, int64_t nb, unsigned long long* info,
-                  uint32_t slots, uint64_t* c = nullptr, int64_t nc = 0);
+                  uint32_t slots, uint64_t* c = nullptr, int64_t nc = 0, unsigned long long* word = nullptr);
 
 
 // ===========================================================================

@@ -1223,22 +1223,23 @@ int radix_select(spc_ctx* ctx, const uint64_t* keys, const unsigned long long* c
 __global__ void k_set_u64(unsigned long long* p, unsigned long long v) { *p = v; }
 
 __global__ void k_clear(int32_t* a, int64_t na, uint64_t* b, int64_t nb, uint64_t* c, int64_t nc,
-                        unsigned long long* info, uint32_t slots) {
+                        unsigned long long* info, uint32_t slots, unsigned long long* word) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t i = i0; i < na; i += stride) a[i] = 0;
   for (int64_t i = i0; i < nb; i += stride) b[i] = 0;
   for (int64_t i = i0; i < nc; i += stride) c[i] = 0;
   if (info && i0 < 32 && (slots >> i0 & 1u)) info[i0] = 0;
+  if (word && i0 == 32) *word = 0;
 }
 
 void launch_clear(spc_ctx* ctx, int32_t* a, int64_t na, uint64_t* b, int64_t nb, unsigned long long* info,
-                  uint32_t slots, uint64_t* c, int64_t nc) {
+                  uint32_t slots, uint64_t* c, int64_t nc, unsigned long long* word) {
   int64_t big = na > nb ? na : nb;
   if (nc > big) big = nc;
-  if (big < 32) big = 32;
+  if (big < 64) big = 64;
   hipLaunchKernelGGL(k_clear, dim3(grid_for(big, 256, ctx->num_cus * 4)), dim3(256), 0, ctx->stream, a, na,
-                     b, nb, c, nc, info, slots);
+                     b, nb, c, nc, info, slots, word);
 }
 
 __global__ void k_readback(const unsigned long long* info, int ninfo, const int64_t* x0,
@@ -1579,8 +1580,17 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
   ctx->lb_words = lb_words(n, g.nnz);
   ctx->lb_epoch = 0;
   ctx->sel_epoch = 0;
+  // every level starts with the scan chain's error flag clear, so one
+  // failed wait does not fail later calls on this context
   launch_clear(ctx, nullptr, 0, W.lbstate, ctx->lb_words, info, 0xffffffffu, W.selflag,
-               (int64_t)SEL_MAXB * SEL_FLAG);
+               (int64_t)SEL_MAXB * SEL_FLAG,
+               ctx->scan_state ? (unsigned long long*)(ctx->scan_state + ctx->scan_cap - 1) : nullptr);
+  if (ctx->force_scan_flag && ctx->scan_state) {
+    // test option: this level finds the flag raised, as after a wait that gave up
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st,
+                       (unsigned long long*)(ctx->scan_state + ctx->scan_cap - 1), 1ull);
+    ctx->force_scan_flag = 0;
+  }
 
   // A1
   int nb = grid_for(n, DEG_ROWS);

@@ -36,7 +36,8 @@ __global__ void k_lift(const int32_t* __restrict__ cmap, const int32_t* __restri
   int32_t a = cmap[u];
   double s = 1.0;
   if (mode == 1) {
-    // |c(u)| relative to u's own size; from the input level this is |c(u)|
+    // orthonormal lift in level from's own orthonormal basis: the super-node's
+    // size relative to u's (from the input level, u's size is 1)
     double sf = size_from ? (double)size_from[u] : 1.0;
     double st = size_to ? (double)size_to[a] : 1.0;
     s = sqrt(st / sf);

@@ -8,8 +8,10 @@ never falls back to another implementation.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from dataclasses import dataclass
 from typing import Optional
 
@@ -223,12 +225,36 @@ class Context:
             raise SpcError(rc, msg)
 
     def close(self):
+        """Destroy the library context (waits for its stream, returns its
+        workspace through the allocator hook), then drop the callbacks."""
         if getattr(self, "h", None):
             lib().spc_destroy(self.h)
             self.h = None
+        self._alloc = self._free = None
 
 
 _contexts = {}
+_live = weakref.WeakSet()     # hierarchies whose library handle is still held
+_shutting_down = False
+
+
+def _teardown():
+    """At interpreter exit, while torch (whose allocator the library calls
+    back into) is still intact: free every live hierarchy, then destroy the
+    contexts.  Registered after torch's own exit handlers, so it runs before
+    them; afterwards Hierarchy.__del__ does nothing."""
+    global _shutting_down
+    try:
+        for h in list(_live):
+            h.free()
+        for ctx in list(_contexts.values()):
+            ctx.close()
+        _contexts.clear()
+    finally:
+        _shutting_down = True
+
+
+atexit.register(_teardown)
 
 
 def context(device=None) -> Context:
@@ -298,6 +324,7 @@ class Hierarchy:
         self.ctx = ctx
         self.h = handle
         self.n0 = n0
+        _live.add(self)
 
     @property
     def num_levels(self) -> int:
@@ -328,10 +355,15 @@ class Hierarchy:
 
     def free(self):
         if self.h:
+            if self.ctx.h is None:
+                raise RuntimeError("the hierarchy's context was destroyed")
             lib().spc_hier_free(self.h)
             self.h = None
+        _live.discard(self)
 
     def __del__(self):
+        if _shutting_down:
+            return
         try:
             self.free()
         except Exception:

@@ -1,21 +1,50 @@
-"""GPU checks at the benchmark's full sizes, in the configuration bench.py
-times (coarsen_to with halving levels):
+"""GPU checks at the full sizes of every workload, in the configuration
+bench.py times (coarsen_to with halving levels):
 
-* 128^3 grid, weights U{1..16} (the bench workload): every level bit-exact
-  against the oracle, and level 1 against the closed form of a bipartite
-  grid (one giant super-node {0..k} plus singletons);
-* 4096^2 triangle mesh: invariants of every level and Definition 1's sums
-  recomputed for sampled super-nodes;
-* a batch of 256 triangle meshes: each graph against its own call.
+* 128^3 grid, weights U{1..16}: every level bit-exact against the oracle
+  run here, and level 1 against the closed form of a bipartite grid (one
+  giant super-node {0..k} plus singletons);
+* 4096^2 triangle mesh, weights U{1..8}: every level's cluster map and
+  coarse CSR bit-exact against the oracle's digests (tests/golden/
+  fullsize_digests.json, written by make_fullsize_digests.py from the
+  oracle alone), plus Definition 1's invariants;
+* the 4,096-mesh batch: every level of the packed union and every graph
+  over all its levels against the oracle's digests;
+* 64^3 grid with float32 lognormal weights: every level bit-exact against
+  the oracle run here and against its digests.
 
 Every case prints its name and shape before the GPU call."""
+import hashlib
+import json
+import os
+import sys
+
 import numpy as np
 import pytest
 
 import oracle
-from meshgen import batch_trimeshes, grid3d, trimesh
+from meshgen import batch_sides, batch_trimeshes, grid3d, trimesh
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+import digest as D  # noqa: E402
 
 pytestmark = pytest.mark.gpu
+
+with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize_digests.json")) as _f:
+    GOLD = json.load(_f)
+
+
+def compare_level_digest(cl, gh, want, fp, what):
+    """Whole-array digests of one level against the oracle's; on a mismatch
+    name the first differing chunk."""
+    assert gh.n == want["n"] and gh.col.shape[0] == want["nnz"], f"{what}: sizes {gh.n}/{gh.col.shape[0]}"
+    bad = []
+    for name, a in D.level_fields(cl, gh).items():
+        c = D.canonical(name, a, fp)
+        if D.sha(c) != want["sha"][name]:
+            ch = want["chunks"].get(name)
+            bad.append(D.first_mismatch(name, c, ch) if ch else name)
+    assert not bad, f"{what}: differs from the oracle: " + "; ".join(bad)
 
 
 @pytest.fixture(scope="module")
@@ -68,30 +97,6 @@ def check_invariants(prev, cl, gc, t, what):
     assert int(prev.w[cross].astype(np.int64).sum()) == int(w.sum()), what + " cross weight"
 
 
-def sampled_definition1(prev, c, gc, k, seed, what):
-    """Coarse rows of k sampled super-nodes recomputed from the fine graph."""
-    r = np.random.Generator(np.random.PCG64(seed))
-    t = gc.n
-    pick = np.unique(r.integers(0, t, size=k))
-    prow = np.repeat(np.arange(prev.n), np.diff(prev.row_ptr))
-    a = c[prow]
-    sel = np.isin(a, pick)
-    a, b, w = a[sel], c[prev.col[sel]], prev.w[sel].astype(np.int64)
-    selfs = np.zeros(t, dtype=np.int64)
-    np.add.at(selfs, a[a == b], w[a == b])
-    np.add.at(selfs, c, prev.self_w_or_zero().astype(np.int64))
-    keep = a != b
-    key = a[keep].astype(np.int64) * t + b[keep]
-    u, inv = np.unique(key, return_inverse=True)
-    sums = np.bincount(inv, weights=w[keep]).astype(np.int64)
-    for x in pick:
-        lo, hi = gc.row_ptr[x], gc.row_ptr[x + 1]
-        m = (u // t) == x
-        assert np.array_equal(gc.col[lo:hi], (u[m] % t).astype(np.int32)), f"{what} row {x} columns"
-        assert np.array_equal(gc.w[lo:hi].astype(np.int64), sums[m]), f"{what} row {x} weights"
-        assert gc.self_w[x] == selfs[x], f"{what} self {x}"
-
-
 def test_bench_workload_grid3d_128_every_level(P):
     g = grid3d(128, ("uniform", 1, 16), seed=2)
     n_c = g.n // 64
@@ -117,47 +122,85 @@ def test_bench_workload_grid3d_128_every_level(P):
         prev = g_or
 
 
-def test_roofline_workload_trimesh_4096_invariants(P):
+def test_roofline_workload_trimesh_4096_every_level(P):
     g = trimesh(4096, ("uniform", 1, 8), seed=3)
     n_c = g.n // 100
+    gold = GOLD["trimesh-4096"]
+    assert (g.n, g.m, n_c) == (gold["n"], gold["m"], gold["n_c"])
     say("trimesh-4096 full hierarchy", f"n={g.n} m={g.m} n_c={n_c}")
     h = P.coarsen_to(P.DeviceGraph.from_host(g, "cuda:0"), n_c, 0)
     targets = oracle.level_targets(g.n, n_c, 0)
-    assert h.num_levels == len(targets) == 7
+    assert h.num_levels == len(targets) == len(gold["levels"]) == 7
     prev = g
-    for lvl, t in enumerate(targets, start=1):
+    for lvl, (t, want) in enumerate(zip(targets, gold["levels"]), start=1):
         cl, gc, st = h.level(lvl)
         gh = gc.to_host()
         c = host(cl)
+        compare_level_digest(c, gh, want, False, f"level {lvl}")
+        assert st.eps_max == float.fromhex(want["eps_max"]), f"level {lvl} eps"
         check_invariants(prev, c, gh, t, f"level {lvl}")
-        sampled_definition1(prev, c, gh, 400, lvl, f"level {lvl}")
-        assert 0.0 <= st.eps_max <= 2.0
         prev = gh
+    h.free()
 
 
-def test_batch_of_256_meshes_against_separate_calls(P):
-    graphs = batch_trimeshes(256, seed=4)
+def test_batch_of_4096_meshes_every_level_every_graph(P):
+    import torch
+    gold = GOLD["batch-4096"]
+    assert D.sha(np.ascontiguousarray(batch_sides(4096, 4), dtype="<i8"))[:16] == gold["sides_sha"]
+    graphs = batch_trimeshes(4096, seed=4)
     n_c = [max(1, x.n // 10) for x in graphs]
     union, offs = P.pack_graphs(graphs)
-    say("batch-256", f"n={union.n} m={union.m}")
-    h = P.coarsen_batched(P.DeviceGraph.from_host(union, "cuda:0"), offs, n_c, 0)
+    assert (union.n, union.m) == (gold["n"], gold["m"])
+    say("batch-4096", f"n={union.n} m={union.m}")
+    dg = P.DeviceGraph.from_host(union, "cuda:0")
+    del union
+    h = P.coarsen_batched(dg, offs, n_c, 0)
     L = h.num_levels
-    cl, gc, _ = h.level(L)
-    gh = gc.to_host()
-    o_in, o_out = h.offsets(L - 1), h.offsets(L)
-    r = np.random.Generator(np.random.PCG64(1))
-    check_oracle = set(r.choice(len(graphs), size=6, replace=False).tolist())
-    for i, x in enumerate(graphs):
-        a, b = o_out[i], o_out[i + 1]
-        e0, e1 = gh.row_ptr[a], gh.row_ptr[b]
-        hi = P.coarsen_to(P.DeviceGraph.from_host(x, "cuda:0"), n_c[i], 0)
-        _, gs, _ = hi.level(hi.num_levels)
-        np.testing.assert_array_equal(gh.row_ptr[a:b + 1] - e0, host(gs.row_ptr), err_msg=f"graph {i}")
-        np.testing.assert_array_equal(gh.col[e0:e1] - a, host(gs.col), err_msg=f"graph {i}")
-        np.testing.assert_array_equal(gh.w[e0:e1], host(gs.w), err_msg=f"graph {i}")
-        np.testing.assert_array_equal(gh.self_w[a:b], host(gs.self_w), err_msg=f"graph {i}")
-        if i in check_oracle:
-            g_or = oracle.coarsen_to(x, n_c[i], 0)[-1][1]
-            np.testing.assert_array_equal(gh.col[e0:e1] - a, g_or.col, err_msg=f"graph {i} oracle")
-            np.testing.assert_array_equal(gh.w[e0:e1], g_or.w, err_msg=f"graph {i} oracle")
-        hi.free()
+    assert L == len(gold["levels"]) == 4
+    per_graph = [hashlib.sha256() for _ in graphs]
+    for lvl in range(1, L + 1):
+        cl, gc, _ = h.level(lvl)
+        gh = gc.to_host()
+        c = host(cl)
+        del cl, gc
+        torch.cuda.empty_cache()
+        want = gold["levels"][lvl - 1]
+        assert (gh.n, gh.col.shape[0]) == (want["n"], want["nnz"]), f"level {lvl} sizes"
+        got = {name: D.sha(D.canonical(name, a, False)) for name, a in D.level_fields(c, gh).items()}
+        o_in, o_out = h.offsets(lvl - 1), h.offsets(lvl)
+        # per graph: its own arrays (cluster map and columns local, row
+        # pointers rebased), in the order the oracle's per-graph digest takes
+        for i in range(len(graphs)):
+            a, b = int(o_out[i]), int(o_out[i + 1])
+            e0, e1 = int(gh.row_ptr[a]), int(gh.row_ptr[b])
+            parts = {"cluster_of": c[o_in[i]:o_in[i + 1]].astype(np.int64) - a,
+                     "row_ptr": gh.row_ptr[a:b + 1] - e0, "col": gh.col[e0:e1].astype(np.int64) - a,
+                     "w": gh.w[e0:e1], "self_w": gh.self_w[a:b], "size": gh.size[a:b]}
+            for name in D.FIELDS:
+                per_graph[i].update(memoryview(D.canonical(name, parts[name], False)).cast("B"))
+        bad = [name for name in D.FIELDS if got[name] != want["sha"][name]]
+        assert not bad, f"level {lvl}: packed union differs from the oracle in {bad}"
+    wrong = [i for i, hh in enumerate(per_graph) if hh.hexdigest()[:16] != gold["graph_sha"][i]]
+    assert not wrong, f"{len(wrong)} graphs differ from the oracle, first {wrong[:8]}"
+    h.free()
+
+
+def test_differentiation_workload_grid3d_64_lognormal_every_level(P):
+    g = grid3d(64, "lognormal", seed=5)
+    n_c = 32768
+    gold = GOLD["grid3d-64-lognormal"]
+    say("grid3d-64 lognormal full hierarchy", f"n={g.n} m={g.m} n_c={n_c}")
+    h = P.coarsen_to(P.DeviceGraph.from_host(g, "cuda:0"), n_c, 0)
+    want = oracle.coarsen_to(g, n_c, 0)
+    assert h.num_levels == len(want) == len(gold["levels"]) == 3
+    for lvl, ((c_or, g_or, eps), wd) in enumerate(zip(want, gold["levels"]), start=1):
+        cl, gc, st = h.level(lvl)
+        c = host(cl)
+        gh = gc.to_host()
+        np.testing.assert_array_equal(c, c_or, err_msg=f"level {lvl} cluster_of")
+        for name in ("row_ptr", "col", "w", "self_w", "size"):
+            np.testing.assert_array_equal(getattr(gh, name), getattr(g_or, name),
+                                          err_msg=f"level {lvl} {name}")
+        assert st.eps_max == eps == float.fromhex(wd["eps_max"])
+        compare_level_digest(c, gh, wd, True, f"level {lvl}")
+    h.free()

@@ -296,6 +296,16 @@ def test_lift_and_spectral_error(P):
         for mode in (0, 1):
             xf = P.lift(h, 0, lvl, mode, torch.from_numpy(xc).cuda())
             np.testing.assert_array_equal(host(xf), S.lift_vectors(xc, comp, gc.size, mode))
+    # between intermediate levels: the lift of the oracle's hierarchy
+    maps = [c for c, _, _ in want]
+    sizes = [np.ones(g.n, np.int32)] + [gc.size for _, gc, _ in want]
+    L = len(want)
+    for a, b in [(1, L), (1, 2), (2, L), (L - 1, L), (2, 2)]:
+        xc = np.random.default_rng(10 * a + b).normal(size=(sizes[b].shape[0], 3))
+        for mode in (0, 1):
+            xf = P.lift(h, a, b, mode, torch.from_numpy(xc).cuda())
+            np.testing.assert_array_equal(host(xf), S.lift_between(maps, sizes, a, b, xc, mode),
+                                          err_msg=f"lift {b} -> {a} mode {mode}")
 
 
 def test_calls_queued_back_to_back_and_freed_without_waiting(P):
@@ -321,3 +331,51 @@ def test_calls_queued_back_to_back_and_freed_without_waiting(P):
             assert_same_graph(gc, gc_or, f"{what} level {l}")
             assert st.ms_total > 0
         h.free()
+
+
+def test_scan_flag_raised_once_does_not_fail_later_calls(P):
+    # one level that finds the scan chain's error flag raised fails; the
+    # next call on the same context starts with the flag clear
+    g = trimesh(40, ("uniform", 1, 8), seed=41)
+    dg = P.DeviceGraph.from_host(g)
+    say("scan flag", f"trimesh-40 n={g.n}")
+    P.coarsen_to(dg, g.n // 4, 0).free()        # the context's scan chain exists
+    P.set_option("scan_flag", 1)
+    with pytest.raises(P.SpcError) as e:
+        P.coarsen_to(dg, g.n // 4, 0)
+    assert e.value.code == P.SPC_EINVAL and "look-back" in str(e.value)
+    h = P.coarsen_to(dg, g.n // 4, 0)
+    want = oracle.coarsen_to(g, g.n // 4, 0)
+    for l, (c_or, gc_or, _) in enumerate(want, start=1):
+        cl, gc, _ = h.level(l)
+        np.testing.assert_array_equal(host(cl), c_or, err_msg=f"level {l} cluster_of")
+        assert_same_graph(gc, gc_or, f"level {l}")
+    h.free()
+
+
+def test_calls_on_two_streams(P):
+    # a call on one torch stream, then at once a call and the level exports
+    # on another: the context orders the new stream after the old one
+    import torch
+    ga = grid3d(28, ("uniform", 1, 16), seed=51)
+    gb = trimesh(120, ("uniform", 1, 8), seed=52)
+    da, db = P.DeviceGraph.from_host(ga), P.DeviceGraph.from_host(gb)
+    torch.cuda.synchronize()
+    say("two streams", f"grid3d-28 n={ga.n}, trimesh-120 n={gb.n}")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    with torch.cuda.stream(s1):
+        ha = P.coarsen_to(da, ga.n // 32, 0)
+    with torch.cuda.stream(s2):
+        hb = P.coarsen_to(db, gb.n // 16, 0)
+        out_a = [ha.level(l) for l in range(1, ha.num_levels + 1)]
+        out_b = [hb.level(l) for l in range(1, hb.num_levels + 1)]
+    s2.synchronize()
+    for outs, g, n_c, what in ((out_a, ga, ga.n // 32, "grid3d-28"), (out_b, gb, gb.n // 16, "trimesh-120")):
+        want = oracle.coarsen_to(g, n_c, 0)
+        assert len(outs) == len(want)
+        for l, ((c_or, gc_or, _), (cl, gc, _)) in enumerate(zip(want, outs), start=1):
+            np.testing.assert_array_equal(host(cl), c_or, err_msg=f"{what} level {l} cluster_of")
+            assert_same_graph(gc, gc_or, f"{what} level {l}")
+    torch.cuda.synchronize()
+    ha.free()
+    hb.free()

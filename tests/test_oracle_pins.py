@@ -415,6 +415,37 @@ def test_lift_vectors_orthonormal():
     np.testing.assert_allclose(S.restrict(U, c, gc.size), Q.T @ U, atol=1e-14)
 
 
+@pytest.mark.parametrize("seed", range(3))
+def test_lift_between_levels(seed):
+    """Lift between intermediate levels: orthonormal columns, composition
+    with the lift from the input equals the input's orthonormal lift
+    B S^-1/2 (built here from a dense membership matrix), and piecewise
+    constant vectors stay constant."""
+    g = random_graph(24, p=0.2, seed=seed, wmax=4)
+    levels = oracle.coarsen_to(g, 4, 0)
+    maps = [c for c, _, _ in levels]
+    sizes = [np.ones(g.n, np.int32)] + [gc.size for _, gc, _ in levels]
+    L = len(levels)
+    assert L >= 3
+    for a, b in [(1, L), (1, 2), (2, L), (0, L), (L - 1, L)]:
+        nb = sizes[b].shape[0]
+        P = S.lift_between(maps, sizes, a, b, np.eye(nb), mode=1)
+        np.testing.assert_allclose(P.T @ P, np.eye(nb), atol=1e-14)
+        one = S.lift_between(maps, sizes, a, b, np.ones(nb), mode=0)
+        assert np.all(one == 1.0)
+        # Q_a P = Q_b with Q_l = B_l S_l^-1/2 from the composed membership
+        def Q(lvl):
+            c = oracle.compose(levels, lvl) if lvl else np.arange(g.n)
+            k = sizes[lvl].shape[0]
+            B = np.zeros((g.n, k))
+            B[np.arange(g.n), c] = 1.0
+            return B / np.sqrt(B.sum(axis=0))[None, :]
+        np.testing.assert_allclose(Q(a) @ P, Q(b), atol=1e-14)
+    # identity when from == to
+    x = np.random.default_rng(seed).normal(size=(sizes[2].shape[0], 2))
+    assert np.array_equal(S.lift_between(maps, sizes, 2, 2, x, mode=1), x)
+
+
 # ----------------------------------------------------------------------------
 # Theorems 1 and 2 (brute force on tiny graphs)
 # ----------------------------------------------------------------------------
