@@ -179,6 +179,29 @@ const char* spc_strerror(int code);
 int spc_coarsen_level(spc_ctx* ctx, const spc_graph* g, int64_t n_target, int32_t* cluster_of,
                       spc_graph_out* coarse, int64_t* nnz_c, spc_level_stats* st);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * level as spc_coarsen_level, computed in the library's own fixed scratch
+ * array instead of an allocated workspace.  The call makes no allocation
+ * (no hipMalloc, hipFree, allocator hook, event or pinned-memory
+ * creation); the caller passes inputs and outputs as for
+ * spc_coarsen_level, and st->ms_total is 0 (not timed).
+ *   Scratch: SPC_NOALLOC_SCRATCH_BYTES per device, a static device array
+ *   held from the library's load until the process ends, its address
+ *   resolved once per device by spc_create.  The level needs about 100
+ *   bytes per CSR entry plus 170 per node (FP weights: about 160 more per
+ *   entry), so graphs up to roughly a million CSR entries fit; a larger one
+ *   gets SPC_ECAPACITY with the bytes it would need.
+ *   Every call on a device shares that device's array, which keeps the last
+ *   call's contents (the level clears what must start at zero).  Calls that
+ *   overlap on one device -- from two streams or two contexts on it --
+ *   race on the array; calls ordered on one stream do not.
+ * Errors: those of spc_coarsen_level, SPC_ECAPACITY for a graph too large
+ * for the array, SPC_EHIP if the array's address could not be resolved. */
+#define SPC_NOALLOC_SCRATCH_BYTES (134217728)
+int spc_coarsen_level_noalloc(spc_ctx* ctx, const spc_graph* g, int64_t n_target, int32_t* cluster_of,
+                              spc_graph_out* coarse, int64_t* nnz_c, spc_level_stats* st);
+
 /* Coarsen to n_c super-nodes level by level, re-scoring each level (the
  * multilevel refinement the conclusion proposes).  schedule 0: halve the
  * node count per level, t = max(n_c, ceil(n_l / 2)); schedule 1: a single

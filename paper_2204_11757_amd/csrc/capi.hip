@@ -3,6 +3,7 @@
 // the hierarchy, the lift (Definition 2) and the spectral error.
 #include <cmath>
 #include <cstdarg>
+#include <mutex>
 #include <new>
 
 #include "level.hpp"
@@ -44,6 +45,9 @@ void dev_free(spc_ctx* ctx, void* p) {
 
 int ensure_workspace(spc_ctx* ctx, size_t bytes) {
   if (bytes <= ctx->ws_cap) return SPC_OK;
+  if (ctx->no_alloc)
+    return set_error(ctx, SPC_ECAPACITY, "the level needs %zu bytes of workspace, the scratch array holds %zu",
+                     bytes, ctx->ws_cap);
   if (ctx->ws) {
     SPC_HIP(ctx, hipStreamSynchronize(ctx->stream));
     dev_free(ctx, ctx->ws);
@@ -66,6 +70,11 @@ int readback(spc_ctx* ctx, const void* dev, size_t bytes, void* host) {
 uint32_t scan_state_reserve(spc_ctx* ctx, int64_t words) {
   words += 1;   // the last word is the error flag
   if (words > ctx->scan_cap || ctx->scan_epoch >= LB_MAX_EPOCH) {
+    if (words > ctx->scan_cap && ctx->no_alloc) {
+      set_error(ctx, SPC_ECAPACITY, "a scan needs %lld look-back words, the scratch array holds %lld",
+                (long long)words, (long long)ctx->scan_cap);
+      return 0;
+    }
     if (words > ctx->scan_cap) {
       int64_t cap = words > (1 << 16) ? words : (1 << 16);
       if (ctx->scan_state) {
@@ -186,7 +195,7 @@ static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* clus
     return set_error(ctx, SPC_EINVAL, "output arrays are NULL");
   if (out->n_cap < t) return set_error(ctx, SPC_ECAPACITY, "n_cap %lld < %lld", (long long)out->n_cap, (long long)t);
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (st) {
+  if (st && !ctx->no_alloc) {
     // events from the context's pool (creating one is a runtime call the
     // level boundary need not wait for)
     e0 = ev_get(ctx);
@@ -267,7 +276,9 @@ static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* clus
   *nnz_c = R.nnz_c;
   if (st) {
     float ms = 0;
-    if (ev) {
+    if (!e0) {
+      // no events (the call that allocates nothing): not timed
+    } else if (ev) {
       SPC_HIP(ctx, hipEventRecord(e1, ctx->stream));
       ev[0] = e0;
       ev[1] = e1;
@@ -301,6 +312,35 @@ static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* clus
 }
 
 }  // namespace spc
+
+// ===========================================================================
+// scratch of the entry point that allocates nothing
+// ===========================================================================
+
+// One array per device, in the library's code object: the workspace of
+// spc_coarsen_level_noalloc (its first SPC_NOALLOC_SCAN_WORDS 8-byte words
+// from the end hold the scan chain's look-back words).  In host code the
+// name stands for a host-side shadow, not a device address: kernels only
+// ever receive the address hipGetSymbolAddress resolves for the current
+// device (kept per device in g_scratch).
+static __device__ __align__(256) char scratch[SPC_NOALLOC_SCRATCH_BYTES];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+constexpr int64_t SPC_NOALLOC_SCAN_WORDS = 1 << 16;
+static std::mutex g_scratch_mu;
+static void* g_scratch[SCRATCH_MAX_DEVICES];
+
+// Device address of `scratch` on `device`, which must be current; resolved
+// once per device.  Null when the lookup fails.
+static void* resolve_scratch(int device) {
+  if (device < 0 || device >= SCRATCH_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess && p) g_scratch[device] = p;
+  }
+  return g_scratch[device];
+}
 
 // ===========================================================================
 // hierarchy
@@ -381,6 +421,9 @@ int spc_create(spc_ctx** out, int device, void* stream) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     ctx->num_cus = cus;
+  // with the device current: this device's scratch array (a failure only
+  // disables the entry point that allocates nothing)
+  ctx->scratch = resolve_scratch(device);
   // coherent: the host polls a word that a running kernel writes
   if (hipHostMalloc((void**)&ctx->h_pinned, 4096, hipHostMallocCoherent) != hipSuccess) {
     delete ctx;
@@ -500,6 +543,54 @@ int spc_coarsen_level(spc_ctx* ctx, const spc_graph* g, int64_t n_target, int32_
   if (!ctx) return SPC_EINVAL;
   ctx->spec_ok = 0;   // a new graph: its first level waits for its forest
   return level_impl(ctx, g, n_target, cluster_of, coarse, nnz_c, st);
+}
+
+int spc_coarsen_level_noalloc(spc_ctx* ctx, const spc_graph* g, int64_t n_target, int32_t* cluster_of,
+                              spc_graph_out* coarse, int64_t* nnz_c, spc_level_stats* st) {
+  if (!ctx) return SPC_EINVAL;
+  if (!ctx->scratch)
+    return set_error(ctx, SPC_EHIP, "the scratch array of device %d could not be resolved", ctx->device);
+  int rc = check_graph(ctx, g);
+  if (rc) return rc;
+  const size_t scan_bytes = sizeof(uint64_t) * (size_t)SPC_NOALLOC_SCAN_WORDS;
+  const size_t ws_bytes = (size_t)SPC_NOALLOC_SCRATCH_BYTES - scan_bytes;
+  {
+    Arena count;
+    count.counting = true;
+    LevelWork W;
+    plan_level(count, g->n, g->nnz, W, g->wtype != SPC_W_I32);
+    if (count.off + 256 > ws_bytes)
+      return set_error(ctx, SPC_ECAPACITY,
+                       "n=%lld nnz=%lld needs %zu bytes of workspace; the scratch array holds %zu",
+                       (long long)g->n, (long long)g->nnz, (size_t)(count.off + 256), ws_bytes);
+  }
+  // the context's workspace and scan chain stand aside for the scratch
+  // array's; the scan words start cleared (the first scan clears them, as
+  // with a fresh chain), the level clears the rest of what must start at zero
+  void* ws = ctx->ws;
+  size_t ws_cap = ctx->ws_cap;
+  uint64_t* scan = ctx->scan_state;
+  int64_t scan_cap = ctx->scan_cap;
+  uint32_t scan_epoch = ctx->scan_epoch;
+  int timing = ctx->timing;
+  ctx->ws = ctx->scratch;
+  ctx->ws_cap = ws_bytes;
+  ctx->scan_state = (uint64_t*)((char*)ctx->scratch + ws_bytes);
+  ctx->scan_cap = SPC_NOALLOC_SCAN_WORDS;
+  ctx->scan_epoch = LB_MAX_EPOCH;
+  ctx->timing = 0;
+  ctx->no_alloc = 1;
+  ctx->spec_ok = 0;
+  rc = level_impl(ctx, g, n_target, cluster_of, coarse, nnz_c, st);
+  ctx->no_alloc = 0;
+  ctx->timing = timing;
+  ctx->ws = ws;
+  ctx->ws_cap = ws_cap;
+  ctx->scan_state = scan;
+  ctx->scan_cap = scan_cap;
+  ctx->scan_epoch = scan_epoch;
+  ctx->spec_ok = 0;
+  return rc;
 }
 
 int spc_coarsen_to(spc_ctx* ctx, const spc_graph* g, int64_t n_c, int schedule, spc_hier** out) {

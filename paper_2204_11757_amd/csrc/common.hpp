@@ -331,6 +331,11 @@ struct spc_ctx {
   int force_redo_rank = 0;   // flag every packed-key level as inexact (redone with rank keys)
   int force_bad_guess = 0;   // give the cutoff selection key bounds that some keys lie outside
   int force_scan_flag = 0;   // the next level finds the scan chain's error flag raised (once)
+  // the entry point that allocates nothing: this device's scratch array
+  // (resolved once per device at creation; null if that failed) and, during
+  // such a call, 1 so that nothing on the level path allocates
+  void* scratch = nullptr;
+  int no_alloc = 0;
   int contract_wait = 0;     // 0: as the last level suggests, 1: the host reads the row-class counts
                              // before the class kernels, 2: never (when the huge rows fit)
   int contract_dev = 0;      // the last level's row classes suited the contraction without that wait

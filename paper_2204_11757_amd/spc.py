@@ -34,6 +34,7 @@ EXPORTS = [
     "spc_spectral_error", "spc_validate_graph", "spc_timing_report", "spc_hier_cluster_map",
     "spc_spectral_error_graph", "spc_spectral_error_backward", "spc_entry_map",
     "spc_contract_backward", "spc_coarsen_batched", "spc_hier_graph_offsets",
+    "spc_coarsen_level_noalloc",
 ]
 
 
@@ -88,6 +89,8 @@ def lib():
             "spc_set_option": [p, C.c_char_p, i64],
             "spc_coarsen_level": [p, C.POINTER(_Graph), i64, p, C.POINTER(_GraphOut),
                                   C.POINTER(C.c_int64), C.POINTER(LevelStats)],
+            "spc_coarsen_level_noalloc": [p, C.POINTER(_Graph), i64, p, C.POINTER(_GraphOut),
+                                          C.POINTER(C.c_int64), C.POINTER(LevelStats)],
             "spc_coarsen_to": [p, C.POINTER(_Graph), i64, i32, C.POINTER(C.c_void_p)],
             "spc_hier_num_levels": [p],
             "spc_hier_level": [p, i32, C.POINTER(_Graph), C.POINTER(C.c_void_p),
@@ -315,6 +318,25 @@ def coarsen_level(g: DeviceGraph, n_target: int):
     coarse = DeviceGraph(n=n_c, row_ptr=out.row_ptr[: n_c + 1], col=out.col[:k], w=out.w[:k],
                          self_w=out.self_w[:n_c], size=out.size[:n_c])
     return cl, coarse, st
+
+
+SPC_NOALLOC_SCRATCH_BYTES = 134217728
+
+
+def coarsen_level_noalloc(g: DeviceGraph, n_target: int, cluster_of: torch.Tensor, out: DeviceGraph):
+    """coarsen_level for callers that cannot allocate: the library works in
+    its fixed per-device scratch array (SPC_NOALLOC_SCRATCH_BYTES) and
+    allocates nothing; the caller provides cluster_of (int32[n]) and the
+    output graph's tensors (capacities: out.n nodes, out.col.numel()
+    entries).  Returns (number of coarse entries, LevelStats)."""
+    ctx = context(_dev(g.row_ptr))
+    nnz = C.c_int64()
+    st = LevelStats()
+    gc = g._c()
+    oc = _out_c(out, out.n, int(out.col.numel()))
+    ctx.check(lib().spc_coarsen_level_noalloc(ctx.h, C.byref(gc), int(n_target), cluster_of.data_ptr(),
+                                              C.byref(oc), C.byref(nnz), C.byref(st)))
+    return nnz.value, st
 
 
 class Hierarchy:
