@@ -133,6 +133,7 @@ def test_roofline_workload_trimesh_4096_every_level(P):
     assert h.num_levels == len(targets) == len(gold["levels"]) == 7
     prev = g
     for lvl, (t, want) in enumerate(zip(targets, gold["levels"]), start=1):
+        say("trimesh-4096 level", lvl)
         cl, gc, st = h.level(lvl)
         gh = gc.to_host()
         c = host(cl)
@@ -159,6 +160,7 @@ def test_batch_of_4096_meshes_every_level_every_graph(P):
     assert L == len(gold["levels"]) == 4
     per_graph = [hashlib.sha256() for _ in graphs]
     for lvl in range(1, L + 1):
+        say("batch-4096 level", lvl)
         cl, gc, _ = h.level(lvl)
         gh = gc.to_host()
         c = host(cl)
