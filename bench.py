@@ -41,6 +41,12 @@ def make_config(name):
     if name == "trimesh-1024":
         g = trimesh(1024, ("uniform", 1, 8), seed=3)
         return g, g.n // 100, "jittered triangle mesh 1024x1024, int32 weights uniform in [1,8], to n/100"
+    if name == "powerlaw-131k":
+        from meshgen import powerlaw_graph
+        g = powerlaw_graph(1 << 17, avg_deg=8.0, gamma=2.5, seed=7)
+        return g, g.n // 100, (f"Chung-Lu power-law graph (irregular degrees): 131,072 nodes, {g.m:,} edges, "
+                               "expected degrees ~ i^(-1/1.5), mean 8, plus a path through all nodes, int32 "
+                               "weights uniform in [1,8] (seed 7), halving levels to n/100 = 1,310")
     if name == "grid2d-64":
         g = grid2d(64)
         return g, 1024, "2D 5-point grid 64x64, unit weights, halving to 1,024"

@@ -4,16 +4,27 @@
 // self-loop weight together with the members' own self-loops; sizes add.
 // Coarse rows are ascending in b with no diagonal entry.
 //
-// Rows are grouped by the number E_a of fine entries their members hold:
-//   E_a <= SMALL_CAP   one thread per coarse row, sorted insertion into a
-//                      thread-private LDS list (merging equal columns);
-//   E_a <= WAVE_CAP    one wavefront per row, bitonic sort in LDS;
-//   E_a <= BLOCK_CAP   one 256-thread block per row, bitonic sort in LDS;
-//   larger             all entries of such rows are gathered, merge-sorted
-//                      by (row, column) and reduced.
-// Each path writes its row's distinct (column, weight) pairs into a scratch
-// region at the row's gathered-entry offset; a scan of the row counts then
-// yields the coarse row_ptr and a tiled copy packs the entries.
+// Two streaming passes put every super-node's inputs side by side, then
+// one reduction per coarse row:
+//   slots    each fine node x holds 1 + len(x) records of super-node c(x)
+//            (a member record with its size and self-loop, then one record
+//            (c(y), w) per entry x -> y); run-aggregated atomics on the
+//            super-node's record count hand out x's slot range;
+//   scatter  entry-parallel tiles write every entry's record, and the
+//            member records, at those slots: super-node a's records are
+//            then contiguous at rec[gptr[a], gptr[a + 1]);
+//   reduce   by the record count E_a of the row:
+//              E_a <= SMALL_CAP   one thread, a sorted register list;
+//              E_a <= REG32_CAP   the same, longer list;
+//              E_a <= WAVE_CAP    one wavefront, bitonic sort in LDS;
+//              E_a <= BLOCK_CAP   one 256-thread block, bitonic sort in LDS;
+//              larger             dense accumulators over the coarse ids
+//                                 (few such rows) or a merge sort of all
+//                                 their records.
+// A row's distinct (column, weight) pairs overwrite its own records (they
+// are fewer), a scan of the row counts gives the coarse row pointer, and a
+// tiled copy packs the entries.  Integer sums do not depend on the order in
+// which the atomics placed the members, so the result is deterministic.
 #include "level.hpp"
 
 namespace spc {
@@ -24,6 +35,15 @@ constexpr int SMALL_BS = 128;
 constexpr int SMALL_RPT = 4;   // rows per thread, at most (fewer when there are few rows)
 constexpr int WAVE_CAP = 512;
 constexpr int BLOCK_CAP = 4096;
+
+// Records: an entry x -> y of a member is (c(y) << 32) | w (c(y) < 2^31); a
+// member record has bit 63 set, the member's size in bits 32..62 and its
+// self-loop weight in bits 0..31 (both below 2^31 by the weight bound).
+constexpr uint64_t REC_MEMBER = 1ull << 63;
+
+__device__ __forceinline__ uint64_t member_record(uint32_t size, uint32_t self) {
+  return REC_MEMBER | ((uint64_t)size << 32) | self;
+}
 
 // Lanes of a wavefront holding the same key in consecutive lanes form a
 // run.  head: this lane starts its run; end: one past the run's last lane
@@ -57,7 +77,7 @@ struct RunPieces {
   int32_t fc[CM_W], lc[CM_W];             // their lengths in nodes
   unsigned long long fe[CM_W], le[CM_W];  // their summed values
   int32_t single[CM_W];                   // the wavefront is one run
-  int32_t fb[CM_W], lb[CM_W];             // slot bases handed back (scatter)
+  unsigned long long fb[CM_W], lb[CM_W];  // slot bases handed back
 };
 
 // Border pieces: piece 0 of wavefront w is its first run, piece 1 its last
@@ -87,14 +107,21 @@ __device__ __forceinline__ bool chain_at(const RunPieces& P, int q, int32_t& key
   return true;
 }
 
-// member counts and gathered-entry counts per super-node
+// ---- slots: each fine node's record range inside its super-node -----------
+// Thread per node x (blocks of CM_BS): x needs 1 + len(x) slots of c(x).  A
+// run of lanes with one super-node takes its slots with one atomic on the
+// super-node's count; runs continuing across wavefront borders are chained
+// by thread 0's pieces (one atomic per chain).  off[x] = x's first slot
+// relative to its super-node's first record; ecnt[a] ends as a's record
+// count.
 __global__ void __launch_bounds__(CM_BS)
-    k_cluster_count(LevelIn g, const int32_t* __restrict__ c, int32_t* mcount, unsigned long long* ecnt) {
+    k_slot_alloc(LevelIn g, const int32_t* __restrict__ c, unsigned long long* ecnt,
+                 int64_t* __restrict__ off) {
   __shared__ RunPieces P;
   int64_t x = (int64_t)blockIdx.x * CM_BS + threadIdx.x;
   bool valid = x < g.n;
   int32_t a = valid ? c[x] : -1;
-  int64_t len = valid ? g.rp[x + 1] - g.rp[x] : 0;
+  int64_t len = valid ? 1 + (g.rp[x + 1] - g.rp[x]) : 0;
   bool head;
   int end;
   uint64_t heads;
@@ -102,6 +129,7 @@ __global__ void __launch_bounds__(CM_BS)
   int64_t inc = wave_incl_sum(len);
   int64_t at_end = __shfl(inc, end - 1);
   int l = lane_id(), w = threadIdx.x / WAVE;
+  unsigned long long base = 0;   // on head lanes of inner runs: the run's first slot
   if (head) {
     int cnt = end - l;
     unsigned long long e = (unsigned long long)(at_end - inc + len);
@@ -116,8 +144,7 @@ __global__ void __launch_bounds__(CM_BS)
       P.lc[w] = cnt;
       P.le[w] = e;
     } else if (a >= 0) {
-      atomicAdd(&mcount[a], cnt);
-      atomicAdd(&ecnt[a], e);
+      base = atomicAdd(&ecnt[a], e);
     }
   }
   __syncthreads();
@@ -126,59 +153,16 @@ __global__ void __launch_bounds__(CM_BS)
     int cnt, wl, pl;
     unsigned long long e;
     if (chain_at(P, threadIdx.x, k, cnt, e, wl, pl) && k >= 0) {
-      atomicAdd(&mcount[k], cnt);
-      atomicAdd(&ecnt[k], e);
-    }
-  }
-}
-
-// members[mptr[a] + slot] = x; slots are taken from the top of mcount[a]
-// downwards (the order of members inside a super-node is arbitrary)
-__global__ void __launch_bounds__(CM_BS)
-    k_member_scatter(const int32_t* __restrict__ c, const int32_t* __restrict__ mptr, int32_t* mcount,
-                     int32_t* __restrict__ members, int64_t n) {
-  __shared__ RunPieces P;
-  int64_t x = (int64_t)blockIdx.x * CM_BS + threadIdx.x;
-  bool valid = x < n;
-  int32_t a = valid ? c[x] : -1;
-  bool head;
-  int end;
-  uint64_t heads;
-  wave_runs(a, head, end, heads);
-  int l = lane_id(), w = threadIdx.x / WAVE;
-  int base = 0;   // on head lanes of inner runs: the run's first slot
-  if (head) {
-    int cnt = end - l;
-    bool first = l == 0, last = end == WAVE;
-    if (first) {
-      P.fk[w] = a;
-      P.fc[w] = cnt;
-      P.fe[w] = 0;
-      P.single[w] = last ? 1 : 0;
-    } else if (last) {
-      P.lk[w] = a;
-      P.lc[w] = cnt;
-      P.le[w] = 0;
-    } else if (a >= 0) {
-      base = atomicSub(&mcount[a], cnt) - cnt;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x < 2 * CM_W) {
-    int32_t k;
-    int cnt, wl, pl;
-    unsigned long long e;
-    if (chain_at(P, threadIdx.x, k, cnt, e, wl, pl) && k >= 0) {
-      int b = atomicSub(&mcount[k], cnt) - cnt;
-      // consecutive slots to the chain's pieces in block order
+      unsigned long long b = atomicAdd(&ecnt[k], e);
+      // consecutive slot ranges to the chain's pieces in block order
       int v = threadIdx.x >> 1, q = threadIdx.x & 1;
       while (true) {
         if (q == 0) {
           P.fb[v] = b;
-          b += P.fc[v];
+          b += P.fe[v];
         } else {
           P.lb[v] = b;
-          b += P.lc[v];
+          b += P.le[v];
         }
         if (v == wl && q == pl) break;
         v++;
@@ -188,29 +172,84 @@ __global__ void __launch_bounds__(CM_BS)
   }
   __syncthreads();
   int h = run_head_of(heads);
-  int bh = __shfl(base, h);
+  unsigned long long bh = __shfl(base, h);
   int endh = __shfl(end, h);
+  int64_t before_h = __shfl(inc, h) - __shfl(len, h);   // the wavefront's slots before the run
   if (valid) {
     if (h == 0) bh = P.fb[w];
     else if (endh == WAVE) bh = P.lb[w];
-    members[mptr[a] + bh + (l - h)] = (int32_t)x;
+    off[x] = (int64_t)bh + (inc - len - before_h);
   }
 }
 
-// One coarse row a by one thread: the sorted distinct (column, weight) list
-// is held in registers (every access uses a compile-time index), built by
-// insertion with equal columns merged.  Requires E_a <= CAP.
+// ---- scatter: every record to its slot --------------------------------------
+// Tiles of RT consecutive fine entries (mapped to rows by the load-balanced
+// search, renumbered per XCD so that a tile's neighbours share its L2) write
+// (c(y) << 32) | w at gptr[c(x)] + off[x] + 1 + (j - rp[x]); the blocks past
+// the tiles write the member records, RM nodes per block.
+constexpr int RT = 2048;
+constexpr int RT_BS = 256;
+constexpr int RT_PER = RT / RT_BS;
+constexpr int RM = 2048;
+
+__global__ void __launch_bounds__(RT_BS)
+    k_record_scatter(LevelIn g, const int32_t* __restrict__ c, const int64_t* __restrict__ gptr,
+                     const int64_t* __restrict__ off, uint64_t* __restrict__ rec, int tiles) {
+  __shared__ int32_t srow[Lbs<RT, RT_BS>::SIZE];
+  __shared__ int64_t sh[2];
+  __shared__ int32_t stmp[RT_BS / WAVE];
+  int tid = threadIdx.x;
+  if ((int)blockIdx.x >= tiles) {
+    int64_t x0 = (int64_t)(blockIdx.x - tiles) * RM;
+#pragma unroll
+    for (int i = 0; i < RM / RT_BS; i++) {
+      int64_t x = x0 + i * RT_BS + tid;
+      if (x >= g.n) break;
+      uint32_t sz = g.size ? (uint32_t)g.size[x] : 1u;
+      uint32_t sw = g.self ? (uint32_t)g.self[x] : 0u;
+      rec[gptr[c[x]] + off[x]] = member_record(sz, sw);
+    }
+    return;
+  }
+  int64_t p0 = xcd_tile(blockIdx.x, tiles) * RT;
+  lbs_tile<RT, RT_BS>(g.rp, g.n, p0, srow, sh, stmp);
+  int32_t xr[RT_PER], yr[RT_PER];
+  uint32_t wr[RT_PER];
+  int64_t pr[RT_PER];
+  // all loads of a stage issued before any is used
+#pragma unroll
+  for (int i = 0; i < RT_PER; i++) {
+    int k = tid + i * RT_BS;
+    int64_t j = p0 + k;
+    bool in = j < g.nnz;
+    xr[i] = in ? srow[Lbs<RT, RT_BS>::at(k)] : -1;
+    yr[i] = in ? g.col[j] : 0;
+    wr[i] = in ? (uint32_t)g.w[j] : 0u;
+  }
+#pragma unroll
+  for (int i = 0; i < RT_PER; i++) {
+    int64_t j = p0 + tid + i * RT_BS;
+    int32_t x = xr[i];
+    pr[i] = x >= 0 ? gptr[c[x]] + off[x] + 1 + (j - g.rp[x]) : 0;
+    yr[i] = x >= 0 ? c[yr[i]] : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < RT_PER; i++)
+    if (xr[i] >= 0) rec[pr[i]] = ((uint64_t)(uint32_t)yr[i] << 32) | wr[i];
+}
+
+// ---- rows of at most CAP records: one thread each ---------------------------
+// The sorted distinct (column, weight) list is held in registers (every
+// access uses a compile-time index), built by insertion with equal columns
+// merged; records are loaded EB at a time.  Returns the row's member count.
 template <int CAP>
-__device__ __forceinline__ void contract_row_regs(const LevelIn& g, const int32_t* __restrict__ c,
-                                                  const int32_t* __restrict__ mptr,
-                                                  const int32_t* __restrict__ members,
-                                                  const int64_t* __restrict__ gptr,
-                                                  uint64_t* __restrict__ temp,
-                                                  int64_t* __restrict__ cnt,
-                                                  int64_t* __restrict__ self_out,
-                                                  int32_t* __restrict__ size_out, int32_t a) {
+__device__ __forceinline__ int reduce_row_regs(const uint64_t* __restrict__ rec_in, uint64_t* __restrict__ rec_out,
+                                               const int64_t* __restrict__ gptr, int64_t* __restrict__ cnt,
+                                               int64_t* __restrict__ self_out, int32_t* __restrict__ size_out,
+                                               int32_t a) {
   int64_t self = 0;
   int32_t sz = 0;
+  int mem = 0;
   int cntd = 0;
   int32_t kb[CAP];
   uint32_t kw[CAP];
@@ -219,83 +258,68 @@ __device__ __forceinline__ void contract_row_regs(const LevelIn& g, const int32_
     kb[q] = INT32_MAX;
     kw[q] = 0;
   }
-  auto insert = [&](int32_t b, uint32_t wv) {
-    if (b == a) {
-      self += wv;
-      return;
-    }
-    bool found = false;
-    int ins = 0;
-#pragma unroll
-    for (int q = 0; q < CAP; q++) {
-      bool hit = kb[q] == b;
-      kw[q] += hit ? wv : 0u;   // sums stay below 2^31
-      found |= hit;
-      ins += kb[q] < b ? 1 : 0;
-    }
-    if (!found) {
-#pragma unroll
-      for (int q = CAP - 1; q >= 0; q--) {
-        if (q > ins) {
-          kb[q] = kb[q - 1];
-          kw[q] = kw[q - 1];
-        } else if (q == ins) {
-          kb[q] = b;
-          kw[q] = wv;
-        }
-      }
-      cntd++;
-    }
-  };
-  // a row's entries are loaded EB at a time and the next member's row
-  // bounds are fetched ahead, so that load latencies overlap
-  constexpr int EB = 4;
-  int32_t m0 = mptr[a], m1 = mptr[a + 1];
-  int32_t x = m0 < m1 ? members[m0] : -1;
-  int64_t rs = x >= 0 ? g.rp[x] : 0, re = x >= 0 ? g.rp[x + 1] : 0;
-  for (int32_t p = m0; p < m1; p++) {
-    int32_t xn = p + 1 < m1 ? members[p + 1] : -1;
-    sz += g.size ? g.size[x] : 1;
-    if (g.self) self += g.self[x];
-    int64_t rsn = xn >= 0 ? g.rp[xn] : 0, ren = xn >= 0 ? g.rp[xn + 1] : 0;
+  constexpr int EB = 8;
+  int64_t g0 = gptr[a], g1 = gptr[a + 1];
 #pragma unroll 1
-    for (int64_t j = rs; j < re; j += EB) {
-      int32_t bq[EB];
-      uint32_t wq[EB];
+  for (int64_t p = g0; p < g1; p += EB) {
+    uint64_t r[EB];
 #pragma unroll
-      for (int q = 0; q < EB; q++) {
-        bool ok = j + q < re;
-        bq[q] = ok ? g.col[j + q] : -1;
-        wq[q] = ok ? (uint32_t)g.w[j + q] : 0u;
+    for (int q = 0; q < EB; q++) r[q] = p + q < g1 ? rec_in[p + q] : ~0ull;
+#pragma unroll
+    for (int q = 0; q < EB; q++) {
+      if (r[q] == ~0ull) continue;
+      if (r[q] & REC_MEMBER) {
+        mem++;
+        sz += (int32_t)((r[q] >> 32) & 0x7fffffffu);
+        self += (uint32_t)r[q];
+        continue;
       }
+      int32_t b = (int32_t)(r[q] >> 32);
+      uint32_t wv = (uint32_t)r[q];
+      if (b == a) {
+        self += wv;
+        continue;
+      }
+      bool found = false;
+      int ins = 0;
 #pragma unroll
-      for (int q = 0; q < EB; q++) bq[q] = bq[q] >= 0 ? c[bq[q]] : -1;
+      for (int s = 0; s < CAP; s++) {
+        bool hit = kb[s] == b;
+        kw[s] += hit ? wv : 0u;   // sums stay below 2^31
+        found |= hit;
+        ins += kb[s] < b ? 1 : 0;
+      }
+      if (!found) {
 #pragma unroll
-      for (int q = 0; q < EB; q++)
-        if (bq[q] >= 0) insert(bq[q], wq[q]);
+        for (int s = CAP - 1; s >= 0; s--) {
+          if (s > ins) {
+            kb[s] = kb[s - 1];
+            kw[s] = kw[s - 1];
+          } else if (s == ins) {
+            kb[s] = b;
+            kw[s] = wv;
+          }
+        }
+        cntd++;
+      }
     }
-    x = xn;
-    rs = rsn;
-    re = ren;
   }
-  int64_t o = gptr[a];
+  // every record of the row is in registers: its slots may be overwritten
 #pragma unroll
   for (int q = 0; q < CAP; q++)
-    if (q < cntd) temp[o + q] = ((uint64_t)(uint32_t)kb[q] << 32) | kw[q];
+    if (q < cntd) rec_out[g0 + q] = ((uint64_t)(uint32_t)kb[q] << 32) | kw[q];
   cnt[a] = cntd;
   self_out[a] = self;
   size_out[a] = sz;
+  return mem;
 }
 
-// ---- rows with at most SMALL_CAP gathered entries: one thread each --------
 // RPT rows per thread: 4 when the rows fill the chip many times over (fewer
-// blocks on the class chains), fewer when there are few, so that the rows'
-// chains of dependent loads run on more threads side by side.
+// blocks on the class chains), fewer when there are few.  Rows above
+// SMALL_CAP records go to their class's list.
 template <int RPT>
 __global__ void __launch_bounds__(SMALL_BS)
-    k_contract_small(LevelIn g, const int32_t* __restrict__ c, const int32_t* __restrict__ mptr,
-                     const int32_t* __restrict__ members, const int64_t* __restrict__ gptr,
-                     uint64_t* __restrict__ temp, int64_t* __restrict__ cnt,
+    k_contract_small(uint64_t* __restrict__ rec, const int64_t* __restrict__ gptr, int64_t* __restrict__ cnt,
                      int64_t* __restrict__ self_out, int32_t* __restrict__ size_out, int64_t n_c,
                      int32_t* __restrict__ r32list, int32_t* __restrict__ midlist,
                      int32_t* __restrict__ blocklist, int32_t* __restrict__ hugelist,
@@ -312,8 +336,6 @@ __global__ void __launch_bounds__(SMALL_BS)
     int64_t a = base + r * SMALL_BS + tid;
     if (a >= n_c) break;
     int64_t E = gptr[a + 1] - gptr[a];
-    int32_t msz = mptr[a + 1] - mptr[a];
-    mx = msz > mx ? msz : mx;
     if (E > SMALL_CAP) {
       cnt[a] = 0;   // until its class's kernel writes it
       if (E <= REG32_CAP) {
@@ -328,12 +350,13 @@ __global__ void __launch_bounds__(SMALL_BS)
       } else {
         hugem |= 1u << r;
         nhuge++;
-        self_out[a] = 0;
+        self_out[a] = 0;   // the huge-row kernels add into these
         size_out[a] = 0;
       }
       continue;
     }
-    contract_row_regs<SMALL_CAP>(g, c, mptr, members, gptr, temp, cnt, self_out, size_out, (int32_t)a);
+    int mem = reduce_row_regs<SMALL_CAP>(rec, rec, gptr, cnt, self_out, size_out, (int32_t)a);
+    mx = mem > mx ? mem : mx;
   }
   mx = wave_max(mx);
   if (lane_id() == 0) smx[tid / WAVE] = mx;
@@ -382,114 +405,123 @@ __global__ void __launch_bounds__(SMALL_BS)
   }
 }
 
-// ---- listed rows with at most REG32_CAP gathered entries: one thread each --
+// ---- listed rows of at most REG32_CAP records: one thread each ----------------
 __global__ void __launch_bounds__(SMALL_BS)
-    k_contract_reg32(LevelIn g, const int32_t* __restrict__ c, const int32_t* __restrict__ mptr,
-                     const int32_t* __restrict__ members, const int64_t* __restrict__ gptr,
+    k_contract_reg32(uint64_t* __restrict__ rec, const int64_t* __restrict__ gptr,
                      const int32_t* __restrict__ rows, int64_t nrows, const unsigned long long* nrows_dev,
-                     uint64_t* __restrict__ temp, int64_t* __restrict__ cnt, int64_t* __restrict__ self_out,
-                     int32_t* __restrict__ size_out) {
+                     int64_t* __restrict__ cnt, int64_t* __restrict__ self_out, int32_t* __restrict__ size_out,
+                     unsigned long long* info) {
   // (with nrows_dev the count is read here and the grid strides over it)
   int64_t nr = nrows_dev ? (int64_t)*nrows_dev : nrows;
-  for (int64_t i = (int64_t)blockIdx.x * SMALL_BS + threadIdx.x; i < nr; i += (int64_t)gridDim.x * SMALL_BS)
-    contract_row_regs<REG32_CAP>(g, c, mptr, members, gptr, temp, cnt, self_out, size_out, rows[i]);
+  int mx = 0;
+  for (int64_t i = (int64_t)blockIdx.x * SMALL_BS + threadIdx.x; i < nr; i += (int64_t)gridDim.x * SMALL_BS) {
+    int mem = reduce_row_regs<REG32_CAP>(rec, rec, gptr, cnt, self_out, size_out, rows[i]);
+    mx = mem > mx ? mem : mx;
+  }
+  mx = wave_max(mx);
+  if (lane_id() == 0 && (unsigned long long)mx >
+      __hip_atomic_load(&info[I_MAXCL], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    atomicMax(&info[I_MAXCL], (unsigned long long)mx);
 }
 
-// ---- rows with at most CAP gathered entries: one BS-thread block each ----
+// ---- listed rows of at most CAP records: one TB-thread block each -----------
 template <int TB, int CAP>
 __global__ void __launch_bounds__(TB)
-    k_contract_row(LevelIn g, const int32_t* __restrict__ c, const int32_t* __restrict__ mptr,
-                   const int32_t* __restrict__ members, const int64_t* __restrict__ gptr,
+    k_contract_row(uint64_t* __restrict__ rec, const int64_t* __restrict__ gptr,
                    const int32_t* __restrict__ rowlist, const unsigned long long* nrows_dev,
-                   uint64_t* __restrict__ temp, int64_t* __restrict__ cnt, int64_t* __restrict__ self_out,
-                   int32_t* __restrict__ size_out) {
+                   int64_t* __restrict__ cnt, int64_t* __restrict__ self_out, int32_t* __restrict__ size_out,
+                   unsigned long long* info) {
   __shared__ uint64_t ent[CAP];
   __shared__ int lcnt;
   __shared__ unsigned long long lself;
-  __shared__ int lsize;
+  __shared__ int lsize, lmem;
   __shared__ int32_t stmp[TB / WAVE];
   int tid = threadIdx.x;
   // one row per block, or (nrows_dev: the count is read here) the blocks
   // stride over the rows
   int64_t nr = nrows_dev ? (int64_t)*nrows_dev : (int64_t)gridDim.x;
   for (int64_t r = blockIdx.x; r < nr; r += gridDim.x) {
-  int32_t a = rowlist[r];
-  if (tid == 0) {
-    lcnt = 0;
-    lself = 0;
-    lsize = 0;
-  }
-  __syncthreads();
-  int64_t self = 0;
-  int32_t sz = 0;
-  for (int32_t p = mptr[a] + tid; p < mptr[a + 1]; p += TB) {
-    int32_t x = members[p];
-    sz += g.size ? g.size[x] : 1;
-    if (g.self) self += g.self[x];
-    for (int64_t j = g.rp[x]; j < g.rp[x + 1]; j++) {
-      int32_t b = c[g.col[j]];
-      uint32_t wv = (uint32_t)g.w[j];
-      if (b == a) {
-        self += wv;
+    int32_t a = rowlist[r];
+    if (tid == 0) {
+      lcnt = 0;
+      lself = 0;
+      lsize = 0;
+      lmem = 0;
+    }
+    __syncthreads();
+    int64_t g0 = gptr[a], g1 = gptr[a + 1];
+    int64_t self = 0;
+    int32_t sz = 0, mem = 0;
+    for (int64_t p = g0 + tid; p < g1; p += TB) {
+      uint64_t v = rec[p];
+      if (v & REC_MEMBER) {
+        mem++;
+        sz += (int32_t)((v >> 32) & 0x7fffffffu);
+        self += (uint32_t)v;
+      } else if ((int32_t)(v >> 32) == a) {
+        self += (uint32_t)v;
       } else {
-        int pos = atomicAdd(&lcnt, 1);
-        ent[pos] = ((uint64_t)(uint32_t)b << 32) | wv;
+        ent[atomicAdd(&lcnt, 1)] = v;
       }
     }
-  }
-  self = wave_sum(self);
-  sz = wave_sum(sz);
-  if (lane_id() == 0) {
-    atomicAdd(&lself, (unsigned long long)self);
-    atomicAdd(&lsize, sz);
-  }
-  __syncthreads();
-  int K = lcnt;
-  int P2 = 1;
-  while (P2 < K) P2 <<= 1;
-  for (int i = K + tid; i < P2; i += TB) ent[i] = KEY_INF;
-  __syncthreads();
-  for (int k = 2; k <= P2; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int p = tid; p < P2 / 2; p += TB) {
-        int i = 2 * j * (p / j) + (p % j);
-        int l = i + j;
-        bool asc = (i & k) == 0;
-        uint64_t x = ent[i], y = ent[l];
-        if (asc ? (y < x) : (x < y)) {
-          ent[i] = y;
-          ent[l] = x;
+    self = wave_sum(self);
+    sz = wave_sum(sz);
+    mem = wave_sum(mem);
+    if (lane_id() == 0) {
+      atomicAdd(&lself, (unsigned long long)self);
+      atomicAdd(&lsize, sz);
+      atomicAdd(&lmem, mem);
+    }
+    __syncthreads();
+    int K = lcnt;
+    int P2 = 1;
+    while (P2 < K) P2 <<= 1;
+    for (int i = K + tid; i < P2; i += TB) ent[i] = KEY_INF;
+    __syncthreads();
+    for (int k = 2; k <= P2; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int p = tid; p < P2 / 2; p += TB) {
+          int i = 2 * j * (p / j) + (p % j);
+          int l = i + j;
+          bool asc = (i & k) == 0;
+          uint64_t x = ent[i], y = ent[l];
+          if (asc ? (y < x) : (x < y)) {
+            ent[i] = y;
+            ent[l] = x;
+          }
         }
+        __syncthreads();
       }
-      __syncthreads();
     }
-  }
-  // distinct columns in ascending order, weights summed
-  int64_t o = gptr[a];
-  int carry = 0;
-  for (int base = 0; base < K; base += TB) {
-    int i = base + tid;
-    bool head = false;
-    uint32_t b = 0;
-    if (i < K) {
-      b = (uint32_t)(ent[i] >> 32);
-      head = (i == 0) || ((uint32_t)(ent[i - 1] >> 32) != b);
+    // distinct columns in ascending order, weights summed, over the row's
+    // own records (all of them are in LDS now)
+    int carry = 0;
+    for (int base = 0; base < K; base += TB) {
+      int i = base + tid;
+      bool head = false;
+      uint32_t b = 0;
+      if (i < K) {
+        b = (uint32_t)(ent[i] >> 32);
+        head = (i == 0) || ((uint32_t)(ent[i - 1] >> 32) != b);
+      }
+      int32_t tot;
+      int32_t inc = block_incl_scan<int32_t, TB, false>(head ? 1 : 0, stmp, &tot);
+      if (head) {
+        uint64_t sum = 0;
+        for (int q = i; q < K && (uint32_t)(ent[q] >> 32) == b; q++) sum += (uint32_t)ent[q];
+        rec[g0 + carry + inc - 1] = ((uint64_t)b << 32) | sum;
+      }
+      carry += tot;
     }
-    int32_t tot;
-    int32_t inc = block_incl_scan<int32_t, TB, false>(head ? 1 : 0, stmp, &tot);
-    if (head) {
-      uint64_t sum = 0;
-      for (int q = i; q < K && (uint32_t)(ent[q] >> 32) == b; q++) sum += (uint32_t)ent[q];
-      temp[o + carry + inc - 1] = ((uint64_t)b << 32) | sum;
+    if (tid == 0) {
+      cnt[a] = carry;
+      self_out[a] = (int64_t)lself;
+      size_out[a] = lsize;
+      if ((unsigned long long)lmem >
+          __hip_atomic_load(&info[I_MAXCL], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(&info[I_MAXCL], (unsigned long long)lmem);
     }
-    carry += tot;
-  }
-  if (tid == 0) {
-    cnt[a] = carry;
-    self_out[a] = (int64_t)lself;
-    size_out[a] = lsize;
-  }
-  __syncthreads();   // the next row reuses the block's LDS
+    __syncthreads();   // the next row reuses the block's LDS
   }
 }
 
@@ -501,34 +533,14 @@ struct LessKW {
   __device__ __forceinline__ bool operator()(const KW& a, const KW& b) const { return a.key < b.key; }
 };
 
-// hcount[h] = members of huge row h, for h < H.  With H_dev (the count in
-// device memory, launch bound H), rows past that count get 0, and a count
-// above the bound sets *over and leaves every entry 0.
-__global__ void k_huge_members_count(const int32_t* __restrict__ hugelist, int64_t H,
-                                     const int32_t* __restrict__ mptr, int64_t* __restrict__ hcount,
-                                     const unsigned long long* H_dev, unsigned long long* over) {
-  int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t Hn = H;
-  if (H_dev) {
-    Hn = (int64_t)*H_dev;
-    if (Hn > H) {
-      if (h == 0) *over = 1;
-      Hn = 0;
-    }
-  }
-  if (h < Hn) {
-    int32_t a = hugelist[h];
-    hcount[h] = mptr[a + 1] - mptr[a];
-  } else if (h < H) {
-    hcount[h] = 0;
-  }
-}
-
-// The same for at most 64 rows, by one wavefront, which also takes the
-// exclusive prefix: hoff[h] = members of rows before h, hoff[H] = all.
-__global__ void k_huge_members_prefix(const int32_t* __restrict__ hugelist, int64_t H,
-                                      const int32_t* __restrict__ mptr, int64_t* __restrict__ hoff,
-                                      const unsigned long long* H_dev, unsigned long long* over) {
+// ---- rows of more than BLOCK_CAP records ("huge") ---------------------------
+// hoff[h] = records of the listed huge rows before h (hoff[H] = all).  With
+// H_dev (the count in device memory, launch bound H) rows past that count
+// have no records, and a count above the bound sets *over and leaves every
+// row empty.  At most 64 rows: one wavefront takes the prefix.
+__global__ void k_huge_prefix_wave(const int32_t* __restrict__ hugelist, int64_t H,
+                                   const int64_t* __restrict__ gptr, int64_t* __restrict__ hoff,
+                                   const unsigned long long* H_dev, unsigned long long* over) {
   int h = threadIdx.x;
   int64_t Hn = H;
   if (H_dev) {
@@ -541,243 +553,52 @@ __global__ void k_huge_members_prefix(const int32_t* __restrict__ hugelist, int6
   int64_t v = 0;
   if (h < Hn) {
     int32_t a = hugelist[h];
-    v = mptr[a + 1] - mptr[a];
+    v = gptr[a + 1] - gptr[a];
   }
   int64_t incl = wave_incl_sum(v);
   if (h < H) hoff[h] = incl - v;
   if (h == WAVE - 1) hoff[H] = incl;
 }
 
-// huge member i (0 <= i < HM, members of huge rows concatenated in list
-// order) -> its huge row h (binary search in hoff[0..H]) and node
-__device__ __forceinline__ int32_t huge_row_of(const int64_t* __restrict__ hoff, int64_t H, int64_t i) {
-  int64_t lo = 0, hi = H - 1;
-  while (lo < hi) {
-    int64_t mid = (lo + hi + 1) >> 1;
-    if (hoff[mid] <= i) lo = mid;
-    else hi = mid - 1;
-  }
-  return (int32_t)lo;
-}
-
-// per huge member: its row length; its self-loop and size go to the
-// super-node with integer atomics (order-independent).  A block covers
-// HMB_T consecutive members, so at most HMB_T rows: lanes of one run add in
-// registers, runs add in LDS, and each row a block touches costs one global
-// atomic per quantity.
-constexpr int HMB_BS = 256;
-constexpr int HMB_T = 1024;
-
-// The member count HM = hoff[H] is read on the device; the launch covers a
-// bound (>= HM) and positions HM..bound-1 get zero row lengths, so a scan
-// over the bound gives the member row prefix with its total at hlen[bound].
-__global__ void __launch_bounds__(HMB_BS)
-    k_huge_members(LevelIn g, const int32_t* __restrict__ hugelist, const int32_t* __restrict__ mptr,
-                   const int32_t* __restrict__ members, const int64_t* __restrict__ hoff, int64_t H,
-                   int64_t bound, int64_t* __restrict__ hpre, int32_t* __restrict__ hrow,
-                   int64_t* __restrict__ hrs, int64_t* self_out, int32_t* size_out,
-                   const unsigned long long* H_dev, TileScan ts, uint32_t* __restrict__ zero,
-                   int64_t nzero) {
-  constexpr int PER = HMB_T / HMB_BS;
-  // (the dense accumulators of the next launch start at zero)
-  for (int64_t i = (int64_t)blockIdx.x * HMB_BS + threadIdx.x; i < nzero; i += (int64_t)gridDim.x * HMB_BS)
-    zero[i] = 0;
-  __shared__ unsigned long long sself[HMB_T];
-  __shared__ int32_t ssize[HMB_T];
-  __shared__ int32_t sh0;
-  __shared__ int64_t stmp64[HMB_BS / WAVE];
-  __shared__ int64_t sbase;
-  int tid = threadIdx.x;
-  int64_t i0 = (int64_t)blockIdx.x * HMB_T;
-  if (H_dev) {
-    // the count in device memory; above the launch bound H nothing is done
-    // (k_huge_members_count flagged it and left hoff all 0)
-    int64_t Hn = (int64_t)*H_dev;
-    H = Hn <= H ? Hn : 0;
-  }
-  int64_t HM = hoff[H];
-  int64_t len[PER];
-#pragma unroll
-  for (int r = 0; r < PER; r++) len[r] = 0;
-  if (i0 < HM) {   // uniform over the block
-    for (int k = tid; k < HMB_T; k += HMB_BS) {
-      sself[k] = 0;
-      ssize[k] = 0;
-    }
-    if (tid == 0) sh0 = huge_row_of(hoff, H, i0);
-    __syncthreads();
-    int32_t h0 = sh0;
-#pragma unroll
-    for (int r = 0; r < PER; r++) {
-      int64_t i = i0 + r * HMB_BS + tid;
-      bool valid = i < HM;
-      int32_t h = -1;
-      int64_t self = 0;
-      int32_t sz = 0;
-      if (valid) {
-        h = huge_row_of(hoff, H, i);
-        int32_t x = members[mptr[hugelist[h]] + (i - hoff[h])];
-        self = g.self ? g.self[x] : 0;
-        sz = g.size ? g.size[x] : 1;
-        int64_t rs = g.rp[x];
-        len[r] = g.rp[x + 1] - rs;
-        hrow[i] = h;
-        hrs[i] = rs;
-      }
-      bool head;
-      int end;
-      uint64_t heads;
-      wave_runs(h, head, end, heads);
-      int64_t si = wave_incl_sum(self);
-      int32_t zi = wave_incl_sum(sz);
-      int64_t se = __shfl(si, end - 1);
-      int32_t ze = __shfl(zi, end - 1);
-      if (head && h >= 0) {
-        atomicAdd(&sself[h - h0], (unsigned long long)(se - si + self));
-        atomicAdd(&ssize[h - h0], ze - zi + sz);
-      }
-    }
-    __syncthreads();
-    for (int k = tid; k < HMB_T; k += HMB_BS) {
-      if (h0 + k >= H) break;
-      if (hoff[h0 + k] >= i0 + HMB_T) break;   // row starts after this block
-      int32_t a = hugelist[h0 + k];
-      if (sself[k]) atomicAdd((unsigned long long*)&self_out[a], sself[k]);
-      if (ssize[k]) atomicAdd(&size_out[a], ssize[k]);
-    }
-  }
-  // hpre: exclusive prefix of the member row lengths in member order (0 past
-  // the huge members), block offsets chained by a decoupled look-back; the
-  // last block stores the total at hpre[bound]
-  int64_t run = 0, pre[PER];
-#pragma unroll
-  for (int r = 0; r < PER; r++) {
-    int64_t tot;
-    int64_t inc = block_incl_scan<int64_t, HMB_BS, false>(len[r], stmp64, &tot);
-    pre[r] = run + inc - len[r];
-    run += tot;
-  }
-  if (tid < WAVE) {
-    uint64_t ex = lb_exclusive_wave(ts, blockIdx.x, (uint64_t)run);
-    if (tid == 0) {
-      sbase = (int64_t)ex;
-      if (blockIdx.x == gridDim.x - 1) hpre[bound] = (int64_t)ex + run;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < PER; r++) {
-    int64_t i = i0 + r * HMB_BS + tid;
-    if (i < bound) hpre[i] = sbase + pre[r];
+// more rows (host-known count): per-row record counts, scanned afterwards
+__global__ void k_huge_count(const int32_t* __restrict__ hugelist, int64_t H, const int64_t* __restrict__ gptr,
+                             int64_t* __restrict__ hcount) {
+  int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h < H) {
+    int32_t a = hugelist[h];
+    hcount[h] = gptr[a + 1] - gptr[a];
   }
 }
 
-// every fine entry of every huge member, in tiles of 4096 mapped to members
-// by a load-balanced search over the member row-length prefix hpre: intra
-// entries add to the self-loop, cross entries are gathered as
-// ((h << 32) | b, w) for the sort
+// Record q (0 <= q < hoff[H]) of the huge rows in list order belongs to row
+// srow's h; member records and intra entries add to the row's size, member
+// count and self-loop (lanes of one row summed in registers, then in LDS: a
+// tile of HD <= BLOCK_CAP records meets at most two rows, since every huge
+// row has more), cross entries go to `cross(h, a, b, w)`.
 constexpr int HT = 4096;
 constexpr int HT_BS = 256;
-static_assert(HT <= BLOCK_CAP, "a tile of gathered entries must meet at most two huge rows");
+static_assert(HT <= BLOCK_CAP, "a tile of records must meet at most two huge rows");
 
-__global__ void __launch_bounds__(HT_BS)
-    k_huge_entries(LevelIn g, const int32_t* __restrict__ c, const int32_t* __restrict__ hugelist,
-                   const int32_t* __restrict__ hrow, const int64_t* __restrict__ hrs,
-                   const int64_t* __restrict__ hpre, int64_t bound, int64_t* self_out,
-                   KW* __restrict__ out, unsigned long long* gcnt, TileScan ts) {
-  __shared__ int32_t srow[Lbs<HT, HT_BS>::SIZE];
-  __shared__ int64_t sh[2];
-  __shared__ int32_t stmp[HT_BS / WAVE];
-  __shared__ unsigned long long sbase;
-  // a huge row has more than HT gathered entries, so a tile meets at most
-  // two rows: h0 and h0 + 1
-  __shared__ unsigned long long sself[2];
-  int64_t q0 = (int64_t)blockIdx.x * HT;
-  int64_t total = hpre[bound];
+struct HugeSums {
+  unsigned long long self[2];
+  int32_t size[2];
+  int32_t mem[2];
+};
+
+template <int HD, typename Cross>
+__device__ __forceinline__ void huge_tile(const uint64_t* __restrict__ rec, const int64_t* __restrict__ gptr,
+                                          const int32_t* __restrict__ hugelist, const int64_t* __restrict__ hoff,
+                                          int64_t H, int64_t q0, int64_t total, int64_t* self_out,
+                                          int32_t* size_out, int64_t* hmem, HugeSums& S, int32_t* srow,
+                                          int64_t* sh, int32_t* stmp, Cross cross) {
+  lbs_tile<HD, HT_BS>(hoff, H, q0, srow, sh, stmp);
   int tid = threadIdx.x;
-  if (q0 >= total) {   // past the gathered entries: an empty tile of the chain
-    block_reserve_lb<HT_BS>(ts, blockIdx.x, blockIdx.x == gridDim.x - 1, 0, nullptr, gcnt, &sbase, stmp);
-    return;
+  if (tid < 2) {
+    S.self[tid] = 0;
+    S.size[tid] = 0;
+    S.mem[tid] = 0;
   }
-  lbs_tile<HT, HT_BS>(hpre, bound, q0, srow, sh, stmp);
-  if (tid < 2) sself[tid] = 0;
-  int32_t h0 = hrow[srow[0]];
-  __syncthreads();
-  uint32_t cross = 0;
-  int ncross = 0;
-  uint64_t keyv[HT / HT_BS];
-  uint32_t wv[HT / HT_BS];
-#pragma unroll
-  for (int r = 0; r < HT / HT_BS; r++) {
-    int k = tid + r * HT_BS;
-    int64_t q = q0 + k;
-    int32_t h = -1;
-    int64_t self = 0;
-    keyv[r] = 0;
-    wv[r] = 0;
-    if (q < total) {
-      int64_t i = srow[Lbs<HT, HT_BS>::at(k)];
-      h = hrow[i];
-      int32_t a = hugelist[h];
-      int64_t j = hrs[i] + (q - hpre[i]);
-      int32_t b = c[g.col[j]];
-      uint32_t w = (uint32_t)g.w[j];
-      if (b == a) {
-        self = w;
-      } else {
-        cross |= 1u << r;
-        ncross++;
-        keyv[r] = ((uint64_t)(uint32_t)h << 32) | (uint32_t)b;
-        wv[r] = w;
-      }
-    }
-    bool head;
-    int end;
-    uint64_t heads;
-    wave_runs(h, head, end, heads);
-    int64_t si = wave_incl_sum(self);
-    int64_t se = __shfl(si, end - 1);
-    if (head && h >= 0 && se - si + self)
-      atomicAdd(&sself[h - h0], (unsigned long long)(se - si + self));
-  }
-  __syncthreads();
-  if (tid < 2 && sself[tid]) atomicAdd((unsigned long long*)&self_out[hugelist[h0 + tid]], sself[tid]);
-  int64_t pos = block_reserve_lb<HT_BS>(ts, blockIdx.x, blockIdx.x == gridDim.x - 1, ncross, nullptr,
-                                       gcnt, &sbase, stmp);
-#pragma unroll
-  for (int r = 0; r < HT / HT_BS; r++)
-    if (cross >> r & 1u) out[pos++] = KW{keyv[r], (uint64_t)wv[r]};
-}
-
-// Dense path for few huge rows: row h's cross weights accumulate in
-// dense[h * ncp + (b - base[h])] (u32; a row's total stays below 2^31), then
-// a compaction in ascending b emits the row.  base is null (0) for one graph;
-// in a batch it is the first coarse node of the row's graph, whose coarse
-// range (at most ncp wide) holds every column of the row.  Same self-loop
-// handling as k_huge_entries, in tiles of HD entries: 4096 on large levels,
-// 1024 (4 per thread) on small ones, where an entry's chain of dependent
-// loads would otherwise repeat 16 times per thread on few blocks.
-constexpr int64_t HD_SMALL_NNZ = 4000000;   // levels up to this many entries use 1024-entry tiles
-
-template <int HD>
-__global__ void __launch_bounds__(HT_BS)
-    k_huge_dense(LevelIn g, const int32_t* __restrict__ c, const int32_t* __restrict__ hugelist,
-                 const int32_t* __restrict__ hrow, const int64_t* __restrict__ hrs,
-                 const int64_t* __restrict__ hpre, int64_t bound, int64_t* self_out,
-                 uint32_t* __restrict__ dense, int64_t ncp, const int32_t* __restrict__ base,
-                 unsigned long long* bad) {
-  __shared__ int32_t srow[Lbs<HD, HT_BS>::SIZE];
-  __shared__ int64_t sh[2];
-  __shared__ int32_t stmp[HT_BS / WAVE];
-  static_assert(HD <= HT && HD % HT_BS == 0, "a dense tile meets at most two huge rows");
-  __shared__ unsigned long long sself[2];
-  int64_t q0 = (int64_t)blockIdx.x * HD;
-  int64_t total = hpre[bound];
-  if (q0 >= total) return;
-  lbs_tile<HD, HT_BS>(hpre, bound, q0, srow, sh, stmp);
-  int tid = threadIdx.x;
-  if (tid < 2) sself[tid] = 0;
-  int32_t h0 = hrow[srow[0]];
+  int32_t h0 = srow[0];
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < HD / HT_BS; r++) {
@@ -785,29 +606,114 @@ __global__ void __launch_bounds__(HT_BS)
     int64_t q = q0 + k;
     int32_t h = -1;
     int64_t self = 0;
+    int32_t sz = 0, mem = 0;
     if (q < total) {
-      int64_t i = srow[Lbs<HD, HT_BS>::at(k)];
-      h = hrow[i];
+      h = srow[Lbs<HD, HT_BS>::at(k)];
       int32_t a = hugelist[h];
-      int64_t j = hrs[i] + (q - hpre[i]);
-      int32_t b = c[g.col[j]];
-      uint32_t w = (uint32_t)g.w[j];
-      int64_t rel = (int64_t)b - (base ? base[h] : 0);
-      if (b == a) self = w;
-      else if ((uint64_t)rel < (uint64_t)ncp) atomicAdd(&dense[(int64_t)h * ncp + rel], w);
-      else *bad = 1;
+      uint64_t v = rec[gptr[a] + (q - hoff[h])];
+      if (v & REC_MEMBER) {
+        mem = 1;
+        sz = (int32_t)((v >> 32) & 0x7fffffffu);
+        self = (uint32_t)v;
+      } else if ((int32_t)(v >> 32) == a) {
+        self = (uint32_t)v;
+      } else {
+        cross(r, h, (int32_t)(v >> 32), (uint32_t)v);
+      }
     }
     bool head;
     int end;
     uint64_t heads;
     wave_runs(h, head, end, heads);
     int64_t si = wave_incl_sum(self);
+    int32_t zi = wave_incl_sum(sz), mi = wave_incl_sum(mem);
     int64_t se = __shfl(si, end - 1);
-    if (head && h >= 0 && se - si + self)
-      atomicAdd(&sself[h - h0], (unsigned long long)(se - si + self));
+    int32_t ze = __shfl(zi, end - 1), me = __shfl(mi, end - 1);
+    if (head && h >= 0) {
+      if (se - si + self) atomicAdd(&S.self[h - h0], (unsigned long long)(se - si + self));
+      if (ze - zi + sz) atomicAdd(&S.size[h - h0], ze - zi + sz);
+      if (me - mi + mem) atomicAdd(&S.mem[h - h0], me - mi + mem);
+    }
   }
   __syncthreads();
-  if (tid < 2 && sself[tid]) atomicAdd((unsigned long long*)&self_out[hugelist[h0 + tid]], sself[tid]);
+  if (tid < 2 && h0 + tid < H) {
+    int32_t a = hugelist[h0 + tid];
+    if (S.self[tid]) atomicAdd((unsigned long long*)&self_out[a], S.self[tid]);
+    if (S.size[tid]) atomicAdd(&size_out[a], S.size[tid]);
+    if (S.mem[tid]) atomicAdd((unsigned long long*)&hmem[h0 + tid], (unsigned long long)S.mem[tid]);
+  }
+}
+
+// Dense path for few huge rows: row h's cross weights accumulate in
+// dense[h * ncp + (b - base[h])] (u32; a row's total stays below 2^31), then
+// a compaction in ascending b emits the row.  base is null (0) for one graph;
+// in a batch it is the first coarse node of the row's graph, whose coarse
+// range (at most ncp wide) holds every column of the row.  Tiles of HD
+// records: 4096 on large levels, 1024 (4 per thread) on small ones.
+constexpr int64_t HD_SMALL_NNZ = 4000000;   // levels up to this many entries use 1024-record tiles
+
+template <int HD>
+__global__ void __launch_bounds__(HT_BS)
+    k_huge_dense(const uint64_t* __restrict__ rec, const int64_t* __restrict__ gptr,
+                 const int32_t* __restrict__ hugelist, const int64_t* __restrict__ hoff, int64_t H,
+                 int64_t* self_out, int32_t* size_out, int64_t* hmem, uint32_t* __restrict__ dense, int64_t ncp,
+                 const int32_t* __restrict__ base, unsigned long long* bad) {
+  __shared__ int32_t srow[Lbs<HD, HT_BS>::SIZE];
+  __shared__ int64_t sh[2];
+  __shared__ int32_t stmp[HT_BS / WAVE];
+  __shared__ HugeSums S;
+  static_assert(HD <= HT && HD % HT_BS == 0, "a dense tile meets at most two huge rows");
+  int64_t q0 = (int64_t)blockIdx.x * HD;
+  int64_t total = hoff[H];
+  if (q0 >= total) return;
+  huge_tile<HD>(rec, gptr, hugelist, hoff, H, q0, total, self_out, size_out, hmem, S, srow, sh, stmp,
+                [&](int, int32_t h, int32_t b, uint32_t w) {
+                  int64_t rel = (int64_t)b - (base ? base[h] : 0);
+                  if ((uint64_t)rel < (uint64_t)ncp) atomicAdd(&dense[(int64_t)h * ncp + rel], w);
+                  else *bad = 1;
+                });
+}
+
+// Sort path: every cross record of the huge rows as ((h << 32) | b, w),
+// compacted in tile order by a decoupled look-back (tiles past the records
+// take part with nothing, so the chain's last tile stores the total).
+__global__ void __launch_bounds__(HT_BS)
+    k_huge_entries(const uint64_t* __restrict__ rec, const int64_t* __restrict__ gptr,
+                   const int32_t* __restrict__ hugelist, const int64_t* __restrict__ hoff, int64_t H,
+                   int64_t* self_out, int32_t* size_out, int64_t* hmem, KW* __restrict__ out,
+                   unsigned long long* gcnt, TileScan ts) {
+  __shared__ int32_t srow[Lbs<HT, HT_BS>::SIZE];
+  __shared__ int64_t sh[2];
+  __shared__ int32_t stmp[HT_BS / WAVE];
+  __shared__ unsigned long long sbase;
+  __shared__ HugeSums S;
+  int64_t q0 = (int64_t)blockIdx.x * HT;
+  int64_t total = hoff[H];
+  if (q0 >= total) {
+    block_reserve_lb<HT_BS>(ts, blockIdx.x, blockIdx.x == gridDim.x - 1, 0, nullptr, gcnt, &sbase, stmp);
+    return;
+  }
+  uint32_t cross = 0;
+  int ncross = 0;
+  uint64_t keyv[HT / HT_BS];
+  uint32_t wv[HT / HT_BS];
+#pragma unroll
+  for (int r = 0; r < HT / HT_BS; r++) {
+    keyv[r] = 0;
+    wv[r] = 0;
+  }
+  huge_tile<HT>(rec, gptr, hugelist, hoff, H, q0, total, self_out, size_out, hmem, S, srow, sh, stmp,
+                [&](int r, int32_t h, int32_t b, uint32_t w) {
+                  cross |= 1u << r;
+                  ncross++;
+                  keyv[r] = ((uint64_t)(uint32_t)h << 32) | (uint32_t)b;
+                  wv[r] = w;
+                });
+  int64_t pos = block_reserve_lb<HT_BS>(ts, blockIdx.x, blockIdx.x == gridDim.x - 1, ncross, nullptr,
+                                       gcnt, &sbase, stmp);
+#pragma unroll
+  for (int r = 0; r < HT / HT_BS; r++)
+    if (cross >> r & 1u) out[pos++] = KW{keyv[r], (uint64_t)wv[r]};
 }
 
 // Compaction of the dense rows: tile t of row h covers b in
@@ -821,7 +727,8 @@ __global__ void __launch_bounds__(DC_BS)
     k_dense_compact(const uint32_t* __restrict__ dense, int64_t ncp, int64_t n_c, int64_t tpr,
                     const int32_t* __restrict__ hugelist, const int64_t* __restrict__ gptr,
                     uint64_t* __restrict__ temp, int64_t* cnt, TileScan ts,
-                    const int32_t* __restrict__ base, const unsigned long long* H_dev, int64_t H) {
+                    const int32_t* __restrict__ base, const unsigned long long* H_dev, int64_t H,
+                    const int64_t* __restrict__ hmem, unsigned long long* info) {
   __shared__ int stmp[DC_BS / WAVE];
   __shared__ unsigned long long sbase;
   int64_t h = blockIdx.x / tpr, t = blockIdx.x % tpr;
@@ -831,6 +738,7 @@ __global__ void __launch_bounds__(DC_BS)
     if (Hn > (unsigned long long)H || h >= (int64_t)Hn) return;
   }
   int32_t a = hugelist[h];
+  if (t == 0 && threadIdx.x == 0) atomicMax(&info[I_MAXCL], (unsigned long long)hmem[h]);
   int64_t cb = base ? base[h] : 0;   // column of the window's first slot
   n_c -= cb;                          // slots past the last coarse node stay unused
   int64_t b0 = t * DC_T + (int64_t)threadIdx.x * DC_PER;
@@ -910,9 +818,13 @@ __global__ void k_huge_rowfirst(const KW* __restrict__ s, int64_t G, const int32
 
 __global__ void k_huge_counts(const int32_t* __restrict__ hugelist, int64_t H,
                               const int32_t* __restrict__ rowfirst, const int32_t* __restrict__ rowlast,
-                              int64_t* __restrict__ cnt) {
+                              int64_t* __restrict__ cnt, const int64_t* __restrict__ hmem,
+                              unsigned long long* info) {
   int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (h < H) cnt[hugelist[h]] = rowlast[h] < 0 ? 0 : (int64_t)(rowlast[h] - rowfirst[h] + 1);
+  if (h < H) {
+    cnt[hugelist[h]] = rowlast[h] < 0 ? 0 : (int64_t)(rowlast[h] - rowfirst[h] + 1);
+    atomicMax(&info[I_MAXCL], (unsigned long long)hmem[h]);
+  }
 }
 
 __global__ void k_fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v) {
@@ -947,10 +859,10 @@ __global__ void __launch_bounds__(PACK_BS)
 // Rows of the register, wavefront and block classes.  With dev the class
 // counts stay in device memory (the kernels read them; grids cover a bound),
 // otherwise hinfo holds them.
-// Classes whose bit is clear in `skip` (dev only) are not launched: the
+// Classes whose bit is clear in `launch` (dev only) are not launched: the
 // caller checks their counts once read.
-static int contract_classes(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c, spc_graph_out* out,
-                            LevelWork& W, bool dev, int launch = 7) {
+static int contract_classes(spc_ctx* ctx, int64_t n_c, spc_graph_out* out, LevelWork& W, bool dev,
+                            int launch = 7) {
   hipStream_t st = ctx->stream;
   int64_t* hinfo = ctx->h_pinned;
   unsigned long long* info = W.info;
@@ -963,94 +875,90 @@ static int contract_classes(spc_ctx* ctx, const LevelIn& g, const int32_t* c, in
   if ((dev && (launch & 1)) || nr32 > 0) {
     TimedScope ts(ctx, "contract_reg32", (double)nr32);
     int64_t gr = dev ? std::min((int64_t)grid_for(n_c, SMALL_BS), cap) : (int64_t)grid_for(nr32, SMALL_BS);
-    hipLaunchKernelGGL(k_contract_reg32, dim3((unsigned)gr), dim3(SMALL_BS), 0, st, g, c, W.mptr, W.members,
-                       W.gptr, W.r32list, nr32, dev ? &info[I_R32] : nullptr, W.temp, W.cnt, self_out, out->size);
+    hipLaunchKernelGGL(k_contract_reg32, dim3((unsigned)gr), dim3(SMALL_BS), 0, st, W.temp, W.gptr, W.r32list,
+                       nr32, dev ? &info[I_R32] : nullptr, W.cnt, self_out, out->size, info);
     SPC_LAUNCH_CHECK(ctx, "contract reg32");
   }
   if ((dev && (launch & 2)) || nmid > 0) {
     TimedScope ts(ctx, "contract_wave_rows", (double)nmid);
     int64_t gr = dev ? std::min(n_c, cap * 4) : nmid;
-    hipLaunchKernelGGL((k_contract_row<WAVE, WAVE_CAP>), dim3((unsigned)gr), dim3(WAVE), 0, st, g, c, W.mptr,
-                       W.members, W.gptr, W.midlist, dev ? &info[I_MID] : nullptr, W.temp, W.cnt, self_out,
-                       out->size);
+    hipLaunchKernelGGL((k_contract_row<WAVE, WAVE_CAP>), dim3((unsigned)gr), dim3(WAVE), 0, st, W.temp, W.gptr,
+                       W.midlist, dev ? &info[I_MID] : nullptr, W.cnt, self_out, out->size, info);
     SPC_LAUNCH_CHECK(ctx, "contract wave rows");
   }
   if ((dev && (launch & 4)) || nblk > 0) {
     TimedScope ts(ctx, "contract_block_rows", (double)nblk);
     int64_t gr = dev ? std::min(n_c, cap) : nblk;
-    hipLaunchKernelGGL((k_contract_row<256, BLOCK_CAP>), dim3((unsigned)gr), dim3(256), 0, st, g, c, W.mptr,
-                       W.members, W.gptr, W.blocklist, dev ? &info[I_BLOCK] : nullptr, W.temp, W.cnt, self_out,
-                       out->size);
+    hipLaunchKernelGGL((k_contract_row<256, BLOCK_CAP>), dim3((unsigned)gr), dim3(256), 0, st, W.temp, W.gptr,
+                       W.blocklist, dev ? &info[I_BLOCK] : nullptr, W.cnt, self_out, out->size, info);
     SPC_LAUNCH_CHECK(ctx, "contract block rows");
   }
   return SPC_OK;
 }
 
-// Rows with more than BLOCK_CAP gathered entries ("huge").  H rows, or with
-// dev at most H (the count in device memory; above H the kernels do nothing
-// and set info[I_HOVER]); dev always takes the dense path, which the caller
-// checked fits for H rows.
-static int contract_huge(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c, spc_graph_out* out,
-                         LevelWork& W, const Segments* seg, int64_t H, bool dev) {
+// Rows with more than BLOCK_CAP records ("huge").  H rows, or with dev at
+// most H (the count in device memory; above H the kernels do nothing and
+// set info[I_HOVER]); dev always takes the dense path, which the caller
+// checked fits for H rows.  total_bound: records of all rows together (the
+// launches that cover the huge rows' records, whose total stays on the
+// device, are sized by it).
+static int contract_huge(spc_ctx* ctx, const LevelIn& g, int64_t n_c, spc_graph_out* out, LevelWork& W,
+                         const Segments* seg, int64_t H, bool dev) {
   hipStream_t st = ctx->stream;
-  int64_t n = g.n;
   int64_t* hinfo = ctx->h_pinned;
   unsigned long long* info = W.info;
   int64_t* self_out = (int64_t*)out->self_w;
   const unsigned long long* Hd = dev ? &info[I_HUGE] : nullptr;
+  int64_t total_bound = g.nnz + g.n;
   int rc;
   TimedScope ts(ctx, "contract_huge", (double)H);
-  if (H <= WAVE) {
-    hipLaunchKernelGGL(k_huge_members_prefix, dim3(1), dim3(WAVE), 0, st, W.hugelist, H, W.mptr, W.hmoff, Hd,
-                       &info[I_HOVER]);
-  } else {
-    hipLaunchKernelGGL(k_huge_members_count, dim3(grid_for(H, 256)), dim3(256), 0, st, W.hugelist, H, W.mptr,
-                       W.hmoff, Hd, &info[I_HOVER]);
-    rc = exclusive_scan<int64_t>(ctx, W.hmoff, W.hmoff, H, (int64_t*)W.scan_partial);
-    if (rc) return rc;
-  }
-  // member and entry totals stay on the device: launches cover bounds
-  // (n members, nnz entries) and read the totals there
-  // few huge rows: dense accumulators over the coarse ids (they fit in
-  // the gather buffers when H * ncp <= 2 nnz), zeroed by the members' launch
-  // (in a batch, per huge row only the coarse range of its own graph)
+  int64_t* hoff = W.hmoff;
+  int64_t* hmem = W.hmrs;   // members per huge row
+  // few huge rows: dense accumulators over the coarse ids (they fit in the
+  // gather buffers when H * ncp <= 2 nnz); in a batch, per huge row only the
+  // coarse range of its own graph
   int64_t win = seg ? seg->wmax : n_c;
   int64_t ncp = (win + DC_T - 1) / DC_T * DC_T;
   bool dense_path = dev || (!ctx->force_huge_sort && H * ncp <= 2 * g.nnz);
   uint32_t* dense = (uint32_t*)W.gkeyA;
-  int64_t* hpre = W.hpos;   // prefix of the member row lengths
-  hipLaunchKernelGGL(k_huge_members, dim3(grid_for(n, HMB_T)), dim3(HMB_BS), 0, st, g, W.hugelist, W.mptr,
-                     W.members, W.hmoff, H, n, hpre, W.hmrow, W.hmrs, self_out, out->size, Hd, next_scan(ctx, W),
-                     dense, dense_path ? H * ncp : (int64_t)0);
+  launch_clear(ctx, nullptr, 0, dense_path ? (uint64_t*)dense : nullptr, dense_path ? (H * ncp + 1) / 2 : 0,
+               nullptr, 0, (uint64_t*)hmem, H);
+  if (H <= WAVE) {
+    hipLaunchKernelGGL(k_huge_prefix_wave, dim3(1), dim3(WAVE), 0, st, W.hugelist, H, W.gptr, hoff, Hd,
+                       &info[I_HOVER]);
+  } else {
+    hipLaunchKernelGGL(k_huge_count, dim3(grid_for(H, 256)), dim3(256), 0, st, W.hugelist, H, W.gptr, hoff);
+    rc = exclusive_scan<int64_t>(ctx, hoff, hoff, H, (int64_t*)W.scan_partial);
+    if (rc) return rc;
+  }
   if (dense_path) {
     int32_t* base = nullptr;
     if (seg) {
-      base = W.hmnode;   // free on this path
+      base = W.hmnode;
       hipLaunchKernelGGL(k_huge_base, dim3(grid_for(H, 256)), dim3(256), 0, st, W.hugelist, H, seg->coff,
                          seg->G, base);
     }
     if (g.nnz > HD_SMALL_NNZ)
-      hipLaunchKernelGGL(k_huge_dense<HT>, dim3(grid_for(g.nnz, HT)), dim3(HT_BS), 0, st, g, c, W.hugelist,
-                         W.hmrow, W.hmrs, hpre, n, self_out, dense, ncp, (const int32_t*)base,
+      hipLaunchKernelGGL(k_huge_dense<HT>, dim3(grid_for(total_bound, HT)), dim3(HT_BS), 0, st, W.temp, W.gptr,
+                         W.hugelist, hoff, H, self_out, out->size, hmem, dense, ncp, (const int32_t*)base,
                          &info[I_DENSE]);
-    else if (g.nnz > 0)
-      hipLaunchKernelGGL(k_huge_dense<1024>, dim3(grid_for(g.nnz, 1024)), dim3(HT_BS), 0, st, g, c,
-                         W.hugelist, W.hmrow, W.hmrs, hpre, n, self_out, dense, ncp, (const int32_t*)base,
+    else
+      hipLaunchKernelGGL(k_huge_dense<1024>, dim3(grid_for(total_bound, 1024)), dim3(HT_BS), 0, st, W.temp,
+                         W.gptr, W.hugelist, hoff, H, self_out, out->size, hmem, dense, ncp, (const int32_t*)base,
                          &info[I_DENSE]);
     int64_t tpr = ncp / DC_T;
     hipLaunchKernelGGL(k_dense_compact, dim3((unsigned)(H * tpr)), dim3(DC_BS), 0, st, dense, ncp, n_c,
-                       tpr, W.hugelist, W.gptr, W.temp, W.cnt, next_scan(ctx, W), (const int32_t*)base, Hd, H);
+                       tpr, W.hugelist, W.gptr, W.temp, W.cnt, next_scan(ctx, W), (const int32_t*)base, Hd, H,
+                       hmem, info);
     SPC_LAUNCH_CHECK(ctx, "huge dense");
     return SPC_OK;
   }
   launch_clear(ctx, nullptr, 0, nullptr, 0, info, 1u << I_LIVE1);
   KW* A = (KW*)W.gkeyA;
   KW* B = (KW*)W.gkeyB;
-  if (g.nnz > 0) {
-    hipLaunchKernelGGL(k_huge_entries, dim3(grid_for(g.nnz, HT)), dim3(HT_BS), 0, st, g, c, W.hugelist,
-                       W.hmrow, W.hmrs, hpre, n, self_out, A, &info[I_LIVE1], next_scan(ctx, W));
-    SPC_LAUNCH_CHECK(ctx, "huge gather");
-  }
+  hipLaunchKernelGGL(k_huge_entries, dim3(grid_for(total_bound, HT)), dim3(HT_BS), 0, st, W.temp, W.gptr,
+                     W.hugelist, hoff, H, self_out, out->size, hmem, A, &info[I_LIVE1], next_scan(ctx, W));
+  SPC_LAUNCH_CHECK(ctx, "huge gather");
   rc = readback_wait(ctx, nullptr, 0, (const int64_t*)&info[I_LIVE1]);
   if (rc) return rc;
   int64_t G = hinfo[I_NINFO];
@@ -1080,7 +988,7 @@ static int contract_huge(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64
                        hstart, wx, W.hugelist, rowfirst, W.gptr, W.temp);
   }
   hipLaunchKernelGGL(k_huge_counts, dim3(grid_for(H, 256)), dim3(256), 0, st, W.hugelist, H, rowfirst,
-                     rowlast, W.cnt);
+                     rowlast, W.cnt, hmem, info);
   SPC_LAUNCH_CHECK(ctx, "huge reduce");
   return SPC_OK;
 }
@@ -1117,22 +1025,25 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
   int64_t* hinfo = ctx->h_pinned;
   unsigned long long* info = W.info;
   int64_t* self_out = (int64_t*)out->self_w;
+  int64_t* off = W.hpos;   // each fine node's first slot inside its super-node's records
   int rc;
   {
     TimedScope ts(ctx, "contract_members", (double)n);
-    // (the merge cutoff's launch zeroed the counts already when it ran; the
-    // class slots are still zero from the level's start then)
+    // (the merge cutoff's launch zeroed the record counts already when it
+    // ran; the class slots are still zero from the level's start then)
     if (!R.contract_zeroed)
       launch_clear(ctx, W.mcount, n_c + 1, (uint64_t*)W.gptr, n_c + 1, info,
                    (1u << I_MID) | (1u << I_HUGE) | (1u << I_MAXCL) | (1u << I_BLOCK) | (1u << I_R32) |
                        (1u << I_HOVER));
-    hipLaunchKernelGGL(k_cluster_count, dim3(grid_for(n, CM_BS)), dim3(CM_BS), 0, st, g, c, W.mcount,
-                       (unsigned long long*)W.gptr);
-    SPC_LAUNCH_CHECK(ctx, "cluster_count");
-    rc = exclusive_scan2<int32_t, int64_t>(ctx, W.mcount, W.mptr, W.gptr, W.gptr, n_c);
+    hipLaunchKernelGGL(k_slot_alloc, dim3(grid_for(n, CM_BS)), dim3(CM_BS), 0, st, g, c,
+                       (unsigned long long*)W.gptr, off);
+    SPC_LAUNCH_CHECK(ctx, "slot_alloc");
+    rc = exclusive_scan<int64_t>(ctx, W.gptr, W.gptr, n_c, (int64_t*)W.scan_partial);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_member_scatter, dim3(grid_for(n, CM_BS)), dim3(CM_BS), 0, st, c, W.mptr,
-                       W.mcount, W.members, n);
+    int tiles = g.nnz > 0 ? grid_for(g.nnz, RT) : 0;
+    hipLaunchKernelGGL(k_record_scatter, dim3(tiles + grid_for(n, RM)), dim3(RT_BS), 0, st, g, c, W.gptr, off,
+                       W.temp, tiles);
+    SPC_LAUNCH_CHECK(ctx, "record_scatter");
   }
   {
     TimedScope ts(ctx, "contract_small", (double)g.nnz);
@@ -1140,17 +1051,17 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
     // four class chains then fit the look-back words any level reserves)
     TileScan tsc = next_scan(ctx, W);
     if (n_c <= 1024 * SMALL_BS)
-      hipLaunchKernelGGL(k_contract_small<1>, dim3(grid_for(n_c, SMALL_BS)), dim3(SMALL_BS), 0, st, g, c,
-                         W.mptr, W.members, W.gptr, W.temp, W.cnt, self_out, out->size, n_c, W.r32list,
-                         W.midlist, W.blocklist, W.hugelist, info, tsc);
+      hipLaunchKernelGGL(k_contract_small<1>, dim3(grid_for(n_c, SMALL_BS)), dim3(SMALL_BS), 0, st, W.temp,
+                         W.gptr, W.cnt, self_out, out->size, n_c, W.r32list, W.midlist, W.blocklist, W.hugelist,
+                         info, tsc);
     else if (n_c <= 1024 * SMALL_BS * 2)
-      hipLaunchKernelGGL(k_contract_small<2>, dim3(grid_for(n_c, SMALL_BS * 2)), dim3(SMALL_BS), 0, st, g,
-                         c, W.mptr, W.members, W.gptr, W.temp, W.cnt, self_out, out->size, n_c, W.r32list,
-                         W.midlist, W.blocklist, W.hugelist, info, tsc);
+      hipLaunchKernelGGL(k_contract_small<2>, dim3(grid_for(n_c, SMALL_BS * 2)), dim3(SMALL_BS), 0, st, W.temp,
+                         W.gptr, W.cnt, self_out, out->size, n_c, W.r32list, W.midlist, W.blocklist, W.hugelist,
+                         info, tsc);
     else
-      hipLaunchKernelGGL(k_contract_small<SMALL_RPT>, dim3(grid_for(n_c, SMALL_BS * SMALL_RPT)),
-                         dim3(SMALL_BS), 0, st, g, c, W.mptr, W.members, W.gptr, W.temp, W.cnt, self_out,
-                         out->size, n_c, W.r32list, W.midlist, W.blocklist, W.hugelist, info, tsc);
+      hipLaunchKernelGGL(k_contract_small<SMALL_RPT>, dim3(grid_for(n_c, SMALL_BS * SMALL_RPT)), dim3(SMALL_BS),
+                         0, st, W.temp, W.gptr, W.cnt, self_out, out->size, n_c, W.r32list, W.midlist,
+                         W.blocklist, W.hugelist, info, tsc);
   }
   SPC_LAUNCH_CHECK(ctx, "contract_small");
   // with a deferred selection, the first read also carries its super-node count
@@ -1167,9 +1078,9 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
     // last level did not have are not launched; should this level have
     // rows of them after all, they run once the counts are read.
     int launch = ctx->contract_wait == 3 ? 0 : ctx->contract_classes_seen;
-    rc = contract_classes(ctx, g, c, n_c, out, W, true, launch);
+    rc = contract_classes(ctx, n_c, out, W, true, launch);
     if (rc) return rc;
-    rc = contract_huge(ctx, g, c, n_c, out, W, seg, H_DEV, true);
+    rc = contract_huge(ctx, g, n_c, out, W, seg, H_DEV, true);
     if (rc) return rc;
     rc = rowptr_and_read(ctx, W, out, n_c, x1);
     if (rc) return rc;
@@ -1183,11 +1094,11 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
       // more huge rows than H_DEV (they were left alone), or rows of a class
       // not launched: the host knows the counts now
       if (missed) {
-        rc = contract_classes(ctx, g, c, n_c, out, W, false, missed);
+        rc = contract_classes(ctx, n_c, out, W, false, missed);
         if (rc) return rc;
       }
       if (hinfo[I_HOVER]) {
-        rc = contract_huge(ctx, g, c, n_c, out, W, seg, hinfo[I_HUGE], false);
+        rc = contract_huge(ctx, g, n_c, out, W, seg, hinfo[I_HUGE], false);
         if (rc) return rc;
       }
       rc = rowptr_and_read(ctx, W, out, n_c, nullptr);
@@ -1201,10 +1112,10 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
       if (rc) return rc;
     }
     int64_t H = hinfo[I_HUGE];
-    rc = contract_classes(ctx, g, c, n_c, out, W, false);
+    rc = contract_classes(ctx, n_c, out, W, false);
     if (rc) return rc;
     if (H > 0) {
-      rc = contract_huge(ctx, g, c, n_c, out, W, seg, H, false);
+      rc = contract_huge(ctx, g, n_c, out, W, seg, H, false);
       if (rc) return rc;
     }
     rc = rowptr_and_read(ctx, W, out, n_c, nullptr);

@@ -194,18 +194,18 @@ struct LevelWork {
   int32_t* mcount;           // [n+1]
   int32_t* mptr;             // [n+1]
   int32_t* members;          // [n]
-  int64_t* gptr;             // [n+1]
-  uint64_t* temp;            // [nnz]
+  int64_t* gptr;             // [n+1] super-node record counts, then their prefix
+  uint64_t* temp;            // [nnz + n] records grouped by super-node, reduced in place
   int64_t* cnt;              // [n+1]
   int32_t* r32list;          // [n]
   int32_t* midlist;          // [n]
   int32_t* blocklist;        // [n]
   int32_t* hugelist;         // [n]
-  int64_t* hmoff;            // [n+1]
-  int32_t* hmrow;            // [n]  huge member -> huge row index
-  int32_t* hmnode;           // [n]
-  int64_t* hpos;             // [n+1] huge member -> gathered offset
-  int64_t* hmrs;             // [n]  huge member -> its first CSR position
+  int64_t* hmoff;            // [n+1] record prefix over the huge rows
+  int32_t* hmrow;            // [n]  sort path: each huge row's first head rank
+  int32_t* hmnode;           // [n]  sort path: last head rank; batches: graph base per huge row
+  int64_t* hpos;             // [n+1] fine node -> its first slot in its super-node's records
+  int64_t* hmrs;             // [n]  members per huge row
   int32_t* htab;             // [H_MAX] rows longer than HUGE_T, in registration order
   int32_t* hmap;             // [H_MAX * n] per such row: column -> position in the row
   uint64_t* gkeyA;           // [nnz] (key, w) pairs, 16 bytes each

@@ -63,7 +63,7 @@ void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W, bool fp) {
   W.mptr = A.take<int32_t>(n + 1);
   W.members = A.take<int32_t>(n);
   W.gptr = A.take<int64_t>(n + 1);
-  W.temp = A.take<uint64_t>(nnz);
+  W.temp = A.take<uint64_t>(nnz + n);
   W.cnt = A.take<int64_t>(n + 1);
   W.r32list = A.take<int32_t>(n);
   W.midlist = A.take<int32_t>(n);

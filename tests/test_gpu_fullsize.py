@@ -11,7 +11,10 @@ bench.py times (coarsen_to with halving levels):
 * the 4,096-mesh batch: every level of the packed union and every graph
   over all its levels against the oracle's digests;
 * 64^3 grid with float32 lognormal weights: every level bit-exact against
-  the oracle run here and against its digests.
+  the oracle run here and against its digests;
+* the irregular-degree workload (a power-law graph of 131,072 nodes, hub
+  rows of thousands of entries): every level bit-exact against the oracle
+  run here.
 
 Every case prints its name and shape before the GPU call."""
 import hashlib
@@ -23,7 +26,7 @@ import numpy as np
 import pytest
 
 import oracle
-from meshgen import batch_sides, batch_trimeshes, grid3d, trimesh
+from meshgen import batch_sides, batch_trimeshes, grid3d, powerlaw_graph, trimesh
 
 sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
 import digest as D  # noqa: E402
@@ -205,4 +208,21 @@ def test_differentiation_workload_grid3d_64_lognormal_every_level(P):
                                           err_msg=f"level {lvl} {name}")
         assert st.eps_max == eps == float.fromhex(wd["eps_max"])
         compare_level_digest(c, gh, wd, True, f"level {lvl}")
+    h.free()
+
+
+def test_irregular_workload_powerlaw_every_level(P):
+    g = powerlaw_graph(1 << 17, avg_deg=8.0, gamma=2.5, seed=7)
+    n_c = g.n // 100
+    say("powerlaw-131k full hierarchy", f"n={g.n} m={g.m} n_c={n_c} max row {int(np.diff(g.row_ptr).max())}")
+    h = P.coarsen_to(P.DeviceGraph.from_host(g, "cuda:0"), n_c, 0)
+    want = oracle.coarsen_to(g, n_c, 0)
+    assert h.num_levels == len(want)
+    for lvl, (c_or, g_or, eps) in enumerate(want, start=1):
+        cl, gc, st = h.level(lvl)
+        np.testing.assert_array_equal(host(cl), c_or, err_msg=f"level {lvl} cluster_of")
+        for name in ("row_ptr", "col", "w", "self_w", "size"):
+            np.testing.assert_array_equal(host(getattr(gc, name)), getattr(g_or, name),
+                                          err_msg=f"level {lvl} {name}")
+        assert st.eps_max == eps
     h.free()
