@@ -205,7 +205,11 @@ int spc_coarsen_level_noalloc(spc_ctx* ctx, const spc_graph* g, int64_t n_target
 /* Coarsen to n_c super-nodes level by level, re-scoring each level (the
  * multilevel refinement the conclusion proposes).  schedule 0: halve the
  * node count per level, t = max(n_c, ceil(n_l / 2)); schedule 1: a single
- * level straight to n_c (Algorithm 1 as printed).  The hierarchy owns every
+ * level straight to n_c (Algorithm 1 as printed); schedule -j (j >= 1): j
+ * merges per level, t = max(n_c, n_l - j), i.e. the scores are recomputed
+ * after every j merges -- the re-scoring cadence of the conclusion, with
+ * j = 1 the explicit greedy algorithm of the introduction, which recomputes
+ * every norm after each merge.  Other values: SPC_EINVAL.  The hierarchy owns every
  * level's graph and cluster map; free it with spc_hier_free.  The call
  * returns once the last level's work is queued on the context's stream
  * (each level waits inside the call for its coarse size): read the arrays

@@ -230,15 +230,21 @@ def coarsen_level(g: Graph, t: int):
 
 def level_targets(n: int, n_c: int, schedule: int = 0):
     """Targets of successive levels.  schedule 0: halve the node count per
-    level, t = max(n_c, ceil(n_l / 2)); schedule 1: one pass straight to n_c."""
+    level, t = max(n_c, ceil(n_l / 2)); schedule 1: one pass straight to n_c
+    (Algorithm 1 as printed); schedule -j: j merges per level, t = max(n_c,
+    n_l - j), so the fitness is recomputed after every j merges (the
+    re-scoring the conclusion proposes; j = 1 is the explicit greedy
+    algorithm described before Theorem 2)."""
     ts = []
     cur = n
     if n_c >= n:
         return [n]
     if schedule == 1:
         return [n_c]
+    if schedule > 1:
+        raise ValueError(f"unknown schedule {schedule}")
     while cur > n_c:
-        cur = max(n_c, (cur + 1) // 2)
+        cur = max(n_c, cur + schedule) if schedule < 0 else max(n_c, (cur + 1) // 2)
         ts.append(cur)
     return ts
 

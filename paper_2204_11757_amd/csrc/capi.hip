@@ -346,6 +346,17 @@ static void* resolve_scratch(int device) {
 // hierarchy
 // ===========================================================================
 
+// Target of the next level from n_l nodes (n_l > n_c).  schedule 0: halve,
+// max(n_c, ceil(n_l / 2)); 1: straight to n_c (Algorithm 1 as printed, one
+// scoring); -j (j >= 1): j merges per level, max(n_c, n_l - j), i.e. the
+// scores are recomputed after every j merges (j = 1 is the explicit greedy
+// algorithm, which recomputes every norm after each merge).
+static int64_t level_target(int64_t n, int64_t n_c, int schedule) {
+  if (schedule == 1) return n_c;
+  if (schedule < 0) return std::max(n_c, n + (int64_t)schedule);
+  return std::max(n_c, (n + 1) / 2);
+}
+
 static void free_level(spc_ctx* ctx, spc_hier::Level& L) {
   dev_free(ctx, L.block);
   for (hipEvent_t& e : L.ev)
@@ -601,7 +612,7 @@ int spc_coarsen_to(spc_ctx* ctx, const spc_graph* g, int64_t n_c, int schedule, 
   int rc = check_graph(ctx, g);
   if (rc) return rc;
   if (n_c < 1) return set_error(ctx, SPC_EINVAL, "n_c must be >= 1");
-  if (schedule != 0 && schedule != 1) return set_error(ctx, SPC_EINVAL, "unknown schedule %d", schedule);
+  if (schedule > 1) return set_error(ctx, SPC_EINVAL, "unknown schedule %d", schedule);
   spc_hier* h = new (std::nothrow) spc_hier();
   if (!h) return SPC_ENOMEM;
   h->ctx = ctx;
@@ -611,7 +622,7 @@ int spc_coarsen_to(spc_ctx* ctx, const spc_graph* g, int64_t n_c, int schedule, 
   bool fp = g->wtype != SPC_W_I32;
   size_t wsz = fp ? sizeof(double) : sizeof(int32_t);
   while (n > n_c) {
-    int64_t t = (schedule == 1) ? n_c : std::max(n_c, (n + 1) / 2);
+    int64_t t = level_target(n, n_c, schedule);
     spc_hier::Level L;
     L.n_prev = n;
     L.wtype = fp ? SPC_W_F64 : SPC_W_I32;
@@ -654,7 +665,7 @@ int spc_coarsen_batched(spc_ctx* ctx, int32_t G, const spc_graph* g, const int64
   if (rc) return rc;
   if (g->wtype != SPC_W_I32) return set_error(ctx, SPC_EINVAL, "batched coarsening takes int32 weights");
   if (G < 1 || !graph_off || !n_c) return set_error(ctx, SPC_EINVAL, "bad batch description");
-  if (schedule != 0 && schedule != 1) return set_error(ctx, SPC_EINVAL, "unknown schedule %d", schedule);
+  if (schedule > 1) return set_error(ctx, SPC_EINVAL, "unknown schedule %d", schedule);
   if (graph_off[0] != 0 || graph_off[G] != g->n)
     return set_error(ctx, SPC_EINVAL, "graph offsets must run from 0 to n");
   std::vector<int64_t> ng(G), nc(G), off(graph_off, graph_off + G + 1);
@@ -691,7 +702,7 @@ int spc_coarsen_batched(spc_ctx* ctx, int32_t G, const spc_graph* g, const int64
     int64_t T = 0;
     bool more = false;
     for (int32_t i = 0; i < G; i++) {
-      tg[i] = ng[i] <= nc[i] ? ng[i] : (schedule == 1 ? nc[i] : std::max(nc[i], (ng[i] + 1) / 2));
+      tg[i] = ng[i] <= nc[i] ? ng[i] : level_target(ng[i], nc[i], schedule);
       kk[i] = ng[i] - tg[i];
       more |= kk[i] > 0;
       noff[i] = T;

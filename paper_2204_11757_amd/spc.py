@@ -393,8 +393,9 @@ class Hierarchy:
 
 
 def coarsen_to(g: DeviceGraph, n_c: int, schedule: int = 0) -> Hierarchy:
-    """Multilevel coarsening to n_c super-nodes (schedule 0 halves per level,
-    schedule 1 is a single level)."""
+    """Multilevel coarsening to n_c super-nodes.  schedule 0 halves the node
+    count per level, 1 is a single level, -j takes j merges per level (the
+    scores recomputed after every j merges; -1 is the explicit greedy)."""
     ctx = context(_dev(g.row_ptr))
     h = C.c_void_p()
     gc = g._c()

@@ -95,6 +95,17 @@ def test_first_config_halving_and_single_pass(P):
     check_hierarchy(P, g, 1024, 1, "grid2d-64 single pass")
 
 
+@pytest.mark.parametrize("j", [1, 7, 64, 1000])
+def test_rescoring_cadence(P, j):
+    # j merges per level (the scores recomputed after every j merges); j = 1
+    # is the explicit greedy algorithm, j large enough is the single pass
+    g = trimesh(24, ("uniform", 1, 8), seed=40 + j)
+    check_hierarchy(P, g, g.n // 4, -j, f"trimesh-24 cadence {j}")
+    if j == 1:
+        f = grid2d(12, ("uniform", 1, 6), seed=9)   # self-loops from the second level on
+        check_hierarchy(P, f, f.n // 3, -1, "grid2d-12 cadence 1")
+
+
 @pytest.mark.parametrize("s,seed", [(96, 3), (131, 5)])
 def test_trimesh_multilevel(P, s, seed):
     g = trimesh(s, ("uniform", 1, 8), seed=seed)

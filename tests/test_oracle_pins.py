@@ -144,6 +144,55 @@ def prim_prefix(g: Graph, t: int):
     return canonical(components(g.n, [(u, v) for _, u, v in tree[: g.n - t]]))
 
 
+def explicit_greedy_bruteforce(g: Graph, t: int):
+    """The explicit greedy algorithm, straight from its description: merge
+    the adjacent pair of current super-nodes with the smallest literal
+    score (ties by the smaller, then the larger current id, ids numbered by
+    smallest member), rebuild the coarse graph (B^T W B, self-loops kept),
+    recompute every score, repeat until t super-nodes.  Returns the input
+    nodes' final labels, canonical."""
+    n = g.n
+    W = [[Fraction(0)] * n for _ in range(n)]
+    for u, row in enumerate(dense_rows(g)):
+        for x, a in row.items():
+            W[u][x] = Fraction(a)
+    members = [[u] for u in range(n)]
+    while len(members) > t:
+        k = len(members)
+        d = [sum(W[a]) for a in range(k)]
+        best = None
+        for a in range(k):
+            for b in range(a + 1, k):
+                if W[a][b] == 0:
+                    continue
+                sc = sum(abs(W[a][x] / d[a] - W[b][x] / d[b]) for x in range(k))
+                if best is None or (sc, a, b) < best:
+                    best = (sc, a, b)
+        assert best is not None
+        _, a, b = best
+        merged = members[a] + members[b]
+        groups = [m for i, m in enumerate(members) if i not in (a, b)] + [merged]
+        groups.sort(key=min)
+        lab = {}
+        for i, m in enumerate(groups):
+            for u in m:
+                lab[u] = i
+        old_of = {}
+        for i, m in enumerate(members):
+            old_of[i] = lab[m[0]]
+        Wn = [[Fraction(0)] * len(groups) for _ in range(len(groups))]
+        for i in range(k):
+            for j in range(k):
+                if W[i][j]:
+                    Wn[old_of[i]][old_of[j]] += W[i][j]
+        W, members = Wn, groups
+    out = np.zeros(n, dtype=np.int64)
+    for i, m in enumerate(members):
+        for u in m:
+            out[u] = i
+    return out
+
+
 def small_graphs():
     out = []
     for seed in range(6):
@@ -276,6 +325,35 @@ def test_merge_loop_matches_bruteforce_greedy_and_prim(g):
         assert np.array_equal(c.astype(np.int64), want), t
         assert np.array_equal(c.astype(np.int64), prim_prefix(g, t)), t
         assert gc.n == t
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_rescoring_every_merge_is_the_explicit_greedy(seed):
+    """Schedule -1 (one merge per level, scores recomputed each time) equals
+    the explicit greedy algorithm written from its description."""
+    g = random_graph(8 + seed % 3, p=0.4, seed=200 + seed, wmax=4, self_loops=seed % 2 == 1,
+                     sizes=seed % 3 == 0)
+    for t in (g.n - 1, g.n // 2, 2):
+        lv = oracle.coarsen_to(g, t, -1)
+        assert len(lv) == g.n - t
+        got = oracle.compose(lv)
+        np.testing.assert_array_equal(got, explicit_greedy_bruteforce(g, t))
+
+
+def test_rescoring_cadence_extremes():
+    """j = n - n_c merges per level is the single pass; every cadence reaches
+    n_c with levels of exactly j merges (the last one fewer)."""
+    g = trimesh(9, ("uniform", 1, 5), seed=3)
+    n_c = g.n // 4
+    single = oracle.coarsen_to(g, n_c, 1)
+    whole = oracle.coarsen_to(g, n_c, -(g.n - n_c))
+    assert len(single) == len(whole) == 1
+    np.testing.assert_array_equal(single[0][0], whole[0][0])
+    for j in (1, 5, 17):
+        lv = oracle.coarsen_to(g, n_c, -j)
+        sizes = [gc.n for _, gc, _ in lv]
+        steps = [a - b for a, b in zip([g.n] + sizes[:-1], sizes)]
+        assert sizes[-1] == n_c and all(x == j for x in steps[:-1]) and 0 < steps[-1] <= j
 
 
 def test_merge_loop_accepts_only_cross_edges_in_order():
