@@ -202,6 +202,20 @@ int spc_coarsen_level(spc_ctx* ctx, const spc_graph* g, int64_t n_target, int32_
 int spc_coarsen_level_noalloc(spc_ctx* ctx, const spc_graph* g, int64_t n_target, int32_t* cluster_of,
                               spc_graph_out* coarse, int64_t* nnz_c, spc_level_stats* st);
 
+/* The graph under a node relabeling: node u becomes perm[u] (perm: device
+ * int32[n], a permutation of [0, n)), so out's row perm[u] holds row u's
+ * entries with their columns relabeled, ascending; self-loops and sizes
+ * move with their nodes.  This is Definition 1's contraction with one
+ * member per super-node.  Every score is unchanged (the measure of
+ * Theorem 1 does not depend on node names), so coarsening the relabeled
+ * graph changes only the tie-break of Algorithm 1's sort: equal scores
+ * fall by (perm[u], perm[v]) instead of (u, v), and with a seeded random
+ * perm the ties are broken by a seeded hash instead of the lowest ids.
+ * out: capacities n and nnz; *nnz_out = nnz.  Weight types as the input's
+ * (FP weights come out as FP64).  SPC_EINVAL if perm is not a permutation.
+ * Waits for the permutation check. */
+int spc_relabel(spc_ctx* ctx, const spc_graph* g, const int32_t* perm, spc_graph_out* out, int64_t* nnz_out);
+
 /* Coarsen to n_c super-nodes level by level, re-scoring each level (the
  * multilevel refinement the conclusion proposes).  schedule 0: halve the
  * node count per level, t = max(n_c, ceil(n_l / 2)); schedule 1: a single

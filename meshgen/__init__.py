@@ -16,4 +16,5 @@ from .meshes import (  # noqa: F401
     random_graph,
     from_edges,
     powerlaw_graph,
+    tie_permutation,
 )

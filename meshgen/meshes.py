@@ -291,3 +291,11 @@ def powerlaw_graph(n: int, avg_deg: float = 8.0, gamma: float = 2.5, seed: int =
     g = from_edges(n, u, v, w)
     g.meta = {"kind": "powerlaw", "n": n, "avg_deg": avg_deg, "gamma": gamma, "seed": seed}
     return g
+
+
+def tie_permutation(n: int, seed: int) -> np.ndarray:
+    """A seeded random permutation of [0, n) (int32), for relabeling a graph
+    so that equal merge scores fall in a seeded pseudo-random order instead
+    of by the lowest node ids."""
+    r = np.random.Generator(np.random.PCG64([0x7e, seed]))
+    return r.permutation(n).astype(np.int32)

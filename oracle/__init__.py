@@ -204,6 +204,15 @@ def contract(g: Graph, cluster_of, n_c: int) -> Graph:
                  size=size_c)
 
 
+def relabel(g: Graph, perm) -> Graph:
+    """The graph with node u renamed perm[u]: Definition 1's contraction with
+    one member per super-node (perm must be a permutation of [0, n))."""
+    perm = np.asarray(perm, dtype=np.int64)
+    if perm.shape[0] != g.n or not np.array_equal(np.sort(perm), np.arange(g.n)):
+        raise OracleError(EINVAL, "relabel")
+    return contract(g, perm, g.n)
+
+
 def coarsen_level(g: Graph, t: int):
     """One level of Algorithm 1 to t super-nodes.
     Returns (cluster_of, coarse Graph, eps_max)."""

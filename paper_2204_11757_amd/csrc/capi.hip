@@ -167,6 +167,15 @@ __global__ void k_identity_fp(const void* __restrict__ w, int w32, int64_t nnz, 
   }
 }
 
+// seen[perm[i]] counts the preimages of every target; a target out of
+// range or hit twice sets *bad
+__global__ void k_perm_mark(const int32_t* __restrict__ perm, int64_t n, int32_t* seen, unsigned long long* bad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t p = perm[i];
+  if (p < 0 || p >= n || atomicAdd(&seen[p], 1) != 0) *bad = 1;
+}
+
 static LevelIn level_in(const spc_graph* g) {
   LevelIn L;
   L.n = g->n;
@@ -602,6 +611,36 @@ int spc_coarsen_level_noalloc(spc_ctx* ctx, const spc_graph* g, int64_t n_target
   ctx->scan_epoch = scan_epoch;
   ctx->spec_ok = 0;
   return rc;
+}
+
+int spc_relabel(spc_ctx* ctx, const spc_graph* g, const int32_t* perm, spc_graph_out* out, int64_t* nnz_out) {
+  if (!ctx) return SPC_EINVAL;
+  int rc = check_graph(ctx, g);
+  if (rc) return rc;
+  if (!perm || !out || !nnz_out) return set_error(ctx, SPC_EINVAL, "relabel arguments are NULL");
+  if (!out->row_ptr || !out->self_w || !out->size || (g->nnz > 0 && (!out->col || !out->w)))
+    return set_error(ctx, SPC_EINVAL, "output arrays are NULL");
+  if (out->n_cap < g->n || out->nnz_cap < g->nnz)
+    return set_error(ctx, SPC_ECAPACITY, "relabel output needs n_cap >= n and nnz_cap >= nnz");
+  bool fp = g->wtype != SPC_W_I32;
+  LevelWork W;
+  rc = plan_and_bind(ctx, g->n, g->nnz, W, fp);
+  if (rc) return rc;
+  // perm must be a permutation of [0, n): every target hit exactly once
+  launch_clear(ctx, W.mcount, g->n + 1, nullptr, 0, W.info, 0xffffffffu);
+  hipLaunchKernelGGL(k_perm_mark, dim3(grid_for(g->n, 256)), dim3(256), 0, ctx->stream, perm, g->n, W.mcount,
+                     &W.info[I_VIOL]);
+  SPC_LAUNCH_CHECK(ctx, "permutation check");
+  rc = readback_wait(ctx, W.info, (int)I_NINFO);
+  if (rc) return rc;
+  if (ctx->h_pinned[I_VIOL]) return set_error(ctx, SPC_EINVAL, "perm is not a permutation of [0, n)");
+  // the contraction of Definition 1 with singleton super-nodes c(u) = perm[u]
+  LevelResult R;
+  if (fp) rc = contract_level_fp(ctx, level_in_f(g), perm, g->n, out, W, R);
+  else rc = contract_level(ctx, level_in(g), perm, g->n, out, W, R, nullptr);
+  if (rc) return rc;
+  *nnz_out = R.nnz_c;
+  return SPC_OK;
 }
 
 int spc_coarsen_to(spc_ctx* ctx, const spc_graph* g, int64_t n_c, int schedule, spc_hier** out) {

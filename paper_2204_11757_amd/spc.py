@@ -34,7 +34,7 @@ EXPORTS = [
     "spc_spectral_error", "spc_validate_graph", "spc_timing_report", "spc_hier_cluster_map",
     "spc_spectral_error_graph", "spc_spectral_error_backward", "spc_entry_map",
     "spc_contract_backward", "spc_coarsen_batched", "spc_hier_graph_offsets",
-    "spc_coarsen_level_noalloc",
+    "spc_coarsen_level_noalloc", "spc_relabel",
 ]
 
 
@@ -91,6 +91,7 @@ def lib():
                                   C.POINTER(C.c_int64), C.POINTER(LevelStats)],
             "spc_coarsen_level_noalloc": [p, C.POINTER(_Graph), i64, p, C.POINTER(_GraphOut),
                                           C.POINTER(C.c_int64), C.POINTER(LevelStats)],
+            "spc_relabel": [p, C.POINTER(_Graph), p, C.POINTER(_GraphOut), C.POINTER(C.c_int64)],
             "spc_coarsen_to": [p, C.POINTER(_Graph), i64, i32, C.POINTER(C.c_void_p)],
             "spc_hier_num_levels": [p],
             "spc_hier_level": [p, i32, C.POINTER(_Graph), C.POINTER(C.c_void_p),
@@ -318,6 +319,27 @@ def coarsen_level(g: DeviceGraph, n_target: int):
     coarse = DeviceGraph(n=n_c, row_ptr=out.row_ptr[: n_c + 1], col=out.col[:k], w=out.w[:k],
                          self_w=out.self_w[:n_c], size=out.size[:n_c])
     return cl, coarse, st
+
+
+def relabel(g: DeviceGraph, perm) -> DeviceGraph:
+    """The graph with node u renamed perm[u] (a permutation of [0, n)).
+    Scores do not depend on node names, so coarsening the result changes
+    only how ties fall: by (perm[u], perm[v]) instead of (u, v) -- with a
+    seeded random perm, a hash tie-break."""
+    ctx = context(_dev(g.row_ptr))
+    dev = g.row_ptr.device
+    pt = torch.as_tensor(np.ascontiguousarray(perm, dtype=np.int32)).to(dev) if not torch.is_tensor(perm) \
+        else perm.to(device=dev, dtype=torch.int32).contiguous()
+    if pt.numel() != g.n:
+        raise ValueError("perm must have n entries")
+    out = _empty_out(g.n, g.nnz, dev, fp=g.wtype != SPC_W_I32)
+    nnz = C.c_int64()
+    gc = g._c()
+    oc = _out_c(out, g.n, max(g.nnz, 1))
+    ctx.check(lib().spc_relabel(ctx.h, C.byref(gc), pt.data_ptr(), C.byref(oc), C.byref(nnz)))
+    k = nnz.value
+    return DeviceGraph(n=g.n, row_ptr=out.row_ptr, col=out.col[:k], w=out.w[:k], self_w=out.self_w,
+                       size=out.size)
 
 
 SPC_NOALLOC_SCRATCH_BYTES = 134217728

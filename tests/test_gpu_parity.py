@@ -390,3 +390,38 @@ def test_calls_on_two_streams(P):
     torch.cuda.synchronize()
     ha.free()
     hb.free()
+
+
+@pytest.mark.parametrize("fp", [False, True])
+def test_relabel_and_hash_tie_break(P, fp):
+    # the graph relabeled by a seeded permutation (equal scores then fall in
+    # a seeded order), and its hierarchy, against the oracle
+    from meshgen import tie_permutation
+    g = grid3d(10, "lognormal", seed=5) if fp else trimesh(40, ("uniform", 1, 4), seed=[9, 1])
+    perm = tie_permutation(g.n, 3)
+    say("relabel", f"n={g.n} m={g.m} fp={fp}")
+    dg = P.DeviceGraph.from_host(g)
+    r = P.relabel(dg, perm)
+    want = oracle.relabel(g, perm)
+    assert_same_graph(r, want, "relabel")
+    check_hierarchy(P, want, g.n // 8, 0, "hash tie-break hierarchy")
+    with pytest.raises(P.SpcError) as e:
+        bad = perm.copy()
+        bad[0] = bad[1]
+        P.relabel(dg, bad)
+    assert e.value.code == P.SPC_EINVAL
+
+
+def test_hash_tie_break_on_a_bipartite_grid(P):
+    # every score ties: the lowest-id rule grows one giant super-node, the
+    # seeded order does not; both bit-exact against the oracle
+    from meshgen import tie_permutation
+    g = grid3d(16, ("uniform", 1, 16), seed=2)
+    say("hash tie-break grid3d-16", f"n={g.n}")
+    t = g.n // 2
+    st0 = check_level(P, g, t, "lowest id")
+    perm = tie_permutation(g.n, 7)
+    r = P.relabel(P.DeviceGraph.from_host(g), perm)
+    st1 = check_level(P, r.to_host(), t, "seeded order")
+    assert st0.largest_cluster == g.n - t + 1
+    assert st1.largest_cluster < st0.largest_cluster // 2

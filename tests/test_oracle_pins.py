@@ -23,7 +23,7 @@ import pytest
 
 import oracle
 from oracle import spectral as S
-from meshgen import Graph, from_edges, grid2d, grid3d, random_graph, trimesh
+from meshgen import Graph, from_edges, grid2d, grid3d, random_graph, tie_permutation, trimesh
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -354,6 +354,72 @@ def test_rescoring_cadence_extremes():
         sizes = [gc.n for _, gc, _ in lv]
         steps = [a - b for a, b in zip([g.n] + sizes[:-1], sizes)]
         assert sizes[-1] == n_c and all(x == j for x in steps[:-1]) and 0 < steps[-1] <= j
+
+
+# ----------------------------------------------------------------------------
+# the seeded-hash tie-break variant (relabeling by a seeded permutation)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(4))
+def test_relabel_is_the_permuted_adjacency(seed):
+    g = random_graph(11, p=0.4, seed=300 + seed, wmax=5, self_loops=True, sizes=True,
+                     float_weights=seed % 2 == 1)
+    perm = tie_permutation(g.n, seed)
+    r = oracle.relabel(g, perm)
+    W, Wr = S.dense_w(g), S.dense_w(r)
+    P = np.zeros((g.n, g.n))
+    P[perm, np.arange(g.n)] = 1.0           # P e_u = e_perm[u]
+    np.testing.assert_array_equal(Wr, P @ W @ P.T)
+    np.testing.assert_array_equal(r.size[perm], g.size)
+    inv = np.argsort(perm)
+    back = oracle.relabel(r, inv)
+    for name in ("row_ptr", "col", "w", "self_w", "size"):
+        np.testing.assert_array_equal(getattr(back, name), getattr(oracle.contract(g, np.arange(g.n), g.n), name))
+
+
+def test_relabel_rejects_non_permutations():
+    g = random_graph(6, p=0.5, seed=1)
+    with pytest.raises(oracle.OracleError):
+        oracle.relabel(g, [0, 1, 2, 3, 4, 4])
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_hash_tie_break_is_greedy_under_the_permuted_order(seed):
+    """Coarsening the relabeled graph is Algorithm 1 on the original graph
+    with ties between equal scores broken by (perm[u], perm[v]): scores are
+    unchanged, only the order of equal ones moves."""
+    g = random_graph(9, p=0.45, seed=400 + seed, wmax=2)      # small weights: many ties
+    perm = tie_permutation(g.n, seed)
+    rows = dense_rows(g)
+    E = edges_of(g)
+    key = {e: (literal_score(rows, *e), min(perm[e[0]], perm[e[1]]), max(perm[e[0]], perm[e[1]])) for e in E}
+    r = oracle.relabel(g, perm)
+    eu, ev, N, D = oracle.scores(r)
+    got = sorted(Fraction(int(a), int(b)) for a, b in zip(N, D))
+    assert got == sorted(k[0] for k in key.values())
+    for t in (g.n - 1, g.n // 2, 2):
+        lab = list(range(g.n))
+        s_ = g.n
+        while s_ > t:
+            best = min((e for e in E if lab[e[0]] != lab[e[1]]), key=lambda e: key[e])
+            a, b = lab[best[0]], lab[best[1]]
+            lab = [a if l == b else l for l in lab]
+            s_ -= 1
+        c, _, _ = oracle.coarsen_level(r, t)
+        np.testing.assert_array_equal(canonical(c[perm]), canonical(lab))
+
+
+def test_hash_tie_break_avoids_the_giant_cluster():
+    """On a bipartite grid every score ties: the lowest-id rule grows one
+    super-node {0..k}, a seeded order does not."""
+    g = grid2d(24)
+    t = g.n // 2
+    k = g.n - t
+    c0, _, _ = oracle.coarsen_level(g, t)
+    assert np.bincount(c0).max() == k + 1
+    perm = tie_permutation(g.n, 1)
+    c1, _, _ = oracle.coarsen_level(oracle.relabel(g, perm), t)
+    assert np.bincount(c1).max() < (k + 1) // 4
 
 
 def test_merge_loop_accepts_only_cross_edges_in_order():
