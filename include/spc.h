@@ -282,14 +282,16 @@ int spc_lift(spc_ctx* ctx, const spc_hier* h, int from_lvl, int to_lvl, int mode
 
 /* Spectral error of level lvl's lift against k eigenpairs of the input
  * graph's normalised Laplacian (Theorem 1's Lambda; the lift of
- * Definition 2).  U: device double[n0 * k] column-major, unit-norm
+ * Definition 2).  prec (SPC_W_F64 or SPC_W_F32) is the type of U, R and
+ * every intermediate: U device prec[n0 * k] column-major, unit-norm
  * eigenvectors; lambda: device double[k].  For each i, with Q the
  * orthonormal lift, t = D_c^{-1/2} Q^T u_i, R_i = 1 - t^T W_c t (the lift's
  * Rayleigh quotient at u_i; W_c includes the self-loops).  Writes R
- * (device double[k], nullable) and the host scalar
- * loss = sum_i (R_i - lambda_i)^2.  Synchronises. */
-int spc_spectral_error(spc_ctx* ctx, const spc_hier* h, int lvl, const double* U,
-                       const double* lambda, int k, double* R, double* loss);
+ * (device prec[k], nullable) and the host scalar
+ * loss = sum_i (R_i - lambda_i)^2 (summed in double).  Synchronises.
+ * SPC_EINVAL for another prec. */
+int spc_spectral_error(spc_ctx* ctx, const spc_hier* h, int lvl, const void* U,
+                       const double* lambda, int k, int prec, void* R, double* loss);
 
 /* Composed cluster map of level lvl: cmap[x] (device int32[n0]) is the
  * level-lvl super-node holding input node x (lvl = 0: the identity). */
@@ -299,23 +301,24 @@ int spc_hier_cluster_map(spc_ctx* ctx, const spc_hier* h, int lvl, int32_t* cmap
  * one whose FP64 weights are being refined after coarsening.  coarse:
  * device graph with SPC_W_I32 or SPC_W_F64 weights, its size[] the number
  * of input nodes per super-node; cmap: device int32[n0], input node ->
- * super-node of coarse.  Writes R (nullable) and the host loss.
- * Synchronises. */
+ * super-node of coarse.  prec, U and R as for spc_spectral_error.  Writes R
+ * (nullable) and the host loss.  Synchronises. */
 int spc_spectral_error_graph(spc_ctx* ctx, const spc_graph* coarse, const int32_t* cmap, int64_t n0,
-                             const double* U, const double* lambda, int k, double* R, double* loss);
+                             const void* U, const double* lambda, int k, int prec, void* R, double* loss);
 
-/* Gradient of that loss with respect to the coarse weights.  The weight of
- * an undirected coarse edge {a, b} is one parameter held at both CSR
- * entries (a, b) and (b, a); d_wc[j] (device double[nnz]) receives
+/* Gradient of that loss with respect to the coarse weights, computed in
+ * prec (SPC_W_F64 or SPC_W_F32, also the type of U, d_wc and d_selfc).
+ * The weight of an undirected coarse edge {a, b} is one parameter held at
+ * both CSR entries (a, b) and (b, a); d_wc[j] (device prec[nnz]) receives
  * d loss / d w_ab at both of them, so a step that updates both entries
- * alike keeps the graph symmetric.  d_selfc (device double[n_c]) receives
+ * alike keeps the graph symmetric.  d_selfc (device prec[n_c]) receives
  * d loss / d self_w[a].  With z = W_c t:
  *   d(t^T W_c t)/d w_ab   = 2 t_a t_b - t_a z_a / d_a - t_b z_b / d_b,
  *   d(t^T W_c t)/d self_a = t_a^2 - t_a z_a / d_a,
  * and d loss / d(t_i^T W_c t_i) = -2 (R_i - lambda_i).  Stream-ordered. */
 int spc_spectral_error_backward(spc_ctx* ctx, const spc_graph* coarse, const int32_t* cmap, int64_t n0,
-                                const double* U, const double* lambda, int k, double* d_wc,
-                                double* d_selfc);
+                                const void* U, const double* lambda, int k, int prec, void* d_wc,
+                                void* d_selfc);
 
 /* Entry map of a contraction (Definition 1): for every fine CSR entry j of
  * `fine` (device int32[nnz]), the position of its coarse entry

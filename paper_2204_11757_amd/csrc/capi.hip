@@ -631,9 +631,16 @@ int spc_relabel(spc_ctx* ctx, const spc_graph* g, const int32_t* perm, spc_graph
   hipLaunchKernelGGL(k_perm_mark, dim3(grid_for(g->n, 256)), dim3(256), 0, ctx->stream, perm, g->n, W.mcount,
                      &W.info[I_VIOL]);
   SPC_LAUNCH_CHECK(ctx, "permutation check");
+  // FP weights: their exponent range fixes the fixed-point unit of the
+  // exact sums (and is checked like a level's input)
+  if (fp) launch_fp_degree(ctx, level_in_f(g), W);
   rc = readback_wait(ctx, W.info, (int)I_NINFO);
   if (rc) return rc;
   if (ctx->h_pinned[I_VIOL]) return set_error(ctx, SPC_EINVAL, "perm is not a permutation of [0, n)");
+  if (fp && (ctx->h_pinned[I_FP_BAD] & 1))
+    return set_error(ctx, SPC_EINVAL, "floating-point weights must be finite and positive");
+  if (fp && (ctx->h_pinned[I_FP_BAD] & 2))
+    return set_error(ctx, SPC_ERANGE, "floating-point weights span more than %d binades", FP_MAX_SPAN);
   // the contraction of Definition 1 with singleton super-nodes c(u) = perm[u]
   LevelResult R;
   if (fp) rc = contract_level_fp(ctx, level_in_f(g), perm, g->n, out, W, R);

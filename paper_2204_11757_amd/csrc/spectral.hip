@@ -81,62 +81,66 @@ __device__ __forceinline__ double cv_self(const CoarseView& g, int64_t a) {
 // Sums over a super-node's members and over a coarse row run in a fixed
 // order, so results are reproducible: one thread walks a short list in
 // order; a list longer than LONG_LIST is summed by one block with a fixed
-// shape (strided partial sums, then a tree), in a separate launch.
+// shape (strided partial sums, then a tree), in a separate launch.  Every
+// quantity is computed in the type T (double, or float for the FP32 form).
 constexpr int LONG_LIST = 2048;
 constexpr int SP_BS = 256;
 
-__device__ __forceinline__ double block_sum_fixed(double v, double* tmp) {
+template <typename T>
+__device__ __forceinline__ T block_sum_fixed(T v, T* tmp) {
   tmp[threadIdx.x] = v;
   __syncthreads();
   for (int o = SP_BS / 2; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) tmp[threadIdx.x] += tmp[threadIdx.x + o];
     __syncthreads();
   }
-  double r = tmp[0];
+  T r = tmp[0];
   __syncthreads();
   return r;
 }
 
 // y = Q^T u_i (members summed in ascending fine id), d = W_c row sums with
 // the diagonal, t = D_c^{-1/2} y; short lists here, long ones in k_restrict_long
+template <typename T>
 __global__ void k_restrict_scale(const uint64_t* __restrict__ sorted, const int32_t* __restrict__ mptr,
-                                 const double* __restrict__ U, int64_t n0, int k, CoarseView g,
-                                 double* __restrict__ t, double* __restrict__ dc) {
+                                 const T* __restrict__ U, int64_t n0, int k, CoarseView g,
+                                 T* __restrict__ t, T* __restrict__ dc) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= g.nc * k) return;
   int64_t a = idx % g.nc;
   int i = (int)(idx / g.nc);
   if (mptr[a + 1] - mptr[a] > LONG_LIST || g.rp[a + 1] - g.rp[a] > LONG_LIST) return;
-  double y = 0.0;
+  T y = 0;
   for (int32_t p = mptr[a]; p < mptr[a + 1]; p++) {
     int64_t u = (int64_t)(sorted[p] & 0xffffffffull);
     y += U[u + n0 * i];
   }
-  y = y / sqrt((double)(g.size ? g.size[a] : 1));
-  double d = cv_self(g, a);
-  for (int64_t j = g.rp[a]; j < g.rp[a + 1]; j++) d += cv_w(g, j);
+  y = y / sqrt((T)(g.size ? g.size[a] : 1));
+  T d = (T)cv_self(g, a);
+  for (int64_t j = g.rp[a]; j < g.rp[a + 1]; j++) d += (T)cv_w(g, j);
   t[a + g.nc * i] = y / sqrt(d);
   if (i == 0) dc[a] = d;
 }
 
 // one block per super-node with a long member list or a long row
+template <typename T>
 __global__ void __launch_bounds__(SP_BS)
     k_restrict_long(const uint64_t* __restrict__ sorted, const int32_t* __restrict__ mptr,
-                    const double* __restrict__ U, int64_t n0, int k, CoarseView g, double* __restrict__ t,
-                    double* __restrict__ dc) {
-  __shared__ double tmp[SP_BS];
+                    const T* __restrict__ U, int64_t n0, int k, CoarseView g, T* __restrict__ t,
+                    T* __restrict__ dc) {
+  __shared__ T tmp[SP_BS];
   int64_t a = blockIdx.x;
   int32_t m0 = mptr[a], m1 = mptr[a + 1];
   int64_t r0 = g.rp[a], r1 = g.rp[a + 1];
   if (m1 - m0 <= LONG_LIST && r1 - r0 <= LONG_LIST) return;
-  double part = 0.0;
-  for (int64_t j = r0 + threadIdx.x; j < r1; j += SP_BS) part += cv_w(g, j);
-  double d = cv_self(g, a) + block_sum_fixed(part, tmp);
+  T part = 0;
+  for (int64_t j = r0 + threadIdx.x; j < r1; j += SP_BS) part += (T)cv_w(g, j);
+  T d = (T)cv_self(g, a) + block_sum_fixed(part, tmp);
   for (int i = 0; i < k; i++) {
-    part = 0.0;
+    part = 0;
     for (int32_t p = m0 + threadIdx.x; p < m1; p += SP_BS)
       part += U[(int64_t)(sorted[p] & 0xffffffffull) + n0 * i];
-    double y = block_sum_fixed(part, tmp) / sqrt((double)(g.size ? g.size[a] : 1));
+    T y = block_sum_fixed(part, tmp) / sqrt((T)(g.size ? g.size[a] : 1));
     if (threadIdx.x == 0) t[a + g.nc * i] = y / sqrt(d);
   }
   if (threadIdx.x == 0) dc[a] = d;
@@ -144,42 +148,42 @@ __global__ void __launch_bounds__(SP_BS)
 
 // z = W_c t (W_c with its diagonal, summed in ascending column), prod = t z;
 // short rows here, long ones in k_quad_long
-__global__ void k_quad(CoarseView g, int k, const double* __restrict__ t, double* __restrict__ z,
-                       double* __restrict__ prod) {
+template <typename T>
+__global__ void k_quad(CoarseView g, int k, const T* __restrict__ t, T* __restrict__ z, T* __restrict__ prod) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= g.nc * k) return;
   int64_t a = idx % g.nc;
   int i = (int)(idx / g.nc);
   if (g.rp[a + 1] - g.rp[a] > LONG_LIST) return;
-  const double* ti = t + g.nc * i;
-  double s = cv_self(g, a);
-  double acc = 0.0;
-  bool placed = (s == 0.0);
+  const T* ti = t + g.nc * i;
+  T s = (T)cv_self(g, a);
+  T acc = 0;
+  bool placed = (s == (T)0);
   for (int64_t j = g.rp[a]; j < g.rp[a + 1]; j++) {
     int32_t b = g.col[j];
     if (!placed && b > a) {
       acc += s * ti[a];
       placed = true;
     }
-    acc += cv_w(g, j) * ti[b];
+    acc += (T)cv_w(g, j) * ti[b];
   }
   if (!placed) acc += s * ti[a];
   z[idx] = acc;
   prod[idx] = ti[a] * acc;
 }
 
+template <typename T>
 __global__ void __launch_bounds__(SP_BS)
-    k_quad_long(CoarseView g, int k, const double* __restrict__ t, double* __restrict__ z,
-                double* __restrict__ prod) {
-  __shared__ double tmp[SP_BS];
+    k_quad_long(CoarseView g, int k, const T* __restrict__ t, T* __restrict__ z, T* __restrict__ prod) {
+  __shared__ T tmp[SP_BS];
   int64_t a = blockIdx.x;
   int64_t r0 = g.rp[a], r1 = g.rp[a + 1];
   if (r1 - r0 <= LONG_LIST) return;
   for (int i = 0; i < k; i++) {
-    const double* ti = t + g.nc * i;
-    double part = 0.0;
-    for (int64_t j = r0 + threadIdx.x; j < r1; j += SP_BS) part += cv_w(g, j) * ti[g.col[j]];
-    double acc = block_sum_fixed(part, tmp) + cv_self(g, a) * ti[a];
+    const T* ti = t + g.nc * i;
+    T part = 0;
+    for (int64_t j = r0 + threadIdx.x; j < r1; j += SP_BS) part += (T)cv_w(g, j) * ti[g.col[j]];
+    T acc = block_sum_fixed(part, tmp) + (T)cv_self(g, a) * ti[a];
     if (threadIdx.x == 0) {
       z[a + g.nc * i] = acc;
       prod[a + g.nc * i] = ti[a] * acc;
@@ -188,11 +192,11 @@ __global__ void __launch_bounds__(SP_BS)
 }
 
 // f_i = sum_a prod[a, i]: one block per i, fixed reduction shape
-__global__ void __launch_bounds__(256) k_colsum(const double* __restrict__ prod, int64_t nc,
-                                                double* __restrict__ R) {
-  __shared__ double tmp[256];
+template <typename T>
+__global__ void __launch_bounds__(256) k_colsum(const T* __restrict__ prod, int64_t nc, T* __restrict__ R) {
+  __shared__ T tmp[256];
   int i = blockIdx.x;
-  double s = 0.0;
+  T s = 0;
   for (int64_t a = threadIdx.x; a < nc; a += 256) s += prod[a + nc * i];
   tmp[threadIdx.x] = s;
   __syncthreads();
@@ -200,7 +204,7 @@ __global__ void __launch_bounds__(256) k_colsum(const double* __restrict__ prod,
     if ((int)threadIdx.x < o) tmp[threadIdx.x] += tmp[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) R[i] = 1.0 - tmp[0];
+  if (threadIdx.x == 0) R[i] = (T)1 - tmp[0];
 }
 
 // Gradient of loss = sum_i (R_i - lambda_i)^2, R_i = 1 - t_i^T W_c t_i,
@@ -208,9 +212,10 @@ __global__ void __launch_bounds__(256) k_colsum(const double* __restrict__ prod,
 // (written at both of its CSR entries) and to the self-loop weights:
 //   d(t^T W t)/d w_ab   = 2 t_a t_b - t_a z_a / d_a - t_b z_b / d_b
 //   d(t^T W t)/d self_a = t_a^2 - t_a z_a / d_a          (z = W t)
-__global__ void k_spectral_grad(CoarseView g, int k, const double* __restrict__ t, const double* __restrict__ z,
-                                const double* __restrict__ dc, const double* __restrict__ coef,
-                                double* __restrict__ d_w, double* __restrict__ d_self) {
+template <typename T>
+__global__ void k_spectral_grad(CoarseView g, int k, const T* __restrict__ t, const T* __restrict__ z,
+                                const T* __restrict__ dc, const T* __restrict__ coef, T* __restrict__ d_w,
+                                T* __restrict__ d_self) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < g.nnz) {
     // the row of entry idx: binary search in rp
@@ -221,30 +226,30 @@ __global__ void k_spectral_grad(CoarseView g, int k, const double* __restrict__ 
       else hi = mid - 1;
     }
     int64_t a = lo, b = g.col[idx];
-    double s = 0.0;
+    T s = 0;
     for (int i = 0; i < k; i++) {
-      const double* ti = t + g.nc * i;
-      const double* zi = z + g.nc * i;
-      double f = 2.0 * ti[a] * ti[b] - ti[a] * zi[a] / dc[a] - ti[b] * zi[b] / dc[b];
+      const T* ti = t + g.nc * i;
+      const T* zi = z + g.nc * i;
+      T f = (T)2 * ti[a] * ti[b] - ti[a] * zi[a] / dc[a] - ti[b] * zi[b] / dc[b];
       s += coef[i] * f;
     }
     d_w[idx] = s;
   } else if (idx < g.nnz + g.nc) {
     int64_t a = idx - g.nnz;
-    double s = 0.0;
+    T s = 0;
     for (int i = 0; i < k; i++) {
-      const double* ti = t + g.nc * i;
-      const double* zi = z + g.nc * i;
+      const T* ti = t + g.nc * i;
+      const T* zi = z + g.nc * i;
       s += coef[i] * (ti[a] * ti[a] - ti[a] * zi[a] / dc[a]);
     }
     d_self[a] = s;
   }
 }
 
-__global__ void k_loss_coef(const double* __restrict__ R, const double* __restrict__ lam, int k,
-                            double* __restrict__ coef) {
+template <typename T>
+__global__ void k_loss_coef(const T* __restrict__ R, const double* __restrict__ lam, int k, T* __restrict__ coef) {
   int i = threadIdx.x;
-  if (i < k) coef[i] = -2.0 * (R[i] - lam[i]);   // d loss / d f_i, f_i = t_i^T W t_i
+  if (i < k) coef[i] = (T)-2 * (R[i] - (T)lam[i]);   // d loss / d f_i, f_i = t_i^T W t_i
 }
 
 int compose_map(spc_ctx* ctx, const spc_hier* h, int from_lvl, int to_lvl, int32_t* out, int64_t n_from) {
@@ -262,9 +267,10 @@ int compose_map(spc_ctx* ctx, const spc_hier* h, int from_lvl, int to_lvl, int32
 // Forward (and, when d_w is non-NULL, backward) of the spectral error of a
 // coarse graph whose super-nodes are given by cmap (fine id -> coarse id,
 // n0 entries; cmap may live in the workspace when own_cmap is false).
-int spectral_impl(spc_ctx* ctx, const CoarseView& g, const int32_t* cmap_in, const spc_hier* h, int lvl,
-                  int64_t n0, const double* U, const double* lambda, int k, double* R, double* loss,
-                  double* d_w, double* d_self) {
+template <typename T>
+static int spectral_t(spc_ctx* ctx, const CoarseView& g, const int32_t* cmap_in, const spc_hier* h, int lvl,
+                      int64_t n0, const T* U, const double* lambda, int k, T* R, double* loss, T* d_w,
+                      T* d_self) {
   int64_t nc = g.nc;
   Arena A;
   A.counting = true;
@@ -281,12 +287,12 @@ int spectral_impl(spc_ctx* ctx, const CoarseView& g, const int32_t* cmap_in, con
     uint64_t* ka = A.take<uint64_t>(n0);
     uint64_t* kb = A.take<uint64_t>(n0);
     int32_t* mptr = A.take<int32_t>(nc + 1);
-    double* t = A.take<double>(nc * k);
-    double* z = A.take<double>(nc * k);
-    double* prod = A.take<double>(nc * k);
-    double* dc = A.take<double>(nc);
-    double* Rd = A.take<double>(k);
-    double* coef = A.take<double>(k);
+    T* t = A.take<T>(nc * k);
+    T* z = A.take<T>(nc * k);
+    T* prod = A.take<T>(nc * k);
+    T* dc = A.take<T>(nc);
+    T* Rd = A.take<T>(k);
+    T* coef = A.take<T>(k);
     if (pass == 0) {
       A.cap = A.off;
       continue;
@@ -308,31 +314,45 @@ int spectral_impl(spc_ctx* ctx, const CoarseView& g, const int32_t* cmap_in, con
     rc = exclusive_scan<int32_t>(ctx, mptr, mptr, nc, nullptr);
     if (rc) return rc;
     int64_t nk = nc * k;
-    double* Rout = R ? R : Rd;
-    hipLaunchKernelGGL(k_restrict_scale, dim3(grid_for(nk, 256)), dim3(256), 0, st, sorted, mptr, U, n0, k,
+    T* Rout = R ? R : Rd;
+    hipLaunchKernelGGL(k_restrict_scale<T>, dim3(grid_for(nk, 256)), dim3(256), 0, st, sorted, mptr, U, n0, k,
                        g, t, dc);
-    hipLaunchKernelGGL(k_restrict_long, dim3((unsigned)nc), dim3(SP_BS), 0, st, sorted, mptr, U, n0, k, g, t,
-                       dc);
-    hipLaunchKernelGGL(k_quad, dim3(grid_for(nk, 256)), dim3(256), 0, st, g, k, t, z, prod);
-    hipLaunchKernelGGL(k_quad_long, dim3((unsigned)nc), dim3(SP_BS), 0, st, g, k, t, z, prod);
-    hipLaunchKernelGGL(k_colsum, dim3(k), dim3(256), 0, st, prod, nc, Rout);
+    hipLaunchKernelGGL(k_restrict_long<T>, dim3((unsigned)nc), dim3(SP_BS), 0, st, sorted, mptr, U, n0, k, g,
+                       t, dc);
+    hipLaunchKernelGGL(k_quad<T>, dim3(grid_for(nk, 256)), dim3(256), 0, st, g, k, t, z, prod);
+    hipLaunchKernelGGL(k_quad_long<T>, dim3((unsigned)nc), dim3(SP_BS), 0, st, g, k, t, z, prod);
+    hipLaunchKernelGGL(k_colsum<T>, dim3(k), dim3(256), 0, st, prod, nc, Rout);
     if (d_w) {
-      hipLaunchKernelGGL(k_loss_coef, dim3(1), dim3(256), 0, st, Rout, lambda, k, coef);
-      hipLaunchKernelGGL(k_spectral_grad, dim3(grid_for(g.nnz + nc, 256)), dim3(256), 0, st, g, k, t, z, dc,
-                         coef, d_w, d_self);
+      hipLaunchKernelGGL(k_loss_coef<T>, dim3(1), dim3(256), 0, st, Rout, lambda, k, coef);
+      hipLaunchKernelGGL(k_spectral_grad<T>, dim3(grid_for(g.nnz + nc, 256)), dim3(256), 0, st, g, k, t, z,
+                         dc, coef, d_w, d_self);
     }
     SPC_LAUNCH_CHECK(ctx, "spectral_error");
     if (loss) {
-      std::vector<double> hR(k), hl(k);
-      SPC_HIP(ctx, hipMemcpyAsync(hR.data(), Rout, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+      std::vector<T> hR(k);
+      std::vector<double> hl(k);
+      SPC_HIP(ctx, hipMemcpyAsync(hR.data(), Rout, sizeof(T) * k, hipMemcpyDeviceToHost, st));
       SPC_HIP(ctx, hipMemcpyAsync(hl.data(), lambda, sizeof(double) * k, hipMemcpyDeviceToHost, st));
       SPC_HIP(ctx, hipStreamSynchronize(st));
       double s = 0.0;
-      for (int i = 0; i < k; i++) s += (hR[i] - hl[i]) * (hR[i] - hl[i]);
+      for (int i = 0; i < k; i++) s += ((double)hR[i] - hl[i]) * ((double)hR[i] - hl[i]);
       *loss = s;
     }
   }
   return SPC_OK;
+}
+
+// The spectral error (and, with d_w, its gradient) in FP64 or FP32.
+int spectral_impl(spc_ctx* ctx, const CoarseView& g, const int32_t* cmap_in, const spc_hier* h, int lvl,
+                  int64_t n0, const void* U, const double* lambda, int k, int prec, void* R, double* loss,
+                  void* d_w, void* d_self) {
+  if (prec == SPC_W_F64)
+    return spectral_t<double>(ctx, g, cmap_in, h, lvl, n0, (const double*)U, lambda, k, (double*)R, loss,
+                              (double*)d_w, (double*)d_self);
+  if (prec == SPC_W_F32)
+    return spectral_t<float>(ctx, g, cmap_in, h, lvl, n0, (const float*)U, lambda, k, (float*)R, loss,
+                             (float*)d_w, (float*)d_self);
+  return set_error(ctx, SPC_EINVAL, "spectral precision must be SPC_W_F32 or SPC_W_F64");
 }
 
 CoarseView view_of_level(const spc_hier::Level& L) {
@@ -433,14 +453,14 @@ int spc_lift(spc_ctx* ctx, const spc_hier* h, int from_lvl, int to_lvl, int mode
   return SPC_OK;
 }
 
-int spc_spectral_error(spc_ctx* ctx, const spc_hier* h, int lvl, const double* U,
-                       const double* lambda, int k, double* R, double* loss) {
+int spc_spectral_error(spc_ctx* ctx, const spc_hier* h, int lvl, const void* U,
+                       const double* lambda, int k, int prec, void* R, double* loss) {
   if (!ctx) return SPC_EINVAL;
   if (!h || lvl < 0 || lvl > (int)h->levels.size() || k < 1 || !U || !lambda || !loss)
     return set_error(ctx, SPC_EINVAL, "bad spectral_error arguments");
   if (lvl == 0) return set_error(ctx, SPC_EINVAL, "level 0 is the input graph; pass lvl >= 1");
-  return spectral_impl(ctx, view_of_level(h->levels[lvl - 1]), nullptr, h, lvl, h->n0, U, lambda, k, R, loss,
-                       nullptr, nullptr);
+  return spectral_impl(ctx, view_of_level(h->levels[lvl - 1]), nullptr, h, lvl, h->n0, U, lambda, k, prec, R,
+                       loss, nullptr, nullptr);
 }
 
 int spc_hier_cluster_map(spc_ctx* ctx, const spc_hier* h, int lvl, int32_t* cmap) {
@@ -451,25 +471,26 @@ int spc_hier_cluster_map(spc_ctx* ctx, const spc_hier* h, int lvl, int32_t* cmap
 }
 
 int spc_spectral_error_graph(spc_ctx* ctx, const spc_graph* coarse, const int32_t* cmap, int64_t n0,
-                             const double* U, const double* lambda, int k, double* R, double* loss) {
+                             const void* U, const double* lambda, int k, int prec, void* R, double* loss) {
   if (!ctx) return SPC_EINVAL;
   if (!cmap || n0 < 1 || k < 1 || !U || !lambda || !loss)
     return set_error(ctx, SPC_EINVAL, "bad spectral_error arguments");
   CoarseView g;
   int rc = view_of_graph(ctx, coarse, g);
   if (rc) return rc;
-  return spectral_impl(ctx, g, cmap, nullptr, 0, n0, U, lambda, k, R, loss, nullptr, nullptr);
+  return spectral_impl(ctx, g, cmap, nullptr, 0, n0, U, lambda, k, prec, R, loss, nullptr, nullptr);
 }
 
 int spc_spectral_error_backward(spc_ctx* ctx, const spc_graph* coarse, const int32_t* cmap, int64_t n0,
-                                const double* U, const double* lambda, int k, double* d_wc, double* d_selfc) {
+                                const void* U, const double* lambda, int k, int prec, void* d_wc,
+                                void* d_selfc) {
   if (!ctx) return SPC_EINVAL;
   if (!cmap || n0 < 1 || k < 1 || !U || !lambda || !d_wc || !d_selfc)
     return set_error(ctx, SPC_EINVAL, "bad spectral_error_backward arguments");
   CoarseView g;
   int rc = view_of_graph(ctx, coarse, g);
   if (rc) return rc;
-  return spectral_impl(ctx, g, cmap, nullptr, 0, n0, U, lambda, k, nullptr, nullptr, d_wc, d_selfc);
+  return spectral_impl(ctx, g, cmap, nullptr, 0, n0, U, lambda, k, prec, nullptr, nullptr, d_wc, d_selfc);
 }
 
 int spc_entry_map(spc_ctx* ctx, const spc_graph* fine, const int32_t* cluster_of, const spc_graph* coarse,

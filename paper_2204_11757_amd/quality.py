@@ -118,13 +118,20 @@ def compose_levels(levels, n0):
     return c
 
 
-def evaluate_levels(lam, U, levels, n0, k=50):
+def evaluate_levels(lam, U, levels, n0, k=50, perm=None):
+    """Quality of a hierarchy's last level.  perm: the relabeling the
+    hierarchy was computed on (input node u was node perm[u]), if any."""
     gc = levels[-1][1]
-    return evaluate(lam, U, gc, compose_levels(levels, n0), k, [(m, e) for _, _, e, m in levels])
+    cmap = compose_levels(levels, n0)
+    if perm is not None:
+        cmap = cmap[np.asarray(perm, dtype=np.int64)]
+    return evaluate(lam, U, gc, cmap, k, [(m, e) for _, _, e, m in levels])
 
 
 SCHEDULES = [("halving", 0), ("single pass", 1), ("every merge (explicit greedy)", -1),
              ("every 16 merges", -16), ("every 256 merges", -256)]
+# the seeded-hash tie-break (the graph relabeled by a seeded permutation)
+HASHED = [("halving, hash tie-break", 0), ("single pass, hash tie-break", 1)]
 
 
 def main(argv=None):
@@ -135,7 +142,7 @@ def main(argv=None):
     ap.add_argument("--side", type=int, default=64)
     args = ap.parse_args(argv)
     import torch
-    from meshgen import grid2d, trimesh
+    from meshgen import grid2d, tie_permutation, trimesh
     from paper_2204_11757_amd import spc
 
     s = args.side
@@ -148,14 +155,17 @@ def main(argv=None):
         t0 = time.time()
         lam, U = input_spectrum(g)
         dg = spc.DeviceGraph.from_host(g, "cuda:0")
+        perm = tie_permutation(g.n, 1)
+        dr = spc.relabel(dg, perm)
         entry = {"mesh": name, "n": g.n, "m": g.m, "runs": []}
         for ratio in (2, 4, 8):
             n_c = g.n // ratio
-            for sname, sched in SCHEDULES:
-                h = spc.coarsen_to(dg, n_c, sched)
+            for sname, sched in SCHEDULES + HASHED:
+                hashed = (sname, sched) in HASHED
+                h = spc.coarsen_to(dr if hashed else dg, n_c, sched)
                 levels = hierarchy_levels(h, g.n)
                 h.free()
-                q, _, _ = evaluate_levels(lam, U, levels, g.n, args.k)
+                q, _, _ = evaluate_levels(lam, U, levels, g.n, args.k, perm if hashed else None)
                 q.update({"ratio": f"1/{ratio}", "schedule": sname})
                 entry["runs"].append(q)
                 print(f"[quality] {name} 1/{ratio} {sname}: eig err k max {q['eig_err_k_max']:.4f} "

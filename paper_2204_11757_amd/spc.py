@@ -98,13 +98,13 @@ def lib():
                                C.POINTER(LevelStats)],
             "spc_hier_export_level": [p, p, i32, C.POINTER(_GraphOut), p],
             "spc_lift": [p, p, i32, i32, i32, p, i32, p],
-            "spc_spectral_error": [p, p, i32, p, p, i32, p, C.POINTER(C.c_double)],
+            "spc_spectral_error": [p, p, i32, p, p, i32, i32, p, C.POINTER(C.c_double)],
             "spc_validate_graph": [C.POINTER(_Graph)],
             "spc_timing_report": [p, C.c_char_p, C.c_size_t],
             "spc_hier_cluster_map": [p, p, i32, p],
-            "spc_spectral_error_graph": [p, C.POINTER(_Graph), p, i64, p, p, i32, p,
+            "spc_spectral_error_graph": [p, C.POINTER(_Graph), p, i64, p, p, i32, i32, p,
                                          C.POINTER(C.c_double)],
-            "spc_spectral_error_backward": [p, C.POINTER(_Graph), p, i64, p, p, i32, p, p],
+            "spc_spectral_error_backward": [p, C.POINTER(_Graph), p, i64, p, p, i32, i32, p, p],
             "spc_entry_map": [p, C.POINTER(_Graph), p, C.POINTER(_Graph), p],
             "spc_contract_backward": [p, p, p, i64, i64, p, p, p, p],
             "spc_coarsen_batched": [p, i32, C.POINTER(_Graph), p, p, i32, C.POINTER(C.c_void_p)],
@@ -493,15 +493,23 @@ def lift(h: Hierarchy, from_lvl: int, to_lvl: int, mode: int, x_c: torch.Tensor)
     return out[:, 0] if x_c.dim() == 1 else out
 
 
+def _prec(U: torch.Tensor):
+    """The spectral computation's type follows U's: float32 runs the FP32
+    form, anything else FP64."""
+    return (SPC_W_F32, torch.float32) if U.dtype == torch.float32 else (SPC_W_F64, torch.float64)
+
+
 def spectral_error(h: Hierarchy, lvl: int, U: torch.Tensor, lam: torch.Tensor):
-    """(loss, R): R_i = 1 - t_i^T W_c t_i, loss = sum (R_i - lambda_i)^2."""
+    """(loss, R): R_i = 1 - t_i^T W_c t_i, loss = sum (R_i - lambda_i)^2.
+    Computed in U's precision (float32 or float64)."""
     ctx = context(h.ctx.device)
-    Uc = U.to(torch.float64).t().contiguous()
+    prec, dt = _prec(U)
+    Uc = U.to(dt).t().contiguous()
     k = Uc.shape[0]
     lamd = lam.to(torch.float64).contiguous()
-    R = torch.empty(k, dtype=torch.float64, device=U.device)
+    R = torch.empty(k, dtype=dt, device=U.device)
     loss = C.c_double()
-    ctx.check(lib().spc_spectral_error(ctx.h, h.h, lvl, Uc.data_ptr(), lamd.data_ptr(), k,
+    ctx.check(lib().spc_spectral_error(ctx.h, h.h, lvl, Uc.data_ptr(), lamd.data_ptr(), k, prec,
                                        R.data_ptr(), C.byref(loss)))
     return loss.value, R
 
@@ -515,37 +523,40 @@ def cluster_map(h: Hierarchy, lvl: int) -> torch.Tensor:
 
 
 def _colmajor(U: torch.Tensor) -> torch.Tensor:
-    return U.to(torch.float64).t().contiguous()
+    return U.to(_prec(U)[1]).t().contiguous()
 
 
 def spectral_error_graph(coarse: DeviceGraph, cmap: torch.Tensor, U: torch.Tensor, lam: torch.Tensor):
     """(loss, R) of an explicit coarse graph (int32 or float64 weights) whose
-    super-nodes are cmap (input node -> super-node)."""
+    super-nodes are cmap (input node -> super-node), in U's precision."""
     ctx = context(_dev(coarse.row_ptr))
+    prec, dt = _prec(U)
     Uc = _colmajor(U)
     k = Uc.shape[0]
     lamd = lam.to(torch.float64).contiguous()
-    R = torch.empty(k, dtype=torch.float64, device=U.device)
+    R = torch.empty(k, dtype=dt, device=U.device)
     loss = C.c_double()
     gc = coarse._c()
     ctx.check(lib().spc_spectral_error_graph(ctx.h, C.byref(gc), cmap.data_ptr(), int(cmap.numel()),
-                                             Uc.data_ptr(), lamd.data_ptr(), k, R.data_ptr(),
+                                             Uc.data_ptr(), lamd.data_ptr(), k, prec, R.data_ptr(),
                                              C.byref(loss)))
     return loss.value, R
 
 
 def spectral_error_backward(coarse: DeviceGraph, cmap: torch.Tensor, U: torch.Tensor, lam: torch.Tensor):
-    """(d loss / d w_c at every CSR entry, d loss / d self_c)."""
+    """(d loss / d w_c at every CSR entry, d loss / d self_c), computed in
+    U's precision (float32 gives the FP32 gradients)."""
     ctx = context(_dev(coarse.row_ptr))
+    prec, dt = _prec(U)
     Uc = _colmajor(U)
     k = Uc.shape[0]
     lamd = lam.to(torch.float64).contiguous()
     dev = coarse.row_ptr.device
-    dw = torch.empty(max(coarse.nnz, 1), dtype=torch.float64, device=dev)
-    ds = torch.empty(coarse.n, dtype=torch.float64, device=dev)
+    dw = torch.empty(max(coarse.nnz, 1), dtype=dt, device=dev)
+    ds = torch.empty(coarse.n, dtype=dt, device=dev)
     gc = coarse._c()
     ctx.check(lib().spc_spectral_error_backward(ctx.h, C.byref(gc), cmap.data_ptr(), int(cmap.numel()),
-                                                Uc.data_ptr(), lamd.data_ptr(), k, dw.data_ptr(),
+                                                Uc.data_ptr(), lamd.data_ptr(), k, prec, dw.data_ptr(),
                                                 ds.data_ptr()))
     return dw[: coarse.nnz], ds
 
@@ -599,8 +610,9 @@ class SpectralError(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx_, grad):
+        w_c, self_c = ctx_.saved_tensors
         dw, ds = spectral_error_backward(ctx_.g, ctx_.cmap, ctx_.U, ctx_.lam)
-        return grad * (0.5 * dw), grad * ds, None, None, None, None
+        return (grad * (0.5 * dw)).to(w_c.dtype), (grad * ds).to(self_c.dtype), None, None, None, None
 
 
 def spectral_error_loss(w_c, self_c, structure: DeviceGraph, cmap, U, lam):

@@ -155,6 +155,31 @@ def test_spectral_error_forward_and_backward(P):
     np.testing.assert_allclose(host(ds), gs_or, rtol=1e-10, atol=1e-12 * scale)
 
 
+def test_fp32_spectral_error_and_gradients(P):
+    # the FP32 form against the FP64 oracle: loss and R to 1e-5 relative,
+    # gradients to 1e-5 relative in the max norm
+    say("spectral error FP32 grid3d-16")
+    g, h, gc, gc_or, cmap, cmap_or, Ut, lt, U, lam = _spectral_case(P, s=16, k=12)
+    U32 = Ut.float()
+    loss, R = P.spectral_error_graph(gc, cmap, U32, lt)
+    loss_or, R_or = osp.spectral_error(gc_or, cmap_or, U, lam)
+    assert R.dtype.is_floating_point and R.element_size() == 4
+    assert loss == pytest.approx(loss_or, rel=1e-5)
+    np.testing.assert_allclose(host(R), R_or, rtol=1e-5, atol=1e-6)
+    dw, ds = P.spectral_error_backward(gc, cmap, U32, lt)
+    assert dw.element_size() == 4 and ds.element_size() == 4
+    gw_or, gs_or = osp.spectral_error_grad(gc_or, cmap_or, U, lam)
+    scale = max(np.abs(gw_or).max(), np.abs(gs_or).max())
+    assert np.abs(host(dw).astype(np.float64) - gw_or).max() <= 1e-5 * scale
+    assert np.abs(host(ds).astype(np.float64) - gs_or).max() <= 1e-5 * scale
+    # through autograd: FP64 parameters, FP32 spectral kernels
+    w = gc.w.clone().requires_grad_(True)
+    sw = gc.self_w.clone().requires_grad_(True)
+    P.spectral_error_loss(w, sw, gc, cmap, U32, lt).backward()
+    assert w.grad.dtype == w.dtype
+    np.testing.assert_allclose(host(w.grad), 0.5 * host(dw).astype(np.float64), rtol=1e-6, atol=0)
+
+
 def test_spectral_gradient_central_differences(P):
     import torch
     say("spectral gradient FD grid3d-8")

@@ -211,6 +211,39 @@ def test_differentiation_workload_grid3d_64_lognormal_every_level(P):
     h.free()
 
 
+def test_differentiation_workload_spectral_gradients(P):
+    # the 64^3 lognormal mesh coarsened to 32,768 super-nodes: the spectral
+    # error against its 16 leading nontrivial eigenpairs, FP64 loss to 1e-10
+    # and gradients against the oracle, FP32 gradients to 1e-5 (max norm)
+    import torch
+    from oracle import spectral as osp
+    from paper_2204_11757_amd.reweight import _leading_eigenpairs
+    g = grid3d(64, "lognormal", seed=5)
+    say("grid3d-64 lognormal spectral gradients", f"n={g.n} k=16")
+    lam, U = _leading_eigenpairs(g, 16)
+    h = P.coarsen_to(P.DeviceGraph.from_host(g, "cuda:0"), 32768, 0)
+    L = h.num_levels
+    _, gc, _ = h.level(L)
+    cmap = P.cluster_map(h, L)
+    want = oracle.coarsen_to(g, 32768, 0)
+    gc_or, cmap_or = want[-1][1], oracle.compose(want)
+    np.testing.assert_array_equal(host(cmap), cmap_or)
+    Ut = torch.from_numpy(np.ascontiguousarray(U)).cuda()
+    lt = torch.from_numpy(lam).cuda()
+    loss, R = P.spectral_error_graph(gc, cmap, Ut, lt)
+    loss_or, R_or = osp.spectral_error(gc_or, cmap_or, U, lam)
+    assert loss == pytest.approx(loss_or, rel=1e-10)
+    gw_or, gs_or = osp.spectral_error_grad(gc_or, cmap_or, U, lam)
+    scale = max(np.abs(gw_or).max(), np.abs(gs_or).max())
+    for dt, tol in ((torch.float64, 1e-10), (torch.float32, 1e-5)):
+        dw, ds = P.spectral_error_backward(gc, cmap, Ut.to(dt), lt)
+        err = max(np.abs(host(dw).astype(np.float64) - gw_or).max(),
+                  np.abs(host(ds).astype(np.float64) - gs_or).max()) / scale
+        say("gradient", dt, "relative error", err)
+        assert err <= tol
+    h.free()
+
+
 def test_irregular_workload_powerlaw_every_level(P):
     g = powerlaw_graph(1 << 17, avg_deg=8.0, gamma=2.5, seed=7)
     n_c = g.n // 100

@@ -48,7 +48,7 @@ def test_quality_cli_runs(P, tmp_path):
     from paper_2204_11757_amd import quality as Qm
     print("[case] quality cli side 16", flush=True)
     rep = Qm.main(["--side", "16", "--k", "8", "--out", str(tmp_path / "q.json")])
-    assert len(rep["meshes"]) == 2 and all(len(m["runs"]) == 15 for m in rep["meshes"])
+    assert len(rep["meshes"]) == 2 and all(len(m["runs"]) == 21 for m in rep["meshes"])
     for m in rep["meshes"]:
         for r in m["runs"]:
             assert r["spectral_error_inf"] <= r["thm2_bound"] + 1e-9
