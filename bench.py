@@ -210,6 +210,8 @@ def main():
     ap.add_argument("--no-per-graph", action="store_true",
                     help="batch configs: skip the one-call-per-graph comparison (for profiling)")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the library's autotuner (run before the warmup, outside the timed steps)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device-to-device tensor copy (reference kernel for "
                          "scaling hardware byte counters)")
@@ -240,6 +242,14 @@ def main():
             return spc.coarsen_batched(dg, g.meta["offsets"], g.meta["n_c"], 0)
         return spc.coarsen_to(dg, n_c, 0)
 
+    tuned = None
+    if not args.no_autotune:
+        print("[bench] autotune", file=sys.stderr, flush=True)
+        if batch:
+            rep = spc.autotune(dg, None, 0, g.meta["offsets"], g.meta["n_c"])
+        else:
+            rep = spc.autotune(dg, n_c, 0)
+        tuned = rep.strip().splitlines()[-1]
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     h = None
     for _ in range(args.warmup):
@@ -371,6 +381,7 @@ def main():
                    "n_c": n_c if not batch else "n/10 per graph", "levels": len(levels),
                    "schedule": "halving"},
         "fine_edges_per_s": total_edges / (ms * 1e-3),
+        "autotune": tuned,
         "per_graph": per_graph,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -151,6 +151,14 @@ int spc_set_allocator(spc_ctx* ctx, void* (*alloc)(size_t, void*), void (*free_)
  *                 no class kernel launched before the counts are read.
  *   "timing"      1: record a HIP event pair on the context stream around
  *                 every kernel launch, for spc_timing_report.
+ *   Launch settings (0 = the tuned or built-in choice; a value fixes it for
+ *   every later call): "lane_max" 16 or 32 (contraction rows of 17..lane_max
+ *   records take one thread each, larger ones a wavefront), "wave_max"
+ *   64..512 (rows up to it take a wavefront, larger ones a 256-thread
+ *   block), "small_rpt" 1, 2 or 4 (rows per thread of the small-row pass),
+ *   "huge_tile" 1024 or 4096 (records per tile of the dense huge rows),
+ *   "sel_blocks" 1..128 (blocks of the radix select), "bv_short" (live
+ *   lists up to this length use the 4-items-per-thread hooking pass).
  * Unknown names return SPC_EINVAL. */
 int spc_set_option(spc_ctx* ctx, const char* name, int64_t value);
 
@@ -215,6 +223,19 @@ int spc_coarsen_level_noalloc(spc_ctx* ctx, const spc_graph* g, int64_t n_target
  * (FP weights come out as FP64).  SPC_EINVAL if perm is not a permutation.
  * Waits for the permutation check. */
 int spc_relabel(spc_ctx* ctx, const spc_graph* g, const int32_t* perm, spc_graph_out* out, int64_t* nnz_out);
+
+/* Autotuner: times the call (spc_coarsen_to(g, n_c, schedule), or with
+ * G > 0 spc_coarsen_batched(G, g, graph_off, n_c_graph, schedule)) under
+ * launch settings chosen by coordinate descent -- contraction rows per
+ * thread, thread- versus wavefront- versus block-per-row boundaries, dense
+ * tile size, radix-select blocks, hooking-pass width; each setting in turn
+ * with the others at their best so far, two runs each, a change kept when
+ * it saves 2 percent -- and keeps the fastest for the input's size class
+ * (bit length of nnz; batches apart).  Later calls on inputs of that class
+ * use it.  Results never depend on these settings.  report (nullable):
+ * the trials as text, "setting=value ms" per line.  Waits for every trial. */
+int spc_autotune(spc_ctx* ctx, const spc_graph* g, int64_t n_c, int schedule, int32_t G, const int64_t* graph_off,
+                 const int64_t* n_c_graph, char* report, size_t cap);
 
 /* Coarsen to n_c super-nodes level by level, re-scoring each level (the
  * multilevel refinement the conclusion proposes).  schedule 0: halve the

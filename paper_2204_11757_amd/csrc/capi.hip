@@ -1,6 +1,7 @@
 // C ABI of the coarsening library (declared in include/spc.h): context,
 // allocation hooks, error reporting, the level / multilevel entry points,
 // the hierarchy, the lift (Definition 2) and the spectral error.
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <mutex>
@@ -366,6 +367,25 @@ static int64_t level_target(int64_t n, int64_t n_c, int schedule) {
   return std::max(n_c, (n + 1) / 2);
 }
 
+// Launch settings for a call on input g: the tuned ones of its size class
+// (unless spc_autotune is running a trial), else the built-in rules.
+static int size_class(int64_t nnz, bool batched) { return bitlen64((uint64_t)nnz) + (batched ? 64 : 0); }
+
+static void apply_tune(spc_ctx* ctx, int64_t nnz, bool batched) {
+  if (ctx->tune_forced) return;
+  ctx->tune = spc_tune();
+  int key = size_class(nnz, batched);
+  for (auto& kv : ctx->tuned)
+    if (kv.first == key) ctx->tune = kv.second;
+  const spc_tune& f = ctx->tune_set;
+  if (f.lane_max) ctx->tune.lane_max = f.lane_max;
+  if (f.wave_max) ctx->tune.wave_max = f.wave_max;
+  if (f.small_rpt) ctx->tune.small_rpt = f.small_rpt;
+  if (f.huge_tile) ctx->tune.huge_tile = f.huge_tile;
+  if (f.sel_blocks) ctx->tune.sel_blocks = f.sel_blocks;
+  if (f.bv_short) ctx->tune.bv_short = f.bv_short;
+}
+
 static void free_level(spc_ctx* ctx, spc_hier::Level& L) {
   dev_free(ctx, L.block);
   for (hipEvent_t& e : L.ev)
@@ -511,6 +531,27 @@ int spc_set_option(spc_ctx* ctx, const char* name, int64_t value) {
   else if (!strcmp(name, "redo_rank")) ctx->force_redo_rank = value ? 1 : 0;
   else if (!strcmp(name, "bad_select_guess")) ctx->force_bad_guess = value ? 1 : 0;
   else if (!strcmp(name, "scan_flag")) ctx->force_scan_flag = value ? 1 : 0;
+  else if (!strcmp(name, "lane_max")) {
+    if (value != 0 && value != 16 && value != 32) return set_error(ctx, SPC_EINVAL, "lane_max takes 0, 16 or 32");
+    ctx->tune_set.lane_max = (int)value;
+  } else if (!strcmp(name, "wave_max")) {
+    if (value != 0 && (value < 64 || value > 512)) return set_error(ctx, SPC_EINVAL, "wave_max takes 0 or 64..512");
+    ctx->tune_set.wave_max = (int)value;
+  } else if (!strcmp(name, "small_rpt")) {
+    if (value != 0 && value != 1 && value != 2 && value != 4)
+      return set_error(ctx, SPC_EINVAL, "small_rpt takes 0, 1, 2 or 4");
+    ctx->tune_set.small_rpt = (int)value;
+  } else if (!strcmp(name, "huge_tile")) {
+    if (value != 0 && value != 1024 && value != 4096)
+      return set_error(ctx, SPC_EINVAL, "huge_tile takes 0, 1024 or 4096");
+    ctx->tune_set.huge_tile = (int)value;
+  } else if (!strcmp(name, "sel_blocks")) {
+    if (value < 0 || value > 128) return set_error(ctx, SPC_EINVAL, "sel_blocks takes 0..128");
+    ctx->tune_set.sel_blocks = (int)value;
+  } else if (!strcmp(name, "bv_short")) {
+    if (value < 0) return set_error(ctx, SPC_EINVAL, "bv_short takes a length >= 0");
+    ctx->tune_set.bv_short = value;
+  }
   else if (!strcmp(name, "speculate")) {
     if (value < 0 || value > 2) return set_error(ctx, SPC_EINVAL, "speculate takes 0, 1 or 2");
     ctx->speculate = (int)value;
@@ -562,6 +603,7 @@ int spc_coarsen_level(spc_ctx* ctx, const spc_graph* g, int64_t n_target, int32_
                       spc_graph_out* coarse, int64_t* nnz_c, spc_level_stats* st) {
   if (!ctx) return SPC_EINVAL;
   ctx->spec_ok = 0;   // a new graph: its first level waits for its forest
+  if (g) apply_tune(ctx, g->nnz, false);
   return level_impl(ctx, g, n_target, cluster_of, coarse, nnz_c, st);
 }
 
@@ -601,6 +643,7 @@ int spc_coarsen_level_noalloc(spc_ctx* ctx, const spc_graph* g, int64_t n_target
   ctx->timing = 0;
   ctx->no_alloc = 1;
   ctx->spec_ok = 0;
+  apply_tune(ctx, g->nnz, false);
   rc = level_impl(ctx, g, n_target, cluster_of, coarse, nnz_c, st);
   ctx->no_alloc = 0;
   ctx->timing = timing;
@@ -623,6 +666,7 @@ int spc_relabel(spc_ctx* ctx, const spc_graph* g, const int32_t* perm, spc_graph
   if (out->n_cap < g->n || out->nnz_cap < g->nnz)
     return set_error(ctx, SPC_ECAPACITY, "relabel output needs n_cap >= n and nnz_cap >= nnz");
   bool fp = g->wtype != SPC_W_I32;
+  apply_tune(ctx, g->nnz, false);
   LevelWork W;
   rc = plan_and_bind(ctx, g->n, g->nnz, W, fp);
   if (rc) return rc;
@@ -659,6 +703,7 @@ int spc_coarsen_to(spc_ctx* ctx, const spc_graph* g, int64_t n_c, int schedule, 
   if (rc) return rc;
   if (n_c < 1) return set_error(ctx, SPC_EINVAL, "n_c must be >= 1");
   if (schedule > 1) return set_error(ctx, SPC_EINVAL, "unknown schedule %d", schedule);
+  apply_tune(ctx, g->nnz, false);
   spc_hier* h = new (std::nothrow) spc_hier();
   if (!h) return SPC_ENOMEM;
   h->ctx = ctx;
@@ -714,6 +759,7 @@ int spc_coarsen_batched(spc_ctx* ctx, int32_t G, const spc_graph* g, const int64
   if (schedule > 1) return set_error(ctx, SPC_EINVAL, "unknown schedule %d", schedule);
   if (graph_off[0] != 0 || graph_off[G] != g->n)
     return set_error(ctx, SPC_EINVAL, "graph offsets must run from 0 to n");
+  apply_tune(ctx, g->nnz, true);
   std::vector<int64_t> ng(G), nc(G), off(graph_off, graph_off + G + 1);
   for (int32_t i = 0; i < G; i++) {
     ng[i] = off[i + 1] - off[i];
@@ -794,6 +840,102 @@ int spc_coarsen_batched(spc_ctx* ctx, int32_t G, const spc_graph* g, const int64
   dev_free(ctx, d_k);
   dev_free(ctx, d_coff);
   *out = h;
+  return SPC_OK;
+}
+
+int spc_autotune(spc_ctx* ctx, const spc_graph* g, int64_t n_c, int schedule, int32_t G, const int64_t* graph_off,
+                 const int64_t* n_c_graph, char* report, size_t cap) {
+  if (!ctx) return SPC_EINVAL;
+  int rc = check_graph(ctx, g);
+  if (rc) return rc;
+  bool batched = G > 0;
+  // one trial: the whole call, freed, on a drained stream; the best of two
+  auto trial = [&](const spc_tune& t, double& ms) -> int {
+    ctx->tune = t;
+    ctx->tune_forced = 1;
+    ms = 1e30;
+    for (int rep = 0; rep < 2; rep++) {
+      int r = hipStreamSynchronize(ctx->stream) == hipSuccess ? SPC_OK : SPC_EHIP;
+      if (r) break;
+      auto t0 = std::chrono::steady_clock::now();
+      spc_hier* h = nullptr;
+      r = batched ? spc_coarsen_batched(ctx, G, g, graph_off, n_c_graph, schedule, &h)
+                  : spc_coarsen_to(ctx, g, n_c, schedule, &h);
+      if (r == SPC_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) r = SPC_EHIP;
+      double dt = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      if (h) spc_hier_free(h);
+      if (r) {
+        ctx->tune_forced = 0;
+        return r;
+      }
+      ms = std::min(ms, dt);
+    }
+    ctx->tune_forced = 0;
+    return SPC_OK;
+  };
+  std::string log;
+  char line[160];
+  spc_tune best;
+  int key = size_class(g->nnz, batched);
+  for (auto& kv : ctx->tuned)
+    if (kv.first == key) best = kv.second;
+  double best_ms;
+  rc = trial(best, best_ms);
+  if (rc) return rc;
+  snprintf(line, sizeof(line), "start %.3f ms\n", best_ms);
+  log += line;
+  // coordinate descent: each setting in turn, the others at their best so
+  // far; a change is kept when it saves at least 2 percent
+  struct Knob {
+    const char* name;
+    int64_t spc_tune::*i64;
+    int spc_tune::*i32;
+    int64_t vals[4];
+    int nv;
+  };
+  const Knob knobs[] = {
+      {"lane_max", nullptr, &spc_tune::lane_max, {16, 32}, 2},
+      {"wave_max", nullptr, &spc_tune::wave_max, {128, 256, 512}, 3},
+      {"small_rpt", nullptr, &spc_tune::small_rpt, {1, 2, 4}, 3},
+      {"huge_tile", nullptr, &spc_tune::huge_tile, {1024, 4096}, 2},
+      {"sel_blocks", nullptr, &spc_tune::sel_blocks, {32, 64, 128}, 3},
+      {"bv_short", &spc_tune::bv_short, nullptr, {1 << 18, 1 << 20, 1 << 22}, 3},
+  };
+  for (const Knob& k : knobs) {
+    for (int v = 0; v < k.nv; v++) {
+      spc_tune t = best;
+      int64_t cur = k.i64 ? best.*(k.i64) : (int64_t)(best.*(k.i32));
+      if (cur == k.vals[v]) continue;
+      if (k.i64) t.*(k.i64) = k.vals[v];
+      else t.*(k.i32) = (int)k.vals[v];
+      double ms;
+      rc = trial(t, ms);
+      if (rc) return rc;
+      snprintf(line, sizeof(line), "%s=%lld %.3f ms\n", k.name, (long long)k.vals[v], ms);
+      log += line;
+      if (ms < 0.98 * best_ms) {
+        best = t;
+        best_ms = ms;
+      }
+    }
+  }
+  bool found = false;
+  for (auto& kv : ctx->tuned)
+    if (kv.first == key) {
+      kv.second = best;
+      found = true;
+    }
+  if (!found) ctx->tuned.push_back({key, best});
+  snprintf(line, sizeof(line),
+           "best %.3f ms: lane_max=%d wave_max=%d small_rpt=%d huge_tile=%d sel_blocks=%d bv_short=%lld\n",
+           best_ms, best.lane_max, best.wave_max, best.small_rpt, best.huge_tile, best.sel_blocks,
+           (long long)best.bv_short);
+  log += line;
+  if (report && cap > 0) {
+    size_t k = std::min(cap - 1, log.size());
+    memcpy(report, log.data(), k);
+    report[k] = 0;
+  }
   return SPC_OK;
 }
 

@@ -304,6 +304,17 @@ struct Arena {
 
 }  // namespace spc
 
+// Launch settings that results never depend on (spc_autotune picks them per
+// size class of the input; 0 = the built-in rule).
+struct spc_tune {
+  int lane_max = 32;      // contraction rows of 17..lane_max records: one thread each (16 or 32)
+  int wave_max = 512;     // rows up to wave_max records: one wavefront each; larger: one block
+  int small_rpt = 0;      // rows per thread of the small-row contraction (1, 2, 4)
+  int huge_tile = 0;      // records per tile of the dense huge-row accumulation (1024, 4096)
+  int sel_blocks = 0;     // blocks of the radix select (at most 128)
+  int64_t bv_short = 0;   // live lists up to this length: 4 items per thread in the hooking pass
+};
+
 struct spc_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -331,6 +342,12 @@ struct spc_ctx {
   int force_redo_rank = 0;   // flag every packed-key level as inexact (redone with rank keys)
   int force_bad_guess = 0;   // give the cutoff selection key bounds that some keys lie outside
   int force_scan_flag = 0;   // the next level finds the scan chain's error flag raised (once)
+  // launch settings in effect, and the tuned ones per size class (key:
+  // bit length of the input's nnz, plus 64 for batches)
+  spc_tune tune;
+  std::vector<std::pair<int, spc_tune>> tuned;
+  spc_tune tune_set{0, 0, 0, 0, 0, 0};   // settings fixed by spc_set_option (0: not fixed)
+  int tune_forced = 0;       // spc_autotune's trials: keep ctx->tune as set
   // the entry point that allocates nothing: this device's scratch array
   // (resolved once per device at creation; null if that failed) and, during
   // such a call, 1 so that nothing on the level path allocates

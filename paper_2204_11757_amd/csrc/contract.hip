@@ -122,6 +122,28 @@ __global__ void __launch_bounds__(CM_BS)
   bool valid = x < g.n;
   int32_t a = valid ? c[x] : -1;
   int64_t len = valid ? 1 + (g.rp[x + 1] - g.rp[x]) : 0;
+  // a super-node whose members are spread over the wavefront (a large
+  // super-node of an irregular graph) would cost one atomic per member on
+  // one address: the lanes of the first lane's super-node take their slots
+  // together first, and drop out of the runs below (when they are one run
+  // from lane 0 the runs already take them together, across wavefronts)
+  int32_t hot = __shfl(a, 0);
+  uint64_t hmask = __ballot(a == hot && hot >= 0);
+  int64_t hot_off = -1;
+  if (hot >= 0 && __popcll(hmask) > 1 && (hmask & (hmask + 1)) != 0) {
+    bool mine = (hmask >> lane_id()) & 1ull;
+    int64_t hl = mine ? len : 0;
+    int64_t hinc = wave_incl_sum(hl);
+    int64_t htot = __shfl(hinc, WAVE - 1);
+    unsigned long long hb = 0;
+    if (lane_id() == 0) hb = atomicAdd(&ecnt[hot], (unsigned long long)htot);
+    hb = __shfl(hb, 0);
+    if (mine) {
+      hot_off = (int64_t)hb + hinc - hl;
+      a = -1;
+      len = 0;
+    }
+  }
   bool head;
   int end;
   uint64_t heads;
@@ -176,9 +198,13 @@ __global__ void __launch_bounds__(CM_BS)
   int endh = __shfl(end, h);
   int64_t before_h = __shfl(inc, h) - __shfl(len, h);   // the wavefront's slots before the run
   if (valid) {
-    if (h == 0) bh = P.fb[w];
-    else if (endh == WAVE) bh = P.lb[w];
-    off[x] = (int64_t)bh + (inc - len - before_h);
+    if (hot_off >= 0) {
+      off[x] = hot_off;
+    } else {
+      if (h == 0) bh = P.fb[w];
+      else if (endh == WAVE) bh = P.lb[w];
+      off[x] = (int64_t)bh + (inc - len - before_h);
+    }
   }
 }
 
@@ -323,7 +349,7 @@ __global__ void __launch_bounds__(SMALL_BS)
                      int64_t* __restrict__ self_out, int32_t* __restrict__ size_out, int64_t n_c,
                      int32_t* __restrict__ r32list, int32_t* __restrict__ midlist,
                      int32_t* __restrict__ blocklist, int32_t* __restrict__ hugelist,
-                     unsigned long long* info, TileScan ts) {
+                     unsigned long long* info, TileScan ts, int lane_cap, int wave_cap) {
   __shared__ unsigned long long stmp[SMALL_BS / WAVE];
   __shared__ int64_t sbase[4];
   __shared__ int32_t smx[SMALL_BS / WAVE];
@@ -338,10 +364,10 @@ __global__ void __launch_bounds__(SMALL_BS)
     int64_t E = gptr[a + 1] - gptr[a];
     if (E > SMALL_CAP) {
       cnt[a] = 0;   // until its class's kernel writes it
-      if (E <= REG32_CAP) {
+      if (E <= lane_cap) {
         r32m |= 1u << r;
         nr32++;
-      } else if (E <= WAVE_CAP) {
+      } else if (E <= wave_cap) {
         midm |= 1u << r;
         nmid++;
       } else if (E <= BLOCK_CAP) {
@@ -938,7 +964,8 @@ static int contract_huge(spc_ctx* ctx, const LevelIn& g, int64_t n_c, spc_graph_
       hipLaunchKernelGGL(k_huge_base, dim3(grid_for(H, 256)), dim3(256), 0, st, W.hugelist, H, seg->coff,
                          seg->G, base);
     }
-    if (g.nnz > HD_SMALL_NNZ)
+    bool big_tiles = ctx->tune.huge_tile == 4096 || (ctx->tune.huge_tile != 1024 && g.nnz > HD_SMALL_NNZ);
+    if (big_tiles)
       hipLaunchKernelGGL(k_huge_dense<HT>, dim3(grid_for(total_bound, HT)), dim3(HT_BS), 0, st, W.temp, W.gptr,
                          W.hugelist, hoff, H, self_out, out->size, hmem, dense, ncp, (const int32_t*)base,
                          &info[I_DENSE]);
@@ -1047,21 +1074,28 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
   }
   {
     TimedScope ts(ctx, "contract_small", (double)g.nnz);
-    // the fewest rows per thread that keep the grid within 1024 blocks (its
-    // four class chains then fit the look-back words any level reserves)
+    // the fewest rows per thread that keep the grid within 1024 blocks, or
+    // the tuned count when its four class chains fit the level's look-back
+    // words
     TileScan tsc = next_scan(ctx, W);
-    if (n_c <= 1024 * SMALL_BS)
+    int rpt = n_c <= 1024 * SMALL_BS ? 1 : n_c <= 1024 * SMALL_BS * 2 ? 2 : SMALL_RPT;
+    int want = ctx->tune.small_rpt;
+    if ((want == 1 || want == 2 || want == 4) && 4 * (int64_t)grid_for(n_c, SMALL_BS * want) <= ctx->lb_words)
+      rpt = want;
+    int lane_max = ctx->tune.lane_max == 16 ? 16 : REG32_CAP;
+    int wave_max = ctx->tune.wave_max >= 64 && ctx->tune.wave_max <= WAVE_CAP ? ctx->tune.wave_max : WAVE_CAP;
+    if (rpt == 1)
       hipLaunchKernelGGL(k_contract_small<1>, dim3(grid_for(n_c, SMALL_BS)), dim3(SMALL_BS), 0, st, W.temp,
                          W.gptr, W.cnt, self_out, out->size, n_c, W.r32list, W.midlist, W.blocklist, W.hugelist,
-                         info, tsc);
-    else if (n_c <= 1024 * SMALL_BS * 2)
+                         info, tsc, lane_max, wave_max);
+    else if (rpt == 2)
       hipLaunchKernelGGL(k_contract_small<2>, dim3(grid_for(n_c, SMALL_BS * 2)), dim3(SMALL_BS), 0, st, W.temp,
                          W.gptr, W.cnt, self_out, out->size, n_c, W.r32list, W.midlist, W.blocklist, W.hugelist,
-                         info, tsc);
+                         info, tsc, lane_max, wave_max);
     else
       hipLaunchKernelGGL(k_contract_small<SMALL_RPT>, dim3(grid_for(n_c, SMALL_BS * SMALL_RPT)), dim3(SMALL_BS),
                          0, st, W.temp, W.gptr, W.cnt, self_out, out->size, n_c, W.r32list, W.midlist,
-                         W.blocklist, W.hugelist, info, tsc);
+                         W.blocklist, W.hugelist, info, tsc, lane_max, wave_max);
   }
   SPC_LAUNCH_CHECK(ctx, "contract_small");
   // with a deferred selection, the first read also carries its super-node count

@@ -612,7 +612,7 @@ static void launch_bv_merge(spc_ctx* ctx, LevelWork& W, int64_t bound, const uin
                             const uint64_t* lo, const unsigned long long* cnt, const uint64_t* best, int64_t n,
                             const KeyND* guard_keys, int ebits) {
   unsigned long long* info = W.info;
-  if (bound <= BV_SHORT_MAX)
+  if (bound <= (ctx->tune.bv_short > 0 ? ctx->tune.bv_short : (int64_t)BV_SHORT_MAX))
     hipLaunchKernelGGL(k_bv_merge<BV_SHORT>, dim3(grid_for(bound, BV_SHORT * BS)), dim3(BS), 0, ctx->stream,
                        lr, lp, lo, cnt, best, W.parent, W.msfP, W.msfO, W.msfC, &info[I_MSF], n, guard_keys,
                        W.kexact, &info[I_GUARD], ebits, (int*)&info[I_VIOL], next_scan(ctx, W),
@@ -692,20 +692,64 @@ __global__ void __launch_bounds__(BS)
     pa[i] = __hip_atomic_load(&parent[(int32_t)(uint32_t)suv[i]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     pb[i] = __hip_atomic_load(&parent[(int32_t)(suv[i] >> 32)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  int32_t ra[BC_PER], rb[BC_PER];
+  for (int i = 0; i < BC_PER; i++) {
+    int64_t idx = base + tid + i * BS;
+    ra[i] = rb[i] = -1;
+    if (idx < n) {
+      ra[i] = uf_find_from(parent, (int32_t)(uint32_t)suv[i], pa[i]);
+      rb[i] = uf_find_from(parent, (int32_t)(suv[i] >> 32), pb[i]);
+    }
+  }
+  // Late rounds and hubs make one component's root the target of most
+  // updates, and atomics on one address serialise.  The roots' current
+  // values are loaded first (all items' loads together) and an update that
+  // cannot lower cur (it only decreases) or change nxt (only ever set to
+  // KEY_INF here) is skipped; besides, when at least a quarter of the
+  // wavefront's live lanes share the first live lane's root on a side, they
+  // fold their keys and one lane updates.
+  uint64_t va[BC_PER], vb[BC_PER], na[BC_PER], nb[BC_PER];
+#pragma unroll
+  for (int i = 0; i < BC_PER; i++) {
+    bool live = ra[i] != rb[i];
+    va[i] = live ? __hip_atomic_load(&cur[ra[i]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+    vb[i] = live ? __hip_atomic_load(&cur[rb[i]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+    na[i] = live ? __hip_atomic_load(&nxt[ra[i]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : KEY_INF;
+    nb[i] = live ? __hip_atomic_load(&nxt[rb[i]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : KEY_INF;
+  }
   for (int i = 0; i < BC_PER; i++) {
     ruv[i] = 0;
-    int64_t idx = base + tid + i * BS;
-    if (idx >= n) break;
-    uint64_t uv = suv[i];
     uint64_t key = skey[i];
-    int32_t a = uf_find_from(parent, (int32_t)(uint32_t)uv, pa[i]);
-    int32_t b = uf_find_from(parent, (int32_t)(uv >> 32), pb[i]);
-    if (a != b) {
-      atomicMin((unsigned long long*)&cur[a], (unsigned long long)key);
-      atomicMin((unsigned long long*)&cur[b], (unsigned long long)key);
-      nxt[a] = KEY_INF;
-      nxt[b] = KEY_INF;
-      ruv[i] = (uint64_t)(uint32_t)a | ((uint64_t)(uint32_t)b << 32);
+    bool live = ra[i] != rb[i];
+#pragma unroll
+    for (int side = 0; side < 2; side++) {
+      int32_t r = side ? rb[i] : ra[i];
+      bool lower = live && key < (side ? vb[i] : va[i]);
+      bool clear = live && (side ? nb[i] : na[i]) != KEY_INF;
+      uint64_t lmask = __ballot(lower || clear);
+      bool done = false;
+      if (lmask) {
+        int leader = __ffsll((long long)lmask) - 1;
+        int32_t rl = __shfl(r, leader);
+        bool same = (lower || clear) && r == rl;
+        uint64_t smask = __ballot(same);
+        if (4 * __popcll(smask) >= __popcll(lmask) && __popcll(smask) > 1) {
+          uint64_t mn = wave_min<uint64_t>(same && lower ? key : KEY_INF);
+          bool anyc = __ballot(same && clear) != 0;
+          if (lane_id() == leader) {
+            if (mn != KEY_INF) atomicMin((unsigned long long*)&cur[rl], (unsigned long long)mn);
+            if (anyc) nxt[rl] = KEY_INF;
+          }
+          done = same;
+        }
+      }
+      if (!done) {
+        if (lower) atomicMin((unsigned long long*)&cur[r], (unsigned long long)key);
+        if (clear) nxt[r] = KEY_INF;
+      }
+    }
+    if (live) {
+      ruv[i] = (uint64_t)(uint32_t)ra[i] | ((uint64_t)(uint32_t)rb[i] << 32);
       keep |= 1u << i;
       nk++;
     }
@@ -1208,6 +1252,7 @@ int radix_select(spc_ctx* ctx, const uint64_t* keys, const unsigned long long* c
   // 32 keys per thread and pass up to SEL_MAXB blocks (a barrier's cost
   // grows with the blocks that meet at it)
   int maxb = ctx->num_cus < SEL_MAXB ? ctx->num_cus : SEL_MAXB;
+  if (ctx->tune.sel_blocks > 0 && ctx->tune.sel_blocks < maxb) maxb = ctx->tune.sel_blocks;
   int grid = cnt_bound <= SEL_SMALL ? 1 : grid_for(cnt_bound, SEL_BS * 32, maxb);
   if (grid < 2 && cnt_bound > SEL_SMALL) grid = 2;
   hipLaunchKernelGGL(k_select, dim3(grid), dim3(SEL_BS), 0, ctx->stream, keys, cnt_dev, cnt_bound, k_dev,

@@ -34,7 +34,7 @@ EXPORTS = [
     "spc_spectral_error", "spc_validate_graph", "spc_timing_report", "spc_hier_cluster_map",
     "spc_spectral_error_graph", "spc_spectral_error_backward", "spc_entry_map",
     "spc_contract_backward", "spc_coarsen_batched", "spc_hier_graph_offsets",
-    "spc_coarsen_level_noalloc", "spc_relabel",
+    "spc_coarsen_level_noalloc", "spc_relabel", "spc_autotune",
 ]
 
 
@@ -92,6 +92,7 @@ def lib():
             "spc_coarsen_level_noalloc": [p, C.POINTER(_Graph), i64, p, C.POINTER(_GraphOut),
                                           C.POINTER(C.c_int64), C.POINTER(LevelStats)],
             "spc_relabel": [p, C.POINTER(_Graph), p, C.POINTER(_GraphOut), C.POINTER(C.c_int64)],
+            "spc_autotune": [p, C.POINTER(_Graph), i64, i32, i32, p, p, C.c_char_p, C.c_size_t],
             "spc_coarsen_to": [p, C.POINTER(_Graph), i64, i32, C.POINTER(C.c_void_p)],
             "spc_hier_num_levels": [p],
             "spc_hier_level": [p, i32, C.POINTER(_Graph), C.POINTER(C.c_void_p),
@@ -340,6 +341,23 @@ def relabel(g: DeviceGraph, perm) -> DeviceGraph:
     k = nnz.value
     return DeviceGraph(n=g.n, row_ptr=out.row_ptr, col=out.col[:k], w=out.w[:k], self_w=out.self_w,
                        size=out.size)
+
+
+def autotune(g: DeviceGraph, n_c=None, schedule: int = 0, graph_off=None, n_c_graph=None) -> str:
+    """Tune the launch settings for inputs of g's size class (see
+    spc_autotune): a plain call to n_c, or with graph_off and n_c_graph the
+    batched call.  Returns the trials' report."""
+    ctx = context(_dev(g.row_ptr))
+    buf = C.create_string_buffer(1 << 14)
+    gc = g._c()
+    if graph_off is not None:
+        off = np.ascontiguousarray(graph_off, dtype=np.int64)
+        nc = np.ascontiguousarray(n_c_graph, dtype=np.int64)
+        ctx.check(lib().spc_autotune(ctx.h, C.byref(gc), 0, int(schedule), int(off.shape[0] - 1),
+                                     off.ctypes.data, nc.ctypes.data, buf, len(buf)))
+    else:
+        ctx.check(lib().spc_autotune(ctx.h, C.byref(gc), int(n_c), int(schedule), 0, None, None, buf, len(buf)))
+    return buf.value.decode()
 
 
 SPC_NOALLOC_SCRATCH_BYTES = 134217728

@@ -425,3 +425,46 @@ def test_hash_tie_break_on_a_bipartite_grid(P):
     st1 = check_level(P, r.to_host(), t, "seeded order")
     assert st0.largest_cluster == g.n - t + 1
     assert st1.largest_cluster < st0.largest_cluster // 2
+
+
+@pytest.mark.parametrize("opt,val", [("lane_max", 16), ("wave_max", 64), ("wave_max", 200), ("small_rpt", 1),
+                                     ("small_rpt", 2), ("small_rpt", 4), ("huge_tile", 1024), ("huge_tile", 4096),
+                                     ("sel_blocks", 2), ("sel_blocks", 32), ("bv_short", 1),
+                                     ("bv_short", 1 << 40)])
+def test_launch_settings_do_not_change_results(P, opt, val):
+    # every launch setting the autotuner may pick gives the same result
+    P.set_option(opt, val)
+    try:
+        g = trimesh(96, ("uniform", 1, 8), seed=61)
+        check_hierarchy(P, g, g.n // 50, 0, f"trimesh-96 {opt}={val}")
+        f = grid3d(16, ("uniform", 1, 16), seed=62)   # a giant super-node: huge rows
+        check_hierarchy(P, f, f.n // 32, 0, f"grid3d-16 {opt}={val}")
+    finally:
+        P.set_option(opt, 0)
+
+
+def test_autotune_plain_and_batched(P):
+    g = trimesh(120, ("uniform", 1, 8), seed=63)
+    dg = P.DeviceGraph.from_host(g)
+    say("autotune trimesh-120", f"n={g.n}")
+    rep = P.autotune(dg, g.n // 100, 0)
+    assert "best" in rep and "start" in rep
+    check_hierarchy(P, g, g.n // 100, 0, "trimesh-120 tuned")
+    from meshgen import batch_trimeshes
+    graphs = batch_trimeshes(24, seed=64, lo=16, hi=48)
+    union, offs = P.pack_graphs(graphs)
+    n_c = [max(1, x.n // 10) for x in graphs]
+    say("autotune batch-24", f"n={union.n}")
+    du = P.DeviceGraph.from_host(union)
+    rep = P.autotune(du, None, 0, offs, n_c)
+    assert "best" in rep
+    h = P.coarsen_batched(du, offs, n_c, 0)
+    cl, gc, _ = h.level(h.num_levels)
+    o = h.offsets(h.num_levels)
+    for i, x in enumerate(graphs):
+        want = oracle.coarsen_to(x, n_c[i], 0)[-1][1]
+        a, b = o[i], o[i + 1]
+        e0, e1 = int(host(gc.row_ptr)[a]), int(host(gc.row_ptr)[b])
+        np.testing.assert_array_equal(host(gc.col)[e0:e1] - a, want.col, err_msg=f"graph {i}")
+        np.testing.assert_array_equal(host(gc.w)[e0:e1], want.w, err_msg=f"graph {i}")
+    h.free()
