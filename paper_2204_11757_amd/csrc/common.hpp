@@ -166,10 +166,6 @@ struct Lbs {
   __device__ __forceinline__ static int at(int k) { return k + k / PER; }
 };
 
-// Load-balanced mapping of a tile of T consecutive positions
-// [p0, p0 + T) of a CSR-like prefix array ptr[0..nrows] onto rows:
-// srow[Lbs<T,BS>::at(k)] = row containing position p0 + k (srow holds
-// Lbs<T,BS>::SIZE words).  Called by all BS threads.
 // Workgroups are dispatched round-robin over the chip's 8 XCDs, each with its
 // own L2.  xcd_tile renumbers block b of G so that every XCD takes one
 // contiguous run of tiles: neighbouring tiles, which read and write the same
@@ -180,24 +176,18 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) {
   return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+// Load-balanced mapping of a tile of T consecutive positions
+// [p0, p0 + T) of a CSR-like prefix array ptr[0..nrows] onto rows:
+// srow[Lbs<T,BS>::at(k)] = row containing position p0 + k (srow holds
+// Lbs<T,BS>::SIZE words).  Called by all BS threads.  lbs_fill is given the
+// rows r0 <= r1 that hold the tile's first and last positions (r1 may be
+// any later row: rows starting at or past the tile's end are skipped);
+// lbs_tile finds them by searching ptr.
 template <int T, int BS>
-__device__ __forceinline__ void lbs_tile(const int64_t* __restrict__ ptr, int64_t nrows, int64_t p0,
-                                         int32_t* srow, int64_t* sh, int32_t* scan_tmp) {
+__device__ __forceinline__ void lbs_fill(const int64_t* __restrict__ ptr, int64_t r0, int64_t r1, int64_t p0,
+                                         int32_t* srow, int32_t* scan_tmp) {
   using L = Lbs<T, BS>;
-  static_assert(BS >= 2 * WAVE, "the tile's first and last rows are searched by two wavefronts");
   int tid = threadIdx.x;
-  if (tid < WAVE) {
-    int64_t r0 = wave_upper_search(ptr, nrows, p0);
-    if (tid == 0) sh[0] = r0;
-  } else if (tid < 2 * WAVE) {
-    int64_t total = ptr[nrows];
-    int64_t last = p0 + T - 1;
-    if (last > total - 1) last = total - 1;
-    int64_t r1 = wave_upper_search(ptr, nrows, last);
-    if (tid == WAVE) sh[1] = r1;
-  }
-  __syncthreads();
-  int64_t r0 = sh[0], r1 = sh[1];
   for (int k = tid; k < T; k += BS) srow[L::at(k)] = (int32_t)r0;
   __syncthreads();
   for (int64_t r = r0 + 1 + tid; r <= r1; r += BS) {
@@ -229,6 +219,25 @@ __device__ __forceinline__ void lbs_tile(const int64_t* __restrict__ ptr, int64_
     srow[L::at(tid * PER + i)] = v;
   }
   __syncthreads();
+}
+
+template <int T, int BS>
+__device__ __forceinline__ void lbs_tile(const int64_t* __restrict__ ptr, int64_t nrows, int64_t p0,
+                                         int32_t* srow, int64_t* sh, int32_t* scan_tmp) {
+  static_assert(BS >= 2 * WAVE, "the tile's first and last rows are searched by two wavefronts");
+  int tid = threadIdx.x;
+  if (tid < WAVE) {
+    int64_t r0 = wave_upper_search(ptr, nrows, p0);
+    if (tid == 0) sh[0] = r0;
+  } else if (tid < 2 * WAVE) {
+    int64_t total = ptr[nrows];
+    int64_t last = p0 + T - 1;
+    if (last > total - 1) last = total - 1;
+    int64_t r1 = wave_upper_search(ptr, nrows, last);
+    if (tid == WAVE) sh[1] = r1;
+  }
+  __syncthreads();
+  lbs_fill<T, BS>(ptr, sh[0], sh[1], p0, srow, scan_tmp);
 }
 
 // ---------------------------------------------------------------------------

@@ -40,6 +40,8 @@ constexpr int BS = 256;   // block size of the selection kernels
 // edges looks columns up instead of searching the long row.
 constexpr int HUGE_T = 1024;
 constexpr int H_MAX = 4;
+// edges per tile of the score kernel (three per thread)
+constexpr int SCORE_TILE = 768;
 
 // Device view of an integer-path input graph.
 struct LevelIn {
@@ -169,6 +171,7 @@ struct LevelWork {
   uint64_t* degpart;         // [n / 4096 + 2] per-block weight sums
   int32_t* lc;               // [n]  entries with col < row
   int64_t* uptr;             // [n+1] upper-edge prefix (edge ids)
+  int32_t* trow;             // [m / SCORE_TILE + 2] row holding each score tile's first edge
   uint64_t* P;               // [m]  order key per edge (sorted-rank order)
   uint64_t* Pc;              // [nnz] order key per CSR entry (both directions)
   uint64_t* samples;         // [m/64 + 2], keys of edges 0, s, 2s, ... (s = 2^sample_shift(m))

@@ -81,30 +81,157 @@ __device__ __forceinline__ void score_mapped_block(
 }
 
 // ---------------------------------------------------------------------------
-// A2 + A3: 3 edges (u < v) per thread; tiles of TILE_S consecutive edge ids
-// are mapped to rows by a load-balanced search over the upper-entry prefix
-// uptr.
+// A2 + A3: 3 edges (u < v) per thread; tiles of SCORE_TILE consecutive edge
+// ids are mapped to rows by a load-balanced search over the upper-entry
+// prefix uptr, starting from the tile's first row, which the degree pass
+// recorded (trow).
 // ---------------------------------------------------------------------------
-constexpr int TILE_S = 768;   // 3 edges per thread: the register budget of 5 waves per SIMD
+constexpr int TILE_S = SCORE_TILE;
+constexpr int EPT = TILE_S / BS;
 
-// five waves per SIMD: the register budget that keeps the long-row paths
-// free of spills
+// Writes edge e's key into both of its entries (and its sample and exact
+// record); returns whether the packed key is exact.
+template <int MODE>
+__device__ __forceinline__ bool emit_key(int64_t e, int64_t j, int64_t jm, uint64_t N, uint64_t D, int c,
+                                         int ebits, uint64_t* __restrict__ Pc, uint64_t* __restrict__ samples,
+                                         KeyND* __restrict__ keys, int write_keys, int sshift) {
+  bool ex = false;
+  if (MODE == 0) {
+    uint64_t K = c <= 50 ? fixed_key_fast(N, D, c, ex) : fixed_key(N, D, c, ex);
+    uint64_t key = (K << ebits) | (uint64_t)e;
+    Pc[j] = key;    // entry (u -> v)
+    Pc[jm] = key;   // entry (v -> u)
+    if ((e & ((1ll << sshift) - 1)) == 0) samples[e >> sshift] = key;
+  }
+  if (MODE == 1 || write_keys) keys[e] = KeyND{N, D, (uint64_t)e};
+  return ex;
+}
+
+// The edge tile of k_score.  The loads come in rounds that each serve all of
+// the thread's edges at once: u's row bounds, offsets and degree; the edge's
+// entry (v and the weight); v's bounds and degree; then the two rows of each
+// edge whose rows both hold at most RC entries (others take edge_score,
+// after the short ones).  NARROW: every degree is below 2^24.
+template <int MODE, bool NARROW>
+__device__ __forceinline__ void score_tile(const LevelIn& g, const uint64_t* __restrict__ deg,
+                                           const int32_t* __restrict__ lc, const int64_t* __restrict__ uptr,
+                                           int64_t m, int c, int ebits, uint64_t* __restrict__ Pc,
+                                           uint64_t* __restrict__ samples, KeyND* __restrict__ keys,
+                                           int write_keys, uint64_t* __restrict__ kexact, int sshift,
+                                           const int32_t* srow, int64_t e0, const int32_t (&hrow)[H_MAX],
+                                           uint64_t& dmx) {
+  using L = Lbs<TILE_S, BS>;
+  int tid = threadIdx.x;
+  int32_t eu[EPT], ev[EPT];
+  uint32_t ew[EPT];
+  int64_t ej[EPT], au[EPT], av[EPT];
+  int32_t lu[EPT], lv[EPT];
+  uint64_t du[EPT], dv[EPT], su[EPT], ms[EPT];
+  bool live[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; i++) {
+    int k = tid + i * BS;
+    live[i] = e0 + k < m;
+    eu[i] = live[i] ? srow[L::at(k)] : 0;
+  }
+  // round 1: row u
+#pragma unroll
+  for (int i = 0; i < EPT; i++) {
+    int32_t u = eu[i];
+    au[i] = g.rp[u];
+    lu[i] = (int32_t)(g.rp[u + 1] - au[i]);
+    ej[i] = au[i] + lc[u] + (e0 + tid + i * BS - uptr[u]);
+    du[i] = deg[u];
+    su[i] = g.self ? (uint64_t)g.self[u] : 0;
+  }
+  // round 2: the edge's entry
+#pragma unroll
+  for (int i = 0; i < EPT; i++) {
+    ej[i] = live[i] ? ej[i] : 0;   // (entry 0 exists: the tile holds an edge)
+    ev[i] = g.col[ej[i]];
+    ew[i] = (uint32_t)g.w[ej[i]];
+  }
+  // round 3: row v, and the diagonal terms x = u and x = v of the sum
+#pragma unroll
+  for (int i = 0; i < EPT; i++) {
+    int32_t v = ev[i];
+    av[i] = g.rp[v];
+    lv[i] = (int32_t)(g.rp[v + 1] - av[i]);
+    dv[i] = deg[v];
+    uint64_t sv = g.self ? (uint64_t)g.self[v] : 0;
+    ms[i] = umin64(wmul<NARROW>(su[i], dv[i]), wmul<NARROW>(ew[i], du[i])) +
+            umin64(wmul<NARROW>(ew[i], dv[i]), wmul<NARROW>(sv, du[i]));
+  }
+  uint32_t shrt = 0, exm = 0;
+#pragma unroll
+  for (int i = 0; i < EPT; i++) {
+    bool mapped = false;
+#pragma unroll
+    for (int s = 0; s < H_MAX; s++) mapped |= hrow[s] == eu[i] || hrow[s] == ev[i];
+    // edges of a mapped row are scored by the mapped rows' blocks (their bit stays clear)
+    live[i] = live[i] && !mapped;
+    // (a live edge's rows both hold it, so neither is empty)
+    shrt |= (live[i] && lu[i] <= RC && lv[i] <= RC && g.nnz >= RC ? 1u : 0u) << i;
+  }
+  // round 4: the rows of the short edges, one edge after the other
+#pragma unroll
+  for (int i = 0; i < EPT; i++) {
+    if (shrt >> i & 1u) {
+      int32_t below;
+      uint64_t M = ms[i] + short_rows_sum<NARROW>(g.col, g.w, g.nnz, au[i], lu[i], du[i], av[i], lv[i],
+                                                  dv[i], (uint32_t)eu[i], below);
+      uint64_t D = wmul<NARROW>(du[i], dv[i]);
+      dmx = D > dmx ? D : dmx;
+      bool ex = emit_key<MODE>(e0 + tid + i * BS, ej[i], av[i] + below, 2 * D - 2 * M, D, c, ebits, Pc,
+                               samples, keys, write_keys, sshift);
+      exm |= (ex ? 1u : 0u) << i;
+    }
+  }
+  // the other live edges (a row longer than RC), one at a time: a
+  // wavefront runs this loop only for the slots where one of its lanes has
+  // such an edge
+#pragma unroll 1
+  for (int i = 0; i < EPT; i++) {
+    if (live[i] && !(shrt >> i & 1u)) {
+      uint64_t N, D;
+      int64_t jm;
+      edge_score(g, deg, lc, eu[i], ev[i], (int32_t)ew[i], N, D, jm);
+      dmx = D > dmx ? D : dmx;
+      bool ex = emit_key<MODE>(e0 + tid + i * BS, ej[i], jm, N, D, c, ebits, Pc, samples, keys, write_keys,
+                               sshift);
+      exm |= (ex ? 1u : 0u) << i;
+    }
+  }
+  if (MODE == 0) {
+    // the exactness map: a wavefront's 64 consecutive edges make one word
+#pragma unroll
+    for (int i = 0; i < EPT; i++) {
+      uint64_t bits = __ballot(exm >> i & 1u);
+      int64_t ew0 = e0 + (tid & ~(WAVE - 1)) + i * BS;
+      if (lane_id() == 0 && ew0 < m) kexact[ew0 >> 6] = bits;
+    }
+  }
+}
+
+// four waves per SIMD: the register budget that keeps the rounds of loads
+// of three edges in flight free of spills
 template <int MODE>  // 0: 64-bit key (+ optional exact records), 1: exact records only
-__global__ void __launch_bounds__(BS, 5)
+__global__ void __launch_bounds__(BS, 4)
     k_score(LevelIn g, const uint64_t* __restrict__ deg, const int32_t* __restrict__ lc,
             const int64_t* __restrict__ uptr, int64_t m, int c, int ebits,
             uint64_t* __restrict__ Pc, uint64_t* __restrict__ samples, KeyND* __restrict__ keys,
             int write_keys, unsigned long long* info, const int32_t* __restrict__ htab,
-            uint64_t* __restrict__ kexact, int sshift, int tiles, const int32_t* __restrict__ hmap) {
+            uint64_t* __restrict__ kexact, int sshift, int tiles, const int32_t* __restrict__ hmap,
+            const int32_t* __restrict__ trow) {
   // write_keys < 0: exact records only when the packed key is not exact
   // for sure, i.e. when dmax^4 > 2^c
+  uint64_t dmax = info[I_DMAX];
   if (MODE == 0 && write_keys < 0) {
-    unsigned __int128 d2 = (unsigned __int128)info[I_DMAX] * info[I_DMAX];
+    unsigned __int128 d2 = (unsigned __int128)dmax * dmax;
     write_keys = (d2 >> 64) != 0 || d2 * d2 > ((unsigned __int128)1 << c) ? 1 : 0;
     if (write_keys && blockIdx.x == 0 && threadIdx.x == 0) info[I_KEYS] = 1;
   }
   __shared__ int32_t srow[Lbs<TILE_S, BS>::SIZE];
-  __shared__ int64_t sh[2];
   __shared__ int32_t stmp[BS / WAVE];
   __shared__ uint64_t sred[BS / WAVE];
   if ((int)blockIdx.x >= tiles) {
@@ -114,9 +241,10 @@ __global__ void __launch_bounds__(BS, 5)
                              write_keys, info, htab, hmap, sshift, sred);
     return;
   }
-  int64_t e0 = xcd_tile(blockIdx.x, tiles) * TILE_S;
-  lbs_tile<TILE_S, BS>(uptr, g.n, e0, srow, sh, stmp);
-  int tid = threadIdx.x;
+  int64_t t = xcd_tile(blockIdx.x, tiles);
+  int64_t e0 = t * TILE_S;
+  int64_t r1 = t + 1 < tiles ? trow[t + 1] : g.n - 1;
+  lbs_fill<TILE_S, BS>(uptr, trow[t], r1, e0, srow, stmp);
   uint64_t dmx = 0;
   // rows with a position map (uniform over the block)
   unsigned long long nh = info[I_LONGROW];
@@ -124,59 +252,16 @@ __global__ void __launch_bounds__(BS, 5)
   int32_t hrow[H_MAX];
 #pragma unroll
   for (int s = 0; s < H_MAX; s++) hrow[s] = s < hc ? htab[s] : -1;
-  constexpr int EPT = TILE_S / BS;
-  // locate all of this thread's edges first so their loads overlap
-  int32_t eu[EPT], ev[EPT], ew[EPT];
-  int64_t ej[EPT];
-#pragma unroll
-  for (int i = 0; i < EPT; i++) {
-    int k = tid + i * BS;
-    int64_t e = e0 + k;
-    eu[i] = e < m ? srow[Lbs<TILE_S, BS>::at(k)] : 0;
-  }
-#pragma unroll
-  for (int i = 0; i < EPT; i++) {
-    int64_t e = e0 + tid + i * BS;
-    ej[i] = e < m ? g.rp[eu[i]] + lc[eu[i]] + (e - uptr[eu[i]]) : 0;
-  }
-#pragma unroll
-  for (int i = 0; i < EPT; i++) {
-    int64_t e = e0 + tid + i * BS;
-    ev[i] = e < m ? g.col[ej[i]] : 0;
-    ew[i] = e < m ? g.w[ej[i]] : 0;
-  }
-  for (int i = 0; i < EPT; i++) {
-    int64_t e = e0 + tid + i * BS;
-    bool ex = false;
-    bool mapped = false;
-#pragma unroll
-    for (int s = 0; s < H_MAX; s++) mapped |= hrow[s] == eu[i] || hrow[s] == ev[i];
-    // edges of a mapped row are scored by the mapped rows' blocks (their bit stays clear)
-    if (e < m && !mapped) {
-      uint64_t N, D;
-      int64_t jm;
-      edge_score(g, deg, lc, eu[i], ev[i], ew[i], N, D, jm);
-      dmx = D > dmx ? D : dmx;
-      if (MODE == 0) {
-        uint64_t K = fixed_key(N, D, c, ex);
-        uint64_t key = (K << ebits) | (uint64_t)e;
-        Pc[ej[i]] = key;   // entry (u -> v)
-        Pc[jm] = key;      // entry (v -> u)
-        if ((e & ((1ll << sshift) - 1)) == 0) samples[e >> sshift] = key;
-      }
-      if (MODE == 1 || write_keys) keys[e] = KeyND{N, D, (uint64_t)e};
-    }
-    if (MODE == 0) {
-      // the exactness map: a wavefront's 64 consecutive edges make one word
-      uint64_t bits = __ballot(ex);
-      int64_t ew0 = e0 + (tid & ~(WAVE - 1)) + i * BS;
-      if (lane_id() == 0 && ew0 < m) kexact[ew0 >> 6] = bits;
-    }
-  }
+  if (dmax < (1ull << 24))
+    score_tile<MODE, true>(g, deg, lc, uptr, m, c, ebits, Pc, samples, keys, write_keys, kexact, sshift, srow,
+                           e0, hrow, dmx);
+  else
+    score_tile<MODE, false>(g, deg, lc, uptr, m, c, ebits, Pc, samples, keys, write_keys, kexact, sshift, srow,
+                            e0, hrow, dmx);
   dmx = wave_max(dmx);
-  if (lane_id() == 0) sred[tid / WAVE] = dmx;
+  if (lane_id() == 0) sred[threadIdx.x / WAVE] = dmx;
   __syncthreads();
-  if (tid == 0) {
+  if (threadIdx.x == 0) {
     uint64_t a = 0;
     for (int w = 0; w < BS / WAVE; w++) a = sred[w] > a ? sred[w] : a;
     atomic_max_lazy(&info[I_DMAXE], (unsigned long long)a);
@@ -262,12 +347,13 @@ void launch_score(spc_ctx* ctx, const LevelIn& g, const LevelWork& W, int64_t m,
   if (mode == 0) {
     TimedScope ts(ctx, "score", (double)m);
     hipLaunchKernelGGL(k_score<0>, dim3(grid), dim3(BS), 0, ctx->stream, g, W.deg, W.lc, W.uptr, m, c, ebits,
-                       W.Pc, W.samples, W.keysA, -1, W.info, W.htab, W.kexact, sample_shift(m), tiles, W.hmap);
+                       W.Pc, W.samples, W.keysA, -1, W.info, W.htab, W.kexact, sample_shift(m), tiles, W.hmap,
+                       W.trow);
   } else {
     TimedScope ts(ctx, "score_rank", (double)m);
     hipLaunchKernelGGL(k_score<1>, dim3(grid), dim3(BS), 0, ctx->stream, g, W.deg, W.lc, W.uptr, m, c, ebits,
                        (uint64_t*)nullptr, (uint64_t*)nullptr, W.keysA, 1, W.info, W.htab, (uint64_t*)nullptr,
-                       sample_shift(m), tiles, W.hmap);
+                       sample_shift(m), tiles, W.hmap, W.trow);
   }
 }
 

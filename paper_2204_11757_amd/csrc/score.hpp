@@ -252,6 +252,58 @@ __device__ __forceinline__ void edge_score(const LevelIn& g, const uint64_t* __r
   N = 2 * D - 2 * M;
 }
 
+// Products of a weight (or self-loop weight) and a degree.  Every weight
+// of a row is at most its node's degree, so when the largest degree is
+// below 2^24 all operands fit 24 bits and the full product takes the two
+// full-rate 24-bit multiplies.
+template <bool NARROW>
+__device__ __forceinline__ uint64_t wmul(uint64_t a, uint64_t b) {
+  if constexpr (NARROW) return (uint64_t)((uint32_t)a & 0xFFFFFFu) * (uint64_t)((uint32_t)b & 0xFFFFFFu);
+  else return a * b;
+}
+
+// Common-support sum min(w_u[x] dv, w_v[x] du) of an edge whose rows
+// [au, au + lu) and [av, av + lv) both hold between 1 and RC entries, in
+// arrays of nnz >= RC entries.  Each row is read as the RC entries from its
+// start, or the array's last RC entries when it ends within them, so every
+// load is an immediate offset from one base and none waits on a branch;
+// entries outside the row turn into sentinel columns above every node id
+// (u's and v's differ, so they never match).  below: v's columns smaller
+// than u.
+template <bool NARROW>
+__device__ __forceinline__ uint64_t short_rows_sum(const int32_t* __restrict__ col,
+                                                   const int32_t* __restrict__ w, int64_t nnz, int64_t au,
+                                                   int32_t lu, uint64_t du, int64_t av, int32_t lv, uint64_t dv,
+                                                   uint32_t u, int32_t& below) {
+  int64_t bu = au + RC <= nnz ? au : nnz - RC, bv = av + RC <= nnz ? av : nnz - RC;
+  int32_t hu = (int32_t)(au - bu), hv = (int32_t)(av - bv);   // the row's first entry in the window
+  const int32_t *cpu = col + bu, *wpu = w + bu, *cpv = col + bv, *wpv = w + bv;
+  uint32_t cu[RC], cv[RC], wu[RC], wv[RC];
+#pragma unroll
+  for (int k = 0; k < RC; k++) {
+    cu[k] = (uint32_t)cpu[k];
+    wu[k] = (uint32_t)wpu[k];
+    cv[k] = (uint32_t)cpv[k];
+    wv[k] = (uint32_t)wpv[k];
+  }
+  below = 0;
+#pragma unroll
+  for (int k = 0; k < RC; k++) {
+    cu[k] = (uint32_t)(k - hu) < (uint32_t)lu ? cu[k] : 0xFFFFFFFFu;
+    cv[k] = (uint32_t)(k - hv) < (uint32_t)lv ? cv[k] : 0xFFFFFFFEu;
+    below += cv[k] < u ? 1 : 0;
+  }
+  uint64_t M = 0;
+#pragma unroll
+  for (int p = 0; p < RC; p++) {
+    uint32_t mw = 0;   // weight of cu[p] in row v (0: absent)
+#pragma unroll
+    for (int q = 0; q < RC; q++) mw = cu[p] == cv[q] ? wv[q] : mw;
+    M += umin64(wmul<NARROW>(wu[p], dv), wmul<NARROW>(mw, du));
+  }
+  return M;
+}
+
 // floor(N * 2^b / D) for N < 2^63, D < 2^62, b <= 61 (the result is below 2^62);
 // exact says whether the division left no remainder (then two edges with the
 // same K have exactly the same score).
@@ -272,6 +324,25 @@ __device__ __forceinline__ uint64_t fixed_key(uint64_t N, uint64_t D, int b, boo
   unsigned __int128 num = (unsigned __int128)N << b;
   uint64_t q = (uint64_t)(num / D);
   exact = (unsigned __int128)q * D == num;
+  return q;
+}
+
+// The same for b <= 50: the quotient is below 2^51, so its double-precision
+// estimate (three correctly rounded steps, relative error under 2^-51) is
+// within one of the floor, and one exact step on the remainder
+// N 2^b - q D (in (-D, 2D), so exact modulo 2^64) corrects it.
+__device__ __forceinline__ uint64_t fixed_key_fast(uint64_t N, uint64_t D, int b, bool& exact) {
+  double x = (double)N / (double)D * (double)(1ull << b);
+  uint64_t q = (uint64_t)x;
+  int64_t r = (int64_t)((N << b) - q * D);
+  if (r < 0) {
+    q--;
+    r += (int64_t)D;
+  } else if (r >= (int64_t)D) {
+    q++;
+    r -= (int64_t)D;
+  }
+  exact = r == 0;
   return q;
 }
 

@@ -36,6 +36,7 @@ void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W, bool fp) {
   W.degpart = A.take<uint64_t>(n / DEG_ROWS + 2);
   W.lc = A.take<int32_t>(n);
   W.uptr = A.take<int64_t>(n + 1);
+  W.trow = A.take<int32_t>(m / SCORE_TILE + 2);
   W.P = A.take<uint64_t>(m);
   W.Pc = A.take<uint64_t>(nnz);
   W.samples = A.take<uint64_t>(m / 64 + 2);
@@ -103,7 +104,7 @@ __global__ void __launch_bounds__(BS)
              int64_t* __restrict__ uptr, uint64_t* __restrict__ bestA,
              uint64_t* __restrict__ bestB, int32_t* __restrict__ parent, int32_t* __restrict__ cc,
              uint64_t* __restrict__ part, int32_t* __restrict__ htab, unsigned long long* info,
-             TileScan ts) {
+             TileScan ts, int32_t* __restrict__ trow) {
   __shared__ int stmp[BS / WAVE];
   __shared__ int64_t stmp64[BS / WAVE];
   __shared__ int64_t sbase;
@@ -194,7 +195,14 @@ __global__ void __launch_bounds__(BS)
 #pragma unroll
     for (int i = 0; i < DEG_PER; i++) {
       int64_t u = base + i * BS + tid;
-      if (u < g.n) uptr[u] = sbase + pre[i];
+      if (u < g.n) {
+        int64_t e = sbase + pre[i];
+        uptr[u] = e;
+        // the score tiles whose first edge lies in this row (the row that a
+        // search of uptr for that edge would find)
+        for (int64_t t = (e + SCORE_TILE - 1) / SCORE_TILE; t * SCORE_TILE < e + ucnt[i]; t++)
+          trow[t] = (int32_t)u;
+      }
     }
   }
   // rows longer than DEG_SHORT: the whole block sums each of them, except
@@ -1646,7 +1654,7 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
     {
       TimedScope ts(ctx, "degree", (double)n);
       hipLaunchKernelGGL(k_degree, dim3(nb), dim3(BS), 0, st, g, W.deg, W.lc, W.uptr, W.bestA, W.bestB,
-                         W.parent, W.root, W.degpart, W.htab, info, next_scan(ctx, W));
+                         W.parent, W.root, W.degpart, W.htab, info, next_scan(ctx, W), W.trow);
     }
     TimedScope ts(ctx, "degree_total", (double)nb);
     // (with the long rows' position maps for the scores, when rows can be long)

@@ -268,6 +268,37 @@ def test_edge_cases(P):
     torch.cuda.synchronize()
 
 
+def _tile_boundary_graph(seed=21):
+    # a row of 900 upper entries (it spans a boundary of the score's
+    # 768-edge tiles), a run of isolated nodes, then a sparse random part in
+    # which every seventh node is isolated: many tiles start inside long
+    # rows or after rows without upper entries
+    rng = np.random.default_rng(seed)
+    n = 6000
+    us = [np.zeros(900, np.int64)]
+    vs = [np.arange(1, 901)]
+    pool = np.array([x for x in range(2000, n) if x % 7])
+    a = rng.choice(pool, 20000)
+    b = rng.choice(pool, 20000)
+    keep = a != b
+    us.append(a[keep])
+    vs.append(b[keep])
+    u = np.concatenate(us)
+    v = np.concatenate(vs)
+    lo, hi = np.minimum(u, v), np.maximum(u, v)
+    pairs = np.unique(lo * n + hi)
+    w = rng.integers(1, 9, len(pairs)).astype(np.int32)
+    return from_edges(n, (pairs // n).astype(np.int64), (pairs % n).astype(np.int64), w)
+
+
+def test_tiles_across_long_and_empty_rows(P):
+    g = _tile_boundary_graph()
+    # every node of the connected part but one merges away at most; isolated
+    # nodes stay, so aim well above the number of components
+    check_level(P, g, g.n - 1500, "tile boundaries in long and empty rows")
+    h, want, _ = check_hierarchy(P, g, g.n - 2500, 0, "tile boundaries, halving")
+
+
 def test_deterministic_reruns(P):
     g = trimesh(100, ("uniform", 1, 8), seed=12)
     dg = P.DeviceGraph.from_host(g)
