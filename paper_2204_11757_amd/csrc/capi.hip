@@ -266,20 +266,21 @@ static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* clus
     R.nnz_c = g->nnz;
     R.maxcl = 1;
   } else {
-    rc = contract_level(ctx, L, cluster_of, R.n_c, out, W, R, seg);
+    // (the level's integer degree pass left the entry tiles' first rows)
+    rc = contract_level(ctx, L, cluster_of, R.n_c, out, W, R, seg, W.ptrow);
     if (rc == SPC_REDO_SPEC) {
       // the forest needed more than its first batch: the level again, waiting
       R = LevelResult();
       rc = select_level(ctx, L, t, cluster_of, W, R, nullptr, seg, defer, false, false);
       if (rc) return rc;
-      rc = contract_level(ctx, L, cluster_of, R.n_c, out, W, R, seg);
+      rc = contract_level(ctx, L, cluster_of, R.n_c, out, W, R, seg, W.ptrow);
     }
     if (rc == SPC_REDO_RANK) {
       // a guarded key decision failed: the level again with rank keys
       R = LevelResult();
       rc = select_level(ctx, L, t, cluster_of, W, R, nullptr, seg, false, true);
       if (rc) return rc;
-      rc = contract_level(ctx, L, cluster_of, R.n_c, out, W, R, seg);
+      rc = contract_level(ctx, L, cluster_of, R.n_c, out, W, R, seg, W.ptrow);
     }
     if (rc) return rc;
   }

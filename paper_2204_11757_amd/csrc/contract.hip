@@ -213,14 +213,15 @@ __global__ void __launch_bounds__(CM_BS)
 // search, renumbered per XCD so that a tile's neighbours share its L2) write
 // (c(y) << 32) | w at gptr[c(x)] + off[x] + 1 + (j - rp[x]); the blocks past
 // the tiles write the member records, RM nodes per block.
-constexpr int RT = 2048;
+constexpr int RT = ENTRY_TILE;
 constexpr int RT_BS = 256;
 constexpr int RT_PER = RT / RT_BS;
 constexpr int RM = 2048;
 
 __global__ void __launch_bounds__(RT_BS)
     k_record_scatter(LevelIn g, const int32_t* __restrict__ c, const int64_t* __restrict__ gptr,
-                     const int64_t* __restrict__ off, uint64_t* __restrict__ rec, int tiles) {
+                     const int64_t* __restrict__ off, uint64_t* __restrict__ rec, int tiles,
+                     const int32_t* __restrict__ ptrow) {
   __shared__ int32_t srow[Lbs<RT, RT_BS>::SIZE];
   __shared__ int64_t sh[2];
   __shared__ int32_t stmp[RT_BS / WAVE];
@@ -237,8 +238,15 @@ __global__ void __launch_bounds__(RT_BS)
     }
     return;
   }
-  int64_t p0 = xcd_tile(blockIdx.x, tiles) * RT;
-  lbs_tile<RT, RT_BS>(g.rp, g.n, p0, srow, sh, stmp);
+  int64_t t = xcd_tile(blockIdx.x, tiles);
+  int64_t p0 = t * RT;
+  if (ptrow) {
+    // the tile's first row from the degree pass (uniform over the block)
+    int64_t r1 = t + 1 < tiles ? ptrow[t + 1] : g.n - 1;
+    lbs_fill<RT, RT_BS>(g.rp, ptrow[t], r1, p0, srow, stmp);
+  } else {
+    lbs_tile<RT, RT_BS>(g.rp, g.n, p0, srow, sh, stmp);
+  }
   int32_t xr[RT_PER], yr[RT_PER];
   uint32_t wr[RT_PER];
   int64_t pr[RT_PER];
@@ -1046,7 +1054,8 @@ static int rowptr_and_read(spc_ctx* ctx, const LevelWork& W, spc_graph_out* out,
 constexpr int64_t H_DEV = 4;
 
 int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c,
-                   spc_graph_out* out, LevelWork& W, LevelResult& R, const Segments* seg) {
+                   spc_graph_out* out, LevelWork& W, LevelResult& R, const Segments* seg,
+                   const int32_t* ptrow) {
   hipStream_t st = ctx->stream;
   int64_t n = g.n;
   int64_t* hinfo = ctx->h_pinned;
@@ -1069,7 +1078,7 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
     if (rc) return rc;
     int tiles = g.nnz > 0 ? grid_for(g.nnz, RT) : 0;
     hipLaunchKernelGGL(k_record_scatter, dim3(tiles + grid_for(n, RM)), dim3(RT_BS), 0, st, g, c, W.gptr, off,
-                       W.temp, tiles);
+                       W.temp, tiles, ptrow);
     SPC_LAUNCH_CHECK(ctx, "record_scatter");
   }
   {

@@ -42,6 +42,8 @@ constexpr int HUGE_T = 1024;
 constexpr int H_MAX = 4;
 // edges per tile of the score kernel (three per thread)
 constexpr int SCORE_TILE = 768;
+// CSR entries per tile of the row pass and of the contraction's record scatter
+constexpr int ENTRY_TILE = 2048;
 
 // Device view of an integer-path input graph.
 struct LevelIn {
@@ -172,6 +174,8 @@ struct LevelWork {
   int32_t* lc;               // [n]  entries with col < row
   int64_t* uptr;             // [n+1] upper-edge prefix (edge ids)
   int32_t* trow;             // [m / SCORE_TILE + 2] row holding each score tile's first edge
+  int32_t* ptrow;            // [nnz / ENTRY_TILE + 2] row holding each entry tile's first entry
+                             // (both written by the integer degree pass)
   uint64_t* P;               // [m]  order key per edge (sorted-rank order)
   uint64_t* Pc;              // [nnz] order key per CSR entry (both directions)
   uint64_t* samples;         // [m/64 + 2], keys of edges 0, s, 2s, ... (s = 2^sample_shift(m))
@@ -333,7 +337,10 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
 int finish_select(spc_ctx* ctx, LevelResult& R, int64_t t, bool rank, bool fp, const Segments* seg);
 
 // Step A5: contraction of Definition 1 into caller buffers.
+// ptrow: the entry tiles' first rows of g (W.ptrow after the integer degree
+// pass on g), or null to search for them.
 int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* cluster_of, int64_t n_c,
-                   spc_graph_out* out, LevelWork& W, LevelResult& R, const Segments* seg = nullptr);
+                   spc_graph_out* out, LevelWork& W, LevelResult& R, const Segments* seg = nullptr,
+                   const int32_t* ptrow = nullptr);
 
 }  // namespace spc

@@ -37,6 +37,7 @@ void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W, bool fp) {
   W.lc = A.take<int32_t>(n);
   W.uptr = A.take<int64_t>(n + 1);
   W.trow = A.take<int32_t>(m / SCORE_TILE + 2);
+  W.ptrow = A.take<int32_t>(nnz / ENTRY_TILE + 2);
   W.P = A.take<uint64_t>(m);
   W.Pc = A.take<uint64_t>(nnz);
   W.samples = A.take<uint64_t>(m / 64 + 2);
@@ -104,7 +105,7 @@ __global__ void __launch_bounds__(BS)
              int64_t* __restrict__ uptr, uint64_t* __restrict__ bestA,
              uint64_t* __restrict__ bestB, int32_t* __restrict__ parent, int32_t* __restrict__ cc,
              uint64_t* __restrict__ part, int32_t* __restrict__ htab, unsigned long long* info,
-             TileScan ts, int32_t* __restrict__ trow) {
+             TileScan ts, int32_t* __restrict__ trow, int32_t* __restrict__ ptrow) {
   __shared__ int stmp[BS / WAVE];
   __shared__ int64_t stmp64[BS / WAVE];
   __shared__ int64_t sbase;
@@ -202,6 +203,9 @@ __global__ void __launch_bounds__(BS)
         // search of uptr for that edge would find)
         for (int64_t t = (e + SCORE_TILE - 1) / SCORE_TILE; t * SCORE_TILE < e + ucnt[i]; t++)
           trow[t] = (int32_t)u;
+        // and the entry tiles whose first entry lies in this row
+        for (int64_t t = (rs[i] + ENTRY_TILE - 1) / ENTRY_TILE; t * ENTRY_TILE < re[i]; t++)
+          ptrow[t] = (int32_t)u;
       }
     }
   }
@@ -342,14 +346,15 @@ __global__ void __launch_bounds__(SP_BS)
 //  - upper entries (u < v) with lo < key <= hi form the live list (lo is
 //    absent for the first band); its roots are still the original endpoints,
 //    so the list's endpoint array is not written (readers take lr for it).
-constexpr int TILE_R = 2048;
+constexpr int TILE_R = ENTRY_TILE;
 constexpr int R_PER = TILE_R / BS;
 
 __global__ void __launch_bounds__(BS)
     k_rowpass(LevelIn g, const int32_t* __restrict__ lc, const uint64_t* __restrict__ Pc,
               const unsigned long long* thr_lo, const unsigned long long* thr_hi, int use_lo,
               int do_best, uint64_t* best, uint64_t* __restrict__ lr, uint64_t* __restrict__ lp,
-              unsigned long long* cnt, unsigned long long* cnt_copy, TileScan ts) {
+              unsigned long long* cnt, unsigned long long* cnt_copy, TileScan ts,
+              const int32_t* __restrict__ ptrow) {
   using L = Lbs<TILE_R, BS>;
   static_assert(R_PER == 8, "one 8-byte flag word per thread");
   __shared__ int32_t srow[L::SIZE];
@@ -362,7 +367,14 @@ __global__ void __launch_bounds__(BS)
   int64_t j0 = (int64_t)blockIdx.x * TILE_R;
   int64_t nnz = g.nnz;
   uint64_t tlo = use_lo ? *thr_lo : 0, thi = *thr_hi;   // issued early, used at the end
-  lbs_tile<TILE_R, BS>(g.rp, g.n, j0, srow, sh, stmp);
+  if (ptrow) {
+    // the tile's first row from the degree pass (uniform over the block)
+    int64_t t = blockIdx.x;
+    int64_t r1 = t + 1 < (int64_t)gridDim.x ? ptrow[t + 1] : g.n - 1;
+    lbs_fill<TILE_R, BS>(g.rp, ptrow[t], r1, j0, srow, stmp);
+  } else {
+    lbs_tile<TILE_R, BS>(g.rp, g.n, j0, srow, sh, stmp);
+  }
   int tid = threadIdx.x;
   // coalesced: key, and from the column the upper / row-head flags
 #pragma unroll
@@ -1560,7 +1572,8 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
       TimedScope ts(ctx, "rowpass", (double)g.nnz);
       hipLaunchKernelGGL(k_rowpass, dim3(grid_for(g.nnz, TILE_R)), dim3(BS), 0, st, g, W.lc, W.Pc,
                          thr_lo, thr_hi, band > 0 ? 1 : 0, band == 0 ? 1 : 0, W.bestA, W.lr[0],
-                         W.lp[0], &info[I_LIVE0], &info[I_CAND], next_scan(ctx, W));
+                         W.lp[0], &info[I_LIVE0], &info[I_CAND], next_scan(ctx, W),
+                         gf ? (const int32_t*)nullptr : W.ptrow);   // (the integer degree pass wrote it)
     }
     SPC_LAUNCH_CHECK(ctx, "rowpass");
     int64_t live0 = 0;
@@ -1654,7 +1667,7 @@ int select_level(spc_ctx* ctx, const LevelIn& g, int64_t t, int32_t* cluster_of,
     {
       TimedScope ts(ctx, "degree", (double)n);
       hipLaunchKernelGGL(k_degree, dim3(nb), dim3(BS), 0, st, g, W.deg, W.lc, W.uptr, W.bestA, W.bestB,
-                         W.parent, W.root, W.degpart, W.htab, info, next_scan(ctx, W), W.trow);
+                         W.parent, W.root, W.degpart, W.htab, info, next_scan(ctx, W), W.trow, W.ptrow);
     }
     TimedScope ts(ctx, "degree_total", (double)nb);
     // (with the long rows' position maps for the scores, when rows can be long)
