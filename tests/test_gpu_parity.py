@@ -299,6 +299,30 @@ def test_tiles_across_long_and_empty_rows(P):
     h, want, _ = check_hierarchy(P, g, g.n - 2500, 0, "tile boundaries, halving")
 
 
+def _heavy_edge_graph():
+    # a 30x30 triangle mesh whose edges at three nodes weigh 2^23: degrees
+    # reach 2^26 (the score's products then take 64-bit multiplies) while
+    # the total weight stays far below 2^31
+    g = trimesh(30, ("uniform", 1, 8), seed=11)
+    rp = np.asarray(g.row_ptr)
+    col = np.asarray(g.col, np.int64)
+    w = np.asarray(g.w, np.int64)
+    rows = np.repeat(np.arange(g.n), np.diff(rp))
+    up = col > rows
+    u, v, ww = rows[up], col[up], w[up].copy()
+    ww[np.isin(u, [100, 437, 781]) | np.isin(v, [100, 437, 781])] = 1 << 23
+    return from_edges(g.n, u, v, ww.astype(np.int32))
+
+
+def test_degrees_above_2_24(P):
+    g = _heavy_edge_graph()
+    rp = np.asarray(g.row_ptr)
+    assert np.add.reduceat(np.asarray(g.w, np.int64), rp[:-1]).max() >= 1 << 24
+    assert g.m > 1 << 11   # (keys from the corrected double-precision quotient)
+    check_level(P, g, g.n // 2, "degrees above 2^24")
+    check_hierarchy(P, g, g.n // 16, 0, "degrees above 2^24, halving")
+
+
 def test_deterministic_reruns(P):
     g = trimesh(100, ("uniform", 1, 8), seed=12)
     dg = P.DeviceGraph.from_host(g)
