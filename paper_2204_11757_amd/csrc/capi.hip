@@ -93,8 +93,8 @@ uint32_t scan_state_reserve(spc_ctx* ctx, int64_t words) {
       }
       ctx->scan_cap = cap;
     }
-    if (hipMemsetAsync(ctx->scan_state, 0, sizeof(uint64_t) * (size_t)ctx->scan_cap, ctx->stream) !=
-        hipSuccess) {
+    launch_zero(ctx, ctx->scan_state, sizeof(uint64_t) * (size_t)ctx->scan_cap);
+    if (hipGetLastError() != hipSuccess) {
       set_error(ctx, SPC_EHIP, "scan state clear failed");
       return 0;
     }

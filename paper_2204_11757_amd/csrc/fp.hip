@@ -542,8 +542,8 @@ int contract_level_fp(spc_ctx* ctx, const LevelInF& g, const int32_t* c, int64_t
   if (rc) return rc;
   int64_t nnz_c = R.nnz_c;
   TimedScope ts(ctx, "contract_fp_sums", (double)g.nnz);
-  SPC_HIP(ctx, hipMemsetAsync(W.acc, 0, sizeof(uint64_t) * (size_t)(FP_LIMBS * std::max<int64_t>(nnz_c, 1)), st));
-  SPC_HIP(ctx, hipMemsetAsync(W.selfacc, 0, sizeof(uint64_t) * (size_t)(FP_LIMBS * n_c), st));
+  launch_zero(ctx, W.acc, sizeof(uint64_t) * (size_t)(FP_LIMBS * std::max<int64_t>(nnz_c, 1)));
+  launch_zero(ctx, W.selfacc, sizeof(uint64_t) * (size_t)(FP_LIMBS * n_c));
   if (g.nnz > 0)
     hipLaunchKernelGGL(k_fp_scatter, dim3(grid_for(g.nnz, SC_T)), dim3(BS), 0, st, g, c, out->row_ptr,
                        out->col, nnz_c, W.emap, W.acc, W.selfacc, n_c, W.info);

@@ -252,7 +252,7 @@ void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W, bool fp = false)
 // array; the array is zeroed again when the epochs run out.
 inline TileScan next_scan(spc_ctx* ctx, const LevelWork& W, int64_t off = 0) {
   if (ctx->lb_epoch >= LB_MAX_EPOCH) {
-    (void)hipMemsetAsync(W.lbstate, 0, sizeof(uint64_t) * (size_t)ctx->lb_words, ctx->stream);
+    launch_zero(ctx, W.lbstate, sizeof(uint64_t) * (size_t)ctx->lb_words);
     ctx->lb_epoch = 0;
   }
   return TileScan{W.lbstate + off, ++ctx->lb_epoch, &W.info[I_LBERR]};

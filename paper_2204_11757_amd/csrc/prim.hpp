@@ -290,6 +290,11 @@ __global__ void __launch_bounds__(SCAN_BS)
 // returns a fresh epoch; 0 on allocation failure.
 uint32_t scan_state_reserve(spc_ctx* ctx, int64_t words);
 
+// Zeroes `bytes` (a multiple of 4) at device address p with a kernel on the
+// context's stream rather than a memset, so that a caller who captures the
+// library's launches into a graph gets kernel nodes only.
+void launch_zero(spc_ctx* ctx, void* p, size_t bytes);
+
 // Host wrapper.  `partial` is unused (kept for callers' scratch layout).
 // in may equal out (each tile reads all of its items before writing).
 template <typename T>
@@ -297,7 +302,8 @@ int exclusive_scan(spc_ctx* ctx, const T* in, T* out, int64_t n, T* partial,
                    ScanReadback rb = ScanReadback{nullptr, 0, nullptr, nullptr, 0}) {
   (void)partial;
   if (n <= 0) {
-    SPC_HIP(ctx, hipMemsetAsync(out, 0, sizeof(T), ctx->stream));
+    launch_zero(ctx, out, sizeof(T));
+    SPC_LAUNCH_CHECK(ctx, "exclusive_scan (empty)");
     return SPC_OK;
   }
   int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
@@ -313,8 +319,9 @@ int exclusive_scan(spc_ctx* ctx, const T* in, T* out, int64_t n, T* partial,
 template <typename T1, typename T2>
 int exclusive_scan2(spc_ctx* ctx, const T1* in1, T1* out1, const T2* in2, T2* out2, int64_t n) {
   if (n <= 0) {
-    SPC_HIP(ctx, hipMemsetAsync(out1, 0, sizeof(T1), ctx->stream));
-    SPC_HIP(ctx, hipMemsetAsync(out2, 0, sizeof(T2), ctx->stream));
+    launch_zero(ctx, out1, sizeof(T1));
+    launch_zero(ctx, out2, sizeof(T2));
+    SPC_LAUNCH_CHECK(ctx, "exclusive_scan2 (empty)");
     return SPC_OK;
   }
   int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;

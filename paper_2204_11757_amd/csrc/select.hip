@@ -1349,6 +1349,19 @@ __global__ void k_fill_u64(uint64_t* __restrict__ a, int64_t n, uint64_t v) {
   if (i < n) a[i] = v;
 }
 
+__global__ void k_zero32(uint32_t* __restrict__ a, int64_t n) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) a[i] = 0u;
+}
+
+void launch_zero(spc_ctx* ctx, void* p, size_t bytes) {
+  int64_t n = (int64_t)(bytes / sizeof(uint32_t));
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_zero32, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, ctx->stream,
+                     (uint32_t*)p, n);
+}
+
 // a band threshold without a selection ("everything")
 __global__ void k_thr_all(ThrSpec ts) { band_threshold(ts, 0, true); }
 

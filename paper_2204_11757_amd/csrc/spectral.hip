@@ -309,7 +309,7 @@ static int spectral_t(spc_ctx* ctx, const CoarseView& g, const int32_t* cmap_in,
     uint64_t* sorted = nullptr;
     rc = merge_sort<uint64_t, LessU64>(ctx, ka, kb, n0, LessU64(), &sorted);
     if (rc) return rc;
-    SPC_HIP(ctx, hipMemsetAsync(mptr, 0, sizeof(int32_t) * (nc + 1), st));
+    launch_zero(ctx, mptr, sizeof(int32_t) * (nc + 1));
     hipLaunchKernelGGL(k_count_clusters, dim3(grid_for(n0, 256)), dim3(256), 0, st, cmap, n0, mptr);
     rc = exclusive_scan<int32_t>(ctx, mptr, mptr, nc, nullptr);
     if (rc) return rc;
