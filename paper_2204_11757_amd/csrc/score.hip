@@ -134,7 +134,7 @@ __device__ __forceinline__ void score_tile(const LevelIn& g, const uint64_t* __r
     live[i] = e0 + k < m;
     eu[i] = live[i] ? srow[L::at(k)] : 0;
   }
-  // round 1: row u
+  // first loads: row u
 #pragma unroll
   for (int i = 0; i < EPT; i++) {
     int32_t u = eu[i];
@@ -144,14 +144,14 @@ __device__ __forceinline__ void score_tile(const LevelIn& g, const uint64_t* __r
     du[i] = deg[u];
     su[i] = g.self ? (uint64_t)g.self[u] : 0;
   }
-  // round 2: the edge's entry
+  // second loads: the edge's entry
 #pragma unroll
   for (int i = 0; i < EPT; i++) {
     ej[i] = live[i] ? ej[i] : 0;   // (entry 0 exists: the tile holds an edge)
     ev[i] = g.col[ej[i]];
     ew[i] = (uint32_t)g.w[ej[i]];
   }
-  // round 3: row v, and the diagonal terms x = u and x = v of the sum
+  // third loads: row v, and the diagonal terms x = u and x = v of the sum
 #pragma unroll
   for (int i = 0; i < EPT; i++) {
     int32_t v = ev[i];
@@ -173,7 +173,7 @@ __device__ __forceinline__ void score_tile(const LevelIn& g, const uint64_t* __r
     // (a live edge's rows both hold it, so neither is empty)
     shrt |= (live[i] && lu[i] <= RC && lv[i] <= RC && g.nnz >= RC ? 1u : 0u) << i;
   }
-  // round 4: the rows of the short edges, one edge after the other
+  // then the rows of the short edges, one edge after the other
 #pragma unroll
   for (int i = 0; i < EPT; i++) {
     if (shrt >> i & 1u) {
