@@ -119,7 +119,7 @@ __device__ __forceinline__ void score_tile(const LevelIn& g, const uint64_t* __r
                                            uint64_t* __restrict__ samples, KeyND* __restrict__ keys,
                                            int write_keys, uint64_t* __restrict__ kexact, int sshift,
                                            const int32_t* srow, int64_t e0, const int32_t (&hrow)[H_MAX],
-                                           uint64_t& dmx) {
+                                           uint64_t& dmx, uint4* sdesc, int* sfb, unsigned long long* sbits) {
   using L = Lbs<TILE_S, BS>;
   int tid = threadIdx.x;
   int32_t eu[EPT], ev[EPT];
@@ -187,29 +187,50 @@ __device__ __forceinline__ void score_tile(const LevelIn& g, const uint64_t* __r
       exm |= (ex ? 1u : 0u) << i;
     }
   }
-  // the other live edges (a row longer than RC), one at a time: a
-  // wavefront runs this loop only for the slots where one of its lanes has
-  // such an edge
-#pragma unroll 1
-  for (int i = 0; i < EPT; i++) {
-    if (live[i] && !(shrt >> i & 1u)) {
-      uint64_t N, D;
-      int64_t jm;
-      edge_score(g, deg, lc, eu[i], ev[i], (int32_t)ew[i], N, D, jm);
-      dmx = D > dmx ? D : dmx;
-      bool ex = emit_key<MODE>(e0 + tid + i * BS, ej[i], jm, N, D, c, ebits, Pc, samples, keys, write_keys,
-                               sshift);
-      exm |= (ex ? 1u : 0u) << i;
-    }
-  }
   if (MODE == 0) {
-    // the exactness map: a wavefront's 64 consecutive edges make one word
+    // the short edges' exactness bits: word (wavefront, slot) of the tile's map
 #pragma unroll
     for (int i = 0; i < EPT; i++) {
       uint64_t bits = __ballot(exm >> i & 1u);
-      int64_t ew0 = e0 + (tid & ~(WAVE - 1)) + i * BS;
-      if (lane_id() == 0 && ew0 < m) kexact[ew0 >> 6] = bits;
+      if (lane_id() == 0) sbits[tid / WAVE + i * (BS / WAVE)] = bits;
     }
+  }
+  // The block's other live edges (a row longer than RC) are compacted into
+  // LDS (endpoints, weight, place in the tile) and then taken by all of its
+  // threads in turn: a wavefront would otherwise run the long-row path once
+  // per slot that holds one, with most of its lanes idle.
+#pragma unroll
+  for (int i = 0; i < EPT; i++) {
+    bool take = live[i] && !(shrt >> i & 1u);
+    uint64_t mask = __ballot(take);
+    if (mask == 0) continue;   // (uniform over the wavefront)
+    int lead = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane_id() == lead) base = atomicAdd(sfb, (int)__popcll(mask));
+    base = __shfl(base, lead);
+    if (take)
+      sdesc[base + (int)__popcll(mask & ((1ull << lane_id()) - 1))] =
+          make_uint4((uint32_t)eu[i], (uint32_t)ev[i], ew[i], (uint32_t)(tid + i * BS));
+  }
+  __syncthreads();
+  int nf = *sfb;
+  for (int k = tid; k < nf; k += BS) {
+    uint4 d = sdesc[k];
+    int32_t u = (int32_t)d.x, v = (int32_t)d.y;
+    int64_t e = e0 + d.w;
+    int64_t j = g.rp[u] + lc[u] + (e - uptr[u]);   // entry (u -> v)
+    uint64_t N, D;
+    int64_t jm;
+    edge_score(g, deg, lc, u, v, (int32_t)d.z, N, D, jm);
+    dmx = D > dmx ? D : dmx;
+    bool ex = emit_key<MODE>(e, j, jm, N, D, c, ebits, Pc, samples, keys, write_keys, sshift);
+    if (MODE == 0 && ex) atomicOr(&sbits[d.w / WAVE], 1ull << (d.w % WAVE));
+  }
+  __syncthreads();
+  if (MODE == 0 && tid < TILE_S / WAVE) {
+    // the exactness map: 64 consecutive edges make one word
+    int64_t ew0 = e0 + (int64_t)tid * WAVE;
+    if (ew0 < m) kexact[ew0 >> 6] = sbits[tid];
   }
 }
 
@@ -234,6 +255,9 @@ __global__ void __launch_bounds__(BS, 4)
   __shared__ int32_t srow[Lbs<TILE_S, BS>::SIZE];
   __shared__ int32_t stmp[BS / WAVE];
   __shared__ uint64_t sred[BS / WAVE];
+  __shared__ uint4 sdesc[TILE_S];                      // the tile's long-row edges
+  __shared__ unsigned long long sbits[TILE_S / WAVE];  // the tile's exactness map
+  __shared__ int sfb;                                  // its long-row edges
   if ((int)blockIdx.x >= tiles) {
     // the blocks past the edge tiles score the mapped long rows' edges
     // (dispatched last, they fill the tail of the launch)
@@ -244,6 +268,7 @@ __global__ void __launch_bounds__(BS, 4)
   int64_t t = xcd_tile(blockIdx.x, tiles);
   int64_t e0 = t * TILE_S;
   int64_t r1 = t + 1 < tiles ? trow[t + 1] : g.n - 1;
+  if (threadIdx.x == 0) sfb = 0;   // (lbs_fill synchronises the block before it is used)
   lbs_fill<TILE_S, BS>(uptr, trow[t], r1, e0, srow, stmp);
   uint64_t dmx = 0;
   // rows with a position map (uniform over the block)
@@ -254,10 +279,10 @@ __global__ void __launch_bounds__(BS, 4)
   for (int s = 0; s < H_MAX; s++) hrow[s] = s < hc ? htab[s] : -1;
   if (dmax < (1ull << 24))
     score_tile<MODE, true>(g, deg, lc, uptr, m, c, ebits, Pc, samples, keys, write_keys, kexact, sshift, srow,
-                           e0, hrow, dmx);
+                           e0, hrow, dmx, sdesc, &sfb, sbits);
   else
     score_tile<MODE, false>(g, deg, lc, uptr, m, c, ebits, Pc, samples, keys, write_keys, kexact, sshift, srow,
-                            e0, hrow, dmx);
+                            e0, hrow, dmx, sdesc, &sfb, sbits);
   dmx = wave_max(dmx);
   if (lane_id() == 0) sred[threadIdx.x / WAVE] = dmx;
   __syncthreads();
