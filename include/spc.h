@@ -134,6 +134,10 @@ int spc_set_allocator(spc_ctx* ctx, void* (*alloc)(size_t, void*), void (*free_)
  *   "bad_select_guess" 1: give the merge cutoff's selection key bounds above
  *                 every forest key, so that the cutoff lies below them and the
  *                 selection starts over (its fallback path).
+ *   "batch_band_short" 1: in a batch, each graph's merge-cutoff candidate
+ *                 band aims at a quarter of that graph's merges, so that
+ *                 bands fall short and the level is redone over every edge
+ *                 (the batched selection's fallback path).
  *   "scan_flag"   1: the next level (once) finds the error flag of the
  *                 context's scan chain raised, as after a look-back wait that
  *                 gave up, and fails with SPC_EINVAL; later levels start with

@@ -192,6 +192,94 @@ __global__ void __launch_bounds__(SEL_BS)
   }
 }
 
+// Each node's graph: one block per graph writes its node range.
+__global__ void k_seg_gid(const int64_t* __restrict__ off, int32_t* __restrict__ gid) {
+  int64_t lo = off[blockIdx.x], hi = off[blockIdx.x + 1];
+  for (int64_t u = lo + threadIdx.x; u < hi; u += blockDim.x) gid[u] = (int32_t)blockIdx.x;
+}
+
+// One block per graph: its band threshold.  The graph's CSR entries hold
+// each of its edges' keys twice (both directions), so SB_S entries taken at
+// even spacing sample the key distribution of its edges; sorted in LDS, the
+// sample at the band's share (plus 5 % and two samples) gives the threshold.
+// The band aims at 2 k + 64 edges for k merges: on triangle meshes of unit
+// weight a graph's k-th forest edge lies at up to about 1.7 k in key order
+// (the first two halving levels; less later), and a band that falls short
+// costs the level a second selection over every edge.
+// Graphs without merges take no candidates; graphs whose band would hold
+// all of their edges take all of them.  (shrink, a test option: bands aim at
+// a quarter of the merges and are not extended over ties, so that they fall
+// short.)
+constexpr int SB_S = 2048;
+constexpr int SB_BS = 256;
+
+__global__ void __launch_bounds__(SB_BS)
+    k_seg_band(const int64_t* __restrict__ off, const int64_t* __restrict__ kseg, LevelIn g,
+               const int64_t* __restrict__ uptr, const uint64_t* __restrict__ Pc, const unsigned long long* info,
+               int ebits, int shrink, uint64_t* __restrict__ thrg) {
+  __shared__ uint64_t sb[SB_S];
+  int t = threadIdx.x;
+  int64_t gi = blockIdx.x;
+  int64_t lo = off[gi], hi = off[gi + 1];
+  int64_t kk = kseg[gi];
+  int64_t a = g.rp[lo], b = g.rp[hi];
+  int64_t nnz_g = b - a, m_g = nnz_g / 2;
+  int64_t target = shrink ? kk / 4 : 2 * kk + 64;
+  if (kk <= 0 || target >= m_g) {   // (uniform over the block)
+    if (t == 0) thrg[gi] = kk <= 0 ? 0ull : KEY_INF;
+    return;
+  }
+  int S = nnz_g < SB_S ? (int)nnz_g : SB_S;
+  for (int i = t; i < SB_S; i += SB_BS) sb[i] = i < S ? Pc[a + (int64_t)i * nnz_g / S] : KEY_INF;
+  __syncthreads();
+  // ascending bitonic sort of the samples
+  for (int k = 2; k <= SB_S; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int p = t; p < SB_S / 2; p += SB_BS) {
+        int i = 2 * j * (p / j) + (p % j);
+        int l = i + j;
+        bool asc = (i & k) == 0;
+        uint64_t x = sb[i], y = sb[l];
+        if (asc ? (y < x) : (x < y)) {
+          sb[i] = y;
+          sb[l] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (t != 0) return;
+  double share = (double)target / (double)m_g * 1.05;
+  int q = (int)(share * (double)S) + 2;
+  if (q >= S) {
+    thrg[gi] = KEY_INF;
+    return;
+  }
+  uint64_t emask = (1ull << ebits) - 1;
+  uint64_t p = sb[q];
+  uint64_t thr = p;
+  if (info[I_GUARD]) {
+    // guarded keys order one K bucket only approximately: all of it
+    thr = p | emask;
+  } else if (!shrink && q >= 16 && (sb[q - 16] >> ebits) == (p >> ebits)) {
+    // inside a tied K bucket, read in edge order (consecutive rows): cover
+    // about 1.1 k rows of the graph
+    double rows = 1.1 * (double)kk * (double)m_g / (double)(hi - lo) + 64.0;
+    int64_t span = rows >= (double)(m_g - 1) ? m_g - 1 : (int64_t)rows;
+    uint64_t tie = (p & ~emask) | (uint64_t)(uptr[lo] + span);
+    thr = tie > thr ? tie : thr;
+  }
+  thrg[gi] = thr;
+}
+
+int seg_bands(spc_ctx* ctx, const LevelIn& g, LevelWork& W, const Segments& seg, int ebits, bool shrink) {
+  hipLaunchKernelGGL(k_seg_gid, dim3((unsigned)seg.G), dim3(256), 0, ctx->stream, seg.off, W.gid);
+  hipLaunchKernelGGL(k_seg_band, dim3((unsigned)seg.G), dim3(SB_BS), 0, ctx->stream, seg.off, seg.k, g, W.uptr,
+                     W.Pc, W.info, ebits, shrink ? 1 : 0, W.thrg);
+  SPC_LAUNCH_CHECK(ctx, "batch bands");
+  return SPC_OK;
+}
+
 int seg_cutoff_union(spc_ctx* ctx, const LevelIn& g, LevelWork& W, const LevelResult& R, const Segments& seg,
                      int ebits, bool rank) {
   hipStream_t st = ctx->stream;

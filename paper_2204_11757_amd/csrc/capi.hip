@@ -232,6 +232,14 @@ static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* clus
   // after it, in one band
   bool spec = defer && (ctx->speculate == 2 || (ctx->speculate == 0 && ctx->spec_ok));
   rc = select_level(ctx, L, t, cluster_of, W, R, fp ? &LF : nullptr, seg, defer, false, spec);
+  if (rc == SPC_REDO_BAND) {
+    // a graph of the batch had fewer forest edges inside its band than
+    // merges: the selection again over every edge
+    R = LevelResult();
+    ctx->seg_full_band = 1;
+    rc = select_level(ctx, L, t, cluster_of, W, R, fp ? &LF : nullptr, seg, defer, false, spec);
+    ctx->seg_full_band = 0;
+  }
   if (rc) return rc;
   if (fp && R.n_c == g->n) {
     if (out->nnz_cap < g->nnz) return set_error(ctx, SPC_ECAPACITY, "nnz_cap too small");
@@ -527,6 +535,7 @@ int spc_set_option(spc_ctx* ctx, const char* name, int64_t value) {
   if (!ctx || !name) return SPC_EINVAL;
   if (!strcmp(name, "rank_order")) ctx->force_rank_mode = value ? 1 : 0;
   else if (!strcmp(name, "full_forest")) ctx->force_full_filter = value ? 1 : 0;
+  else if (!strcmp(name, "batch_band_short")) ctx->seg_band_shrink = value ? 1 : 0;
   else if (!strcmp(name, "timing")) ctx->timing = value ? 1 : 0;
   else if (!strcmp(name, "huge_sort")) ctx->force_huge_sort = value ? 1 : 0;
   else if (!strcmp(name, "redo_rank")) ctx->force_redo_rank = value ? 1 : 0;

@@ -347,6 +347,8 @@ struct spc_ctx {
   // knobs
   int force_rank_mode = 0;   // use the sorted-rank order even when a packed key fits
   int force_full_filter = 0; // run the spanning-forest phase over every edge
+  int seg_full_band = 0;     // a batch's level redone over every edge (a band fell short)
+  int seg_band_shrink = 0;   // test option: batch bands aim at a quarter of the merges
   int force_huge_sort = 0;   // contract huge rows by sorting even when dense accumulators fit
   int force_redo_rank = 0;   // flag every packed-key level as inexact (redone with rank keys)
   int force_bad_guess = 0;   // give the cutoff selection key bounds that some keys lie outside

@@ -176,6 +176,8 @@ struct LevelWork {
   int32_t* trow;             // [m / SCORE_TILE + 2] row holding each score tile's first edge
   int32_t* ptrow;            // [nnz / ENTRY_TILE + 2] row holding each entry tile's first entry
                              // (both written by the integer degree pass)
+  int32_t* gid;              // [n] batch: each node's graph
+  uint64_t* thrg;            // [n] batch: each graph's band threshold (at most n graphs)
   uint64_t* P;               // [m]  order key per edge (sorted-rank order)
   uint64_t* Pc;              // [nnz] order key per CSR entry (both directions)
   uint64_t* samples;         // [m/64 + 2], keys of edges 0, s, 2s, ... (s = 2^sample_shift(m))
@@ -273,6 +275,8 @@ struct LevelResult {
   bool first_batch_complete = false;
   // the selection zeroed the contraction's member counts and gather prefix
   bool contract_zeroed = false;
+  // a batch's forest was built over per-graph bands (not every edge)
+  bool seg_band = false;
 };
 
 // internal return codes (never reach the caller): a guarded key decision
@@ -281,6 +285,9 @@ struct LevelResult {
 // although the host did not wait for it, the level is redone waiting
 constexpr int SPC_REDO_RANK = 1;
 constexpr int SPC_REDO_SPEC = 2;
+// a graph of a batch had fewer forest edges inside its band than merges:
+// the level is redone over every edge
+constexpr int SPC_REDO_BAND = 3;
 
 // A2 and A3 launches (score.hip).  mode 0: packed keys into Pc and the
 // samples (exact records too when the key is not surely exact); mode 1:
@@ -316,6 +323,11 @@ int contract_level_fp(spc_ctx* ctx, const LevelInF& g, const int32_t* cluster_of
 // each graph's first k[i] are joined in `parent` (which must hold the
 // identity); info[I_EPS] receives the largest accepted score, info[I_VIOL]
 // a failed guarded decision, info[I_SEG_SHORT] a graph short of edges.
+// Batch bands: gid[u] = u's graph, and each graph's band threshold: about
+// 2 k_g of its edges (from a sorted sample of its keys; whole K buckets
+// when keys are guarded; a tied bucket is extended to cover about 1.1 k_g
+// rows).  shrink (a test option) aims at k_g / 4 instead.
+int seg_bands(spc_ctx* ctx, const LevelIn& g, LevelWork& W, const Segments& seg, int ebits, bool shrink);
 int seg_cutoff_union(spc_ctx* ctx, const LevelIn& g, LevelWork& W, const LevelResult& R,
                      const Segments& seg, int ebits, bool rank);
 

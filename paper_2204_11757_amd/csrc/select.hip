@@ -38,6 +38,8 @@ void plan_level(Arena& A, int64_t n, int64_t nnz, LevelWork& W, bool fp) {
   W.uptr = A.take<int64_t>(n + 1);
   W.trow = A.take<int32_t>(m / SCORE_TILE + 2);
   W.ptrow = A.take<int32_t>(nnz / ENTRY_TILE + 2);
+  W.gid = A.take<int32_t>(n);
+  W.thrg = A.take<uint64_t>(n);
   W.P = A.take<uint64_t>(m);
   W.Pc = A.take<uint64_t>(nnz);
   W.samples = A.take<uint64_t>(m / 64 + 2);
@@ -354,7 +356,8 @@ __global__ void __launch_bounds__(BS)
               const unsigned long long* thr_lo, const unsigned long long* thr_hi, int use_lo,
               int do_best, uint64_t* best, uint64_t* __restrict__ lr, uint64_t* __restrict__ lp,
               unsigned long long* cnt, unsigned long long* cnt_copy, TileScan ts,
-              const int32_t* __restrict__ ptrow) {
+              const int32_t* __restrict__ ptrow, const int32_t* __restrict__ gid,
+              const uint64_t* __restrict__ thrg) {
   using L = Lbs<TILE_R, BS>;
   static_assert(R_PER == 8, "one 8-byte flag word per thread");
   __shared__ int32_t srow[L::SIZE];
@@ -462,7 +465,9 @@ __global__ void __launch_bounds__(BS)
     int64_t j = cb + i;
     if (j >= nnz) break;
     uint64_t p = kp[i];
-    if ((fl[i] & 1) && p <= thi && (!use_lo || p > tlo)) {
+    // a batch's graphs each have their own band (thrg, by the row's graph)
+    uint64_t th = thrg ? thrg[gid[ku[i]]] : thi;
+    if ((fl[i] & 1) && p <= th && (!use_lo || p > tlo)) {
       keep |= 1u << i;
       nk++;
     }
@@ -1542,9 +1547,13 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
   bool sampled = false;   // a band threshold came from the key samples
   R.candidates = 0;
   for (int band = 0;; band++) {
-    // a batch builds the whole forest in one band (each graph needs its own
-    // count of forest edges)
-    bool all = ctx->force_full_filter || target >= m || band >= 2 || seg != nullptr;
+    // a batch builds its forest in one band: each graph's own (each graph
+    // needs its own count of forest edges), or every edge when a graph's
+    // band fell short
+    bool seg_band = seg && band == 0 && !rank && !gf && !ctx->seg_full_band && !ctx->force_full_filter &&
+                    target < m;
+    bool all = ctx->force_full_filter || target >= m || band >= 2 || (seg && !seg_band);
+    R.seg_band = seg_band;
     int kc = (!rank && band == 0) ? c : 0;   // the first threshold kernel also sets the key mode
     if (band > 0) {
       hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, W.bestA, n, KEY_INF);
@@ -1552,8 +1561,14 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
       // the previous band's upper bound is this band's lower bound
       hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(1), 0, st, thr_lo, thr_hi);
     }
-    if (all) {
+    if (all || seg_band) {
+      // (also the key mode of the level, read by the batch bands)
       hipLaunchKernelGGL(k_thr_all, dim3(1), dim3(1), 0, st, ThrSpec{thr_hi, info, kc, ebits, 0, 0, nullptr, 0});
+      if (seg_band) {
+        TimedScope ts(ctx, "batch_bands", (double)seg->G);
+        int rc = seg_bands(ctx, g, W, *seg, ebits, ctx->seg_band_shrink != 0);
+        if (rc) return rc;
+      }
     } else if (!rank) {
       int sh = sample_shift(m);
       int64_t ns = ((m - 1) >> sh) + 1;
@@ -1586,7 +1601,8 @@ static int order_and_select(spc_ctx* ctx, const LevelIn& g, int64_t t, int64_t k
       hipLaunchKernelGGL(k_rowpass, dim3(grid_for(g.nnz, TILE_R)), dim3(BS), 0, st, g, W.lc, W.Pc,
                          thr_lo, thr_hi, band > 0 ? 1 : 0, band == 0 ? 1 : 0, W.bestA, W.lr[0],
                          W.lp[0], &info[I_LIVE0], &info[I_CAND], next_scan(ctx, W),
-                         gf ? (const int32_t*)nullptr : W.ptrow);   // (the integer degree pass wrote it)
+                         gf ? (const int32_t*)nullptr : W.ptrow,   // (the integer degree pass wrote it)
+                         seg_band ? W.gid : (const int32_t*)nullptr, seg_band ? W.thrg : (const uint64_t*)nullptr);
     }
     SPC_LAUNCH_CHECK(ctx, "rowpass");
     int64_t live0 = 0;
@@ -1805,8 +1821,10 @@ int finish_select(spc_ctx* ctx, LevelResult& R, int64_t t, bool rank, bool fp, c
     return SPC_REDO_RANK;
   }
   if (hinfo[I_LBERR]) return set_error(ctx, SPC_EINVAL, "internal: look-back wait gave up");
-  if (seg && hinfo[I_SEG_SHORT])
+  if (seg && hinfo[I_SEG_SHORT]) {
+    if (R.seg_band) return SPC_REDO_BAND;   // a band, not the graph, may have fallen short
     return set_error(ctx, SPC_EUNREACHABLE, "a graph of the batch has more components than its target");
+  }
   double eps;
   memcpy(&eps, &hinfo[I_EPS], sizeof(double));
   R.eps = eps;

@@ -275,7 +275,7 @@ def context(device=None) -> Context:
 
 
 def set_option(name: str, value: int, device=None):
-    """Context option (tests / tuning): "rank_order" or "full_forest"."""
+    """Context option (tests / tuning), by the names the C header lists."""
     ctx = context(device)
     ctx.check(lib().spc_set_option(ctx.h, name.encode(), int(value)))
 

@@ -136,3 +136,36 @@ def test_batch_unreachable_target(P):
     with pytest.raises(P.SpcError) as ei:
         P.coarsen_batched(P.DeviceGraph.from_host(union), offs, [10, 1], 0)
     assert ei.value.code == -2
+
+
+def test_batch_band_short_redo(P):
+    # bands aimed at a quarter of each graph's merges fall short: the level
+    # is redone over every edge, with the same result
+    graphs = batch_trimeshes(12, seed=21, lo=12, hi=40, weights=("uniform", 1, 9))
+    n_c = [max(1, g.n // 10) for g in graphs]
+    try:
+        P.set_option("timing", 1)
+        P.timing_report()
+        P.set_option("batch_band_short", 1)
+        h = check_batch(P, graphs, n_c, 0, "batch bands fall short")
+        rep = P.timing_report()
+    finally:
+        P.set_option("batch_band_short", 0)
+        P.set_option("timing", 0)
+    assert rep["batch_bands"][0] >= 1
+    assert rep["rowpass"][0] > h.num_levels   # some level was redone
+
+
+def test_batch_bands_hold(P):
+    # per-graph bands that hold: one forest pass per level
+    graphs = batch_trimeshes(12, seed=22, lo=12, hi=40, weights=("uniform", 1, 9))
+    n_c = [max(1, g.n // 10) for g in graphs]
+    try:
+        P.set_option("timing", 1)
+        P.timing_report()
+        h = check_batch(P, graphs, n_c, 0, "batch bands")
+        rep = P.timing_report()
+    finally:
+        P.set_option("timing", 0)
+    assert rep["batch_bands"][0] >= 1
+    assert rep["rowpass"][0] == h.num_levels
