@@ -458,7 +458,107 @@ __global__ void __launch_bounds__(SMALL_BS)
     atomicMax(&info[I_MAXCL], (unsigned long long)mx);
 }
 
+// ---- a row of at most WAVE_CAP / 2 records, one wavefront ------------------
+// The row's entries are summed per coarse column in an LDS hash table of
+// T >= 2 E slots (open addressing; a slot holds column << 32 | weight sum,
+// the sum below 2^31 by the weight bound), the occupied slots are compacted
+// to the table's front, and each distinct column's place in the output is
+// its rank among them: a row's distinct columns are few (about six on
+// triangle meshes) against its records, so this replaces a sort of all the
+// records with one of the distinct columns.  Returns the member count.
+__device__ __forceinline__ int reduce_row_hashed(uint64_t* __restrict__ rec, int64_t g0, int64_t g1, int32_t a,
+                                                 uint64_t* ent, int64_t* __restrict__ cnt,
+                                                 int64_t* __restrict__ self_out, int32_t* __restrict__ size_out) {
+  int l = lane_id();
+  int E = (int)(g1 - g0);
+  int lg = 6;
+  while ((1 << lg) < 2 * E) lg++;
+  int T = 1 << lg;   // a multiple of WAVE, at most WAVE_CAP
+  for (int i = l; i < T; i += WAVE) ent[i] = KEY_INF;
+  __syncthreads();
+  uint64_t self = 0;
+  int32_t sz = 0, mem = 0;
+  for (int64_t p = g0 + l; p < g1; p += WAVE) {
+    uint64_t v = rec[p];
+    uint32_t b = (uint32_t)(v >> 32);
+    if (v & REC_MEMBER) {
+      mem++;
+      sz += (int32_t)(b & 0x7fffffffu);
+      self += (uint32_t)v;
+    } else if ((int32_t)b == a) {
+      self += (uint32_t)v;
+    } else {
+      // T > E >= distinct columns: a free slot always exists
+      uint32_t h = (b * 0x9E3779B1u) >> (32 - lg);
+      while (true) {
+        unsigned long long old = atomicCAS((unsigned long long*)&ent[h], (unsigned long long)KEY_INF,
+                                           (unsigned long long)v);
+        if (old == KEY_INF) break;
+        if ((uint32_t)(old >> 32) == b) {
+          atomicAdd((unsigned long long*)&ent[h], (unsigned long long)(uint32_t)v);
+          break;
+        }
+        h = (h + 1) & (uint32_t)(T - 1);
+      }
+    }
+  }
+  self = wave_sum(self);
+  sz = wave_sum(sz);
+  mem = wave_sum(mem);
+  __syncthreads();
+  // compaction in place: a write lands below the slots still to be read
+  // (every lane reads slot q + l before any lane writes in that step)
+  int D = 0;
+  for (int q = 0; q < T; q += WAVE) {
+    uint64_t x = ent[q + l];
+    bool occ = x != KEY_INF;
+    uint64_t bm = __ballot(occ);
+    if (occ) ent[D + __popcll(bm & lanemask_lt())] = x;
+    D += __popcll(bm);
+  }
+  __syncthreads();
+  if (D <= WAVE) {
+    if (l < D) {
+      uint64_t x = ent[l];
+      uint32_t b = (uint32_t)(x >> 32);
+      int rank = 0;
+      for (int j = 0; j < D; j++) rank += (uint32_t)(ent[j] >> 32) < b ? 1 : 0;
+      rec[g0 + rank] = x;
+    }
+  } else {
+    // more distinct columns than lanes: sort them (columns are distinct)
+    int P2 = 1;
+    while (P2 < D) P2 <<= 1;
+    for (int i = D + l; i < P2; i += WAVE) ent[i] = KEY_INF;
+    __syncthreads();
+    for (int k = 2; k <= P2; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int p = l; p < P2 / 2; p += WAVE) {
+          int i = 2 * j * (p / j) + (p % j);
+          int r = i + j;
+          bool asc = (i & k) == 0;
+          uint64_t x = ent[i], y = ent[r];
+          if (asc ? (y < x) : (x < y)) {
+            ent[i] = y;
+            ent[r] = x;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int i = l; i < D; i += WAVE) rec[g0 + i] = ent[i];
+  }
+  if (l == 0) {
+    cnt[a] = D;
+    self_out[a] = (int64_t)self;
+    size_out[a] = sz;
+  }
+  __syncthreads();   // the next row reuses the table
+  return mem;
+}
+
 // ---- listed rows of at most CAP records: one TB-thread block each -----------
+// (one wavefront: rows of at most CAP / 2 records take the hashed reduction)
 template <int TB, int CAP>
 __global__ void __launch_bounds__(TB)
     k_contract_row(uint64_t* __restrict__ rec, const int64_t* __restrict__ gptr,
@@ -476,6 +576,16 @@ __global__ void __launch_bounds__(TB)
   int64_t nr = nrows_dev ? (int64_t)*nrows_dev : (int64_t)gridDim.x;
   for (int64_t r = blockIdx.x; r < nr; r += gridDim.x) {
     int32_t a = rowlist[r];
+    if constexpr (TB == WAVE) {
+      int64_t h0 = gptr[a], h1 = gptr[a + 1];
+      if (h1 - h0 <= CAP / 2) {   // (uniform over the block)
+        int mem = reduce_row_hashed(rec, h0, h1, a, ent, cnt, self_out, size_out);
+        if (tid == 0 && (unsigned long long)mem >
+            __hip_atomic_load(&info[I_MAXCL], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+          atomicMax(&info[I_MAXCL], (unsigned long long)mem);
+        continue;
+      }
+    }
     if (tid == 0) {
       lcnt = 0;
       lself = 0;
