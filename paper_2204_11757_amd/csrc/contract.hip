@@ -15,8 +15,10 @@
 //            then contiguous at rec[gptr[a], gptr[a + 1]);
 //   reduce   by the record count E_a of the row:
 //              E_a <= SMALL_CAP   one thread, a sorted register list;
-//              E_a <= REG32_CAP   the same, longer list;
-//              E_a <= WAVE_CAP    one wavefront, bitonic sort in LDS;
+//              E_a <= REG32_CAP   sixteen lanes, sums in an LDS hash table
+//                                 and each distinct column's rank;
+//              E_a <= WAVE_CAP    one wavefront, the same (a bitonic sort in
+//                                 LDS above WAVE_CAP / 2 records);
 //              E_a <= BLOCK_CAP   one 256-thread block, bitonic sort in LDS;
 //              larger             dense accumulators over the coarse ids
 //                                 (few such rows) or a merge sort of all
@@ -439,18 +441,97 @@ __global__ void __launch_bounds__(SMALL_BS)
   }
 }
 
-// ---- listed rows of at most REG32_CAP records: one thread each ----------------
-__global__ void __launch_bounds__(SMALL_BS)
+// ---- listed rows of at most REG32_CAP records: RG_L lanes each --------------
+// Four rows per wavefront, each with RG_L lanes and a table of RG_T slots in
+// LDS: the hashed reduction below (same table, compaction and ranks), run
+// by lane groups.  One thread per row would insert every record into a
+// sorted register list, a chain of dependent steps per record.
+constexpr int RG_L = 16;
+constexpr int RG_N = WAVE / RG_L;
+constexpr int RG_T = 2 * REG32_CAP;   // >= 2 E: a free slot always exists
+static_assert(RG_T % RG_L == 0 && RG_T == 64, "the hash below takes 6 bits");
+
+template <typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int o = RG_L / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__global__ void __launch_bounds__(WAVE)
     k_contract_reg32(uint64_t* __restrict__ rec, const int64_t* __restrict__ gptr,
                      const int32_t* __restrict__ rows, int64_t nrows, const unsigned long long* nrows_dev,
                      int64_t* __restrict__ cnt, int64_t* __restrict__ self_out, int32_t* __restrict__ size_out,
                      unsigned long long* info) {
+  __shared__ uint64_t tab[RG_N * RG_T];
+  int l = lane_id(), gi = l / RG_L, gl = l % RG_L;
+  uint64_t* t = tab + gi * RG_T;
   // (with nrows_dev the count is read here and the grid strides over it)
   int64_t nr = nrows_dev ? (int64_t)*nrows_dev : nrows;
   int mx = 0;
-  for (int64_t i = (int64_t)blockIdx.x * SMALL_BS + threadIdx.x; i < nr; i += (int64_t)gridDim.x * SMALL_BS) {
-    int mem = reduce_row_regs<REG32_CAP>(rec, rec, gptr, cnt, self_out, size_out, rows[i]);
+  for (int64_t base = (int64_t)blockIdx.x * RG_N; base < nr; base += (int64_t)gridDim.x * RG_N) {
+    int64_t r = base + gi;
+    bool has = r < nr;
+    int32_t a = has ? rows[r] : 0;
+    int64_t g0 = has ? gptr[a] : 0, g1 = has ? gptr[a + 1] : 0;
+#pragma unroll
+    for (int i = gl; i < RG_T; i += RG_L) t[i] = KEY_INF;
+    __syncthreads();
+    uint64_t self = 0;
+    int32_t sz = 0, mem = 0;
+    for (int64_t p = g0 + gl; p < g1; p += RG_L) {
+      uint64_t v = rec[p];
+      uint32_t b = (uint32_t)(v >> 32);
+      if (v & REC_MEMBER) {
+        mem++;
+        sz += (int32_t)(b & 0x7fffffffu);
+        self += (uint32_t)v;
+      } else if ((int32_t)b == a) {
+        self += (uint32_t)v;
+      } else {
+        uint32_t h = (b * 0x9E3779B1u) >> 26;
+        while (true) {
+          unsigned long long old = atomicCAS((unsigned long long*)&t[h], (unsigned long long)KEY_INF,
+                                             (unsigned long long)v);
+          if (old == KEY_INF) break;
+          if ((uint32_t)(old >> 32) == b) {
+            atomicAdd((unsigned long long*)&t[h], (unsigned long long)(uint32_t)v);
+            break;
+          }
+          h = (h + 1) & (uint32_t)(RG_T - 1);
+        }
+      }
+    }
+    self = group_sum(self);
+    sz = group_sum(sz);
+    mem = group_sum(mem);
+    __syncthreads();
+    // compaction in place, as in the wavefront reduction (each write lands
+    // at or below the writer's own slot of the step)
+    int D = 0;
+#pragma unroll
+    for (int q = 0; q < RG_T; q += RG_L) {
+      uint64_t x = t[q + gl];
+      bool occ = x != KEY_INF;
+      uint32_t gb = (uint32_t)(__ballot(occ) >> (gi * RG_L)) & ((1u << RG_L) - 1);
+      if (occ) t[D + __popc(gb & ((1u << gl) - 1))] = x;
+      D += __popc(gb);
+    }
+    __syncthreads();
+    for (int i = gl; i < D; i += RG_L) {
+      uint64_t x = t[i];
+      uint32_t b = (uint32_t)(x >> 32);
+      int rank = 0;
+      for (int j = 0; j < D; j++) rank += (uint32_t)(t[j] >> 32) < b ? 1 : 0;
+      rec[g0 + rank] = x;
+    }
+    if (has && gl == 0) {
+      cnt[a] = D;
+      self_out[a] = (int64_t)self;
+      size_out[a] = sz;
+    }
     mx = mem > mx ? mem : mx;
+    __syncthreads();   // the next rows reuse the tables
   }
   mx = wave_max(mx);
   if (lane_id() == 0 && (unsigned long long)mx >
@@ -1018,8 +1099,8 @@ static int contract_classes(spc_ctx* ctx, int64_t n_c, spc_graph_out* out, Level
   if (!(launch & 4)) nblk = 0;
   if ((dev && (launch & 1)) || nr32 > 0) {
     TimedScope ts(ctx, "contract_reg32", (double)nr32);
-    int64_t gr = dev ? std::min((int64_t)grid_for(n_c, SMALL_BS), cap) : (int64_t)grid_for(nr32, SMALL_BS);
-    hipLaunchKernelGGL(k_contract_reg32, dim3((unsigned)gr), dim3(SMALL_BS), 0, st, W.temp, W.gptr, W.r32list,
+    int64_t gr = dev ? std::min((int64_t)grid_for(n_c, RG_N), cap * 4) : (int64_t)grid_for(nr32, RG_N);
+    hipLaunchKernelGGL(k_contract_reg32, dim3((unsigned)gr), dim3(WAVE), 0, st, W.temp, W.gptr, W.r32list,
                        nr32, dev ? &info[I_R32] : nullptr, W.cnt, self_out, out->size, info);
     SPC_LAUNCH_CHECK(ctx, "contract reg32");
   }
