@@ -220,6 +220,69 @@ constexpr int RT_BS = 256;
 constexpr int RT_PER = RT / RT_BS;
 constexpr int RM = 2048;
 
+// A tile whose rows r0..r1 number at most RT: each row's record base
+// gptr[c(x)] + off[x] + 1 - rp[x] is computed once, in the pass that marks
+// the rows' first positions for the load-balanced search, and the entries'
+// own loads are issued before it.
+__device__ __forceinline__ void scatter_tile_rows(const LevelIn& g, const int32_t* __restrict__ c,
+                                                  const int64_t* __restrict__ gptr,
+                                                  const int64_t* __restrict__ off, uint64_t* __restrict__ rec,
+                                                  int64_t p0, int64_t r0, int64_t r1, int32_t* srow,
+                                                  int64_t* sbase_row, int32_t* stmp) {
+  using L = Lbs<RT, RT_BS>;
+  int tid = threadIdx.x;
+  int32_t yr[RT_PER];
+  uint32_t wr[RT_PER];
+#pragma unroll
+  for (int i = 0; i < RT_PER; i++) {
+    int64_t j = p0 + tid + i * RT_BS;
+    bool in = j < g.nnz;
+    yr[i] = in ? g.col[j] : 0;
+    wr[i] = in ? (uint32_t)g.w[j] : 0u;
+  }
+  for (int k = tid; k < RT; k += RT_BS) srow[L::at(k)] = (int32_t)r0;
+  __syncthreads();
+  int nr = (int)(r1 - r0) + 1;   // at most RT
+  for (int i = tid; i < nr; i += RT_BS) {
+    int64_t r = r0 + i;
+    int64_t pr = g.rp[r];
+    int64_t b = gptr[c[r]] + off[r] + 1 - pr;
+    int64_t q = pr - p0;
+    if (i > 0 && q > 0 && q < RT) atomicMax(&srow[L::at((int)q)], (int32_t)r);
+    sbase_row[i] = b;
+  }
+#pragma unroll
+  for (int i = 0; i < RT_PER; i++) yr[i] = c[yr[i]];
+  __syncthreads();
+  // inclusive max-scan of the marks: every position's row
+  constexpr int PER = L::PER;
+  int32_t loc[PER];
+  int32_t run = INT32_MIN;
+#pragma unroll
+  for (int i = 0; i < PER; i++) {
+    int32_t v = srow[L::at(tid * PER + i)];
+    run = v > run ? v : run;
+    loc[i] = run;
+  }
+  int32_t tot;
+  int32_t inc = block_incl_scan<int32_t, RT_BS, true>(run, stmp, &tot);
+  int32_t prev = __shfl_up(inc, 1);
+  if (lane_id() == 0) prev = (tid / WAVE > 0) ? stmp[tid / WAVE - 1] : INT32_MIN;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; i++) srow[L::at(tid * PER + i)] = loc[i] > prev ? loc[i] : prev;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < RT_PER; i++) {
+    int k = tid + i * RT_BS;
+    int64_t j = p0 + k;
+    if (j < g.nnz) {
+      int32_t x = srow[L::at(k)];
+      rec[sbase_row[x - r0] + j] = ((uint64_t)(uint32_t)yr[i] << 32) | wr[i];
+    }
+  }
+}
+
 __global__ void __launch_bounds__(RT_BS)
     k_record_scatter(LevelIn g, const int32_t* __restrict__ c, const int64_t* __restrict__ gptr,
                      const int64_t* __restrict__ off, uint64_t* __restrict__ rec, int tiles,
@@ -227,6 +290,7 @@ __global__ void __launch_bounds__(RT_BS)
   __shared__ int32_t srow[Lbs<RT, RT_BS>::SIZE];
   __shared__ int64_t sh[2];
   __shared__ int32_t stmp[RT_BS / WAVE];
+  __shared__ int64_t sbase_row[RT];
   int tid = threadIdx.x;
   if ((int)blockIdx.x >= tiles) {
     int64_t x0 = (int64_t)(blockIdx.x - tiles) * RM;
@@ -244,8 +308,13 @@ __global__ void __launch_bounds__(RT_BS)
   int64_t p0 = t * RT;
   if (ptrow) {
     // the tile's first row from the degree pass (uniform over the block)
+    int64_t r0 = ptrow[t];
     int64_t r1 = t + 1 < tiles ? ptrow[t + 1] : g.n - 1;
-    lbs_fill<RT, RT_BS>(g.rp, ptrow[t], r1, p0, srow, stmp);
+    if (r1 - r0 < RT) {
+      scatter_tile_rows(g, c, gptr, off, rec, p0, r0, r1, srow, (int64_t*)sbase_row, stmp);
+      return;
+    }
+    lbs_fill<RT, RT_BS>(g.rp, r0, r1, p0, srow, stmp);
   } else {
     lbs_tile<RT, RT_BS>(g.rp, g.n, p0, srow, sh, stmp);
   }
