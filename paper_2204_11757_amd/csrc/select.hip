@@ -370,6 +370,17 @@ __global__ void __launch_bounds__(BS)
   int64_t j0 = (int64_t)blockIdx.x * TILE_R;
   int64_t nnz = g.nnz;
   uint64_t tlo = use_lo ? *thr_lo : 0, thi = *thr_hi;   // issued early, used at the end
+  int tid = threadIdx.x;
+  // the tile's keys and columns, loaded before the row search (which does
+  // not need them) so that their latency overlaps it
+  uint64_t pk[R_PER];
+  int32_t ck[R_PER];
+#pragma unroll
+  for (int i = 0; i < R_PER; i++) {
+    int64_t j = j0 + tid + i * BS;
+    pk[i] = j < nnz ? Pc[j] : KEY_INF;
+    ck[i] = j < nnz ? g.col[j] : 0;
+  }
   if (ptrow) {
     // the tile's first row from the degree pass (uniform over the block)
     int64_t t = blockIdx.x;
@@ -378,20 +389,17 @@ __global__ void __launch_bounds__(BS)
   } else {
     lbs_tile<TILE_R, BS>(g.rp, g.n, j0, srow, sh, stmp);
   }
-  int tid = threadIdx.x;
-  // coalesced: key, and from the column the upper / row-head flags
+  // the key, and from the column the upper / row-head flags
 #pragma unroll
   for (int i = 0; i < R_PER; i++) {
     int k = tid + i * BS;
     int64_t j = j0 + k;
-    uint64_t p = KEY_INF;
     uint32_t f = 0;
     if (j < nnz) {
-      p = Pc[j];
       int32_t u = srow[L::at(k)];
-      f = (g.col[j] > u ? 1u : 0u) | ((k == 0 || srow[L::at(k - 1)] != u) ? 2u : 0u);
+      f = (ck[i] > u ? 1u : 0u) | ((k == 0 || srow[L::at(k - 1)] != u) ? 2u : 0u);
     }
-    sp[L::at(k)] = p;
+    sp[L::at(k)] = pk[i];
     sfl[k] = (uint8_t)f;
   }
   __syncthreads();
