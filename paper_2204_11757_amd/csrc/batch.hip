@@ -159,35 +159,52 @@ __global__ void __launch_bounds__(SEL_BS)
     unsigned int c = slocal < (unsigned)SEG_SMALL ? slocal : (unsigned)SEG_SMALL;
     cut = lds_select(sbuf, (int)c, k, h, tmp, red, spick, &info[I_LBERR], s2, &s2cnt);
   }
-  // join the forest edges up to the cutoff; the cutoff edge gives epsilon
+  // join the forest edges up to the cutoff; the cutoff edge gives epsilon.
+  // SJ nodes per thread at a time: their keys, records and endpoints are
+  // each loaded together before the joins
   bool guarded = exact && info[I_GUARD];
   uint64_t emask = (1ull << ebits) - 1;
-  for (int64_t x0 = lo; x0 < hi_n; x0 += SEL_BS) {
-    int64_t x = x0 + t;
-    if (x >= hi_n) break;
-    uint64_t key = fkey[x];
-    if (key == KEY_INF) continue;
-    if (key <= cut) {
-      uint64_t uv = msfO[fidx[x]];
-      int32_t u = (int32_t)(uint32_t)uv, v = (int32_t)(uv >> 32);
-      uf_union(parent, u, v);
-      if (key == cut) {
-        int64_t a = g.rp[u], b = g.rp[u + 1];
-        while (a < b) {
-          int64_t mid = (a + b) >> 1;
-          if (g.col[mid] < v) a = mid + 1;
-          else b = mid;
-        }
-        uint64_t N, D;
-        int64_t jm;
-        edge_score(g, deg, lc, u, v, g.w[a], N, D, jm);
-        atomic_max_double(&info[I_EPS], (double)N / (double)D);
-      }
+  constexpr int SJ = 4;
+  for (int64_t x0 = lo; x0 < hi_n; x0 += SEL_BS * SJ) {
+    uint64_t ks[SJ], uvs[SJ];
+    int64_t fs[SJ];
+#pragma unroll
+    for (int q = 0; q < SJ; q++) {
+      int64_t x = x0 + q * SEL_BS + t;
+      ks[q] = x < hi_n ? fkey[x] : KEY_INF;
     }
-    if (guarded && key != cut && (key >> ebits) == (cut >> ebits) &&
-        !(key_exact(kexact, key & emask) && key_exact(kexact, cut & emask))) {
-      KeyND p = exact[key & emask], q = exact[cut & emask];
-      if ((unsigned __int128)p.N * q.D != (unsigned __int128)q.N * p.D) atomicOr(&info[I_VIOL], 1ull);
+#pragma unroll
+    for (int q = 0; q < SJ; q++) {
+      int64_t x = x0 + q * SEL_BS + t;
+      fs[q] = ks[q] <= cut ? (int64_t)fidx[x] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < SJ; q++) uvs[q] = fs[q] >= 0 ? msfO[fs[q]] : 0;
+    for (int q = 0; q < SJ; q++) {
+      uint64_t key = ks[q];
+      if (key == KEY_INF) continue;
+      if (key <= cut) {
+        uint64_t uv = uvs[q];
+        int32_t u = (int32_t)(uint32_t)uv, v = (int32_t)(uv >> 32);
+        uf_union(parent, u, v);
+        if (key == cut) {
+          int64_t a = g.rp[u], b = g.rp[u + 1];
+          while (a < b) {
+            int64_t mid = (a + b) >> 1;
+            if (g.col[mid] < v) a = mid + 1;
+            else b = mid;
+          }
+          uint64_t N, D;
+          int64_t jm;
+          edge_score(g, deg, lc, u, v, g.w[a], N, D, jm);
+          atomic_max_double(&info[I_EPS], (double)N / (double)D);
+        }
+      }
+      if (guarded && key != cut && (key >> ebits) == (cut >> ebits) &&
+          !(key_exact(kexact, key & emask) && key_exact(kexact, cut & emask))) {
+        KeyND p = exact[key & emask], r = exact[cut & emask];
+        if ((unsigned __int128)p.N * r.D != (unsigned __int128)r.N * p.D) atomicOr(&info[I_VIOL], 1ull);
+      }
     }
   }
 }
