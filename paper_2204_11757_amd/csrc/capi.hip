@@ -231,6 +231,10 @@ static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* clus
   // nor for the first forest batch when the last level's forest was complete
   // after it, in one band
   bool spec = defer && (ctx->speculate == 2 || (ctx->speculate == 0 && ctx->spec_ok));
+  // the first batch of forest rounds as long as the last level of this size
+  // class needed (else as the previous level's); launch counts only
+  int cls = bitlen64((uint64_t)g->nnz);
+  if (ctx->forest_batch_cls[cls] > 0) ctx->forest_batch = ctx->forest_batch_cls[cls];
   rc = select_level(ctx, L, t, cluster_of, W, R, fp ? &LF : nullptr, seg, defer, false, spec);
   if (rc == SPC_REDO_BAND) {
     // a graph of the batch had fewer forest edges inside its band than
@@ -293,6 +297,7 @@ static int level_impl(spc_ctx* ctx, const spc_graph* g, int64_t t, int32_t* clus
     if (rc) return rc;
   }
   *nnz_c = R.nnz_c;
+  ctx->forest_batch_cls[cls] = ctx->forest_batch;   // (this level's need, from its selection)
   if (st) {
     float ms = 0;
     if (!e0) {

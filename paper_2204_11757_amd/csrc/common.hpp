@@ -344,6 +344,7 @@ struct spc_ctx {
   int64_t lb_words = 0;        // size of the current level's look-back array
   unsigned long long sel_epoch = 0;   // radix-select barrier epochs handed out this level
   int forest_batch = 2;        // forest rounds issued before the first wait (from the last level)
+  int forest_batch_cls[64] = {};   // the same per input size class (bit length of nnz; 0: none yet)
   // knobs
   int force_rank_mode = 0;   // use the sorted-rank order even when a packed key fits
   int force_full_filter = 0; // run the spanning-forest phase over every edge

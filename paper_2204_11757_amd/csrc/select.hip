@@ -1818,7 +1818,7 @@ int finish_select(spc_ctx* ctx, LevelResult& R, int64_t t, bool rank, bool fp, c
     // rounds after the fused first one, plus the lookup that finds the
     // list empty
     int64_t need = R.rounds - (R.bands == 1 ? 1 : 0) + 1;
-    ctx->forest_batch = need < 1 ? 1 : need > 6 ? 6 : (int)need;
+    ctx->forest_batch = need < 1 ? 1 : need > 8 ? 8 : (int)need;
   }
   R.forest_in = hinfo[I_FIN];
   R.forest_kept = hinfo[I_FKEPT];
