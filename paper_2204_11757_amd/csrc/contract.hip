@@ -213,8 +213,10 @@ __global__ void __launch_bounds__(CM_BS)
 // ---- scatter: every record to its slot --------------------------------------
 // Tiles of RT consecutive fine entries (mapped to rows by the load-balanced
 // search, renumbered per XCD so that a tile's neighbours share its L2) write
-// (c(y) << 32) | w at gptr[c(x)] + off[x] + 1 + (j - rp[x]); the blocks past
-// the tiles write the member records, RM nodes per block.
+// (c(y) << 32) | w at gptr[c(x)] + off[x] + 1 + (j - rp[x]); the member
+// records are written by the tiles that take the per-row path, for the rows
+// starting in them, and by the blocks past the tiles (RM nodes per block)
+// for the other rows.
 constexpr int RT = ENTRY_TILE;
 constexpr int RT_BS = 256;
 constexpr int RT_PER = RT / RT_BS;
@@ -223,11 +225,21 @@ constexpr int RM = 2048;
 // A tile whose rows r0..r1 number at most RT: each row's record base
 // gptr[c(x)] + off[x] + 1 - rp[x] is computed once, in the pass that marks
 // the rows' first positions for the load-balanced search, and the entries'
-// own loads are issued before it.
+// own loads are issued before it.  The same pass writes the member record
+// (just before the row's first entry record) of every row that starts in
+// the tile (the last tile: at or after its start), so it lands beside the
+// row's entries.
+__device__ __forceinline__ bool scatter_rows_tile(const int32_t* __restrict__ ptrow, int64_t t, int tiles,
+                                                  int64_t n, int64_t& r0, int64_t& r1) {
+  r0 = ptrow[t];
+  r1 = t + 1 < tiles ? ptrow[t + 1] : n - 1;
+  return r1 - r0 < RT;
+}
+
 __device__ __forceinline__ void scatter_tile_rows(const LevelIn& g, const int32_t* __restrict__ c,
                                                   const int64_t* __restrict__ gptr,
                                                   const int64_t* __restrict__ off, uint64_t* __restrict__ rec,
-                                                  int64_t p0, int64_t r0, int64_t r1, int32_t* srow,
+                                                  int64_t p0, int64_t r0, int64_t r1, bool last, int32_t* srow,
                                                   int64_t* sbase_row, int32_t* stmp) {
   using L = Lbs<RT, RT_BS>;
   int tid = threadIdx.x;
@@ -250,6 +262,11 @@ __device__ __forceinline__ void scatter_tile_rows(const LevelIn& g, const int32_
     int64_t q = pr - p0;
     if (i > 0 && q > 0 && q < RT) atomicMax(&srow[L::at((int)q)], (int32_t)r);
     sbase_row[i] = b;
+    if (q >= 0 && (q < RT || last)) {
+      uint32_t sz = g.size ? (uint32_t)g.size[r] : 1u;
+      uint32_t sw = g.self ? (uint32_t)g.self[r] : 0u;
+      rec[b + pr - 1] = member_record(sz, sw);
+    }
   }
 #pragma unroll
   for (int i = 0; i < RT_PER; i++) yr[i] = c[yr[i]];
@@ -293,11 +310,22 @@ __global__ void __launch_bounds__(RT_BS)
   __shared__ int64_t sbase_row[RT];
   int tid = threadIdx.x;
   if ((int)blockIdx.x >= tiles) {
+    // the member records the tiles did not write: rows whose tile (the one
+    // holding the row's start; the last one for rows starting at the end)
+    // took the per-entry path, or whose rows it does not span (an empty row
+    // starting right at the tile's first position, before the row that
+    // holds it)
     int64_t x0 = (int64_t)(blockIdx.x - tiles) * RM;
 #pragma unroll
     for (int i = 0; i < RM / RT_BS; i++) {
       int64_t x = x0 + i * RT_BS + tid;
       if (x >= g.n) break;
+      if (ptrow && tiles > 0) {
+        int64_t t = g.rp[x] / RT;
+        if (t > tiles - 1) t = tiles - 1;
+        int64_t ra, rb;
+        if (scatter_rows_tile(ptrow, t, tiles, g.n, ra, rb) && x >= ra && x <= rb) continue;
+      }
       uint32_t sz = g.size ? (uint32_t)g.size[x] : 1u;
       uint32_t sw = g.self ? (uint32_t)g.self[x] : 0u;
       rec[gptr[c[x]] + off[x]] = member_record(sz, sw);
@@ -308,10 +336,9 @@ __global__ void __launch_bounds__(RT_BS)
   int64_t p0 = t * RT;
   if (ptrow) {
     // the tile's first row from the degree pass (uniform over the block)
-    int64_t r0 = ptrow[t];
-    int64_t r1 = t + 1 < tiles ? ptrow[t + 1] : g.n - 1;
-    if (r1 - r0 < RT) {
-      scatter_tile_rows(g, c, gptr, off, rec, p0, r0, r1, srow, (int64_t*)sbase_row, stmp);
+    int64_t r0, r1;
+    if (scatter_rows_tile(ptrow, t, tiles, g.n, r0, r1)) {
+      scatter_tile_rows(g, c, gptr, off, rec, p0, r0, r1, t == tiles - 1, srow, (int64_t*)sbase_row, stmp);
       return;
     }
     lbs_fill<RT, RT_BS>(g.rp, r0, r1, p0, srow, stmp);
