@@ -299,6 +299,31 @@ def test_tiles_across_long_and_empty_rows(P):
     h, want, _ = check_hierarchy(P, g, g.n - 2500, 0, "tile boundaries, halving")
 
 
+def _star_gap_graph(seed=5):
+    # a star of 1024 leaves fills the first 2048 CSR entries exactly, then 76
+    # isolated nodes start at entry 2048, ahead of the row that holds it: the
+    # contraction's record scatter tiles (2048 entries) start right there
+    n = 3000
+    rng = np.random.default_rng(seed)
+    a = rng.integers(1101, n, 6000)
+    b = rng.integers(1101, n, 6000)
+    keep = a != b
+    u = np.concatenate([np.zeros(1024, np.int64), a[keep]])
+    v = np.concatenate([np.arange(1, 1025), b[keep]])
+    lo, hi = np.minimum(u, v), np.maximum(u, v)
+    pairs = np.unique(lo * n + hi)
+    w = rng.integers(1, 9, len(pairs)).astype(np.int32)
+    g = from_edges(n, (pairs // n).astype(np.int64), (pairs % n).astype(np.int64), w)
+    assert g.row_ptr[1025] == 2048 and g.row_ptr[1101] == 2048
+    return g
+
+
+def test_empty_rows_at_a_tile_start(P):
+    g = _star_gap_graph()
+    check_level(P, g, g.n - 800, "empty rows at a scatter tile's start")
+    check_hierarchy(P, g, g.n - 1600, 0, "empty rows at a scatter tile's start, halving")
+
+
 def _heavy_edge_graph():
     # a 30x30 triangle mesh whose edges at three nodes weigh 2^23: degrees
     # reach 2^26 (the score's products then take 64-bit multiplies) while
