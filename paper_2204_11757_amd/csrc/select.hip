@@ -211,18 +211,35 @@ __global__ void __launch_bounds__(BS)
       }
     }
   }
-  // rows longer than DEG_SHORT: the whole block sums each of them, except
-  // the first H_MAX rows longer than HUGE_T, which get a position map for
-  // the scores and are summed by k_sum_parts with a block of its own
+  // rows longer than DEG_SHORT: up to HUGE_T entries one wavefront sums
+  // each of them (the block's four wavefronts take turns over its list);
+  // longer ones the whole block, except the first H_MAX rows longer than
+  // HUGE_T, which get a position map for the scores and are summed by
+  // k_sum_parts with a block of its own
   int total_long;
   int p = block_incl_scan<int, BS, false>(nlong, stmp, &total_long) - nlong;
   for (int i = 0; i < DEG_PER; i++)
     if (longmask >> i & 1u) slong[p++] = (int32_t)(base + i * BS + tid);
   __syncthreads();
+  for (int r = tid / WAVE; r < total_long; r += BS / WAVE) {
+    int64_t u = slong[r];
+    int64_t s = g.rp[u], e = g.rp[u + 1];
+    if (e - s > HUGE_T) continue;   // (uniform over the wavefront)
+    uint64_t d = 0;
+    for (int64_t j = s + lane_id(); j < e; j += WAVE) d += (uint64_t)g.w[j];
+    d = wave_sum(d);
+    if (lane_id() == 0) {
+      uint64_t t = d + (g.self ? (uint64_t)g.self[u] : 0);
+      deg[u] = t;
+      mx = t > mx ? t : mx;
+      sm += t;
+    }
+  }
   for (int r = 0; r < total_long; r++) {
     int64_t u = slong[r];
     int64_t s = g.rp[u], e = g.rp[u + 1];
-    if (e - s > HUGE_T) {
+    if (e - s <= HUGE_T) continue;   // (uniform over the block; summed above)
+    {
       if (tid == 0) {
         // few rows are this long, so one atomic each stays cheap
         unsigned long long slot = atomicAdd(&info[I_LONGROW], 1ull);
