@@ -1164,8 +1164,9 @@ __global__ void __launch_bounds__(PACK_BS)
   __shared__ int64_t sh[2];
   __shared__ int32_t stmp[PACK_BS / WAVE];
   int64_t p0 = (int64_t)blockIdx.x * PACK_T;
-  lbs_tile<PACK_T, PACK_BS>(rpc, n_c, p0, srow, sh, stmp);
   int64_t total = rpc[n_c];
+  if (p0 >= total) return;   // (a grid sized by a bound; uniform over the block)
+  lbs_tile<PACK_T, PACK_BS>(rpc, n_c, p0, srow, sh, stmp);
   for (int i = 0; i < PACK_T / PACK_BS; i++) {
     int k = threadIdx.x + i * PACK_BS;
     int64_t p = p0 + k;
@@ -1317,17 +1318,28 @@ static int contract_huge(spc_ctx* ctx, const LevelIn& g, int64_t n_c, spc_graph_
 
 // Coarse row pointer from the row counts, then the info block, the entry
 // total and the look-back error flags to the host.
+// pack_bound > 0: the pack is launched right after the scan, before the
+// wait, over pack_bound entries (at least the coarse entries, which the
+// output must hold; the pack reads the total from the row pointer)
 static int rowptr_and_read(spc_ctx* ctx, const LevelWork& W, spc_graph_out* out, int64_t n_c,
-                           const int32_t* x1) {
+                           const int32_t* x1, int64_t pack_bound = 0) {
   if (n_c > 0) {
     // the scan's last tile writes the host's copy (one launch fewer) and
     // then a new token, which the host polls
-    TimedScope ts(ctx, "contract_rowptr", (double)n_c);
     int64_t token = ++ctx->rb_token;
-    int rc = exclusive_scan<int64_t>(ctx, W.cnt, out->row_ptr, n_c, (int64_t*)W.scan_partial,
-                                     ScanReadback{W.info, (int)I_NINFO, x1, ctx->h_pinned, token});
-    if (rc) return rc;
-    SPC_LAUNCH_CHECK(ctx, "row-pointer scan");
+    {
+      TimedScope ts(ctx, "contract_rowptr", (double)n_c);
+      int rc = exclusive_scan<int64_t>(ctx, W.cnt, out->row_ptr, n_c, (int64_t*)W.scan_partial,
+                                       ScanReadback{W.info, (int)I_NINFO, x1, ctx->h_pinned, token});
+      if (rc) return rc;
+      SPC_LAUNCH_CHECK(ctx, "row-pointer scan");
+    }
+    if (pack_bound > 0) {
+      TimedScope ts(ctx, "contract_pack", (double)pack_bound);
+      hipLaunchKernelGGL(k_pack, dim3(grid_for(pack_bound, PACK_T)), dim3(PACK_BS), 0, ctx->stream, out->row_ptr,
+                         n_c, W.gptr, W.temp, out->col, (int32_t*)out->w);
+      SPC_LAUNCH_CHECK(ctx, "pack");
+    }
     return wait_token(ctx, token);
   }
   int rc = exclusive_scan<int64_t>(ctx, W.cnt, out->row_ptr, n_c, (int64_t*)W.scan_partial);
@@ -1350,6 +1362,7 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
   int64_t* self_out = (int64_t*)out->self_w;
   int64_t* off = W.hpos;   // each fine node's first slot inside its super-node's records
   int rc;
+  int64_t packed_bound = 0;   // entries a pack launched before the last wait covers
   {
     TimedScope ts(ctx, "contract_members", (double)n);
     // (the merge cutoff's launch zeroed the record counts already when it
@@ -1448,7 +1461,11 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
       rc = contract_huge(ctx, g, n_c, out, W, seg, H, false);
       if (rc) return rc;
     }
-    rc = rowptr_and_read(ctx, W, out, n_c, nullptr);
+    // every row's entries are final here: when the output holds as many
+    // entries as the fine graph (a bound on the coarse one), the pack goes
+    // before the host's wait for the coarse count
+    if (out->nnz_cap >= g.nnz && g.nnz > 0) packed_bound = g.nnz;
+    rc = rowptr_and_read(ctx, W, out, n_c, nullptr, packed_bound);
     if (rc) return rc;
   }
   R.maxcl = hinfo[I_MAXCL];
@@ -1465,7 +1482,7 @@ int contract_level(spc_ctx* ctx, const LevelIn& g, const int32_t* c, int64_t n_c
   if (nnz_c > out->nnz_cap)
     return set_error(ctx, SPC_ECAPACITY, "coarse graph needs %lld entries, capacity %lld",
                      (long long)nnz_c, (long long)out->nnz_cap);
-  if (nnz_c > 0) {
+  if (nnz_c > 0 && packed_bound < nnz_c) {   // (not packed before the wait)
     TimedScope ts(ctx, "contract_pack", (double)nnz_c);
     hipLaunchKernelGGL(k_pack, dim3(grid_for(nnz_c, PACK_T)), dim3(PACK_BS), 0, st, out->row_ptr, n_c,
                        W.gptr, W.temp, out->col, (int32_t*)out->w);
